@@ -1,0 +1,206 @@
+"""Reference definitions of the preprocessing steps (numpy).
+
+TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.  Shares no code with
+the HIP library.
+
+Paper, Section 2.1: an octree level-of-detail structure with two coarser
+levels, each holding one eighth of the cells of the previous one.  Section 2.2:
+changing the brush modifies no volume data and rebuilds no acceleration
+structure -- so everything brush-dependent here (voxel mask, brick skip bits)
+is derived from brush-independent tables at render time.
+
+Every definition below is written in float32 with an explicit operation order
+(numpy float32 arithmetic rounds after each operation), because the GPU
+library must reproduce these arrays bit for bit:
+
+* level build: parent = fl32(fl32(fl32((a+b)+(c+d)) + fl32((e+f)+(g+h))) * 0.125)
+  with the eight children in (z, y, x) lexicographic order;
+* FP16 storage: round to nearest even, subnormals kept;
+* 8-bit storage: per 8^3 brick of its own 512 voxels, offset = min,
+  scale = fl32((max - min)/255), q = clamp(rint(fl32(fl32(v - offset)/scale)), 0, 255)
+  (scale 0 and q 0 for a constant brick); value = fl32(fl32(scale*q) + offset);
+* brick min/max: over the dequantised values of voxel indices
+  [8b, min(8b+8, N-1)] per axis (the brick plus a one-voxel apron), which is
+  every voxel a sample whose clamped floor index lies in the brick can read;
+* skip bit: some active field's brick range misses its [lo, hi] (or lo > hi, an
+  empty interval), or the table
+  opacity is zero over every entry the transfer-function field's brick range
+  can address; the index map is x(v) = fl32(min(max(fl32(fl32(v - vmin)*inv), 0), 1)*255)
+  with inv = fl32(1/(vmax - vmin)).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+BRICK = 8
+F32 = np.float32
+
+
+def build_level(v: np.ndarray) -> np.ndarray:
+    """2x2x2 box mean of a float32 [N,N,N] array, fixed order, float32 [N/2]^3."""
+    v = np.ascontiguousarray(v, dtype=F32)
+    a = v[0::2, 0::2, 0::2]
+    b = v[0::2, 0::2, 1::2]
+    c = v[0::2, 1::2, 0::2]
+    d = v[0::2, 1::2, 1::2]
+    e = v[1::2, 0::2, 0::2]
+    f = v[1::2, 0::2, 1::2]
+    g = v[1::2, 1::2, 0::2]
+    h = v[1::2, 1::2, 1::2]
+    s0 = (a + b) + (c + d)
+    s1 = (e + f) + (g + h)
+    return ((s0 + s1) * F32(0.125)).astype(F32)
+
+
+def build_levels(v: np.ndarray, n_lods: int):
+    """[L0, L1, ...] float32 levels, each built from the float32 level above it."""
+    out = [np.ascontiguousarray(v, dtype=F32)]
+    for _ in range(1, n_lods):
+        out.append(build_level(out[-1]))
+    return out
+
+
+# ----------------------------------------------------------------------------- storage
+def encode_f16(v: np.ndarray) -> np.ndarray:
+    """float32 -> IEEE binary16 bit patterns (round to nearest even, subnormals kept)."""
+    return np.asarray(v, F32).astype(np.float16).view(np.uint16)
+
+
+def decode_f16(bits: np.ndarray) -> np.ndarray:
+    return np.asarray(bits, np.uint16).view(np.float16).astype(F32)
+
+
+def _bricks_view(v: np.ndarray) -> np.ndarray:
+    n = v.shape[0]
+    nb = n // BRICK
+    return v.reshape(nb, BRICK, nb, BRICK, nb, BRICK).transpose(0, 2, 4, 1, 3, 5).reshape(nb, nb, nb, BRICK ** 3)
+
+
+def _unbricks(b: np.ndarray, n: int) -> np.ndarray:
+    nb = n // BRICK
+    return b.reshape(nb, nb, nb, BRICK, BRICK, BRICK).transpose(0, 3, 1, 4, 2, 5).reshape(n, n, n)
+
+
+def encode_u8(v: np.ndarray):
+    """Per-8^3-brick 8-bit codes.  Returns (q uint8 [N,N,N], scale f32 [nb]^3, offset f32 [nb]^3)."""
+    v = np.asarray(v, F32)
+    n = v.shape[0]
+    bv = _bricks_view(v)
+    mn = bv.min(axis=-1)
+    mx = bv.max(axis=-1)
+    scale = ((mx - mn) / F32(255.0)).astype(F32)
+    d = (bv - mn[..., None]).astype(F32)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = (d / scale[..., None]).astype(F32)
+    r = np.where(scale[..., None] > 0, r, F32(0.0))
+    q = np.clip(np.rint(r), 0, 255).astype(np.uint8)
+    return _unbricks(q, n), scale, mn.astype(F32)
+
+
+def decode_u8(q: np.ndarray, scale: np.ndarray, offset: np.ndarray) -> np.ndarray:
+    n = q.shape[0]
+    bq = _bricks_view(q).astype(F32)
+    val = ((scale[..., None] * bq).astype(F32) + offset[..., None]).astype(F32)
+    return _unbricks(val, n)
+
+
+def stored_values(v: np.ndarray, storage: str) -> np.ndarray:
+    """What a renderer reads after storing float32 level data as `storage`."""
+    if storage == "f32":
+        return np.asarray(v, F32)
+    if storage == "f16":
+        return decode_f16(encode_f16(v))
+    if storage == "u8":
+        return decode_u8(*encode_u8(v))
+    raise ValueError(storage)
+
+
+def stored_levels(fields: np.ndarray, n_lods: int, storage: str):
+    """levels[l] = float32 [F, N_l, N_l, N_l] stored (dequantised) values of level l."""
+    per_field = [build_levels(fields[f], n_lods) for f in range(fields.shape[0])]
+    return [np.stack([stored_values(per_field[f][l], storage) for f in range(fields.shape[0])])
+            for l in range(n_lods)]
+
+
+# ----------------------------------------------------------------------------- tables
+def brick_minmax(v: np.ndarray):
+    """(min, max) float32 [nb]^3 over the apron window [8b, min(8b+8, N-1)] per axis."""
+    v = np.asarray(v, F32)
+    n = v.shape[0]
+    nb = n // BRICK
+    # pad one voxel at the far end by edge replication: the window then is [8b, 8b+8]
+    p = np.pad(v, ((0, 1), (0, 1), (0, 1)), mode="edge")
+    mn = np.empty((nb, nb, nb), F32)
+    mx = np.empty((nb, nb, nb), F32)
+    for bz in range(nb):
+        slab = p[8 * bz:8 * bz + 9]
+        for by in range(nb):
+            row = slab[:, 8 * by:8 * by + 9]
+            win = np.lib.stride_tricks.sliding_window_view(row, 9, axis=2)[:, :, ::8][:, :, :nb]
+            mn[bz, by] = win.min(axis=(0, 1, 3))
+            mx[bz, by] = win.max(axis=(0, 1, 3))
+    return mn, mx
+
+
+def tf_index(v, vmin: float, vmax: float) -> np.ndarray:
+    """x(v) in float32 with the host-precomputed reciprocal."""
+    vmin32 = F32(vmin)
+    inv = F32(F32(1.0) / (F32(vmax) - vmin32))
+    t = ((np.asarray(v, F32) - vmin32).astype(F32) * inv).astype(F32)
+    t = np.minimum(np.maximum(t, F32(0.0)), F32(1.0))
+    return (t * F32(255.0)).astype(F32)
+
+
+def skip_bits(mins, maxs, active, lo, hi, tf_field: int, vmin: float, vmax: float, tf_rgba) -> np.ndarray:
+    """bool [nb]^3 brick skip flags from per-field tables (lists of [nb]^3 arrays)."""
+    nb = mins[0].shape[0]
+    skip = np.zeros((nb, nb, nb), bool)
+    for f in range(len(mins)):
+        if active[f]:
+            skip |= (maxs[f] < F32(lo[f])) | (mins[f] > F32(hi[f])) | (F32(lo[f]) > F32(hi[f]))
+    alpha = np.asarray(tf_rgba, F32).reshape(256, 4)[:, 3]
+    x0 = tf_index(mins[tf_field], vmin, vmax)
+    x1 = tf_index(maxs[tf_field], vmin, vmax)
+    i0 = np.floor(x0).astype(np.int64)
+    i1 = np.minimum(np.ceil(x1).astype(np.int64), 255)
+    # zero over [i0, i1]  <=>  no positive entry in that range
+    csum = np.concatenate([[0], np.cumsum(alpha > 0)])
+    nz = csum[i1 + 1] - csum[i0]
+    skip |= nz == 0
+    return skip
+
+
+def pack_bits(flags: np.ndarray) -> np.ndarray:
+    """bool array (linear brick order) -> uint32 words, brick k in word k//32 bit k%32."""
+    flat = np.asarray(flags, bool).ravel()
+    nw = (flat.size + 31) // 32
+    padded = np.zeros(nw * 32, bool)
+    padded[:flat.size] = flat
+    w = padded.reshape(nw, 32).astype(np.uint64) << np.arange(32, dtype=np.uint64)
+    return w.sum(axis=1).astype(np.uint32)
+
+
+def voxel_mask(level_fields: np.ndarray, active, lo, hi) -> np.ndarray:
+    """uint8 [N]^3: 1 where every active field lies in its inclusive [lo, hi]."""
+    m = np.ones(level_fields.shape[1:], bool)
+    for f in range(level_fields.shape[0]):
+        if active[f]:
+            m &= (level_fields[f] >= F32(lo[f])) & (level_fields[f] <= F32(hi[f]))
+    return m.astype(np.uint8)
+
+
+# ----------------------------------------------------------------------------- LOD choice
+def select_lod(n0: int, n_lods: int, eye, fov_y_deg: float, height: int, r_outer: float = 1.0) -> int:
+    """Keep about one finest-level voxel per pixel: with P the projected diameter of the
+    outer sphere in pixels, lod = clamp(ceil(log2(N0/P)), 0, n_lods-1) when N0 > P, else 0;
+    an eye inside the outer sphere gets level 0."""
+    dist = math.sqrt(sum(float(e) ** 2 for e in eye))
+    if dist <= r_outer:
+        return 0
+    p = height * math.tan(math.asin(r_outer / dist)) / math.tan(math.radians(fov_y_deg) / 2)
+    if n0 <= p:
+        return 0
+    return int(min(max(math.ceil(math.log2(n0 / p)), 0), n_lods - 1))

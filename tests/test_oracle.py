@@ -1,0 +1,413 @@
+"""Pins for the FP64 oracle (CPU only).
+
+Each test ties the oracle to something other than itself: an independent
+brute-force implementation on tiny inputs, closed forms of the geometry and of
+the compositing integral, invariants the paper's brushing semantics imply
+(Section 2.2: a discarded sample contributes nothing to the ray's colour), and
+textbook facts (IEEE half precision, library trilinear interpolation).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.ndimage import map_coordinates
+
+import oracle
+from oracle import preprocess as pp
+from paper_2207_12011_amd import workloads as W
+
+from . import bruteforce as bf
+
+
+def const_tf(a0, rgb=(0.2, 0.5, 0.9)):
+    t = np.zeros((256, 4), np.float32)
+    t[:, :3] = rgb
+    t[:, 3] = a0
+    return t
+
+
+def axis_camera(dist=3.0, fov=60.0):
+    return np.array([dist, 0, 0, 0, 0, 0, 0, 0, 1, fov], np.float32)
+
+
+def chord(p, r_in=float(np.float32(0.55)), r_out=1.0):
+    """Length of a line at impact parameter p inside the shell r_in <= r <= r_out."""
+    if p >= r_out:
+        return 0.0
+    L = 2 * math.sqrt(r_out ** 2 - p ** 2)
+    if p < r_in:
+        L -= 2 * math.sqrt(r_in ** 2 - p ** 2)
+    return L
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return W.make_workload(0, n=16, width=16, height=16)
+
+
+# ----------------------------------------------------------------------------- brute force
+@pytest.mark.parametrize("brushed", [True, False])
+@pytest.mark.parametrize("step", [0.5, 1.3])
+def test_bruteforce_agrees(tiny, brushed, step):
+    wl = tiny
+    act = wl.brush.active if brushed else np.zeros(2, np.uint8)
+    kw = dict(active=act, lo=wl.brush.lo, hi=wl.brush.hi, tf_field=0, vmin=wl.tf.vmin, vmax=wl.tf.vmax,
+              tf_rgba=wl.tf.rgba, ert=0.99)
+    cam = wl.camera.as_array()
+    o = oracle.render(wl.fields, cam, 16, 16, step, **kw)
+    rgba, nom, comp = bf.render(wl.fields, cam, 16, 16, step, **kw)
+    assert np.abs(o.rgba - rgba).max() <= 1e-12
+    ok = (o.fragile & oracle.FRAGILE_ERT) == 0
+    assert np.array_equal(o.nominal[ok], nom[ok])
+    assert np.array_equal(o.composited[ok], comp[ok])
+    assert nom.sum() > 0 and (rgba[..., 3] > 0).sum() > 20
+
+
+def test_bruteforce_agrees_opaque_ert(tiny):
+    """A high-opacity table so that early termination fires on most rays."""
+    wl = tiny
+    tab = wl.tf.rgba.copy()
+    tab[:, 3] = np.linspace(0.3, 0.9, 256, dtype=np.float32)
+    kw = dict(active=np.zeros(2, np.uint8), lo=wl.brush.lo, hi=wl.brush.hi, tf_field=0, vmin=wl.tf.vmin,
+              vmax=wl.tf.vmax, tf_rgba=tab, ert=0.95)
+    cam = wl.camera.as_array()
+    o = oracle.render(wl.fields, cam, 16, 16, 0.5, **kw)
+    rgba, nom, comp = bf.render(wl.fields, cam, 16, 16, 0.5, **kw)
+    assert np.abs(o.rgba - rgba).max() <= 1e-12
+    ok = (o.fragile & oracle.FRAGILE_ERT) == 0
+    assert np.array_equal(o.nominal[ok], nom[ok])
+    assert (o.rgba[..., 3] >= 0.95).sum() > 50   # termination really happened
+
+
+def test_trilinear_matches_library():
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal((9, 9, 9)).astype(np.float32)
+    u = rng.uniform(-0.5, 8.5, (500, 3))           # includes the clamped half-voxel border
+    ref = map_coordinates(v.astype(np.float64), u[:, ::-1].T, order=1, mode="nearest", prefilter=False)
+    assert np.abs(oracle.trilinear(v, u) - ref).max() <= 1e-12
+
+
+def test_trilinear_affine_exact():
+    n = 12
+    c = W.cell_centres(n)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    f = (0.25 + 0.5 * x - 0.75 * y + 0.125 * z).astype(np.float32)
+    rng = np.random.default_rng(2)
+    u = rng.uniform(0.0, n - 1.0, (400, 3))
+    px = -1 + (u + 0.5) * (2.0 / n)
+    want = 0.25 + 0.5 * px[:, 0] - 0.75 * px[:, 1] + 0.125 * px[:, 2]
+    assert np.abs(oracle.trilinear(f, u) - want).max() <= 1e-6  # float32 storage of f
+    f64 = f.astype(np.float64)
+    # exact in the stored values: affine in index space
+    g = np.arange(n, dtype=np.float32)
+    zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+    h = (xx + 2 * yy + 4 * zz).astype(np.float32)
+    assert np.abs(oracle.trilinear(h, u) - (u[:, 0] + 2 * u[:, 1] + 4 * u[:, 2])).max() <= 1e-12
+    del f64
+
+
+# ----------------------------------------------------------------------------- closed forms
+def constant_volume(n=16, value=0.5, nf=1):
+    return np.full((nf, n, n, n), value, np.float32)
+
+
+def test_chord_lengths_closed_form():
+    """Sum of sample lengths equals the analytic chord through the shell, for every pixel."""
+    vol = constant_volume()
+    cam = axis_camera()
+    W_, H_ = 21, 17
+    o = oracle.render(vol, cam, W_, H_, 0.7, active=[0], lo=[0], hi=[1], tf_field=0, vmin=0, vmax=1,
+                      tf_rgba=const_tf(0.0), ert=1.0)
+    eye, dirs = bf.camera_rays(cam, W_, H_)
+    for py in range(H_):
+        for px in range(W_):
+            d = dirs[py, px]
+            p = np.linalg.norm(np.cross(eye, d))
+            assert abs(o.pathlen[py, px] - chord(p)) <= 1e-12
+
+
+def test_camera_centre_and_silhouette():
+    """Odd image: the centre ray passes through the origin (chord 2 (1 - 0.55)).  The hit
+    pixels are those whose angle from the view axis is below asin(1/3)."""
+    vol = constant_volume()
+    cam = axis_camera()
+    n = 31
+    o = oracle.render(vol, cam, n, n, 0.5, active=[0], lo=[0], hi=[1], tf_field=0, vmin=0, vmax=1,
+                      tf_rgba=const_tf(0.0), ert=1.0)
+    assert abs(o.pathlen[n // 2, n // 2] - 2 * (1 - float(np.float32(0.55)))) <= 1e-12
+    th = math.tan(math.radians(30))
+    ang_max = math.asin(1 / 3)
+    for py in range(n):
+        for px in range(n):
+            sx = (2 * (px + 0.5) / n - 1) * th
+            sy = (1 - 2 * (py + 0.5) / n) * th
+            ang = math.atan(math.hypot(sx, sy))
+            if abs(ang - ang_max) > 1e-3:
+                assert (o.pathlen[py, px] > 0) == (ang < ang_max)
+
+
+def test_camera_orientation():
+    """With up = +z, material at z > 0 shows in the top rows; with the eye on +x looking at
+    the origin, right = forward x up = +y, so +y material shows in the right columns."""
+    n = 16
+    c = W.cell_centres(n)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    top = (z > 0.2).astype(np.float32)[None]
+    lefty = (y > 0.2).astype(np.float32)[None]
+    kw = dict(active=[1], lo=[0.5], hi=[2.0], tf_field=0, vmin=0, vmax=1, tf_rgba=const_tf(0.5), ert=1.0)
+    a = oracle.render(top, axis_camera(), 32, 32, 0.5, **kw).rgba[..., 3]
+    assert a[:12].sum() > 0 and a[20:].sum() == 0
+    b = oracle.render(lefty, axis_camera(), 32, 32, 0.5, **kw).rgba[..., 3]
+    assert b[:, 20:].sum() > 0 and b[:, :12].sum() == 0
+
+
+@pytest.mark.parametrize("a0", [0.02, 0.3, 0.75])
+@pytest.mark.parametrize("step", [0.25, 0.5, 1.0])
+@pytest.mark.parametrize("radii", [(0.55, 1.0), (0.3, 0.9), (0.0, 0.8)])
+def test_constant_density_transmittance(a0, step, radii):
+    """Constant field and table, no brush, no termination: alpha = 1 - (1-A0)^(L/ref),
+    colour = rgb * alpha, with L the analytic chord."""
+    r_in, r_out = radii
+    vol = constant_volume(value=0.25)
+    cam = axis_camera()
+    rgb = np.array([0.2, 0.5, 0.9])
+    o = oracle.render(vol, cam, 15, 15, step, active=[0], lo=[0], hi=[1], tf_field=0, vmin=0, vmax=1,
+                      tf_rgba=const_tf(a0, rgb), ert=1.0, r_inner=r_in, r_outer=r_out)
+    eye, dirs = bf.camera_rays(cam, 15, 15)
+    ref = np.float32(2 / 256)
+    for py in range(15):
+        for px in range(15):
+            p = np.linalg.norm(np.cross(eye, dirs[py, px]))
+            L = chord(p, float(np.float32(r_in)), float(np.float32(r_out)))
+            want = 1 - (1 - float(np.float32(a0))) ** (L / float(ref))
+            assert abs(o.rgba[py, px, 3] - want) <= 1e-12
+            assert np.abs(o.rgba[py, px, :3] - rgb.astype(np.float32).astype(np.float64) * want).max() <= 1e-12
+
+
+def test_step_and_lod_invariance_constant_field():
+    base = constant_volume(n=32, value=0.5)
+    kw = dict(active=[0], lo=[0], hi=[1], tf_field=0, vmin=0, vmax=1, tf_rgba=const_tf(0.1), ert=1.0)
+    cam = axis_camera()
+    ref = oracle.render(base, cam, 24, 24, 0.5, **kw).rgba
+    for step in (0.25, 1.0, 2.0):
+        assert np.abs(oracle.render(base, cam, 24, 24, step, **kw).rgba - ref).max() <= 1e-12
+    levels = pp.build_levels(base[0], 3)
+    for lv in levels[1:]:
+        assert np.all(lv == np.float32(0.5))
+        assert np.abs(oracle.render(lv[None], cam, 24, 24, 0.5, **kw).rgba - ref).max() <= 1e-12
+
+
+def test_ert_closed_form():
+    """Centre ray along -x: first shell segment is t in [2, 2.45]; with a constant opacity the
+    ray stops after k* = ceil(ln(1-tau)/ln(1-alpha)) full samples."""
+    vol = constant_volume(value=0.5)
+    cam = axis_camera()
+    a0, step, tau = 0.3, 0.5, 0.99
+    o = oracle.render(vol, cam, 3, 3, step, active=[0], lo=[0], hi=[1], tf_field=0, vmin=0, vmax=1,
+                      tf_rgba=const_tf(a0), ert=tau)
+    ds = step * 2 / 16
+    a0f = float(np.float32(a0))
+    alpha = 1 - (1 - a0f) ** (ds / float(np.float32(2 / 256)))
+    k = math.ceil(math.log(1 - float(np.float32(tau))) / math.log(1 - alpha))
+    assert k * ds <= 0.45
+    assert o.nominal[1, 1] == k
+    assert abs(o.rgba[1, 1, 3] - (1 - (1 - alpha) ** k)) <= 1e-12
+
+
+def test_slab_brush_on_affine_field():
+    """Field = world x.  Brush x in [x0, x1] keeps exactly the samples whose midpoint lies in
+    the slab; T = (1-A0)^(kept length / ref) ~ exp(-sigma * slab length)."""
+    n = 32
+    c = W.cell_centres(n)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    fx = x.astype(np.float32)
+    colour = np.full_like(fx, 0.5)
+    vol = np.stack([fx, colour])
+    x0, x1 = np.float32(0.6), np.float32(0.9)
+    a0 = np.float32(0.2)
+    step = 0.5
+    o = oracle.render(vol, axis_camera(), 3, 3, step, active=[1, 0], lo=[x0, 0], hi=[x1, 0], tf_field=1,
+                      vmin=0, vmax=1, tf_rgba=const_tf(a0), ert=1.0)
+    # centre ray: x = 3 - t, first segment t in [2, 2.45], second t in [3.55, 4]
+    ds = step * 2 / n
+    kept = 0.0
+    for a, b in [(2.0, 2.45), (3.55, 4.0)]:
+        k = math.ceil((b - a) / ds - 1e-12)
+        for j in range(k):
+            t0, t1 = a + j * ds, min(a + (j + 1) * ds, b)
+            xm = 3 - 0.5 * (t0 + t1)
+            if x0 <= xm <= x1:
+                kept += t1 - t0
+    assert o.composited[1, 1] == round(kept / ds)
+    T = 1 - o.rgba[1, 1, 3]
+    assert abs(T - (1 - float(a0)) ** (kept / float(np.float32(2 / 256)))) <= 1e-12
+    sigma = -math.log(1 - float(a0)) / float(np.float32(2 / 256))
+    assert abs(math.log(T) + sigma * (float(x1) - float(x0))) <= sigma * 2 * ds
+
+
+# ----------------------------------------------------------------------------- invariants
+def test_inclusive_brush_equals_no_brush(tiny):
+    wl = tiny
+    cam = wl.camera.as_array()
+    kw = dict(tf_field=0, vmin=wl.tf.vmin, vmax=wl.tf.vmax, tf_rgba=wl.tf.rgba)
+    none = oracle.render(wl.fields, cam, 16, 16, 0.5, active=[0, 0], lo=[0, 0], hi=[0, 0], **kw)
+    inf = oracle.render(wl.fields, cam, 16, 16, 0.5, active=[1, 1], lo=[-np.inf] * 2, hi=[np.inf] * 2, **kw)
+    mn, mx = wl.fields.min(axis=(1, 2, 3)), wl.fields.max(axis=(1, 2, 3))
+    rng_ = oracle.render(wl.fields, cam, 16, 16, 0.5, active=[1, 1], lo=mn - 1e-3, hi=mx + 1e-3, **kw)
+    for o in (inf, rng_):
+        assert np.array_equal(o.rgba, none.rgba)
+        assert np.array_equal(o.nominal, none.nominal)
+
+
+def test_empty_brush_gives_background(tiny):
+    wl = tiny
+    cam = wl.camera.as_array()
+    kw = dict(tf_field=0, vmin=wl.tf.vmin, vmax=wl.tf.vmax, tf_rgba=wl.tf.rgba)
+    for lo, hi in ([[1, -np.inf], [0, np.inf]], [[wl.fields[0].max() + 1, -np.inf], [np.inf, np.inf]]):
+        o = oracle.render(wl.fields, cam, 16, 16, 0.5, active=[1, 1], lo=lo, hi=hi, **kw)
+        assert np.all(o.rgba == 0.0) and np.all(o.composited == 0)
+        bg = oracle.render(wl.fields, cam, 16, 16, 0.5, active=[1, 1], lo=lo, hi=hi,
+                           bg=[0.1, 0.2, 0.3, 1.0], **kw)
+        assert np.all(bg.rgba == np.array([0.1, 0.2, 0.3, 1.0], np.float32).astype(np.float64))
+
+
+def test_sample_count_definition():
+    """Nominal count per segment is ceil(length / step): sum over the image of ceil(L/ds)."""
+    vol = constant_volume(n=16)
+    cam = axis_camera()
+    o = oracle.render(vol, cam, 9, 9, 0.75, active=[0], lo=[0], hi=[1], tf_field=0, vmin=0, vmax=1,
+                      tf_rgba=const_tf(0.0), ert=1.0)
+    eye, dirs = bf.camera_rays(cam, 9, 9)
+    ds = float(np.float32(0.75)) * 2 / 16
+    for py in range(9):
+        for px in range(9):
+            want = sum(int(math.ceil((b - a) / ds)) for a, b in bf.segments(eye, dirs[py, px], 0.55, 1.0))
+            assert o.nominal[py, px] == want
+
+
+# ----------------------------------------------------------------------------- preprocessing
+def test_level_build_exact():
+    rng = np.random.default_rng(3)
+    q = rng.integers(-64, 64, (8, 8, 8)).astype(np.float32)
+    lv = pp.build_level(q)
+    for z in range(4):
+        for y in range(4):
+            for x in range(4):
+                want = q[2 * z:2 * z + 2, 2 * y:2 * y + 2, 2 * x:2 * x + 2].astype(np.float64).mean()
+                assert lv[z, y, x] == want           # small integers: every sum is exact
+    assert np.all(pp.build_level(np.full((8, 8, 8), 0.3, np.float32)) == np.float32(0.3))
+    assert lv.shape == (4, 4, 4) and pp.build_levels(q, 3)[2].shape == (2, 2, 2)
+
+
+def test_level_build_op_order():
+    """fl32(fl32(fl32((a+b)+(c+d)) + fl32((e+f)+(g+h))) * 0.125) differs from a naive
+    left-to-right sum on some inputs; the definition is the bracketed order."""
+    rng = np.random.default_rng(4)
+    v = (rng.standard_normal((16, 16, 16)) * 1e3).astype(np.float32)
+    lv = pp.build_level(v)
+    for z, y, x in [(0, 0, 0), (3, 5, 7), (7, 7, 7)]:
+        c = [v[2 * z + i, 2 * y + j, 2 * x + k] for i in range(2) for j in range(2) for k in range(2)]
+        f = np.float32
+        s = f(f(f(c[0] + c[1]) + f(c[2] + c[3])) + f(f(c[4] + c[5]) + f(c[6] + c[7])))
+        assert lv[z, y, x] == f(s * f(0.125))
+
+
+def test_f16_bit_patterns():
+    vals = np.array([1.0, 1 / 3, 65504.0, 2.0 ** -24, 2.0 ** -14, 1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11, -2.0,
+                     1.5e-5, 0.0], np.float32)
+    want = [0x3C00, 0x3555, 0x7BFF, 0x0001, 0x0400, 0x3C00, 0x3C02, 0xC000, 0x00FC, 0x0000]
+    assert list(pp.encode_f16(vals)) == want
+    assert pp.decode_f16(np.array([0x0001], np.uint16))[0] == np.float32(2.0 ** -24)
+
+
+def test_u8_roundtrip_and_bound():
+    rng = np.random.default_rng(5)
+    n = 16
+    # exactly representable: offset + 2^-6 * q per brick
+    q = rng.integers(0, 256, (n, n, n)).astype(np.float32)
+    q[0, 0, 0] = 0
+    q[7, 7, 7] = 255   # brick (0,0,0) spans the full code range
+    off = np.float32(0.5)
+    exact = (off + q * np.float32(2.0 ** -6)).astype(np.float32)
+    got = pp.stored_values(exact, "u8")
+    bz = slice(0, 8)
+    assert np.array_equal(got[bz, bz, bz], exact[bz, bz, bz])
+    v = rng.standard_normal((n, n, n)).astype(np.float32)
+    codes, scale, offset = pp.encode_u8(v)
+    dec = pp.decode_u8(codes, scale, offset)
+    s_full = np.repeat(np.repeat(np.repeat(scale, 8, 0), 8, 1), 8, 2)
+    assert np.all(np.abs(dec - v) <= 0.5 * s_full * (1 + 1e-5) + 1e-6)
+    c = np.full((8, 8, 8), 2.5, np.float32)
+    cq, cs, co = pp.encode_u8(c)
+    assert cs[0, 0, 0] == 0 and np.all(cq == 0) and np.all(pp.decode_u8(cq, cs, co) == np.float32(2.5))
+
+
+def test_minmax_bruteforce():
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal((24, 24, 24)).astype(np.float32)
+    mn, mx = pp.brick_minmax(v)
+    for bz in range(3):
+        for by in range(3):
+            for bx in range(3):
+                w = v[8 * bz:min(8 * bz + 9, 24), 8 * by:min(8 * by + 9, 24), 8 * bx:min(8 * bx + 9, 24)]
+                assert mn[bz, by, bx] == w.min() and mx[bz, by, bx] == w.max()
+
+
+def test_voxel_mask_enumeration(tiny):
+    wl = tiny
+    m = pp.voxel_mask(wl.fields, wl.brush.active, wl.brush.lo, wl.brush.hi)
+    n = wl.n
+    for z in range(0, n, 3):
+        for y in range(n):
+            for x in range(n):
+                want = all(wl.brush.lo[f] <= wl.fields[f, z, y, x] <= wl.brush.hi[f] for f in range(2))
+                assert m[z, y, x] == want
+
+
+def test_skip_bits_are_conservative():
+    """Every sample position whose clamped floor index lies in a skipped brick fails the brush
+    or has zero table opacity (dense random positions, FP64 trilinear)."""
+    wl = W.make_workload(0, n=32)
+    fields = wl.fields
+    mins, maxs = zip(*[pp.brick_minmax(fields[f]) for f in range(2)])
+    tab = wl.tf.rgba.copy()
+    tab[:60, 3] = 0.0     # zero opacity at the low end so that the table rule fires too
+    skip = pp.skip_bits(mins, maxs, wl.brush.active, wl.brush.lo, wl.brush.hi, 0, wl.tf.vmin, wl.tf.vmax, tab)
+    assert 0 < skip.sum() < skip.size
+    rng = np.random.default_rng(7)
+    u = rng.uniform(-0.5, 31.5, (200000, 3))
+    b = np.clip(np.floor(u), 0, 31).astype(int) >> 3
+    sel = skip[b[:, 2], b[:, 1], b[:, 0]]
+    us = u[sel]
+    v0 = oracle.trilinear(fields[0], us)
+    v1 = oracle.trilinear(fields[1], us)
+    passes = (v0 >= wl.brush.lo[0]) & (v0 <= wl.brush.hi[0]) & (v1 >= wl.brush.lo[1]) & (v1 <= wl.brush.hi[1])
+    x = np.clip((v0 - wl.tf.vmin) / (wl.tf.vmax - wl.tf.vmin), 0, 1) * 255
+    i = np.minimum(np.floor(x).astype(int), 254)
+    w = x - i
+    a = (1 - w) * tab[i, 3] + w * tab[i + 1, 3]
+    assert not np.any(passes & (a > 0))
+
+
+def test_skip_bits_extremes(tiny):
+    wl = tiny
+    mins, maxs = zip(*[pp.brick_minmax(wl.fields[f]) for f in range(2)])
+    empty = pp.skip_bits(mins, maxs, [1, 1], [1, 0], [0, 0], 0, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba)
+    assert empty.all()
+    none = pp.skip_bits(mins, maxs, [0, 0], [0, 0], [0, 0], 0, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba)
+    assert not none.any()
+    words = pp.pack_bits(np.array([1, 0, 0, 1] + [0] * 30 + [1], bool))
+    assert list(words) == [0b1001, 0b100]
+
+
+@pytest.mark.parametrize("n0,size,want", [(512, 256, 2), (512, 512, 1), (512, 1024, 0), (512, 2048, 0),
+                                          (256, 256, 1), (256, 512, 0), (256, 1080, 0)])
+def test_select_lod_table(n0, size, want):
+    eye = (3.0, 0.0, 0.0)
+    assert pp.select_lod(n0, 3, eye, 60.0, size) == want
+
+
+def test_select_lod_inside_and_clamp():
+    assert pp.select_lod(512, 3, (0.5, 0, 0), 60, 64) == 0
+    assert pp.select_lod(1024, 3, (3, 0, 0), 60, 32) == 2
+    assert pp.select_lod(1024, 1, (3, 0, 0), 60, 32) == 0
