@@ -1,0 +1,226 @@
+/*
+ * raypc.h -- C ABI of the brushed spherical-shell volume ray caster (gfx950).
+ *
+ * Method: direct volume ray casting of a multi-variable volume with
+ * parallel-coordinates brushing (paper, Section 2 and Section 2.2): every
+ * sample is tested against per-variable lower/upper bounds and a sample that
+ * fails any of them is discarded and contributes nothing to the ray's colour;
+ * samples that pass are classified through an RGBA transfer function on one
+ * variable and composited front to back.  The volume carries an octree
+ * level-of-detail pyramid with two coarser levels of 1/8 the cells each
+ * (Section 2.1) and is rendered in progressive passes (Section 2.2).
+ *
+ * Conventions shared by every call
+ *  - Return value: RAYPC_OK (0) or a RAYPC_ERR_* code.  No exception or
+ *    signal crosses the ABI.  raypc_last_error() gives a message for the last
+ *    failing call made by the calling thread.
+ *  - A failing call leaves the context state unchanged.
+ *  - Device pointers are HIP device addresses on the context's device;
+ *    "stream" is a hipStream_t (NULL = the default stream).  Calls named
+ *    "async" only enqueue work: outputs are valid once the stream is
+ *    synchronised.  Host pointers are only read during the call.
+ *  - A context is used by one host thread at a time.  State changes
+ *    (brush, transfer function, options) apply to renders enqueued after the
+ *    call; a render still in flight on another stream when its volume's brush
+ *    or skip list is rewritten races with it, so synchronise such streams
+ *    first.
+ *  - Grid: cubic N^3, cell centred over [-1,1]^3 (x_i = -1 + (i + 1/2) 2/N),
+ *    C order [z][y][x].  The shell is r_inner <= |x| <= r_outer; rays are
+ *    marched only inside it.
+ *  - Images: H x W x 4 float32, row 0 at the top, premultiplied RGBA.
+ */
+#ifndef RAYPC_H
+#define RAYPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RAYPC_OK = 0,
+    RAYPC_ERR_INVALID = 1,   /* bad argument; state unchanged */
+    RAYPC_ERR_NOMEM = 2,     /* device allocation failed / would exceed a budget */
+    RAYPC_ERR_DEVICE = 3,    /* a HIP runtime call failed; the context may be unusable */
+    RAYPC_ERR_BUSY = 4,      /* resource in use (e.g. unloading a volume with requests in flight) */
+    RAYPC_ERR_TIMEOUT = 5,   /* wait deadline passed */
+    RAYPC_ERR_CANCELLED = 6, /* request cancelled before it ran */
+    RAYPC_ERR_STATE = 7      /* call not valid in the current state (e.g. server not running) */
+};
+
+enum {
+    RAYPC_STORAGE_F32 = 0,     /* 4 bytes per value */
+    RAYPC_STORAGE_F16 = 1,     /* IEEE binary16, round to nearest even, subnormals kept */
+    RAYPC_STORAGE_U8_BRICK = 2 /* 8-bit codes with a (scale, offset) pair per 8^3 brick */
+};
+
+#define RAYPC_MAX_FIELDS 8
+#define RAYPC_MAX_LODS 3
+#define RAYPC_TF_ENTRIES 256
+#define RAYPC_TF_SLOTS 8
+#define RAYPC_BRICK 8
+
+typedef struct raypc_ctx raypc_ctx;
+
+/* Pinhole camera.  fov_y_deg is the vertical field of view in (0, 180);
+ * right = normalize(forward x up), true up = right x forward; pixel (px, py)
+ * looks through its centre. */
+typedef struct {
+    float eye[3];
+    float target[3];
+    float up[3];
+    float fov_y_deg;
+} raypc_camera;
+
+/* Create a context on HIP device `device`; *out receives it.  The context owns
+ * every device allocation it makes.  Errors: RAYPC_ERR_INVALID (bad device or
+ * NULL out), RAYPC_ERR_DEVICE. */
+int raypc_create(int device, raypc_ctx **out);
+
+/* Wait for the context's own work, stop its server if running and free
+ * everything it owns.  NULL is ignored. */
+void raypc_destroy(raypc_ctx *ctx);
+
+/* Message of the last failing call on this thread ("" if none).  Valid until
+ * the next call from the same thread. */
+const char *raypc_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int raypc_version(void);
+
+/*
+ * Load a multi-variable volume (paper, Section 1: a snapshot holds several
+ * output variables; Section 2.1: derived variables are added in
+ * preprocessing).
+ *   n_fields   1..8 variables; fields[f] points at N^3 float32 values.
+ *   n          N, a multiple of 32 in [32, 2048].
+ *   on_device  0: fields[] are host pointers (copied);  1: device pointers
+ *              (read only, e.g. torch tensors).
+ *   storage    RAYPC_STORAGE_*: how every level is kept in device memory.
+ *   n_lods     1..3 levels: level l+1 is the 2x2x2 mean of level l (float32,
+ *              fixed summation order), built from float32 data and only then
+ *              encoded (Section 2.1: two coarser levels with 1/8 the cells).
+ *   r_inner, r_outer  shell radii, 0 <= r_inner < r_outer <= 1.
+ *   stream     work is enqueued here; the call synchronises it before
+ *              returning, so inputs may be freed or reused afterwards.
+ *   volume_id  receives a handle (> 0).
+ * Builds, per level: the encoded brick-ordered field data and the per-brick
+ * (min, max) tables of the stored values over each brick's 9^3 window.  The
+ * brush starts empty-handed: no variable restricted.
+ * Errors: RAYPC_ERR_INVALID (argument out of range, NULL pointer, or a
+ * non-finite input value), RAYPC_ERR_NOMEM, RAYPC_ERR_DEVICE.
+ */
+int raypc_load_fields(raypc_ctx *ctx, int n_fields, int n, const float *const *fields, int on_device,
+                      int storage, int n_lods, float r_inner, float r_outer, void *stream, int *volume_id);
+
+/* Free a volume.  RAYPC_ERR_BUSY while serving requests reference it. */
+int raypc_unload(raypc_ctx *ctx, int volume_id);
+
+/* Describe a loaded volume.  Any output pointer may be NULL.  *bytes is the
+ * device memory it holds (field data, tables, skip lists). */
+int raypc_volume_info(const raypc_ctx *ctx, int volume_id, int *n_fields, int *n, int *n_lods, int *storage,
+                      uint64_t *bytes);
+
+/*
+ * Set the brush of a volume (paper, Section 2: upper and lower bounds for
+ * each variable, set in the parallel-coordinates plot; Section 2.2: the
+ * volume data is not modified and nothing is rebuilt).
+ *   active[f] != 0 restricts variable f to the inclusive interval
+ *   [lo[f], hi[f]]; inactive variables are not tested.  lo > hi selects
+ *   nothing; +-INFINITY bounds are allowed; NaN bounds are rejected.
+ * Copies the arrays; touches no device memory (the affected skip lists are
+ * recomputed by the next render).  Errors: RAYPC_ERR_INVALID.
+ */
+int raypc_set_brush(raypc_ctx *ctx, int volume_id, int n_fields, const uint8_t *active, const float *lo,
+                    const float *hi);
+
+/*
+ * Define transfer-function slot `slot` (0..7; slot 0 is the one raypc_render
+ * uses).  The colour comes from one variable (paper, Section 3: radial
+ * velocity, density anomaly or temperature anomaly colour the volume).
+ *   field       variable that is classified.
+ *   vmin < vmax value range mapped onto the table; values outside clamp.
+ *   rgba        n_entries x 4 straight (not premultiplied) colour and opacity,
+ *               each in [0, 1]; entry i sits at normalised value i/255 and the
+ *               table is interpolated linearly.
+ *   n_entries   must be 256.
+ *   ref_step    world-space length the table's opacity refers to (> 0);
+ *               a sample of length l gets alpha = 1 - (1 - A)^(l / ref_step).
+ * Waits for the device before replacing a table that kernels may read.
+ * Errors: RAYPC_ERR_INVALID.
+ */
+int raypc_set_transfer_function(raypc_ctx *ctx, int slot, int field, float vmin, float vmax, const float *rgba,
+                                int n_entries, float ref_step);
+
+/*
+ * Early ray termination threshold (default 0.99; >= 1 disables) and the
+ * background (NULL = transparent black, which keeps the output
+ * premultiplied).  With a background, out = C + (1 - A) bg_rgb,
+ * A_out = A + (1 - A) bg_a.  Errors: RAYPC_ERR_INVALID (threshold <= 0 or NaN,
+ * background outside [0, 1]).
+ */
+int raypc_set_options(raypc_ctx *ctx, float ert_threshold, const float *bg_rgba);
+
+/*
+ * Level-of-detail choice (paper, Section 2: a level-of-detail structure is
+ * used to raise rendering performance; the rule is this library's): with P
+ * the projected diameter of the outer sphere in pixels, the level is
+ * clamp(ceil(log2(N / P)), 0, n_lods - 1) when N > P and 0 otherwise, and 0
+ * when the eye is inside the outer sphere.  Pure host computation.
+ */
+int raypc_select_lod(const raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height,
+                     int *lod);
+
+/*
+ * Render one view (async).  lod = -1 picks the level with raypc_select_lod.
+ * step is the sample spacing in voxels of the rendered level, in [1/64, 64].
+ * rgba_out: device buffer of height*width*4 float32, written once per pixel.
+ * Uses the volume's brush, transfer-function slot 0 and the options.
+ * Errors: RAYPC_ERR_INVALID (width/height outside [1, 16384], bad lod, step,
+ * camera with NaN, fov outside (0, 180), up parallel to the view direction,
+ * slot 0 undefined or naming a field the volume lacks), RAYPC_ERR_NOMEM,
+ * RAYPC_ERR_DEVICE.
+ */
+int raypc_render(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height, int lod,
+                 float step, float *rgba_out, void *stream);
+
+/*
+ * Progressive passes (paper, Section 2.2: while the camera is stationary
+ * additional render passes raise the number of samples per pixel).  Pass k of
+ * n_passes (1..8) renders the full image at step * 2^(n_passes - 1 - k) into
+ * outs[k]; every pass equals raypc_render at that step (async).
+ */
+int raypc_render_progressive(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height,
+                             int lod, float step, int n_passes, float *const *outs, void *stream);
+
+/* ---------------------------------------------------------------- debug exports
+ * For parity tests and accounting.  All outputs are device buffers (async). */
+
+/* Stored (decoded) values of one level and field as float32 [z][y][x]. */
+int raypc_export_level(raypc_ctx *ctx, int volume_id, int lod, int field, float *out, void *stream);
+
+/* Per-brick (min, max) table of one level and field: nb^3 pairs of float32,
+ * bricks in [bz][by][bx] order (nb = N_l / 8). */
+int raypc_export_minmax(raypc_ctx *ctx, int volume_id, int lod, int field, float *out, void *stream);
+
+/* Skip bits of one level for the volume's brush and transfer slot `slot`:
+ * ceil(nb^3 / 32) uint32 words; brick k is bit k % 32 of word k / 32. */
+int raypc_export_skiplist(raypc_ctx *ctx, int volume_id, int lod, int slot, uint32_t *out, void *stream);
+
+/* Voxel brush mask of one level: N_l^3 bytes, 1 where every active variable
+ * lies in its [lo, hi]. */
+int raypc_export_voxel_mask(raypc_ctx *ctx, int volume_id, int lod, uint8_t *out, void *stream);
+
+/* raypc_render plus per-pixel sample counts: nominal = samples visited up to
+ * and including an early-termination stop; composited = samples that passed
+ * the brush with non-zero table opacity.  flags bit 0 disables empty-space
+ * skipping.  nominal / composited may be NULL. */
+int raypc_render_debug(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height, int lod,
+                       float step, float *rgba_out, uint32_t *nominal, uint32_t *composited, int flags,
+                       void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RAYPC_H */

@@ -1,0 +1,715 @@
+// api.hip -- host side of the C ABI declared in include/raypc.h.
+//
+// Owns the per-device context, the resident volumes (brick-ordered level data,
+// min/max tables, cached skip bits), brush / transfer-function / option state,
+// argument validation and error reporting, and the dispatch of the kernels in
+// preprocess.hip and raymarch.hip.  No compute happens on the host apart from
+// the camera basis, the level-of-detail choice and small table preparation.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/raypc.h"
+#include "internal.h"
+#include "server.h"
+
+using namespace raypc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? RAYPC_ERR_NOMEM : RAYPC_ERR_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                      \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Switches the calling thread to the context's device for the scope.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+namespace raypc {
+
+struct Level {
+    int n = 0, nb = 0;
+    void* data[kMaxFields] = {};
+    float2* par[kMaxFields] = {};
+    float2* mm[kMaxFields] = {};
+    uint32_t* skip = nullptr;
+    bool skip_valid = false;
+    uint64_t skip_brush_gen = 0, skip_tf_gen = 0;
+    int skip_slot = -1;
+    uint32_t n_bricks() const { return static_cast<uint32_t>(nb) * nb * nb; }
+    uint32_t n_words() const { return (n_bricks() + 31) / 32; }
+};
+
+struct Volume {
+    int id = 0, n = 0, nf = 0, n_lods = 0, storage = 0;
+    float r_in = 0.55f, r_out = 1.0f;
+    Level lv[RAYPC_MAX_LODS];
+    uint8_t active[kMaxFields] = {};
+    float lo[kMaxFields] = {}, hi[kMaxFields] = {};
+    uint64_t brush_gen = 1;
+    uint64_t bytes = 0;
+    std::vector<void*> allocs;
+    int refs = 0;  // serving requests in flight
+};
+
+struct TFSlot {
+    bool defined = false;
+    int field = 0;
+    float vmin = 0, vmax = 1, ref_step = 2.0f / 256;
+    float rgba[RAYPC_TF_ENTRIES * 4] = {};
+    uint64_t gen = 0;
+    float4* dev = nullptr;
+};
+
+}  // namespace raypc
+
+struct raypc_ctx {
+    int device = 0;
+    std::map<int, Volume*> vols;
+    int next_id = 1;
+    TFSlot tf[RAYPC_TF_SLOTS];
+    uint64_t tf_gen_counter = 0;
+    float ert = 0.99f;
+    float bg[4] = {0, 0, 0, 0};
+    bool has_bg = false;
+    std::mutex mu;  // guards state shared with the serving thread
+    Server* server = nullptr;
+};
+
+namespace {
+
+size_t storage_bytes(int storage) { return storage == kF32 ? 4 : (storage == kF16 ? 2 : 1); }
+
+void free_volume(Volume* v) {
+    for (void* p : v->allocs) (void)hipFree(p);
+    delete v;
+}
+
+int dev_alloc(Volume* v, void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(RAYPC_ERR_NOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    v->allocs.push_back(*p);
+    v->bytes += bytes;
+    return RAYPC_OK;
+}
+
+Volume* find_volume(const raypc_ctx* ctx, int id) {
+    auto it = ctx->vols.find(id);
+    return it == ctx->vols.end() ? nullptr : it->second;
+}
+
+bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// Camera basis in double precision, rounded to float for the kernels.
+int camera_setup(const raypc_camera* cam, int width, int height, RenderArgs& a) {
+    if (!cam) return fail(RAYPC_ERR_INVALID, "camera is NULL");
+    if (!finite3(cam->eye) || !finite3(cam->target) || !finite3(cam->up) || !std::isfinite(cam->fov_y_deg))
+        return fail(RAYPC_ERR_INVALID, "camera has a non-finite component");
+    if (!(cam->fov_y_deg > 0.0f && cam->fov_y_deg < 180.0f))
+        return fail(RAYPC_ERR_INVALID, "fov_y_deg %g outside (0, 180)", cam->fov_y_deg);
+    double f[3], u[3], r[3], t[3];
+    for (int k = 0; k < 3; ++k) {
+        f[k] = static_cast<double>(cam->target[k]) - cam->eye[k];
+        u[k] = cam->up[k];
+    }
+    const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    const double ul = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(fl > 0.0) || !(ul > 0.0)) return fail(RAYPC_ERR_INVALID, "camera eye == target or up is zero");
+    for (int k = 0; k < 3; ++k) f[k] /= fl;
+    r[0] = f[1] * u[2] - f[2] * u[1];
+    r[1] = f[2] * u[0] - f[0] * u[2];
+    r[2] = f[0] * u[1] - f[1] * u[0];
+    const double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(rl > 1e-6 * ul)) return fail(RAYPC_ERR_INVALID, "camera up is parallel to the view direction");
+    for (int k = 0; k < 3; ++k) r[k] /= rl;
+    t[0] = r[1] * f[2] - r[2] * f[1];
+    t[1] = r[2] * f[0] - r[0] * f[2];
+    t[2] = r[0] * f[1] - r[1] * f[0];
+    const double th = std::tan(0.5 * static_cast<double>(cam->fov_y_deg) * M_PI / 180.0);
+    double oo = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        a.eye[k] = cam->eye[k];
+        a.fwd[k] = static_cast<float>(f[k]);
+        a.right[k] = static_cast<float>(r[k]);
+        a.upv[k] = static_cast<float>(t[k]);
+        oo += static_cast<double>(cam->eye[k]) * cam->eye[k];
+    }
+    a.sx_scale = static_cast<float>(th * width / height);
+    a.sy_scale = static_cast<float>(th);
+    a.inv_w2 = static_cast<float>(2.0 / width);
+    a.inv_h2 = static_cast<float>(2.0 / height);
+    a.width = width;
+    a.height = height;
+    a.oo = static_cast<float>(oo);
+    return RAYPC_OK;
+}
+
+int select_lod_impl(const Volume* v, const raypc_camera* cam, int height, int* lod) {
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) d2 += static_cast<double>(cam->eye[k]) * cam->eye[k];
+    const double dist = std::sqrt(d2);
+    const double r = v->r_out;
+    if (dist <= r) {
+        *lod = 0;
+        return RAYPC_OK;
+    }
+    const double p = height * std::tan(std::asin(r / dist)) / std::tan(0.5 * cam->fov_y_deg * M_PI / 180.0);
+    if (!(v->n > p)) {
+        *lod = 0;
+        return RAYPC_OK;
+    }
+    const int l = static_cast<int>(std::ceil(std::log2(v->n / p)));
+    *lod = std::min(std::max(l, 0), v->n_lods - 1);
+    return RAYPC_OK;
+}
+
+// Recompute the skip bits of level l for the volume's brush and a transfer slot if stale.
+int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s) {
+    Level& L = v->lv[l];
+    const TFSlot& tf = ctx->tf[slot];
+    if (L.skip_valid && L.skip_brush_gen == v->brush_gen && L.skip_slot == slot && L.skip_tf_gen == tf.gen)
+        return RAYPC_OK;
+    SkipArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int k = 0;
+    for (int f = 0; f < v->nf; ++f) {
+        if (!v->active[f]) continue;
+        a.minmax[k] = L.mm[f];
+        a.lo[k] = v->lo[f];
+        a.hi[k] = v->hi[f];
+        ++k;
+    }
+    a.n_active = k;
+    a.tf_minmax = L.mm[tf.field];
+    a.vmin = tf.vmin;
+    a.inv_range = 1.0f / (tf.vmax - tf.vmin);
+    int nxt = RAYPC_TF_ENTRIES;
+    a.next_nonzero[RAYPC_TF_ENTRIES] = RAYPC_TF_ENTRIES;
+    for (int i = RAYPC_TF_ENTRIES - 1; i >= 0; --i) {
+        if (tf.rgba[4 * i + 3] > 0.0f) nxt = i;
+        a.next_nonzero[i] = nxt;
+    }
+    a.n_bricks = L.n_bricks();
+    a.out = L.skip;
+    HIP_TRY(launch_skip(a, s), "skip-list kernel launch");
+    L.skip_valid = true;
+    L.skip_brush_gen = v->brush_gen;
+    L.skip_slot = slot;
+    L.skip_tf_gen = tf.gen;
+    return RAYPC_OK;
+}
+
+int check_level(const Volume* v, int lod) {
+    if (lod < 0 || lod >= v->n_lods) return fail(RAYPC_ERR_INVALID, "lod %d outside [0, %d]", lod, v->n_lods - 1);
+    return RAYPC_OK;
+}
+
+}  // namespace
+
+// ============================================================================ internal entry used by serving
+namespace raypc {
+
+int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod, float step,
+                   const uint8_t* brush_active, const float* brush_lo, const float* brush_hi, int tf_slot,
+                   bool use_skip, float* rgba_out, RenderArgs& a, int& storage, Volume** vol_out,
+                   bool skip_from_volume, hipStream_t s);
+
+int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod, float step,
+                   const uint8_t* brush_active, const float* brush_lo, const float* brush_hi, int tf_slot,
+                   bool use_skip, float* rgba_out, RenderArgs& a, int& storage, Volume** vol_out,
+                   bool skip_from_volume, hipStream_t s) {
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    if (width < 1 || width > 16384 || height < 1 || height > 16384)
+        return fail(RAYPC_ERR_INVALID, "image size %dx%d outside [1, 16384]", width, height);
+    if (!(step >= 1.0f / 64.0f && step <= 64.0f)) return fail(RAYPC_ERR_INVALID, "step %g outside [1/64, 64]", step);
+    if (!rgba_out) return fail(RAYPC_ERR_INVALID, "rgba_out is NULL");
+    if (reinterpret_cast<uintptr_t>(rgba_out) % 16 != 0) return fail(RAYPC_ERR_INVALID, "rgba_out must be 16-byte aligned");
+    if (tf_slot < 0 || tf_slot >= RAYPC_TF_SLOTS || !ctx->tf[tf_slot].defined)
+        return fail(RAYPC_ERR_INVALID, "transfer-function slot %d is not defined", tf_slot);
+    const TFSlot& tf = ctx->tf[tf_slot];
+    if (tf.field >= v->nf)
+        return fail(RAYPC_ERR_INVALID, "transfer function classifies field %d but the volume has %d", tf.field, v->nf);
+    std::memset(&a, 0, sizeof(a));
+    int rc = camera_setup(cam, width, height, a);
+    if (rc) return rc;
+    if (lod == -1) select_lod_impl(v, cam, height, &lod);
+    rc = check_level(v, lod);
+    if (rc) return rc;
+    const Level& L = v->lv[lod];
+
+    int k = 0;
+    bool tf_brushed = false;
+    for (int f = 0; f < v->nf; ++f) {
+        if (!brush_active[f]) continue;
+        a.field[k] = L.data[f];
+        a.u8par[k] = L.par[f];
+        a.lo[k] = brush_lo[f];
+        a.hi[k] = brush_hi[f];
+        if (f == tf.field) {
+            a.tf_slot = k;
+            tf_brushed = true;
+        }
+        ++k;
+    }
+    a.n_brushed = k;
+    if (!tf_brushed) {
+        a.tf_slot = k;
+        a.field[k] = L.data[tf.field];
+        a.u8par[k] = L.par[tf.field];
+    }
+    a.n = L.n;
+    a.nb = L.nb;
+    a.half_n = 0.5f * static_cast<float>(L.n);
+    a.tf = tf.dev;
+    a.vmin = tf.vmin;
+    a.inv_range = 1.0f / (tf.vmax - tf.vmin);
+    a.inv_ref = 1.0f / tf.ref_step;
+    a.ert = ctx->ert;
+    a.ert_on = ctx->ert < 1.0f;
+    for (int c = 0; c < 4; ++c) a.bg[c] = ctx->bg[c];
+    a.has_bg = ctx->has_bg;
+    a.r_in2 = v->r_in * v->r_in;
+    a.r_out2 = v->r_out * v->r_out;
+    a.c_in = a.oo - a.r_in2;
+    a.c_out = a.oo - a.r_out2;
+    a.has_inner = v->r_in > 0.0f;
+    a.ds = step * (2.0f / static_cast<float>(L.n));
+    a.inv_ds = 1.0f / a.ds;
+    a.out = reinterpret_cast<float4*>(rgba_out);
+    a.blocks_x = (width + kBlockPix - 1) / kBlockPix;
+    a.n_blocks = a.blocks_x * ((height + kBlockPix - 1) / kBlockPix);
+    a.skip = nullptr;
+    if (use_skip && skip_from_volume) {
+        rc = ensure_skip(ctx, v, lod, tf_slot, s);
+        if (rc) return rc;
+        a.skip = v->lv[lod].skip;
+    }
+    storage = v->storage;
+    if (vol_out) *vol_out = v;
+    return RAYPC_OK;
+}
+
+Volume* lookup_volume(raypc_ctx* ctx, int id) { return find_volume(ctx, id); }
+int volume_nf(const Volume* v) { return v->nf; }
+int volume_ref(Volume* v, int delta) { return v->refs += delta; }
+std::mutex& ctx_mutex(raypc_ctx* ctx) { return ctx->mu; }
+int ctx_device(const raypc_ctx* ctx) { return ctx->device; }
+Server*& ctx_server(raypc_ctx* ctx) { return ctx->server; }
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+const Level& volume_level(const Volume* v, int l) { return v->lv[l]; }
+int volume_lods(const Volume* v) { return v->n_lods; }
+const TFSlot& ctx_tf(const raypc_ctx* ctx, int slot) { return ctx->tf[slot]; }
+
+}  // namespace raypc
+
+// ============================================================================ C ABI
+extern "C" {
+
+int raypc_version(void) { return 10000; }
+
+const char* raypc_last_error(void) { return g_last_error.c_str(); }
+
+int raypc_create(int device, raypc_ctx** out) {
+    if (!out) return fail(RAYPC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return fail(RAYPC_ERR_INVALID, "device %d outside [0, %d)", device, count);
+    DeviceGuard g(device);
+    raypc_ctx* ctx = new raypc_ctx();
+    ctx->device = device;
+    for (int s = 0; s < RAYPC_TF_SLOTS; ++s) {
+        e = hipMalloc(reinterpret_cast<void**>(&ctx->tf[s].dev), RAYPC_TF_ENTRIES * sizeof(float4));
+        if (e != hipSuccess) {
+            for (int t = 0; t < s; ++t) (void)hipFree(ctx->tf[t].dev);
+            delete ctx;
+            return hip_fail(e, "hipMalloc(transfer-function tables)");
+        }
+    }
+    *out = ctx;
+    return RAYPC_OK;
+}
+
+void raypc_destroy(raypc_ctx* ctx) {
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    server_shutdown(ctx);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->vols) free_volume(kv.second);
+    for (auto& t : ctx->tf) (void)hipFree(t.dev);
+    delete ctx;
+}
+
+int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* fields, int on_device, int storage,
+                      int n_lods, float r_inner, float r_outer, void* stream, int* volume_id) {
+    if (!ctx || !fields || !volume_id) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    if (n_fields < 1 || n_fields > RAYPC_MAX_FIELDS) return fail(RAYPC_ERR_INVALID, "n_fields %d outside [1, 8]", n_fields);
+    if (n < 32 || n > 1024 || n % 32 != 0) return fail(RAYPC_ERR_INVALID, "n %d must be a multiple of 32 in [32, 1024]", n);
+    if (storage < RAYPC_STORAGE_F32 || storage > RAYPC_STORAGE_U8_BRICK)
+        return fail(RAYPC_ERR_INVALID, "storage %d unknown", storage);
+    if (n_lods < 1 || n_lods > RAYPC_MAX_LODS) return fail(RAYPC_ERR_INVALID, "n_lods %d outside [1, 3]", n_lods);
+    if (!(r_inner >= 0.0f && r_inner < r_outer && r_outer <= 1.0f))
+        return fail(RAYPC_ERR_INVALID, "radii must satisfy 0 <= r_inner < r_outer <= 1");
+    for (int f = 0; f < n_fields; ++f)
+        if (!fields[f]) return fail(RAYPC_ERR_INVALID, "fields[%d] is NULL", f);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t nvox = static_cast<size_t>(n) * n * n;
+
+    Volume* v = new Volume();
+    v->n = n;
+    v->nf = n_fields;
+    v->n_lods = n_lods;
+    v->storage = storage;
+    v->r_in = r_inner;
+    v->r_out = r_outer;
+    for (int f = 0; f < n_fields; ++f) {
+        v->lo[f] = -INFINITY;
+        v->hi[f] = INFINITY;
+    }
+    int rc = RAYPC_OK;
+    // scratch: host-input staging (one field), two level buffers, a flag
+    std::vector<void*> tmp;
+    auto tmp_alloc = [&](void** p, size_t bytes) -> int {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RAYPC_ERR_NOMEM, "scratch allocation of %zu bytes failed", bytes);
+        }
+        tmp.push_back(*p);
+        return RAYPC_OK;
+    };
+    float* stage = nullptr;
+    float* lvbuf[2] = {nullptr, nullptr};
+    unsigned int* flag = nullptr;
+    do {
+        for (int l = 0; l < n_lods && !rc; ++l) {
+            Level& L = v->lv[l];
+            L.n = n >> l;
+            L.nb = L.n / kBrick;
+            const size_t lvox = static_cast<size_t>(L.n) * L.n * L.n;
+            for (int f = 0; f < n_fields && !rc; ++f) {
+                rc = dev_alloc(v, &L.data[f], lvox * storage_bytes(storage));
+                if (!rc && storage == kU8) rc = dev_alloc(v, reinterpret_cast<void**>(&L.par[f]), L.n_bricks() * sizeof(float2));
+                if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm[f]), L.n_bricks() * sizeof(float2));
+            }
+            if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip), L.n_words() * sizeof(uint32_t));
+        }
+        if (rc) break;
+        if (!on_device && (rc = tmp_alloc(reinterpret_cast<void**>(&stage), nvox * sizeof(float)))) break;
+        if (n_lods > 1 && (rc = tmp_alloc(reinterpret_cast<void**>(&lvbuf[0]), nvox / 8 * sizeof(float)))) break;
+        if (n_lods > 2 && (rc = tmp_alloc(reinterpret_cast<void**>(&lvbuf[1]), nvox / 64 * sizeof(float)))) break;
+        if ((rc = tmp_alloc(reinterpret_cast<void**>(&flag), sizeof(unsigned int)))) break;
+        hipError_t e = hipMemsetAsync(flag, 0, sizeof(unsigned int), s);
+        if (e != hipSuccess) { rc = hip_fail(e, "hipMemsetAsync"); break; }
+        for (int f = 0; f < n_fields && !rc; ++f) {
+            const float* src = fields[f];
+            if (!on_device) {
+                e = hipMemcpyAsync(stage, src, nvox * sizeof(float), hipMemcpyHostToDevice, s);
+                if (e != hipSuccess) { rc = hip_fail(e, "hipMemcpyAsync(field)"); break; }
+                src = stage;
+            }
+            if ((e = launch_count_nonfinite(src, nvox, flag, s)) != hipSuccess) { rc = hip_fail(e, "finite check"); break; }
+            const float* cur = src;
+            for (int l = 0; l < n_lods; ++l) {
+                Level& L = v->lv[l];
+                if (l > 0) {
+                    float* nxt = lvbuf[l - 1];
+                    if ((e = launch_lod_build(cur, v->lv[l - 1].n, nxt, s)) != hipSuccess) { rc = hip_fail(e, "level build"); break; }
+                    cur = nxt;
+                }
+                if ((e = launch_encode(cur, L.n, storage, L.data[f], L.par[f], s)) != hipSuccess) { rc = hip_fail(e, "encode"); break; }
+                if ((e = launch_minmax(L.data[f], L.par[f], L.n, storage, L.mm[f], s)) != hipSuccess) { rc = hip_fail(e, "min/max"); break; }
+            }
+        }
+        if (rc) break;
+        unsigned int h_flag = 0;
+        e = hipMemcpyAsync(&h_flag, flag, sizeof(h_flag), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { rc = hip_fail(e, "load synchronisation"); break; }
+        if (h_flag) rc = fail(RAYPC_ERR_INVALID, "input contains a non-finite value");
+    } while (0);
+    if (!tmp.empty()) (void)hipStreamSynchronize(s);
+    for (void* p : tmp) (void)hipFree(p);
+    if (rc) {
+        free_volume(v);
+        return rc;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    v->id = ctx->next_id++;
+    ctx->vols[v->id] = v;
+    *volume_id = v->id;
+    return RAYPC_OK;
+}
+
+int raypc_unload(raypc_ctx* ctx, int volume_id) {
+    if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    if (v->refs > 0) return fail(RAYPC_ERR_BUSY, "volume %d has %d serving requests in flight", volume_id, v->refs);
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->vols.erase(volume_id);
+    free_volume(v);
+    return RAYPC_OK;
+}
+
+int raypc_volume_info(const raypc_ctx* ctx, int volume_id, int* n_fields, int* n, int* n_lods, int* storage,
+                      uint64_t* bytes) {
+    if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
+    const Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    if (n_fields) *n_fields = v->nf;
+    if (n) *n = v->n;
+    if (n_lods) *n_lods = v->n_lods;
+    if (storage) *storage = v->storage;
+    if (bytes) *bytes = v->bytes;
+    return RAYPC_OK;
+}
+
+int raypc_set_brush(raypc_ctx* ctx, int volume_id, int n_fields, const uint8_t* active, const float* lo,
+                    const float* hi) {
+    if (!ctx || !active || !lo || !hi) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    if (n_fields != v->nf) return fail(RAYPC_ERR_INVALID, "brush has %d fields, volume has %d", n_fields, v->nf);
+    for (int f = 0; f < n_fields; ++f)
+        if (std::isnan(lo[f]) || std::isnan(hi[f])) return fail(RAYPC_ERR_INVALID, "NaN bound for field %d", f);
+    for (int f = 0; f < n_fields; ++f) {
+        v->active[f] = active[f] ? 1 : 0;
+        v->lo[f] = lo[f];
+        v->hi[f] = hi[f];
+    }
+    ++v->brush_gen;
+    return RAYPC_OK;
+}
+
+int raypc_set_transfer_function(raypc_ctx* ctx, int slot, int field, float vmin, float vmax, const float* rgba,
+                                int n_entries, float ref_step) {
+    if (!ctx || !rgba) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    if (slot < 0 || slot >= RAYPC_TF_SLOTS) return fail(RAYPC_ERR_INVALID, "slot %d outside [0, 8)", slot);
+    if (n_entries != RAYPC_TF_ENTRIES) return fail(RAYPC_ERR_INVALID, "n_entries must be 256");
+    if (field < 0 || field >= RAYPC_MAX_FIELDS) return fail(RAYPC_ERR_INVALID, "field %d outside [0, 8)", field);
+    if (!std::isfinite(vmin) || !std::isfinite(vmax) || !(vmax > vmin))
+        return fail(RAYPC_ERR_INVALID, "need finite vmin < vmax");
+    if (!std::isfinite(1.0f / (vmax - vmin))) return fail(RAYPC_ERR_INVALID, "value range too narrow");
+    if (!(ref_step > 0.0f) || !std::isfinite(ref_step)) return fail(RAYPC_ERR_INVALID, "ref_step must be > 0");
+    for (int i = 0; i < RAYPC_TF_ENTRIES * 4; ++i)
+        if (!(rgba[i] >= 0.0f && rgba[i] <= 1.0f)) return fail(RAYPC_ERR_INVALID, "table entry %d outside [0, 1]", i / 4);
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    TFSlot& t = ctx->tf[slot];
+    hipError_t e = hipDeviceSynchronize();  // kernels in flight may read the old table
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    e = hipMemcpy(t.dev, rgba, RAYPC_TF_ENTRIES * sizeof(float4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(transfer function)");
+    t.defined = true;
+    t.field = field;
+    t.vmin = vmin;
+    t.vmax = vmax;
+    t.ref_step = ref_step;
+    std::memcpy(t.rgba, rgba, sizeof(t.rgba));
+    t.gen = ++ctx->tf_gen_counter;
+    return RAYPC_OK;
+}
+
+int raypc_set_options(raypc_ctx* ctx, float ert_threshold, const float* bg_rgba) {
+    if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
+    if (!(ert_threshold > 0.0f)) return fail(RAYPC_ERR_INVALID, "ert_threshold must be > 0");
+    if (bg_rgba)
+        for (int c = 0; c < 4; ++c)
+            if (!(bg_rgba[c] >= 0.0f && bg_rgba[c] <= 1.0f)) return fail(RAYPC_ERR_INVALID, "background outside [0, 1]");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->ert = ert_threshold;
+    ctx->has_bg = bg_rgba != nullptr;
+    for (int c = 0; c < 4; ++c) ctx->bg[c] = bg_rgba ? bg_rgba[c] : 0.0f;
+    return RAYPC_OK;
+}
+
+int raypc_select_lod(const raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int* lod) {
+    if (!ctx || !cam || !lod) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    const Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    RenderArgs a;
+    int rc = camera_setup(cam, std::max(width, 1), std::max(height, 1), a);
+    if (rc) return rc;
+    if (width < 1 || height < 1) return fail(RAYPC_ERR_INVALID, "image size must be positive");
+    return select_lod_impl(v, cam, height, lod);
+}
+
+static int render_common(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
+                         float step, float* rgba_out, uint32_t* nominal, uint32_t* composited, bool counts,
+                         bool use_skip, void* stream) {
+    if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    RenderArgs a;
+    int storage = 0;
+    int rc = prepare_render(ctx, volume_id, cam, width, height, lod, step, v->active, v->lo, v->hi, 0, use_skip,
+                            rgba_out, a, storage, nullptr, true, s);
+    if (rc) return rc;
+    a.nominal = nominal;
+    a.composited = composited;
+    HIP_TRY(launch_render(a, storage, counts, s), "ray-march kernel launch");
+    return RAYPC_OK;
+}
+
+int raypc_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod, float step,
+                 float* rgba_out, void* stream) {
+    return render_common(ctx, volume_id, cam, width, height, lod, step, rgba_out, nullptr, nullptr, false, true, stream);
+}
+
+int raypc_render_debug(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
+                       float step, float* rgba_out, uint32_t* nominal, uint32_t* composited, int flags, void* stream) {
+    return render_common(ctx, volume_id, cam, width, height, lod, step, rgba_out, nominal, composited, true,
+                         (flags & 1) == 0, stream);
+}
+
+int raypc_render_progressive(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
+                             float step, int n_passes, float* const* outs, void* stream) {
+    if (!ctx || !outs) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    if (n_passes < 1 || n_passes > 8) return fail(RAYPC_ERR_INVALID, "n_passes %d outside [1, 8]", n_passes);
+    const float coarsest = std::ldexp(step, n_passes - 1);
+    if (!(step >= 1.0f / 64.0f && coarsest <= 64.0f))
+        return fail(RAYPC_ERR_INVALID, "pass steps %g..%g outside [1/64, 64]", coarsest, step);
+    for (int k = 0; k < n_passes; ++k)
+        if (!outs[k]) return fail(RAYPC_ERR_INVALID, "outs[%d] is NULL", k);
+    if (lod == -1) {
+        if (!cam) return fail(RAYPC_ERR_INVALID, "camera is NULL");
+        const Volume* v = find_volume(ctx, volume_id);
+        if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+        select_lod_impl(v, cam, height, &lod);
+    }
+    for (int k = 0; k < n_passes; ++k) {
+        const int rc = raypc_render(ctx, volume_id, cam, width, height, lod, std::ldexp(step, n_passes - 1 - k),
+                                    outs[k], stream);
+        if (rc) return rc;
+    }
+    return RAYPC_OK;
+}
+
+int raypc_export_level(raypc_ctx* ctx, int volume_id, int lod, int field, float* out, void* stream) {
+    if (!ctx || !out) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    DeviceGuard g(ctx->device);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    int rc = check_level(v, lod);
+    if (rc) return rc;
+    if (field < 0 || field >= v->nf) return fail(RAYPC_ERR_INVALID, "field %d outside [0, %d)", field, v->nf);
+    const Level& L = v->lv[lod];
+    HIP_TRY(launch_decode(L.data[field], L.par[field], L.n, v->storage, out, static_cast<hipStream_t>(stream)),
+            "decode kernel launch");
+    return RAYPC_OK;
+}
+
+int raypc_export_minmax(raypc_ctx* ctx, int volume_id, int lod, int field, float* out, void* stream) {
+    if (!ctx || !out) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    DeviceGuard g(ctx->device);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    int rc = check_level(v, lod);
+    if (rc) return rc;
+    if (field < 0 || field >= v->nf) return fail(RAYPC_ERR_INVALID, "field %d outside [0, %d)", field, v->nf);
+    const Level& L = v->lv[lod];
+    HIP_TRY(hipMemcpyAsync(out, L.mm[field], L.n_bricks() * sizeof(float2), hipMemcpyDeviceToDevice,
+                           static_cast<hipStream_t>(stream)),
+            "hipMemcpyAsync(min/max)");
+    return RAYPC_OK;
+}
+
+int raypc_export_skiplist(raypc_ctx* ctx, int volume_id, int lod, int slot, uint32_t* out, void* stream) {
+    if (!ctx || !out) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    int rc = check_level(v, lod);
+    if (rc) return rc;
+    if (slot < 0 || slot >= RAYPC_TF_SLOTS || !ctx->tf[slot].defined)
+        return fail(RAYPC_ERR_INVALID, "transfer-function slot %d is not defined", slot);
+    if (ctx->tf[slot].field >= v->nf) return fail(RAYPC_ERR_INVALID, "transfer function field outside the volume");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = ensure_skip(ctx, v, lod, slot, s);
+    if (rc) return rc;
+    const Level& L = v->lv[lod];
+    HIP_TRY(hipMemcpyAsync(out, L.skip, L.n_words() * sizeof(uint32_t), hipMemcpyDeviceToDevice, s),
+            "hipMemcpyAsync(skip list)");
+    return RAYPC_OK;
+}
+
+int raypc_export_voxel_mask(raypc_ctx* ctx, int volume_id, int lod, uint8_t* out, void* stream) {
+    if (!ctx || !out) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    DeviceGuard g(ctx->device);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    int rc = check_level(v, lod);
+    if (rc) return rc;
+    const Level& L = v->lv[lod];
+    MaskArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int k = 0;
+    for (int f = 0; f < v->nf; ++f) {
+        if (!v->active[f]) continue;
+        a.field[k] = L.data[f];
+        a.u8par[k] = L.par[f];
+        a.lo[k] = v->lo[f];
+        a.hi[k] = v->hi[f];
+        ++k;
+    }
+    a.n_active = k;
+    a.n = L.n;
+    a.nb = L.nb;
+    a.storage = v->storage;
+    a.out = out;
+    HIP_TRY(launch_voxel_mask(a, static_cast<hipStream_t>(stream)), "voxel-mask kernel launch");
+    return RAYPC_OK;
+}
+
+}  // extern "C"

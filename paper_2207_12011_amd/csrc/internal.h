@@ -1,0 +1,96 @@
+// internal.h -- declarations shared by the library's HIP translation units.
+// Not part of the public ABI (that is include/raypc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace raypc {
+
+constexpr int kMaxFields = 8;
+constexpr int kBrick = 8;           // brick edge in voxels
+constexpr int kBrickVoxels = 512;   // 8^3
+constexpr int kTileW = 8;           // one wave64 marches an 8 x 8 pixel tile
+constexpr int kBlockPix = 16;       // a 256-thread block covers 16 x 16 pixels (2 x 2 tiles)
+
+enum Storage : int { kF32 = 0, kF16 = 1, kU8 = 2 };
+
+// Brick-ordered address of voxel (x, y, z) on a level with nb bricks per axis:
+// bricks in [bz][by][bx] order, 512 voxels each, [z][y][x] inside a brick.
+__host__ __device__ inline uint32_t brick_addr(int x, int y, int z, int nb) {
+    uint32_t brick = (static_cast<uint32_t>(z >> 3) * nb + static_cast<uint32_t>(y >> 3)) * nb +
+                     static_cast<uint32_t>(x >> 3);
+    return (brick << 9) | (static_cast<uint32_t>(z & 7) << 6) | (static_cast<uint32_t>(y & 7) << 3) |
+           static_cast<uint32_t>(x & 7);
+}
+
+// ------------------------------------------------------------------ preprocessing launchers
+hipError_t launch_count_nonfinite(const float* x, size_t count, unsigned int* flag, hipStream_t s);
+// out[N/2]^3 = 2x2x2 mean of in[N]^3 (both linear [z][y][x] float32).
+hipError_t launch_lod_build(const float* in, int n, float* out, hipStream_t s);
+// Encode a linear float32 level into brick-ordered storage (u8 also writes per-brick (scale, offset)).
+hipError_t launch_encode(const float* in, int n, int storage, void* out, float2* u8par, hipStream_t s);
+// Per-brick (min, max) of stored values over the 9^3 apron window.
+hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, hipStream_t s);
+// Decode stored values back to linear [z][y][x] float32.
+hipError_t launch_decode(const void* data, const float2* u8par, int n, int storage, float* out, hipStream_t s);
+
+struct MaskArgs {
+    const void* field[kMaxFields];
+    const float2* u8par[kMaxFields];
+    float lo[kMaxFields], hi[kMaxFields];
+    int n_active;  // fields [0, n_active) of the arrays above are the active ones
+    int n, nb, storage;
+    uint8_t* out;  // linear [z][y][x]
+};
+hipError_t launch_voxel_mask(const MaskArgs& a, hipStream_t s);
+
+struct SkipArgs {
+    const float2* minmax[kMaxFields];  // active fields' (min, max) tables
+    float lo[kMaxFields], hi[kMaxFields];
+    int n_active;
+    const float2* tf_minmax;           // table of the transfer-function field
+    float vmin, inv_range;             // inv_range = fl32(1 / (vmax - vmin))
+    int next_nonzero[257];             // smallest entry index >= i with opacity > 0 (256 if none)
+    uint32_t n_bricks;
+    uint32_t* out;                     // ceil(n_bricks / 32) words
+};
+hipError_t launch_skip(const SkipArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------------ ray marcher
+struct RenderArgs {
+    // fields in "slot" order: slots [0, n_brushed) are brushed, the transfer-function field is
+    // slot tf_slot (< n_brushed when it is brushed itself, else == n_brushed)
+    const void* field[kMaxFields];
+    const float2* u8par[kMaxFields];
+    float lo[kMaxFields], hi[kMaxFields];
+    int n_brushed, tf_slot;
+    int n, nb;
+    float half_n;                 // N / 2: u = (p + 1) N/2 - 1/2
+    const uint32_t* skip;         // brick skip bits, or nullptr for no skipping
+    const float4* tf;             // 256 straight-RGBA entries
+    float vmin, inv_range;
+    float inv_ref;                // 1 / ref_step
+    float ert;                    // termination threshold (used only when ert_on)
+    int ert_on;
+    float bg[4];
+    int has_bg;
+    float eye[3], fwd[3], right[3], upv[3];
+    float sx_scale, sy_scale;     // tan(fov/2) * aspect, tan(fov/2)
+    float inv_w2, inv_h2;         // 2 / W, 2 / H
+    int width, height;
+    float oo;                     // |eye|^2
+    float r_in2, r_out2;          // squared radii
+    float c_in, c_out;            // |eye|^2 - r^2
+    int has_inner;
+    float ds, inv_ds;             // sample spacing (world units) and its reciprocal
+    float4* out;                  // H x W premultiplied RGBA
+    uint32_t* nominal;            // debug counts (only in the counting variant)
+    uint32_t* composited;
+    int blocks_x, n_blocks;       // 16 x 16 pixel blocks per row, total
+};
+hipError_t launch_render(const RenderArgs& a, int storage, bool counts, hipStream_t s);
+
+}  // namespace raypc

@@ -1,0 +1,253 @@
+// preprocess.hip -- one-off volume preparation and brush-time tables (gfx950).
+//
+//  * level build: the octree level-of-detail pyramid of the paper's
+//    preprocessing (Section 2.1, two coarser levels with 1/8 the cells):
+//    parent = fl32(fl32(fl32((a+b)+(c+d)) + fl32((e+f)+(g+h))) * 0.125),
+//    children in (z, y, x) lexicographic order, no contraction;
+//  * encode: float32 -> brick-ordered float32 / binary16 (nearest even) /
+//    8-bit codes with a per-8^3-brick (scale, offset): offset = brick min,
+//    scale = fl32((max - min) / 255), q = clamp(rint(fl32(fl32(v - offset) / scale)), 0, 255),
+//    decoded as fl32(fl32(scale * q) + offset);
+//  * brick (min, max) of decoded values over voxel indices [8b, min(8b+8, N-1)]
+//    per axis -- every voxel a sample whose clamped floor index lies in brick b
+//    can read;
+//  * skip bits (Section 2.2: brush changes rebuild nothing, so only this
+//    bit-per-brick table is recomputed): a brick is skipped when an active
+//    variable's brick range misses [lo, hi] (or lo > hi), or when the table
+//    opacity is zero over every entry the transfer-function variable's brick
+//    range can address;
+//  * voxel brush masks and decoded exports for parity checks.
+// Everything here is streaming work over HBM; none of it is on the per-frame path
+// except the skip bits, which touch only the small min/max tables.
+#include <hip/hip_fp16.h>
+
+#include "internal.h"
+
+namespace raypc {
+namespace {
+
+template <int S>
+__device__ __forceinline__ float stored(const void* base, const float2* par, uint32_t a) {
+    if constexpr (S == kF32) {
+        return static_cast<const float*>(base)[a];
+    } else if constexpr (S == kF16) {
+        return __half2float(static_cast<const __half*>(base)[a]);
+    } else {
+        const float q = static_cast<float>(static_cast<const uint8_t*>(base)[a]);
+        const float2 p = par[a >> 9];
+        return __fadd_rn(__fmul_rn(p.x, q), p.y);
+    }
+}
+
+__global__ void count_nonfinite_kernel(const float* __restrict__ x, size_t count, unsigned int* flag) {
+    size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    bool bad = false;
+    for (; i < count; i += stride) bad |= !isfinite(x[i]);
+    if (__any(bad) && bad) atomicOr(flag, 1u);
+}
+
+__global__ void lod_build_kernel(const float* __restrict__ in, int n, float* __restrict__ out) {
+    const int m = n >> 1;
+    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t total = static_cast<uint32_t>(m) * m * m;
+    if (o >= total) return;
+    const int x = o % m, y = (o / m) % m, z = o / (static_cast<uint32_t>(m) * m);
+    const size_t nn = static_cast<size_t>(n);
+    const size_t base = ((2 * static_cast<size_t>(z)) * nn + 2 * y) * nn + 2 * x;
+    const size_t dy = nn, dz = nn * nn;
+    const float a = in[base], b = in[base + 1];
+    const float c = in[base + dy], d = in[base + dy + 1];
+    const float e = in[base + dz], f = in[base + dz + 1];
+    const float g = in[base + dz + dy], h = in[base + dz + dy + 1];
+    const float s0 = __fadd_rn(__fadd_rn(a, b), __fadd_rn(c, d));
+    const float s1 = __fadd_rn(__fadd_rn(e, f), __fadd_rn(g, h));
+    out[o] = __fmul_rn(__fadd_rn(s0, s1), 0.125f);
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
+}
+
+// One 512-thread block per brick; thread t is the brick-local voxel t.
+template <int S>
+__global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ in, int n, void* __restrict__ out,
+                                                     float2* __restrict__ u8par) {
+    const int nb = n >> 3;
+    const uint32_t brick = blockIdx.x;
+    const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
+    const int t = threadIdx.x;
+    const int x = bx * 8 + (t & 7), y = by * 8 + ((t >> 3) & 7), z = bz * 8 + (t >> 6);
+    const size_t nn = static_cast<size_t>(n);
+    const float v = in[(static_cast<size_t>(z) * nn + y) * nn + x];
+    const uint32_t a = (brick << 9) | t;
+    if constexpr (S == kF32) {
+        static_cast<float*>(out)[a] = v;
+    } else if constexpr (S == kF16) {
+        static_cast<__half*>(out)[a] = __float2half_rn(v);
+    } else {
+        __shared__ float smin[8], smax[8];
+        float mn = wave_min(v), mx = wave_max(v);
+        const int w = t >> 6;
+        if ((t & 63) == 0) {
+            smin[w] = mn;
+            smax[w] = mx;
+        }
+        __syncthreads();
+        mn = smin[0];
+        mx = smax[0];
+        for (int k = 1; k < 8; ++k) {
+            mn = fminf(mn, smin[k]);
+            mx = fmaxf(mx, smax[k]);
+        }
+        const float scale = __fdiv_rn(__fsub_rn(mx, mn), 255.0f);
+        float q = 0.0f;
+        if (scale > 0.0f) q = fminf(fmaxf(rintf(__fdiv_rn(__fsub_rn(v, mn), scale)), 0.0f), 255.0f);
+        static_cast<uint8_t*>(out)[a] = static_cast<uint8_t>(q);
+        if (t == 0) u8par[brick] = make_float2(scale, mn);
+    }
+}
+
+// One wave per brick: min / max over the 9^3 apron window of stored values.
+template <int S>
+__global__ __launch_bounds__(64) void minmax_kernel(const void* __restrict__ data, const float2* __restrict__ par,
+                                                    int n, float2* __restrict__ out) {
+    const int nb = n >> 3;
+    const uint32_t brick = blockIdx.x;
+    const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
+    float mn = INFINITY, mx = -INFINITY;
+    for (int k = threadIdx.x; k < 729; k += 64) {
+        const int x = min(bx * 8 + k % 9, n - 1);
+        const int y = min(by * 8 + (k / 9) % 9, n - 1);
+        const int z = min(bz * 8 + k / 81, n - 1);
+        const float v = stored<S>(data, par, brick_addr(x, y, z, nb));
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (threadIdx.x == 0) out[brick] = make_float2(mn, mx);
+}
+
+template <int S>
+__global__ void decode_kernel(const void* __restrict__ data, const float2* __restrict__ par, int n,
+                              float* __restrict__ out) {
+    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t total = static_cast<uint32_t>(n) * n * n;
+    if (o >= total) return;
+    const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
+    out[o] = stored<S>(data, par, brick_addr(x, y, z, n >> 3));
+}
+
+template <int S>
+__global__ void voxel_mask_kernel(MaskArgs a) {
+    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t total = static_cast<uint32_t>(a.n) * a.n * a.n;
+    if (o >= total) return;
+    const int x = o % a.n, y = (o / a.n) % a.n, z = o / (static_cast<uint32_t>(a.n) * a.n);
+    const uint32_t addr = brick_addr(x, y, z, a.nb);
+    bool keep = true;
+    for (int f = 0; f < a.n_active; ++f) {
+        const float v = stored<S>(a.field[f], a.u8par[f], addr);
+        keep = keep && (v >= a.lo[f]) && (v <= a.hi[f]);
+    }
+    a.out[o] = keep ? 1 : 0;
+}
+
+// One thread per brick; a wave ballot packs 64 skip flags into two words.
+__global__ __launch_bounds__(256) void skip_kernel(SkipArgs a) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    bool skip = false;
+    if (b < a.n_bricks) {
+        for (int f = 0; f < a.n_active; ++f) {
+            const float2 mm = a.minmax[f][b];
+            skip |= (mm.y < a.lo[f]) | (mm.x > a.hi[f]) | (a.lo[f] > a.hi[f]);
+        }
+        const float2 tm = a.tf_minmax[b];
+        const float t0 = fminf(fmaxf(__fmul_rn(__fsub_rn(tm.x, a.vmin), a.inv_range), 0.0f), 1.0f);
+        const float t1 = fminf(fmaxf(__fmul_rn(__fsub_rn(tm.y, a.vmin), a.inv_range), 0.0f), 1.0f);
+        const int i0 = static_cast<int>(floorf(__fmul_rn(t0, 255.0f)));
+        const int i1 = min(static_cast<int>(ceilf(__fmul_rn(t1, 255.0f))), 255);
+        skip |= a.next_nonzero[i0] > i1;
+    }
+    const unsigned long long m = __ballot(skip);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t word = (b - lane) >> 5;  // first of the wave's two words
+    const uint32_t n_words = (a.n_bricks + 31) >> 5;
+    if (lane == 0 && word < n_words) a.out[word] = static_cast<uint32_t>(m);
+    if (lane == 32 && word + 1 < n_words) a.out[word + 1] = static_cast<uint32_t>(m >> 32);
+}
+
+inline unsigned blocks_for(size_t count, unsigned threads) {
+    return static_cast<unsigned>((count + threads - 1) / threads);
+}
+
+}  // namespace
+
+hipError_t launch_count_nonfinite(const float* x, size_t count, unsigned int* flag, hipStream_t s) {
+    const unsigned blocks = static_cast<unsigned>(std::min<size_t>(blocks_for(count, 256), 8192));
+    hipLaunchKernelGGL(count_nonfinite_kernel, dim3(std::max(blocks, 1u)), dim3(256), 0, s, x, count, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_lod_build(const float* in, int n, float* out, hipStream_t s) {
+    const size_t m = static_cast<size_t>(n / 2);
+    hipLaunchKernelGGL(lod_build_kernel, dim3(blocks_for(m * m * m, 256)), dim3(256), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode(const float* in, int n, int storage, void* out, float2* u8par, hipStream_t s) {
+    const unsigned nbr = static_cast<unsigned>((n / 8) * (n / 8) * (n / 8));
+    switch (storage) {
+        case kF32: hipLaunchKernelGGL(encode_kernel<kF32>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par); break;
+        case kF16: hipLaunchKernelGGL(encode_kernel<kF16>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par); break;
+        default: hipLaunchKernelGGL(encode_kernel<kU8>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, hipStream_t s) {
+    const unsigned nbr = static_cast<unsigned>((n / 8) * (n / 8) * (n / 8));
+    switch (storage) {
+        case kF32: hipLaunchKernelGGL(minmax_kernel<kF32>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out); break;
+        case kF16: hipLaunchKernelGGL(minmax_kernel<kF16>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out); break;
+        default: hipLaunchKernelGGL(minmax_kernel<kU8>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_decode(const void* data, const float2* u8par, int n, int storage, float* out, hipStream_t s) {
+    const size_t total = static_cast<size_t>(n) * n * n;
+    const dim3 g(blocks_for(total, 256));
+    switch (storage) {
+        case kF32: hipLaunchKernelGGL(decode_kernel<kF32>, g, dim3(256), 0, s, data, u8par, n, out); break;
+        case kF16: hipLaunchKernelGGL(decode_kernel<kF16>, g, dim3(256), 0, s, data, u8par, n, out); break;
+        default: hipLaunchKernelGGL(decode_kernel<kU8>, g, dim3(256), 0, s, data, u8par, n, out); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_voxel_mask(const MaskArgs& a, hipStream_t s) {
+    const size_t total = static_cast<size_t>(a.n) * a.n * a.n;
+    const dim3 g(blocks_for(total, 256));
+    switch (a.storage) {
+        case kF32: hipLaunchKernelGGL(voxel_mask_kernel<kF32>, g, dim3(256), 0, s, a); break;
+        case kF16: hipLaunchKernelGGL(voxel_mask_kernel<kF16>, g, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(voxel_mask_kernel<kU8>, g, dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_skip(const SkipArgs& a, hipStream_t s) {
+    // whole waves only, so that every ballot covers 64 consecutive bricks
+    const unsigned blocks = blocks_for(a.n_bricks, 256);
+    hipLaunchKernelGGL(skip_kernel, dim3(std::max(blocks, 1u)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace raypc

@@ -1,0 +1,10 @@
+// server.h -- continuous-batching request loop (internal).
+#pragma once
+
+#include "../../include/raypc.h"
+
+namespace raypc {
+struct Server;
+// Stop the context's server if one runs; waits for requests on the device.
+void server_shutdown(raypc_ctx* ctx);
+}  // namespace raypc

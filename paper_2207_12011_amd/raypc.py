@@ -1,0 +1,300 @@
+"""Python binding of libraypc.so -- argument marshalling only.
+
+Each function wraps the C entry point of the same name in include/raypc.h
+(``render`` wraps ``raypc_render`` and so on).  Device buffers are torch CUDA
+tensors (passed by ``data_ptr()``) and streams are torch streams (passed by
+their HIP handle); torch provides memory and streams, every step of the
+rendering runs in the library's HIP kernels.  There is no fallback: if the
+library is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # must load before libraypc.so so that one HIP runtime serves both
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libraypc.so")
+
+OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_BUSY, ERR_TIMEOUT, ERR_CANCELLED, ERR_STATE = range(8)
+STORAGE = {"f32": 0, "f16": 1, "u8": 2}
+MAX_FIELDS = 8
+TF_ENTRIES = 256
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "or `python paper_2207_12011_amd/build.py`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_F = ctypes.c_float
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", _F * 3), ("target", _F * 3), ("up", _F * 3), ("fov_y_deg", _F)]
+
+    @staticmethod
+    def make(cam) -> "Camera":
+        """From a 10-vector [eye, target, up, fov_y_deg] or an object with those attributes."""
+        if hasattr(cam, "eye"):
+            v = list(cam.eye) + list(cam.target) + list(cam.up) + [cam.fov_y_deg]
+        else:
+            v = [float(x) for x in cam]
+        c = Camera()
+        c.eye[:] = v[0:3]
+        c.target[:] = v[3:6]
+        c.up[:] = v[6:9]
+        c.fov_y_deg = v[9]
+        return c
+
+
+def _sig(name, restype, *argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(argtypes)
+    return f
+
+
+_create = _sig("raypc_create", _I, _I, ctypes.POINTER(_P))
+_destroy = _sig("raypc_destroy", None, _P)
+_last_error = _sig("raypc_last_error", ctypes.c_char_p)
+_version = _sig("raypc_version", _I)
+_load_fields = _sig("raypc_load_fields", _I, _P, _I, _I, _P, _I, _I, _I, _F, _F, _P, ctypes.POINTER(_I))
+_unload = _sig("raypc_unload", _I, _P, _I)
+_volume_info = _sig("raypc_volume_info", _I, _P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
+                    ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_uint64))
+_set_brush = _sig("raypc_set_brush", _I, _P, _I, _I, _P, _P, _P)
+_set_tf = _sig("raypc_set_transfer_function", _I, _P, _I, _I, _F, _F, _P, _I, _F)
+_set_options = _sig("raypc_set_options", _I, _P, _F, _P)
+_select_lod = _sig("raypc_select_lod", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, ctypes.POINTER(_I))
+_render = _sig("raypc_render", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P)
+_render_prog = _sig("raypc_render_progressive", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _I, _P, _P)
+_export_level = _sig("raypc_export_level", _I, _P, _I, _I, _I, _P, _P)
+_export_minmax = _sig("raypc_export_minmax", _I, _P, _I, _I, _I, _P, _P)
+_export_skip = _sig("raypc_export_skiplist", _I, _P, _I, _I, _I, _P, _P)
+_export_mask = _sig("raypc_export_voxel_mask", _I, _P, _I, _I, _P, _P)
+_render_debug = _sig("raypc_render_debug", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _I, _P)
+
+EXPORTED = ["raypc_create", "raypc_destroy", "raypc_last_error", "raypc_version", "raypc_load_fields",
+            "raypc_unload", "raypc_volume_info", "raypc_set_brush", "raypc_set_transfer_function",
+            "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
+            "raypc_export_level", "raypc_export_minmax", "raypc_export_skiplist", "raypc_export_voxel_mask",
+            "raypc_render_debug"]
+
+
+class RaypcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"raypc error {code}: {msg}")
+        self.code = code
+
+
+def last_error() -> str:
+    return (_last_error() or b"").decode()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise RaypcError(rc, last_error())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def _dptr(t: torch.Tensor, dtype, numel: int, what: str) -> int:
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"{what} must be a contiguous CUDA tensor of {dtype}")
+    if t.numel() < numel:
+        raise ValueError(f"{what} holds {t.numel()} elements, needs {numel}")
+    return t.data_ptr()
+
+
+def version() -> int:
+    return _version()
+
+
+# ----------------------------------------------------------------------------- context
+def create(device: int = 0):
+    h = _P()
+    _check(_create(int(device), ctypes.byref(h)))
+    return h
+
+
+def destroy(ctx) -> None:
+    _destroy(ctx)
+
+
+def load_fields(ctx, fields, storage: str = "f32", n_lods: int = 3, r_inner: float = 0.55,
+                r_outer: float = 1.0, stream=None) -> int:
+    """`fields`: float32 [F, N, N, N] as a numpy array (host copy) or a CUDA tensor, or a list of
+    per-field arrays/tensors."""
+    seq = list(fields) if not isinstance(fields, (np.ndarray, torch.Tensor)) else [fields[i] for i in range(fields.shape[0])]
+    if not seq:
+        raise ValueError("no fields")
+    on_device = isinstance(seq[0], torch.Tensor) and seq[0].is_cuda
+    n = int(seq[0].shape[0])
+    for f in seq:
+        if tuple(f.shape) != (n, n, n):
+            raise ValueError(f"every field must have shape ({n}, {n}, {n}), got {tuple(f.shape)}")
+    keep = []
+    ptrs = []
+    for f in seq:
+        if on_device:
+            if not (isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float32 and f.is_contiguous()):
+                raise TypeError("device fields must be contiguous float32 CUDA tensors")
+            ptrs.append(f.data_ptr())
+        else:
+            a = np.ascontiguousarray(np.asarray(f), dtype=np.float32)
+            keep.append(a)
+            ptrs.append(a.ctypes.data)
+    arr = (_P * len(ptrs))(*ptrs)
+    vid = _I()
+    _check(_load_fields(ctx, len(ptrs), n, ctypes.cast(arr, _P), 1 if on_device else 0, STORAGE[storage],
+                        int(n_lods), float(r_inner), float(r_outer), _stream(stream), ctypes.byref(vid)))
+    return vid.value
+
+
+def unload(ctx, volume_id: int) -> None:
+    _check(_unload(ctx, int(volume_id)))
+
+
+def volume_info(ctx, volume_id: int) -> dict:
+    nf, n, nl, st = _I(), _I(), _I(), _I()
+    by = ctypes.c_uint64()
+    _check(_volume_info(ctx, int(volume_id), ctypes.byref(nf), ctypes.byref(n), ctypes.byref(nl), ctypes.byref(st),
+                        ctypes.byref(by)))
+    return {"n_fields": nf.value, "n": n.value, "n_lods": nl.value, "storage": st.value, "bytes": by.value}
+
+
+def set_brush(ctx, volume_id: int, active, lo, hi) -> None:
+    a = np.ascontiguousarray(np.asarray(active, np.uint8))
+    l = np.ascontiguousarray(np.asarray(lo, np.float32))
+    h = np.ascontiguousarray(np.asarray(hi, np.float32))
+    _check(_set_brush(ctx, int(volume_id), int(a.size), a.ctypes.data, l.ctypes.data, h.ctypes.data))
+
+
+def set_transfer_function(ctx, slot: int, field: int, vmin: float, vmax: float, rgba,
+                          ref_step: float = 2.0 / 256) -> None:
+    t = np.ascontiguousarray(np.asarray(rgba, np.float32).reshape(-1))
+    _check(_set_tf(ctx, int(slot), int(field), float(vmin), float(vmax), t.ctypes.data, int(t.size // 4),
+                   float(ref_step)))
+
+
+def set_options(ctx, ert: float = 0.99, bg=None) -> None:
+    b = None if bg is None else np.ascontiguousarray(np.asarray(bg, np.float32))
+    _check(_set_options(ctx, float(ert), None if b is None else b.ctypes.data))
+
+
+def select_lod(ctx, volume_id: int, camera, width: int, height: int) -> int:
+    out = _I()
+    _check(_select_lod(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height),
+                       ctypes.byref(out)))
+    return out.value
+
+
+# ----------------------------------------------------------------------------- rendering
+def _image(out, width, height, device):
+    if out is None:
+        out = torch.empty((height, width, 4), dtype=torch.float32, device=device)
+    _dptr(out, torch.float32, width * height * 4, "out")
+    return out
+
+
+def render(ctx, volume_id: int, camera, width: int, height: int, lod: int = -1, step: float = 0.5,
+           out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Async render into `out` (allocated as [H, W, 4] float32 when None)."""
+    out = _image(out, width, height, "cuda")
+    _check(_render(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height), int(lod),
+                   float(step), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def render_progressive(ctx, volume_id: int, camera, width: int, height: int, lod: int = -1, step: float = 0.5,
+                       n_passes: int = 3, outs: Optional[Sequence[torch.Tensor]] = None, stream=None):
+    if outs is None:
+        outs = [torch.empty((height, width, 4), dtype=torch.float32, device="cuda") for _ in range(n_passes)]
+    ptrs = (_P * n_passes)(*[_dptr(o, torch.float32, width * height * 4, "outs[k]") for o in outs])
+    _check(_render_prog(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height), int(lod),
+                        float(step), int(n_passes), ctypes.cast(ptrs, _P), _stream(stream)))
+    return list(outs)
+
+
+def render_debug(ctx, volume_id: int, camera, width: int, height: int, lod: int = -1, step: float = 0.5,
+                 skip: bool = True, stream=None):
+    """(rgba [H,W,4] f32, nominal [H,W] i32, composited [H,W] i32) as CUDA tensors (async)."""
+    out = torch.empty((height, width, 4), dtype=torch.float32, device="cuda")
+    nom = torch.empty((height, width), dtype=torch.int32, device="cuda")
+    comp = torch.empty((height, width), dtype=torch.int32, device="cuda")
+    _check(_render_debug(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height), int(lod),
+                         float(step), out.data_ptr(), nom.data_ptr(), comp.data_ptr(), 0 if skip else 1,
+                         _stream(stream)))
+    return out, nom, comp
+
+
+# ----------------------------------------------------------------------------- exports
+def export_level(ctx, volume_id: int, lod: int, field: int, stream=None) -> torch.Tensor:
+    info = volume_info(ctx, volume_id)
+    n = info["n"] >> lod
+    out = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+    _check(_export_level(ctx, int(volume_id), int(lod), int(field), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def export_minmax(ctx, volume_id: int, lod: int, field: int, stream=None) -> torch.Tensor:
+    nb = (volume_info(ctx, volume_id)["n"] >> lod) // 8
+    out = torch.empty((nb, nb, nb, 2), dtype=torch.float32, device="cuda")
+    _check(_export_minmax(ctx, int(volume_id), int(lod), int(field), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def export_skiplist(ctx, volume_id: int, lod: int, slot: int = 0, stream=None) -> torch.Tensor:
+    nb = (volume_info(ctx, volume_id)["n"] >> lod) // 8
+    out = torch.empty(((nb ** 3 + 31) // 32,), dtype=torch.int32, device="cuda")
+    _check(_export_skip(ctx, int(volume_id), int(lod), int(slot), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def export_voxel_mask(ctx, volume_id: int, lod: int, stream=None) -> torch.Tensor:
+    n = volume_info(ctx, volume_id)["n"] >> lod
+    out = torch.empty((n, n, n), dtype=torch.uint8, device="cuda")
+    _check(_export_mask(ctx, int(volume_id), int(lod), out.data_ptr(), _stream(stream)))
+    return out
+
+
+class Renderer:
+    """Owns one context; thin convenience over the functions above."""
+
+    def __init__(self, device: int = 0):
+        self.ctx = create(device)
+
+    def close(self):
+        if self.ctx is not None:
+            destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_workload_volume(self, wl, storage="f32", n_lods=3, device_input=True):
+        """Load a workloads.Workload's fields, brush and transfer function (slot 0)."""
+        fields = torch.from_numpy(wl.fields).cuda() if device_input else wl.fields
+        vid = load_fields(self.ctx, fields, storage, n_lods, wl.r_inner, wl.r_outer)
+        set_brush(self.ctx, vid, wl.brush.active, wl.brush.lo, wl.brush.hi)
+        set_transfer_function(self.ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
+        set_options(self.ctx, wl.ert)
+        return vid
