@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark: brushed spherical-shell ray casting on one MI355X.
+
+Workload (the precision-study configuration): 512^3 x 5 fields (temperature,
+temperature anomaly, conductivity, expansivity, |velocity|; seeded synthetic
+stand-ins for the paper's mantle snapshots), octree LOD 512/256/128,
+1920x1080 image, step 0.5 voxel, 5-axis upper-tail brush keeping ~10 % of the
+shell, transfer function on the temperature anomaly, early termination at 0.99.
+
+One step = one interactive brush update followed by one frame: the brush
+cycles through four nearby 5-axis brushes, so every step recomputes the brick
+skip bits (brush changes rebuild nothing else) and ray-marches the frame with
+the level chosen automatically (level 0 at this size).  The volume stays
+resident; nothing crosses PCIe inside the timed region.
+
+value = nominal samples/s with FP16 fields (samples the method visits, including
+discarded ones, up to early termination; counted once per brush outside the
+timed region).  FP32 and 8-bit-brick storage are measured the same way and
+reported alongside.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK = 8.0e12          # bytes/s, MI355X
+ALU_PEAK = 256 * 64 * 2.4e9  # non-packed fp32 lane-ops/s: 256 CUs x 64 lanes/clk x 2.4 GHz
+IMAGE_BYTES_PER_PIXEL = 16
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storages", default="f16,f32,u8", help="first one is the headline value")
+    ap.add_argument("--cpu-stride", type=int, default=4, help="oracle sample: every k-th row and column")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1080)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the renderer shards by "
+              "request across GPUs with no communication, so per-GPU numbers are the 1-GPU numbers.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2207_12011_amd import raypc
+    from paper_2207_12011_amd import workloads as W
+
+    t_gen = time.perf_counter()
+    wl = W.make_workload(2, n=args.n, width=args.width, height=args.height)
+    mask = W.shell_mask(W.radius(wl.n))
+    rng = np.random.default_rng(7)
+    brushes = [wl.brush] + [W.upper_tail_brush(wl.fields, mask, rng, target=t) for t in (0.08, 0.12, 0.09)]
+    del mask
+    print(f"[bench] workload generated in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+
+    cam = wl.camera.as_array()
+    W_, H_ = wl.width, wl.height
+    ctx = raypc.create(0)
+    fields_dev = torch.from_numpy(wl.fields).cuda()
+    raypc.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
+    raypc.set_options(ctx, wl.ert)
+    stream = torch.cuda.current_stream()
+    out = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
+    results = {}
+    storages = args.storages.split(",")
+    bpv = {"f32": 4, "f16": 2, "u8": 1}
+
+    for si, storage in enumerate(storages):
+        vid = raypc.load_fields(ctx, fields_dev, storage, 3, wl.r_inner, wl.r_outer)
+        lod = raypc.select_lod(ctx, vid, cam, W_, H_)
+        nb = (wl.n >> lod) // 8
+        # per-brush nominal sample counts and touched bricks (outside the timed region)
+        samples, touched_bricks = [], []
+        for b in brushes:
+            raypc.set_brush(ctx, vid, b.active, b.lo, b.hi)
+            touched = torch.zeros(((nb ** 3 + 31) // 32,), dtype=torch.int32, device="cuda")
+            _, nom, _ = raypc.render_debug(ctx, vid, cam, W_, H_, lod, wl.step, touched=touched)
+            torch.cuda.synchronize()
+            samples.append(int(nom.to(torch.int64).sum().item()))
+            tb = touched.cpu().numpy().view(np.uint32)
+            touched_bricks.append(int(np.unpackbits(tb.view(np.uint8)).sum()))
+        n_needed = len(set(np.flatnonzero(brushes[0].active).tolist()) | {wl.tf.field})
+
+        # warmup
+        for s in range(args.warmup):
+            b = brushes[s % len(brushes)]
+            raypc.set_brush(ctx, vid, b.active, b.lo, b.hi)
+            raypc.render(ctx, vid, cam, W_, H_, -1, wl.step, out=out, stream=stream)
+        torch.cuda.synchronize()
+
+        # timed: K steps (brush change + frame)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        total_samples = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            k = s % len(brushes)
+            b = brushes[k]
+            raypc.set_brush(ctx, vid, b.active, b.lo, b.hi)
+            ev[s][0].record(stream)
+            raypc.render(ctx, vid, cam, W_, H_, -1, wl.step, out=out, stream=stream)
+            ev[s][1].record(stream)
+            total_samples += samples[k]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = [a.elapsed_time(b) for a, b in ev]
+
+        # kernel-only: fixed brush (skip bits cached), back-to-back launches on the same stream
+        b = brushes[0]
+        raypc.set_brush(ctx, vid, b.active, b.lo, b.hi)
+        raypc.render(ctx, vid, cam, W_, H_, lod, wl.step, out=out, stream=stream)
+        torch.cuda.synchronize()
+        kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+        for a, e in kev:
+            a.record(stream)
+            raypc.render(ctx, vid, cam, W_, H_, lod, wl.step, out=out, stream=stream)
+            e.record(stream)
+        torch.cuda.synchronize()
+        kms = float(np.mean([a.elapsed_time(e) for a, e in kev]))
+
+        alg_bytes = touched_bricks[0] * 512 * n_needed * bpv[storage] + W_ * H_ * IMAGE_BYTES_PER_PIXEL
+        if storage == "u8":
+            alg_bytes += touched_bricks[0] * 8 * n_needed
+        alg_ops = samples[0] * (50 + 22 * n_needed)
+        results[storage] = {
+            "samples_per_s": total_samples / wall,
+            "frames_per_s": args.steps / wall,
+            "ms_per_step": 1e3 * wall / args.steps,
+            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat)},
+            "nominal_samples_per_frame": samples,
+            "touched_bricks": touched_bricks[0],
+            "bricks_per_level": nb ** 3,
+            "lod": lod,
+            "kernel_ms": kms,
+            "alg_bytes_per_launch": alg_bytes,
+            "alg_ops_per_launch": alg_ops,
+            "volume_bytes": raypc.volume_info(ctx, vid)["bytes"],
+        }
+        print(f"[bench] {storage}: {results[storage]}", file=sys.stderr, flush=True)
+        raypc.unload(ctx, vid)
+
+    head = storages[0]
+    r = results[head]
+    achieved_bw = r["alg_bytes_per_launch"] / (r["kernel_ms"] * 1e-3)
+    achieved_ops = r["alg_ops_per_launch"] / (r["kernel_ms"] * 1e-3)
+    roofline = {"bound": "hbm", "kernel": "raymarch_kernel", "achieved": achieved_bw / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": achieved_bw / HBM_PEAK, "traffic": None,
+                "kernel_ms": r["kernel_ms"],
+                "alu_algorithmic": {"achieved": achieved_ops / 1e12, "peak": ALU_PEAK / 1e12, "unit": "Tlane-op/s",
+                                    "frac": achieved_ops / ALU_PEAK}}
+
+    cpu_baseline = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import preprocess as pp
+        level = np.stack([pp.stored_values(wl.fields[f], head) for f in range(wl.n_fields)])
+        ys, xs = np.meshgrid(np.arange(0, H_, args.cpu_stride), np.arange(0, W_, args.cpu_stride), indexing="ij")
+        pix = (ys * W_ + xs).ravel()
+        threads = min(len(os.sched_getaffinity(0)), 16)
+        b = brushes[0]
+        t0 = time.perf_counter()
+        ref = oracle.render(level, cam, W_, H_, wl.step, active=b.active, lo=b.lo, hi=b.hi, tf_field=wl.tf.field,
+                            vmin=wl.tf.vmin, vmax=wl.tf.vmax, tf_rgba=wl.tf.rgba, ref_step=wl.tf.ref_step,
+                            ert=wl.ert, r_inner=wl.r_inner, r_outer=wl.r_outer, pixels=pix, threads=threads)
+        dt = time.perf_counter() - t0
+        ns = int(ref.nominal.astype(np.int64).sum())
+        cpu_baseline = {"value": ns / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+                        "sample": f"every {args.cpu_stride}th row and column of the {W_}x{H_} frame "
+                                  f"({pix.size} px, {ns} nominal samples, {dt:.1f} s), brush 0, "
+                                  f"{head}-stored {wl.n}^3 x {wl.n_fields} level 0, FP64"}
+
+    line = {
+        "metric": "brushed ray-march samples/s (FP16 fields; frames/s, p50/p99 latency and FP32/u8 alongside)",
+        "value": r["samples_per_s"],
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"precision study: {wl.n}^3 x {wl.n_fields} fields stored {head}, LOD 3 levels, "
+                               f"{W_}x{H_}, step {wl.step} voxel, 5-axis ~10% brush changed every step, ERT 0.99",
+                   "volume": wl.n, "fields": wl.n_fields, "width": W_, "height": H_, "step": wl.step,
+                   "storage": head, "lod": r["lod"]},
+        "frames_per_s": r["frames_per_s"],
+        "latency_ms": r["latency_ms"],
+        "per_storage": results,
+        "roofline": roofline,
+        "cpu_baseline": cpu_baseline,
+    }
+    raypc.destroy(ctx)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

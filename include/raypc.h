@@ -94,7 +94,7 @@ int raypc_version(void);
  * output variables; Section 2.1: derived variables are added in
  * preprocessing).
  *   n_fields   1..8 variables; fields[f] points at N^3 float32 values.
- *   n          N, a multiple of 32 in [32, 2048].
+ *   n          N, a multiple of 32 in [32, 1024].
  *   on_device  0: fields[] are host pointers (copied);  1: device pointers
  *              (read only, e.g. torch tensors).
  *   storage    RAYPC_STORAGE_*: how every level is kept in device memory.
@@ -107,7 +107,7 @@ int raypc_version(void);
  *   volume_id  receives a handle (> 0).
  * Builds, per level: the encoded brick-ordered field data and the per-brick
  * (min, max) tables of the stored values over each brick's 9^3 window.  The
- * brush starts empty-handed: no variable restricted.
+ * brush starts with no variable restricted.
  * Errors: RAYPC_ERR_INVALID (argument out of range, NULL pointer, or a
  * non-finite input value), RAYPC_ERR_NOMEM, RAYPC_ERR_DEVICE.
  */
@@ -214,11 +214,14 @@ int raypc_export_voxel_mask(raypc_ctx *ctx, int volume_id, int lod, uint8_t *out
 
 /* raypc_render plus per-pixel sample counts: nominal = samples visited up to
  * and including an early-termination stop; composited = samples that passed
- * the brush with non-zero table opacity.  flags bit 0 disables empty-space
- * skipping.  nominal / composited may be NULL. */
+ * the brush with non-zero table opacity.  touched_bricks (ceil(nb^3 / 32)
+ * words of the rendered level, zeroed by the caller) receives a bit for every
+ * brick that holds the base corner of an evaluated (not skipped) sample.
+ * flags bit 0 disables empty-space skipping.  nominal / composited /
+ * touched_bricks may be NULL. */
 int raypc_render_debug(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height, int lod,
-                       float step, float *rgba_out, uint32_t *nominal, uint32_t *composited, int flags,
-                       void *stream);
+                       float step, float *rgba_out, uint32_t *nominal, uint32_t *composited,
+                       uint32_t *touched_bricks, int flags, void *stream);
 
 #ifdef __cplusplus
 }

@@ -582,8 +582,8 @@ int raypc_select_lod(const raypc_ctx* ctx, int volume_id, const raypc_camera* ca
 }
 
 static int render_common(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
-                         float step, float* rgba_out, uint32_t* nominal, uint32_t* composited, bool counts,
-                         bool use_skip, void* stream) {
+                         float step, float* rgba_out, uint32_t* nominal, uint32_t* composited, uint32_t* touched,
+                         bool counts, bool use_skip, void* stream) {
     if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
     DeviceGuard g(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -597,19 +597,22 @@ static int render_common(raypc_ctx* ctx, int volume_id, const raypc_camera* cam,
     if (rc) return rc;
     a.nominal = nominal;
     a.composited = composited;
+    a.touched = touched;
     HIP_TRY(launch_render(a, storage, counts, s), "ray-march kernel launch");
     return RAYPC_OK;
 }
 
 int raypc_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod, float step,
                  float* rgba_out, void* stream) {
-    return render_common(ctx, volume_id, cam, width, height, lod, step, rgba_out, nullptr, nullptr, false, true, stream);
+    return render_common(ctx, volume_id, cam, width, height, lod, step, rgba_out, nullptr, nullptr, nullptr, false, true,
+                         stream);
 }
 
 int raypc_render_debug(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
-                       float step, float* rgba_out, uint32_t* nominal, uint32_t* composited, int flags, void* stream) {
-    return render_common(ctx, volume_id, cam, width, height, lod, step, rgba_out, nominal, composited, true,
-                         (flags & 1) == 0, stream);
+                       float step, float* rgba_out, uint32_t* nominal, uint32_t* composited, uint32_t* touched_bricks,
+                       int flags, void* stream) {
+    return render_common(ctx, volume_id, cam, width, height, lod, step, rgba_out, nominal, composited, touched_bricks,
+                         true, (flags & 1) == 0, stream);
 }
 
 int raypc_render_progressive(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,

@@ -89,6 +89,7 @@ struct RenderArgs {
     float4* out;                  // H x W premultiplied RGBA
     uint32_t* nominal;            // debug counts (only in the counting variant)
     uint32_t* composited;
+    uint32_t* touched;            // debug: bit per brick read by an evaluated sample (may be null)
     int blocks_x, n_blocks;       // 16 x 16 pixel blocks per row, total
 };
 hipError_t launch_render(const RenderArgs& a, int storage, bool counts, hipStream_t s);

@@ -162,6 +162,7 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
 
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t cnt_nom = 0, cnt_comp = 0;
+    uint32_t last_brick = 0xFFFFFFFFu;
     int seg = 0, j = 0;
     float sa = seg_a[0], sb = seg_b[0];
     int ns = nseg > 0 ? static_cast<int>(ceilf((sb - sa) / ds)) : 0;
@@ -179,9 +180,9 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
         const int z0 = min(max(iz, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
 
         bool skipped = false;
+        const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
+        const uint32_t brick = (static_cast<uint32_t>(bzi) * nb + byi) * nb + bxi;
         if (A.skip != nullptr) {
-            const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
-            const uint32_t brick = (static_cast<uint32_t>(bzi) * nb + byi) * nb + bxi;
             if ((A.skip[brick >> 5] >> (brick & 31)) & 1u) {
                 skipped = true;
                 const float lx = bxi == 0 ? -INFINITY : bxi * 8.0f + kSkipShrink;
@@ -203,6 +204,12 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
 
         if (!skipped) {
             cnt_nom += 1;
+            if constexpr (COUNTS) {
+                if (A.touched != nullptr && brick != last_brick) {
+                    atomicOr(&A.touched[brick >> 5], 1u << (brick & 31));
+                    last_brick = brick;
+                }
+            }
             const float wx = ux - flx, wy = uy - fly, wz = uz - flz;
             const uint32_t X0 = (static_cast<uint32_t>(x0 >> 3) << 9) | (x0 & 7);
             const uint32_t X1 = (static_cast<uint32_t>(x1 >> 3) << 9) | (x1 & 7);

@@ -77,7 +77,8 @@ _export_level = _sig("raypc_export_level", _I, _P, _I, _I, _I, _P, _P)
 _export_minmax = _sig("raypc_export_minmax", _I, _P, _I, _I, _I, _P, _P)
 _export_skip = _sig("raypc_export_skiplist", _I, _P, _I, _I, _I, _P, _P)
 _export_mask = _sig("raypc_export_voxel_mask", _I, _P, _I, _I, _P, _P)
-_render_debug = _sig("raypc_render_debug", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _I, _P)
+_render_debug = _sig("raypc_render_debug", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _P, _I,
+                     _P)
 
 EXPORTED = ["raypc_create", "raypc_destroy", "raypc_last_error", "raypc_version", "raypc_load_fields",
             "raypc_unload", "raypc_volume_info", "raypc_set_brush", "raypc_set_transfer_function",
@@ -226,13 +227,21 @@ def render_progressive(ctx, volume_id: int, camera, width: int, height: int, lod
 
 
 def render_debug(ctx, volume_id: int, camera, width: int, height: int, lod: int = -1, step: float = 0.5,
-                 skip: bool = True, stream=None):
-    """(rgba [H,W,4] f32, nominal [H,W] i32, composited [H,W] i32) as CUDA tensors (async)."""
+                 skip: bool = True, touched: Optional[torch.Tensor] = None, stream=None):
+    """(rgba [H,W,4] f32, nominal [H,W] i32, composited [H,W] i32) as CUDA tensors (async).
+    `touched`, if given, is a zeroed int32 CUDA tensor of ceil(nb^3/32) words (nb of the
+    rendered level) that receives the touched-brick bits."""
     out = torch.empty((height, width, 4), dtype=torch.float32, device="cuda")
     nom = torch.empty((height, width), dtype=torch.int32, device="cuda")
     comp = torch.empty((height, width), dtype=torch.int32, device="cuda")
+    tptr = None
+    if touched is not None:
+        info = volume_info(ctx, volume_id)
+        lv = lod if lod >= 0 else select_lod(ctx, volume_id, camera, width, height)
+        nb = (info["n"] >> lv) // 8
+        tptr = _dptr(touched, torch.int32, (nb ** 3 + 31) // 32, "touched")
     _check(_render_debug(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height), int(lod),
-                         float(step), out.data_ptr(), nom.data_ptr(), comp.data_ptr(), 0 if skip else 1,
+                         float(step), out.data_ptr(), nom.data_ptr(), comp.data_ptr(), tptr, 0 if skip else 1,
                          _stream(stream)))
     return out, nom, comp
 
