@@ -37,17 +37,41 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
+def profile(args, wl, raypc, torch):
+    """A short, fixed sequence for hardware-counter runs."""
+    ctx = raypc.create(0)
+    raypc.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
+    raypc.set_options(ctx, wl.ert)
+    storage = args.storages.split(",")[0]
+    vid = raypc.load_fields(ctx, torch.from_numpy(wl.fields).cuda(), storage, 3, wl.r_inner, wl.r_outer)
+    raypc.set_brush(ctx, vid, wl.brush.active, wl.brush.lo, wl.brush.hi)
+    out = torch.empty((wl.height, wl.width, 4), dtype=torch.float32, device="cuda")
+    for _ in range(args.profile_frames):
+        raypc.render(ctx, vid, wl.camera.as_array(), wl.width, wl.height, -1, wl.step, out=out)
+    torch.cuda.synchronize()
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    raypc.destroy(ctx)
+    print(f"[bench] profile mode: {args.profile_frames} frames ({storage}) + 1 GiB copy", file=sys.stderr)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storages", default="f16,f32,u8", help="first one is the headline value")
-    ap.add_argument("--cpu-stride", type=int, default=4, help="oracle sample: every k-th row and column")
+    ap.add_argument("--cpu-stride", type=int, default=2, help="oracle sample: every k-th row and column")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--profile-frames", type=int, default=0,
+                    help="profiling mode: load the headline storage, render this many frames with the first "
+                         "brush, then copy 1 GiB device-to-device (a known-size kernel for counter scaling); "
+                         "prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the renderer shards by "
@@ -61,6 +85,9 @@ def main():
 
     t_gen = time.perf_counter()
     wl = W.make_workload(2, n=args.n, width=args.width, height=args.height)
+    if args.profile_frames > 0:
+        profile(args, wl, raypc, torch)
+        return
     mask = W.shell_mask(W.radius(wl.n))
     rng = np.random.default_rng(7)
     brushes = [wl.brush] + [W.upper_tail_brush(wl.fields, mask, rng, target=t) for t in (0.08, 0.12, 0.09)]
