@@ -12,18 +12,36 @@ namespace raypc {
 constexpr int kMaxFields = 8;
 constexpr int kBrick = 8;           // brick edge in voxels
 constexpr int kBrickVoxels = 512;   // 8^3
-constexpr int kTileW = 8;           // one wave64 marches an 8 x 8 pixel tile
-constexpr int kBlockPix = 16;       // a 256-thread block covers 16 x 16 pixels (2 x 2 tiles)
+constexpr int kBlockPix = 8;        // a 256-thread ray-march block covers 8 x 8 pixels
 
 enum Storage : int { kF32 = 0, kF16 = 1, kU8 = 2 };
 
 // Brick-ordered address of voxel (x, y, z) on a level with nb bricks per axis:
-// bricks in [bz][by][bx] order, 512 voxels each, [z][y][x] inside a brick.
+// bricks in [bz][by][bx] order, 512 voxels each.  Inside a brick the voxels
+// form eight 4^3 sub-bricks (x, y, z half-index in bits 6, 7, 8), each stored
+// [z][y][x]; with binary16 storage one 128-byte cache line is one 4x4x4 block,
+// so a compact cluster of samples touches few lines whatever the view direction.
+// The address is a sum of independent per-axis parts (see axis_x/y/z).
+__host__ __device__ inline uint32_t axis_x(int x) {
+    return (static_cast<uint32_t>(x >> 3) << 9) | (static_cast<uint32_t>((x >> 2) & 1) << 6) |
+           static_cast<uint32_t>(x & 3);
+}
+__host__ __device__ inline uint32_t axis_y(int y, int nb) {
+    return ((static_cast<uint32_t>(y >> 3) * nb) << 9) | (static_cast<uint32_t>((y >> 2) & 1) << 7) |
+           (static_cast<uint32_t>(y & 3) << 2);
+}
+__host__ __device__ inline uint32_t axis_z(int z, int nb) {
+    return ((static_cast<uint32_t>(z >> 3) * nb * nb) << 9) | (static_cast<uint32_t>((z >> 2) & 1) << 8) |
+           (static_cast<uint32_t>(z & 3) << 4);
+}
 __host__ __device__ inline uint32_t brick_addr(int x, int y, int z, int nb) {
-    uint32_t brick = (static_cast<uint32_t>(z >> 3) * nb + static_cast<uint32_t>(y >> 3)) * nb +
-                     static_cast<uint32_t>(x >> 3);
-    return (brick << 9) | (static_cast<uint32_t>(z & 7) << 6) | (static_cast<uint32_t>(y & 7) << 3) |
-           static_cast<uint32_t>(x & 7);
+    return axis_x(x) + axis_y(y, nb) + axis_z(z, nb);
+}
+// Brick-local index (0..511) of the voxel at offsets (x, y, z) in 0..7 within its brick.
+__host__ __device__ inline uint32_t brick_local(int x, int y, int z) {
+    return (static_cast<uint32_t>(z >> 2) << 8) | (static_cast<uint32_t>(y >> 2) << 7) |
+           (static_cast<uint32_t>(x >> 2) << 6) | (static_cast<uint32_t>(z & 3) << 4) |
+           (static_cast<uint32_t>(y & 3) << 2) | static_cast<uint32_t>(x & 3);
 }
 
 // ------------------------------------------------------------------ preprocessing launchers
@@ -90,7 +108,7 @@ struct RenderArgs {
     uint32_t* nominal;            // debug counts (only in the counting variant)
     uint32_t* composited;
     uint32_t* touched;            // debug: bit per brick read by an evaluated sample (may be null)
-    int blocks_x, n_blocks;       // 16 x 16 pixel blocks per row, total
+    int blocks_x, n_blocks;       // 8 x 8 pixel blocks per row, total
 };
 hipError_t launch_render(const RenderArgs& a, int storage, bool counts, hipStream_t s);
 

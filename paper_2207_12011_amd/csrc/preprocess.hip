@@ -85,7 +85,7 @@ __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ i
     const int x = bx * 8 + (t & 7), y = by * 8 + ((t >> 3) & 7), z = bz * 8 + (t >> 6);
     const size_t nn = static_cast<size_t>(n);
     const float v = in[(static_cast<size_t>(z) * nn + y) * nn + x];
-    const uint32_t a = (brick << 9) | t;
+    const uint32_t a = (brick << 9) | brick_local(t & 7, (t >> 3) & 7, t >> 6);
     if constexpr (S == kF32) {
         static_cast<float*>(out)[a] = v;
     } else if constexpr (S == kF16) {

@@ -23,16 +23,22 @@
 //  * front-to-back "over", stop once the accumulated opacity reaches the
 //    termination threshold.
 //
-// Mapping to CDNA4: one ray per lane, one wave64 per 8 x 8 pixel tile, four
-// waves per 256-thread block (16 x 16 pixels).  The lane loop runs while any
-// lane of the wave is alive, so a tile leaves as soon as all of its rays have
-// terminated or left the shell.  Blocks are remapped so that each XCD (blocks
-// are dealt round-robin over the 8 XCDs) works on one contiguous band of the
-// image and its L2 sees neighbouring rays.  The transfer function sits in LDS.
-// Field data is brick ordered (8^3 bricks), so the 8 corners of a sample
-// usually fall into one 512-voxel brick.  Bricks whose skip bit is set are
-// stepped over without fetching: every sample inside such a brick would be
-// discarded or fully transparent, so skipping changes no value.
+// Mapping to CDNA4.  Four lanes share a ray and evaluate four consecutive
+// samples of it at once; a wave64 covers a 4 x 4 pixel tile, so the 64
+// samples it fetches per step form a compact cluster of about 3 x 3 x 3
+// voxels, which the brick layout (4^3 sub-bricks per cache line for binary16)
+// serves from a handful of cache lines.  The four samples are merged in order
+// with DPP quad broadcasts: every lane replays the four sequential
+// front-to-back updates, stopping at the first sample whose accumulated
+// opacity reaches the threshold, so the result is bit for bit the sequential
+// sum whatever the grouping.  Every lane of a quad holds identical copies of
+// the ray state.  A wave
+// leaves its loop when all 16 of its rays have terminated or left the shell.
+// Bricks whose skip bit is set are stepped over without fetching: every sample
+// inside such a brick would be discarded or fully transparent, so skipping
+// changes no value.  Blocks of 4 waves (8 x 8 pixels) are remapped so that each
+// XCD works on one contiguous band of the image; the transfer function sits in
+// LDS.
 #include <hip/hip_fp16.h>
 
 #include "internal.h"
@@ -40,8 +46,11 @@
 namespace raypc {
 namespace {
 
-constexpr float kSkipShrink = 2e-3f;    // voxels: shrink of a skipped brick before computing its exit
-constexpr float kSkipMargin = 0.01f;    // samples: margin on the first sample after a skipped brick
+constexpr float kSkipShrink = 2e-3f;  // voxels: shrink of a skipped brick before computing its exit
+constexpr float kSkipMargin = 0.01f;  // samples: margin on the first sample after a skipped brick
+constexpr int kQuad = 4;              // lanes (consecutive samples) per ray
+constexpr int kWaveTile = 4;          // a wave covers kWaveTile x kWaveTile pixels
+constexpr int kBlockTile = 8;         // a 256-thread block covers 8 x 8 pixels
 
 template <int S>
 __device__ __forceinline__ float corner(const void* __restrict__ base, const float2* __restrict__ par, uint32_t a) {
@@ -92,6 +101,16 @@ __device__ __forceinline__ bool sphere_hit(float b, float px, float py, float pz
     return true;
 }
 
+// Value of `v` held by lane SRC (0..3) of the calling lane's quad (one DPP quad_perm move).
+template <int SRC>
+__device__ __forceinline__ float quad_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), SRC * 0x55, 0xF, 0xF, true));
+}
+template <int SRC>
+__device__ __forceinline__ int quad_bcast(int v) {
+    return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xF, 0xF, true);
+}
+
 template <int S, int NB, bool COUNTS>
 __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     __shared__ float4 s_tf[256];
@@ -106,11 +125,12 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     const int blk = xcd < r8 ? xcd * (q8 + 1) + pos : r8 * (q8 + 1) + (xcd - r8) * q8 + pos;
     const int bx = blk % A.blocks_x, by = blk / A.blocks_x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int px = bx * kBlockPix + (wave & 1) * kTileW + (lane & 7);
-    const int py = by * kBlockPix + (wave >> 1) * kTileW + (lane >> 3);
+    const int ray = lane >> 2, sub = lane & 3, quad_base = lane & ~3;
+    const int px = bx * kBlockTile + (wave & 1) * kWaveTile + (ray & 3);
+    const int py = by * kBlockTile + (wave >> 1) * kWaveTile + (ray >> 2);
     const bool inside = px < A.width && py < A.height;
 
-    // ---- ray through the pixel centre
+    // ---- ray through the pixel centre (identical in the four lanes of the quad)
     const float sx = fmaf(static_cast<float>(px) + 0.5f, A.inv_w2, -1.0f) * A.sx_scale;
     const float sy = fmaf(-(static_cast<float>(py) + 0.5f), A.inv_h2, 1.0f) * A.sy_scale;
     float dx = fmaf(sy, A.upv[0], fmaf(sx, A.right[0], A.fwd[0]));
@@ -163,27 +183,33 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     uint32_t cnt_nom = 0, cnt_comp = 0;
     uint32_t last_brick = 0xFFFFFFFFu;
-    int seg = 0, j = 0;
+    int seg = 0, j0 = 0;  // j0: first sample of the quad's current group of four
     float sa = seg_a[0], sb = seg_b[0];
-    int ns = nseg > 0 ? static_cast<int>(ceilf((sb - sa) / ds)) : 0;
+    int ns = nseg > 0 ? max(static_cast<int>(ceilf((sb - sa) / ds)), 1) : 0;
     bool alive = nseg > 0;
 
     while (alive) {
-        const float tlo = fmaf(static_cast<float>(j), ds, sa);
-        const bool last = j == ns - 1;
-        const float tm = last ? 0.5f * (tlo + sb) : fmaf(static_cast<float>(j) + 0.5f, ds, sa);
-        const float ux = fmaf(dux, tm, uox), uy = fmaf(duy, tm, uoy), uz = fmaf(duz, tm, uoz);
-        const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
-        const int ix = static_cast<int>(flx), iy = static_cast<int>(fly), iz = static_cast<int>(flz);
-        const int x0 = min(max(ix, 0), n - 1), x1 = min(max(ix + 1, 0), n - 1);
-        const int y0 = min(max(iy, 0), n - 1), y1 = min(max(iy + 1, 0), n - 1);
-        const int z0 = min(max(iz, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
+        const int j = j0 + sub;
+        const bool valid = j < ns;
+        float keep = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+        bool contributes = false, skipped = false;
+        int jn = j + 1;
 
-        bool skipped = false;
-        const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
-        const uint32_t brick = (static_cast<uint32_t>(bzi) * nb + byi) * nb + bxi;
-        if (A.skip != nullptr) {
-            if ((A.skip[brick >> 5] >> (brick & 31)) & 1u) {
+        if (valid) {
+            const float tlo = fmaf(static_cast<float>(j), ds, sa);
+            const bool last = j == ns - 1;
+            const float tm = last ? 0.5f * (tlo + sb) : fmaf(static_cast<float>(j) + 0.5f, ds, sa);
+            const float ux = fmaf(dux, tm, uox), uy = fmaf(duy, tm, uoy), uz = fmaf(duz, tm, uoz);
+            const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
+            const int ix = static_cast<int>(flx), iy = static_cast<int>(fly), iz = static_cast<int>(flz);
+            const int x0 = min(max(ix, 0), n - 1), x1 = min(max(ix + 1, 0), n - 1);
+            const int y0 = min(max(iy, 0), n - 1), y1 = min(max(iy + 1, 0), n - 1);
+            const int z0 = min(max(iz, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
+            const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
+            const uint32_t brick = (static_cast<uint32_t>(bzi) * nb + byi) * nb + bxi;
+            if (A.skip != nullptr && ((A.skip[brick >> 5] >> (brick & 31)) & 1u)) {
+                // every sample inside this brick is discarded or transparent: find the first
+                // sample that may lie beyond it (brick shrunk by a margin against rounding)
                 skipped = true;
                 const float lx = bxi == 0 ? -INFINITY : bxi * 8.0f + kSkipShrink;
                 const float hx = bxi == nb - 1 ? INFINITY : bxi * 8.0f + 8.0f - kSkipShrink;
@@ -193,82 +219,124 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
                 const float hz = bzi == nb - 1 ? INFINITY : bzi * 8.0f + 8.0f - kSkipShrink;
                 const float t_exit = fminf(axis_exit(uox, dux, lx, hx),
                                            fminf(axis_exit(uoy, duy, ly, hy), axis_exit(uoz, duz, lz, hz)));
-                // first sample whose midpoint may lie beyond the exit
                 float jc = (t_exit - sa) * inv_ds - 0.5f - kSkipMargin;
                 jc = fminf(fmaxf(jc, 0.0f), static_cast<float>(ns));
-                const int jn = max(j + 1, static_cast<int>(ceilf(jc)));
-                cnt_nom += static_cast<uint32_t>(jn - j);
-                j = jn;
-            }
-        }
-
-        if (!skipped) {
-            cnt_nom += 1;
-            if constexpr (COUNTS) {
-                if (A.touched != nullptr && brick != last_brick) {
-                    atomicOr(&A.touched[brick >> 5], 1u << (brick & 31));
-                    last_brick = brick;
-                }
-            }
-            const float wx = ux - flx, wy = uy - fly, wz = uz - flz;
-            const uint32_t X0 = (static_cast<uint32_t>(x0 >> 3) << 9) | (x0 & 7);
-            const uint32_t X1 = (static_cast<uint32_t>(x1 >> 3) << 9) | (x1 & 7);
-            const uint32_t Y0 = ((static_cast<uint32_t>(y0 >> 3) * nb) << 9) | ((y0 & 7) << 3);
-            const uint32_t Y1 = ((static_cast<uint32_t>(y1 >> 3) * nb) << 9) | ((y1 & 7) << 3);
-            const uint32_t Z0 = ((static_cast<uint32_t>(z0 >> 3) * nb * nb) << 9) | ((z0 & 7) << 6);
-            const uint32_t Z1 = ((static_cast<uint32_t>(z1 >> 3) * nb * nb) << 9) | ((z1 & 7) << 6);
-            const uint32_t zy00 = Z0 + Y0, zy01 = Z0 + Y1, zy10 = Z1 + Y0, zy11 = Z1 + Y1;
-            const uint32_t o[8] = {zy00 + X0, zy00 + X1, zy01 + X0, zy01 + X1,
-                                   zy10 + X0, zy10 + X1, zy11 + X0, zy11 + X1};
-
-            bool pass = true;
-            float tv = 0.0f;
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                if (pass) {
-                    const float v = fetch<S>(A.field[k], A.u8par[k], o, wx, wy, wz);
-                    pass = (v >= A.lo[k]) && (v <= A.hi[k]);
-                    if (k == A.tf_slot) tv = v;
-                }
-            }
-            if (pass) {
-                if constexpr (NB < kMaxFields) {
-                    if (A.tf_slot == NB) tv = fetch<S>(A.field[NB], A.u8par[NB], o, wx, wy, wz);
-                }
-                const float xt = fminf(fmaxf((tv - A.vmin) * A.inv_range, 0.0f), 1.0f) * 255.0f;
-                const int it = min(static_cast<int>(xt), 254);
-                const float wt = xt - static_cast<float>(it);
-                const float4 e0 = s_tf[it], e1 = s_tf[it + 1];
-                const float al = fmaf(wt, e1.w - e0.w, e0.w);
-                if (al > 0.0f) {
-                    if constexpr (COUNTS) cnt_comp += 1;
-                    const float r = last ? fmaxf(sb - tlo, 0.0f) * A.inv_ref : r_full;
-                    const float keep = al >= 1.0f ? 0.0f : exp2f(r * __log2f(1.0f - al));
-                    const float w = T * (1.0f - keep);
-                    C0 = fmaf(w, fmaf(wt, e1.x - e0.x, e0.x), C0);
-                    C1 = fmaf(w, fmaf(wt, e1.y - e0.y, e0.y), C1);
-                    C2 = fmaf(w, fmaf(wt, e1.z - e0.z, e0.z), C2);
-                    T *= keep;
-                    if (A.ert_on && 1.0f - T >= A.ert) alive = false;
-                }
-            }
-            j += 1;
-        }
-
-        if (alive && j >= ns) {
-            if (seg == 0 && nseg == 2) {
-                seg = 1;
-                sa = seg_a[1];
-                sb = seg_b[1];
-                ns = static_cast<int>(ceilf((sb - sa) / ds));
-                j = 0;
+                jn = max(j + 1, static_cast<int>(ceilf(jc)));
             } else {
-                alive = false;
+                if constexpr (COUNTS) {
+                    if (A.touched != nullptr && brick != last_brick) {
+                        atomicOr(&A.touched[brick >> 5], 1u << (brick & 31));
+                        last_brick = brick;
+                    }
+                }
+                const float wx = ux - flx, wy = uy - fly, wz = uz - flz;
+                const uint32_t X0 = axis_x(x0), X1 = axis_x(x1);
+                const uint32_t Y0 = axis_y(y0, nb), Y1 = axis_y(y1, nb);
+                const uint32_t Z0 = axis_z(z0, nb), Z1 = axis_z(z1, nb);
+                const uint32_t zy00 = Z0 + Y0, zy01 = Z0 + Y1, zy10 = Z1 + Y0, zy11 = Z1 + Y1;
+                const uint32_t o[8] = {zy00 + X0, zy00 + X1, zy01 + X0, zy01 + X1,
+                                       zy10 + X0, zy10 + X1, zy11 + X0, zy11 + X1};
+                bool pass = true;
+                float tv = 0.0f;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    if (pass) {
+                        const float v = fetch<S>(A.field[k], A.u8par[k], o, wx, wy, wz);
+                        pass = (v >= A.lo[k]) && (v <= A.hi[k]);
+                        if (k == A.tf_slot) tv = v;
+                    }
+                }
+                if (pass) {
+                    if constexpr (NB < kMaxFields) {
+                        if (A.tf_slot == NB) tv = fetch<S>(A.field[NB], A.u8par[NB], o, wx, wy, wz);
+                    }
+                    const float xt = fminf(fmaxf((tv - A.vmin) * A.inv_range, 0.0f), 1.0f) * 255.0f;
+                    const int it = min(static_cast<int>(xt), 254);
+                    const float wt = xt - static_cast<float>(it);
+                    const float4 e0 = s_tf[it], e1 = s_tf[it + 1];
+                    const float al = fmaf(wt, e1.w - e0.w, e0.w);
+                    if (al > 0.0f) {
+                        contributes = true;
+                        const float r = last ? fmaxf(sb - tlo, 0.0f) * A.inv_ref : r_full;
+                        keep = al >= 1.0f ? 0.0f : exp2f(r * __log2f(1.0f - al));
+                        cr = fmaf(wt, e1.x - e0.x, e0.x);
+                        cg = fmaf(wt, e1.y - e0.y, e0.y);
+                        cb = fmaf(wt, e1.z - e0.z, e0.z);
+                    }
+                }
+            }
+        }
+
+        // ---- merge the quad's four samples in sample order.  Every lane replays the same
+        // sequential updates (T <- T k, C <- fma(w, rgb, C)) on broadcast values, so the ray
+        // state is identical in the four lanes and independent of how samples were grouped
+        // (a skipped or discarded sample has k = 1 and w = 0, both exact).
+        const float k0 = quad_bcast<0>(keep), k1 = quad_bcast<1>(keep);
+        const float k2 = quad_bcast<2>(keep), k3 = quad_bcast<3>(keep);
+        const float t1 = T * k0, t2 = t1 * k1, t3 = t2 * k2, t4 = t3 * k3;  // T after each sample
+        const float t_before = sub == 0 ? T : (sub == 1 ? t1 : (sub == 2 ? t2 : t3));
+        const float t_after = sub == 0 ? t1 : (sub == 1 ? t2 : (sub == 2 ? t3 : t4));
+        const float w = t_before * (1.0f - keep);
+        const bool stop_here = contributes && A.ert_on && (1.0f - t_after >= A.ert);
+        const unsigned long long stop_mask = __ballot(stop_here);
+        const int stop_bits = static_cast<int>((stop_mask >> quad_base) & 0xFull);
+        const int first_stop = stop_bits ? __ffs(stop_bits) - 1 : kQuad - 1;  // last sample that counts
+        {
+            const float w0 = quad_bcast<0>(w), w1 = quad_bcast<1>(w), w2 = quad_bcast<2>(w), w3 = quad_bcast<3>(w);
+            const float r0 = quad_bcast<0>(cr), r1 = quad_bcast<1>(cr), r2 = quad_bcast<2>(cr), r3 = quad_bcast<3>(cr);
+            const float g0 = quad_bcast<0>(cg), g1 = quad_bcast<1>(cg), g2 = quad_bcast<2>(cg), g3 = quad_bcast<3>(cg);
+            const float b0 = quad_bcast<0>(cb), b1 = quad_bcast<1>(cb), b2 = quad_bcast<2>(cb), b3 = quad_bcast<3>(cb);
+            C0 = fmaf(w0, r0, C0);
+            C1 = fmaf(w0, g0, C1);
+            C2 = fmaf(w0, b0, C2);
+            if (first_stop >= 1) {
+                C0 = fmaf(w1, r1, C0);
+                C1 = fmaf(w1, g1, C1);
+                C2 = fmaf(w1, b1, C2);
+            }
+            if (first_stop >= 2) {
+                C0 = fmaf(w2, r2, C0);
+                C1 = fmaf(w2, g2, C1);
+                C2 = fmaf(w2, b2, C2);
+            }
+            if (first_stop >= 3) {
+                C0 = fmaf(w3, r3, C0);
+                C1 = fmaf(w3, g3, C1);
+                C2 = fmaf(w3, b3, C2);
+            }
+        }
+        if constexpr (COUNTS) {
+            const unsigned long long comp_mask = __ballot(contributes);
+            const int comp_bits = static_cast<int>((comp_mask >> quad_base) & 0xFull);
+            cnt_comp += __popc(comp_bits & ((2 << first_stop) - 1));
+        }
+        if (stop_bits) {
+            T = first_stop == 0 ? t1 : (first_stop == 1 ? t2 : (first_stop == 2 ? t3 : t4));
+            cnt_nom += static_cast<uint32_t>(first_stop + 1);
+            alive = false;
+        } else {
+            T = t4;
+            // next group: after the four samples, or past the brick of the fourth if it was skipped
+            const int last_skipped = quad_bcast<3>(static_cast<int>(skipped && valid));
+            const int jn3 = quad_bcast<3>(jn);
+            const int next = last_skipped ? max(j0 + kQuad, jn3) : j0 + kQuad;
+            cnt_nom += static_cast<uint32_t>(min(next, ns) - j0);
+            j0 = next;
+            if (j0 >= ns) {
+                if (seg == 0 && nseg == 2) {
+                    seg = 1;
+                    sa = seg_a[1];
+                    sb = seg_b[1];
+                    ns = max(static_cast<int>(ceilf((sb - sa) / ds)), 1);
+                    j0 = 0;
+                } else {
+                    alive = false;
+                }
             }
         }
     }
 
-    if (!inside) return;
+    if (!inside || sub != 0) return;
     float4 res = make_float4(C0, C1, C2, 1.0f - T);
     if (A.has_bg) {
         res.x = fmaf(T, A.bg[0], res.x);
