@@ -33,6 +33,26 @@ ALU_PEAK = 256 * 64 * 2.4e9  # non-packed fp32 lane-ops/s: 256 CUs x 64 lanes/cl
 IMAGE_BYTES_PER_PIXEL = 16
 
 
+N_NEEDED_DEFAULT = 5  # fields read per sample in the headline workload (5 brushed, TF field among them)
+TRAFFIC_RECORD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                              "raymarch_f16_512x5_1080p_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per ray-march launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE record,
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
+        return None
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        h.update(open(os.path.join(root, f), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
@@ -182,13 +202,19 @@ def main():
 
     head = storages[0]
     r = results[head]
-    achieved_bw = r["alg_bytes_per_launch"] / (r["kernel_ms"] * 1e-3)
-    achieved_ops = r["alg_ops_per_launch"] / (r["kernel_ms"] * 1e-3)
-    roofline = {"bound": "hbm", "kernel": "raymarch_kernel", "achieved": achieved_bw / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": achieved_bw / HBM_PEAK, "traffic": None,
-                "kernel_ms": r["kernel_ms"],
-                "alu_algorithmic": {"achieved": achieved_ops / 1e12, "peak": ALU_PEAK / 1e12, "unit": "Tlane-op/s",
-                                    "frac": achieved_ops / ALU_PEAK}}
+    ksec = r["kernel_ms"] * 1e-3
+    achieved_bw = r["alg_bytes_per_launch"] / ksec
+    achieved_ops = r["alg_ops_per_launch"] / ksec
+    traffic = measured_traffic() if head == "f16" and (wl.n, W_, H_) == (512, 1920, 1080) else None
+    roofline = {"bound": "alu", "kernel": f"raymarch_kernel ({head})", "achieved": achieved_ops / 1e12,
+                "peak": ALU_PEAK / 1e12, "unit": "Tlane-op/s", "frac": achieved_ops / ALU_PEAK,
+                "traffic": traffic, "kernel_ms": r["kernel_ms"],
+                "ops_per_sample": 50 + 22 * N_NEEDED_DEFAULT,
+                "hbm_algorithmic": {"achieved": achieved_bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                    "frac": achieved_bw / HBM_PEAK},
+                "hbm_measured": None if traffic is None else
+                {"achieved": traffic / ksec / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                 "frac": traffic / ksec / HBM_PEAK}}
 
     cpu_baseline = None
     if not args.no_cpu_baseline:
