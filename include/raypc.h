@@ -223,6 +223,90 @@ int raypc_render_debug(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, i
                        float step, float *rgba_out, uint32_t *nominal, uint32_t *composited,
                        uint32_t *touched_bricks, int flags, void *stream);
 
+/* ---------------------------------------------------------------- serving
+ * A request loop that keeps volumes resident and renders many requests at once
+ * (continuous batching).  It replaces the paper's asynchronous render thread
+ * (Section 2.2: rendering is decoupled from the application's frame rate):
+ * a scheduler thread owned by the context admits requests in submission order
+ * while a request slot is free and the memory budget allows, and every
+ * launch ("step") marches 8x8-pixel tiles of all admitted requests together,
+ * oldest request first; requests that arrive while others run join the next
+ * step.  Each request carries its own brush and names a transfer-function slot;
+ * the brush, the table and the options (termination threshold, background)
+ * are captured when it is submitted, so later set_brush /
+ * set_transfer_function / set_options calls do not affect it.  A request's image is exactly
+ * what raypc_render would produce for the same view, brush and table.
+ * submit / poll / wait / cancel / request_times / release / stats may be
+ * called from any thread.  The other context calls keep their one-thread rule
+ * and must not unload a volume that queued requests name (RAYPC_ERR_BUSY). */
+
+typedef struct {
+    uint64_t mem_budget_bytes; /* device memory in-flight requests may hold: each counts its image
+                                  (width*height*16 bytes, caller-owned) plus its skip bits;
+                                  0 = unlimited */
+    int max_inflight;          /* request slots, 1..256 */
+    int tiles_per_step;        /* 8x8-pixel tiles per step, 0 = 8192 */
+    int steps_in_flight;       /* steps queued ahead on the device, 1..4 (0 = 2) */
+} raypc_server_cfg;
+
+typedef struct {
+    int volume_id;
+    raypc_camera camera;
+    int width, height;                /* 1..16384 */
+    int lod;                          /* -1 = raypc_select_lod */
+    float step;                       /* voxels of the rendered level, [1/64, 64] */
+    uint8_t active[RAYPC_MAX_FIELDS]; /* the request's brush, as in raypc_set_brush; entries beyond */
+    float lo[RAYPC_MAX_FIELDS];       /* the volume's field count are ignored */
+    float hi[RAYPC_MAX_FIELDS];
+    int tf_slot;                      /* defined transfer-function slot */
+    float *out;                       /* device, height*width*4 float32, 16-byte aligned, caller-owned,
+                                         valid until the request is done */
+    double deadline_ms;               /* must be admitted within this many ms of submission; <= 0: none */
+} raypc_request;
+
+/* Request states reported by raypc_poll; a negative state is -RAYPC_ERR_* (failed, timed out or
+ * cancelled). */
+enum { RAYPC_REQ_QUEUED = 0, RAYPC_REQ_RUNNING = 1, RAYPC_REQ_DONE = 2 };
+
+typedef struct {
+    uint64_t submitted, completed, timed_out, cancelled, failed;
+    uint64_t steps, tiles;
+    uint64_t bytes_in_use, peak_bytes_in_use;
+    int inflight, queued;
+} raypc_server_stats;
+
+/* Start the context's scheduler.  RAYPC_ERR_STATE if one is running; RAYPC_ERR_INVALID for a bad
+ * configuration; RAYPC_ERR_NOMEM / RAYPC_ERR_DEVICE if its buffers cannot be created. */
+int raypc_server_start(raypc_ctx *ctx, const raypc_server_cfg *cfg);
+
+/* Stop accepting requests, finish every queued and running one, join the scheduler. */
+int raypc_server_stop(raypc_ctx *ctx);
+
+/* Queue a copy of *req; *ticket identifies it.  Checks the request as raypc_render does and
+ * returns RAYPC_ERR_NOMEM if it alone exceeds the memory budget, RAYPC_ERR_STATE if no server
+ * runs.  Never blocks on the device. */
+int raypc_submit(raypc_ctx *ctx, const raypc_request *req, uint64_t *ticket);
+
+/* Current state of a ticket (RAYPC_REQ_* or -RAYPC_ERR_*); RAYPC_ERR_INVALID for an unknown one. */
+int raypc_poll(raypc_ctx *ctx, uint64_t ticket, int *state);
+
+/* Block until the request is done (RAYPC_OK: its image is complete in device memory), failed
+ * (its error code) or timeout_ms passed (RAYPC_ERR_TIMEOUT; < 0 waits without limit). */
+int raypc_wait(raypc_ctx *ctx, uint64_t ticket, int timeout_ms);
+
+/* Cancel a request that is still queued (it ends with -RAYPC_ERR_CANCELLED); RAYPC_ERR_BUSY once
+ * it has been admitted. */
+int raypc_cancel(raypc_ctx *ctx, uint64_t ticket);
+
+/* Host monotonic timestamps in ms: [0] submitted, [1] admitted, [2] first tile launched,
+ * [3] completed (0 where not reached). */
+int raypc_request_times(raypc_ctx *ctx, uint64_t ticket, double times_ms[4]);
+
+/* Forget a finished ticket (its state and times); queued or running tickets: RAYPC_ERR_BUSY. */
+int raypc_release(raypc_ctx *ctx, uint64_t ticket);
+
+int raypc_server_get_stats(raypc_ctx *ctx, raypc_server_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

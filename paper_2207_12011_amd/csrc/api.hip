@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/raypc.h"
+#include "context.h"
 #include "internal.h"
 #include "server.h"
 
@@ -60,57 +61,6 @@ struct DeviceGuard {
 };
 
 }  // namespace
-
-namespace raypc {
-
-struct Level {
-    int n = 0, nb = 0;
-    void* data[kMaxFields] = {};
-    float2* par[kMaxFields] = {};
-    float2* mm[kMaxFields] = {};
-    uint32_t* skip = nullptr;
-    bool skip_valid = false;
-    uint64_t skip_brush_gen = 0, skip_tf_gen = 0;
-    int skip_slot = -1;
-    uint32_t n_bricks() const { return static_cast<uint32_t>(nb) * nb * nb; }
-    uint32_t n_words() const { return (n_bricks() + 31) / 32; }
-};
-
-struct Volume {
-    int id = 0, n = 0, nf = 0, n_lods = 0, storage = 0;
-    float r_in = 0.55f, r_out = 1.0f;
-    Level lv[RAYPC_MAX_LODS];
-    uint8_t active[kMaxFields] = {};
-    float lo[kMaxFields] = {}, hi[kMaxFields] = {};
-    uint64_t brush_gen = 1;
-    uint64_t bytes = 0;
-    std::vector<void*> allocs;
-    int refs = 0;  // serving requests in flight
-};
-
-struct TFSlot {
-    bool defined = false;
-    int field = 0;
-    float vmin = 0, vmax = 1, ref_step = 2.0f / 256;
-    float rgba[RAYPC_TF_ENTRIES * 4] = {};
-    uint64_t gen = 0;
-    float4* dev = nullptr;
-};
-
-}  // namespace raypc
-
-struct raypc_ctx {
-    int device = 0;
-    std::map<int, Volume*> vols;
-    int next_id = 1;
-    TFSlot tf[RAYPC_TF_SLOTS];
-    uint64_t tf_gen_counter = 0;
-    float ert = 0.99f;
-    float bg[4] = {0, 0, 0, 0};
-    bool has_bg = false;
-    std::mutex mu;  // guards state shared with the serving thread
-    Server* server = nullptr;
-};
 
 namespace {
 
@@ -203,20 +153,39 @@ int select_lod_impl(const Volume* v, const raypc_camera* cam, int height, int* l
     return RAYPC_OK;
 }
 
-// Recompute the skip bits of level l for the volume's brush and a transfer slot if stale.
-int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s) {
-    Level& L = v->lv[l];
-    const TFSlot& tf = ctx->tf[slot];
-    if (L.skip_valid && L.skip_brush_gen == v->brush_gen && L.skip_slot == slot && L.skip_tf_gen == tf.gen)
-        return RAYPC_OK;
-    SkipArgs a;
+int check_level(const Volume* v, int lod) {
+    if (lod < 0 || lod >= v->n_lods) return fail(RAYPC_ERR_INVALID, "lod %d outside [0, %d]", lod, v->n_lods - 1);
+    return RAYPC_OK;
+}
+
+}  // namespace
+
+// ============================================================================ internal entry points
+namespace raypc {
+
+int set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+Volume* lookup_volume(raypc_ctx* ctx, int id) { return find_volume(ctx, id); }
+
+void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t* active, const float* lo,
+                     const float* hi, int tf_slot, SkipArgs& a) {
+    const Level& L = v->lv[l];
+    const TFSlot& tf = ctx->tf[tf_slot];
     std::memset(&a, 0, sizeof(a));
     int k = 0;
     for (int f = 0; f < v->nf; ++f) {
-        if (!v->active[f]) continue;
+        if (!active[f]) continue;
         a.minmax[k] = L.mm[f];
-        a.lo[k] = v->lo[f];
-        a.hi[k] = v->hi[f];
+        a.lo[k] = lo[f];
+        a.hi[k] = hi[f];
         ++k;
     }
     a.n_active = k;
@@ -230,6 +199,17 @@ int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s) {
         a.next_nonzero[i] = nxt;
     }
     a.n_bricks = L.n_bricks();
+    a.out = nullptr;
+}
+
+// Recompute the skip bits of level l for the volume's own brush and a transfer slot if stale.
+static int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s) {
+    Level& L = v->lv[l];
+    const TFSlot& tf = ctx->tf[slot];
+    if (L.skip_valid && L.skip_brush_gen == v->brush_gen && L.skip_slot == slot && L.skip_tf_gen == tf.gen)
+        return RAYPC_OK;
+    SkipArgs a;
+    build_skip_args(ctx, v, l, v->active, v->lo, v->hi, slot, a);
     a.out = L.skip;
     HIP_TRY(launch_skip(a, s), "skip-list kernel launch");
     L.skip_valid = true;
@@ -239,25 +219,10 @@ int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s) {
     return RAYPC_OK;
 }
 
-int check_level(const Volume* v, int lod) {
-    if (lod < 0 || lod >= v->n_lods) return fail(RAYPC_ERR_INVALID, "lod %d outside [0, %d]", lod, v->n_lods - 1);
-    return RAYPC_OK;
-}
-
-}  // namespace
-
-// ============================================================================ internal entry used by serving
-namespace raypc {
-
-int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod, float step,
-                   const uint8_t* brush_active, const float* brush_lo, const float* brush_hi, int tf_slot,
-                   bool use_skip, float* rgba_out, RenderArgs& a, int& storage, Volume** vol_out,
-                   bool skip_from_volume, hipStream_t s);
-
-int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod, float step,
-                   const uint8_t* brush_active, const float* brush_lo, const float* brush_hi, int tf_slot,
-                   bool use_skip, float* rgba_out, RenderArgs& a, int& storage, Volume** vol_out,
-                   bool skip_from_volume, hipStream_t s) {
+int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
+                   float step, const uint8_t* brush_active, const float* brush_lo, const float* brush_hi,
+                   int tf_slot, float* rgba_out, bool use_volume_state, hipStream_t s, RenderArgs& a, int& storage,
+                   int& level, Volume** vol_out) {
     Volume* v = find_volume(ctx, volume_id);
     if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
     if (width < 1 || width > 16384 || height < 1 || height > 16384)
@@ -270,6 +235,9 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
     const TFSlot& tf = ctx->tf[tf_slot];
     if (tf.field >= v->nf)
         return fail(RAYPC_ERR_INVALID, "transfer function classifies field %d but the volume has %d", tf.field, v->nf);
+    for (int f = 0; f < v->nf; ++f)
+        if (brush_active[f] && (std::isnan(brush_lo[f]) || std::isnan(brush_hi[f])))
+            return fail(RAYPC_ERR_INVALID, "NaN bound for field %d", f);
     std::memset(&a, 0, sizeof(a));
     int rc = camera_setup(cam, width, height, a);
     if (rc) return rc;
@@ -320,26 +288,16 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
     a.blocks_x = (width + kBlockPix - 1) / kBlockPix;
     a.n_blocks = a.blocks_x * ((height + kBlockPix - 1) / kBlockPix);
     a.skip = nullptr;
-    if (use_skip && skip_from_volume) {
+    if (use_volume_state) {
         rc = ensure_skip(ctx, v, lod, tf_slot, s);
         if (rc) return rc;
         a.skip = v->lv[lod].skip;
     }
     storage = v->storage;
+    level = lod;
     if (vol_out) *vol_out = v;
     return RAYPC_OK;
 }
-
-Volume* lookup_volume(raypc_ctx* ctx, int id) { return find_volume(ctx, id); }
-int volume_nf(const Volume* v) { return v->nf; }
-int volume_ref(Volume* v, int delta) { return v->refs += delta; }
-std::mutex& ctx_mutex(raypc_ctx* ctx) { return ctx->mu; }
-int ctx_device(const raypc_ctx* ctx) { return ctx->device; }
-Server*& ctx_server(raypc_ctx* ctx) { return ctx->server; }
-int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
-const Level& volume_level(const Volume* v, int l) { return v->lv[l]; }
-int volume_lods(const Volume* v) { return v->n_lods; }
-const TFSlot& ctx_tf(const raypc_ctx* ctx, int slot) { return ctx->tf[slot]; }
 
 }  // namespace raypc
 
@@ -591,10 +549,11 @@ static int render_common(raypc_ctx* ctx, int volume_id, const raypc_camera* cam,
     Volume* v = find_volume(ctx, volume_id);
     if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
     RenderArgs a;
-    int storage = 0;
-    int rc = prepare_render(ctx, volume_id, cam, width, height, lod, step, v->active, v->lo, v->hi, 0, use_skip,
-                            rgba_out, a, storage, nullptr, true, s);
+    int storage = 0, level = 0;
+    int rc = prepare_render(ctx, volume_id, cam, width, height, lod, step, v->active, v->lo, v->hi, 0, rgba_out,
+                            true, s, a, storage, level, nullptr);
     if (rc) return rc;
+    if (!use_skip) a.skip = nullptr;
     a.nominal = nominal;
     a.composited = composited;
     a.touched = touched;

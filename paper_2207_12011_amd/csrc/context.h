@@ -1,0 +1,79 @@
+// context.h -- host-side state of a raypc context (internal, shared by api.hip and server.hip).
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/raypc.h"
+#include "internal.h"
+
+namespace raypc {
+
+struct Server;
+
+struct Level {
+    int n = 0, nb = 0;
+    void* data[kMaxFields] = {};
+    float2* par[kMaxFields] = {};
+    float2* mm[kMaxFields] = {};
+    uint32_t* skip = nullptr;
+    bool skip_valid = false;
+    uint64_t skip_brush_gen = 0, skip_tf_gen = 0;
+    int skip_slot = -1;
+    uint32_t n_bricks() const { return static_cast<uint32_t>(nb) * nb * nb; }
+    uint32_t n_words() const { return (n_bricks() + 31) / 32; }
+};
+
+struct Volume {
+    int id = 0, n = 0, nf = 0, n_lods = 0, storage = 0;
+    float r_in = 0.55f, r_out = 1.0f;
+    Level lv[RAYPC_MAX_LODS];
+    uint8_t active[kMaxFields] = {};
+    float lo[kMaxFields] = {}, hi[kMaxFields] = {};
+    uint64_t brush_gen = 1;
+    uint64_t bytes = 0;
+    std::vector<void*> allocs;
+    int refs = 0;  // serving requests queued or running on this volume
+};
+
+struct TFSlot {
+    bool defined = false;
+    int field = 0;
+    float vmin = 0, vmax = 1, ref_step = 2.0f / 256;
+    float rgba[RAYPC_TF_ENTRIES * 4] = {};
+    uint64_t gen = 0;
+    float4* dev = nullptr;
+};
+
+}  // namespace raypc
+
+struct raypc_ctx {
+    int device = 0;
+    std::map<int, raypc::Volume*> vols;
+    int next_id = 1;
+    raypc::TFSlot tf[RAYPC_TF_SLOTS];
+    uint64_t tf_gen_counter = 0;
+    float ert = 0.99f;
+    float bg[4] = {0, 0, 0, 0};
+    bool has_bg = false;
+    std::mutex mu;  // guards state shared with the serving thread
+    raypc::Server* server = nullptr;
+};
+
+
+namespace raypc {
+// Defined in api.hip; callers hold ctx->mu.
+int set_error(int code, const char* fmt, ...);
+Volume* lookup_volume(raypc_ctx* ctx, int id);
+// Validate a render and fill the kernel arguments (skip list and table pointers left for the caller
+// when use_volume_state is false).  Brush arrays are per field of the volume.
+int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
+                   float step, const uint8_t* active, const float* lo, const float* hi, int tf_slot,
+                   float* rgba_out, bool use_volume_state, hipStream_t s, RenderArgs& a, int& storage,
+                   int& level, Volume** vol_out);
+// Skip-kernel arguments for level l of v under a brush and a transfer-function slot (out left null).
+void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t* active, const float* lo,
+                     const float* hi, int tf_slot, SkipArgs& a);
+}  // namespace raypc

@@ -111,5 +111,7 @@ struct RenderArgs {
     int blocks_x, n_blocks;       // 8 x 8 pixel blocks per row, total
 };
 hipError_t launch_render(const RenderArgs& a, int storage, bool counts, hipStream_t s);
+// items[i] = (descriptor slot, tile index); every descriptor's volume uses `storage`.
+hipError_t launch_render_batch(const RenderArgs* descs, const uint2* items, int n_items, int storage, hipStream_t s);
 
 }  // namespace raypc

@@ -111,18 +111,22 @@ __device__ __forceinline__ int quad_bcast(int v) {
     return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xF, 0xF, true);
 }
 
-template <int S, int NB, bool COUNTS>
-__global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
-    __shared__ float4 s_tf[256];
-    s_tf[threadIdx.x] = A.tf[threadIdx.x];
-    __syncthreads();
-
-    // XCD-aware block order: block i runs on XCD i % 8; give each XCD a contiguous range.
-    const int nbk = A.n_blocks;
-    const int bid = blockIdx.x;
-    const int q8 = nbk >> 3, r8 = nbk & 7;
+// Blocks are dealt round-robin over the 8 XCDs (block i runs on XCD i % 8).  Map block i to work
+// index so that each XCD gets one contiguous range of [0, count): neighbouring tiles then share
+// that XCD's L2.  A bijection for any count.
+__device__ __forceinline__ int xcd_contiguous(int bid, int count) {
+    const int q8 = count >> 3, r8 = count & 7;
     const int xcd = bid & 7, pos = bid >> 3;
-    const int blk = xcd < r8 ? xcd * (q8 + 1) + pos : r8 * (q8 + 1) + (xcd - r8) * q8 + pos;
+    return xcd < r8 ? xcd * (q8 + 1) + pos : r8 * (q8 + 1) + (xcd - r8) * q8 + pos;
+}
+
+// Number of brushed fields known only at run time (batched launches mix requests).
+constexpr int kRuntimeNB = -1;
+
+// One 8 x 8 pixel tile (index blk in row-major tile order) of the image described by A, marched by
+// the calling 256-thread block.  NB is the number of brushed fields, or kRuntimeNB to read it from A.
+template <int S, int NB, bool COUNTS>
+__device__ __forceinline__ void march_tile(const RenderArgs& A, int blk, const float4* s_tf) {
     const int bx = blk % A.blocks_x, by = blk / A.blocks_x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ray = lane >> 2, sub = lane & 3, quad_base = lane & ~3;
@@ -238,17 +242,22 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
                                        zy10 + X0, zy10 + X1, zy11 + X0, zy11 + X1};
                 bool pass = true;
                 float tv = 0.0f;
+                constexpr int kUnroll = NB >= 0 ? NB : kMaxFields;
+                const int nbr = NB >= 0 ? NB : A.n_brushed;
 #pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    if (pass) {
+                for (int k = 0; k < kUnroll; ++k) {
+                    if (pass && (NB >= 0 || k < nbr)) {
                         const float v = fetch<S>(A.field[k], A.u8par[k], o, wx, wy, wz);
                         pass = (v >= A.lo[k]) && (v <= A.hi[k]);
                         if (k == A.tf_slot) tv = v;
                     }
                 }
                 if (pass) {
-                    if constexpr (NB < kMaxFields) {
+                    if constexpr (NB >= 0 && NB < kMaxFields) {
                         if (A.tf_slot == NB) tv = fetch<S>(A.field[NB], A.u8par[NB], o, wx, wy, wz);
+                    } else if constexpr (NB < 0) {
+                        if (A.tf_slot == nbr && nbr < kMaxFields)
+                            tv = fetch<S>(A.field[nbr], A.u8par[nbr], o, wx, wy, wz);
                     }
                     const float xt = fminf(fmaxf((tv - A.vmin) * A.inv_range, 0.0f), 1.0f) * 255.0f;
                     const int it = min(static_cast<int>(xt), 254);
@@ -352,6 +361,30 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     }
 }
 
+template <int S, int NB, bool COUNTS>
+__global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
+    __shared__ float4 s_tf[256];
+    s_tf[threadIdx.x] = A.tf[threadIdx.x];
+    __syncthreads();
+    march_tile<S, NB, COUNTS>(A, xcd_contiguous(blockIdx.x, A.n_blocks), s_tf);
+}
+
+// Batched launch: block i marches tile items[i].y of the request whose arguments are descs[items[i].x].
+// Tiles of many requests (different images, brushes, levels and transfer functions, one storage
+// type) share a launch; each tile runs exactly the code path of a single-request render.
+template <int S>
+__global__ __launch_bounds__(256) void raymarch_batch_kernel(const RenderArgs* __restrict__ descs,
+                                                             const uint2* __restrict__ items, int n_items) {
+    __shared__ float4 s_tf[256];
+    const uint2 item = items[xcd_contiguous(blockIdx.x, n_items)];
+    const int slot = __builtin_amdgcn_readfirstlane(static_cast<int>(item.x));
+    const int tile = __builtin_amdgcn_readfirstlane(static_cast<int>(item.y));
+    const RenderArgs& A = descs[slot];
+    s_tf[threadIdx.x] = A.tf[threadIdx.x];
+    __syncthreads();
+    march_tile<S, kRuntimeNB, false>(A, tile, s_tf);
+}
+
 template <int S, bool COUNTS>
 hipError_t launch_nb(const RenderArgs& a, hipStream_t s) {
     const dim3 grid(a.n_blocks), block(256);
@@ -370,6 +403,17 @@ hipError_t launch_nb(const RenderArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_render_batch(const RenderArgs* descs, const uint2* items, int n_items, int storage, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    const dim3 grid(n_items), block(256);
+    switch (storage) {
+        case kF32: hipLaunchKernelGGL(raymarch_batch_kernel<kF32>, grid, block, 0, s, descs, items, n_items); break;
+        case kF16: hipLaunchKernelGGL(raymarch_batch_kernel<kF16>, grid, block, 0, s, descs, items, n_items); break;
+        default: hipLaunchKernelGGL(raymarch_batch_kernel<kU8>, grid, block, 0, s, descs, items, n_items); break;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_render(const RenderArgs& a, int storage, bool counts, hipStream_t s) {
     if (counts) {

@@ -5,6 +5,6 @@
 
 namespace raypc {
 struct Server;
-// Stop the context's server if one runs; waits for requests on the device.
+// Stop the context's server if one runs; finishes queued and running requests first.
 void server_shutdown(raypc_ctx* ctx);
 }  // namespace raypc

@@ -80,7 +80,38 @@ _export_mask = _sig("raypc_export_voxel_mask", _I, _P, _I, _I, _P, _P)
 _render_debug = _sig("raypc_render_debug", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _P, _I,
                      _P)
 
-EXPORTED = ["raypc_create", "raypc_destroy", "raypc_last_error", "raypc_version", "raypc_load_fields",
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", _I), ("tiles_per_step", _I),
+                ("steps_in_flight", _I)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("volume_id", _I), ("camera", Camera), ("width", _I), ("height", _I), ("lod", _I), ("step", _F),
+                ("active", ctypes.c_uint8 * MAX_FIELDS), ("lo", _F * MAX_FIELDS), ("hi", _F * MAX_FIELDS),
+                ("tf_slot", _I), ("out", _P), ("deadline_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "timed_out", "cancelled", "failed", "steps",
+                                                "tiles", "bytes_in_use", "peak_bytes_in_use")] + \
+               [("inflight", _I), ("queued", _I)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
+
+_server_start = _sig("raypc_server_start", _I, _P, ctypes.POINTER(ServerCfg))
+_server_stop = _sig("raypc_server_stop", _I, _P)
+_submit = _sig("raypc_submit", _I, _P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64))
+_poll = _sig("raypc_poll", _I, _P, ctypes.c_uint64, ctypes.POINTER(_I))
+_wait = _sig("raypc_wait", _I, _P, ctypes.c_uint64, _I)
+_cancel = _sig("raypc_cancel", _I, _P, ctypes.c_uint64)
+_request_times = _sig("raypc_request_times", _I, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double * 4))
+_release = _sig("raypc_release", _I, _P, ctypes.c_uint64)
+_server_get_stats = _sig("raypc_server_get_stats", _I, _P, ctypes.POINTER(ServerStats))
+
+EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_poll", "raypc_wait", "raypc_cancel",
+            "raypc_request_times", "raypc_release", "raypc_server_get_stats",
+            "raypc_create", "raypc_destroy", "raypc_last_error", "raypc_version", "raypc_load_fields",
             "raypc_unload", "raypc_volume_info", "raypc_set_brush", "raypc_set_transfer_function",
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
             "raypc_export_level", "raypc_export_minmax", "raypc_export_skiplist", "raypc_export_voxel_mask",
@@ -274,6 +305,74 @@ def export_voxel_mask(ctx, volume_id: int, lod: int, stream=None) -> torch.Tenso
     out = torch.empty((n, n, n), dtype=torch.uint8, device="cuda")
     _check(_export_mask(ctx, int(volume_id), int(lod), out.data_ptr(), _stream(stream)))
     return out
+
+
+# ----------------------------------------------------------------------------- serving
+def server_start(ctx, mem_budget_bytes: int = 0, max_inflight: int = 64, tiles_per_step: int = 0,
+                 steps_in_flight: int = 0) -> None:
+    cfg = ServerCfg(int(mem_budget_bytes), int(max_inflight), int(tiles_per_step), int(steps_in_flight))
+    _check(_server_start(ctx, ctypes.byref(cfg)))
+
+
+def server_stop(ctx) -> None:
+    _check(_server_stop(ctx))
+
+
+def make_request(volume_id: int, camera, width: int, height: int, out: torch.Tensor, lod: int = -1,
+                 step: float = 0.5, active=(), lo=(), hi=(), tf_slot: int = 0, deadline_ms: float = 0.0) -> Request:
+    r = Request()
+    r.volume_id = int(volume_id)
+    r.camera = Camera.make(camera)
+    r.width, r.height, r.lod, r.step = int(width), int(height), int(lod), float(step)
+    a = np.zeros(MAX_FIELDS, np.uint8)
+    l = np.zeros(MAX_FIELDS, np.float32)
+    h = np.zeros(MAX_FIELDS, np.float32)
+    a[:len(active)] = np.asarray(active, np.uint8)
+    l[:len(lo)] = np.asarray(lo, np.float32)
+    h[:len(hi)] = np.asarray(hi, np.float32)
+    r.active[:] = a.tolist()
+    r.lo[:] = l.tolist()
+    r.hi[:] = h.tolist()
+    r.tf_slot = int(tf_slot)
+    r.out = _dptr(out, torch.float32, width * height * 4, "out")
+    r.deadline_ms = float(deadline_ms)
+    return r
+
+
+def submit(ctx, request: Request) -> int:
+    t = ctypes.c_uint64()
+    _check(_submit(ctx, ctypes.byref(request), ctypes.byref(t)))
+    return t.value
+
+
+def poll(ctx, ticket: int) -> int:
+    st = _I()
+    _check(_poll(ctx, int(ticket), ctypes.byref(st)))
+    return st.value
+
+
+def wait(ctx, ticket: int, timeout_ms: int = -1) -> None:
+    _check(_wait(ctx, int(ticket), int(timeout_ms)))
+
+
+def cancel(ctx, ticket: int) -> None:
+    _check(_cancel(ctx, int(ticket)))
+
+
+def request_times(ctx, ticket: int):
+    arr = (ctypes.c_double * 4)()
+    _check(_request_times(ctx, int(ticket), ctypes.byref(arr)))
+    return list(arr)
+
+
+def release(ctx, ticket: int) -> None:
+    _check(_release(ctx, int(ticket)))
+
+
+def server_get_stats(ctx) -> dict:
+    st = ServerStats()
+    _check(_server_get_stats(ctx, ctypes.byref(st)))
+    return {n: getattr(st, n) for n, _ in ServerStats._fields_}
 
 
 class Renderer:
