@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -77,6 +78,80 @@ def profile(args, wl, raypc, torch):
     print(f"[bench] profile mode: {args.profile_frames} frames ({storage}) + 1 GiB copy", file=sys.stderr)
 
 
+def serving(args, raypc, torch, W, wl512, fields512_dev):
+    """Serving configuration: 256^3 and 512^3 x 5 FP16 volumes resident; a seeded trace of
+    requests (sizes 256^2 .. 2048^2, orbit cameras, 1-5-axis quantile brushes, level by the
+    selection rule, step 0.5) replayed with Poisson arrivals at several rates through the
+    continuous-batching server; latency = completion - submission (host monotonic clock).
+    The plain FP32 single-request path renders the same requests one at a time (no load)."""
+    wl256 = W.make_workload(1)
+    rng = np.random.default_rng(3)
+    tables = [W.quantile_table(wl256.fields, W.shell_mask(W.radius(256)), rng),
+              W.quantile_table(wl512.fields, W.shell_mask(W.radius(512)), rng)]
+    trace = W.serving_trace(tables, n=args.serving_requests)
+    ctx = raypc.create(0)
+    tf = wl512.tf
+    raypc.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, tf.rgba, tf.ref_step)
+    raypc.set_options(ctx, wl512.ert)
+    f256 = torch.from_numpy(wl256.fields).cuda()
+    vols16 = [raypc.load_fields(ctx, f256, "f16", 3), raypc.load_fields(ctx, fields512_dev, "f16", 3)]
+    outs = [torch.empty((q.height, q.width, 4), dtype=torch.float32, device="cuda") for q in trace]
+    reqs = [raypc.make_request(vols16[q.volume], q.camera, q.width, q.height, o, -1, 0.5, q.active, q.lo, q.hi, 0)
+            for q, o in zip(trace, outs)]
+    pixels = sum(q.width * q.height for q in trace)
+    result = {"requests": len(trace), "pixels": pixels, "volumes": ["256^3 x 5 f16", "512^3 x 5 f16"],
+              "sizes": [list(s) for s in W.SERVING_SIZES], "server": {"max_inflight": 64, "tiles_per_step": 8192,
+                                                                     "steps_in_flight": 2, "mem_budget_bytes": 8 << 30},
+              "by_qps": {}}
+    # warm the batched kernel
+    raypc.server_start(ctx, 8 << 30, 64, 8192, 2)
+    for r in reqs[:8]:
+        raypc.wait(ctx, raypc.submit(ctx, r), 120000)
+    raypc.server_stop(ctx)
+    for qps_s in args.serving_qps.split(","):
+        qps = float(qps_s)
+        raypc.server_start(ctx, 8 << 30, 64, 8192, 2)
+        tickets = []
+        t0 = time.perf_counter()
+        due = 0.0
+        for q, r in zip(trace, reqs):
+            if math.isfinite(qps):
+                due += q.gap / qps
+                while time.perf_counter() - t0 < due:
+                    pass
+            tickets.append(raypc.submit(ctx, r))
+        for t in tickets:
+            raypc.wait(ctx, t, 120000)
+        times = np.array([raypc.request_times(ctx, t) for t in tickets])
+        stats = raypc.server_get_stats(ctx)
+        raypc.server_stop(ctx)
+        lat = times[:, 3] - times[:, 0]
+        span = (times[:, 3].max() - times[:, 0].min()) / 1e3
+        result["by_qps"][qps_s] = {"p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                                   "max_ms": float(lat.max()), "requests_per_s": len(trace) / span,
+                                   "pixels_per_s": pixels / span, "steps": stats["steps"],
+                                   "peak_bytes_in_use": stats["peak_bytes_in_use"]}
+        print(f"[bench] serving qps={qps_s}: {result['by_qps'][qps_s]}", file=sys.stderr, flush=True)
+    for v in vols16:
+        raypc.unload(ctx, v)
+    # plain FP32 single-request path on the same GPU
+    vols32 = [raypc.load_fields(ctx, f256, "f32", 3), raypc.load_fields(ctx, fields512_dev, "f32", 3)]
+    lat32 = []
+    for i, (q, o) in enumerate(zip(trace, outs)):
+        vid = vols32[q.volume]
+        raypc.set_brush(ctx, vid, q.active, q.lo, q.hi)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        raypc.render(ctx, vid, q.camera, q.width, q.height, -1, 0.5, out=o)
+        torch.cuda.synchronize()
+        lat32.append(1e3 * (time.perf_counter() - a))
+    result["fp32_single_request"] = {"p50_ms": percentile(lat32, 50), "p99_ms": percentile(lat32, 99),
+                                     "max_ms": max(lat32), "requests_per_s": len(lat32) / (sum(lat32) / 1e3)}
+    print(f"[bench] fp32 single-request path: {result['fp32_single_request']}", file=sys.stderr, flush=True)
+    raypc.destroy(ctx)
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +163,10 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--serving-qps", default="50,100,200,400,inf",
+                    help="Poisson arrival rates (requests/s); inf submits the whole trace at once")
     ap.add_argument("--profile-frames", type=int, default=0,
                     help="profiling mode: load the headline storage, render this many frames with the first "
                          "brush, then copy 1 GiB device-to-device (a known-size kernel for counter scaling); "
@@ -216,6 +295,10 @@ def main():
                 {"achieved": traffic / ksec / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                  "frac": traffic / ksec / HBM_PEAK}}
 
+    serving_result = None
+    if not args.no_serving and (wl.n, W_, H_) == (512, 1920, 1080):
+        serving_result = serving(args, raypc, torch, W, wl, fields_dev)
+
     cpu_baseline = None
     if not args.no_cpu_baseline:
         import oracle
@@ -257,6 +340,7 @@ def main():
         "latency_ms": r["latency_ms"],
         "per_storage": results,
         "roofline": roofline,
+        "serving": serving_result,
         "cpu_baseline": cpu_baseline,
     }
     raypc.destroy(ctx)

@@ -345,3 +345,56 @@ def make_workload(config_id: int, n: Optional[int] = None, width: Optional[int] 
             w, h, name = width or 1920, height or 1080, f"precision {n}^3 x 5 fields, {width or 1920}x{height or 1080}"
         return Workload(config_id, name, fields, FIELD_NAMES_5, brush, tf, cam, w, h, 0.5)
     raise ValueError(f"unknown config {config_id}")
+
+
+# --------------------------------------------------------------------------
+# serving trace
+# --------------------------------------------------------------------------
+SERVING_SIZES = ((256, 256), (512, 512), (1024, 1024), (1920, 1080), (2048, 2048))
+
+
+def quantile_table(fields: np.ndarray, mask: np.ndarray, rng, levels: int = 1001,
+                   sample: int = 1 << 21) -> np.ndarray:
+    """float32 [F, levels]: shell-voxel quantiles of every field at linspace(0, 1, levels),
+    estimated on a seeded subsample of up to `sample` shell voxels."""
+    s = _subsample_shell(fields, mask, rng, sample)
+    return np.quantile(s, np.linspace(0.0, 1.0, levels), axis=1).T.astype(np.float32)
+
+
+@dataclass
+class ServingRequest:
+    volume: int            # index into the list of resident volumes
+    camera: Camera
+    width: int
+    height: int
+    active: np.ndarray     # uint8[5]
+    lo: np.ndarray         # float32[5]
+    hi: np.ndarray         # float32[5]
+    gap: float             # unit-rate exponential inter-arrival gap (divide by QPS)
+
+
+def serving_trace(qtables, n: int = 512, seed: int = SEED_BASE + 3):
+    """Requests of the serving configuration: volume uniform over the resident ones, image size
+    uniform over SERVING_SIZES, orbit camera (azimuth U[0, 2 pi), elevation U[-60, 60] deg,
+    distance 3, up +z, 60 deg FOV), brush on k ~ U{1..5} distinct fields, each [Q(u), Q(u + w)]
+    with w ~ U(0.3, 0.9), u ~ U(0, 1 - w) in shell quantiles; Poisson arrivals (unit-rate gaps)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        vi = int(rng.integers(len(qtables)))
+        qt = qtables[vi]
+        nf, levels = qt.shape
+        w_, h_ = SERVING_SIZES[int(rng.integers(len(SERVING_SIZES)))]
+        cam = orbit_camera(rng.uniform(0.0, 2 * math.pi), math.radians(rng.uniform(-60.0, 60.0)))
+        k = int(rng.integers(1, nf + 1))
+        act = np.zeros(nf, np.uint8)
+        lo = np.zeros(nf, np.float32)
+        hi = np.zeros(nf, np.float32)
+        for f in rng.choice(nf, size=k, replace=False):
+            w = rng.uniform(0.3, 0.9)
+            u = rng.uniform(0.0, 1.0 - w)
+            act[f] = 1
+            lo[f] = np.interp(u, np.linspace(0, 1, levels), qt[f])
+            hi[f] = np.interp(u + w, np.linspace(0, 1, levels), qt[f])
+        out.append(ServingRequest(vi, cam, w_, h_, act, lo, hi, float(rng.exponential(1.0))))
+    return out
