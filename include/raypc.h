@@ -50,9 +50,14 @@ enum {
 };
 
 enum {
-    RAYPC_STORAGE_F32 = 0,     /* 4 bytes per value */
-    RAYPC_STORAGE_F16 = 1,     /* IEEE binary16, round to nearest even, subnormals kept */
-    RAYPC_STORAGE_U8_BRICK = 2 /* 8-bit codes with a (scale, offset) pair per 8^3 brick */
+    RAYPC_STORAGE_F32 = 0,      /* 4 bytes per value */
+    RAYPC_STORAGE_F16 = 1,      /* IEEE binary16, round to nearest even, subnormals kept */
+    RAYPC_STORAGE_U8_BRICK = 2, /* 8-bit codes with a (scale, offset) pair per 8^3 brick */
+    /* Flag OR-ed into RAYPC_STORAGE_F32 / _F16: keep only the compact layout.  Without it the
+     * library also keeps, per voxel, a record of the 8 stored values of its 2x2x2 neighbourhood
+     * (8x the field memory), so that one wide load serves the whole trilinear fetch of a sample;
+     * both layouts hold the same values and render identically. */
+    RAYPC_STORAGE_COMPACT = 0x100
 };
 
 #define RAYPC_MAX_FIELDS 8
@@ -97,7 +102,8 @@ int raypc_version(void);
  *   n          N, a multiple of 32 in [32, 1024].
  *   on_device  0: fields[] are host pointers (copied);  1: device pointers
  *              (read only, e.g. torch tensors).
- *   storage    RAYPC_STORAGE_*: how every level is kept in device memory.
+ *   storage    RAYPC_STORAGE_*: how every level is kept in device memory
+ *              (optionally | RAYPC_STORAGE_COMPACT for F32 / F16).
  *   n_lods     1..3 levels: level l+1 is the 2x2x2 mean of level l (float32,
  *              fixed summation order), built from float32 data and only then
  *              encoded (Section 2.1: two coarser levels with 1/8 the cells).

@@ -252,6 +252,7 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
         if (!brush_active[f]) continue;
         a.field[k] = L.data[f];
         a.u8par[k] = L.par[f];
+        a.rec[k] = L.rec[f];
         a.lo[k] = brush_lo[f];
         a.hi[k] = brush_hi[f];
         if (f == tf.field) {
@@ -265,9 +266,15 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
         a.tf_slot = k;
         a.field[k] = L.data[tf.field];
         a.u8par[k] = L.par[tf.field];
+        a.rec[k] = L.rec[tf.field];
     }
     a.n = L.n;
     a.nb = L.nb;
+    {
+        const uint64_t fb = static_cast<uint64_t>(L.n) * L.n * L.n * storage_bytes(v->storage);
+        a.field_bytes = fb > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(fb);
+        a.par_bytes = static_cast<uint32_t>(L.n_bricks() * sizeof(float2));
+    }
     a.half_n = 0.5f * static_cast<float>(L.n);
     a.tf = tf.dev;
     a.vmin = tf.vmin;
@@ -293,7 +300,7 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
         if (rc) return rc;
         a.skip = v->lv[lod].skip;
     }
-    storage = v->storage;
+    storage = v->records ? (v->storage == kF32 ? kKindF32Rec : kKindF16Rec) : v->storage;  // kernel kind
     level = lod;
     if (vol_out) *vol_out = v;
     return RAYPC_OK;
@@ -345,8 +352,13 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
     if (!ctx || !fields || !volume_id) return fail(RAYPC_ERR_INVALID, "NULL argument");
     if (n_fields < 1 || n_fields > RAYPC_MAX_FIELDS) return fail(RAYPC_ERR_INVALID, "n_fields %d outside [1, 8]", n_fields);
     if (n < 32 || n > 1024 || n % 32 != 0) return fail(RAYPC_ERR_INVALID, "n %d must be a multiple of 32 in [32, 1024]", n);
+    const int storage_arg = storage;
+    const bool compact = (storage & RAYPC_STORAGE_COMPACT) != 0;
+    storage &= ~RAYPC_STORAGE_COMPACT;
     if (storage < RAYPC_STORAGE_F32 || storage > RAYPC_STORAGE_U8_BRICK)
-        return fail(RAYPC_ERR_INVALID, "storage %d unknown", storage);
+        return fail(RAYPC_ERR_INVALID, "storage %d unknown", storage_arg);
+    if (compact && storage == RAYPC_STORAGE_U8_BRICK)
+        return fail(RAYPC_ERR_INVALID, "RAYPC_STORAGE_COMPACT applies to F32 and F16 only (U8 is always compact)");
     if (n_lods < 1 || n_lods > RAYPC_MAX_LODS) return fail(RAYPC_ERR_INVALID, "n_lods %d outside [1, 3]", n_lods);
     if (!(r_inner >= 0.0f && r_inner < r_outer && r_outer <= 1.0f))
         return fail(RAYPC_ERR_INVALID, "radii must satisfy 0 <= r_inner < r_outer <= 1");
@@ -361,6 +373,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
     v->nf = n_fields;
     v->n_lods = n_lods;
     v->storage = storage;
+    v->records = !compact && storage != kU8;
     v->r_in = r_inner;
     v->r_out = r_outer;
     for (int f = 0; f < n_fields; ++f) {
@@ -392,6 +405,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 rc = dev_alloc(v, &L.data[f], lvox * storage_bytes(storage));
                 if (!rc && storage == kU8) rc = dev_alloc(v, reinterpret_cast<void**>(&L.par[f]), L.n_bricks() * sizeof(float2));
                 if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm[f]), L.n_bricks() * sizeof(float2));
+                if (!rc && v->records) rc = dev_alloc(v, &L.rec[f], lvox * 8 * storage_bytes(storage));
             }
             if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip), L.n_words() * sizeof(uint32_t));
         }
@@ -420,6 +434,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 }
                 if ((e = launch_encode(cur, L.n, storage, L.data[f], L.par[f], s)) != hipSuccess) { rc = hip_fail(e, "encode"); break; }
                 if ((e = launch_minmax(L.data[f], L.par[f], L.n, storage, L.mm[f], s)) != hipSuccess) { rc = hip_fail(e, "min/max"); break; }
+                if (v->records && (e = launch_records(L.data[f], L.n, storage, L.rec[f], s)) != hipSuccess) { rc = hip_fail(e, "corner records"); break; }
             }
         }
         if (rc) break;
@@ -463,7 +478,7 @@ int raypc_volume_info(const raypc_ctx* ctx, int volume_id, int* n_fields, int* n
     if (n_fields) *n_fields = v->nf;
     if (n) *n = v->n;
     if (n_lods) *n_lods = v->n_lods;
-    if (storage) *storage = v->storage;
+    if (storage) *storage = v->storage | (v->records || v->storage == kU8 ? 0 : RAYPC_STORAGE_COMPACT);
     if (bytes) *bytes = v->bytes;
     return RAYPC_OK;
 }

@@ -18,6 +18,7 @@ struct Level {
     void* data[kMaxFields] = {};
     float2* par[kMaxFields] = {};
     float2* mm[kMaxFields] = {};
+    void* rec[kMaxFields] = {};  // corner records (null when the volume keeps only the compact layout)
     uint32_t* skip = nullptr;
     bool skip_valid = false;
     uint64_t skip_brush_gen = 0, skip_tf_gen = 0;
@@ -28,6 +29,7 @@ struct Level {
 
 struct Volume {
     int id = 0, n = 0, nf = 0, n_lods = 0, storage = 0;
+    bool records = false;  // corner records kept (binary16 / float32 without RAYPC_STORAGE_COMPACT)
     float r_in = 0.55f, r_out = 1.0f;
     Level lv[RAYPC_MAX_LODS];
     uint8_t active[kMaxFields] = {};

@@ -15,6 +15,8 @@ constexpr int kBrickVoxels = 512;   // 8^3
 constexpr int kBlockPix = 8;        // a 256-thread ray-march block covers 8 x 8 pixels
 
 enum Storage : int { kF32 = 0, kF16 = 1, kU8 = 2 };
+// Kernel variants: a storage type, read from the compact layout or from corner records.
+enum Kind : int { kKindF32 = 0, kKindF16 = 1, kKindU8 = 2, kKindF32Rec = 3, kKindF16Rec = 4, kKinds = 5 };
 
 // Brick-ordered address of voxel (x, y, z) on a level with nb bricks per axis:
 // bricks in [bz][by][bx] order, 512 voxels each.  Inside a brick the voxels
@@ -52,6 +54,10 @@ hipError_t launch_lod_build(const float* in, int n, float* out, hipStream_t s);
 hipError_t launch_encode(const float* in, int n, int storage, void* out, float2* u8par, hipStream_t s);
 // Per-brick (min, max) of stored values over the 9^3 apron window.
 hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, hipStream_t s);
+// Corner records: for every voxel (x, y, z), the 8 stored values at (x+dx, y+dy, z+dz), dx, dy, dz in
+// {0, 1}, clamped to N-1, in the order bit 0 = dx, bit 1 = dy, bit 2 = dz; record i sits at
+// brick_addr(x, y, z) x 8 values (binary16: 16 bytes, float32: 32 bytes).
+hipError_t launch_records(const void* data, int n, int storage, void* out, hipStream_t s);
 // Decode stored values back to linear [z][y][x] float32.
 hipError_t launch_decode(const void* data, const float2* u8par, int n, int storage, float* out, hipStream_t s);
 
@@ -83,9 +89,12 @@ struct RenderArgs {
     // slot tf_slot (< n_brushed when it is brushed itself, else == n_brushed)
     const void* field[kMaxFields];
     const float2* u8par[kMaxFields];
+    const void* rec[kMaxFields];  // corner records, in the same slot order (record kinds only)
     float lo[kMaxFields], hi[kMaxFields];
     int n_brushed, tf_slot;
     int n, nb;
+    uint32_t field_bytes;         // bytes of one field of this level (buffer range; f16 and u8 only)
+    uint32_t par_bytes;           // bytes of one field's per-brick (scale, offset) table (u8)
     float half_n;                 // N / 2: u = (p + 1) N/2 - 1/2
     const uint32_t* skip;         // brick skip bits, or nullptr for no skipping
     const float4* tf;             // 256 straight-RGBA entries
@@ -110,8 +119,8 @@ struct RenderArgs {
     uint32_t* touched;            // debug: bit per brick read by an evaluated sample (may be null)
     int blocks_x, n_blocks;       // 8 x 8 pixel blocks per row, total
 };
-hipError_t launch_render(const RenderArgs& a, int storage, bool counts, hipStream_t s);
-// items[i] = (descriptor slot, tile index); every descriptor's volume uses `storage`.
-hipError_t launch_render_batch(const RenderArgs* descs, const uint2* items, int n_items, int storage, hipStream_t s);
+hipError_t launch_render(const RenderArgs& a, int kind, bool counts, hipStream_t s);
+// items[i] = (descriptor slot, tile index); every descriptor's volume uses kernel kind `kind`.
+hipError_t launch_render_batch(const RenderArgs* descs, const uint2* items, int n_items, int kind, hipStream_t s);
 
 }  // namespace raypc

@@ -144,6 +144,26 @@ __global__ void decode_kernel(const void* __restrict__ data, const float2* __res
     out[o] = stored<S>(data, par, brick_addr(x, y, z, n >> 3));
 }
 
+// One thread per voxel: gather the 8 stored values of its 2x2x2 neighbourhood (bit patterns copied).
+template <typename T>
+__global__ void records_kernel(const T* __restrict__ data, int n, T* __restrict__ out) {
+    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t total = static_cast<uint32_t>(n) * n * n;
+    if (o >= total) return;
+    const int nb = n >> 3;
+    const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
+    const int x1 = min(x + 1, n - 1), y1 = min(y + 1, n - 1), z1 = min(z + 1, n - 1);
+    T* r = out + static_cast<size_t>(brick_addr(x, y, z, nb)) * 8;
+    r[0] = data[brick_addr(x, y, z, nb)];
+    r[1] = data[brick_addr(x1, y, z, nb)];
+    r[2] = data[brick_addr(x, y1, z, nb)];
+    r[3] = data[brick_addr(x1, y1, z, nb)];
+    r[4] = data[brick_addr(x, y, z1, nb)];
+    r[5] = data[brick_addr(x1, y, z1, nb)];
+    r[6] = data[brick_addr(x, y1, z1, nb)];
+    r[7] = data[brick_addr(x1, y1, z1, nb)];
+}
+
 template <int S>
 __global__ void voxel_mask_kernel(MaskArgs a) {
     const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
@@ -229,6 +249,18 @@ hipError_t launch_decode(const void* data, const float2* u8par, int n, int stora
         case kF16: hipLaunchKernelGGL(decode_kernel<kF16>, g, dim3(256), 0, s, data, u8par, n, out); break;
         default: hipLaunchKernelGGL(decode_kernel<kU8>, g, dim3(256), 0, s, data, u8par, n, out); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_records(const void* data, int n, int storage, void* out, hipStream_t s) {
+    const size_t total = static_cast<size_t>(n) * n * n;
+    const dim3 g(blocks_for(total, 256));
+    if (storage == kF32)
+        hipLaunchKernelGGL(records_kernel<uint32_t>, g, dim3(256), 0, s, static_cast<const uint32_t*>(data), n,
+                           static_cast<uint32_t*>(out));
+    else
+        hipLaunchKernelGGL(records_kernel<uint16_t>, g, dim3(256), 0, s, static_cast<const uint16_t*>(data), n,
+                           static_cast<uint16_t*>(out));
     return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ struct Request {
     RenderArgs args{};             // complete except the per-slot skip / table pointers
     SkipArgs skip_args{};          // complete except the output pointer
     float tf_rgba[RAYPC_TF_ENTRIES * 4];
-    int storage = 0;
+    int storage = 0;  // kernel kind
     int n_tiles = 0, next_tile = 0;
     uint64_t bytes = 0;
     int slot = -1;
@@ -235,8 +235,8 @@ void launch_step(Server* S) {
         takes.push_back({r, r->next_tile, c});
         budget -= c;
     }
-    int k = 0, seg_begin[3] = {0, 0, 0}, seg_count[3] = {0, 0, 0};
-    for (int st = 0; st < 3; ++st) {
+    int k = 0, seg_begin[kKinds] = {}, seg_count[kKinds] = {};
+    for (int st = 0; st < kKinds; ++st) {
         seg_begin[st] = k;
         for (const Take& t : takes) {
             if (t.r->storage != st) continue;
@@ -246,7 +246,7 @@ void launch_step(Server* S) {
         seg_count[st] = k - seg_begin[st];
     }
     hipError_t e = hipMemcpyAsync(d, h, sizeof(uint2) * k, hipMemcpyHostToDevice, S->stream);
-    for (int st = 0; st < 3 && e == hipSuccess; ++st)
+    for (int st = 0; st < kKinds && e == hipSuccess; ++st)
         if (seg_count[st]) e = launch_render_batch(S->d_args, d + seg_begin[st], seg_count[st], st, S->stream);
     Step step;
     step.buf = buf;

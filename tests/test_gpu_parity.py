@@ -198,6 +198,25 @@ def test_skip_on_off_bitexact(rp, ctx, small5):
         rp.unload(ctx, vid)
 
 
+@pytest.mark.parametrize("base", ["f16", "f32"])
+def test_corner_records_equal_compact_layout(rp, ctx, small5, c0, base):
+    """Both layouts hold the same stored values; every render is bit-identical."""
+    for wl in (small5, c0):
+        rec = load(rp, ctx, wl, base)
+        cmp_ = load(rp, ctx, wl, base + "c")
+        assert rp.volume_info(ctx, rec)["bytes"] > 4 * rp.volume_info(ctx, cmp_)["bytes"]
+        views = [(wl.camera.as_array(), 0, 0.5), (wl.camera.as_array(), 1, 0.37),
+                 (np.array([0.8, 0.1, 0.1, 0, 0, 0, 0, 0, 1, 90], np.float32), 0, 1.0),
+                 (np.array([3, 0, 0, 0, 0.55, 0, 0, 0, 1, 20], np.float32), 2, 0.5)]
+        for cam, lod, step in views:
+            a = gpu_render(rp, ctx, rec, wl, lod, step, camera=cam, width=120, height=72)
+            b = gpu_render(rp, ctx, cmp_, wl, lod, step, camera=cam, width=120, height=72)
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), (base, lod, step)
+        rp.unload(ctx, rec)
+        rp.unload(ctx, cmp_)
+
+
 def test_inclusive_brush_equals_none_and_empty_is_background(rp, ctx, small5):
     wl = small5
     vid = load(rp, ctx, wl, "f16")
