@@ -198,16 +198,35 @@ __device__ __forceinline__ int xcd_contiguous(int bid, int count) {
     return xcd < r8 ? xcd * (q8 + 1) + pos : r8 * (q8 + 1) + (xcd - r8) * q8 + pos;
 }
 
+// Single-image launches: tiles are grouped in 8 x 8 super-tiles (64 x 64 pixels) and super-tiles are
+// dealt round-robin over the 8 XCDs (block i runs on XCD i % 8): the j-th block an XCD receives is
+// tile j % 64 of super-tile (j / 64) * 8 + xcd.  The 64 tiles of a super-tile run together on one
+// XCD (their rays share voxels in its L2), and every XCD gets super-tiles from all over the image,
+// so the work of the shell's disc is spread evenly.  The grid is padded to whole rounds of 8
+// super-tiles; blocks outside the image return at once.
+__host__ __device__ inline int super_cols(int blocks_x) { return (blocks_x + 7) / 8; }
+__host__ __device__ inline int padded_blocks(int blocks_x, int blocks_y) {
+    const int supers = super_cols(blocks_x) * ((blocks_y + 7) / 8);
+    return (supers + 7) / 8 * 8 * 64;
+}
+__device__ __forceinline__ void interleaved_tile(int bid, int blocks_x, int& bx, int& by) {
+    const int xcd = bid & 7, p = bid >> 3;
+    const int st = (p >> 6) * 8 + xcd;
+    const int w = p & 63;
+    const int sc = super_cols(blocks_x);
+    bx = (st % sc) * 8 + (w & 7);
+    by = (st / sc) * 8 + (w >> 3);
+}
+
 // Number of brushed fields known only at run time (batched launches mix requests).
 constexpr int kRuntimeNB = -1;
 
 // One 8 x 8 pixel tile (index blk in row-major tile order) of the image described by A, marched by
 // the calling 256-thread block.  NB is the number of brushed fields, or kRuntimeNB to read it from A.
 template <int K, int NB, bool COUNTS>
-__device__ __forceinline__ void march_tile(const RenderArgs& A, int blk, const float4* s_tf) {
+__device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, const float4* s_tf) {
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
-    const int bx = blk % A.blocks_x, by = blk / A.blocks_x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ray = lane >> 2, sub = lane & 3, quad_base = lane & ~3;
     const int px = bx * kBlockTile + (wave & 1) * kWaveTile + (ray & 3);
@@ -482,10 +501,13 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int blk, const f
 
 template <int K, int NB, bool COUNTS>
 __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
+    int bx, by;
+    interleaved_tile(blockIdx.x, A.blocks_x, bx, by);
+    if (by * kBlockTile >= A.height || bx * kBlockTile >= A.width) return;  // padding block
     __shared__ float4 s_tf[256];
     s_tf[threadIdx.x] = A.tf[threadIdx.x];
     __syncthreads();
-    march_tile<K, NB, COUNTS>(A, xcd_contiguous(blockIdx.x, A.n_blocks), s_tf);
+    march_tile<K, NB, COUNTS>(A, bx, by, s_tf);
 }
 
 // Batched launch: block i marches tile items[i].y of the request whose arguments are descs[items[i].x].
@@ -501,12 +523,12 @@ __global__ __launch_bounds__(256) void raymarch_batch_kernel(const RenderArgs* _
     const RenderArgs& A = descs[slot];
     s_tf[threadIdx.x] = A.tf[threadIdx.x];
     __syncthreads();
-    march_tile<K, kRuntimeNB, false>(A, tile, s_tf);
+    march_tile<K, kRuntimeNB, false>(A, tile % A.blocks_x, tile / A.blocks_x, s_tf);
 }
 
 template <int K, bool COUNTS>
 hipError_t launch_nb(const RenderArgs& a, hipStream_t s) {
-    const dim3 grid(a.n_blocks), block(256);
+    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x)), block(256);
     switch (a.n_brushed) {
         case 0: hipLaunchKernelGGL((raymarch_kernel<K, 0, COUNTS>), grid, block, 0, s, a); break;
         case 1: hipLaunchKernelGGL((raymarch_kernel<K, 1, COUNTS>), grid, block, 0, s, a); break;
