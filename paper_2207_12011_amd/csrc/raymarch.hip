@@ -189,13 +189,26 @@ __device__ __forceinline__ int quad_bcast(int v) {
     return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xF, 0xF, true);
 }
 
-// Blocks are dealt round-robin over the 8 XCDs (block i runs on XCD i % 8).  Map block i to work
-// index so that each XCD gets one contiguous range of [0, count): neighbouring tiles then share
-// that XCD's L2.  A bijection for any count.
-__device__ __forceinline__ int xcd_contiguous(int bid, int count) {
-    const int q8 = count >> 3, r8 = count & 7;
-    const int xcd = bid & 7, pos = bid >> 3;
-    return xcd < r8 ? xcd * (q8 + 1) + pos : r8 * (q8 + 1) + (xcd - r8) * q8 + pos;
+// Batched launches number a request's tiles in 8 x 8 super-tiles (64 x 64 pixels) in row-major order,
+// tiles row-major inside each (narrower at the right and bottom edges), so consecutive tile indices
+// cover a compact patch of the image.  A bijection of [0, bx_count * by_count).
+__device__ __forceinline__ void tile_coords(int i, int bx_count, int by_count, int& bx, int& by) {
+    constexpr int kS = 8;
+    const int sr = i / (bx_count * kS);
+    const int rem = i - sr * bx_count * kS;
+    const int rows = min(kS, by_count - sr * kS);
+    const int full_cols = bx_count / kS;
+    const int sc = rem / (kS * rows);
+    if (sc < full_cols) {
+        const int r2 = rem - sc * kS * rows;
+        bx = sc * kS + r2 % kS;
+        by = sr * kS + r2 / kS;
+    } else {
+        const int wl = bx_count - full_cols * kS;
+        const int r3 = rem - full_cols * kS * rows;
+        bx = full_cols * kS + r3 % wl;
+        by = sr * kS + r3 / wl;
+    }
 }
 
 // Single-image launches: tiles are grouped in 8 x 8 super-tiles (64 x 64 pixels) and super-tiles are
@@ -510,20 +523,27 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     march_tile<K, NB, COUNTS>(A, bx, by, s_tf);
 }
 
-// Batched launch: block i marches tile items[i].y of the request whose arguments are descs[items[i].x].
-// Tiles of many requests (different images, brushes, levels and transfer functions, one storage
-// type) share a launch; each tile runs exactly the code path of a single-request render.
+// Batched launch: item j marches tile items[j].y of the request whose arguments are descs[items[j].x].
+// Tiles of many requests (different images, brushes, levels and transfer functions, one kernel
+// kind) share a launch; each tile runs exactly the code path of a single-request render.  Chunks
+// of 64 consecutive items (one super-tile of a request, as the scheduler lists them) are dealt
+// round-robin over the 8 XCDs; the grid is padded to whole rounds of 8 chunks.
 template <int K>
 __global__ __launch_bounds__(256) void raymarch_batch_kernel(const RenderArgs* __restrict__ descs,
                                                              const uint2* __restrict__ items, int n_items) {
     __shared__ float4 s_tf[256];
-    const uint2 item = items[xcd_contiguous(blockIdx.x, n_items)];
+    const int xcd = blockIdx.x & 7, p = blockIdx.x >> 3;
+    const int j = ((p >> 6) * 8 + xcd) * 64 + (p & 63);
+    if (j >= n_items) return;  // padding block
+    const uint2 item = items[j];
     const int slot = __builtin_amdgcn_readfirstlane(static_cast<int>(item.x));
     const int tile = __builtin_amdgcn_readfirstlane(static_cast<int>(item.y));
     const RenderArgs& A = descs[slot];
     s_tf[threadIdx.x] = A.tf[threadIdx.x];
     __syncthreads();
-    march_tile<K, kRuntimeNB, false>(A, tile % A.blocks_x, tile / A.blocks_x, s_tf);
+    int bx, by;
+    tile_coords(tile, A.blocks_x, A.n_blocks / A.blocks_x, bx, by);
+    march_tile<K, kRuntimeNB, false>(A, bx, by, s_tf);
 }
 
 template <int K, bool COUNTS>
@@ -558,7 +578,7 @@ hipError_t launch_kind(const RenderArgs& a, int kind, hipStream_t s) {
 
 hipError_t launch_render_batch(const RenderArgs* descs, const uint2* items, int n_items, int kind, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    const dim3 grid(n_items), block(256);
+    const dim3 grid((n_items + 511) / 512 * 512), block(256);
     switch (kind) {
         case kKindF32: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF32>, grid, block, 0, s, descs, items, n_items); break;
         case kKindF16: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16>, grid, block, 0, s, descs, items, n_items); break;
