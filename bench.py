@@ -100,17 +100,17 @@ def serving(args, raypc, torch, W, wl512, fields512_dev):
             for q, o in zip(trace, outs)]
     pixels = sum(q.width * q.height for q in trace)
     result = {"requests": len(trace), "pixels": pixels, "volumes": ["256^3 x 5 f16", "512^3 x 5 f16"],
-              "sizes": [list(s) for s in W.SERVING_SIZES], "server": {"max_inflight": 64, "tiles_per_step": 8192,
+              "sizes": [list(s) for s in W.SERVING_SIZES], "server": {"max_inflight": 64, "tiles_per_step": 32768,
                                                                      "steps_in_flight": 2, "mem_budget_bytes": 8 << 30},
               "by_qps": {}}
     # warm the batched kernel
-    raypc.server_start(ctx, 8 << 30, 64, 8192, 2)
+    raypc.server_start(ctx, 8 << 30, 64, 32768, 2)
     for r in reqs[:8]:
         raypc.wait(ctx, raypc.submit(ctx, r), 120000)
     raypc.server_stop(ctx)
     for qps_s in args.serving_qps.split(","):
         qps = float(qps_s)
-        raypc.server_start(ctx, 8 << 30, 64, 8192, 2)
+        raypc.server_start(ctx, 8 << 30, 64, 32768, 2)
         tickets = []
         t0 = time.perf_counter()
         due = 0.0

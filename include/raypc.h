@@ -251,7 +251,7 @@ typedef struct {
                                   (width*height*16 bytes, caller-owned) plus its skip bits;
                                   0 = unlimited */
     int max_inflight;          /* request slots, 1..256 */
-    int tiles_per_step;        /* 8x8-pixel tiles per step, 0 = 8192 */
+    int tiles_per_step;        /* 8x8-pixel tiles per step, 0 = 32768 (about one 1920x1080 image) */
     int steps_in_flight;       /* steps queued ahead on the device, 1..4 (0 = 2) */
 } raypc_server_cfg;
 

@@ -120,7 +120,16 @@ struct RenderArgs {
     int blocks_x, n_blocks;       // 8 x 8 pixel blocks per row, total
 };
 hipError_t launch_render(const RenderArgs& a, int kind, bool counts, hipStream_t s);
-// items[i] = (descriptor slot, tile index); every descriptor's volume uses kernel kind `kind`.
-hipError_t launch_render_batch(const RenderArgs* descs, const uint2* items, int n_items, int kind, hipStream_t s);
+// Work of one batched launch, passed by value in the kernel arguments: range r covers items
+// [end[r-1], end[r]) (end[-1] = 0), which march tiles first[r], first[r] + 1, ... of the request whose
+// arguments are descs[slot[r]].  Every descriptor's volume uses the launch's kernel kind.
+constexpr int kMaxRanges = 32;
+struct BatchRanges {
+    int n;
+    int end[kMaxRanges];
+    int first[kMaxRanges];
+    int slot[kMaxRanges];
+};
+hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& ranges, int kind, hipStream_t s);
 
 }  // namespace raypc

@@ -52,6 +52,16 @@ constexpr int kQuad = 4;              // lanes (consecutive samples) per ray
 constexpr int kWaveTile = 4;          // a wave covers kWaveTile x kWaveTile pixels
 constexpr int kBlockTile = 8;         // a 256-thread block covers 8 x 8 pixels
 
+// Global-memory view of a pointer.  Pointers read from memory (the batched launch takes its
+// arguments from a device array) would otherwise be accessed with generic flat loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const void* p) {
+    return reinterpret_cast<const __attribute__((address_space(1))) T*>(reinterpret_cast<uintptr_t>(p));
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // log2 of the bytes per stored value.
 template <int S>
 constexpr int kLogBytes = S == kF32 ? 2 : (S == kF16 ? 1 : 0);
@@ -95,7 +105,7 @@ __device__ __forceinline__ Source<S> source(const RenderArgs& A, int k) {
 template <int S>
 __device__ __forceinline__ float corner(const Source<S>& src, uint32_t ob) {
     if constexpr (S == kF32) {
-        return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(src.base) + ob);
+        return global_ptr<float>(reinterpret_cast<const char*>(src.base) + ob)[0];
     } else if constexpr (S == kF16) {
         const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(src.rsrc, static_cast<int>(ob), 0, 0);
         return __half2float(__ushort_as_half(h));
@@ -132,7 +142,7 @@ __device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32
                                            float wz) {
     float c0, c1, c2, c3, c4, c5, c6, c7;
     if constexpr (S == kF16) {
-        const uint4 r = *reinterpret_cast<const uint4*>(static_cast<const char*>(base) + static_cast<size_t>(voxel) * 16u);
+        const u32x4 r = global_ptr<u32x4>(static_cast<const char*>(base) + static_cast<size_t>(voxel) * 16u)[0];
         c0 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.x & 0xFFFFu)));
         c1 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.x >> 16)));
         c2 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.y & 0xFFFFu)));
@@ -142,8 +152,8 @@ __device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32
         c6 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.w & 0xFFFFu)));
         c7 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.w >> 16)));
     } else {
-        const float4* p = reinterpret_cast<const float4*>(static_cast<const char*>(base) + static_cast<size_t>(voxel) * 32u);
-        const float4 a = p[0], b = p[1];
+        const auto* p = global_ptr<f32x4>(static_cast<const char*>(base) + static_cast<size_t>(voxel) * 32u);
+        const f32x4 a = p[0], b = p[1];
         c0 = a.x, c1 = a.y, c2 = a.z, c3 = a.w, c4 = b.x, c5 = b.y, c6 = b.z, c7 = b.w;
     }
     const float x00 = fmaf(wx, c1 - c0, c0);
@@ -324,7 +334,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
             const int z0 = min(max(iz, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
             const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
             const uint32_t brick = (static_cast<uint32_t>(bzi) * nb + byi) * nb + bxi;
-            if (A.skip != nullptr && ((A.skip[brick >> 5] >> (brick & 31)) & 1u)) {
+            if (A.skip != nullptr && ((global_ptr<uint32_t>(A.skip)[brick >> 5] >> (brick & 31)) & 1u)) {
                 // every sample inside this brick is discarded or transparent: find the first
                 // sample that may lie beyond it (brick shrunk by a margin against rounding)
                 skipped = true;
@@ -505,7 +515,9 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
         res.w = fmaf(T, A.bg[3], res.w);
     }
     const size_t pix = static_cast<size_t>(py) * A.width + px;
-    A.out[pix] = res;
+    f32x4 o4;
+    o4.x = res.x, o4.y = res.y, o4.z = res.z, o4.w = res.w;
+    reinterpret_cast<__attribute__((address_space(1))) f32x4*>(reinterpret_cast<uintptr_t>(A.out))[pix] = o4;
     if constexpr (COUNTS) {
         if (A.nominal) A.nominal[pix] = cnt_nom;
         if (A.composited) A.composited[pix] = cnt_comp;
@@ -518,28 +530,33 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     interleaved_tile(blockIdx.x, A.blocks_x, bx, by);
     if (by * kBlockTile >= A.height || bx * kBlockTile >= A.width) return;  // padding block
     __shared__ float4 s_tf[256];
-    s_tf[threadIdx.x] = A.tf[threadIdx.x];
+    {
+        const f32x4 e = global_ptr<f32x4>(A.tf)[threadIdx.x];
+        s_tf[threadIdx.x] = make_float4(e.x, e.y, e.z, e.w);
+    }
     __syncthreads();
     march_tile<K, NB, COUNTS>(A, bx, by, s_tf);
 }
 
-// Batched launch: item j marches tile items[j].y of the request whose arguments are descs[items[j].x].
-// Tiles of many requests (different images, brushes, levels and transfer functions, one kernel
-// kind) share a launch; each tile runs exactly the code path of a single-request render.  Chunks
-// of 64 consecutive items (one super-tile of a request, as the scheduler lists them) are dealt
-// round-robin over the 8 XCDs; the grid is padded to whole rounds of 8 chunks.
+// Batched launch: item j marches one tile of one request, as the ranges in the kernel arguments
+// say.  Tiles of many requests (different images, brushes, levels and transfer functions, one
+// kernel kind) share a launch; each tile runs exactly the code path of a single-request render.
+// Chunks of 64 consecutive items (one super-tile of a request, as the scheduler lists them) are
+// dealt round-robin over the 8 XCDs; the grid is padded to whole rounds of 8 chunks.
 template <int K>
-__global__ __launch_bounds__(256) void raymarch_batch_kernel(const RenderArgs* __restrict__ descs,
-                                                             const uint2* __restrict__ items, int n_items) {
+__global__ __launch_bounds__(256) void raymarch_batch_kernel(const RenderArgs* __restrict__ descs, BatchRanges R) {
     __shared__ float4 s_tf[256];
     const int xcd = blockIdx.x & 7, p = blockIdx.x >> 3;
     const int j = ((p >> 6) * 8 + xcd) * 64 + (p & 63);
-    if (j >= n_items) return;  // padding block
-    const uint2 item = items[j];
-    const int slot = __builtin_amdgcn_readfirstlane(static_cast<int>(item.x));
-    const int tile = __builtin_amdgcn_readfirstlane(static_cast<int>(item.y));
-    const RenderArgs& A = descs[slot];
-    s_tf[threadIdx.x] = A.tf[threadIdx.x];
+    if (j >= R.end[R.n - 1]) return;  // padding block
+    int r = 0;
+    while (j >= R.end[r]) ++r;
+    const int tile = R.first[r] + j - (r ? R.end[r - 1] : 0);
+    const RenderArgs& A = descs[R.slot[r]];
+    {
+        const f32x4 e = global_ptr<f32x4>(A.tf)[threadIdx.x];
+        s_tf[threadIdx.x] = make_float4(e.x, e.y, e.z, e.w);
+    }
     __syncthreads();
     int bx, by;
     tile_coords(tile, A.blocks_x, A.n_blocks / A.blocks_x, bx, by);
@@ -576,19 +593,15 @@ hipError_t launch_kind(const RenderArgs& a, int kind, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_render_batch(const RenderArgs* descs, const uint2* items, int n_items, int kind, hipStream_t s) {
-    if (n_items <= 0) return hipSuccess;
-    const dim3 grid((n_items + 511) / 512 * 512), block(256);
+hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& R, int kind, hipStream_t s) {
+    if (R.n <= 0 || R.n > kMaxRanges || R.end[R.n - 1] <= 0) return hipSuccess;
+    const dim3 grid((R.end[R.n - 1] + 511) / 512 * 512), block(256);
     switch (kind) {
-        case kKindF32: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF32>, grid, block, 0, s, descs, items, n_items); break;
-        case kKindF16: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16>, grid, block, 0, s, descs, items, n_items); break;
-        case kKindU8: hipLaunchKernelGGL(raymarch_batch_kernel<kKindU8>, grid, block, 0, s, descs, items, n_items); break;
-        case kKindF32Rec:
-            hipLaunchKernelGGL(raymarch_batch_kernel<kKindF32Rec>, grid, block, 0, s, descs, items, n_items);
-            break;
-        default:
-            hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16Rec>, grid, block, 0, s, descs, items, n_items);
-            break;
+        case kKindF32: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF32>, grid, block, 0, s, descs, R); break;
+        case kKindF16: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16>, grid, block, 0, s, descs, R); break;
+        case kKindU8: hipLaunchKernelGGL(raymarch_batch_kernel<kKindU8>, grid, block, 0, s, descs, R); break;
+        case kKindF32Rec: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF32Rec>, grid, block, 0, s, descs, R); break;
+        default: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16Rec>, grid, block, 0, s, descs, R); break;
     }
     return hipGetLastError();
 }

@@ -10,18 +10,24 @@
 //  * admission takes requests in submission order while a request slot is free
 //    and the memory budget (image bytes + skip bits) allows; admitting uploads
 //    the request's kernel arguments and table to its slot and computes its
-//    skip bits on the server stream;
-//  * every step is one batched launch (one per storage type present) over a
-//    list of (slot, tile) items drawn from the admitted requests, oldest first,
-//    up to tiles_per_step tiles; requests admitted meanwhile join the next step,
-//    so work of many requests overlaps on the device;
-//  * steps are recorded with events; a request is done when the step holding
-//    its last tile has completed, and its slot and budget are released.
+//    skip bits on the upload stream;
+//  * every step is one batched launch (one per storage type present) over
+//    tile ranges of the admitted requests, oldest first, up to tiles_per_step
+//    tiles; the ranges travel in the kernel arguments, so a step copies
+//    nothing.  Requests admitted meanwhile join the next step, so work of many
+//    requests overlaps on the device;
+//  * steps alternate between two streams that wait for the upload stream only
+//    when something was uploaded since they last did: a step's blocks start
+//    while the previous step's last blocks still run, instead of the device
+//    draining at every step boundary;
+//  * steps are recorded with events and retired in launch order; a request is
+//    done when the steps up to the one holding its last tile have completed,
+//    and its slot and budget are released.
 //
 // Device memory is allocated once at server start (per-slot arguments, tables
-// and skip bits, and a small ring of work lists); nothing is allocated or
-// freed per request.  Waiting uses event queries, short condition-variable
-// waits and hipEventSynchronize when the device queue is full.
+// and skip bits); nothing is allocated or freed per request.  Waiting uses
+// event queries, short condition-variable waits and hipEventSynchronize when
+// the device queue is full.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -44,7 +50,7 @@ double now_ms() {
 
 constexpr int kMaxSlots = 256;
 constexpr uint32_t kMaxSkipWords = (128u * 128u * 128u + 31u) / 32u;  // skip bits of a level with 128^3 bricks
-constexpr int kDefaultTilesPerStep = 8192;
+constexpr int kDefaultTilesPerStep = 32768;
 
 struct Request {
     uint64_t ticket = 0;
@@ -63,7 +69,6 @@ struct Request {
 
 struct Step {
     hipEvent_t done = nullptr;
-    int buf = -1;
     std::vector<Request*> finishing;
 };
 
@@ -82,18 +87,19 @@ struct Server {
     std::unordered_map<uint64_t, Request*> all;
     std::vector<int> free_slots;
     std::deque<Step> steps;
-    std::vector<int> free_bufs;
     std::vector<hipEvent_t> events;
     raypc_server_stats stats{};
-    hipStream_t stream = nullptr;
+    hipStream_t upload = nullptr;          // argument / table uploads and skip bits
+    hipStream_t step_stream[2] = {nullptr, nullptr};
+    hipEvent_t uploaded = nullptr;         // recorded on `upload` after each admission round
+    uint64_t upload_seq = 0;               // admission rounds recorded so far
+    uint64_t waited_seq[2] = {0, 0};       // last round each step stream waited for
+    uint64_t n_launched = 0;
     RenderArgs* d_args = nullptr;
     RenderArgs* h_args = nullptr;
     float4* d_tf = nullptr;
     float4* h_tf = nullptr;
     uint32_t* d_skip = nullptr;
-    uint2* d_items = nullptr;
-    uint2* h_items = nullptr;
-    int n_bufs = 0;
     int fatal = 0;  // set when a device call failed: every later request fails with it
 };
 
@@ -129,10 +135,8 @@ void finish_admitted(Server* S, Request* r, int code, double t) {
 
 void fail_everything_active(Server* S, int code) {
     const double t = now_ms();
-    for (auto& st : S->steps) {
-        S->free_bufs.push_back(st.buf);
+    for (auto& st : S->steps)
         if (st.done) S->events.push_back(st.done);
-    }
     S->steps.clear();
     while (!S->active.empty()) finish_admitted(S, S->active.front(), code, t);
     S->fatal = code;
@@ -153,13 +157,13 @@ void retire(Server* S) {
         S->steps.pop_front();
         const double t = now_ms();
         for (Request* r : st.finishing) finish_admitted(S, r, RAYPC_OK, t);
-        S->free_bufs.push_back(st.buf);
         S->events.push_back(st.done);
         S->cv_done.notify_all();
     }
 }
 
 void admit(Server* S) {
+    bool any = false;
     while (!S->queue.empty()) {
         Request* r = S->queue.front();
         if (r->state != RAYPC_REQ_QUEUED) {  // cancelled while queued
@@ -189,11 +193,12 @@ void admit(Server* S) {
         SkipArgs sk = r->skip_args;
         sk.out = const_cast<uint32_t*>(a.skip);
         hipError_t e = hipMemcpyAsync(S->d_args + slot, S->h_args + slot, sizeof(RenderArgs), hipMemcpyHostToDevice,
-                                      S->stream);
+                                      S->upload);
         if (e == hipSuccess)
             e = hipMemcpyAsync(const_cast<float4*>(a.tf), S->h_tf + static_cast<size_t>(slot) * RAYPC_TF_ENTRIES,
-                               sizeof(r->tf_rgba), hipMemcpyHostToDevice, S->stream);
-        if (e == hipSuccess) e = launch_skip(sk, S->stream);
+                               sizeof(r->tf_rgba), hipMemcpyHostToDevice, S->upload);
+        if (e == hipSuccess) e = launch_skip(sk, S->upload);
+        any = true;
         r->slot = slot;
         r->state = RAYPC_REQ_RUNNING;
         r->t[1] = now_ms();
@@ -206,6 +211,14 @@ void admit(Server* S) {
             return;
         }
     }
+    if (any) {
+        if (hipEventRecord(S->uploaded, S->upload) != hipSuccess) {
+            (void)hipGetLastError();
+            fail_everything_active(S, RAYPC_ERR_DEVICE);
+            return;
+        }
+        S->upload_seq++;
+    }
 }
 
 bool has_pending_tiles(const Server* S) {
@@ -214,19 +227,15 @@ bool has_pending_tiles(const Server* S) {
     return false;
 }
 
-// One batched step: tiles of the admitted requests, oldest first, grouped by storage type.
+// One batched step: tile ranges of the admitted requests, oldest first, one launch per kernel kind
+// (more if a kind has more ranges than one launch carries).
 void launch_step(Server* S) {
-    const int tps = S->cfg.tiles_per_step;
-    const int buf = S->free_bufs.back();
-    S->free_bufs.pop_back();
-    uint2* h = S->h_items + static_cast<size_t>(buf) * tps;
-    uint2* d = S->d_items + static_cast<size_t>(buf) * tps;
     struct Take {
         Request* r;
         int start, count;
     };
     std::vector<Take> takes;
-    int budget = tps;
+    int budget = S->cfg.tiles_per_step;
     for (Request* r : S->active) {
         if (budget == 0) break;
         const int left = r->n_tiles - r->next_tile;
@@ -235,21 +244,36 @@ void launch_step(Server* S) {
         takes.push_back({r, r->next_tile, c});
         budget -= c;
     }
-    int k = 0, seg_begin[kKinds] = {}, seg_count[kKinds] = {};
-    for (int st = 0; st < kKinds; ++st) {
-        seg_begin[st] = k;
-        for (const Take& t : takes) {
-            if (t.r->storage != st) continue;
-            for (int i = 0; i < t.count; ++i) h[k++] = make_uint2(static_cast<unsigned>(t.r->slot),
-                                                                  static_cast<unsigned>(t.start + i));
-        }
-        seg_count[st] = k - seg_begin[st];
+    const int which = static_cast<int>(S->n_launched & 1u);
+    hipStream_t s = S->step_stream[which];
+    hipError_t e = hipSuccess;
+    if (S->waited_seq[which] != S->upload_seq) {
+        e = hipStreamWaitEvent(s, S->uploaded, 0);
+        S->waited_seq[which] = S->upload_seq;
     }
-    hipError_t e = hipMemcpyAsync(d, h, sizeof(uint2) * k, hipMemcpyHostToDevice, S->stream);
-    for (int st = 0; st < kKinds && e == hipSuccess; ++st)
-        if (seg_count[st]) e = launch_render_batch(S->d_args, d + seg_begin[st], seg_count[st], st, S->stream);
+    int k = 0;
+    for (int kind = 0; kind < kKinds && e == hipSuccess; ++kind) {
+        BatchRanges R;
+        R.n = 0;
+        int items = 0;
+        for (const Take& t : takes) {
+            if (t.r->storage != kind) continue;
+            if (R.n == kMaxRanges) {
+                e = launch_render_batch(S->d_args, R, kind, s);
+                if (e != hipSuccess) break;
+                R.n = 0;
+                items = 0;
+            }
+            items += t.count;
+            R.end[R.n] = items;
+            R.first[R.n] = t.start;
+            R.slot[R.n] = t.r->slot;
+            R.n++;
+            k += t.count;
+        }
+        if (e == hipSuccess && R.n) e = launch_render_batch(S->d_args, R, kind, s);
+    }
     Step step;
-    step.buf = buf;
     if (S->events.empty()) {
         hipEvent_t ev;
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -258,7 +282,7 @@ void launch_step(Server* S) {
     if (e == hipSuccess) {
         step.done = S->events.back();
         S->events.pop_back();
-        e = hipEventRecord(step.done, S->stream);
+        e = hipEventRecord(step.done, s);
     }
     const double t = now_ms();
     for (const Take& tk : takes) {
@@ -267,6 +291,7 @@ void launch_step(Server* S) {
         if (tk.r->next_tile == tk.r->n_tiles) step.finishing.push_back(tk.r);
     }
     S->steps.push_back(step);
+    S->n_launched++;
     S->stats.steps++;
     S->stats.tiles += static_cast<uint64_t>(k);
     if (e != hipSuccess) {
@@ -309,14 +334,15 @@ void free_resources(Server* S) {
     for (hipEvent_t e : S->events) (void)hipEventDestroy(e);
     for (auto& st : S->steps)
         if (st.done) (void)hipEventDestroy(st.done);
-    if (S->stream) (void)hipStreamDestroy(S->stream);
+    if (S->uploaded) (void)hipEventDestroy(S->uploaded);
+    if (S->upload) (void)hipStreamDestroy(S->upload);
+    for (hipStream_t st : S->step_stream)
+        if (st) (void)hipStreamDestroy(st);
     (void)hipFree(S->d_args);
     (void)hipFree(S->d_tf);
     (void)hipFree(S->d_skip);
-    (void)hipFree(S->d_items);
     (void)hipHostFree(S->h_args);
     (void)hipHostFree(S->h_tf);
-    (void)hipHostFree(S->h_items);
     for (auto& kv : S->all) delete kv.second;
     delete S;
 }
@@ -362,18 +388,16 @@ int raypc_server_start(raypc_ctx* ctx, const raypc_server_cfg* cfg) {
     Server* S = new Server();
     S->ctx = ctx;
     S->cfg = c;
-    S->n_bufs = c.steps_in_flight + 1;
     const size_t slots = static_cast<size_t>(c.max_inflight);
-    hipError_t e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+    hipError_t e = hipStreamCreateWithFlags(&S->upload, hipStreamNonBlocking);
+    for (hipStream_t& st : S->step_stream)
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->uploaded, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_args), slots * sizeof(RenderArgs));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_tf), slots * RAYPC_TF_ENTRIES * sizeof(float4));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_skip), slots * kMaxSkipWords * sizeof(uint32_t));
-    if (e == hipSuccess)
-        e = hipMalloc(reinterpret_cast<void**>(&S->d_items), static_cast<size_t>(S->n_bufs) * c.tiles_per_step * sizeof(uint2));
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&S->h_args), slots * sizeof(RenderArgs), 0);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&S->h_tf), slots * RAYPC_TF_ENTRIES * sizeof(float4), 0);
-    if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&S->h_items), static_cast<size_t>(S->n_bufs) * c.tiles_per_step * sizeof(uint2), 0);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         free_resources(S);
@@ -382,7 +406,6 @@ int raypc_server_start(raypc_ctx* ctx, const raypc_server_cfg* cfg) {
                          hipGetErrorString(e));
     }
     for (int i = c.max_inflight - 1; i >= 0; --i) S->free_slots.push_back(i);
-    for (int i = 0; i < S->n_bufs; ++i) S->free_bufs.push_back(i);
     ctx->server = S;
     S->thread = std::thread(run, S);
     if (prev >= 0) (void)hipSetDevice(prev);
