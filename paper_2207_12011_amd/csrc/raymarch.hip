@@ -118,51 +118,55 @@ __device__ __forceinline__ float corner(const Source<S>& src, uint32_t ob) {
     }
 }
 
-// Corner byte offsets are indexed by bit 0 = x, bit 1 = y, bit 2 = z.
-template <int S>
-__device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)[8], float wx, float wy, float wz) {
-    const float c0 = corner<S>(src, o[0]), c1 = corner<S>(src, o[1]);
-    const float c2 = corner<S>(src, o[2]), c3 = corner<S>(src, o[3]);
-    const float c4 = corner<S>(src, o[4]), c5 = corner<S>(src, o[5]);
-    const float c6 = corner<S>(src, o[6]), c7 = corner<S>(src, o[7]);
-    const float x00 = fmaf(wx, c1 - c0, c0);
-    const float x10 = fmaf(wx, c3 - c2, c2);
-    const float x01 = fmaf(wx, c5 - c4, c4);
-    const float x11 = fmaf(wx, c7 - c6, c6);
-    const float y0 = fmaf(wy, x10 - x00, x00);
-    const float y1 = fmaf(wy, x11 - x01, x01);
-    return fmaf(wz, y1 - y0, y0);
+// Trilinear interpolation written as a weighted sum of the eight corners (index bit 0 = x, bit 1 = y,
+// bit 2 = z).  The weights depend only on the sample position, so one sample computes them once for
+// all its fields; each field then costs eight multiply-adds, which take binary16 corners as operands
+// directly (mixed-precision FMA) instead of converting them first.
+struct Tri {
+    float w[8];
+};
+__device__ __forceinline__ Tri tri_weights(float wx, float wy, float wz) {
+    const float ax = 1.0f - wx, ay = 1.0f - wy, az = 1.0f - wz;
+    const float q0 = ay * az, q1 = wy * az, q2 = ay * wz, q3 = wy * wz;  // (y, z) = (0,0) (1,0) (0,1) (1,1)
+    Tri t;
+    t.w[0] = ax * q0, t.w[1] = wx * q0, t.w[2] = ax * q1, t.w[3] = wx * q1;
+    t.w[4] = ax * q2, t.w[5] = wx * q2, t.w[6] = ax * q3, t.w[7] = wx * q3;
+    return t;
+}
+__device__ __forceinline__ float blend(const Tri& t, float c0, float c1, float c2, float c3, float c4, float c5,
+                                       float c6, float c7) {
+    float v = fmaf(t.w[0], c0, 0.0f);
+    v = fmaf(t.w[1], c1, v);
+    v = fmaf(t.w[2], c2, v);
+    v = fmaf(t.w[3], c3, v);
+    v = fmaf(t.w[4], c4, v);
+    v = fmaf(t.w[5], c5, v);
+    v = fmaf(t.w[6], c6, v);
+    return fmaf(t.w[7], c7, v);
 }
 
-// Trilinear fetch from a corner record (the 8 stored values of one voxel's 2x2x2 neighbourhood, bit 0 =
-// x, bit 1 = y, bit 2 = z): one 16- or 32-byte load per field instead of eight scattered ones.  The
-// arithmetic is the same as fetch(), so both layouts give identical values.
+// Trilinear value from the 8 stored corners at byte offsets o[].
 template <int S>
-__device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32_t voxel, float wx, float wy,
-                                           float wz) {
-    float c0, c1, c2, c3, c4, c5, c6, c7;
+__device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)[8], const Tri& t) {
+    return blend(t, corner<S>(src, o[0]), corner<S>(src, o[1]), corner<S>(src, o[2]), corner<S>(src, o[3]),
+                 corner<S>(src, o[4]), corner<S>(src, o[5]), corner<S>(src, o[6]), corner<S>(src, o[7]));
+}
+
+// Trilinear value from a corner record (the 8 stored values of one voxel's 2x2x2 neighbourhood):
+// one 16- or 32-byte load per field instead of eight scattered ones.  The arithmetic is that of
+// fetch(), so both layouts give identical values.
+template <int S>
+__device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32_t voxel, const Tri& t) {
     if constexpr (S == kF16) {
         const u32x4 r = global_ptr<u32x4>(static_cast<const char*>(base) + static_cast<size_t>(voxel) * 16u)[0];
-        c0 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.x & 0xFFFFu)));
-        c1 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.x >> 16)));
-        c2 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.y & 0xFFFFu)));
-        c3 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.y >> 16)));
-        c4 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.z & 0xFFFFu)));
-        c5 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.z >> 16)));
-        c6 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.w & 0xFFFFu)));
-        c7 = __half2float(__ushort_as_half(static_cast<unsigned short>(r.w >> 16)));
+        auto lo = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u & 0xFFFFu))); };
+        auto hi = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u >> 16))); };
+        return blend(t, lo(r.x), hi(r.x), lo(r.y), hi(r.y), lo(r.z), hi(r.z), lo(r.w), hi(r.w));
     } else {
         const auto* p = global_ptr<f32x4>(static_cast<const char*>(base) + static_cast<size_t>(voxel) * 32u);
         const f32x4 a = p[0], b = p[1];
-        c0 = a.x, c1 = a.y, c2 = a.z, c3 = a.w, c4 = b.x, c5 = b.y, c6 = b.z, c7 = b.w;
+        return blend(t, a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
     }
-    const float x00 = fmaf(wx, c1 - c0, c0);
-    const float x10 = fmaf(wx, c3 - c2, c2);
-    const float x01 = fmaf(wx, c5 - c4, c4);
-    const float x11 = fmaf(wx, c7 - c6, c6);
-    const float y0 = fmaf(wy, x10 - x00, x00);
-    const float y1 = fmaf(wy, x11 - x01, x01);
-    return fmaf(wz, y1 - y0, y0);
 }
 
 // Kernel kinds: storage type and layout.
@@ -199,46 +203,50 @@ __device__ __forceinline__ int quad_bcast(int v) {
     return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xF, 0xF, true);
 }
 
-// Batched launches number a request's tiles in 8 x 8 super-tiles (64 x 64 pixels) in row-major order,
-// tiles row-major inside each (narrower at the right and bottom edges), so consecutive tile indices
+// Tiles are grouped in super-tiles of kSuper x kSuper tiles (32 x 32 pixels) and super-tiles are dealt
+// round-robin over the 8 XCDs (block i runs on XCD i % 8).  The tiles of a super-tile run together
+// on one XCD (their rays share voxels in its L2), and every XCD gets super-tiles from all over the
+// image, so the work of the shell's disc is spread evenly; 32 x 32 pixels balances the two (larger
+// super-tiles leave some XCDs with more of the disc's costly centre, smaller ones share less).
+constexpr int kSuper = 4;
+constexpr int kSuperTiles = kSuper * kSuper;
+
+// Batched launches number a request's tiles super-tile by super-tile in row-major order, tiles
+// row-major inside each (narrower at the right and bottom edges), so consecutive tile indices
 // cover a compact patch of the image.  A bijection of [0, bx_count * by_count).
 __device__ __forceinline__ void tile_coords(int i, int bx_count, int by_count, int& bx, int& by) {
-    constexpr int kS = 8;
-    const int sr = i / (bx_count * kS);
-    const int rem = i - sr * bx_count * kS;
-    const int rows = min(kS, by_count - sr * kS);
-    const int full_cols = bx_count / kS;
-    const int sc = rem / (kS * rows);
+    const int sr = i / (bx_count * kSuper);
+    const int rem = i - sr * bx_count * kSuper;
+    const int rows = min(kSuper, by_count - sr * kSuper);
+    const int full_cols = bx_count / kSuper;
+    const int sc = rem / (kSuper * rows);
     if (sc < full_cols) {
-        const int r2 = rem - sc * kS * rows;
-        bx = sc * kS + r2 % kS;
-        by = sr * kS + r2 / kS;
+        const int r2 = rem - sc * kSuper * rows;
+        bx = sc * kSuper + r2 % kSuper;
+        by = sr * kSuper + r2 / kSuper;
     } else {
-        const int wl = bx_count - full_cols * kS;
-        const int r3 = rem - full_cols * kS * rows;
-        bx = full_cols * kS + r3 % wl;
-        by = sr * kS + r3 / wl;
+        const int wl = bx_count - full_cols * kSuper;
+        const int r3 = rem - full_cols * kSuper * rows;
+        bx = full_cols * kSuper + r3 % wl;
+        by = sr * kSuper + r3 / wl;
     }
 }
 
-// Single-image launches: tiles are grouped in 8 x 8 super-tiles (64 x 64 pixels) and super-tiles are
-// dealt round-robin over the 8 XCDs (block i runs on XCD i % 8): the j-th block an XCD receives is
-// tile j % 64 of super-tile (j / 64) * 8 + xcd.  The 64 tiles of a super-tile run together on one
-// XCD (their rays share voxels in its L2), and every XCD gets super-tiles from all over the image,
-// so the work of the shell's disc is spread evenly.  The grid is padded to whole rounds of 8
-// super-tiles; blocks outside the image return at once.
-__host__ __device__ inline int super_cols(int blocks_x) { return (blocks_x + 7) / 8; }
+// Single-image launches: the j-th block an XCD receives is tile j % 16 of super-tile (j / 16) * 8 + xcd
+// (super-tiles row-major over the image).  The grid is padded to whole rounds of 8 super-tiles;
+// blocks outside the image return at once.
+__host__ __device__ inline int super_cols(int blocks_x) { return (blocks_x + kSuper - 1) / kSuper; }
 __host__ __device__ inline int padded_blocks(int blocks_x, int blocks_y) {
-    const int supers = super_cols(blocks_x) * ((blocks_y + 7) / 8);
-    return (supers + 7) / 8 * 8 * 64;
+    const int supers = super_cols(blocks_x) * ((blocks_y + kSuper - 1) / kSuper);
+    return (supers + 7) / 8 * 8 * kSuperTiles;
 }
 __device__ __forceinline__ void interleaved_tile(int bid, int blocks_x, int& bx, int& by) {
     const int xcd = bid & 7, p = bid >> 3;
-    const int st = (p >> 6) * 8 + xcd;
-    const int w = p & 63;
+    const int st = (p / kSuperTiles) * 8 + xcd;
+    const int w = p % kSuperTiles;
     const int sc = super_cols(blocks_x);
-    bx = (st % sc) * 8 + (w & 7);
-    by = (st / sc) * 8 + (w >> 3);
+    bx = (st % sc) * kSuper + (w % kSuper);
+    by = (st / sc) * kSuper + (w / kSuper);
 }
 
 // Number of brushed fields known only at run time (batched launches mix requests).
@@ -357,17 +365,15 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                         last_brick = brick;
                     }
                 }
-                const float wx = ux - flx, wy = uy - fly, wz = uz - flz;
+                // below the grid both corners of an axis clamp to index 0: a zero weight on the upper
+                // corner gives that value exactly, and lets a record of the clamped base voxel serve
+                const float wx = ix < 0 ? 0.0f : ux - flx, wy = iy < 0 ? 0.0f : uy - fly;
+                const float wz = iz < 0 ? 0.0f : uz - flz;
+                const Tri tw = tri_weights(wx, wy, wz);
                 uint32_t o[8];
                 uint32_t voxel = 0;
-                float rwx = wx, rwy = wy, rwz = wz;
                 if constexpr (R) {
-                    // the record of the clamped base voxel; below the grid both corners clamp to 0,
-                    // which a zero weight reproduces exactly
                     voxel = axis_x(x0) + axis_y(y0, nb) + axis_z(z0, nb);
-                    rwx = ix < 0 ? 0.0f : wx;
-                    rwy = iy < 0 ? 0.0f : wy;
-                    rwz = iz < 0 ? 0.0f : wz;
                 } else {
                     constexpr int L = kLogBytes<S>;
                     const uint32_t X0 = axis_x(x0) << L, X1 = axis_x(x1) << L;
@@ -378,8 +384,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                     o[4] = zy10 + X0, o[5] = zy10 + X1, o[6] = zy11 + X0, o[7] = zy11 + X1;
                 }
                 auto field_value = [&](int k) -> float {
-                    if constexpr (R) return fetch_rec<S>(A.rec[k], voxel, rwx, rwy, rwz);
-                    else return fetch<S>(source<S>(A, k), o, wx, wy, wz);
+                    if constexpr (R) return fetch_rec<S>(A.rec[k], voxel, tw);
+                    else return fetch<S>(source<S>(A, k), o, tw);
                 };
                 bool pass = true;
                 float tv = 0.0f;
@@ -541,13 +547,13 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
 // Batched launch: item j marches one tile of one request, as the ranges in the kernel arguments
 // say.  Tiles of many requests (different images, brushes, levels and transfer functions, one
 // kernel kind) share a launch; each tile runs exactly the code path of a single-request render.
-// Chunks of 64 consecutive items (one super-tile of a request, as the scheduler lists them) are
+// Chunks of 16 consecutive items (one super-tile of a request, as the scheduler lists them) are
 // dealt round-robin over the 8 XCDs; the grid is padded to whole rounds of 8 chunks.
 template <int K>
 __global__ __launch_bounds__(256) void raymarch_batch_kernel(const RenderArgs* __restrict__ descs, BatchRanges R) {
     __shared__ float4 s_tf[256];
     const int xcd = blockIdx.x & 7, p = blockIdx.x >> 3;
-    const int j = ((p >> 6) * 8 + xcd) * 64 + (p & 63);
+    const int j = ((p / kSuperTiles) * 8 + xcd) * kSuperTiles + p % kSuperTiles;
     if (j >= R.end[R.n - 1]) return;  // padding block
     int r = 0;
     while (j >= R.end[r]) ++r;
@@ -595,7 +601,8 @@ hipError_t launch_kind(const RenderArgs& a, int kind, hipStream_t s) {
 
 hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& R, int kind, hipStream_t s) {
     if (R.n <= 0 || R.n > kMaxRanges || R.end[R.n - 1] <= 0) return hipSuccess;
-    const dim3 grid((R.end[R.n - 1] + 511) / 512 * 512), block(256);
+    constexpr int kRound = 8 * kSuperTiles;
+    const dim3 grid((R.end[R.n - 1] + kRound - 1) / kRound * kRound), block(256);
     switch (kind) {
         case kKindF32: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF32>, grid, block, 0, s, descs, R); break;
         case kKindF16: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16>, grid, block, 0, s, descs, R); break;
