@@ -27,7 +27,12 @@ library must reproduce these arrays bit for bit:
   empty interval), or the table
   opacity is zero over every entry the transfer-function field's brick range
   can address; the index map is x(v) = fl32(min(max(fl32(fl32(v - vmin)*inv), 0), 1)*255)
-  with inv = fl32(1/(vmax - vmin)).
+  with inv = fl32(1/(vmax - vmin));
+* sub-brick skip flags: the same rule over the eight 4^3 sub-bricks of every
+  brick, each with its own apron window [4s, min(4s+4, N-1)] per axis, packed
+  one byte per brick with sub-brick (sx, sy, sz) in bit sx + 2 sy + 4 sz.  A
+  sub-brick window lies inside its brick's window, so a skipped brick has all
+  eight sub-bricks skipped; the finer flags let a ray skip part of a brick.
 """
 from __future__ import annotations
 
@@ -36,6 +41,7 @@ import math
 import numpy as np
 
 BRICK = 8
+SUB = 4
 F32 = np.float32
 
 
@@ -126,20 +132,20 @@ def stored_levels(fields: np.ndarray, n_lods: int, storage: str):
 
 
 # ----------------------------------------------------------------------------- tables
-def brick_minmax(v: np.ndarray):
-    """(min, max) float32 [nb]^3 over the apron window [8b, min(8b+8, N-1)] per axis."""
+def brick_minmax(v: np.ndarray, brick: int = BRICK):
+    """(min, max) float32 [N/brick]^3 over the apron window [brick*b, min(brick*b+brick, N-1)] per axis."""
     v = np.asarray(v, F32)
     n = v.shape[0]
-    nb = n // BRICK
-    # pad one voxel at the far end by edge replication: the window then is [8b, 8b+8]
+    nb = n // brick
+    # pad one voxel at the far end by edge replication: the window then is [B b, B b + B]
     p = np.pad(v, ((0, 1), (0, 1), (0, 1)), mode="edge")
     mn = np.empty((nb, nb, nb), F32)
     mx = np.empty((nb, nb, nb), F32)
     for bz in range(nb):
-        slab = p[8 * bz:8 * bz + 9]
+        slab = p[brick * bz:brick * bz + brick + 1]
         for by in range(nb):
-            row = slab[:, 8 * by:8 * by + 9]
-            win = np.lib.stride_tricks.sliding_window_view(row, 9, axis=2)[:, :, ::8][:, :, :nb]
+            row = slab[:, brick * by:brick * by + brick + 1]
+            win = np.lib.stride_tricks.sliding_window_view(row, brick + 1, axis=2)[:, :, ::brick][:, :, :nb]
             mn[bz, by] = win.min(axis=(0, 1, 3))
             mx[bz, by] = win.max(axis=(0, 1, 3))
     return mn, mx
@@ -171,6 +177,25 @@ def skip_bits(mins, maxs, active, lo, hi, tf_field: int, vmin: float, vmax: floa
     nz = csum[i1 + 1] - csum[i0]
     skip |= nz == 0
     return skip
+
+
+def sub_skip_bytes(sub_flags: np.ndarray) -> np.ndarray:
+    """bool [2 nb]^3 sub-brick skip flags -> uint8 [nb^3] (linear brick order), one byte per brick
+    with sub-brick (sx, sy, sz) in bit sx + 2 sy + 4 sz."""
+    f = np.asarray(sub_flags, bool)
+    nb = f.shape[0] // 2
+    out = np.zeros((nb, nb, nb), np.uint8)
+    for sz in range(2):
+        for sy in range(2):
+            for sx in range(2):
+                out |= (f[sz::2, sy::2, sx::2].astype(np.uint8) << (sx + 2 * sy + 4 * sz)).astype(np.uint8)
+    return out.reshape(-1)
+
+
+def sub_skip(fields_level, active, lo, hi, tf_field: int, vmin: float, vmax: float, tf_rgba) -> np.ndarray:
+    """Sub-brick skip bytes of one level's stored fields: the skip rule over 4^3 windows, packed."""
+    mins, maxs = zip(*[brick_minmax(f, SUB) for f in fields_level])
+    return sub_skip_bytes(skip_bits(mins, maxs, active, lo, hi, tf_field, vmin, vmax, tf_rgba))
 
 
 def pack_bits(flags: np.ndarray) -> np.ndarray:

@@ -353,6 +353,73 @@ def test_minmax_bruteforce():
                 assert mn[bz, by, bx] == w.min() and mx[bz, by, bx] == w.max()
 
 
+def test_sub_minmax_bruteforce():
+    rng = np.random.default_rng(16)
+    v = rng.standard_normal((16, 16, 16)).astype(np.float32)
+    mn, mx = pp.brick_minmax(v, 4)
+    assert mn.shape == (4, 4, 4)
+    for sz in range(4):
+        for sy in range(4):
+            for sx in range(4):
+                w = v[4 * sz:min(4 * sz + 5, 16), 4 * sy:min(4 * sy + 5, 16), 4 * sx:min(4 * sx + 5, 16)]
+                assert mn[sz, sy, sx] == w.min() and mx[sz, sy, sx] == w.max()
+
+
+def test_sub_skip_layout():
+    """One sub-brick window holds the only in-range voxels: exactly its bit is clear.  The
+    region (x >= 13, y <= 2, z in 5..6) of a 16^3 grid meets sub-brick windows x [12, 15],
+    y [0, 4], z [4, 8] only: brick (bx, by, bz) = (1, 0, 0), sub-brick (1, 0, 1), bit 5."""
+    v = np.zeros((16, 16, 16), np.float32)
+    v[5:7, 0:3, 13:16] = 1.0
+    tab = np.ones((256, 4), np.float32)
+    got = pp.sub_skip([v], [1], [0.5], [2.0], 0, 0.0, 1.0, tab)
+    want = np.full(8, 0xFF, np.uint8)
+    want[1] = 0xFF & ~(1 << 5)
+    assert np.array_equal(got, want)
+    mins, maxs = pp.brick_minmax(v)
+    coarse = pp.skip_bits([mins], [maxs], [1], [0.5], [2.0], 0, 0.0, 1.0, tab).reshape(-1)
+    assert list(np.flatnonzero(~coarse)) == [1]
+
+
+def test_sub_skip_refines_brick_skip():
+    """A skipped brick has all eight sub-bricks skipped (its window contains theirs), and the
+    sub-brick rule skips strictly more on the tiny workload."""
+    wl = W.make_workload(0, n=32)
+    b = wl.brush
+    mins, maxs = zip(*[pp.brick_minmax(wl.fields[f]) for f in range(2)])
+    coarse = pp.skip_bits(mins, maxs, b.active, b.lo, b.hi, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba)
+    sub = pp.sub_skip(wl.fields, b.active, b.lo, b.hi, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba)
+    c = coarse.reshape(-1)
+    assert np.all(sub[c] == 0xFF)
+    assert np.any(sub[~c] != 0)
+
+
+def test_sub_skip_is_conservative():
+    """Every sample position whose clamped floor index lies in a skipped sub-brick fails the
+    brush or has zero table opacity (dense random positions, FP64 trilinear)."""
+    wl = W.make_workload(0, n=32)
+    fields = wl.fields
+    tab = wl.tf.rgba.copy()
+    tab[:60, 3] = 0.0
+    sub = pp.sub_skip(fields, wl.brush.active, wl.brush.lo, wl.brush.hi, 0, wl.tf.vmin, wl.tf.vmax, tab)
+    rng = np.random.default_rng(17)
+    u = rng.uniform(-0.5, 31.5, (200000, 3))
+    c = np.clip(np.floor(u), 0, 31).astype(int)
+    brick = ((c[:, 2] >> 3) * 4 + (c[:, 1] >> 3)) * 4 + (c[:, 0] >> 3)
+    bit = ((c[:, 0] >> 2) & 1) + 2 * ((c[:, 1] >> 2) & 1) + 4 * ((c[:, 2] >> 2) & 1)
+    sel = ((sub[brick] >> bit) & 1).astype(bool)
+    assert 0 < sel.sum() < sel.size
+    us = u[sel]
+    v0 = oracle.trilinear(fields[0], us)
+    v1 = oracle.trilinear(fields[1], us)
+    passes = (v0 >= wl.brush.lo[0]) & (v0 <= wl.brush.hi[0]) & (v1 >= wl.brush.lo[1]) & (v1 <= wl.brush.hi[1])
+    x = np.clip((v0 - wl.tf.vmin) / (wl.tf.vmax - wl.tf.vmin), 0, 1) * 255
+    i = np.minimum(np.floor(x).astype(int), 254)
+    w = x - i
+    a = (1 - w) * tab[i, 3] + w * tab[i + 1, 3]
+    assert not np.any(passes & (a > 0))
+
+
 def test_voxel_mask_enumeration(tiny):
     wl = tiny
     m = pp.voxel_mask(wl.fields, wl.brush.active, wl.brush.lo, wl.brush.hi)
