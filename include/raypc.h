@@ -210,9 +210,21 @@ int raypc_export_level(raypc_ctx *ctx, int volume_id, int lod, int field, float 
  * bricks in [bz][by][bx] order (nb = N_l / 8). */
 int raypc_export_minmax(raypc_ctx *ctx, int volume_id, int lod, int field, float *out, void *stream);
 
+/* Per-sub-brick (min, max) of one level and field (Section 2.2's empty-space
+ * skipping at a finer grain): for every brick, its eight 4^3 sub-bricks, each
+ * over voxel indices [4s, min(4s+4, N_l-1)] per axis; pair 8 k + sx + 2 sy + 4 sz
+ * belongs to brick k, sub-brick (sx, sy, sz).  nb^3 * 16 float32. */
+int raypc_export_minmax_sub(raypc_ctx *ctx, int volume_id, int lod, int field, float *out, void *stream);
+
 /* Skip bits of one level for the volume's brush and transfer slot `slot`:
  * ceil(nb^3 / 32) uint32 words; brick k is bit k % 32 of word k / 32. */
 int raypc_export_skiplist(raypc_ctx *ctx, int volume_id, int lod, int slot, uint32_t *out, void *stream);
+
+/* Sub-brick skip flags of one level for the volume's brush and transfer slot
+ * `slot` (the skip rule applied to each sub-brick's (min, max)): nb^3 bytes,
+ * byte k = brick k, bit sx + 2 sy + 4 sz set when that sub-brick is skipped.
+ * A skipped brick has all eight bits set.  The renderer skips by these. */
+int raypc_export_subskip(raypc_ctx *ctx, int volume_id, int lod, int slot, uint8_t *out, void *stream);
 
 /* Voxel brush mask of one level: N_l^3 bytes, 1 where every active variable
  * lies in its [lo, hi]. */
@@ -248,7 +260,7 @@ int raypc_render_debug(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, i
 
 typedef struct {
     uint64_t mem_budget_bytes; /* device memory in-flight requests may hold: each counts its image
-                                  (width*height*16 bytes, caller-owned) plus its skip bits;
+                                  (width*height*16 bytes, caller-owned) plus its sub-brick skip flags (one byte per brick);
                                   0 = unlimited */
     int max_inflight;          /* request slots, 1..256 */
     int tiles_per_step;        /* 8x8-pixel tiles per step, 0 = 32768 (about one 1920x1080 image) */

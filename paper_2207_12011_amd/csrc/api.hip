@@ -184,12 +184,14 @@ void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t
     for (int f = 0; f < v->nf; ++f) {
         if (!active[f]) continue;
         a.minmax[k] = L.mm[f];
+        a.minmax_sub[k] = L.mm_sub[f];
         a.lo[k] = lo[f];
         a.hi[k] = hi[f];
         ++k;
     }
     a.n_active = k;
     a.tf_minmax = L.mm[tf.field];
+    a.tf_minmax_sub = L.mm_sub[tf.field];
     a.vmin = tf.vmin;
     a.inv_range = 1.0f / (tf.vmax - tf.vmin);
     int nxt = RAYPC_TF_ENTRIES;
@@ -200,9 +202,11 @@ void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t
     }
     a.n_bricks = L.n_bricks();
     a.out = nullptr;
+    a.out_sub = nullptr;
 }
 
-// Recompute the skip bits of level l for the volume's own brush and a transfer slot if stale.
+// Recompute the skip bits and sub-brick flags of level l for the volume's own brush and a transfer
+// slot if stale.
 static int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s) {
     Level& L = v->lv[l];
     const TFSlot& tf = ctx->tf[slot];
@@ -211,6 +215,7 @@ static int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s
     SkipArgs a;
     build_skip_args(ctx, v, l, v->active, v->lo, v->hi, slot, a);
     a.out = L.skip;
+    a.out_sub = L.skip_sub;
     HIP_TRY(launch_skip(a, s), "skip-list kernel launch");
     L.skip_valid = true;
     L.skip_brush_gen = v->brush_gen;
@@ -298,7 +303,7 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
     if (use_volume_state) {
         rc = ensure_skip(ctx, v, lod, tf_slot, s);
         if (rc) return rc;
-        a.skip = v->lv[lod].skip;
+        a.skip = v->lv[lod].skip_sub;
     }
     storage = v->records ? (v->storage == kF32 ? kKindF32Rec : kKindF16Rec) : v->storage;  // kernel kind
     level = lod;
@@ -405,9 +410,11 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 rc = dev_alloc(v, &L.data[f], lvox * storage_bytes(storage));
                 if (!rc && storage == kU8) rc = dev_alloc(v, reinterpret_cast<void**>(&L.par[f]), L.n_bricks() * sizeof(float2));
                 if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm[f]), L.n_bricks() * sizeof(float2));
+                if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm_sub[f]), L.n_bricks() * 8 * sizeof(float2));
                 if (!rc && v->records) rc = dev_alloc(v, &L.rec[f], lvox * 8 * storage_bytes(storage));
             }
             if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip), L.n_words() * sizeof(uint32_t));
+            if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip_sub), L.n_bricks());
         }
         if (rc) break;
         if (!on_device && (rc = tmp_alloc(reinterpret_cast<void**>(&stage), nvox * sizeof(float)))) break;
@@ -433,7 +440,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                     cur = nxt;
                 }
                 if ((e = launch_encode(cur, L.n, storage, L.data[f], L.par[f], s)) != hipSuccess) { rc = hip_fail(e, "encode"); break; }
-                if ((e = launch_minmax(L.data[f], L.par[f], L.n, storage, L.mm[f], s)) != hipSuccess) { rc = hip_fail(e, "min/max"); break; }
+                if ((e = launch_minmax(L.data[f], L.par[f], L.n, storage, L.mm[f], L.mm_sub[f], s)) != hipSuccess) { rc = hip_fail(e, "min/max"); break; }
                 if (v->records && (e = launch_records(L.data[f], L.n, storage, L.rec[f], s)) != hipSuccess) { rc = hip_fail(e, "corner records"); break; }
             }
         }
@@ -641,7 +648,22 @@ int raypc_export_minmax(raypc_ctx* ctx, int volume_id, int lod, int field, float
     return RAYPC_OK;
 }
 
-int raypc_export_skiplist(raypc_ctx* ctx, int volume_id, int lod, int slot, uint32_t* out, void* stream) {
+int raypc_export_minmax_sub(raypc_ctx* ctx, int volume_id, int lod, int field, float* out, void* stream) {
+    if (!ctx || !out) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    DeviceGuard g(ctx->device);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    int rc = check_level(v, lod);
+    if (rc) return rc;
+    if (field < 0 || field >= v->nf) return fail(RAYPC_ERR_INVALID, "field %d outside [0, %d)", field, v->nf);
+    const Level& L = v->lv[lod];
+    HIP_TRY(hipMemcpyAsync(out, L.mm_sub[field], L.n_bricks() * 8 * sizeof(float2), hipMemcpyDeviceToDevice,
+                           static_cast<hipStream_t>(stream)),
+            "hipMemcpyAsync(sub-brick min/max)");
+    return RAYPC_OK;
+}
+
+static int export_skip(raypc_ctx* ctx, int volume_id, int lod, int slot, void* out, bool sub, void* stream) {
     if (!ctx || !out) return fail(RAYPC_ERR_INVALID, "NULL argument");
     DeviceGuard g(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -656,9 +678,20 @@ int raypc_export_skiplist(raypc_ctx* ctx, int volume_id, int lod, int slot, uint
     rc = ensure_skip(ctx, v, lod, slot, s);
     if (rc) return rc;
     const Level& L = v->lv[lod];
-    HIP_TRY(hipMemcpyAsync(out, L.skip, L.n_words() * sizeof(uint32_t), hipMemcpyDeviceToDevice, s),
-            "hipMemcpyAsync(skip list)");
+    if (sub)
+        HIP_TRY(hipMemcpyAsync(out, L.skip_sub, L.n_bricks(), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(sub-brick flags)");
+    else
+        HIP_TRY(hipMemcpyAsync(out, L.skip, L.n_words() * sizeof(uint32_t), hipMemcpyDeviceToDevice, s),
+                "hipMemcpyAsync(skip list)");
     return RAYPC_OK;
+}
+
+int raypc_export_skiplist(raypc_ctx* ctx, int volume_id, int lod, int slot, uint32_t* out, void* stream) {
+    return export_skip(ctx, volume_id, lod, slot, out, false, stream);
+}
+
+int raypc_export_subskip(raypc_ctx* ctx, int volume_id, int lod, int slot, uint8_t* out, void* stream) {
+    return export_skip(ctx, volume_id, lod, slot, out, true, stream);
 }
 
 int raypc_export_voxel_mask(raypc_ctx* ctx, int volume_id, int lod, uint8_t* out, void* stream) {

@@ -18,8 +18,10 @@ struct Level {
     void* data[kMaxFields] = {};
     float2* par[kMaxFields] = {};
     float2* mm[kMaxFields] = {};
+    float2* mm_sub[kMaxFields] = {};  // per brick, its eight 4^3 sub-bricks' (min, max)
     void* rec[kMaxFields] = {};  // corner records (null when the volume keeps only the compact layout)
-    uint32_t* skip = nullptr;
+    uint32_t* skip = nullptr;    // brick skip bits
+    uint8_t* skip_sub = nullptr; // sub-brick skip flags, one byte per brick
     bool skip_valid = false;
     uint64_t skip_brush_gen = 0, skip_tf_gen = 0;
     int skip_slot = -1;

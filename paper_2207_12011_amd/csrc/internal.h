@@ -52,8 +52,10 @@ hipError_t launch_count_nonfinite(const float* x, size_t count, unsigned int* fl
 hipError_t launch_lod_build(const float* in, int n, float* out, hipStream_t s);
 // Encode a linear float32 level into brick-ordered storage (u8 also writes per-brick (scale, offset)).
 hipError_t launch_encode(const float* in, int n, int storage, void* out, float2* u8par, hipStream_t s);
-// Per-brick (min, max) of stored values over the 9^3 apron window.
-hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, hipStream_t s);
+// Per-brick (min, max) of stored values over the 9^3 apron window, and per 4^3 sub-brick over its 5^3
+// apron window: out_sub[8 brick + sx + 2 sy + 4 sz].
+hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, float2* out_sub,
+                         hipStream_t s);
 // Corner records: for every voxel (x, y, z), the 8 stored values at (x+dx, y+dy, z+dz), dx, dy, dz in
 // {0, 1}, clamped to N-1, in the order bit 0 = dx, bit 1 = dy, bit 2 = dz; record i sits at
 // brick_addr(x, y, z) x 8 values (binary16: 16 bytes, float32: 32 bytes).
@@ -72,14 +74,17 @@ struct MaskArgs {
 hipError_t launch_voxel_mask(const MaskArgs& a, hipStream_t s);
 
 struct SkipArgs {
-    const float2* minmax[kMaxFields];  // active fields' (min, max) tables
+    const float2* minmax[kMaxFields];      // active fields' brick (min, max) tables
+    const float2* minmax_sub[kMaxFields];  // and their sub-brick tables
     float lo[kMaxFields], hi[kMaxFields];
     int n_active;
-    const float2* tf_minmax;           // table of the transfer-function field
-    float vmin, inv_range;             // inv_range = fl32(1 / (vmax - vmin))
-    int next_nonzero[257];             // smallest entry index >= i with opacity > 0 (256 if none)
+    const float2* tf_minmax;               // tables of the transfer-function field
+    const float2* tf_minmax_sub;
+    float vmin, inv_range;                 // inv_range = fl32(1 / (vmax - vmin))
+    int next_nonzero[257];                 // smallest entry index >= i with opacity > 0 (256 if none)
     uint32_t n_bricks;
-    uint32_t* out;                     // ceil(n_bricks / 32) words
+    uint32_t* out;                         // brick skip bits, ceil(n_bricks / 32) words (may be null)
+    uint8_t* out_sub;                      // sub-brick skip flags, one byte per brick (may be null)
 };
 hipError_t launch_skip(const SkipArgs& a, hipStream_t s);
 
@@ -96,7 +101,7 @@ struct RenderArgs {
     uint32_t field_bytes;         // bytes of one field of this level (buffer range; f16 and u8 only)
     uint32_t par_bytes;           // bytes of one field's per-brick (scale, offset) table (u8)
     float half_n;                 // N / 2: u = (p + 1) N/2 - 1/2
-    const uint32_t* skip;         // brick skip bits, or nullptr for no skipping
+    const uint8_t* skip;          // per brick, bit sx + 2 sy + 4 sz: 4^3 sub-brick skipped (nullptr: no skipping)
     const float4* tf;             // 256 straight-RGBA entries
     float vmin, inv_range;
     float inv_ref;                // 1 / ref_step

@@ -10,12 +10,15 @@
 //    decoded as fl32(fl32(scale * q) + offset);
 //  * brick (min, max) of decoded values over voxel indices [8b, min(8b+8, N-1)]
 //    per axis -- every voxel a sample whose clamped floor index lies in brick b
-//    can read;
+//    can read -- and the same over [4s, min(4s+4, N-1)] for each 4^3 sub-brick s;
 //  * skip bits (Section 2.2: brush changes rebuild nothing, so only this
 //    bit-per-brick table is recomputed): a brick is skipped when an active
 //    variable's brick range misses [lo, hi] (or lo > hi), or when the table
 //    opacity is zero over every entry the transfer-function variable's brick
-//    range can address;
+//    range can address; the same rule per 4^3 sub-brick gives one byte of
+//    sub-brick flags per brick (bit sx + 2 sy + 4 sz), which the ray marcher
+//    reads: a brick's window contains its sub-bricks' windows, so a skipped
+//    brick has all eight flags set and the bytes alone drive the skipping;
 //  * voxel brush masks and decoded exports for parity checks.
 // Everything here is streaming work over HBM; none of it is on the per-frame path
 // except the skip bits, which touch only the small min/max tables.
@@ -113,25 +116,53 @@ __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ i
     }
 }
 
-// One wave per brick: min / max over the 9^3 apron window of stored values.
+// One wave per brick: min / max over the 9^3 apron window of stored values, and over the 5^3 apron
+// window of each 4^3 sub-brick (local offsets [4 s, 4 s + 4] per axis, s = 0, 1; offset 4 belongs
+// to both halves).  The brick window is the union of the sub-brick windows.
 template <int S>
 __global__ __launch_bounds__(64) void minmax_kernel(const void* __restrict__ data, const float2* __restrict__ par,
-                                                    int n, float2* __restrict__ out) {
+                                                    int n, float2* __restrict__ out, float2* __restrict__ out_sub) {
     const int nb = n >> 3;
     const uint32_t brick = blockIdx.x;
     const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
-    float mn = INFINITY, mx = -INFINITY;
-    for (int k = threadIdx.x; k < 729; k += 64) {
-        const int x = min(bx * 8 + k % 9, n - 1);
-        const int y = min(by * 8 + (k / 9) % 9, n - 1);
-        const int z = min(bz * 8 + k / 81, n - 1);
-        const float v = stored<S>(data, par, brick_addr(x, y, z, nb));
-        mn = fminf(mn, v);
-        mx = fmaxf(mx, v);
+    float mn[8], mx[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        mn[i] = INFINITY;
+        mx[i] = -INFINITY;
     }
-    mn = wave_min(mn);
-    mx = wave_max(mx);
-    if (threadIdx.x == 0) out[brick] = make_float2(mn, mx);
+    for (int k = threadIdx.x; k < 729; k += 64) {
+        const int lx = k % 9, ly = (k / 9) % 9, lz = k / 81;
+        const int x = min(bx * 8 + lx, n - 1);
+        const int y = min(by * 8 + ly, n - 1);
+        const int z = min(bz * 8 + lz, n - 1);
+        const float v = stored<S>(data, par, brick_addr(x, y, z, nb));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const bool in = ((i & 1) ? lx >= 4 : lx <= 4) && ((i & 2) ? ly >= 4 : ly <= 4) &&
+                            ((i & 4) ? lz >= 4 : lz <= 4);
+            if (in) {
+                mn[i] = fminf(mn[i], v);
+                mx[i] = fmaxf(mx[i], v);
+            }
+        }
+    }
+    float bmn = INFINITY, bmx = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        mn[i] = wave_min(mn[i]);
+        mx[i] = wave_max(mx[i]);
+        bmn = fminf(bmn, mn[i]);
+        bmx = fmaxf(bmx, mx[i]);
+    }
+    if (threadIdx.x < 8) {
+        float a = mn[0], b = mx[0];
+#pragma unroll
+        for (int i = 1; i < 8; ++i)
+            if (static_cast<int>(threadIdx.x) == i) a = mn[i], b = mx[i];
+        out_sub[static_cast<size_t>(brick) * 8 + threadIdx.x] = make_float2(a, b);
+    }
+    if (threadIdx.x == 0) out[brick] = make_float2(bmn, bmx);
 }
 
 template <int S>
@@ -179,22 +210,43 @@ __global__ void voxel_mask_kernel(MaskArgs a) {
     a.out[o] = keep ? 1 : 0;
 }
 
-// One thread per brick; a wave ballot packs 64 skip flags into two words.
+// The skip rule for one (min, max) window: some active field misses its [lo, hi] (or lo > hi), or
+// the table opacity is zero over every entry the transfer-function field's range can address.
+__device__ __forceinline__ bool tf_range_empty(const SkipArgs& a, float2 tm) {
+    const float t0 = fminf(fmaxf(__fmul_rn(__fsub_rn(tm.x, a.vmin), a.inv_range), 0.0f), 1.0f);
+    const float t1 = fminf(fmaxf(__fmul_rn(__fsub_rn(tm.y, a.vmin), a.inv_range), 0.0f), 1.0f);
+    const int i0 = static_cast<int>(floorf(__fmul_rn(t0, 255.0f)));
+    const int i1 = min(static_cast<int>(ceilf(__fmul_rn(t1, 255.0f))), 255);
+    return a.next_nonzero[i0] > i1;
+}
+
+// One thread per brick: the brick's skip bit (a wave ballot packs 64 into two words) and its byte
+// of sub-brick flags.
 __global__ __launch_bounds__(256) void skip_kernel(SkipArgs a) {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     bool skip = false;
+    uint32_t sub = 0;
     if (b < a.n_bricks) {
         for (int f = 0; f < a.n_active; ++f) {
             const float2 mm = a.minmax[f][b];
             skip |= (mm.y < a.lo[f]) | (mm.x > a.hi[f]) | (a.lo[f] > a.hi[f]);
         }
-        const float2 tm = a.tf_minmax[b];
-        const float t0 = fminf(fmaxf(__fmul_rn(__fsub_rn(tm.x, a.vmin), a.inv_range), 0.0f), 1.0f);
-        const float t1 = fminf(fmaxf(__fmul_rn(__fsub_rn(tm.y, a.vmin), a.inv_range), 0.0f), 1.0f);
-        const int i0 = static_cast<int>(floorf(__fmul_rn(t0, 255.0f)));
-        const int i1 = min(static_cast<int>(ceilf(__fmul_rn(t1, 255.0f))), 255);
-        skip |= a.next_nonzero[i0] > i1;
+        skip |= tf_range_empty(a, a.tf_minmax[b]);
+        if (a.out_sub != nullptr) {
+            for (int i = 0; i < 8; ++i) {
+                const size_t o = static_cast<size_t>(b) * 8 + i;
+                bool s = false;
+                for (int f = 0; f < a.n_active; ++f) {
+                    const float2 mm = a.minmax_sub[f][o];
+                    s |= (mm.y < a.lo[f]) | (mm.x > a.hi[f]) | (a.lo[f] > a.hi[f]);
+                }
+                s |= tf_range_empty(a, a.tf_minmax_sub[o]);
+                sub |= static_cast<uint32_t>(s) << i;
+            }
+            a.out_sub[b] = static_cast<uint8_t>(sub);
+        }
     }
+    if (a.out == nullptr) return;
     const unsigned long long m = __ballot(skip);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t word = (b - lane) >> 5;  // first of the wave's two words
@@ -231,12 +283,19 @@ hipError_t launch_encode(const float* in, int n, int storage, void* out, float2*
     return hipGetLastError();
 }
 
-hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, hipStream_t s) {
+hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, float2* out_sub,
+                         hipStream_t s) {
     const unsigned nbr = static_cast<unsigned>((n / 8) * (n / 8) * (n / 8));
     switch (storage) {
-        case kF32: hipLaunchKernelGGL(minmax_kernel<kF32>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out); break;
-        case kF16: hipLaunchKernelGGL(minmax_kernel<kF16>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out); break;
-        default: hipLaunchKernelGGL(minmax_kernel<kU8>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out); break;
+        case kF32:
+            hipLaunchKernelGGL(minmax_kernel<kF32>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out, out_sub);
+            break;
+        case kF16:
+            hipLaunchKernelGGL(minmax_kernel<kF16>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out, out_sub);
+            break;
+        default:
+            hipLaunchKernelGGL(minmax_kernel<kU8>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out, out_sub);
+            break;
     }
     return hipGetLastError();
 }

@@ -34,11 +34,11 @@
 // sum whatever the grouping.  Every lane of a quad holds identical copies of
 // the ray state.  A wave
 // leaves its loop when all 16 of its rays have terminated or left the shell.
-// Bricks whose skip bit is set are stepped over without fetching: every sample
-// inside such a brick would be discarded or fully transparent, so skipping
-// changes no value.  Blocks of 4 waves (8 x 8 pixels) are remapped so that each
-// XCD works on one contiguous band of the image; the transfer function sits in
-// LDS.
+// 4^3 sub-bricks flagged as skipped are stepped over without fetching (the whole
+// 8^3 brick when all eight of its sub-bricks are flagged): every sample whose
+// base corner lies in such a box would be discarded or fully transparent, so
+// skipping changes no value.  Blocks of 4 waves (8 x 8 pixels) are dealt to the
+// XCDs by 32 x 32-pixel super-tiles; the transfer function sits in LDS.
 #include <hip/hip_fp16.h>
 
 #include "internal.h"
@@ -46,8 +46,8 @@
 namespace raypc {
 namespace {
 
-constexpr float kSkipShrink = 2e-3f;  // voxels: shrink of a skipped brick before computing its exit
-constexpr float kSkipMargin = 0.01f;  // samples: margin on the first sample after a skipped brick
+constexpr float kSkipShrink = 2e-3f;  // voxels: shrink of a skipped box before computing its exit
+constexpr float kSkipMargin = 0.01f;  // samples: margin on the first sample after a skipped box
 constexpr int kQuad = 4;              // lanes (consecutive samples) per ray
 constexpr int kWaveTile = 4;          // a wave covers kWaveTile x kWaveTile pixels
 constexpr int kBlockTile = 8;         // a 256-thread block covers 8 x 8 pixels
@@ -342,16 +342,24 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
             const int z0 = min(max(iz, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
             const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
             const uint32_t brick = (static_cast<uint32_t>(bzi) * nb + byi) * nb + bxi;
-            if (A.skip != nullptr && ((global_ptr<uint32_t>(A.skip)[brick >> 5] >> (brick & 31)) & 1u)) {
-                // every sample inside this brick is discarded or transparent: find the first
-                // sample that may lie beyond it (brick shrunk by a margin against rounding)
+            const uint32_t flags = A.skip != nullptr ? global_ptr<uint8_t>(A.skip)[brick] : 0u;
+            const uint32_t sub = ((x0 >> 2) & 1) | (((y0 >> 2) & 1) << 1) | (((z0 >> 2) & 1) << 2);
+            if ((flags >> sub) & 1u) {
+                // every sample whose base corner lies in this sub-brick (in this brick, when all
+                // eight are flagged) is discarded or transparent: find the first sample that may lie
+                // beyond the box (shrunk by a margin against rounding; open at the grid's faces,
+                // where clamping maps every outside position to the boundary box)
                 skipped = true;
-                const float lx = bxi == 0 ? -INFINITY : bxi * 8.0f + kSkipShrink;
-                const float hx = bxi == nb - 1 ? INFINITY : bxi * 8.0f + 8.0f - kSkipShrink;
-                const float ly = byi == 0 ? -INFINITY : byi * 8.0f + kSkipShrink;
-                const float hy = byi == nb - 1 ? INFINITY : byi * 8.0f + 8.0f - kSkipShrink;
-                const float lz = bzi == 0 ? -INFINITY : bzi * 8.0f + kSkipShrink;
-                const float hz = bzi == nb - 1 ? INFINITY : bzi * 8.0f + 8.0f - kSkipShrink;
+                const bool whole = flags == 0xFFu;
+                const int e = whole ? 8 : 4;
+                const int cx = whole ? bxi * 8 : x0 & ~3, cy = whole ? byi * 8 : y0 & ~3;
+                const int cz = whole ? bzi * 8 : z0 & ~3;
+                const float lx = cx == 0 ? -INFINITY : static_cast<float>(cx) + kSkipShrink;
+                const float hx = cx + e >= n ? INFINITY : static_cast<float>(cx + e) - kSkipShrink;
+                const float ly = cy == 0 ? -INFINITY : static_cast<float>(cy) + kSkipShrink;
+                const float hy = cy + e >= n ? INFINITY : static_cast<float>(cy + e) - kSkipShrink;
+                const float lz = cz == 0 ? -INFINITY : static_cast<float>(cz) + kSkipShrink;
+                const float hz = cz + e >= n ? INFINITY : static_cast<float>(cz + e) - kSkipShrink;
                 const float t_exit = fminf(axis_exit(uox, dux, inv_dux, lx, hx),
                                            fminf(axis_exit(uoy, duy, inv_duy, ly, hy),
                                                  axis_exit(uoz, duz, inv_duz, lz, hz)));

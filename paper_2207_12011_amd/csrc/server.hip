@@ -8,9 +8,9 @@
 //    captures its brush, transfer function and kernel arguments; it then waits
 //    in a FIFO queue;
 //  * admission takes requests in submission order while a request slot is free
-//    and the memory budget (image bytes + skip bits) allows; admitting uploads
+//    and the memory budget (image bytes + skip flags) allows; admitting uploads
 //    the request's kernel arguments and table to its slot and computes its
-//    skip bits on the upload stream;
+//    sub-brick skip flags on the upload stream;
 //  * every step is one batched launch (one per storage type present) over
 //    tile ranges of the admitted requests, oldest first, up to tiles_per_step
 //    tiles; the ranges travel in the kernel arguments, so a step copies
@@ -25,7 +25,7 @@
 //    and its slot and budget are released.
 //
 // Device memory is allocated once at server start (per-slot arguments, tables
-// and skip bits); nothing is allocated or freed per request.  Waiting uses
+// and skip flags); nothing is allocated or freed per request.  Waiting uses
 // event queries, short condition-variable waits and hipEventSynchronize when
 // the device queue is full.
 #include <algorithm>
@@ -49,7 +49,7 @@ double now_ms() {
 }
 
 constexpr int kMaxSlots = 256;
-constexpr uint32_t kMaxSkipWords = (128u * 128u * 128u + 31u) / 32u;  // skip bits of a level with 128^3 bricks
+constexpr size_t kMaxSkipBytes = 128u * 128u * 128u;  // sub-brick flags of a level with 128^3 bricks
 constexpr int kDefaultTilesPerStep = 32768;
 
 struct Request {
@@ -58,7 +58,7 @@ struct Request {
     double deadline = 0.0;         // absolute, ms; 0: none
     double t[4] = {0, 0, 0, 0};
     RenderArgs args{};             // complete except the per-slot skip / table pointers
-    SkipArgs skip_args{};          // complete except the output pointer
+    SkipArgs skip_args{};          // complete except the output pointers
     float tf_rgba[RAYPC_TF_ENTRIES * 4];
     int storage = 0;  // kernel kind
     int n_tiles = 0, next_tile = 0;
@@ -89,7 +89,7 @@ struct Server {
     std::deque<Step> steps;
     std::vector<hipEvent_t> events;
     raypc_server_stats stats{};
-    hipStream_t upload = nullptr;          // argument / table uploads and skip bits
+    hipStream_t upload = nullptr;          // argument / table uploads and skip flags
     hipStream_t step_stream[2] = {nullptr, nullptr};
     hipEvent_t uploaded = nullptr;         // recorded on `upload` after each admission round
     uint64_t upload_seq = 0;               // admission rounds recorded so far
@@ -99,7 +99,7 @@ struct Server {
     RenderArgs* h_args = nullptr;
     float4* d_tf = nullptr;
     float4* h_tf = nullptr;
-    uint32_t* d_skip = nullptr;
+    uint8_t* d_skip = nullptr;
     int fatal = 0;  // set when a device call failed: every later request fails with it
 };
 
@@ -186,12 +186,13 @@ void admit(Server* S) {
         const int slot = S->free_slots.back();
         S->free_slots.pop_back();
         RenderArgs a = r->args;
-        a.skip = S->d_skip + static_cast<size_t>(slot) * kMaxSkipWords;
+        a.skip = S->d_skip + static_cast<size_t>(slot) * kMaxSkipBytes;
         a.tf = S->d_tf + static_cast<size_t>(slot) * RAYPC_TF_ENTRIES;
         S->h_args[slot] = a;
         std::memcpy(S->h_tf + static_cast<size_t>(slot) * RAYPC_TF_ENTRIES, r->tf_rgba, sizeof(r->tf_rgba));
         SkipArgs sk = r->skip_args;
-        sk.out = const_cast<uint32_t*>(a.skip);
+        sk.out = nullptr;  // the renderer reads only the sub-brick flags
+        sk.out_sub = const_cast<uint8_t*>(a.skip);
         hipError_t e = hipMemcpyAsync(S->d_args + slot, S->h_args + slot, sizeof(RenderArgs), hipMemcpyHostToDevice,
                                       S->upload);
         if (e == hipSuccess)
@@ -395,7 +396,7 @@ int raypc_server_start(raypc_ctx* ctx, const raypc_server_cfg* cfg) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->uploaded, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_args), slots * sizeof(RenderArgs));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_tf), slots * RAYPC_TF_ENTRIES * sizeof(float4));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_skip), slots * kMaxSkipWords * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_skip), slots * kMaxSkipBytes);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&S->h_args), slots * sizeof(RenderArgs), 0);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&S->h_tf), slots * RAYPC_TF_ENTRIES * sizeof(float4), 0);
     if (e != hipSuccess) {
@@ -439,7 +440,7 @@ int raypc_submit(raypc_ctx* ctx, const raypc_request* req, uint64_t* ticket) {
         std::memcpy(r->tf_rgba, ctx->tf[req->tf_slot].rgba, sizeof(r->tf_rgba));
         r->n_tiles = r->args.n_blocks;
         r->bytes = static_cast<uint64_t>(req->width) * req->height * 16u +
-                   static_cast<uint64_t>((r->skip_args.n_bricks + 31u) / 32u) * 4u;
+                   static_cast<uint64_t>(r->skip_args.n_bricks);
         if (S->cfg.mem_budget_bytes && r->bytes > S->cfg.mem_budget_bytes) {
             delete r;
             return set_error(RAYPC_ERR_NOMEM, "request needs %llu bytes, the server budget is %llu",

@@ -77,7 +77,9 @@ _render = _sig("raypc_render", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _
 _render_prog = _sig("raypc_render_progressive", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _I, _P, _P)
 _export_level = _sig("raypc_export_level", _I, _P, _I, _I, _I, _P, _P)
 _export_minmax = _sig("raypc_export_minmax", _I, _P, _I, _I, _I, _P, _P)
+_export_minmax_sub = _sig("raypc_export_minmax_sub", _I, _P, _I, _I, _I, _P, _P)
 _export_skip = _sig("raypc_export_skiplist", _I, _P, _I, _I, _I, _P, _P)
+_export_subskip = _sig("raypc_export_subskip", _I, _P, _I, _I, _I, _P, _P)
 _export_mask = _sig("raypc_export_voxel_mask", _I, _P, _I, _I, _P, _P)
 _render_debug = _sig("raypc_render_debug", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _P, _I,
                      _P)
@@ -116,8 +118,8 @@ EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_po
             "raypc_create", "raypc_destroy", "raypc_last_error", "raypc_version", "raypc_load_fields",
             "raypc_unload", "raypc_volume_info", "raypc_set_brush", "raypc_set_transfer_function",
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
-            "raypc_export_level", "raypc_export_minmax", "raypc_export_skiplist", "raypc_export_voxel_mask",
-            "raypc_render_debug"]
+            "raypc_export_level", "raypc_export_minmax", "raypc_export_minmax_sub", "raypc_export_skiplist",
+            "raypc_export_subskip", "raypc_export_voxel_mask", "raypc_render_debug"]
 
 
 class RaypcError(RuntimeError):
@@ -292,6 +294,21 @@ def export_minmax(ctx, volume_id: int, lod: int, field: int, stream=None) -> tor
     nb = (volume_info(ctx, volume_id)["n"] >> lod) // 8
     out = torch.empty((nb, nb, nb, 2), dtype=torch.float32, device="cuda")
     _check(_export_minmax(ctx, int(volume_id), int(lod), int(field), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def export_minmax_sub(ctx, volume_id: int, lod: int, field: int, stream=None) -> torch.Tensor:
+    """[nb, nb, nb, 8 sub-bricks (bit sx + 2 sy + 4 sz), 2] float32."""
+    nb = (volume_info(ctx, volume_id)["n"] >> lod) // 8
+    out = torch.empty((nb, nb, nb, 8, 2), dtype=torch.float32, device="cuda")
+    _check(_export_minmax_sub(ctx, int(volume_id), int(lod), int(field), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def export_subskip(ctx, volume_id: int, lod: int, slot: int = 0, stream=None) -> torch.Tensor:
+    nb = (volume_info(ctx, volume_id)["n"] >> lod) // 8
+    out = torch.empty((nb ** 3,), dtype=torch.uint8, device="cuda")
+    _check(_export_subskip(ctx, int(volume_id), int(lod), int(slot), out.data_ptr(), _stream(stream)))
     return out
 
 

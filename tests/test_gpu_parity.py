@@ -80,6 +80,12 @@ def test_levels_and_minmax_bitexact(rp, ctx, c0, small5, storage):
                 mm = cpu(rp.export_minmax(ctx, vid, lod, f))
                 mn, mx = pp.brick_minmax(levels[lod][f])
                 assert np.array_equal(mm[..., 0], mn) and np.array_equal(mm[..., 1], mx), (lod, f)
+                sub = cpu(rp.export_minmax_sub(ctx, vid, lod, f))     # [bz, by, bx, sx + 2 sy + 4 sz, 2]
+                smn, smx = pp.brick_minmax(levels[lod][f], pp.SUB)   # [sz, sy, sx] over the 2 nb grid
+                for i in range(8):
+                    sx, sy, sz = i & 1, (i >> 1) & 1, i >> 2
+                    assert np.array_equal(sub[..., i, 0], smn[sz::2, sy::2, sx::2]), (lod, f, i)
+                    assert np.array_equal(sub[..., i, 1], smx[sz::2, sy::2, sx::2]), (lod, f, i)
         rp.unload(ctx, vid)
 
 
@@ -107,6 +113,9 @@ def test_skiplist_and_mask_bitexact(rp, ctx, small5, storage):
                 want = pp.pack_bits(pp.skip_bits(mins, maxs, act, lo, hi, wl.tf.field, wl.tf.vmin, wl.tf.vmax, t))
                 got = cpu(rp.export_skiplist(ctx, vid, lod, slot)).view(np.uint32)
                 assert np.array_equal(got, want), (bi, lod, slot)
+                want_sub = pp.sub_skip(levels[lod], act, lo, hi, wl.tf.field, wl.tf.vmin, wl.tf.vmax, t)
+                got_sub = cpu(rp.export_subskip(ctx, vid, lod, slot))
+                assert np.array_equal(got_sub, want_sub), (bi, lod, slot)
             m = cpu(rp.export_voxel_mask(ctx, vid, lod))
             assert np.array_equal(m, pp.voxel_mask(levels[lod], act, lo, hi)), (bi, lod)
     rp.unload(ctx, vid)
@@ -236,6 +245,7 @@ def test_inclusive_brush_equals_none_and_empty_is_background(rp, ctx, small5):
     assert np.all(empty[0] == 0.0) and np.all(empty[2] == 0)
     skip = cpu(rp.export_skiplist(ctx, vid, 0, 0)).view(np.uint32)
     assert np.all(skip == 0xFFFFFFFF)
+    assert np.all(cpu(rp.export_subskip(ctx, vid, 0, 0)) == 0xFF)
     rp.set_options(ctx, 0.99, [0.1, 0.2, 0.3, 1.0])
     bg = gpu_render(rp, ctx, vid, wl, 0)[0]
     assert np.all(bg == np.array([0.1, 0.2, 0.3, 1.0], np.float32))

@@ -120,7 +120,7 @@ def test_budget_queues_requests_fifo(rp, setup):
     reqs = random_requests(rng, vols, 8)
     for q in reqs:
         q["w"], q["h"] = 96, 96
-    per_req = 96 * 96 * 16 + 4 * ((8 * 8 * 8 + 31) // 32)
+    per_req = 96 * 96 * 16 + 8 * 8 * 8    # image + one byte of sub-brick skip flags per brick
     rp.server_start(ctx, per_req + 100, 8, 16, 2)       # room for exactly one request at a time
     try:
         tickets, outs = submit_all(rp, ctx, reqs)
