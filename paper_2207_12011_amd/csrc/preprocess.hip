@@ -220,12 +220,26 @@ __device__ __forceinline__ bool tf_range_empty(const SkipArgs& a, float2 tm) {
     return a.next_nonzero[i0] > i1;
 }
 
+// Sub-brick flags (bit i) of the eight (min, max) pairs at p (one brick's 64-byte block) against one
+// field's [lo, hi], read as four 16-byte loads.
+__device__ __forceinline__ uint32_t sub_range_misses(const float2* p, float lo, float hi) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float4 v = q[k];
+        m |= static_cast<uint32_t>((v.y < lo) | (v.x > hi)) << (2 * k);
+        m |= static_cast<uint32_t>((v.w < lo) | (v.z > hi)) << (2 * k + 1);
+    }
+    return m;
+}
+
 // One thread per brick: the brick's skip bit (a wave ballot packs 64 into two words) and its byte
-// of sub-brick flags.
+// of sub-brick flags.  A skipped brick's sub-bricks are all skipped (their windows lie inside its
+// window and the table index map is monotone), so only the other bricks read sub-brick tables.
 __global__ __launch_bounds__(256) void skip_kernel(SkipArgs a) {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     bool skip = false;
-    uint32_t sub = 0;
     if (b < a.n_bricks) {
         for (int f = 0; f < a.n_active; ++f) {
             const float2 mm = a.minmax[f][b];
@@ -233,15 +247,18 @@ __global__ __launch_bounds__(256) void skip_kernel(SkipArgs a) {
         }
         skip |= tf_range_empty(a, a.tf_minmax[b]);
         if (a.out_sub != nullptr) {
-            for (int i = 0; i < 8; ++i) {
-                const size_t o = static_cast<size_t>(b) * 8 + i;
-                bool s = false;
-                for (int f = 0; f < a.n_active; ++f) {
-                    const float2 mm = a.minmax_sub[f][o];
-                    s |= (mm.y < a.lo[f]) | (mm.x > a.hi[f]) | (a.lo[f] > a.hi[f]);
+            uint32_t sub = 0xFFu;
+            if (!skip) {
+                sub = 0;
+                for (int f = 0; f < a.n_active; ++f)
+                    sub |= sub_range_misses(a.minmax_sub[f] + static_cast<size_t>(b) * 8, a.lo[f], a.hi[f]);
+                const float4* q = reinterpret_cast<const float4*>(a.tf_minmax_sub + static_cast<size_t>(b) * 8);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4 v = q[k];
+                    sub |= static_cast<uint32_t>(tf_range_empty(a, make_float2(v.x, v.y))) << (2 * k);
+                    sub |= static_cast<uint32_t>(tf_range_empty(a, make_float2(v.z, v.w))) << (2 * k + 1);
                 }
-                s |= tf_range_empty(a, a.tf_minmax_sub[o]);
-                sub |= static_cast<uint32_t>(s) << i;
             }
             a.out_sub[b] = static_cast<uint8_t>(sub);
         }
