@@ -54,9 +54,11 @@ enum {
     RAYPC_STORAGE_F16 = 1,      /* IEEE binary16, round to nearest even, subnormals kept */
     RAYPC_STORAGE_U8_BRICK = 2, /* 8-bit codes with a (scale, offset) pair per 8^3 brick */
     /* Flag OR-ed into RAYPC_STORAGE_F32 / _F16: keep only the compact layout.  Without it the
-     * library also keeps, per voxel, a record of the 8 stored values of its 2x2x2 neighbourhood
-     * (8x the field memory), so that one wide load serves the whole trilinear fetch of a sample;
-     * both layouts hold the same values and render identically. */
+     * library also keeps, per voxel, an 8-byte record of neighbouring stored values (binary16:
+     * the 2x2 values at (x..x+1, y..y+1, z); float32: the pair at (x..x+1, y, z)), so that a
+     * sample's trilinear fetch takes 2 (binary16) or 4 (float32) loads instead of 8.  This costs
+     * 4x (binary16) or 2x (float32) the field memory; both layouts hold the same values and
+     * render identically. */
     RAYPC_STORAGE_COMPACT = 0x100
 };
 

@@ -411,7 +411,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 if (!rc && storage == kU8) rc = dev_alloc(v, reinterpret_cast<void**>(&L.par[f]), L.n_bricks() * sizeof(float2));
                 if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm[f]), L.n_bricks() * sizeof(float2));
                 if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm_sub[f]), L.n_bricks() * 8 * sizeof(float2));
-                if (!rc && v->records) rc = dev_alloc(v, &L.rec[f], lvox * 8 * storage_bytes(storage));
+                if (!rc && v->records) rc = dev_alloc(v, &L.rec[f], lvox * 8);
             }
             if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip), L.n_words() * sizeof(uint32_t));
             if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip_sub), L.n_bricks());
@@ -441,7 +441,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 }
                 if ((e = launch_encode(cur, L.n, storage, L.data[f], L.par[f], s)) != hipSuccess) { rc = hip_fail(e, "encode"); break; }
                 if ((e = launch_minmax(L.data[f], L.par[f], L.n, storage, L.mm[f], L.mm_sub[f], s)) != hipSuccess) { rc = hip_fail(e, "min/max"); break; }
-                if (v->records && (e = launch_records(L.data[f], L.n, storage, L.rec[f], s)) != hipSuccess) { rc = hip_fail(e, "corner records"); break; }
+                if (v->records && (e = launch_records(L.data[f], L.n, storage, L.rec[f], s)) != hipSuccess) { rc = hip_fail(e, "neighbourhood records"); break; }
             }
         }
         if (rc) break;

@@ -19,7 +19,7 @@ struct Level {
     float2* par[kMaxFields] = {};
     float2* mm[kMaxFields] = {};
     float2* mm_sub[kMaxFields] = {};  // per brick, its eight 4^3 sub-bricks' (min, max)
-    void* rec[kMaxFields] = {};  // corner records (null when the volume keeps only the compact layout)
+    void* rec[kMaxFields] = {};  // neighbourhood records (null when the volume keeps only the compact layout)
     uint32_t* skip = nullptr;    // brick skip bits
     uint8_t* skip_sub = nullptr; // sub-brick skip flags, one byte per brick
     bool skip_valid = false;
@@ -31,7 +31,7 @@ struct Level {
 
 struct Volume {
     int id = 0, n = 0, nf = 0, n_lods = 0, storage = 0;
-    bool records = false;  // corner records kept (binary16 / float32 without RAYPC_STORAGE_COMPACT)
+    bool records = false;  // neighbourhood records kept (binary16 / float32 without RAYPC_STORAGE_COMPACT)
     float r_in = 0.55f, r_out = 1.0f;
     Level lv[RAYPC_MAX_LODS];
     uint8_t active[kMaxFields] = {};

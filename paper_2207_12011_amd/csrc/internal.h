@@ -15,7 +15,7 @@ constexpr int kBrickVoxels = 512;   // 8^3
 constexpr int kBlockPix = 8;        // a 256-thread ray-march block covers 8 x 8 pixels
 
 enum Storage : int { kF32 = 0, kF16 = 1, kU8 = 2 };
-// Kernel variants: a storage type, read from the compact layout or from corner records.
+// Kernel variants: a storage type, read from the compact layout or from neighbourhood records.
 enum Kind : int { kKindF32 = 0, kKindF16 = 1, kKindU8 = 2, kKindF32Rec = 3, kKindF16Rec = 4, kKinds = 5 };
 
 // Brick-ordered address of voxel (x, y, z) on a level with nb bricks per axis:
@@ -56,9 +56,9 @@ hipError_t launch_encode(const float* in, int n, int storage, void* out, float2*
 // apron window: out_sub[8 brick + sx + 2 sy + 4 sz].
 hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, float2* out_sub,
                          hipStream_t s);
-// Corner records: for every voxel (x, y, z), the 8 stored values at (x+dx, y+dy, z+dz), dx, dy, dz in
-// {0, 1}, clamped to N-1, in the order bit 0 = dx, bit 1 = dy, bit 2 = dz; record i sits at
-// brick_addr(x, y, z) x 8 values (binary16: 16 bytes, float32: 32 bytes).
+// Neighbourhood records, 8 bytes per voxel (x, y, z) at brick_addr(x, y, z) x 8 bytes, coordinates
+// clamped to N-1: binary16 keeps the 2x2 values at (x+dx, y+dy, z) in the order dx + 2 dy; float32
+// keeps the pair at (x+dx, y, z).  A trilinear fetch reads 2 (binary16) or 4 (float32) records.
 hipError_t launch_records(const void* data, int n, int storage, void* out, hipStream_t s);
 // Decode stored values back to linear [z][y][x] float32.
 hipError_t launch_decode(const void* data, const float2* u8par, int n, int storage, float* out, hipStream_t s);
@@ -94,7 +94,7 @@ struct RenderArgs {
     // slot tf_slot (< n_brushed when it is brushed itself, else == n_brushed)
     const void* field[kMaxFields];
     const float2* u8par[kMaxFields];
-    const void* rec[kMaxFields];  // corner records, in the same slot order (record kinds only)
+    const void* rec[kMaxFields];  // neighbourhood records, in the same slot order (record kinds only)
     float lo[kMaxFields], hi[kMaxFields];
     int n_brushed, tf_slot;
     int n, nb;

@@ -175,24 +175,24 @@ __global__ void decode_kernel(const void* __restrict__ data, const float2* __res
     out[o] = stored<S>(data, par, brick_addr(x, y, z, n >> 3));
 }
 
-// One thread per voxel: gather the 8 stored values of its 2x2x2 neighbourhood (bit patterns copied).
+// One thread per voxel: gather its 8-byte neighbourhood record (bit patterns copied): binary16 the
+// 2x2 values at (x..x+1, y..y+1, z), float32 the pair at (x..x+1, y, z), clamped to N-1.
 template <typename T>
 __global__ void records_kernel(const T* __restrict__ data, int n, T* __restrict__ out) {
+    constexpr int kValues = 8 / sizeof(T);
     const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t total = static_cast<uint32_t>(n) * n * n;
     if (o >= total) return;
     const int nb = n >> 3;
     const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
-    const int x1 = min(x + 1, n - 1), y1 = min(y + 1, n - 1), z1 = min(z + 1, n - 1);
-    T* r = out + static_cast<size_t>(brick_addr(x, y, z, nb)) * 8;
+    const int x1 = min(x + 1, n - 1), y1 = min(y + 1, n - 1);
+    T* r = out + static_cast<size_t>(brick_addr(x, y, z, nb)) * kValues;
     r[0] = data[brick_addr(x, y, z, nb)];
     r[1] = data[brick_addr(x1, y, z, nb)];
-    r[2] = data[brick_addr(x, y1, z, nb)];
-    r[3] = data[brick_addr(x1, y1, z, nb)];
-    r[4] = data[brick_addr(x, y, z1, nb)];
-    r[5] = data[brick_addr(x1, y, z1, nb)];
-    r[6] = data[brick_addr(x, y1, z1, nb)];
-    r[7] = data[brick_addr(x1, y1, z1, nb)];
+    if constexpr (kValues == 4) {
+        r[2] = data[brick_addr(x, y1, z, nb)];
+        r[3] = data[brick_addr(x1, y1, z, nb)];
+    }
 }
 
 template <int S>

@@ -152,20 +152,28 @@ __device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)
                  corner<S>(src, o[4]), corner<S>(src, o[5]), corner<S>(src, o[6]), corner<S>(src, o[7]));
 }
 
-// Trilinear value from a corner record (the 8 stored values of one voxel's 2x2x2 neighbourhood):
-// one 16- or 32-byte load per field instead of eight scattered ones.  The arithmetic is that of
-// fetch(), so both layouts give identical values.
+// Trilinear value from neighbourhood records (8 bytes per voxel): binary16 reads the 2x2 (x, y) records
+// of the base voxel's row at z0 and z1, float32 the x pairs at (y0, z0), (y1, z0), (y0, z1), (y1, z1).
+// ax is the x part of the base voxel's address, ay0 / ay1 / az0 / az1 the y and z parts (see axis_x/y/z).
+// The arithmetic is that of fetch(), so both layouts give identical values.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <int S>
-__device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32_t voxel, const Tri& t) {
+__device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32_t ax, uint32_t ay0, uint32_t ay1,
+                                           uint32_t az0, uint32_t az1, const Tri& t) {
+    const char* b = static_cast<const char*>(base);
     if constexpr (S == kF16) {
-        const u32x4 r = global_ptr<u32x4>(static_cast<const char*>(base) + static_cast<size_t>(voxel) * 16u)[0];
+        const u32x2 p = global_ptr<u32x2>(b + static_cast<size_t>(ax + ay0 + az0) * 8u)[0];
+        const u32x2 q = global_ptr<u32x2>(b + static_cast<size_t>(ax + ay0 + az1) * 8u)[0];
         auto lo = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u & 0xFFFFu))); };
         auto hi = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u >> 16))); };
-        return blend(t, lo(r.x), hi(r.x), lo(r.y), hi(r.y), lo(r.z), hi(r.z), lo(r.w), hi(r.w));
+        return blend(t, lo(p.x), hi(p.x), lo(p.y), hi(p.y), lo(q.x), hi(q.x), lo(q.y), hi(q.y));
     } else {
-        const auto* p = global_ptr<f32x4>(static_cast<const char*>(base) + static_cast<size_t>(voxel) * 32u);
-        const f32x4 a = p[0], b = p[1];
-        return blend(t, a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
+        const f32x2 p0 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay0 + az0) * 8u)[0];
+        const f32x2 p1 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay1 + az0) * 8u)[0];
+        const f32x2 p2 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay0 + az1) * 8u)[0];
+        const f32x2 p3 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay1 + az1) * 8u)[0];
+        return blend(t, p0.x, p0.y, p1.x, p1.y, p2.x, p2.y, p3.x, p3.y);
     }
 }
 
@@ -379,9 +387,11 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                 const float wz = iz < 0 ? 0.0f : uz - flz;
                 const Tri tw = tri_weights(wx, wy, wz);
                 uint32_t o[8];
-                uint32_t voxel = 0;
+                uint32_t ax = 0, ay0 = 0, ay1 = 0, az0 = 0, az1 = 0;
                 if constexpr (R) {
-                    voxel = axis_x(x0) + axis_y(y0, nb) + axis_z(z0, nb);
+                    ax = axis_x(x0);
+                    ay0 = axis_y(y0, nb), ay1 = axis_y(y1, nb);
+                    az0 = axis_z(z0, nb), az1 = axis_z(z1, nb);
                 } else {
                     constexpr int L = kLogBytes<S>;
                     const uint32_t X0 = axis_x(x0) << L, X1 = axis_x(x1) << L;
@@ -392,7 +402,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                     o[4] = zy10 + X0, o[5] = zy10 + X1, o[6] = zy11 + X0, o[7] = zy11 + X1;
                 }
                 auto field_value = [&](int k) -> float {
-                    if constexpr (R) return fetch_rec<S>(A.rec[k], voxel, tw);
+                    if constexpr (R) return fetch_rec<S>(A.rec[k], ax, ay0, ay1, az0, az1, tw);
                     else return fetch<S>(source<S>(A, k), o, tw);
                 };
                 bool pass = true;

@@ -213,7 +213,7 @@ def test_corner_records_equal_compact_layout(rp, ctx, small5, c0, base):
     for wl in (small5, c0):
         rec = load(rp, ctx, wl, base)
         cmp_ = load(rp, ctx, wl, base + "c")
-        assert rp.volume_info(ctx, rec)["bytes"] > 4 * rp.volume_info(ctx, cmp_)["bytes"]
+        assert rp.volume_info(ctx, rec)["bytes"] > 2 * rp.volume_info(ctx, cmp_)["bytes"]
         views = [(wl.camera.as_array(), 0, 0.5), (wl.camera.as_array(), 1, 0.37),
                  (np.array([0.8, 0.1, 0.1, 0, 0, 0, 0, 0, 1, 90], np.float32), 0, 1.0),
                  (np.array([3, 0, 0, 0, 0.55, 0, 0, 0, 1, 20], np.float32), 2, 0.5)]
