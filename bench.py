@@ -157,7 +157,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storages", default="f16,f32,u8", help="first one is the headline value")
+    ap.add_argument("--storages", default="f16,f32,u8,u8c",
+                    help="first one is the headline value; a trailing c keeps only the compact layout")
     ap.add_argument("--cpu-stride", type=int, default=2, help="oracle sample: every k-th row and column")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=512)
@@ -203,7 +204,7 @@ def main():
     out = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
     results = {}
     storages = args.storages.split(",")
-    bpv = {"f32": 4, "f16": 2, "u8": 1}
+    bpv = {"f32": 4, "f16": 2, "u8": 1, "f32c": 4, "f16c": 2, "u8c": 1}
 
     for si, storage in enumerate(storages):
         vid = raypc.load_fields(ctx, fields_dev, storage, 3, wl.r_inner, wl.r_outer)
@@ -259,7 +260,7 @@ def main():
         kms = float(np.mean([a.elapsed_time(e) for a, e in kev]))
 
         alg_bytes = touched_bricks[0] * 512 * n_needed * bpv[storage] + W_ * H_ * IMAGE_BYTES_PER_PIXEL
-        if storage == "u8":
+        if storage.startswith("u8"):
             alg_bytes += touched_bricks[0] * 8 * n_needed
         alg_ops = samples[0] * (50 + 22 * n_needed)
         results[storage] = {

@@ -53,12 +53,12 @@ enum {
     RAYPC_STORAGE_F32 = 0,      /* 4 bytes per value */
     RAYPC_STORAGE_F16 = 1,      /* IEEE binary16, round to nearest even, subnormals kept */
     RAYPC_STORAGE_U8_BRICK = 2, /* 8-bit codes with a (scale, offset) pair per 8^3 brick */
-    /* Flag OR-ed into RAYPC_STORAGE_F32 / _F16: keep only the compact layout.  Without it the
-     * library also keeps, per voxel, an 8-byte record of neighbouring stored values (binary16:
-     * the 2x2 values at (x..x+1, y..y+1, z); float32: the pair at (x..x+1, y, z)), so that a
-     * sample's trilinear fetch takes 2 (binary16) or 4 (float32) loads instead of 8.  This costs
-     * 4x (binary16) or 2x (float32) the field memory; both layouts hold the same values and
-     * render identically. */
+    /* Flag OR-ed into a storage type: keep only the compact layout.  Without it the library also
+     * keeps, per voxel, an 8-byte record of neighbouring stored values (binary16: the 2x2 values
+     * at (x..x+1, y..y+1, z); float32 and 8-bit: the pair of float32 (decoded) values at
+     * (x..x+1, y, z)), so that a sample's trilinear fetch takes 2 (binary16) or 4 loads instead
+     * of 8 (plus 8 (scale, offset) loads for 8-bit codes).  Records cost 8 bytes per voxel and
+     * field besides the compact data; both layouts hold the same values and render identically. */
     RAYPC_STORAGE_COMPACT = 0x100
 };
 
@@ -105,7 +105,7 @@ int raypc_version(void);
  *   on_device  0: fields[] are host pointers (copied);  1: device pointers
  *              (read only, e.g. torch tensors).
  *   storage    RAYPC_STORAGE_*: how every level is kept in device memory
- *              (optionally | RAYPC_STORAGE_COMPACT for F32 / F16).
+ *              (optionally | RAYPC_STORAGE_COMPACT).
  *   n_lods     1..3 levels: level l+1 is the 2x2x2 mean of level l (float32,
  *              fixed summation order), built from float32 data and only then
  *              encoded (Section 2.1: two coarser levels with 1/8 the cells).

@@ -305,7 +305,8 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
         if (rc) return rc;
         a.skip = v->lv[lod].skip_sub;
     }
-    storage = v->records ? (v->storage == kF32 ? kKindF32Rec : kKindF16Rec) : v->storage;  // kernel kind
+    // kernel kind
+    storage = !v->records ? v->storage : (v->storage == kF32 ? kKindF32Rec : v->storage == kF16 ? kKindF16Rec : kKindU8Rec);
     level = lod;
     if (vol_out) *vol_out = v;
     return RAYPC_OK;
@@ -362,8 +363,6 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
     storage &= ~RAYPC_STORAGE_COMPACT;
     if (storage < RAYPC_STORAGE_F32 || storage > RAYPC_STORAGE_U8_BRICK)
         return fail(RAYPC_ERR_INVALID, "storage %d unknown", storage_arg);
-    if (compact && storage == RAYPC_STORAGE_U8_BRICK)
-        return fail(RAYPC_ERR_INVALID, "RAYPC_STORAGE_COMPACT applies to F32 and F16 only (U8 is always compact)");
     if (n_lods < 1 || n_lods > RAYPC_MAX_LODS) return fail(RAYPC_ERR_INVALID, "n_lods %d outside [1, 3]", n_lods);
     if (!(r_inner >= 0.0f && r_inner < r_outer && r_outer <= 1.0f))
         return fail(RAYPC_ERR_INVALID, "radii must satisfy 0 <= r_inner < r_outer <= 1");
@@ -378,7 +377,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
     v->nf = n_fields;
     v->n_lods = n_lods;
     v->storage = storage;
-    v->records = !compact && storage != kU8;
+    v->records = !compact;
     v->r_in = r_inner;
     v->r_out = r_outer;
     for (int f = 0; f < n_fields; ++f) {
@@ -441,7 +440,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 }
                 if ((e = launch_encode(cur, L.n, storage, L.data[f], L.par[f], s)) != hipSuccess) { rc = hip_fail(e, "encode"); break; }
                 if ((e = launch_minmax(L.data[f], L.par[f], L.n, storage, L.mm[f], L.mm_sub[f], s)) != hipSuccess) { rc = hip_fail(e, "min/max"); break; }
-                if (v->records && (e = launch_records(L.data[f], L.n, storage, L.rec[f], s)) != hipSuccess) { rc = hip_fail(e, "neighbourhood records"); break; }
+                if (v->records && (e = launch_records(L.data[f], L.par[f], L.n, storage, L.rec[f], s)) != hipSuccess) { rc = hip_fail(e, "neighbourhood records"); break; }
             }
         }
         if (rc) break;
@@ -485,7 +484,7 @@ int raypc_volume_info(const raypc_ctx* ctx, int volume_id, int* n_fields, int* n
     if (n_fields) *n_fields = v->nf;
     if (n) *n = v->n;
     if (n_lods) *n_lods = v->n_lods;
-    if (storage) *storage = v->storage | (v->records || v->storage == kU8 ? 0 : RAYPC_STORAGE_COMPACT);
+    if (storage) *storage = v->storage | (v->records ? 0 : RAYPC_STORAGE_COMPACT);
     if (bytes) *bytes = v->bytes;
     return RAYPC_OK;
 }

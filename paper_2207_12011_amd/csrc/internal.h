@@ -16,7 +16,9 @@ constexpr int kBlockPix = 8;        // a 256-thread ray-march block covers 8 x 8
 
 enum Storage : int { kF32 = 0, kF16 = 1, kU8 = 2 };
 // Kernel variants: a storage type, read from the compact layout or from neighbourhood records.
-enum Kind : int { kKindF32 = 0, kKindF16 = 1, kKindU8 = 2, kKindF32Rec = 3, kKindF16Rec = 4, kKinds = 5 };
+enum Kind : int {
+    kKindF32 = 0, kKindF16 = 1, kKindU8 = 2, kKindF32Rec = 3, kKindF16Rec = 4, kKindU8Rec = 5, kKinds = 6
+};
 
 // Brick-ordered address of voxel (x, y, z) on a level with nb bricks per axis:
 // bricks in [bz][by][bx] order, 512 voxels each.  Inside a brick the voxels
@@ -58,8 +60,9 @@ hipError_t launch_minmax(const void* data, const float2* u8par, int n, int stora
                          hipStream_t s);
 // Neighbourhood records, 8 bytes per voxel (x, y, z) at brick_addr(x, y, z) x 8 bytes, coordinates
 // clamped to N-1: binary16 keeps the 2x2 values at (x+dx, y+dy, z) in the order dx + 2 dy; float32
-// keeps the pair at (x+dx, y, z).  A trilinear fetch reads 2 (binary16) or 4 (float32) records.
-hipError_t launch_records(const void* data, int n, int storage, void* out, hipStream_t s);
+// keeps the pair at (x+dx, y, z), and 8-bit storage the pair of its decoded float32 values.  A
+// trilinear fetch reads 2 (binary16) or 4 (float32, 8-bit) records.
+hipError_t launch_records(const void* data, const float2* u8par, int n, int storage, void* out, hipStream_t s);
 // Decode stored values back to linear [z][y][x] float32.
 hipError_t launch_decode(const void* data, const float2* u8par, int n, int storage, float* out, hipStream_t s);
 

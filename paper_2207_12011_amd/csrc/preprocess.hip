@@ -195,6 +195,21 @@ __global__ void records_kernel(const T* __restrict__ data, int n, T* __restrict_
     }
 }
 
+// 8-bit storage: the pair of decoded float32 values at (x..x+1, y, z) (exact, as the compact path
+// decodes them).
+__global__ void records_u8_kernel(const void* __restrict__ data, const float2* __restrict__ par, int n,
+                                  float* __restrict__ out) {
+    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t total = static_cast<uint32_t>(n) * n * n;
+    if (o >= total) return;
+    const int nb = n >> 3;
+    const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
+    const int x1 = min(x + 1, n - 1);
+    float* r = out + static_cast<size_t>(brick_addr(x, y, z, nb)) * 2;
+    r[0] = stored<kU8>(data, par, brick_addr(x, y, z, nb));
+    r[1] = stored<kU8>(data, par, brick_addr(x1, y, z, nb));
+}
+
 template <int S>
 __global__ void voxel_mask_kernel(MaskArgs a) {
     const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
@@ -328,15 +343,17 @@ hipError_t launch_decode(const void* data, const float2* u8par, int n, int stora
     return hipGetLastError();
 }
 
-hipError_t launch_records(const void* data, int n, int storage, void* out, hipStream_t s) {
+hipError_t launch_records(const void* data, const float2* u8par, int n, int storage, void* out, hipStream_t s) {
     const size_t total = static_cast<size_t>(n) * n * n;
     const dim3 g(blocks_for(total, 256));
     if (storage == kF32)
         hipLaunchKernelGGL(records_kernel<uint32_t>, g, dim3(256), 0, s, static_cast<const uint32_t*>(data), n,
                            static_cast<uint32_t*>(out));
-    else
+    else if (storage == kF16)
         hipLaunchKernelGGL(records_kernel<uint16_t>, g, dim3(256), 0, s, static_cast<const uint16_t*>(data), n,
                            static_cast<uint16_t*>(out));
+    else
+        hipLaunchKernelGGL(records_u8_kernel, g, dim3(256), 0, s, data, u8par, n, static_cast<float*>(out));
     return hipGetLastError();
 }
 

@@ -112,9 +112,8 @@ __device__ __forceinline__ float corner(const Source<S>& src, uint32_t ob) {
     } else {
         const float q = static_cast<float>(__builtin_amdgcn_raw_buffer_load_b8(src.rsrc, static_cast<int>(ob), 0, 0));
         const uint32_t pb = (ob >> 9) * 8u;
-        const float scale = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(src.par, static_cast<int>(pb), 0, 0));
-        const float offset = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(src.par, static_cast<int>(pb + 4), 0, 0));
-        return __fadd_rn(__fmul_rn(scale, q), offset);
+        const auto so = __builtin_amdgcn_raw_buffer_load_b64(src.par, static_cast<int>(pb), 0, 0);  // (scale, offset)
+        return __fadd_rn(__fmul_rn(__uint_as_float(so[0]), q), __uint_as_float(so[1]));
     }
 }
 
@@ -178,8 +177,12 @@ __device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32
 }
 
 // Kernel kinds: storage type and layout.
-constexpr int storage_of(int K) { return K == kKindF32Rec ? kF32 : (K == kKindF16Rec ? kF16 : K); }
-constexpr bool records_of(int K) { return K == kKindF32Rec || K == kKindF16Rec; }
+constexpr int storage_of(int K) {
+    return K == kKindF32Rec ? kF32 : (K == kKindF16Rec ? kF16 : (K == kKindU8Rec ? kU8 : K));
+}
+constexpr bool records_of(int K) { return K >= kKindF32Rec; }
+// Value type held by a kind's records: binary16 quads, or float32 pairs (also for decoded 8-bit codes).
+constexpr int record_type_of(int K) { return K == kKindF16Rec ? kF16 : kF32; }
 
 // Ray parameter where u(t) = uo + du t leaves [lo, hi] along one axis (forward only); inv_du = 1/du.
 // Rounding of the reciprocal is covered by the shrink margin of skipped bricks.
@@ -266,6 +269,7 @@ template <int K, int NB, bool COUNTS>
 __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, const float4* s_tf) {
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
+    constexpr int RT = record_type_of(K);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ray = lane >> 2, sub = lane & 3, quad_base = lane & ~3;
     const int px = bx * kBlockTile + (wave & 1) * kWaveTile + (ray & 3);
@@ -402,7 +406,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                     o[4] = zy10 + X0, o[5] = zy10 + X1, o[6] = zy11 + X0, o[7] = zy11 + X1;
                 }
                 auto field_value = [&](int k) -> float {
-                    if constexpr (R) return fetch_rec<S>(A.rec[k], ax, ay0, ay1, az0, az1, tw);
+                    if constexpr (R) return fetch_rec<RT>(A.rec[k], ax, ay0, ay1, az0, az1, tw);
                     else return fetch<S>(source<S>(A, k), o, tw);
                 };
                 bool pass = true;
@@ -611,7 +615,8 @@ hipError_t launch_kind(const RenderArgs& a, int kind, hipStream_t s) {
         case kKindF16: return launch_nb<kKindF16, COUNTS>(a, s);
         case kKindU8: return launch_nb<kKindU8, COUNTS>(a, s);
         case kKindF32Rec: return launch_nb<kKindF32Rec, COUNTS>(a, s);
-        default: return launch_nb<kKindF16Rec, COUNTS>(a, s);
+        case kKindF16Rec: return launch_nb<kKindF16Rec, COUNTS>(a, s);
+        default: return launch_nb<kKindU8Rec, COUNTS>(a, s);
     }
 }
 
@@ -626,7 +631,8 @@ hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& R, in
         case kKindF16: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16>, grid, block, 0, s, descs, R); break;
         case kKindU8: hipLaunchKernelGGL(raymarch_batch_kernel<kKindU8>, grid, block, 0, s, descs, R); break;
         case kKindF32Rec: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF32Rec>, grid, block, 0, s, descs, R); break;
-        default: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16Rec>, grid, block, 0, s, descs, R); break;
+        case kKindF16Rec: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16Rec>, grid, block, 0, s, descs, R); break;
+        default: hipLaunchKernelGGL(raymarch_batch_kernel<kKindU8Rec>, grid, block, 0, s, descs, R); break;
     }
     return hipGetLastError();
 }

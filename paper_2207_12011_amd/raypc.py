@@ -21,8 +21,10 @@ LIB_PATH = os.path.join(_HERE, "libraypc.so")
 
 OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_BUSY, ERR_TIMEOUT, ERR_CANCELLED, ERR_STATE = range(8)
 STORAGE_COMPACT = 0x100
-# "f32" / "f16" keep 8-byte neighbourhood records besides the compact layout; "f32c" / "f16c" keep only the compact layout
-STORAGE = {"f32": 0, "f16": 1, "u8": 2, "f32c": 0 | STORAGE_COMPACT, "f16c": 1 | STORAGE_COMPACT}
+# "f32" / "f16" / "u8" keep 8-byte neighbourhood records besides the compact layout; the "c" forms keep only
+# the compact layout
+STORAGE = {"f32": 0, "f16": 1, "u8": 2, "f32c": 0 | STORAGE_COMPACT, "f16c": 1 | STORAGE_COMPACT,
+           "u8c": 2 | STORAGE_COMPACT}
 MAX_FIELDS = 8
 TF_ENTRIES = 256
 

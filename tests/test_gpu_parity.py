@@ -207,9 +207,10 @@ def test_skip_on_off_bitexact(rp, ctx, small5):
         rp.unload(ctx, vid)
 
 
-@pytest.mark.parametrize("base", ["f16", "f32"])
-def test_corner_records_equal_compact_layout(rp, ctx, small5, c0, base):
-    """Both layouts hold the same stored values; every render is bit-identical."""
+@pytest.mark.parametrize("base", ["f16", "f32", "u8"])
+def test_records_equal_compact_layout(rp, ctx, small5, c0, base):
+    """Both layouts hold the same stored values (8-bit records hold the decoded values); every render
+    is bit-identical."""
     for wl in (small5, c0):
         rec = load(rp, ctx, wl, base)
         cmp_ = load(rp, ctx, wl, base + "c")
