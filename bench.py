@@ -54,6 +54,10 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
+def ordinal(k: int) -> str:
+    return f"{k}{'th' if 10 <= k % 100 <= 20 else {1: 'st', 2: 'nd', 3: 'rd'}.get(k % 10, 'th')}"
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
@@ -316,7 +320,7 @@ def main():
         dt = time.perf_counter() - t0
         ns = int(ref.nominal.astype(np.int64).sum())
         cpu_baseline = {"value": ns / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
-                        "sample": f"every {args.cpu_stride}th row and column of the {W_}x{H_} frame "
+                        "sample": f"every {ordinal(args.cpu_stride)} row and column of the {W_}x{H_} frame "
                                   f"({pix.size} px, {ns} nominal samples, {dt:.1f} s), brush 0, "
                                   f"{head}-stored {wl.n}^3 x {wl.n_fields} level 0, FP64"}
 
