@@ -82,6 +82,49 @@ def profile(args, wl, raypc, torch):
     print(f"[bench] profile mode: {args.profile_frames} frames ({storage}) + 1 GiB copy", file=sys.stderr)
 
 
+def brush_axis_sweep(raypc, torch, ctx, vid, wl, lod, stream, frames=30):
+    """Frame time against the number k of brushed variables (the paper notes the brush cost grows
+    linearly with the restricted variables), k = 0..F on the headline view: (a) k fields with
+    all-inclusive bounds, which adds the fetch and test of k fields to every evaluated sample and
+    discards nothing; (b) the first k axes of the headline brush.  Least-squares line and R^2 each."""
+    nf = wl.n_fields
+    out = torch.empty((wl.height, wl.width, 4), dtype=torch.float32, device="cuda")
+    cam = wl.camera.as_array()
+
+    def frame_ms():
+        raypc.render(ctx, vid, cam, wl.width, wl.height, lod, wl.step, out=out, stream=stream)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
+        for a, e in ev:
+            a.record(stream)
+            raypc.render(ctx, vid, cam, wl.width, wl.height, lod, wl.step, out=out, stream=stream)
+            e.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(e) for a, e in ev]))
+
+    res = {}
+    for mode in ("inclusive", "brush_prefix"):
+        ks, ms = list(range(nf + 1)), []
+        for k in ks:
+            act = np.zeros(nf, np.uint8)
+            act[:k] = 1
+            if mode == "inclusive":
+                lo, hi = np.full(nf, -np.inf, np.float32), np.full(nf, np.inf, np.float32)
+            else:
+                lo, hi = wl.brush.lo, wl.brush.hi
+            raypc.set_brush(ctx, vid, act, lo, hi)
+            ms.append(frame_ms())
+        slope, icpt = np.polyfit(ks, ms, 1)
+        fit = slope * np.asarray(ks) + icpt
+        ss_res = float(((np.asarray(ms) - fit) ** 2).sum())
+        ss_tot = float(((np.asarray(ms) - np.mean(ms)) ** 2).sum())
+        res[mode] = {"k": ks, "ms": ms, "slope_ms_per_field": float(slope), "intercept_ms": float(icpt),
+                     "r2": 1.0 - ss_res / ss_tot if ss_tot > 0 else 1.0}
+        print(f"[bench] brush-axis sweep ({mode}): {res[mode]}", file=sys.stderr, flush=True)
+    raypc.set_brush(ctx, vid, wl.brush.active, wl.brush.lo, wl.brush.hi)
+    return res
+
+
 def serving(args, raypc, torch, W, wl512, fields512_dev):
     """Serving configuration: 256^3 and 512^3 x 5 FP16 volumes resident; a seeded trace of
     requests (sizes 256^2 .. 2048^2, orbit cameras, 1-5-axis quantile brushes, level by the
@@ -169,6 +212,7 @@ def main():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the brush-axis sweep")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-qps", default="50,100,200,400,inf",
                     help="Poisson arrival rates (requests/s); inf submits the whole trace at once")
@@ -207,6 +251,7 @@ def main():
     stream = torch.cuda.current_stream()
     out = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
     results = {}
+    sweep_result = None
     storages = args.storages.split(",")
     bpv = {"f32": 4, "f16": 2, "u8": 1, "f32c": 4, "f16c": 2, "u8c": 1}
 
@@ -282,6 +327,8 @@ def main():
             "volume_bytes": raypc.volume_info(ctx, vid)["bytes"],
         }
         print(f"[bench] {storage}: {results[storage]}", file=sys.stderr, flush=True)
+        if si == 0 and not args.no_sweep:
+            sweep_result = brush_axis_sweep(raypc, torch, ctx, vid, wl, lod, stream)
         raypc.unload(ctx, vid)
 
     head = storages[0]
@@ -346,6 +393,7 @@ def main():
         "per_storage": results,
         "roofline": roofline,
         "serving": serving_result,
+        "brush_axis_sweep": sweep_result,
         "cpu_baseline": cpu_baseline,
     }
     raypc.destroy(ctx)
