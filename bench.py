@@ -199,6 +199,80 @@ def serving(args, raypc, torch, W, wl512, fields512_dev):
     return result
 
 
+def progressive(args, raypc, torch, W):
+    """Large progressive configuration: a 1024^3 x 5 volume, a 3840x2160 view (the default camera),
+    three passes at step 1.0 / 0.5 / 0.25 voxel after every brush change, for 10 brush requests
+    narrowing linearly in quantile space from all-inclusive to the ~10 % 5-axis brush.  Per request:
+    brush change -> first pass and -> final pass latency (host clock, from the set_brush call to
+    the pass's completion event; the volume stays resident, only the brush crosses to the device).
+    The requests run twice; the second round is reported.  Prints its own JSON line."""
+    t_gen = time.perf_counter()
+    wl = W.make_workload(4, n=args.prog_n, width=args.prog_width, height=args.prog_height,
+                         progress=lambda msg: print(f"[bench] generated {msg} ({time.perf_counter() - t_gen:.0f}s)",
+                                                    file=sys.stderr, flush=True))
+    mask = W.shell_mask(W.radius(wl.n))
+    brushes = W.narrowing_brushes(wl.fields, mask, np.random.default_rng(W.SEED_BASE + 4), wl.brush)
+    del mask
+    print(f"[bench] progressive workload {wl.name} generated in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    ctx = raypc.create(0)
+    raypc.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
+    raypc.set_options(ctx, wl.ert)
+    fields_dev = torch.from_numpy(wl.fields).cuda()
+    stream = torch.cuda.current_stream()
+    cam = wl.camera.as_array()
+    W_, H_ = wl.width, wl.height
+    steps = [wl.step * 4, wl.step * 2, wl.step]
+    outs = [torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda") for _ in steps]
+    results = {}
+    for storage in args.prog_storages.split(","):
+        t_load = time.perf_counter()
+        vid = raypc.load_fields(ctx, fields_dev, storage, 3, wl.r_inner, wl.r_outer)
+        load_s = time.perf_counter() - t_load
+        lod = raypc.select_lod(ctx, vid, cam, W_, H_)
+        # nominal samples per pass for the final brush (counting variant, outside the timed region)
+        raypc.set_brush(ctx, vid, brushes[-1].active, brushes[-1].lo, brushes[-1].hi)
+        pass_samples = []
+        for st in steps:
+            _, nom, _ = raypc.render_debug(ctx, vid, cam, W_, H_, lod, st)
+            torch.cuda.synchronize()
+            pass_samples.append(int(nom.to(torch.int64).sum().item()))
+        first, final, passes = [], [], []
+        for rnd in range(2):
+            first, final, passes = [], [], []
+            for b in brushes:
+                torch.cuda.synchronize()
+                ev0 = torch.cuda.Event(enable_timing=True)
+                evs = [torch.cuda.Event(enable_timing=True) for _ in steps]
+                t0 = time.perf_counter()
+                raypc.set_brush(ctx, vid, b.active, b.lo, b.hi)
+                ev0.record(stream)
+                for st, o, e in zip(steps, outs, evs):
+                    raypc.render(ctx, vid, cam, W_, H_, lod, st, out=o, stream=stream)
+                    e.record(stream)
+                evs[0].synchronize()
+                first.append(1e3 * (time.perf_counter() - t0))
+                evs[-1].synchronize()
+                final.append(1e3 * (time.perf_counter() - t0))
+                passes.append([ev0.elapsed_time(evs[0])] + [evs[i - 1].elapsed_time(evs[i]) for i in range(1, len(evs))])
+        last = passes[-1]
+        results[storage] = {
+            "brush_to_first_pass_ms": first, "brush_to_final_pass_ms": final, "pass_ms": passes,
+            "final_brush_nominal_samples_per_pass": pass_samples,
+            "final_brush_samples_per_s_per_pass": [n / (t * 1e-3) for n, t in zip(pass_samples, last)],
+            "lod": lod, "load_s": load_s, "volume_bytes": raypc.volume_info(ctx, vid)["bytes"]}
+        print(f"[bench] progressive {storage}: first {np.round(first, 2).tolist()} final {np.round(final, 2).tolist()} "
+              f"samples/pass {pass_samples} load {load_s:.1f}s", file=sys.stderr, flush=True)
+        raypc.unload(ctx, vid)
+    raypc.destroy(ctx)
+    line = {"metric": "large progressive: brush change -> first / final pass latency (ms)",
+            "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+            "config": {"workload": wl.name + f", passes at step {steps} voxel, 10 narrowing brushes",
+                       "volume": wl.n, "fields": wl.n_fields, "width": W_, "height": H_},
+            "per_storage": results}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +287,12 @@ def main():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the brush-axis sweep")
+    ap.add_argument("--progressive", action="store_true",
+                    help="run only the large progressive configuration (1024^3 x 5, 3840x2160) and print its JSON line")
+    ap.add_argument("--prog-n", type=int, default=1024)
+    ap.add_argument("--prog-width", type=int, default=3840)
+    ap.add_argument("--prog-height", type=int, default=2160)
+    ap.add_argument("--prog-storages", default="f16,u8,u8c")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-qps", default="50,100,200,400,inf",
                     help="Poisson arrival rates (requests/s); inf submits the whole trace at once")
@@ -231,6 +311,9 @@ def main():
     from paper_2207_12011_amd import raypc
     from paper_2207_12011_amd import workloads as W
 
+    if args.progressive:
+        progressive(args, raypc, torch, W)
+        return
     t_gen = time.perf_counter()
     wl = W.make_workload(2, n=args.n, width=args.width, height=args.height)
     if args.profile_frames > 0:

@@ -274,6 +274,30 @@ def upper_tail_brush(fields: np.ndarray, mask: np.ndarray, rng, target=0.10, tol
     return Brush(np.ones(nf, np.uint8), lo.astype(np.float32), hi)
 
 
+def narrowing_brushes(fields: np.ndarray, mask: np.ndarray, rng, final: Brush, count: int = 10) -> list:
+    """``count`` brushes narrowing linearly in quantile space from all-inclusive to ``final`` (an
+    upper-tail brush): brush k keeps [Q_f(u_f k / (count - 1)), hi_f] on every field, where u_f is
+    the shell quantile of final.lo[f] (on a seeded subsample); brush 0 has lo = -inf, the last one
+    is ``final``."""
+    sample = _subsample_shell(fields, mask, rng)
+    srt = np.sort(sample, axis=1)
+    nf = fields.shape[0]
+    out = []
+    for k in range(count):
+        if k == 0:
+            lo = np.full(nf, -np.inf, np.float32)
+        elif k == count - 1:
+            lo = final.lo.copy()
+        else:
+            lo = np.empty(nf, np.float32)
+            for f in range(nf):
+                u = np.searchsorted(srt[f], final.lo[f]) / (srt.shape[1] - 1)
+                q = int(round(u * k / (count - 1) * (srt.shape[1] - 1)))
+                lo[f] = srt[f, min(q, srt.shape[1] - 1)]
+        out.append(Brush(final.active.copy(), lo, final.hi.copy()))
+    return out
+
+
 def orbit_camera(az: float, el: float, dist: float = 3.0, fov: float = 60.0) -> Camera:
     eye = (dist * math.cos(el) * math.cos(az), dist * math.cos(el) * math.sin(az), dist * math.sin(el))
     return Camera(eye, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), fov)
@@ -292,32 +316,40 @@ def _children(config_id: int):
     return {name: np.random.default_rng(k) for name, k in zip(CHILDREN, kids)}
 
 
-def make_fields_5(n: int, rngs) -> np.ndarray:
-    """The five-field volume (temperature, anomaly, conductivity, expansivity, |v|)."""
+def make_fields_5(n: int, rngs, progress=None) -> np.ndarray:
+    """The five-field volume (temperature, anomaly, conductivity, expansivity, |v|).  ``progress``,
+    if given, is called with a short message as each field is finished."""
+    done = progress or (lambda msg: None)
     r = radius(n)
     m = shell_mask(r)
     t = temperature(rngs["plumes"], n, r, m)
+    done("temperature")
     dt = temperature_anomaly(t, r, m, n)
+    done("anomaly")
     cond = np.float32(3.0) + np.float32(2.0) * t + np.float32(0.05) * rngs["noise2"].standard_normal(
         (n, n, n), dtype=np.float32)
     cond[~m] = 0.0
+    done("conductivity")
     expn = np.float32(3e-5) * (np.float32(1.0) - np.float32(0.5) * r) + np.float32(1e-6) * \
         rngs["noise3"].standard_normal((n, n, n), dtype=np.float32)
     expn[~m] = 0.0
+    done("expansivity")
     vx = smooth_field(rngs["vel_x"], n, m)
     vy = smooth_field(rngs["vel_y"], n, m)
     vz = smooth_field(rngs["vel_z"], n, m)
     vmag = np.sqrt(vx * vx + vy * vy + vz * vz)
     del vx, vy, vz
     vmag[~m] = 0.0
+    done("velocity magnitude")
     return np.stack([t, dt, cond, expn, vmag]), m
 
 
 def make_workload(config_id: int, n: Optional[int] = None, width: Optional[int] = None,
-                  height: Optional[int] = None) -> Workload:
+                  height: Optional[int] = None, progress=None) -> Workload:
     """Configurations: 0 tiny (64^3, 2 fields, 128^2), 1 single request (256^3, 5 fields,
-    1024^2), 2 precision study (512^3, 5 fields, 1920x1080).  ``n``/``width``/``height``
-    override the sizes (used for small parity cases of the same recipe)."""
+    1024^2), 2 precision study (512^3, 5 fields, 1920x1080), 4 large progressive (1024^3,
+    5 fields, 3840x2160, final step 0.25 voxel).  ``n``/``width``/``height`` override the sizes
+    (used for small cases of the same recipe)."""
     rngs = _children(config_id)
     cam = default_camera()
     if config_id == 0:
@@ -334,16 +366,20 @@ def make_workload(config_id: int, n: Optional[int] = None, width: Optional[int] 
         tf = default_tf(fields, m, 0)
         return Workload(0, "tiny 64^3 x 2 fields fp32, 128x128", fields, FIELD_NAMES_2, brush, tf, cam,
                         width or 128, height or 128, 0.5)
-    if config_id in (1, 2):
-        n = n or (256 if config_id == 1 else 512)
-        fields, m = make_fields_5(n, rngs)
+    if config_id in (1, 2, 4):
+        n = n or {1: 256, 2: 512, 4: 1024}[config_id]
+        fields, m = make_fields_5(n, rngs, progress)
         brush = upper_tail_brush(fields, m, rngs["workload"])
         tf = default_tf(fields, m, 1)
+        step = 0.5
         if config_id == 1:
             w, h, name = width or 1024, height or 1024, f"single request {n}^3 x 5 fields, {width or 1024}x{height or 1024}"
-        else:
+        elif config_id == 2:
             w, h, name = width or 1920, height or 1080, f"precision {n}^3 x 5 fields, {width or 1920}x{height or 1080}"
-        return Workload(config_id, name, fields, FIELD_NAMES_5, brush, tf, cam, w, h, 0.5)
+        else:
+            w, h, step = width or 3840, height or 2160, 0.25
+            name = f"large progressive {n}^3 x 5 fields, {w}x{h}"
+        return Workload(config_id, name, fields, FIELD_NAMES_5, brush, tf, cam, w, h, step)
     raise ValueError(f"unknown config {config_id}")
 
 
