@@ -28,13 +28,22 @@
  * opacity), the marched length (sum of sample lengths) and a fragility mask
  * naming decisions that sit within floating-point reach of a threshold:
  *   bit 0  a brush comparison within delta_b of its bound that could flip the
- *          sample's outcome,
+ *          sample's outcome (delta_b grows with the segment's grazing reach,
+ *          below),
  *   bit 1  accumulated opacity within 1e-4 of the termination threshold,
  *   bit 2  a ray grazing the inner or outer sphere (|discriminant| <= 1e-5),
- *   bit 3  a segment length within 1e-5 (world units) of a whole number of
- *          steps (affects the sample count only),
+ *   bit 3  a segment length within 1e-5 (world units) plus the grazing reach
+ *          of its two ends of a whole number of steps (affects the sample count
+ *          only),
  *   bit 4  a table lookup within 0.05 entries of a zero / non-zero opacity
  *          boundary.
+ * Grazing reach: a renderer working in float32 (unit roundoff u = 2^-24) finds
+ * a sphere hit from the closest-approach discriminant r^2 - |p|^2, p = o - (o.d) d,
+ * which cancels for rays that nearly graze the sphere: a few ulps of error in p
+ * move the roots by about 4 u (|o| + r) r / sqrt(disc) world units.  Near-tangent
+ * chords therefore have ill-conditioned ends in float32 however the renderer
+ * orders its operations, and both their sample count and the positions of their
+ * samples are legitimately uncertain by that much.
  */
 #include <math.h>
 #include <stddef.h>
@@ -144,6 +153,12 @@ typedef struct {
     double pathlen;
 } pixel_result;
 
+/* Float32 reach of a root of the sphere of radius rho with discriminant disc (see the header). */
+static double graze_reach(double o_norm, double rho, double disc)
+{
+    return disc > 0.0 ? 4.0 * ldexp(1.0, -24) * (o_norm + rho) * rho / sqrt(disc) : 0.0;
+}
+
 static void render_pixel(const oracle_params *P, int px, int py, pixel_result *res)
 {
     memset(res, 0, sizeof(*res));
@@ -158,25 +173,34 @@ static void render_pixel(const oracle_params *P, int px, int py, pixel_result *r
     normalize3(d);
 
     /* shell = outer ball minus the open inner ball, restricted to t >= 0 */
-    double seg[2][2];
+    double seg[2][2], reach[2][2];
     int nseg = 0;
     double t0 = 0, t1 = 0, s0 = 0, s1 = 0;
     double disc_out = sphere(o, d, P->r_outer, &t0, &t1);
     double disc_in = P->r_inner > 0.0 ? sphere(o, d, P->r_inner, &s0, &s1) : -1.0;
     if (fabs(disc_out) <= 1e-5 || (P->r_inner > 0.0 && fabs(disc_in) <= 1e-5)) res->fragile |= 4;
     if (disc_out > 0.0) {
-        double cand[2][2];
+        const double o_norm = sqrt(dot3(o, o));
+        const double r_out_reach = graze_reach(o_norm, P->r_outer, disc_out);
+        const double r_in_reach = graze_reach(o_norm, P->r_inner, disc_in);
+        double cand[2][2], cr[2][2];
         int nc = 0;
         if (disc_in > 0.0) {
             cand[nc][0] = t0;
             cand[nc][1] = fmin(t1, s0);
+            cr[nc][0] = r_out_reach;
+            cr[nc][1] = s0 < t1 ? r_in_reach : r_out_reach;
             ++nc;
             cand[nc][0] = fmax(t0, s1);
             cand[nc][1] = t1;
+            cr[nc][0] = s1 > t0 ? r_in_reach : r_out_reach;
+            cr[nc][1] = r_out_reach;
             ++nc;
         } else {
             cand[nc][0] = t0;
             cand[nc][1] = t1;
+            cr[nc][0] = r_out_reach;
+            cr[nc][1] = r_out_reach;
             ++nc;
         }
         for (int k = 0; k < nc; ++k) {
@@ -184,6 +208,8 @@ static void render_pixel(const oracle_params *P, int px, int py, pixel_result *r
             if (b > a) {
                 seg[nseg][0] = a;
                 seg[nseg][1] = b;
+                reach[nseg][0] = cand[k][0] < 0.0 ? 0.0 : cr[k][0];  /* a start clipped at the eye is exact */
+                reach[nseg][1] = cr[k][1];
                 ++nseg;
             }
         }
@@ -198,7 +224,9 @@ static void render_pixel(const oracle_params *P, int px, int py, pixel_result *r
         double a = seg[sgi][0], b = seg[sgi][1];
         double q = (b - a) / ds;
         long ns = (long)ceil(q);
-        if (fabs((b - a) - ds * nearbyint(q)) <= 1e-5) res->fragile |= 8;
+        if (fabs((b - a) - ds * nearbyint(q)) <= 1e-5 + reach[sgi][0] + reach[sgi][1]) res->fragile |= 8;
+        /* grazing reach of the segment's ends in voxels: how far float32 may move its samples */
+        const double pos_reach = fmax(reach[sgi][0], reach[sgi][1]) / h;
         for (long j = 0; j < ns && !done; ++j) {
             double tlo = a + j * ds;
             double thi = fmin(a + (j + 1) * ds, b);
@@ -223,8 +251,8 @@ static void render_pixel(const oracle_params *P, int px, int py, pixel_result *r
                 }
                 int ok = (v >= P->lo[f]) && (v <= P->hi[f]);
                 if (!ok) pass = 0;
-                double dlo = 1e-3 * rng + ldexp(fmax(fabs(P->lo[f]), P->maxabs[f]), -20);
-                double dhi = 1e-3 * rng + ldexp(fmax(fabs(P->hi[f]), P->maxabs[f]), -20);
+                double dlo = (1e-3 + 2.0 * pos_reach) * rng + ldexp(fmax(fabs(P->lo[f]), P->maxabs[f]), -20);
+                double dhi = (1e-3 + 2.0 * pos_reach) * rng + ldexp(fmax(fabs(P->hi[f]), P->maxabs[f]), -20);
                 int near_f = (fabs(v - P->lo[f]) <= dlo) || (fabs(v - P->hi[f]) <= dhi);
                 if (near_f)
                     near = 1;

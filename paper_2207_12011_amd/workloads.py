@@ -383,6 +383,30 @@ def make_workload(config_id: int, n: Optional[int] = None, width: Optional[int] 
     raise ValueError(f"unknown config {config_id}")
 
 
+def analytic_workload(n: int = 1024, width: int = 1920, height: int = 1080) -> Workload:
+    """Two closed-form fields over the shell (zero outside), cheap at the largest grid size:
+    f0 = 0.5 + 0.25 sin(5x) sin(4y) sin(3z) + 0.25 (1 - r) / 0.45 and f1 = r, built one z-slab
+    at a time.  Brush f0 in [0.55, 1], f1 in [0.6, 0.95]; table on f0 over [0, 1]; default camera,
+    step 0.5 voxel."""
+    c = cell_centres(n)
+    sx = np.sin(5.0 * c).astype(np.float32)
+    sy = np.sin(4.0 * c).astype(np.float32)
+    sz = np.sin(3.0 * c).astype(np.float32)
+    yx = (c[None, :] ** 2 + c[:, None] ** 2).astype(np.float32)
+    sxy = sy[:, None] * sx[None, :]
+    fields = np.empty((2, n, n, n), np.float32)
+    for k in range(n):
+        r = np.sqrt(yx + np.float32(c[k] ** 2))
+        m = (r >= np.float32(R_INNER)) & (r <= np.float32(R_OUTER))
+        f0 = np.float32(0.5) + np.float32(0.25) * sxy * sz[k] + np.float32(0.25) * (np.float32(1.0) - r) / np.float32(0.45)
+        fields[0, k] = np.where(m, f0, np.float32(0.0))
+        fields[1, k] = np.where(m, r, np.float32(0.0))
+    brush = Brush(np.ones(2, np.uint8), np.array([0.55, 0.6], np.float32), np.array([1.0, 0.95], np.float32))
+    tf = TransferFunction(0, 0.0, 1.0, default_tf_table())
+    return Workload(5, f"analytic {n}^3 x 2 fields, {width}x{height}", fields, FIELD_NAMES_2, brush, tf,
+                    default_camera(), width, height, 0.5)
+
+
 # --------------------------------------------------------------------------
 # serving trace
 # --------------------------------------------------------------------------

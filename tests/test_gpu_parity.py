@@ -432,3 +432,29 @@ def test_storage_precision_report(rp, ctx, c2):
         assert np.isfinite(rgba).all()
         mx, mean, frac = PRECISION_BOUNDS[storage]
         assert stats["max_abs"] <= mx and stats["mean_abs"] <= mean and stats["frac_gt_1e-2"] <= frac, stats
+
+
+@pytest.mark.timeout(600)
+def test_max_size_1024_sampled(rp, ctx):
+    """The largest grid (1024^3): 64-bit record addressing, a 4 GiB float32 field and a 2 GiB
+    binary16 field in the compact layout (buffer ranges at their limits), all levels; sampled pixels
+    of a 1920x1080 frame against the oracle on the stored values."""
+    wl = W.analytic_workload(1024)
+    print(f"[case] {wl.name}", flush=True)
+    fields_dev = torch.from_numpy(wl.fields).cuda()
+    pix = sample_pixels(wl.width, wl.height, 1500, seed=4)
+    for storage in ("f16", "u8", "f32c", "f16c"):
+        print(f"[case] 1024^3 {storage}", flush=True)
+        vid = rp.load_fields(ctx, fields_dev, storage, 3, wl.r_inner, wl.r_outer)
+        rp.set_brush(ctx, vid, wl.brush.active, wl.brush.lo, wl.brush.hi)
+        rp.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
+        rp.set_options(ctx, wl.ert)
+        rgba, nom, comp = gpu_render(rp, ctx, vid, wl, 0)
+        base = storage.rstrip("c")
+        want_level = np.stack([pp.stored_values(wl.fields[f], base) for f in range(wl.n_fields)])
+        ref = oracle.render_workload(wl, want_level, pixels=pix)
+        del want_level
+        compare(rgba.reshape(-1, 4)[pix], ref, nom.reshape(-1)[pix], comp.reshape(-1)[pix], label=f"1024 {storage}")
+        lod2 = gpu_render(rp, ctx, vid, wl, 2, width=480, height=270)[0]
+        assert np.isfinite(lod2).all() and lod2[..., 3].max() > 0
+        rp.unload(ctx, vid)
