@@ -208,6 +208,41 @@ def pack_bits(flags: np.ndarray) -> np.ndarray:
     return w.sum(axis=1).astype(np.uint32)
 
 
+def pc_bin(v, axis_lo: float, axis_hi: float, n_bins: int) -> np.ndarray:
+    """Histogram bin of values on one parallel-coordinates axis, decided in float32:
+    inv = fl32(1 / fl32(hi - lo)), x = fl32(fl32(fl32(v - lo) * inv) * n_bins),
+    bin = clamp(floor(x), 0, n_bins - 1)."""
+    lo32, hi32 = F32(axis_lo), F32(axis_hi)
+    inv = F32(F32(1.0) / F32(hi32 - lo32))
+    t = ((np.asarray(v, F32) - lo32).astype(F32) * inv).astype(F32)
+    x = (t * F32(n_bins)).astype(F32)
+    return np.clip(np.floor(x), 0, n_bins - 1).astype(np.int64)
+
+
+def pc_lines(level_fields: np.ndarray, cells, active, lo, hi, axis_lo, axis_hi, n_bins: int):
+    """Parallel-coordinates lines (paper, Section 2.1: up to 100 000 randomly chosen cells give the
+    lines of the plot; Section 2: the brush selects the subset that is shown).  For cell indices
+    z N^2 + y N + x of one level: the stored value of every field (the line's coordinates), whether
+    the line passes the brush (every active field inside its inclusive [lo, hi]), and per field a
+    histogram over ``n_bins`` bins of [axis_lo, axis_hi] (pc_bin) of all lines and of passing lines.
+    Returns (values float32 [L, F], passes uint8 [L], hist uint32 [F, n_bins, 2])."""
+    lf = np.asarray(level_fields, F32)
+    nf, n = lf.shape[0], lf.shape[1]
+    c = np.asarray(cells, np.int64)
+    z, y, x = c // (n * n), (c // n) % n, c % n
+    values = np.stack([lf[f, z, y, x] for f in range(nf)], axis=1).astype(F32)
+    keep = np.ones(c.size, bool)
+    for f in range(nf):
+        if active[f]:
+            keep &= (values[:, f] >= F32(lo[f])) & (values[:, f] <= F32(hi[f]))
+    hist = np.zeros((nf, n_bins, 2), np.uint32)
+    for f in range(nf):
+        b = pc_bin(values[:, f], axis_lo[f], axis_hi[f], n_bins)
+        hist[f, :, 0] = np.bincount(b, minlength=n_bins)
+        hist[f, :, 1] = np.bincount(b[keep], minlength=n_bins)
+    return values, keep.astype(np.uint8), hist
+
+
 def voxel_mask(level_fields: np.ndarray, active, lo, hi) -> np.ndarray:
     """uint8 [N]^3: 1 where every active field lies in its inclusive [lo, hi]."""
     m = np.ones(level_fields.shape[1:], bool)

@@ -407,6 +407,15 @@ def analytic_workload(n: int = 1024, width: int = 1920, height: int = 1080) -> W
                     default_camera(), width, height, 0.5)
 
 
+def pc_line_cells(n: int, count: int = 100_000, seed: int = SEED_BASE + 6) -> np.ndarray:
+    """Seeded choice (without replacement) of up to ``count`` shell cells of an N^3 grid, as
+    uint32 linear indices z N^2 + y N + x: the cells whose values are the lines of the
+    parallel-coordinates plot."""
+    idx = np.flatnonzero(shell_mask(radius(n)).ravel())
+    rng = np.random.default_rng(seed)
+    return rng.choice(idx, size=min(count, idx.size), replace=False).astype(np.uint32)
+
+
 # --------------------------------------------------------------------------
 # serving trace
 # --------------------------------------------------------------------------

@@ -420,6 +420,50 @@ def test_sub_skip_is_conservative():
     assert not np.any(passes & (a > 0))
 
 
+def test_pc_lines_pins(tiny):
+    """Lines pass exactly where the (enumeration-pinned) voxel mask is set; every histogram holds
+    every line once and the passing ones once more; inclusive / empty brushes select all / none;
+    inactive fields are not tested."""
+    wl = tiny
+    n = wl.n
+    rng = np.random.default_rng(21)
+    cells = rng.choice(n ** 3, size=500, replace=False)
+    lo_ax = wl.fields.reshape(2, -1).min(axis=1)
+    hi_ax = wl.fields.reshape(2, -1).max(axis=1)
+    vals, passes, hist = pp.pc_lines(wl.fields, cells, wl.brush.active, wl.brush.lo, wl.brush.hi, lo_ax, hi_ax, 32)
+    mask = pp.voxel_mask(wl.fields, wl.brush.active, wl.brush.lo, wl.brush.hi).reshape(-1)
+    assert np.array_equal(passes, mask[cells])
+    assert 0 < passes.sum() < passes.size
+    z, y, x = cells // (n * n), (cells // n) % n, cells % n
+    assert np.array_equal(vals[:, 1], wl.fields[1][z, y, x])
+    assert np.all(hist[:, :, 0].sum(axis=1) == cells.size)
+    assert np.all(hist[:, :, 1].sum(axis=1) == passes.sum())
+    assert np.all(hist[:, :, 1] <= hist[:, :, 0])
+    nf = 2
+    _, p_all, _ = pp.pc_lines(wl.fields, cells, [1, 1], [-np.inf] * nf, [np.inf] * nf, lo_ax, hi_ax, 32)
+    _, p_none, _ = pp.pc_lines(wl.fields, cells, [1, 1], [1.0, 1.0], [0.0, 0.0], lo_ax, hi_ax, 32)
+    _, p_off, _ = pp.pc_lines(wl.fields, cells, [0, 0], [1.0, 1.0], [0.0, 0.0], lo_ax, hi_ax, 32)
+    assert p_all.all() and not p_none.any() and p_off.all()
+
+
+def test_pc_bin_closed_forms():
+    """On the axis [0, 16) with 16 bins, integer values fall in their own bin (exact in float32);
+    values below / above the axis clamp to the first / last bin; away from bin edges the bins agree
+    with numpy.histogram."""
+    ints = np.arange(16, dtype=np.float32)
+    assert np.array_equal(pp.pc_bin(ints, 0.0, 16.0, 16), np.arange(16))
+    assert list(pp.pc_bin(np.array([-5.0, 16.0, 1e9], np.float32), 0.0, 16.0, 16)) == [0, 15, 15]
+    rng = np.random.default_rng(22)
+    v = rng.uniform(-1.0, 3.0, 20000).astype(np.float32)
+    lo, hi, nb = -1.0, 3.0, 50
+    edges = np.linspace(lo, hi, nb + 1)
+    far = np.min(np.abs(v[:, None].astype(np.float64) - edges[None, :]), axis=1) > 1e-5
+    want = np.digitize(v[far], edges[1:-1])
+    assert np.array_equal(pp.pc_bin(v[far], lo, hi, nb), want)
+    h, _ = np.histogram(v[far], bins=edges)
+    assert np.array_equal(np.bincount(pp.pc_bin(v[far], lo, hi, nb), minlength=nb), h)
+
+
 def test_voxel_mask_enumeration(tiny):
     wl = tiny
     m = pp.voxel_mask(wl.fields, wl.brush.active, wl.brush.lo, wl.brush.hi)
