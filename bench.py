@@ -125,6 +125,29 @@ def brush_axis_sweep(raypc, torch, ctx, vid, wl, lod, stream, frames=30):
     return res
 
 
+def pc_lines_timing(raypc, torch, W, ctx, vid, wl, stream, n_lines=100_000, n_bins=64, calls=50):
+    """The parallel-coordinates lines of the paper's preprocessing (up to 100 000 random shell cells):
+    values, brush flags and 64-bin histograms of all / passing lines per axis, for the headline
+    brush; median time of one call."""
+    cells = torch.from_numpy(W.pc_line_cells(wl.n, n_lines).astype(np.int32)).cuda()
+    nf = wl.n_fields
+    axis_lo = wl.fields.reshape(nf, -1).min(axis=1)
+    axis_hi = wl.fields.reshape(nf, -1).max(axis=1)
+    raypc.pc_lines(ctx, vid, 0, cells, axis_lo, axis_hi, n_bins, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for a, e in ev:
+        a.record(stream)
+        _, passes, _ = raypc.pc_lines(ctx, vid, 0, cells, axis_lo, axis_hi, n_bins, stream=stream)
+        e.record(stream)
+    torch.cuda.synchronize()
+    us = 1e3 * float(np.median([a.elapsed_time(e) for a, e in ev]))
+    res = {"lines": int(cells.numel()), "bins": n_bins, "fields": nf, "us": us,
+           "lines_per_s": cells.numel() / (us * 1e-6), "passing": int(passes.sum().item())}
+    print(f"[bench] parallel-coordinates lines: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def serving(args, raypc, torch, W, wl512, fields512_dev):
     """Serving configuration: 256^3 and 512^3 x 5 FP16 volumes resident; a seeded trace of
     requests (sizes 256^2 .. 2048^2, orbit cameras, 1-5-axis quantile brushes, level by the
@@ -335,6 +358,7 @@ def main():
     out = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
     results = {}
     sweep_result = None
+    pc_result = None
     storages = args.storages.split(",")
     bpv = {"f32": 4, "f16": 2, "u8": 1, "f32c": 4, "f16c": 2, "u8c": 1}
 
@@ -412,6 +436,8 @@ def main():
         print(f"[bench] {storage}: {results[storage]}", file=sys.stderr, flush=True)
         if si == 0 and not args.no_sweep:
             sweep_result = brush_axis_sweep(raypc, torch, ctx, vid, wl, lod, stream)
+        if si == 0:
+            pc_result = pc_lines_timing(raypc, torch, W, ctx, vid, wl, stream)
         raypc.unload(ctx, vid)
 
     head = storages[0]
@@ -477,6 +503,7 @@ def main():
         "roofline": roofline,
         "serving": serving_result,
         "brush_axis_sweep": sweep_result,
+        "pc_lines": pc_result,
         "cpu_baseline": cpu_baseline,
     }
     raypc.destroy(ctx)

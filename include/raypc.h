@@ -232,6 +232,28 @@ int raypc_export_subskip(raypc_ctx *ctx, int volume_id, int lod, int slot, uint8
  * lies in its [lo, hi]. */
 int raypc_export_voxel_mask(raypc_ctx *ctx, int volume_id, int lod, uint8_t *out, void *stream);
 
+/* ---------------------------------------------------------------- parallel coordinates
+ * Lines of the parallel-coordinates plot and their linking to the brush (Section 2.1: up to
+ * 100 000 randomly chosen cells are stored as the plot's lines; Section 2: the bounds set on the
+ * plot's axes select the subset of the data that is shown).  For n_lines cell indices of level
+ * `lod` (device uint32, z N_l^2 + y N_l + x, chosen by the caller):
+ *   values  device float32 [n_lines][n_fields]: the stored value of every field, i.e. the line's
+ *           coordinates on the plot's axes (NULL: not written);
+ *   passes  device uint8 [n_lines]: 1 when every active field of the volume's brush lies in its
+ *           inclusive [lo, hi], else 0 (NULL: not written);
+ *   hist    device uint32 [n_fields][n_bins][2], overwritten: per field, the number of lines per
+ *           bin of the axis [axis_lo[f], axis_hi[f]] (host arrays of n_fields floats), all lines in
+ *           [.][.][0] and lines that pass in [.][.][1] (NULL: not written).  The bin of value v is
+ *           decided in float32: inv = fl32(1 / fl32(hi - lo)), x = fl32(fl32(fl32(v - lo) * inv)
+ *           * n_bins), bin = clamp(floor(x), 0, n_bins - 1), so values outside the axis land in
+ *           the end bins.
+ * A cell index >= N_l^3 gives NaN values, flag 0 and no histogram entry.  n_lines in [0, 2^24],
+ * n_bins in [1, 512] (when hist is given), axis ranges finite with hi > lo.  Async on `stream`.
+ * Errors: RAYPC_ERR_INVALID (nothing is launched). */
+int raypc_pc_lines(raypc_ctx *ctx, int volume_id, int lod, int n_lines, const uint32_t *cells,
+                   const float *axis_lo, const float *axis_hi, int n_bins, float *values, uint8_t *passes,
+                   uint32_t *hist, void *stream);
+
 /* raypc_render plus per-pixel sample counts: nominal = samples visited up to
  * and including an early-termination stop; composited = samples that passed
  * the brush with non-zero table opacity.  touched_bricks (ceil(nb^3 / 32)

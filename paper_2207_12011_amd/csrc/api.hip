@@ -693,6 +693,54 @@ int raypc_export_subskip(raypc_ctx* ctx, int volume_id, int lod, int slot, uint8
     return export_skip(ctx, volume_id, lod, slot, out, true, stream);
 }
 
+int raypc_pc_lines(raypc_ctx* ctx, int volume_id, int lod, int n_lines, const uint32_t* cells, const float* axis_lo,
+                   const float* axis_hi, int n_bins, float* values, uint8_t* passes, uint32_t* hist, void* stream) {
+    if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    int rc = check_level(v, lod);
+    if (rc) return rc;
+    if (n_lines < 0 || n_lines > (1 << 24)) return fail(RAYPC_ERR_INVALID, "n_lines %d outside [0, 2^24]", n_lines);
+    if (n_lines > 0 && !cells) return fail(RAYPC_ERR_INVALID, "cells is NULL");
+    PcArgs a;
+    std::memset(&a, 0, sizeof(a));
+    if (hist) {
+        if (n_bins < 1 || n_bins > kMaxPcBins) return fail(RAYPC_ERR_INVALID, "n_bins %d outside [1, %d]", n_bins, kMaxPcBins);
+        if (!axis_lo || !axis_hi) return fail(RAYPC_ERR_INVALID, "axis_lo / axis_hi is NULL");
+        for (int f = 0; f < v->nf; ++f) {
+            const float w = axis_hi[f] - axis_lo[f];
+            const float inv = 1.0f / w;
+            if (!std::isfinite(axis_lo[f]) || !std::isfinite(axis_hi[f]) || !(w > 0.0f) || !std::isfinite(inv))
+                return fail(RAYPC_ERR_INVALID, "axis %d range [%g, %g] is not a finite, non-empty interval", f,
+                            static_cast<double>(axis_lo[f]), static_cast<double>(axis_hi[f]));
+            a.axis_lo[f] = axis_lo[f];
+            a.inv[f] = inv;
+        }
+    }
+    const Level& L = v->lv[lod];
+    for (int f = 0; f < v->nf; ++f) {
+        a.field[f] = L.data[f];
+        a.u8par[f] = L.par[f];
+        a.active[f] = v->active[f];
+        a.lo[f] = v->lo[f];
+        a.hi[f] = v->hi[f];
+    }
+    a.n_fields = v->nf;
+    a.storage = v->storage;
+    a.n = L.n;
+    a.nb = L.nb;
+    a.n_bins = n_bins;
+    a.n_lines = n_lines;
+    a.cells = cells;
+    a.values = values;
+    a.passes = passes;
+    a.hist = hist;
+    HIP_TRY(launch_pc_lines(a, static_cast<hipStream_t>(stream)), "parallel-coordinates kernel launch");
+    return RAYPC_OK;
+}
+
 int raypc_export_voxel_mask(raypc_ctx* ctx, int volume_id, int lod, uint8_t* out, void* stream) {
     if (!ctx || !out) return fail(RAYPC_ERR_INVALID, "NULL argument");
     DeviceGuard g(ctx->device);

@@ -76,6 +76,23 @@ struct MaskArgs {
 };
 hipError_t launch_voxel_mask(const MaskArgs& a, hipStream_t s);
 
+// Parallel-coordinates lines: per cell index, the stored values, the brush flag and per-field
+// histograms of all / passing lines (bins decided in float32, see raypc_pc_lines).
+constexpr int kMaxPcBins = 512;
+struct PcArgs {
+    const void* field[kMaxFields];
+    const float2* u8par[kMaxFields];
+    uint8_t active[kMaxFields];
+    float lo[kMaxFields], hi[kMaxFields];       // the volume's brush
+    float axis_lo[kMaxFields], inv[kMaxFields]; // inv = fl32(1 / fl32(axis_hi - axis_lo))
+    int n_fields, storage, n, nb, n_bins, n_lines;
+    const uint32_t* cells;                      // z N^2 + y N + x
+    float* values;                              // [n_lines][n_fields] or null
+    uint8_t* passes;                            // [n_lines] or null
+    uint32_t* hist;                             // [n_fields][n_bins][2] or null
+};
+hipError_t launch_pc_lines(const PcArgs& a, hipStream_t s);
+
 struct SkipArgs {
     const float2* minmax[kMaxFields];      // active fields' brick (min, max) tables
     const float2* minmax_sub[kMaxFields];  // and their sub-brick tables

@@ -225,6 +225,53 @@ __global__ void voxel_mask_kernel(MaskArgs a) {
     a.out[o] = keep ? 1 : 0;
 }
 
+// Parallel-coordinates lines: one thread per line; histograms gather in LDS and are added to the
+// (zeroed) output once per block.  A cell index outside the grid gives NaN values, flag 0 and no
+// histogram entry.
+template <int S>
+__global__ __launch_bounds__(256) void pc_lines_kernel(PcArgs a) {
+    __shared__ uint32_t s_hist[kMaxFields * kMaxPcBins * 2];
+    const int hist_len = a.n_fields * a.n_bins * 2;
+    if (a.hist != nullptr)
+        for (int i = threadIdx.x; i < hist_len; i += blockDim.x) s_hist[i] = 0;
+    __syncthreads();
+    const uint32_t total = static_cast<uint32_t>(a.n) * a.n * a.n;
+    for (int line = blockIdx.x * blockDim.x + threadIdx.x; line < a.n_lines; line += gridDim.x * blockDim.x) {
+        const uint32_t c = a.cells[line];
+        const bool valid = c < total;
+        const int x = static_cast<int>(c % a.n), y = static_cast<int>((c / a.n) % a.n);
+        const int z = static_cast<int>(c / (static_cast<uint32_t>(a.n) * a.n));
+        const uint32_t addr = valid ? brick_addr(x, y, z, a.nb) : 0u;
+        bool pass = valid;
+        for (int f = 0; f < a.n_fields; ++f) {
+            const float v = valid ? stored<S>(a.field[f], a.u8par[f], addr) : NAN;
+            if (a.values != nullptr) a.values[static_cast<size_t>(line) * a.n_fields + f] = v;
+            if (a.active[f]) pass = pass && (v >= a.lo[f]) && (v <= a.hi[f]);
+        }
+        if (a.passes != nullptr) a.passes[line] = pass ? 1 : 0;
+        if (a.hist != nullptr && valid) {
+            for (int f = 0; f < a.n_fields; ++f) {
+                const float v = stored<S>(a.field[f], a.u8par[f], addr);
+                const float t = __fmul_rn(__fsub_rn(v, a.axis_lo[f]), a.inv[f]);
+                const float xb = fminf(fmaxf(__fmul_rn(t, static_cast<float>(a.n_bins)), 0.0f),
+                                       static_cast<float>(a.n_bins - 1));
+                const int b = static_cast<int>(floorf(xb));
+                atomicAdd(&s_hist[(f * a.n_bins + b) * 2], 1u);
+                if (pass) atomicAdd(&s_hist[(f * a.n_bins + b) * 2 + 1], 1u);
+            }
+        }
+    }
+    if (a.hist == nullptr) return;
+    __syncthreads();
+    for (int i = threadIdx.x; i < hist_len; i += blockDim.x)
+        if (s_hist[i]) atomicAdd(&a.hist[i], s_hist[i]);
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
 // The skip rule for one (min, max) window: some active field misses its [lo, hi] (or lo > hi), or
 // the table opacity is zero over every entry the transfer-function field's range can address.
 __device__ __forceinline__ bool tf_range_empty(const SkipArgs& a, float2 tm) {
@@ -364,6 +411,21 @@ hipError_t launch_voxel_mask(const MaskArgs& a, hipStream_t s) {
         case kF32: hipLaunchKernelGGL(voxel_mask_kernel<kF32>, g, dim3(256), 0, s, a); break;
         case kF16: hipLaunchKernelGGL(voxel_mask_kernel<kF16>, g, dim3(256), 0, s, a); break;
         default: hipLaunchKernelGGL(voxel_mask_kernel<kU8>, g, dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pc_lines(const PcArgs& a, hipStream_t s) {
+    if (a.hist != nullptr) {
+        const int count = a.n_fields * a.n_bins * 2;
+        hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, a.hist, count);
+    }
+    if (a.n_lines <= 0) return hipGetLastError();
+    const unsigned blocks = std::min(blocks_for(static_cast<size_t>(a.n_lines), 256), 1024u);
+    switch (a.storage) {
+        case kF32: hipLaunchKernelGGL(pc_lines_kernel<kF32>, dim3(blocks), dim3(256), 0, s, a); break;
+        case kF16: hipLaunchKernelGGL(pc_lines_kernel<kF16>, dim3(blocks), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(pc_lines_kernel<kU8>, dim3(blocks), dim3(256), 0, s, a); break;
     }
     return hipGetLastError();
 }

@@ -80,6 +80,7 @@ _render_prog = _sig("raypc_render_progressive", _I, _P, _I, ctypes.POINTER(Camer
 _export_level = _sig("raypc_export_level", _I, _P, _I, _I, _I, _P, _P)
 _export_minmax = _sig("raypc_export_minmax", _I, _P, _I, _I, _I, _P, _P)
 _export_minmax_sub = _sig("raypc_export_minmax_sub", _I, _P, _I, _I, _I, _P, _P)
+_pc_lines = _sig("raypc_pc_lines", _I, _P, _I, _I, _I, _P, _P, _P, _I, _P, _P, _P, _P)
 _export_skip = _sig("raypc_export_skiplist", _I, _P, _I, _I, _I, _P, _P)
 _export_subskip = _sig("raypc_export_subskip", _I, _P, _I, _I, _I, _P, _P)
 _export_mask = _sig("raypc_export_voxel_mask", _I, _P, _I, _I, _P, _P)
@@ -121,7 +122,7 @@ EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_po
             "raypc_unload", "raypc_volume_info", "raypc_set_brush", "raypc_set_transfer_function",
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
             "raypc_export_level", "raypc_export_minmax", "raypc_export_minmax_sub", "raypc_export_skiplist",
-            "raypc_export_subskip", "raypc_export_voxel_mask", "raypc_render_debug"]
+            "raypc_export_subskip", "raypc_export_voxel_mask", "raypc_render_debug", "raypc_pc_lines"]
 
 
 class RaypcError(RuntimeError):
@@ -319,6 +320,32 @@ def export_skiplist(ctx, volume_id: int, lod: int, slot: int = 0, stream=None) -
     out = torch.empty(((nb ** 3 + 31) // 32,), dtype=torch.int32, device="cuda")
     _check(_export_skip(ctx, int(volume_id), int(lod), int(slot), out.data_ptr(), _stream(stream)))
     return out
+
+
+def pc_lines(ctx, volume_id: int, lod: int, cells: torch.Tensor, axis_lo=None, axis_hi=None, n_bins: int = 64,
+             stream=None):
+    """Parallel-coordinates lines of `cells` (a device tensor of uint32 or int32 linear indices):
+    (values float32 [L, F], passes uint8 [L], hist int32 [F, n_bins, 2] or None without axis ranges)."""
+    info = volume_info(ctx, volume_id)
+    nf = info["n_fields"]
+    if cells.dtype not in (torch.int32, torch.uint32) or not cells.is_cuda:
+        raise ValueError("cells must be a CUDA tensor of 32-bit integers")
+    c = cells.contiguous()
+    nl = c.numel()
+    values = torch.empty((nl, nf), dtype=torch.float32, device="cuda")
+    passes = torch.empty((nl,), dtype=torch.uint8, device="cuda")
+    hist = None
+    lo_p = hi_p = None
+    if axis_lo is not None:
+        lo_a = np.ascontiguousarray(np.asarray(axis_lo, np.float32).reshape(nf))
+        hi_a = np.ascontiguousarray(np.asarray(axis_hi, np.float32).reshape(nf))
+        # at least one bin so that the library, not a NULL pointer, rejects a bad n_bins
+        hist = torch.empty((nf, max(int(n_bins), 1), 2), dtype=torch.int32, device="cuda")
+        lo_p, hi_p = lo_a.ctypes.data, hi_a.ctypes.data
+    _check(_pc_lines(ctx, int(volume_id), int(lod), nl, c.data_ptr() if nl else None, lo_p, hi_p, int(n_bins),
+                     values.data_ptr() if nl else None, passes.data_ptr() if nl else None,
+                     hist.data_ptr() if hist is not None else None, _stream(stream)))
+    return values, passes, hist
 
 
 def export_voxel_mask(ctx, volume_id: int, lod: int, stream=None) -> torch.Tensor:
