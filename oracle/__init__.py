@@ -44,7 +44,7 @@ def lib():
             ctypes.c_int, ctypes.c_int, P, ctypes.c_double, ctypes.c_double,
             P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, ctypes.c_double,
             ctypes.c_double, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_long,
-            P, P, P, P, P, P, ctypes.c_int]
+            P, P, P, P, P, P, P, ctypes.c_int]
         L.oracle_trilinear.restype = None
         L.oracle_trilinear.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P]
         _lib = L
@@ -68,8 +68,10 @@ def render(level_fields: np.ndarray, camera, width: int, height: int, step: floa
            active, lo, hi, tf_field: int, vmin: float, vmax: float, tf_rgba,
            ref_step: float = 2.0 / 256, ert: float = 0.99, bg=None,
            r_inner: float = 0.55, r_outer: float = 1.0,
-           pixels: Optional[np.ndarray] = None, threads: Optional[int] = None) -> OracleImage:
-    """Render `pixels` (linear indices py*W+px; None = full frame) of one level.
+           pixels: Optional[np.ndarray] = None, threads: Optional[int] = None,
+           jitter: Optional[np.ndarray] = None) -> OracleImage:
+    """Render `pixels` (linear indices py*W+px; None = full frame) of one level.  `jitter` gives
+    each rendered pixel's sample-grid offset in [0, 1) steps (None: the regular partition).
 
     `level_fields` holds the level's stored values as float32 [F, N, N, N];
     scalars and tables are taken at float32 boundary precision and widened
@@ -87,6 +89,7 @@ def render(level_fields: np.ndarray, camera, width: int, height: int, step: floa
     full = pixels is None
     pix = None if full else np.ascontiguousarray(np.asarray(pixels, np.int64))
     npix = width * height if full else pix.size
+    jit = None if jitter is None else np.ascontiguousarray(np.asarray(jitter, np.float64).reshape(npix))
     rgba = np.zeros((npix, 4))
     nom = np.zeros(npix, np.uint32)
     comp = np.zeros(npix, np.uint32)
@@ -97,7 +100,7 @@ def render(level_fields: np.ndarray, camera, width: int, height: int, step: floa
         nf, n, ctypes.cast(ptrs, ctypes.c_void_p), float(np.float32(r_inner)), float(np.float32(r_outer)),
         _ptr(act), _ptr(lo64), _ptr(hi64), int(tf_field), float(np.float32(vmin)), float(np.float32(vmax)),
         _ptr(tf64), float(np.float32(ref_step)), float(np.float32(ert)), _ptr(bg64), _ptr(cam),
-        int(width), int(height), float(np.float32(step)), int(npix), _ptr(pix),
+        int(width), int(height), float(np.float32(step)), int(npix), _ptr(pix), _ptr(jit),
         _ptr(rgba), _ptr(nom), _ptr(comp), _ptr(frag), _ptr(plen), int(threads))
     if rc != 0:
         raise ValueError("oracle_render: invalid arguments")

@@ -159,7 +159,10 @@ static double graze_reach(double o_norm, double rho, double disc)
     return disc > 0.0 ? 4.0 * ldexp(1.0, -24) * (o_norm + rho) * rho / sqrt(disc) : 0.0;
 }
 
-static void render_pixel(const oracle_params *P, int px, int py, pixel_result *res)
+/* `jit` is the pixel's sample-grid offset s in [0, 1) (in steps): samples of a segment [a, b] are
+ * the pieces of [a, b] cut at g + j ds (g = a - s ds), each evaluated at its midpoint; s = 0 gives
+ * the regular partition. */
+static void render_pixel(const oracle_params *P, int px, int py, double jit, pixel_result *res)
 {
     memset(res, 0, sizeof(*res));
     /* ray through the pixel centre; row 0 is the top row */
@@ -222,14 +225,15 @@ static void render_pixel(const oracle_params *P, int px, int py, pixel_result *r
     int done = 0;
     for (int sgi = 0; sgi < nseg && !done; ++sgi) {
         double a = seg[sgi][0], b = seg[sgi][1];
-        double q = (b - a) / ds;
+        double g = a - jit * ds;
+        double q = (b - g) / ds;
         long ns = (long)ceil(q);
-        if (fabs((b - a) - ds * nearbyint(q)) <= 1e-5 + reach[sgi][0] + reach[sgi][1]) res->fragile |= 8;
+        if (fabs((b - g) - ds * nearbyint(q)) <= 1e-5 + reach[sgi][0] + reach[sgi][1]) res->fragile |= 8;
         /* grazing reach of the segment's ends in voxels: how far float32 may move its samples */
         const double pos_reach = fmax(reach[sgi][0], reach[sgi][1]) / h;
         for (long j = 0; j < ns && !done; ++j) {
-            double tlo = a + j * ds;
-            double thi = fmin(a + (j + 1) * ds, b);
+            double tlo = fmax(a, g + j * ds);
+            double thi = fmin(g + (j + 1) * ds, b);
             double len = thi - tlo;
             double tm = 0.5 * (tlo + thi);
             double u[3];
@@ -309,15 +313,17 @@ static void render_pixel(const oracle_params *P, int px, int py, pixel_result *r
  * oracle_render: render the listed pixels (linear index py*width + px; NULL
  * means every pixel in row-major order).  `fields` are the level's stored
  * values already converted to float32 ([z][y][x], n^3 each).  Camera is
- * {eye[3], target[3], up[3], fov_y_deg}.  `bg` may be NULL.  Any output
- * pointer may be NULL.  Returns 0, or -1 on invalid arguments.
+ * {eye[3], target[3], up[3], fov_y_deg}.  `bg` may be NULL.  `jitter` holds
+ * one sample-grid offset in [0, 1) per requested pixel (NULL: 0, the regular
+ * partition).  Any output pointer may be NULL.  Returns 0, or -1 on invalid
+ * arguments.
  */
 int oracle_render(int n_fields, int n, const float *const *fields, double r_inner, double r_outer,
                   const uint8_t *active, const double *lo, const double *hi, int tf_field, double vmin,
                   double vmax, const double *tf_rgba, double ref_step, double ert, const double *bg,
                   const double *camera, int width, int height, double step_vox, long n_pix,
-                  const int64_t *pix, double *rgba, uint32_t *nominal, uint32_t *composited,
-                  uint8_t *fragile, double *pathlen, int n_threads)
+                  const int64_t *pix, const double *jitter, double *rgba, uint32_t *nominal,
+                  uint32_t *composited, uint8_t *fragile, double *pathlen, int n_threads)
 {
     if (n_fields < 1 || n_fields > ORACLE_MAX_FIELDS || n < 2 || width < 1 || height < 1 ||
         tf_field < 0 || tf_field >= n_fields || !(vmax > vmin) || !(step_vox > 0) || !(ref_step > 0))
@@ -367,7 +373,7 @@ int oracle_render(int n_fields, int n, const float *const *fields, double r_inne
     for (long k = 0; k < total; ++k) {
         long lin = pix ? (long)pix[k] : k;
         pixel_result r;
-        render_pixel(&P, (int)(lin % width), (int)(lin / width), &r);
+        render_pixel(&P, (int)(lin % width), (int)(lin / width), jitter ? jitter[k] : 0.0, &r);
         if (rgba)
             for (int c = 0; c < 4; ++c) rgba[4 * k + c] = r.rgba[c];
         if (nominal) nominal[k] = r.nominal;

@@ -13,6 +13,7 @@ import pytest
 from scipy.ndimage import map_coordinates
 
 import oracle
+from oracle import jitter as J
 from oracle import preprocess as pp
 from paper_2207_12011_amd import workloads as W
 
@@ -283,6 +284,85 @@ def test_sample_count_definition():
         for px in range(9):
             want = sum(int(math.ceil((b - a) / ds)) for a, b in bf.segments(eye, dirs[py, px], 0.55, 1.0))
             assert o.nominal[py, px] == want
+
+
+# ----------------------------------------------------------------------------- jittered passes
+def test_splitmix64_reference_outputs():
+    """First outputs of SplitMix64 from state 0, as listed with the generator's reference
+    implementation (Steele, Lea and Flood, OOPSLA 2014; the public-domain splitmix64.c)."""
+    assert J.splitmix64_stream(0, 3) == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_jitter_offsets_stratified_and_uniform():
+    """Pass k of K draws its offsets from [k/K, (k+1)/K) (exactly, for K a power of two); within a
+    stratum they are uniform (chi-square over 16 bins); seeds and passes decorrelate; the clamp
+    keeps every offset below 1."""
+    K, n = 8, 200_000
+    pix = np.arange(n)
+    prev = None
+    for k in range(K):
+        s = J.offsets(1000, pix, k, K, 99)
+        assert np.all(s >= k / K) and np.all(s < (k + 1) / K)
+        u = s * K - k
+        h = np.histogram(u, bins=16, range=(0.0, 1.0))[0]
+        chi2 = float(((h - n / 16) ** 2 / (n / 16)).sum())
+        assert chi2 < 60.0, (k, chi2)
+        if prev is not None:
+            assert abs(np.corrcoef(u, prev)[0, 1]) < 0.01
+        prev = u
+    assert np.array_equal(J.offsets(64, pix[:100], 3, 8, 5), J.offsets(64, pix[:100], 3, 8, 5))
+    assert not np.array_equal(J.offsets(64, pix[:100], 3, 8, 5), J.offsets(64, pix[:100], 3, 8, 6))
+    for K_ in (255, 256, 7):
+        assert J.offsets(64, pix[:5000], K_ - 1, K_, 1).max() < 1.0
+
+
+def test_jittered_zero_offset_is_regular(tiny):
+    wl = tiny
+    a = oracle.render_workload(wl, wl.fields)
+    b = oracle.render_workload(wl, wl.fields, jitter=np.zeros(wl.width * wl.height))
+    assert np.array_equal(a.rgba, b.rgba) and np.array_equal(a.nominal, b.nominal)
+
+
+@pytest.mark.parametrize("step", [0.5, 1.0])
+def test_jittered_closed_forms(step):
+    """Constant field, any grid offsets: the marched length is the analytic chord, the opacity
+    is 1 - (1-A0)^(L/ref), and a segment holds ceil(L/ds + s) samples."""
+    vol = constant_volume()
+    cam = axis_camera()
+    W_, H_ = 15, 15
+    s = J.offsets(W_, np.arange(W_ * H_), 2, 5, 7)
+    a0 = 0.3
+    o = oracle.render(vol, cam, W_, H_, step, active=[0], lo=[0], hi=[1], tf_field=0, vmin=0, vmax=1,
+                      tf_rgba=const_tf(a0), ert=1.0, jitter=s)
+    eye, dirs = bf.camera_rays(cam, W_, H_)
+    ds = float(np.float32(step)) * 2 / 16
+    ref = float(np.float32(2 / 256))
+    for py in range(H_):
+        for px in range(W_):
+            p = np.linalg.norm(np.cross(eye, dirs[py, px]))
+            L = chord(p)
+            assert abs(o.pathlen[py, px] - L) <= 1e-12
+            want = 1 - (1 - float(np.float32(a0))) ** (L / ref)
+            assert abs(o.rgba[py, px, 3] - want) <= 1e-12
+            sj = s[py * W_ + px]
+            n_want = sum(int(math.ceil((b - a) / ds + sj)) for a, b in bf.segments(eye, dirs[py, px], 0.55, 1.0))
+            assert o.nominal[py, px] == n_want
+
+
+def test_jittered_mean_converges_to_fine_render(tiny):
+    """The mean of K jittered passes approaches the render at step / K: its error against a render
+    at step / 64 falls as K grows."""
+    wl = tiny
+    npx = wl.width * wl.height
+    fine = oracle.render_workload(wl, wl.fields, step=wl.step / 64).rgba
+    errs = []
+    for K in (1, 4, 16):
+        acc = np.zeros_like(fine)
+        for k in range(K):
+            acc += oracle.render_workload(wl, wl.fields, jitter=J.offsets(wl.width, np.arange(npx), k, K, 3)).rgba
+        errs.append(float(np.abs(acc / K - fine).mean()))
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[2] < 0.35 * errs[0], errs
 
 
 # ----------------------------------------------------------------------------- preprocessing
