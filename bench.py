@@ -125,6 +125,34 @@ def brush_axis_sweep(raypc, torch, ctx, vid, wl, lod, stream, frames=30):
     return res
 
 
+def jittered_timing(raypc, torch, ctx, vid, wl, lod, stream, n_passes=8, seed=0x5EED2207):
+    """Jittered progressive passes on the headline view and brush: median time of one pass (with the
+    running-mean update) against the plain frame, and the mean-abs error of the running mean after
+    1, 2, 4 and 8 passes against the render at step / 8."""
+    cam = wl.camera.as_array()
+    W_, H_ = wl.width, wl.height
+    out = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
+    fine = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
+    mean = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
+    raypc.render(ctx, vid, cam, W_, H_, lod, wl.step / n_passes, out=fine, stream=stream)
+    errs, times = {}, []
+    for rnd in range(3):
+        for k in range(n_passes):
+            a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            raypc.render_jittered(ctx, vid, cam, W_, H_, lod, wl.step, k, n_passes, seed, mean=mean, stream=stream)
+            e.record(stream)
+            torch.cuda.synchronize()
+            if rnd > 0:
+                times.append(a.elapsed_time(e))
+            if rnd == 0 and (k + 1) in (1, 2, 4, 8):
+                errs[k + 1] = float((mean - fine).abs().mean().item())
+    res = {"passes": n_passes, "ms_per_pass": float(np.median(times)),
+           "mean_abs_err_vs_step_over_8": errs}
+    print(f"[bench] jittered passes: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def pc_lines_timing(raypc, torch, W, ctx, vid, wl, stream, n_lines=100_000, n_bins=64, calls=50):
     """The parallel-coordinates lines of the paper's preprocessing (up to 100 000 random shell cells):
     values, brush flags and 64-bin histograms of all / passing lines per axis, for the headline
@@ -359,6 +387,7 @@ def main():
     results = {}
     sweep_result = None
     pc_result = None
+    jit_result = None
     storages = args.storages.split(",")
     bpv = {"f32": 4, "f16": 2, "u8": 1, "f32c": 4, "f16c": 2, "u8c": 1}
 
@@ -438,6 +467,7 @@ def main():
             sweep_result = brush_axis_sweep(raypc, torch, ctx, vid, wl, lod, stream)
         if si == 0:
             pc_result = pc_lines_timing(raypc, torch, W, ctx, vid, wl, stream)
+            jit_result = jittered_timing(raypc, torch, ctx, vid, wl, lod, stream)
         raypc.unload(ctx, vid)
 
     head = storages[0]
@@ -504,6 +534,7 @@ def main():
         "serving": serving_result,
         "brush_axis_sweep": sweep_result,
         "pc_lines": pc_result,
+        "jittered_passes": jit_result,
         "cpu_baseline": cpu_baseline,
     }
     raypc.destroy(ctx)

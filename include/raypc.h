@@ -202,6 +202,25 @@ int raypc_render(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int wid
 int raypc_render_progressive(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height,
                              int lod, float step, int n_passes, float *const *outs, void *stream);
 
+/* Jittered progressive pass (Section 2.2: while the camera does not move, further passes raise the
+ * samples per pixel and lower the noise).  Pass `pass` of `n_passes` (1..256) renders like
+ * raypc_render with every pixel's sample grid shifted along the ray: the samples of a shell
+ * segment [a, b] are the pieces of [a, b] cut at a - s ds + j ds (j integer), each evaluated at
+ * its midpoint with its own length in the opacity correction, where
+ *   s = min(fl32(fl32(pass + xi) / n_passes), 1 - 2^-24),  xi = (z >> 48) * 2^-16,
+ *   z = output number c + 1 of a SplitMix64 generator started at `seed`, for the counter
+ *       c = pass * 2^32 + (py * width + px)  (Steele, Lea and Flood, OOPSLA 2014),
+ * so each pass draws its offsets from its own stratum [pass, pass + 1) / n_passes.  s = 0 is the
+ * partition of raypc_render.  Outputs (device, H x W x 4 float32, any may be NULL but not both
+ * images): rgba_out = this pass; mean_inout = running mean of the passes, overwritten with this
+ * pass when pass == 0, else updated m <- m + (c - m) / (pass + 1), so after passes 0..k it is
+ * their mean.  nominal / composited: per-pixel sample counts as in raypc_render_debug (NULL: not
+ * counted).  Uses the volume's brush and transfer slot 0; lod -1 selects the level.  Async on
+ * `stream`.  Errors: as raypc_render, plus RAYPC_ERR_INVALID for pass / n_passes out of range. */
+int raypc_render_jittered(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height, int lod,
+                          float step, int pass, int n_passes, uint64_t seed, float *rgba_out, float *mean_inout,
+                          uint32_t *nominal, uint32_t *composited, void *stream);
+
 /* ---------------------------------------------------------------- debug exports
  * For parity tests and accounting.  All outputs are device buffers (async). */
 

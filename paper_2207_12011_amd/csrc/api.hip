@@ -595,6 +595,39 @@ int raypc_render_debug(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, i
                          true, (flags & 1) == 0, stream);
 }
 
+int raypc_render_jittered(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
+                          float step, int pass, int n_passes, uint64_t seed, float* rgba_out, float* mean_inout,
+                          uint32_t* nominal, uint32_t* composited, void* stream) {
+    if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
+    if (n_passes < 1 || n_passes > 256 || pass < 0 || pass >= n_passes)
+        return fail(RAYPC_ERR_INVALID, "need 0 <= pass (%d) < n_passes (%d) <= 256", pass, n_passes);
+    if (!rgba_out && !mean_inout) return fail(RAYPC_ERR_INVALID, "rgba_out and mean_inout are both NULL");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    RenderArgs a;
+    int storage = 0, level = 0;
+    // prepare_render checks rgba_out for NULL; the jittered pass may write only the running mean
+    float* out = rgba_out ? rgba_out : mean_inout;
+    int rc = prepare_render(ctx, volume_id, cam, width, height, lod, step, v->active, v->lo, v->hi, 0, out, true, s, a,
+                            storage, level, nullptr);
+    if (rc) return rc;
+    a.out = reinterpret_cast<float4*>(rgba_out);
+    a.nominal = nominal;
+    a.composited = composited;
+    a.touched = nullptr;
+    a.seed = seed;
+    a.pass = static_cast<uint32_t>(pass);
+    a.n_passes = static_cast<uint32_t>(n_passes);
+    a.inv_pass1 = 1.0f / static_cast<float>(pass + 1);
+    a.mean = reinterpret_cast<float4*>(mean_inout);
+    HIP_TRY(launch_render_jittered(a, storage, nominal != nullptr || composited != nullptr, s),
+            "jittered ray-march kernel launch");
+    return RAYPC_OK;
+}
+
 int raypc_render_progressive(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
                              float step, int n_passes, float* const* outs, void* stream) {
     if (!ctx || !outs) return fail(RAYPC_ERR_INVALID, "NULL argument");

@@ -143,8 +143,16 @@ struct RenderArgs {
     uint32_t* composited;
     uint32_t* touched;            // debug: bit per brick read by an evaluated sample (may be null)
     int blocks_x, n_blocks;       // 8 x 8 pixel blocks per row, total
+    // jittered progressive passes (jittered kernels only): pass `pass` of `n_passes` shifts each
+    // pixel's sample grid by s ds, s from a SplitMix64 stream at `seed`; `mean` (may be null)
+    // holds the running mean of the passes, updated with weight inv_pass1 = 1 / (pass + 1)
+    uint64_t seed;
+    uint32_t pass, n_passes;
+    float inv_pass1;
+    float4* mean;
 };
 hipError_t launch_render(const RenderArgs& a, int kind, bool counts, hipStream_t s);
+hipError_t launch_render_jittered(const RenderArgs& a, int kind, bool counts, hipStream_t s);
 // Work of one batched launch, passed by value in the kernel arguments: range r covers items
 // [end[r-1], end[r]) (end[-1] = 0), which march tiles first[r], first[r] + 1, ... of the request whose
 // arguments are descs[slot[r]].  Every descriptor's volume uses the launch's kernel kind.

@@ -263,9 +263,26 @@ __device__ __forceinline__ void interleaved_tile(int bid, int blocks_x, int& bx,
 // Number of brushed fields known only at run time (batched launches mix requests).
 constexpr int kRuntimeNB = -1;
 
+// Sample-grid offset s in [0, 1) of pixel p in a jittered pass: output number c + 1 of a SplitMix64
+// stream started at the seed (Steele, Lea and Flood, OOPSLA 2014: gamma 0x9E3779B97F4A7C15 and the
+// 30 / 27 / 31 xor-shift, multiply mix), for the counter c = pass 2^32 + p; its top 16 bits give
+// xi, and s = min(fl32(fl32(pass + xi) / n_passes), 1 - 2^-24) (stratified per pass).
+__device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) {
+    const uint64_t c = (static_cast<uint64_t>(A.pass) << 32) | p;
+    uint64_t z = A.seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const float xi = static_cast<float>(static_cast<uint32_t>(z >> 48)) * 0x1p-16f;
+    const float s = __fdiv_rn(__fadd_rn(static_cast<float>(A.pass), xi), static_cast<float>(A.n_passes));
+    return fminf(s, 0x1.fffffep-1f);
+}
+
 // One 8 x 8 pixel tile (index blk in row-major tile order) of the image described by A, marched by
 // the calling 256-thread block.  NB is the number of brushed fields, or kRuntimeNB to read it from A.
-template <int K, int NB, bool COUNTS>
+// JIT: a jittered progressive pass (the sample grid of every segment starts s ds before it, so the
+// first and last samples of a segment are partial).
+template <int K, int NB, bool COUNTS, bool JIT = false>
 __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, const float4* s_tf) {
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
@@ -332,7 +349,11 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     uint32_t last_brick = 0xFFFFFFFFu;
     int seg = 0, j0 = 0;  // j0: first sample of the quad's current group of four
     float sa = seg_a[0], sb = seg_b[0];
-    int ns = nseg > 0 ? max(static_cast<int>(ceilf((sb - sa) / ds)), 1) : 0;
+    // grid origin of the current segment: sample j covers [max(sa, g + j ds), min(g + (j+1) ds, sb)]
+    float s_jit = 0.0f;
+    if constexpr (JIT) s_jit = jitter_offset(A, static_cast<uint32_t>(py) * A.width + px);
+    float g = JIT ? fmaf(-s_jit, ds, sa) : sa;
+    int ns = nseg > 0 ? max(static_cast<int>(ceilf((sb - g) / ds)), 1) : 0;
     bool alive = nseg > 0;
 
     while (alive) {
@@ -343,9 +364,21 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
         int jn = j + 1;
 
         if (valid) {
-            const float tlo = fmaf(static_cast<float>(j), ds, sa);
             const bool last = j == ns - 1;
-            const float tm = last ? 0.5f * (tlo + sb) : fmaf(static_cast<float>(j) + 0.5f, ds, sa);
+            float tlo, tm, len_partial = 0.0f;
+            bool partial = last;
+            if constexpr (JIT) {
+                const bool first = j == 0;
+                partial = first || last;
+                tlo = first ? sa : fmaf(static_cast<float>(j), ds, g);
+                const float thi = last ? sb : fmaf(static_cast<float>(j) + 1.0f, ds, g);
+                tm = partial ? 0.5f * (tlo + thi) : fmaf(static_cast<float>(j) + 0.5f, ds, g);
+                len_partial = fmaxf(thi - tlo, 0.0f);
+            } else {
+                tlo = fmaf(static_cast<float>(j), ds, sa);
+                tm = last ? 0.5f * (tlo + sb) : fmaf(static_cast<float>(j) + 0.5f, ds, sa);
+                len_partial = fmaxf(sb - tlo, 0.0f);
+            }
             const float ux = fmaf(dux, tm, uox), uy = fmaf(duy, tm, uoy), uz = fmaf(duz, tm, uoz);
             const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
             const int ix = static_cast<int>(flx), iy = static_cast<int>(fly), iz = static_cast<int>(flz);
@@ -375,7 +408,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                 const float t_exit = fminf(axis_exit(uox, dux, inv_dux, lx, hx),
                                            fminf(axis_exit(uoy, duy, inv_duy, ly, hy),
                                                  axis_exit(uoz, duz, inv_duz, lz, hz)));
-                float jc = (t_exit - sa) * inv_ds - 0.5f - kSkipMargin;
+                float jc = (t_exit - g) * inv_ds - 0.5f - kSkipMargin;
                 jc = fminf(fmaxf(jc, 0.0f), static_cast<float>(ns));
                 jn = max(j + 1, static_cast<int>(ceilf(jc)));
             } else {
@@ -435,7 +468,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                     const float al = fmaf(wt, e1.w - e0.w, e0.w);
                     if (al > 0.0f) {
                         contributes = true;
-                        const float r = last ? fmaxf(sb - tlo, 0.0f) * A.inv_ref : r_full;
+                        const float r = partial ? len_partial * A.inv_ref : r_full;
                         keep = al >= 1.0f ? 0.0f : __builtin_amdgcn_exp2f(r * __log2f(1.0f - al));
                         cr = fmaf(wt, e1.x - e0.x, e0.x);
                         cg = fmaf(wt, e1.y - e0.y, e0.y);
@@ -458,7 +491,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                     seg = 1;
                     sa = seg_a[1];
                     sb = seg_b[1];
-                    ns = max(static_cast<int>(ceilf((sb - sa) / ds)), 1);
+                    g = JIT ? fmaf(-s_jit, ds, sa) : sa;
+                    ns = max(static_cast<int>(ceilf((sb - g) / ds)), 1);
                     j0 = 0;
                 } else {
                     alive = false;
@@ -525,7 +559,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                     seg = 1;
                     sa = seg_a[1];
                     sb = seg_b[1];
-                    ns = max(static_cast<int>(ceilf((sb - sa) / ds)), 1);
+                    g = JIT ? fmaf(-s_jit, ds, sa) : sa;
+                    ns = max(static_cast<int>(ceilf((sb - g) / ds)), 1);
                     j0 = 0;
                 } else {
                     alive = false;
@@ -545,14 +580,28 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     const size_t pix = static_cast<size_t>(py) * A.width + px;
     f32x4 o4;
     o4.x = res.x, o4.y = res.y, o4.z = res.z, o4.w = res.w;
-    reinterpret_cast<__attribute__((address_space(1))) f32x4*>(reinterpret_cast<uintptr_t>(A.out))[pix] = o4;
+    if (!JIT || A.out != nullptr)
+        reinterpret_cast<__attribute__((address_space(1))) f32x4*>(reinterpret_cast<uintptr_t>(A.out))[pix] = o4;
+    if constexpr (JIT) {
+        if (A.mean != nullptr) {
+            // running mean over the passes: m <- m + (c - m) / (pass + 1), exactly c on pass 0
+            auto* m = reinterpret_cast<__attribute__((address_space(1))) f32x4*>(reinterpret_cast<uintptr_t>(A.mean));
+            f32x4 prev = A.pass == 0 ? o4 : m[pix];
+            f32x4 nm;
+            nm.x = fmaf(o4.x - prev.x, A.inv_pass1, prev.x);
+            nm.y = fmaf(o4.y - prev.y, A.inv_pass1, prev.y);
+            nm.z = fmaf(o4.z - prev.z, A.inv_pass1, prev.z);
+            nm.w = fmaf(o4.w - prev.w, A.inv_pass1, prev.w);
+            m[pix] = nm;
+        }
+    }
     if constexpr (COUNTS) {
         if (A.nominal) A.nominal[pix] = cnt_nom;
         if (A.composited) A.composited[pix] = cnt_comp;
     }
 }
 
-template <int K, int NB, bool COUNTS>
+template <int K, int NB, bool COUNTS, bool JIT = false>
 __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     int bx, by;
     interleaved_tile(blockIdx.x, A.blocks_x, bx, by);
@@ -563,7 +612,7 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
         s_tf[threadIdx.x] = make_float4(e.x, e.y, e.z, e.w);
     }
     __syncthreads();
-    march_tile<K, NB, COUNTS>(A, bx, by, s_tf);
+    march_tile<K, NB, COUNTS, JIT>(A, bx, by, s_tf);
 }
 
 // Batched launch: item j marches one tile of one request, as the ranges in the kernel arguments
@@ -635,6 +684,30 @@ hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& R, in
         default: hipLaunchKernelGGL(raymarch_batch_kernel<kKindU8Rec>, grid, block, 0, s, descs, R); break;
     }
     return hipGetLastError();
+}
+
+namespace {
+template <int K, bool COUNTS>
+hipError_t launch_jit(const RenderArgs& a, hipStream_t s) {
+    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x)), block(256);
+    hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, COUNTS, true>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+template <bool COUNTS>
+hipError_t launch_jit_kind(const RenderArgs& a, int kind, hipStream_t s) {
+    switch (kind) {
+        case kKindF32: return launch_jit<kKindF32, COUNTS>(a, s);
+        case kKindF16: return launch_jit<kKindF16, COUNTS>(a, s);
+        case kKindU8: return launch_jit<kKindU8, COUNTS>(a, s);
+        case kKindF32Rec: return launch_jit<kKindF32Rec, COUNTS>(a, s);
+        case kKindF16Rec: return launch_jit<kKindF16Rec, COUNTS>(a, s);
+        default: return launch_jit<kKindU8Rec, COUNTS>(a, s);
+    }
+}
+}  // namespace
+
+hipError_t launch_render_jittered(const RenderArgs& a, int kind, bool counts, hipStream_t s) {
+    return counts ? launch_jit_kind<true>(a, kind, s) : launch_jit_kind<false>(a, kind, s);
 }
 
 hipError_t launch_render(const RenderArgs& a, int kind, bool counts, hipStream_t s) {

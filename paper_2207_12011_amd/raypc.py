@@ -81,6 +81,8 @@ _export_level = _sig("raypc_export_level", _I, _P, _I, _I, _I, _P, _P)
 _export_minmax = _sig("raypc_export_minmax", _I, _P, _I, _I, _I, _P, _P)
 _export_minmax_sub = _sig("raypc_export_minmax_sub", _I, _P, _I, _I, _I, _P, _P)
 _pc_lines = _sig("raypc_pc_lines", _I, _P, _I, _I, _I, _P, _P, _P, _I, _P, _P, _P, _P)
+_render_jittered = _sig("raypc_render_jittered", _I, _P, _I, _P, _I, _I, _I, ctypes.c_float, _I, _I,
+                        ctypes.c_uint64, _P, _P, _P, _P, _P)
 _export_skip = _sig("raypc_export_skiplist", _I, _P, _I, _I, _I, _P, _P)
 _export_subskip = _sig("raypc_export_subskip", _I, _P, _I, _I, _I, _P, _P)
 _export_mask = _sig("raypc_export_voxel_mask", _I, _P, _I, _I, _P, _P)
@@ -122,7 +124,8 @@ EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_po
             "raypc_unload", "raypc_volume_info", "raypc_set_brush", "raypc_set_transfer_function",
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
             "raypc_export_level", "raypc_export_minmax", "raypc_export_minmax_sub", "raypc_export_skiplist",
-            "raypc_export_subskip", "raypc_export_voxel_mask", "raypc_render_debug", "raypc_pc_lines"]
+            "raypc_export_subskip", "raypc_export_voxel_mask", "raypc_render_debug", "raypc_pc_lines",
+            "raypc_render_jittered"]
 
 
 class RaypcError(RuntimeError):
@@ -281,6 +284,25 @@ def render_debug(ctx, volume_id: int, camera, width: int, height: int, lod: int 
     _check(_render_debug(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height), int(lod),
                          float(step), out.data_ptr(), nom.data_ptr(), comp.data_ptr(), tptr, 0 if skip else 1,
                          _stream(stream)))
+    return out, nom, comp
+
+
+def render_jittered(ctx, volume_id: int, camera, width: int, height: int, lod: int, step: float, pass_index: int,
+                    n_passes: int, seed: int, mean: Optional[torch.Tensor] = None, counts: bool = False,
+                    stream=None):
+    """One jittered progressive pass: (rgba [H,W,4] f32, nominal, composited) as CUDA tensors (the
+    counts are None unless `counts`).  `mean`, if given, is an [H,W,4] float32 CUDA tensor holding
+    the running mean of the passes (overwritten on pass 0)."""
+    out = torch.empty((height, width, 4), dtype=torch.float32, device="cuda")
+    nom = comp = None
+    if counts:
+        nom = torch.empty((height, width), dtype=torch.int32, device="cuda")
+        comp = torch.empty((height, width), dtype=torch.int32, device="cuda")
+    mptr = None if mean is None else _dptr(mean, torch.float32, height * width * 4, "mean")
+    _check(_render_jittered(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height), int(lod),
+                            float(step), int(pass_index), int(n_passes), int(seed) & ((1 << 64) - 1),
+                            out.data_ptr(), mptr, None if nom is None else nom.data_ptr(),
+                            None if comp is None else comp.data_ptr(), _stream(stream)))
     return out, nom, comp
 
 
