@@ -42,7 +42,7 @@ def lib():
         L.oracle_render.restype = ctypes.c_int
         L.oracle_render.argtypes = [
             ctypes.c_int, ctypes.c_int, P, ctypes.c_double, ctypes.c_double,
-            P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, ctypes.c_double,
+            P, P, P, P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, ctypes.c_double,
             ctypes.c_double, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_long,
             P, P, P, P, P, P, P, ctypes.c_int]
         L.oracle_trilinear.restype = None
@@ -69,9 +69,10 @@ def render(level_fields: np.ndarray, camera, width: int, height: int, step: floa
            ref_step: float = 2.0 / 256, ert: float = 0.99, bg=None,
            r_inner: float = 0.55, r_outer: float = 1.0,
            pixels: Optional[np.ndarray] = None, threads: Optional[int] = None,
-           jitter: Optional[np.ndarray] = None) -> OracleImage:
+           jitter: Optional[np.ndarray] = None, coord=None) -> OracleImage:
     """Render `pixels` (linear indices py*W+px; None = full frame) of one level.  `jitter` gives
     each rendered pixel's sample-grid offset in [0, 1) steps (None: the regular partition).
+    `coord` = (active[4], lo[4], hi[4]) restricts the sample position (world x, y, z, radius).
 
     `level_fields` holds the level's stored values as float32 [F, N, N, N];
     scalars and tables are taken at float32 boundary precision and widened
@@ -90,6 +91,11 @@ def render(level_fields: np.ndarray, camera, width: int, height: int, step: floa
     pix = None if full else np.ascontiguousarray(np.asarray(pixels, np.int64))
     npix = width * height if full else pix.size
     jit = None if jitter is None else np.ascontiguousarray(np.asarray(jitter, np.float64).reshape(npix))
+    cact = clo = chi = None
+    if coord is not None:
+        cact = np.ascontiguousarray(np.asarray(coord[0], np.uint8).reshape(4))
+        clo = np.asarray(np.asarray(coord[1], np.float32).reshape(4), np.float64)
+        chi = np.asarray(np.asarray(coord[2], np.float32).reshape(4), np.float64)
     rgba = np.zeros((npix, 4))
     nom = np.zeros(npix, np.uint32)
     comp = np.zeros(npix, np.uint32)
@@ -98,7 +104,7 @@ def render(level_fields: np.ndarray, camera, width: int, height: int, step: floa
     threads = threads or os.cpu_count() or 1
     rc = lib().oracle_render(
         nf, n, ctypes.cast(ptrs, ctypes.c_void_p), float(np.float32(r_inner)), float(np.float32(r_outer)),
-        _ptr(act), _ptr(lo64), _ptr(hi64), int(tf_field), float(np.float32(vmin)), float(np.float32(vmax)),
+        _ptr(act), _ptr(lo64), _ptr(hi64), _ptr(cact), _ptr(clo), _ptr(chi), int(tf_field), float(np.float32(vmin)), float(np.float32(vmax)),
         _ptr(tf64), float(np.float32(ref_step)), float(np.float32(ert)), _ptr(bg64), _ptr(cam),
         int(width), int(height), float(np.float32(step)), int(npix), _ptr(pix), _ptr(jit),
         _ptr(rgba), _ptr(nom), _ptr(comp), _ptr(frag), _ptr(plen), int(threads))

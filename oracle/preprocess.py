@@ -219,11 +219,38 @@ def pc_bin(v, axis_lo: float, axis_hi: float, n_bins: int) -> np.ndarray:
     return np.clip(np.floor(x), 0, n_bins - 1).astype(np.int64)
 
 
-def pc_lines(level_fields: np.ndarray, cells, active, lo, hi, axis_lo, axis_hi, n_bins: int):
+def cell_coord(i, n: int) -> np.ndarray:
+    """World coordinate of cell index i on an N-cell axis, in float32: fl32(fl32(2 i + 1) / N) - 1."""
+    return ((np.asarray(2 * np.asarray(i, np.int64) + 1).astype(F32) / F32(n)).astype(F32) - F32(1.0)).astype(F32)
+
+
+def coord_pass(x, y, z, coord) -> np.ndarray:
+    """The coordinate axes of the brush at positions (float32 arrays): axes 0..2 need
+    lo <= x, y, z <= hi; axis 3 (radius) needs lo <= r <= hi, decided on squares in float32:
+    r2 = fl32(fl32(fl32(x x) + fl32(y y)) + fl32(z z)) >= fl32(lo lo) (when lo > 0) and
+    r2 <= fl32(hi hi) (when hi >= 0; nothing passes when hi < 0)."""
+    act, lo, hi = coord
+    keep = np.ones(np.broadcast_shapes(np.shape(x), np.shape(y), np.shape(z)), bool)
+    for ax, v in enumerate((x, y, z)):
+        if act[ax]:
+            keep &= (v >= F32(lo[ax])) & (v <= F32(hi[ax]))
+    if act[3]:
+        x, y, z = (np.asarray(a, F32) for a in (x, y, z))
+        r2 = ((x * x).astype(F32) + (y * y).astype(F32)).astype(F32)
+        r2 = (r2 + (z * z).astype(F32)).astype(F32)
+        l3, h3 = F32(lo[3]), F32(hi[3])
+        if l3 > 0:
+            keep &= r2 >= F32(l3 * l3)
+        keep &= (r2 <= F32(h3 * h3)) if h3 >= 0 else np.zeros(keep.shape, bool)
+    return keep
+
+
+def pc_lines(level_fields: np.ndarray, cells, active, lo, hi, axis_lo, axis_hi, n_bins: int, coord=None):
     """Parallel-coordinates lines (paper, Section 2.1: up to 100 000 randomly chosen cells give the
     lines of the plot; Section 2: the brush selects the subset that is shown).  For cell indices
     z N^2 + y N + x of one level: the stored value of every field (the line's coordinates), whether
-    the line passes the brush (every active field inside its inclusive [lo, hi]), and per field a
+    the line passes the brush (every active field inside its inclusive [lo, hi], and the cell centre
+    inside the coordinate axes of ``coord`` = (active[4], lo[4], hi[4]), see coord_pass), and per field a
     histogram over ``n_bins`` bins of [axis_lo, axis_hi] (pc_bin) of all lines and of passing lines.
     Returns (values float32 [L, F], passes uint8 [L], hist uint32 [F, n_bins, 2])."""
     lf = np.asarray(level_fields, F32)
@@ -235,6 +262,8 @@ def pc_lines(level_fields: np.ndarray, cells, active, lo, hi, axis_lo, axis_hi, 
     for f in range(nf):
         if active[f]:
             keep &= (values[:, f] >= F32(lo[f])) & (values[:, f] <= F32(hi[f]))
+    if coord is not None:
+        keep &= coord_pass(cell_coord(x, n), cell_coord(y, n), cell_coord(z, n), coord)
     hist = np.zeros((nf, n_bins, 2), np.uint32)
     for f in range(nf):
         b = pc_bin(values[:, f], axis_lo[f], axis_hi[f], n_bins)
@@ -243,12 +272,17 @@ def pc_lines(level_fields: np.ndarray, cells, active, lo, hi, axis_lo, axis_hi, 
     return values, keep.astype(np.uint8), hist
 
 
-def voxel_mask(level_fields: np.ndarray, active, lo, hi) -> np.ndarray:
-    """uint8 [N]^3: 1 where every active field lies in its inclusive [lo, hi]."""
+def voxel_mask(level_fields: np.ndarray, active, lo, hi, coord=None) -> np.ndarray:
+    """uint8 [N]^3: 1 where every active field lies in its inclusive [lo, hi] and the cell centre
+    passes the coordinate axes of ``coord`` (see coord_pass)."""
     m = np.ones(level_fields.shape[1:], bool)
     for f in range(level_fields.shape[0]):
         if active[f]:
             m &= (level_fields[f] >= F32(lo[f])) & (level_fields[f] <= F32(hi[f]))
+    if coord is not None and any(coord[0]):
+        n = level_fields.shape[1]
+        c = cell_coord(np.arange(n), n)
+        m &= coord_pass(c[None, None, :], c[None, :, None], c[:, None, None], coord)
     return m.astype(np.uint8)
 
 

@@ -29,7 +29,8 @@
  * naming decisions that sit within floating-point reach of a threshold:
  *   bit 0  a brush comparison within delta_b of its bound that could flip the
  *          sample's outcome (delta_b grows with the segment's grazing reach,
- *          below),
+ *          below; for a coordinate axis delta_b = 1e-5 plus that reach, in world
+ *          units),
  *   bit 1  accumulated opacity within 1e-4 of the termination threshold,
  *   bit 2  a ray grazing the inner or outer sphere (|discriminant| <= 1e-5),
  *   bit 3  a segment length within 1e-5 (world units) plus the grazing reach
@@ -60,6 +61,8 @@ typedef struct {
     double r_inner, r_outer;
     const uint8_t *active;
     const double *lo, *hi;
+    const uint8_t *coord_active; /* 4 or NULL: brush on the sample position x, y, z and radius */
+    const double *coord_lo, *coord_hi;
     int tf_field;
     double vmin, vmax, ref_step;
     const double *tf; /* 256 x 4 straight RGBA */
@@ -263,6 +266,27 @@ static void render_pixel(const oracle_params *P, int px, int py, double jit, pix
                 else if (!ok)
                     robust_fail = 1;
             }
+            if (P->coord_active) {
+                /* coordinate axes: the sample position (world x, y, z) and its radius */
+                double p[3], pr = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    p[k] = o[k] + d[k] * tm;
+                    pr += p[k] * p[k];
+                }
+                pr = sqrt(pr);
+                const double dc = 1e-5 + pos_reach * h;
+                for (int ax = 0; ax < 4; ++ax) {
+                    if (!P->coord_active[ax]) continue;
+                    const double v = ax < 3 ? p[ax] : pr;
+                    int ok = (v >= P->coord_lo[ax]) && (v <= P->coord_hi[ax]);
+                    if (!ok) pass = 0;
+                    int near_c = (fabs(v - P->coord_lo[ax]) <= dc) || (fabs(v - P->coord_hi[ax]) <= dc);
+                    if (near_c)
+                        near = 1;
+                    else if (!ok)
+                        robust_fail = 1;
+                }
+            }
             if (near && !robust_fail) res->fragile |= 1;
             if (!pass) continue; /* discarded: counted, not composited */
 
@@ -313,13 +337,16 @@ static void render_pixel(const oracle_params *P, int px, int py, double jit, pix
  * oracle_render: render the listed pixels (linear index py*width + px; NULL
  * means every pixel in row-major order).  `fields` are the level's stored
  * values already converted to float32 ([z][y][x], n^3 each).  Camera is
- * {eye[3], target[3], up[3], fov_y_deg}.  `bg` may be NULL.  `jitter` holds
+ * {eye[3], target[3], up[3], fov_y_deg}.  `coord_active` (4 flags or NULL) with
+ * `coord_lo` / `coord_hi` restricts the sample position: axes 0..2 its world x, y,
+ * z, axis 3 its radius.  `bg` may be NULL.  `jitter` holds
  * one sample-grid offset in [0, 1) per requested pixel (NULL: 0, the regular
  * partition).  Any output pointer may be NULL.  Returns 0, or -1 on invalid
  * arguments.
  */
 int oracle_render(int n_fields, int n, const float *const *fields, double r_inner, double r_outer,
-                  const uint8_t *active, const double *lo, const double *hi, int tf_field, double vmin,
+                  const uint8_t *active, const double *lo, const double *hi, const uint8_t *coord_active,
+                  const double *coord_lo, const double *coord_hi, int tf_field, double vmin,
                   double vmax, const double *tf_rgba, double ref_step, double ert, const double *bg,
                   const double *camera, int width, int height, double step_vox, long n_pix,
                   const int64_t *pix, const double *jitter, double *rgba, uint32_t *nominal,
@@ -345,6 +372,9 @@ int oracle_render(int n_fields, int n, const float *const *fields, double r_inne
     P.active = active;
     P.lo = lo;
     P.hi = hi;
+    P.coord_active = coord_active;
+    P.coord_lo = coord_lo;
+    P.coord_hi = coord_hi;
     P.tf_field = tf_field;
     P.vmin = vmin;
     P.vmax = vmax;

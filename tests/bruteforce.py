@@ -58,7 +58,7 @@ def segments(o, d, r_inner, r_outer):
 
 
 def render(level_fields, cam, width, height, step, *, active, lo, hi, tf_field, vmin, vmax,
-           tf_rgba, ref_step=2 / 256, ert=0.99, r_inner=0.55, r_outer=1.0):
+           tf_rgba, ref_step=2 / 256, ert=0.99, r_inner=0.55, r_outer=1.0, coord=None):
     f64 = lambda x: float(np.float32(x))
     lf = np.asarray(level_fields, np.float32).astype(np.float64)
     nf, n = lf.shape[0], lf.shape[1]
@@ -96,6 +96,11 @@ def render(level_fields, cam, width, height, step, *, active, lo, hi, tf_field, 
             for f in range(nf):
                 if active[f]:
                     keep &= (vals[f] >= lo[f]) & (vals[f] <= hi[f])
+            if coord is not None:
+                cvals = [pos[:, 0], pos[:, 1], pos[:, 2], np.linalg.norm(pos, axis=1)]
+                for ax in range(4):
+                    if coord[0][ax]:
+                        keep &= (cvals[ax] >= f64(coord[1][ax])) & (cvals[ax] <= f64(coord[2][ax]))
             x = np.clip((vals[tf_field] - vmin) / (vmax - vmin), 0.0, 1.0) * 255.0
             i = np.minimum(np.floor(x).astype(np.int64), 254)
             w = (x - i)[:, None]

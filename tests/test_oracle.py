@@ -286,6 +286,47 @@ def test_sample_count_definition():
             assert o.nominal[py, px] == want
 
 
+# ----------------------------------------------------------------------------- coordinate axes
+@pytest.mark.parametrize("coord", [([1, 0, 0, 0], [0.0, 0, 0, 0], [1.0, 0, 0, 0]),
+                                   ([0, 1, 1, 0], [0, -0.4, -1.0, 0], [0, 0.3, 0.2, 0]),
+                                   ([0, 0, 0, 1], [0, 0, 0, 0.7], [0, 0, 0, 0.85]),
+                                   ([1, 0, 0, 1], [-0.2, 0, 0, 0.6], [0.5, 0, 0, 2.0])])
+def test_bruteforce_agrees_coordinate_brush(tiny, coord):
+    """Cuts by the sample position (x, y, z) and by its radius, alone and with the field brush,
+    agree with the independent numpy caster."""
+    wl = tiny
+    kw = dict(active=wl.brush.active, lo=wl.brush.lo, hi=wl.brush.hi, tf_field=wl.tf.field, vmin=wl.tf.vmin,
+              vmax=wl.tf.vmax, tf_rgba=wl.tf.rgba, ert=wl.ert)
+    cam = wl.camera.as_array()
+    o = oracle.render(wl.fields, cam, wl.width, wl.height, wl.step, coord=coord, **kw)
+    rgba, nom, comp = bf.render(wl.fields, cam, wl.width, wl.height, wl.step, coord=coord, **kw)
+    assert np.abs(o.rgba - rgba).max() <= 1e-12
+    assert np.array_equal(o.nominal, nom) and np.array_equal(o.composited, comp)
+    plain = oracle.render(wl.fields, cam, wl.width, wl.height, wl.step, **kw)
+    assert o.composited.sum() < plain.composited.sum()
+
+
+def test_coordinate_axes_on_cells():
+    """Cell centres (2 i + 1) / N - 1: the cut x >= 0 keeps exactly the upper half of an even grid;
+    a radius band keeps the cells whose centre radius lies in it (exact away from the bounds); the
+    lines of the parallel coordinates follow the voxel mask."""
+    n = 16
+    vol = np.ones((1, n, n, n), np.float32)
+    half = pp.voxel_mask(vol, [0], [0], [0], coord=([1, 0, 0, 0], [0.0, 0, 0, 0], [1.0, 0, 0, 0]))
+    assert np.all(half[:, :, n // 2:] == 1) and np.all(half[:, :, :n // 2] == 0)
+    band = pp.voxel_mask(vol, [0], [0], [0], coord=([0, 0, 0, 1], [0, 0, 0, 0.5], [0, 0, 0, 0.8]))
+    c = (2 * np.arange(n) + 1) / n - 1.0
+    r = np.sqrt(c[None, None, :] ** 2 + c[None, :, None] ** 2 + c[:, None, None] ** 2)
+    far = (np.abs(r - 0.5) > 1e-5) & (np.abs(r - 0.8) > 1e-5)
+    assert np.array_equal(band.astype(bool)[far], ((r >= 0.5) & (r <= 0.8))[far])
+    none = pp.voxel_mask(vol, [0], [0], [0], coord=([0, 0, 0, 1], [0, 0, 0, 0.0], [0, 0, 0, -0.1]))
+    assert not none.any()
+    cells = np.arange(0, n ** 3, 7)
+    coord = ([1, 0, 1, 1], [-0.5, 0, -1, 0.3], [0.6, 0, 0.2, 0.9])
+    _, passes, _ = pp.pc_lines(vol, cells, [0], [0], [0], [0.0], [2.0], 4, coord=coord)
+    assert np.array_equal(passes, pp.voxel_mask(vol, [0], [0], [0], coord=coord).reshape(-1)[cells])
+
+
 # ----------------------------------------------------------------------------- jittered passes
 def test_splitmix64_reference_outputs():
     """First outputs of SplitMix64 from state 0, as listed with the generator's reference
