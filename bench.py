@@ -121,7 +121,17 @@ def brush_axis_sweep(raypc, torch, ctx, vid, wl, lod, stream, frames=30):
         res[mode] = {"k": ks, "ms": ms, "slope_ms_per_field": float(slope), "intercept_ms": float(icpt),
                      "r2": 1.0 - ss_res / ss_tot if ss_tot > 0 else 1.0}
         print(f"[bench] brush-axis sweep ({mode}): {res[mode]}", file=sys.stderr, flush=True)
+    # coordinate axes with the headline brush: a half-space cut and a radius (altitude) band
     raypc.set_brush(ctx, vid, wl.brush.active, wl.brush.lo, wl.brush.hi)
+    cuts = {"none": ([0, 0, 0, 0], [0] * 4, [0] * 4),
+            "x >= 0": ([1, 0, 0, 0], [0.0, 0, 0, 0], [1.0, 0, 0, 0]),
+            "0.7 <= r <= 0.85": ([0, 0, 0, 1], [0, 0, 0, 0.7], [0, 0, 0, 0.85])}
+    res["coordinate_cuts_ms"] = {}
+    for name, c in cuts.items():
+        raypc.set_coordinate_brush(ctx, vid, *c)
+        res["coordinate_cuts_ms"][name] = frame_ms()
+    raypc.set_coordinate_brush(ctx, vid, *cuts["none"])
+    print(f"[bench] coordinate cuts (ms): {res['coordinate_cuts_ms']}", file=sys.stderr, flush=True)
     return res
 
 

@@ -158,6 +158,19 @@ int raypc_set_brush(raypc_ctx *ctx, int volume_id, int n_fields, const uint8_t *
  * Waits for the device before replacing a table that kernels may read.
  * Errors: RAYPC_ERR_INVALID.
  */
+/* Coordinate axes of the brush (Section 2.1 derives the altitude from the position; the paper's
+ * appendix cuts the volume by Cartesian coordinates on the same plot).  Axes 0, 1, 2 are the world
+ * x, y, z of a sample's position (the volume spans [-1, 1]^3), axis 3 is its radius |p|.
+ * active[a] enables axis a with the inclusive bounds [lo[a], hi[a]] (world units); a sample whose
+ * position falls outside an enabled axis is discarded exactly like a sample failing a field bound
+ * (and is not fetched).  The radius test is made on float32 squares: r^2 >= lo^2 when lo > 0,
+ * r^2 <= hi^2 when hi >= 0, nothing passes when hi < 0.  For cells (raypc_pc_lines,
+ * raypc_export_voxel_mask) the position is the cell centre fl32(fl32(2 i + 1) / N) - 1 per axis.
+ * Arrays of 4, copied; NaN bounds: RAYPC_ERR_INVALID with the state unchanged.  Default: no axis
+ * enabled. */
+int raypc_set_coordinate_brush(raypc_ctx *ctx, int volume_id, const uint8_t *active, const float *lo,
+                               const float *hi);
+
 int raypc_set_transfer_function(raypc_ctx *ctx, int slot, int field, float vmin, float vmax, const float *rgba,
                                 int n_entries, float ref_step);
 
@@ -319,6 +332,8 @@ typedef struct {
     uint8_t active[RAYPC_MAX_FIELDS]; /* the request's brush, as in raypc_set_brush; entries beyond */
     float lo[RAYPC_MAX_FIELDS];       /* the volume's field count are ignored */
     float hi[RAYPC_MAX_FIELDS];
+    uint8_t coord_active[4];          /* the request's coordinate axes, as in */
+    float coord_lo[4], coord_hi[4];   /* raypc_set_coordinate_brush */
     int tf_slot;                      /* defined transfer-function slot */
     float *out;                       /* device, height*width*4 float32, 16-byte aligned, caller-owned,
                                          valid until the request is done */

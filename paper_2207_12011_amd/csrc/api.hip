@@ -224,10 +224,23 @@ static int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s
     return RAYPC_OK;
 }
 
+uint32_t coord_kernel_form(const CoordBrush& c, float clo[4], float chi[4]) {
+    uint32_t mask = 0;
+    for (int ax = 0; ax < 4; ++ax) {
+        clo[ax] = c.lo[ax];
+        chi[ax] = c.hi[ax];
+        if (c.active[ax]) mask |= 1u << ax;
+    }
+    // radius: compared on squares, r^2 >= lo^2 (lo > 0) and r^2 <= hi^2 (hi >= 0; nothing when hi < 0)
+    clo[3] = c.lo[3] > 0.0f ? c.lo[3] * c.lo[3] : -INFINITY;
+    chi[3] = c.hi[3] >= 0.0f ? c.hi[3] * c.hi[3] : -1.0f;
+    return mask;
+}
+
 int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
                    float step, const uint8_t* brush_active, const float* brush_lo, const float* brush_hi,
-                   int tf_slot, float* rgba_out, bool use_volume_state, hipStream_t s, RenderArgs& a, int& storage,
-                   int& level, Volume** vol_out) {
+                   const CoordBrush& coord, int tf_slot, float* rgba_out, bool use_volume_state, hipStream_t s,
+                   RenderArgs& a, int& storage, int& level, Volume** vol_out) {
     Volume* v = find_volume(ctx, volume_id);
     if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
     if (width < 1 || width > 16384 || height < 1 || height > 16384)
@@ -243,7 +256,11 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
     for (int f = 0; f < v->nf; ++f)
         if (brush_active[f] && (std::isnan(brush_lo[f]) || std::isnan(brush_hi[f])))
             return fail(RAYPC_ERR_INVALID, "NaN bound for field %d", f);
+    for (int ax = 0; ax < 4; ++ax)
+        if (coord.active[ax] && (std::isnan(coord.lo[ax]) || std::isnan(coord.hi[ax])))
+            return fail(RAYPC_ERR_INVALID, "NaN bound for coordinate axis %d", ax);
     std::memset(&a, 0, sizeof(a));
+    a.coord_mask = coord_kernel_form(coord, a.clo, a.chi);
     int rc = camera_setup(cam, width, height, a);
     if (rc) return rc;
     if (lod == -1) select_lod_impl(v, cam, height, &lod);
@@ -507,6 +524,22 @@ int raypc_set_brush(raypc_ctx* ctx, int volume_id, int n_fields, const uint8_t* 
     return RAYPC_OK;
 }
 
+int raypc_set_coordinate_brush(raypc_ctx* ctx, int volume_id, const uint8_t* active, const float* lo, const float* hi) {
+    if (!ctx || !active || !lo || !hi) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    for (int ax = 0; ax < 4; ++ax)
+        if (std::isnan(lo[ax]) || std::isnan(hi[ax])) return fail(RAYPC_ERR_INVALID, "NaN bound for axis %d", ax);
+    for (int ax = 0; ax < 4; ++ax) {
+        v->coord.active[ax] = active[ax] ? 1 : 0;
+        v->coord.lo[ax] = lo[ax];
+        v->coord.hi[ax] = hi[ax];
+    }
+    ++v->brush_gen;
+    return RAYPC_OK;
+}
+
 int raypc_set_transfer_function(raypc_ctx* ctx, int slot, int field, float vmin, float vmax, const float* rgba,
                                 int n_entries, float ref_step) {
     if (!ctx || !rgba) return fail(RAYPC_ERR_INVALID, "NULL argument");
@@ -571,7 +604,7 @@ static int render_common(raypc_ctx* ctx, int volume_id, const raypc_camera* cam,
     if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
     RenderArgs a;
     int storage = 0, level = 0;
-    int rc = prepare_render(ctx, volume_id, cam, width, height, lod, step, v->active, v->lo, v->hi, 0, rgba_out,
+    int rc = prepare_render(ctx, volume_id, cam, width, height, lod, step, v->active, v->lo, v->hi, v->coord, 0, rgba_out,
                             true, s, a, storage, level, nullptr);
     if (rc) return rc;
     if (!use_skip) a.skip = nullptr;
@@ -611,7 +644,7 @@ int raypc_render_jittered(raypc_ctx* ctx, int volume_id, const raypc_camera* cam
     int storage = 0, level = 0;
     // prepare_render checks rgba_out for NULL; the jittered pass may write only the running mean
     float* out = rgba_out ? rgba_out : mean_inout;
-    int rc = prepare_render(ctx, volume_id, cam, width, height, lod, step, v->active, v->lo, v->hi, 0, out, true, s, a,
+    int rc = prepare_render(ctx, volume_id, cam, width, height, lod, step, v->active, v->lo, v->hi, v->coord, 0, out, true, s, a,
                             storage, level, nullptr);
     if (rc) return rc;
     a.out = reinterpret_cast<float4*>(rgba_out);
@@ -762,6 +795,7 @@ int raypc_pc_lines(raypc_ctx* ctx, int volume_id, int lod, int n_lines, const ui
     }
     a.n_fields = v->nf;
     a.storage = v->storage;
+    a.coord_mask = coord_kernel_form(v->coord, a.clo, a.chi);
     a.n = L.n;
     a.nb = L.nb;
     a.n_bins = n_bins;
@@ -794,6 +828,7 @@ int raypc_export_voxel_mask(raypc_ctx* ctx, int volume_id, int lod, uint8_t* out
         ++k;
     }
     a.n_active = k;
+    a.coord_mask = coord_kernel_form(v->coord, a.clo, a.chi);
     a.n = L.n;
     a.nb = L.nb;
     a.storage = v->storage;

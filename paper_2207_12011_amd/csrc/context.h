@@ -29,6 +29,12 @@ struct Level {
     uint32_t n_words() const { return (n_bricks() + 31) / 32; }
 };
 
+// Coordinate axes of a brush: x, y, z of the sample position and its radius.
+struct CoordBrush {
+    uint8_t active[4] = {};
+    float lo[4] = {}, hi[4] = {};
+};
+
 struct Volume {
     int id = 0, n = 0, nf = 0, n_lods = 0, storage = 0;
     bool records = false;  // neighbourhood records kept (binary16 / float32 without RAYPC_STORAGE_COMPACT)
@@ -36,6 +42,7 @@ struct Volume {
     Level lv[RAYPC_MAX_LODS];
     uint8_t active[kMaxFields] = {};
     float lo[kMaxFields] = {}, hi[kMaxFields] = {};
+    CoordBrush coord;
     uint64_t brush_gen = 1;
     uint64_t bytes = 0;
     std::vector<void*> allocs;
@@ -74,9 +81,11 @@ Volume* lookup_volume(raypc_ctx* ctx, int id);
 // Validate a render and fill the kernel arguments (skip list and table pointers left for the caller
 // when use_volume_state is false).  Brush arrays are per field of the volume.
 int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
-                   float step, const uint8_t* active, const float* lo, const float* hi, int tf_slot,
-                   float* rgba_out, bool use_volume_state, hipStream_t s, RenderArgs& a, int& storage,
+                   float step, const uint8_t* active, const float* lo, const float* hi, const CoordBrush& coord,
+                   int tf_slot, float* rgba_out, bool use_volume_state, hipStream_t s, RenderArgs& a, int& storage,
                    int& level, Volume** vol_out);
+// Kernel form of a coordinate brush: the mask of enabled axes and bounds, radius as float32 squares.
+uint32_t coord_kernel_form(const CoordBrush& c, float clo[4], float chi[4]);
 // Skip-kernel arguments for level l of v under a brush and a transfer-function slot (out left null).
 void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t* active, const float* lo,
                      const float* hi, int tf_slot, SkipArgs& a);

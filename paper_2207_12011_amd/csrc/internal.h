@@ -48,6 +48,26 @@ __host__ __device__ inline uint32_t brick_local(int x, int y, int z) {
            (static_cast<uint32_t>(y & 3) << 2) | static_cast<uint32_t>(x & 3);
 }
 
+// Coordinate axes of a brush at a position (x, y, z world units): bit a of mask enables axis a
+// (x, y, z, radius) with inclusive bounds [clo[a], chi[a]]; the radius is tested on float32
+// squares, r^2 = fl32(fl32(fl32(x x) + fl32(y y)) + fl32(z z)) against clo[3] <= r^2 <= chi[3].
+__device__ __forceinline__ bool coord_ok(uint32_t mask, const float* clo, const float* chi, float x, float y,
+                                         float z) {
+    bool ok = true;
+    if (mask & 1u) ok = ok && x >= clo[0] && x <= chi[0];
+    if (mask & 2u) ok = ok && y >= clo[1] && y <= chi[1];
+    if (mask & 4u) ok = ok && z >= clo[2] && z <= chi[2];
+    if (mask & 8u) {
+        const float r2 = __fadd_rn(__fadd_rn(__fmul_rn(x, x), __fmul_rn(y, y)), __fmul_rn(z, z));
+        ok = ok && r2 >= clo[3] && r2 <= chi[3];
+    }
+    return ok;
+}
+// World coordinate of the centre of cell i on an N-cell axis: fl32(fl32(2 i + 1) / N) - 1.
+__device__ __forceinline__ float cell_coord(int i, int n) {
+    return __fsub_rn(__fdiv_rn(static_cast<float>(2 * i + 1), static_cast<float>(n)), 1.0f);
+}
+
 // ------------------------------------------------------------------ preprocessing launchers
 hipError_t launch_count_nonfinite(const float* x, size_t count, unsigned int* flag, hipStream_t s);
 // out[N/2]^3 = 2x2x2 mean of in[N]^3 (both linear [z][y][x] float32).
@@ -71,6 +91,8 @@ struct MaskArgs {
     const float2* u8par[kMaxFields];
     float lo[kMaxFields], hi[kMaxFields];
     int n_active;  // fields [0, n_active) of the arrays above are the active ones
+    uint32_t coord_mask;  // coordinate axes at the cell centre (as RenderArgs)
+    float clo[4], chi[4];
     int n, nb, storage;
     uint8_t* out;  // linear [z][y][x]
 };
@@ -85,6 +107,8 @@ struct PcArgs {
     uint8_t active[kMaxFields];
     float lo[kMaxFields], hi[kMaxFields];       // the volume's brush
     float axis_lo[kMaxFields], inv[kMaxFields]; // inv = fl32(1 / fl32(axis_hi - axis_lo))
+    uint32_t coord_mask;                        // coordinate axes at the cell centre (as RenderArgs)
+    float clo[4], chi[4];
     int n_fields, storage, n, nb, n_bins, n_lines;
     const uint32_t* cells;                      // z N^2 + y N + x
     float* values;                              // [n_lines][n_fields] or null
@@ -117,6 +141,8 @@ struct RenderArgs {
     const void* rec[kMaxFields];  // neighbourhood records, in the same slot order (record kinds only)
     float lo[kMaxFields], hi[kMaxFields];
     int n_brushed, tf_slot;
+    uint32_t coord_mask;          // coordinate axes in use (bit a = axis a: x, y, z, radius)
+    float clo[4], chi[4];         // their bounds; radius as float32 squares (see raypc_set_coordinate_brush)
     int n, nb;
     uint32_t field_bytes;         // bytes of one field of this level (buffer range; f16 and u8 only)
     uint32_t par_bytes;           // bytes of one field's per-brick (scale, offset) table (u8)

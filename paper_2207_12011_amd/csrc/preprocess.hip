@@ -222,6 +222,8 @@ __global__ void voxel_mask_kernel(MaskArgs a) {
         const float v = stored<S>(a.field[f], a.u8par[f], addr);
         keep = keep && (v >= a.lo[f]) && (v <= a.hi[f]);
     }
+    if (a.coord_mask)
+        keep = keep && coord_ok(a.coord_mask, a.clo, a.chi, cell_coord(x, a.n), cell_coord(y, a.n), cell_coord(z, a.n));
     a.out[o] = keep ? 1 : 0;
 }
 
@@ -243,6 +245,8 @@ __global__ __launch_bounds__(256) void pc_lines_kernel(PcArgs a) {
         const int z = static_cast<int>(c / (static_cast<uint32_t>(a.n) * a.n));
         const uint32_t addr = valid ? brick_addr(x, y, z, a.nb) : 0u;
         bool pass = valid;
+        if (valid && a.coord_mask)
+            pass = coord_ok(a.coord_mask, a.clo, a.chi, cell_coord(x, a.n), cell_coord(y, a.n), cell_coord(z, a.n));
         for (int f = 0; f < a.n_fields; ++f) {
             const float v = valid ? stored<S>(a.field[f], a.u8par[f], addr) : NAN;
             if (a.values != nullptr) a.values[static_cast<size_t>(line) * a.n_fields + f] = v;

@@ -442,7 +442,14 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                     if constexpr (R) return fetch_rec<RT>(A.rec[k], ax, ay0, ay1, az0, az1, tw);
                     else return fetch<S>(source<S>(A, k), o, tw);
                 };
+                // coordinate axes first: a sample outside them fetches no field (the kernels with a
+                // fixed field count carry no coordinate axes; renders that use them take the
+                // run-time variant)
                 bool pass = true;
+                if constexpr (NB < 0) {
+                    if (A.coord_mask)
+                        pass = coord_ok(A.coord_mask, A.clo, A.chi, fmaf(dx, tm, ox), fmaf(dy, tm, oy), fmaf(dz, tm, oz));
+                }
                 float tv = 0.0f;
                 constexpr int kUnroll = NB >= 0 ? NB : kMaxFields;
                 const int nbr = NB >= 0 ? NB : A.n_brushed;
@@ -643,6 +650,10 @@ __global__ __launch_bounds__(256) void raymarch_batch_kernel(const RenderArgs* _
 template <int K, bool COUNTS>
 hipError_t launch_nb(const RenderArgs& a, hipStream_t s) {
     const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x)), block(256);
+    if (a.coord_mask) {
+        hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, COUNTS>), grid, block, 0, s, a);
+        return hipGetLastError();
+    }
     switch (a.n_brushed) {
         case 0: hipLaunchKernelGGL((raymarch_kernel<K, 0, COUNTS>), grid, block, 0, s, a); break;
         case 1: hipLaunchKernelGGL((raymarch_kernel<K, 1, COUNTS>), grid, block, 0, s, a); break;

@@ -429,9 +429,15 @@ int raypc_submit(raypc_ctx* ctx, const raypc_request* req, uint64_t* ticket) {
         std::lock_guard<std::mutex> lk(ctx->mu);
         int level = 0;
         Volume* v = nullptr;
+        CoordBrush coord;
+        for (int ax = 0; ax < 4; ++ax) {
+            coord.active[ax] = req->coord_active[ax];
+            coord.lo[ax] = req->coord_lo[ax];
+            coord.hi[ax] = req->coord_hi[ax];
+        }
         const int rc = prepare_render(ctx, req->volume_id, &req->camera, req->width, req->height, req->lod, req->step,
-                                      req->active, req->lo, req->hi, req->tf_slot, req->out, false, nullptr, r->args,
-                                      r->storage, level, &v);
+                                      req->active, req->lo, req->hi, coord, req->tf_slot, req->out, false, nullptr,
+                                      r->args, r->storage, level, &v);
         if (rc) {
             delete r;
             return rc;

@@ -72,6 +72,7 @@ _unload = _sig("raypc_unload", _I, _P, _I)
 _volume_info = _sig("raypc_volume_info", _I, _P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
                     ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_uint64))
 _set_brush = _sig("raypc_set_brush", _I, _P, _I, _I, _P, _P, _P)
+_set_coord = _sig("raypc_set_coordinate_brush", _I, _P, _I, _P, _P, _P)
 _set_tf = _sig("raypc_set_transfer_function", _I, _P, _I, _I, _F, _F, _P, _I, _F)
 _set_options = _sig("raypc_set_options", _I, _P, _F, _P)
 _select_lod = _sig("raypc_select_lod", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, ctypes.POINTER(_I))
@@ -97,6 +98,7 @@ class ServerCfg(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("volume_id", _I), ("camera", Camera), ("width", _I), ("height", _I), ("lod", _I), ("step", _F),
                 ("active", ctypes.c_uint8 * MAX_FIELDS), ("lo", _F * MAX_FIELDS), ("hi", _F * MAX_FIELDS),
+                ("coord_active", ctypes.c_uint8 * 4), ("coord_lo", _F * 4), ("coord_hi", _F * 4),
                 ("tf_slot", _I), ("out", _P), ("deadline_ms", ctypes.c_double)]
 
 
@@ -125,7 +127,7 @@ EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_po
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
             "raypc_export_level", "raypc_export_minmax", "raypc_export_minmax_sub", "raypc_export_skiplist",
             "raypc_export_subskip", "raypc_export_voxel_mask", "raypc_render_debug", "raypc_pc_lines",
-            "raypc_render_jittered"]
+            "raypc_render_jittered", "raypc_set_coordinate_brush"]
 
 
 class RaypcError(RuntimeError):
@@ -219,6 +221,14 @@ def set_brush(ctx, volume_id: int, active, lo, hi) -> None:
     l = np.ascontiguousarray(np.asarray(lo, np.float32))
     h = np.ascontiguousarray(np.asarray(hi, np.float32))
     _check(_set_brush(ctx, int(volume_id), int(a.size), a.ctypes.data, l.ctypes.data, h.ctypes.data))
+
+
+def set_coordinate_brush(ctx, volume_id: int, active, lo, hi) -> None:
+    """Coordinate axes (x, y, z of the sample position, its radius): 4 flags and bounds."""
+    a = np.ascontiguousarray(np.asarray(active, np.uint8).reshape(4))
+    l = np.ascontiguousarray(np.asarray(lo, np.float32).reshape(4))
+    h = np.ascontiguousarray(np.asarray(hi, np.float32).reshape(4))
+    _check(_set_coord(ctx, int(volume_id), a.ctypes.data, l.ctypes.data, h.ctypes.data))
 
 
 def set_transfer_function(ctx, slot: int, field: int, vmin: float, vmax: float, rgba,
@@ -389,7 +399,9 @@ def server_stop(ctx) -> None:
 
 
 def make_request(volume_id: int, camera, width: int, height: int, out: torch.Tensor, lod: int = -1,
-                 step: float = 0.5, active=(), lo=(), hi=(), tf_slot: int = 0, deadline_ms: float = 0.0) -> Request:
+                 step: float = 0.5, active=(), lo=(), hi=(), tf_slot: int = 0, deadline_ms: float = 0.0,
+                 coord=None) -> Request:
+    """A serving request; `coord` = (active[4], lo[4], hi[4]) coordinate axes (None: none)."""
     r = Request()
     r.volume_id = int(volume_id)
     r.camera = Camera.make(camera)
@@ -403,6 +415,10 @@ def make_request(volume_id: int, camera, width: int, height: int, out: torch.Ten
     r.active[:] = a.tolist()
     r.lo[:] = l.tolist()
     r.hi[:] = h.tolist()
+    if coord is not None:
+        r.coord_active[:] = np.asarray(coord[0], np.uint8).reshape(4).tolist()
+        r.coord_lo[:] = np.asarray(coord[1], np.float32).reshape(4).tolist()
+        r.coord_hi[:] = np.asarray(coord[2], np.float32).reshape(4).tolist()
     r.tf_slot = int(tf_slot)
     r.out = _dptr(out, torch.float32, width * height * 4, "out")
     r.deadline_ms = float(deadline_ms)
