@@ -160,10 +160,51 @@ def tf_index(v, vmin: float, vmax: float) -> np.ndarray:
     return (t * F32(255.0)).astype(F32)
 
 
-def skip_bits(mins, maxs, active, lo, hi, tf_field: int, vmin: float, vmax: float, tf_rgba) -> np.ndarray:
-    """bool [nb]^3 brick skip flags from per-field tables (lists of [nb]^3 arrays)."""
+def coord_skip(n: int, box: int, coord) -> np.ndarray:
+    """bool [n/box]^3: boxes of box^3 voxels (voxel indices [i0, i1] per axis) in which no sample
+    position can pass the coordinate axes of ``coord``.  The positions whose clamped floor index
+    lies in the box are inside [fl32(fl32(i0 h) - 1), fl32(fl32((i1 + 2) h) - 1)] per axis (half a
+    voxel of margin on each side; open at the grid faces), h = fl32(2 / n).  An axis skips the box
+    when that range misses its bounds; the radius axis when the box's squared radius range
+    (float32, summed x, y, z) misses the bounds' squares (see coord_pass)."""
+    act, lo, hi = coord
+    nbx = n // box
+    h = F32(F32(2.0) / F32(n))
+    i0 = np.arange(nbx, dtype=np.int64) * box
+    i1 = i0 + box - 1
+    with np.errstate(over="ignore", invalid="ignore"):
+        bmin = ((i0.astype(F32) * h).astype(F32) - F32(1.0)).astype(F32)
+        bmax = (((i1 + 2).astype(F32) * h).astype(F32) - F32(1.0)).astype(F32)
+        bmin[i0 == 0] = -np.inf
+        bmax[i1 == n - 1] = np.inf
+        shapes = ((1, 1, nbx), (1, nbx, 1), (nbx, 1, 1))          # x, y, z along the array axes
+        skip = np.zeros((nbx, nbx, nbx), bool)
+        for ax in range(3):
+            if act[ax]:
+                miss = (bmax < F32(lo[ax])) | (bmin > F32(hi[ax]))
+                skip |= miss.reshape(shapes[ax])
+        if act[3]:
+            d = np.maximum(np.maximum(F32(0.0), bmin), -bmax).astype(F32)
+            d2 = (d * d).astype(F32)
+            m2 = np.maximum((bmin * bmin).astype(F32), (bmax * bmax).astype(F32)).astype(F32)
+            rmin2 = ((d2.reshape(shapes[0]) + d2.reshape(shapes[1])).astype(F32) + d2.reshape(shapes[2])).astype(F32)
+            rmax2 = ((m2.reshape(shapes[0]) + m2.reshape(shapes[1])).astype(F32) + m2.reshape(shapes[2])).astype(F32)
+            l3, h3 = F32(lo[3]), F32(hi[3])
+            clo = F32(l3 * l3) if l3 > 0 else F32(-np.inf)
+            chi = F32(h3 * h3) if h3 >= 0 else F32(-1.0)
+            skip |= (rmin2 > chi) | (rmax2 < clo)
+    return skip
+
+
+def skip_bits(mins, maxs, active, lo, hi, tf_field: int, vmin: float, vmax: float, tf_rgba, coord=None,
+              n: int = 0, box: int = BRICK) -> np.ndarray:
+    """bool [nb]^3 brick skip flags from per-field tables (lists of [nb]^3 arrays); with ``coord``
+    (coordinate axes) and the level size ``n``, boxes of ``box`` voxels that no sample position
+    passing the axes can reach are skipped too (coord_skip)."""
     nb = mins[0].shape[0]
     skip = np.zeros((nb, nb, nb), bool)
+    if coord is not None and any(coord[0]):
+        skip |= coord_skip(n, box, coord)
     for f in range(len(mins)):
         if active[f]:
             skip |= (maxs[f] < F32(lo[f])) | (mins[f] > F32(hi[f])) | (F32(lo[f]) > F32(hi[f]))
@@ -192,10 +233,12 @@ def sub_skip_bytes(sub_flags: np.ndarray) -> np.ndarray:
     return out.reshape(-1)
 
 
-def sub_skip(fields_level, active, lo, hi, tf_field: int, vmin: float, vmax: float, tf_rgba) -> np.ndarray:
+def sub_skip(fields_level, active, lo, hi, tf_field: int, vmin: float, vmax: float, tf_rgba,
+             coord=None) -> np.ndarray:
     """Sub-brick skip bytes of one level's stored fields: the skip rule over 4^3 windows, packed."""
     mins, maxs = zip(*[brick_minmax(f, SUB) for f in fields_level])
-    return sub_skip_bytes(skip_bits(mins, maxs, active, lo, hi, tf_field, vmin, vmax, tf_rgba))
+    n = np.asarray(fields_level[0]).shape[0]
+    return sub_skip_bytes(skip_bits(mins, maxs, active, lo, hi, tf_field, vmin, vmax, tf_rgba, coord, n, SUB))
 
 
 def pack_bits(flags: np.ndarray) -> np.ndarray:

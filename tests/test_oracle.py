@@ -327,6 +327,36 @@ def test_coordinate_axes_on_cells():
     assert np.array_equal(passes, pp.voxel_mask(vol, [0], [0], [0], coord=coord).reshape(-1)[cells])
 
 
+@pytest.mark.parametrize("coord", [([1, 0, 0, 0], [0.1, 0, 0, 0], [0.6, 0, 0, 0]),
+                                   ([0, 1, 0, 1], [0, -2, 0, 0.7], [0, -0.3, 0, 0.9]),
+                                   ([0, 0, 1, 1], [0, 0, -0.5, 0.0], [0, 0, 0.5, 0.5])])
+@pytest.mark.parametrize("box", [8, 4])
+def test_coordinate_skip_is_conservative(coord, box):
+    """No position whose clamped floor index lies in a box skipped by the coordinate axes passes
+    them (dense random positions, FP64); the cut skips some boxes and keeps others; a brick skipped
+    by position has all its sub-bricks skipped."""
+    n = 32
+    sk = pp.coord_skip(n, box, coord)
+    assert 0 < sk.sum() < sk.size
+    rng = np.random.default_rng(31)
+    u = rng.uniform(-0.5, n - 0.5, (300000, 3))
+    c = np.clip(np.floor(u), 0, n - 1).astype(int) // box
+    sel = sk[c[:, 2], c[:, 1], c[:, 0]]
+    p = (u + 0.5) * (2.0 / n) - 1.0
+    r = np.linalg.norm(p, axis=1)
+    act, lo, hi = coord
+    ok = np.ones(len(u), bool)
+    for ax in range(3):
+        if act[ax]:
+            ok &= (p[:, ax] >= lo[ax]) & (p[:, ax] <= hi[ax])
+    if act[3]:
+        ok &= (r >= lo[3]) & (r <= hi[3])
+    assert not np.any(sel & ok)
+    if box == 8:
+        sub = pp.coord_skip(n, 4, coord)
+        assert np.all(sub.reshape(n // 8, 2, n // 8, 2, n // 8, 2).all(axis=(1, 3, 5))[sk])
+
+
 # ----------------------------------------------------------------------------- jittered passes
 def test_splitmix64_reference_outputs():
     """First outputs of SplitMix64 from state 0, as listed with the generator's reference
