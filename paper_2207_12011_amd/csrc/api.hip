@@ -176,7 +176,7 @@ int set_error(int code, const char* fmt, ...) {
 Volume* lookup_volume(raypc_ctx* ctx, int id) { return find_volume(ctx, id); }
 
 void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t* active, const float* lo,
-                     const float* hi, int tf_slot, SkipArgs& a) {
+                     const float* hi, const CoordBrush& coord, int tf_slot, SkipArgs& a) {
     const Level& L = v->lv[l];
     const TFSlot& tf = ctx->tf[tf_slot];
     std::memset(&a, 0, sizeof(a));
@@ -200,6 +200,10 @@ void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t
         if (tf.rgba[4 * i + 3] > 0.0f) nxt = i;
         a.next_nonzero[i] = nxt;
     }
+    a.coord_mask = coord_kernel_form(coord, a.clo, a.chi);
+    a.n = L.n;
+    a.nb = L.nb;
+    a.h = 2.0f / static_cast<float>(L.n);
     a.n_bricks = L.n_bricks();
     a.out = nullptr;
     a.out_sub = nullptr;
@@ -213,7 +217,7 @@ static int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s
     if (L.skip_valid && L.skip_brush_gen == v->brush_gen && L.skip_slot == slot && L.skip_tf_gen == tf.gen)
         return RAYPC_OK;
     SkipArgs a;
-    build_skip_args(ctx, v, l, v->active, v->lo, v->hi, slot, a);
+    build_skip_args(ctx, v, l, v->active, v->lo, v->hi, v->coord, slot, a);
     a.out = L.skip;
     a.out_sub = L.skip_sub;
     HIP_TRY(launch_skip(a, s), "skip-list kernel launch");

@@ -88,5 +88,5 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
 uint32_t coord_kernel_form(const CoordBrush& c, float clo[4], float chi[4]);
 // Skip-kernel arguments for level l of v under a brush and a transfer-function slot (out left null).
 void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t* active, const float* lo,
-                     const float* hi, int tf_slot, SkipArgs& a);
+                     const float* hi, const CoordBrush& coord, int tf_slot, SkipArgs& a);
 }  // namespace raypc

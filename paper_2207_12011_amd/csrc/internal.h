@@ -126,6 +126,10 @@ struct SkipArgs {
     const float2* tf_minmax_sub;
     float vmin, inv_range;                 // inv_range = fl32(1 / (vmax - vmin))
     int next_nonzero[257];                 // smallest entry index >= i with opacity > 0 (256 if none)
+    uint32_t coord_mask;                   // coordinate axes (kernel form, see coord_ok)
+    float clo[4], chi[4];
+    int n, nb;                             // level size in voxels and bricks per axis
+    float h;                               // fl32(2 / n)
     uint32_t n_bricks;
     uint32_t* out;                         // brick skip bits, ceil(n_bricks / 32) words (may be null)
     uint8_t* out_sub;                      // sub-brick skip flags, one byte per brick (may be null)

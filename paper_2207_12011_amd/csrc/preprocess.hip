@@ -300,6 +300,35 @@ __device__ __forceinline__ uint32_t sub_range_misses(const float2* p, float lo, 
     return m;
 }
 
+// Coordinate axes against a box of box^3 voxels starting at voxel (x0, y0, z0): true when no sample
+// position whose clamped floor index lies in the box can pass them.  Those positions lie inside
+// [fl32(fl32(i0 h) - 1), fl32(fl32((i1 + 2) h) - 1)] per axis (half a voxel of margin each side,
+// open at the grid faces); the radius axis compares the box's float32 squared-radius range.
+__device__ bool coord_box_miss(const SkipArgs& a, int x0, int y0, int z0, int box) {
+    const int i0[3] = {x0, y0, z0};
+    float bmin[3], bmax[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        const int i1 = i0[ax] + box - 1;
+        bmin[ax] = i0[ax] == 0 ? -INFINITY : __fsub_rn(__fmul_rn(static_cast<float>(i0[ax]), a.h), 1.0f);
+        bmax[ax] = i1 == a.n - 1 ? INFINITY : __fsub_rn(__fmul_rn(static_cast<float>(i1 + 2), a.h), 1.0f);
+    }
+    bool miss = false;
+    for (int ax = 0; ax < 3; ++ax)
+        if (a.coord_mask & (1u << ax)) miss = miss || bmax[ax] < a.clo[ax] || bmin[ax] > a.chi[ax];
+    if (a.coord_mask & 8u) {
+        float d2[3], m2[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            const float d = fmaxf(fmaxf(0.0f, bmin[ax]), -bmax[ax]);
+            d2[ax] = __fmul_rn(d, d);
+            m2[ax] = fmaxf(__fmul_rn(bmin[ax], bmin[ax]), __fmul_rn(bmax[ax], bmax[ax]));
+        }
+        const float rmin2 = __fadd_rn(__fadd_rn(d2[0], d2[1]), d2[2]);
+        const float rmax2 = __fadd_rn(__fadd_rn(m2[0], m2[1]), m2[2]);
+        miss = miss || rmin2 > a.chi[3] || rmax2 < a.clo[3];
+    }
+    return miss;
+}
+
 // One thread per brick: the brick's skip bit (a wave ballot packs 64 into two words) and its byte
 // of sub-brick flags.  A skipped brick's sub-bricks are all skipped (their windows lie inside its
 // window and the table index map is monotone), so only the other bricks read sub-brick tables.
@@ -312,6 +341,9 @@ __global__ __launch_bounds__(256) void skip_kernel(SkipArgs a) {
             skip |= (mm.y < a.lo[f]) | (mm.x > a.hi[f]) | (a.lo[f] > a.hi[f]);
         }
         skip |= tf_range_empty(a, a.tf_minmax[b]);
+        const int bx = static_cast<int>(b % a.nb), by = static_cast<int>((b / a.nb) % a.nb);
+        const int bz = static_cast<int>(b / (static_cast<uint32_t>(a.nb) * a.nb));
+        if (a.coord_mask) skip = skip || coord_box_miss(a, bx * 8, by * 8, bz * 8, 8);
         if (a.out_sub != nullptr) {
             uint32_t sub = 0xFFu;
             if (!skip) {
@@ -325,6 +357,10 @@ __global__ __launch_bounds__(256) void skip_kernel(SkipArgs a) {
                     sub |= static_cast<uint32_t>(tf_range_empty(a, make_float2(v.x, v.y))) << (2 * k);
                     sub |= static_cast<uint32_t>(tf_range_empty(a, make_float2(v.z, v.w))) << (2 * k + 1);
                 }
+                if (a.coord_mask)
+                    for (int i = 0; i < 8; ++i)
+                        if (coord_box_miss(a, bx * 8 + (i & 1) * 4, by * 8 + ((i >> 1) & 1) * 4, bz * 8 + (i >> 2) * 4, 4))
+                            sub |= 1u << i;
             }
             a.out_sub[b] = static_cast<uint8_t>(sub);
         }

@@ -442,7 +442,7 @@ int raypc_submit(raypc_ctx* ctx, const raypc_request* req, uint64_t* ticket) {
             delete r;
             return rc;
         }
-        build_skip_args(ctx, v, level, req->active, req->lo, req->hi, req->tf_slot, r->skip_args);
+        build_skip_args(ctx, v, level, req->active, req->lo, req->hi, coord, req->tf_slot, r->skip_args);
         std::memcpy(r->tf_rgba, ctx->tf[req->tf_slot].rgba, sizeof(r->tf_rgba));
         r->n_tiles = r->args.n_blocks;
         r->bytes = static_cast<uint64_t>(req->width) * req->height * 16u +
