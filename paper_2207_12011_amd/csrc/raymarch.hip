@@ -187,9 +187,8 @@ constexpr int record_type_of(int K) { return K == kKindF16Rec ? kF16 : kF32; }
 // Ray parameter where u(t) = uo + du t leaves [lo, hi] along one axis (forward only); inv_du = 1/du.
 // Rounding of the reciprocal is covered by the shrink margin of skipped bricks.
 __device__ __forceinline__ float axis_exit(float uo, float du, float inv_du, float lo, float hi) {
-    if (du > 0.0f) return (hi - uo) * inv_du;
-    if (du < 0.0f) return (lo - uo) * inv_du;
-    return INFINITY;
+    const float t = ((du > 0.0f ? hi : lo) - uo) * inv_du;
+    return du != 0.0f ? t : INFINITY;
 }
 
 // Stable ray/sphere hit for |d| = 1.  Returns false when the ray misses or touches.
@@ -359,14 +358,14 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     while (alive) {
         const int j = j0 + sub;
         const bool valid = j < ns;
-        float keep = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-        bool contributes = false, skipped = false;
+        bool skipped = false, pass = false;
+        float tv = 0.0f;
         int jn = j + 1;
+        const bool last = j == ns - 1;
+        float tlo = 0.0f, tm = 0.0f, len_partial = 0.0f;
+        bool partial = last;
 
         if (valid) {
-            const bool last = j == ns - 1;
-            float tlo, tm, len_partial = 0.0f;
-            bool partial = last;
             if constexpr (JIT) {
                 const bool first = j == 0;
                 partial = first || last;
@@ -445,12 +444,11 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                 // coordinate axes first: a sample outside them fetches no field (the kernels with a
                 // fixed field count carry no coordinate axes; renders that use them take the
                 // run-time variant)
-                bool pass = true;
+                pass = true;
                 if constexpr (NB < 0) {
                     if (A.coord_mask)
                         pass = coord_ok(A.coord_mask, A.clo, A.chi, fmaf(dx, tm, ox), fmaf(dy, tm, oy), fmaf(dz, tm, oz));
                 }
-                float tv = 0.0f;
                 constexpr int kUnroll = NB >= 0 ? NB : kMaxFields;
                 const int nbr = NB >= 0 ? NB : A.n_brushed;
 #pragma unroll
@@ -468,22 +466,24 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                         if (A.tf_slot == nbr && nbr < kMaxFields)
                             tv = field_value(nbr);
                     }
-                    const float xt = fminf(fmaxf((tv - A.vmin) * A.inv_range, 0.0f), 1.0f) * 255.0f;
-                    const int it = min(static_cast<int>(xt), 254);
-                    const float wt = xt - static_cast<float>(it);
-                    const float4 e0 = s_tf[it], e1 = s_tf[it + 1];
-                    const float al = fmaf(wt, e1.w - e0.w, e0.w);
-                    if (al > 0.0f) {
-                        contributes = true;
-                        const float r = partial ? len_partial * A.inv_ref : r_full;
-                        keep = al >= 1.0f ? 0.0f : __builtin_amdgcn_exp2f(r * __log2f(1.0f - al));
-                        cr = fmaf(wt, e1.x - e0.x, e0.x);
-                        cg = fmaf(wt, e1.y - e0.y, e0.y);
-                        cb = fmaf(wt, e1.z - e0.z, e0.z);
-                    }
                 }
             }
         }
+        // ---- classification: every lane evaluates it, and a lane whose sample was not fetched or
+        // failed the brush contributes nothing (k = 1, w = 0), so the values merged below are those
+        // of the sequential definition
+        const float xt = fminf(fmaxf((tv - A.vmin) * A.inv_range, 0.0f), 1.0f) * 255.0f;
+        const int it = min(static_cast<int>(xt), 254);
+        const float wt = xt - static_cast<float>(it);
+        const float4 e0 = s_tf[it], e1 = s_tf[it + 1];
+        const float al = fmaf(wt, e1.w - e0.w, e0.w);
+        const bool contributes = pass && al > 0.0f;
+        const float r = partial ? len_partial * A.inv_ref : r_full;
+        const float kc = al >= 1.0f ? 0.0f : __builtin_amdgcn_exp2f(r * __log2f(1.0f - al));
+        const float keep = contributes ? kc : 1.0f;
+        const float cr = contributes ? fmaf(wt, e1.x - e0.x, e0.x) : 0.0f;
+        const float cg = contributes ? fmaf(wt, e1.y - e0.y, e0.y) : 0.0f;
+        const float cb = contributes ? fmaf(wt, e1.z - e0.z, e0.z) : 0.0f;
 
         // ---- advance past a skipped brick of the quad's fourth sample
         const int last_skipped = quad_bcast<3>(static_cast<int>(skipped && valid));
