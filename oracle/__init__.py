@@ -44,7 +44,7 @@ def lib():
             ctypes.c_int, ctypes.c_int, P, ctypes.c_double, ctypes.c_double,
             P, P, P, P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, ctypes.c_double,
             ctypes.c_double, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_long,
-            P, P, P, P, P, P, P, ctypes.c_int]
+            P, P, P, P, P, P, P, P, ctypes.c_int]
         L.oracle_trilinear.restype = None
         L.oracle_trilinear.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P]
         _lib = L
@@ -62,6 +62,7 @@ class OracleImage:
     composited: np.ndarray  # uint32
     fragile: np.ndarray     # uint8 bit mask
     pathlen: np.ndarray     # float64
+    depth: np.ndarray       # float64 opacity-weighted mean sample distance (+inf: nothing composited)
 
 
 def render(level_fields: np.ndarray, camera, width: int, height: int, step: float, *,
@@ -101,20 +102,21 @@ def render(level_fields: np.ndarray, camera, width: int, height: int, step: floa
     comp = np.zeros(npix, np.uint32)
     frag = np.zeros(npix, np.uint8)
     plen = np.zeros(npix)
+    dep = np.zeros(npix)
     threads = threads or os.cpu_count() or 1
     rc = lib().oracle_render(
         nf, n, ctypes.cast(ptrs, ctypes.c_void_p), float(np.float32(r_inner)), float(np.float32(r_outer)),
         _ptr(act), _ptr(lo64), _ptr(hi64), _ptr(cact), _ptr(clo), _ptr(chi), int(tf_field), float(np.float32(vmin)), float(np.float32(vmax)),
         _ptr(tf64), float(np.float32(ref_step)), float(np.float32(ert)), _ptr(bg64), _ptr(cam),
         int(width), int(height), float(np.float32(step)), int(npix), _ptr(pix), _ptr(jit),
-        _ptr(rgba), _ptr(nom), _ptr(comp), _ptr(frag), _ptr(plen), int(threads))
+        _ptr(rgba), _ptr(nom), _ptr(comp), _ptr(frag), _ptr(plen), _ptr(dep), int(threads))
     if rc != 0:
         raise ValueError("oracle_render: invalid arguments")
     if full:
         return OracleImage(rgba.reshape(height, width, 4), nom.reshape(height, width),
                            comp.reshape(height, width), frag.reshape(height, width),
-                           plen.reshape(height, width))
-    return OracleImage(rgba, nom, comp, frag, plen)
+                           plen.reshape(height, width), dep.reshape(height, width))
+    return OracleImage(rgba, nom, comp, frag, plen, dep)
 
 
 def trilinear(field: np.ndarray, u_xyz: np.ndarray) -> np.ndarray:

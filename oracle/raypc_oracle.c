@@ -25,8 +25,13 @@
  * Every output is per requested pixel: premultiplied RGBA, the nominal sample
  * count (samples visited up to and including an early-termination stop), the
  * composited count (samples that passed the brush and had non-zero table
- * opacity), the marched length (sum of sample lengths) and a fragility mask
- * naming decisions that sit within floating-point reach of a threshold:
+ * opacity), the marched length (sum of sample lengths), the depth that image
+ * warping reprojects with (the mean distance from the eye of the composited
+ * samples, each weighted by its contribution to the pixel's opacity; the paper,
+ * Sections 2 and 2.2, warps the last image to fill frames the renderer has not
+ * delivered yet and names no depth, so this opacity-weighted mean is the reading
+ * taken here) and a fragility mask naming decisions that sit within
+ * floating-point reach of a threshold:
  *   bit 0  a brush comparison within delta_b of its bound that could flip the
  *          sample's outcome (delta_b grows with the segment's grazing reach,
  *          below; for a coordinate axis delta_b = 1e-5 plus that reach, in world
@@ -154,6 +159,7 @@ typedef struct {
     uint32_t nominal, composited;
     uint8_t fragile;
     double pathlen;
+    double depth; /* opacity-weighted mean distance of the composited samples; +inf if none */
 } pixel_result;
 
 /* Float32 reach of a root of the sphere of radius rho with discriminant disc (see the header). */
@@ -224,7 +230,7 @@ static void render_pixel(const oracle_params *P, int px, int py, double jit, pix
     const int n = P->n;
     const double h = 2.0 / n;
     const double ds = P->step_vox * h;
-    double C[3] = {0, 0, 0}, A = 0.0;
+    double C[3] = {0, 0, 0}, A = 0.0, D = 0.0;
     int done = 0;
     for (int sgi = 0; sgi < nseg && !done; ++sgi) {
         double a = seg[sgi][0], b = seg[sgi][1];
@@ -316,6 +322,7 @@ static void render_pixel(const oracle_params *P, int px, int py, double jit, pix
             double alpha = s[3] >= 1.0 ? 1.0 : -expm1((len / P->ref_step) * log1p(-s[3]));
             if (alpha == 0.0) continue;
             for (int c = 0; c < 3; ++c) C[c] += (1.0 - A) * alpha * s[c];
+            D += (1.0 - A) * alpha * tm;
             A += (1.0 - A) * alpha;
             if (P->ert < 1.0) {
                 if (fabs(A - P->ert) <= 1e-4) res->fragile |= 2;
@@ -323,6 +330,9 @@ static void render_pixel(const oracle_params *P, int px, int py, double jit, pix
             }
         }
     }
+    /* depth: the sample distances tm weighted by each sample's share (1 - A) alpha of the final
+     * opacity, whose sum is A; taken before the background, which has no depth */
+    res->depth = A > 0.0 ? D / A : INFINITY;
     if (P->bg) {
         for (int c = 0; c < 3; ++c) C[c] += (1.0 - A) * P->bg[c];
         A += (1.0 - A) * P->bg[3];
@@ -341,8 +351,9 @@ static void render_pixel(const oracle_params *P, int px, int py, double jit, pix
  * `coord_lo` / `coord_hi` restricts the sample position: axes 0..2 its world x, y,
  * z, axis 3 its radius.  `bg` may be NULL.  `jitter` holds
  * one sample-grid offset in [0, 1) per requested pixel (NULL: 0, the regular
- * partition).  Any output pointer may be NULL.  Returns 0, or -1 on invalid
- * arguments.
+ * partition).  `depth` receives the opacity-weighted mean sample distance from
+ * the eye (+inf where nothing was composited).  Any output pointer may be NULL.
+ * Returns 0, or -1 on invalid arguments.
  */
 int oracle_render(int n_fields, int n, const float *const *fields, double r_inner, double r_outer,
                   const uint8_t *active, const double *lo, const double *hi, const uint8_t *coord_active,
@@ -350,7 +361,7 @@ int oracle_render(int n_fields, int n, const float *const *fields, double r_inne
                   double vmax, const double *tf_rgba, double ref_step, double ert, const double *bg,
                   const double *camera, int width, int height, double step_vox, long n_pix,
                   const int64_t *pix, const double *jitter, double *rgba, uint32_t *nominal,
-                  uint32_t *composited, uint8_t *fragile, double *pathlen, int n_threads)
+                  uint32_t *composited, uint8_t *fragile, double *pathlen, double *depth, int n_threads)
 {
     if (n_fields < 1 || n_fields > ORACLE_MAX_FIELDS || n < 2 || width < 1 || height < 1 ||
         tf_field < 0 || tf_field >= n_fields || !(vmax > vmin) || !(step_vox > 0) || !(ref_step > 0))
@@ -410,6 +421,7 @@ int oracle_render(int n_fields, int n, const float *const *fields, double r_inne
         if (composited) composited[k] = r.composited;
         if (fragile) fragile[k] = r.fragile;
         if (pathlen) pathlen[k] = r.pathlen;
+        if (depth) depth[k] = r.depth;
     }
     return 0;
 }

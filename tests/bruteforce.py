@@ -58,7 +58,7 @@ def segments(o, d, r_inner, r_outer):
 
 
 def render(level_fields, cam, width, height, step, *, active, lo, hi, tf_field, vmin, vmax,
-           tf_rgba, ref_step=2 / 256, ert=0.99, r_inner=0.55, r_outer=1.0, coord=None):
+           tf_rgba, ref_step=2 / 256, ert=0.99, r_inner=0.55, r_outer=1.0, coord=None, with_depth=False):
     f64 = lambda x: float(np.float32(x))
     lf = np.asarray(level_fields, np.float32).astype(np.float64)
     nf, n = lf.shape[0], lf.shape[1]
@@ -73,6 +73,7 @@ def render(level_fields, cam, width, height, step, *, active, lo, hi, tf_field, 
     rgba = np.zeros((height, width, 4))
     nominal = np.zeros((height, width), np.int64)
     composited = np.zeros((height, width), np.int64)
+    depth = np.full((height, width), np.inf)
     for py in range(height):
         for px in range(width):
             d = dirs[py, px]
@@ -120,4 +121,8 @@ def render(level_fields, cam, width, height, step, *, active, lo, hi, tf_field, 
             rgba[py, px, 3] = 1.0 - trans_after[stop - 1]
             nominal[py, px] = stop
             composited[py, px] = int(np.count_nonzero(keep[:stop] & (s[:stop, 3] > 0)))
+            if rgba[py, px, 3] > 0:
+                depth[py, px] = float(wgt @ tm[:stop]) / rgba[py, px, 3]
+    if with_depth:
+        return rgba, nominal, composited, depth
     return rgba, nominal, composited
