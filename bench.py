@@ -163,6 +163,55 @@ def jittered_timing(raypc, torch, ctx, vid, wl, lod, stream, n_passes=8, seed=0x
     return res
 
 
+WARP_BYTES_PER_PIXEL = 68  # key fill 8, depth 4, atomic 8, key read 8, RGBA gather 16, outputs 16 + 4 + 4
+
+
+def warp_timing(raypc, torch, ctx, vid, wl, lod, stream, calls=50):
+    """Image warping of the headline frame: the depth render against the plain frame, and the warp
+    of the rendered frame to a pose moved sideways by 0.1 and 0.2 (median of `calls` warps), with
+    the mean-abs error of the stale and of the warped frame against the frame rendered at the new
+    pose."""
+    cam = wl.camera.as_array()
+    W_, H_ = wl.width, wl.height
+    rgba = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
+    depth = torch.empty((H_, W_), dtype=torch.float32, device="cuda")
+    truth = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
+    out = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
+    out_d = torch.empty((H_, W_), dtype=torch.float32, device="cuda")
+    out_s = torch.empty((H_, W_), dtype=torch.int32, device="cuda")
+
+    def median_ms(fn, n):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for a, e in ev:
+            a.record(stream)
+            fn()
+            e.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(e) for a, e in ev]))
+
+    depth_ms = median_ms(lambda: raypc.render_depth(ctx, vid, cam, W_, H_, lod, wl.step, out=rgba, depth=depth,
+                                                    stream=stream), 20)
+    plain_ms = median_ms(lambda: raypc.render(ctx, vid, cam, W_, H_, lod, wl.step, out=truth, stream=stream), 20)
+    raypc.render_depth(ctx, vid, cam, W_, H_, lod, wl.step, out=rgba, depth=depth, stream=stream)
+    moves = {}
+    for dx in (0.1, 0.2):
+        c1 = cam.copy()
+        c1[0] += np.float32(dx)
+        ms = median_ms(lambda: raypc.warp(ctx, rgba, depth, cam, c1, out=out, out_depth=out_d, out_source=out_s,
+                                          stream=stream), calls)
+        raypc.render(ctx, vid, c1, W_, H_, lod, wl.step, out=truth, stream=stream)
+        torch.cuda.synchronize()
+        moves[f"eye x + {dx}"] = {
+            "warp_ms": ms, "gb_per_s": W_ * H_ * WARP_BYTES_PER_PIXEL / (ms * 1e-3) / 1e9,
+            "covered": float((out_s >= 0).float().mean().item()),
+            "mean_abs_err_stale": float((rgba - truth).abs().mean().item()),
+            "mean_abs_err_warped": float((out - truth).abs().mean().item())}
+    res = {"pixels": W_ * H_, "render_depth_ms": depth_ms, "render_ms": plain_ms,
+           "alg_bytes_per_pixel": WARP_BYTES_PER_PIXEL, "moves": moves}
+    print(f"[bench] image warp: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def pc_lines_timing(raypc, torch, W, ctx, vid, wl, stream, n_lines=100_000, n_bins=64, calls=50):
     """The parallel-coordinates lines of the paper's preprocessing (up to 100 000 random shell cells):
     values, brush flags and 64-bin histograms of all / passing lines per axis, for the headline
@@ -398,6 +447,7 @@ def main():
     sweep_result = None
     pc_result = None
     jit_result = None
+    warp_result = None
     storages = args.storages.split(",")
     bpv = {"f32": 4, "f16": 2, "u8": 1, "f32c": 4, "f16c": 2, "u8c": 1}
 
@@ -478,6 +528,7 @@ def main():
         if si == 0:
             pc_result = pc_lines_timing(raypc, torch, W, ctx, vid, wl, stream)
             jit_result = jittered_timing(raypc, torch, ctx, vid, wl, lod, stream)
+            warp_result = warp_timing(raypc, torch, ctx, vid, wl, lod, stream)
         raypc.unload(ctx, vid)
 
     head = storages[0]
@@ -545,6 +596,7 @@ def main():
         "brush_axis_sweep": sweep_result,
         "pc_lines": pc_result,
         "jittered_passes": jit_result,
+        "image_warp": warp_result,
         "cpu_baseline": cpu_baseline,
     }
     raypc.destroy(ctx)

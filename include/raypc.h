@@ -234,6 +234,44 @@ int raypc_render_jittered(raypc_ctx *ctx, int volume_id, const raypc_camera *cam
                           float step, int pass, int n_passes, uint64_t seed, float *rgba_out, float *mean_inout,
                           uint32_t *nominal, uint32_t *composited, void *stream);
 
+/* raypc_render plus the depth that image warping reprojects with (Sections 2 and 2.2 warp the last
+ * delivered image to fill the frames the renderer has not produced yet; the paper names no depth,
+ * so the one taken is this): depth_out (device, H x W float32) receives the mean distance from the
+ * eye, along the unit ray, of the composited samples' midpoints, each weighted by its share
+ * T_before * alpha of the pixel's opacity (the weights sum to the opacity 1 - T, before any
+ * background), and +inf where nothing was composited.  rgba_out is exactly raypc_render's image.
+ * depth_out must not be NULL.  Async on `stream`.  Errors: as raypc_render. */
+int raypc_render_depth(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height, int lod,
+                       float step, float *rgba_out, float *depth_out, void *stream);
+
+/* Image warping of a frame to another camera pose (Sections 2 and 2.2: the display hides the
+ * renderer's varying frame rate and latency by warping the last image it delivered).  Inputs
+ * (device): rgba (src_height x src_width x 4 float32) and depth (src_height x src_width float32,
+ * as raypc_render_depth writes it; +inf or NaN: a point at infinity) of a frame rendered with
+ * src_cam.  Every source pixel's ray (through its centre, as the render casts it) is followed to
+ * its depth and the point projected through dst_cam; it lands on the destination pixel containing
+ * the projection unless it lies on or behind dst_cam's image plane or outside its image.  Per
+ * destination pixel the point nearest to dst_cam's eye wins (the lowest source index among equal
+ * distances).  A pixel nothing landed on takes the winner of its eight neighbours farthest from
+ * the eye (the highest source index among equal distances), else stays empty.  The landing
+ * pixel and the distance are decided in float32, one correctly rounded operation at a time in the
+ * order: sx = (((px + 0.5) (2/W)) - 1) tan(fov/2) W/H, sy = (1 - (py + 0.5) (2/H)) tan(fov/2),
+ * e = (fwd + sx right) + sy up, n = e / sqrt((e.x e.x + e.y e.y) + e.z e.z), v = (eye + d n) -
+ * dst_eye (v = n at infinity), z = v . fwd' (same summation order), x = (v . right') / (z tan'
+ * W'/H'), y = (v . up') / (z tan'), landing pixel (floor((x + 1) (W'/2)), floor((1 - y) (H'/2))),
+ * distance sqrt(v . v); the camera frames are those of raypc_render (double, rounded to float32).
+ * Outputs (device, dst_height x dst_width): rgba_out = the winner's RGBA unchanged (0 where empty);
+ * depth_out (may be NULL) = the winner's distance from dst_cam's eye (+inf where empty);
+ * source_out (may be NULL) = the winner's linear source index py * src_width + px (-1 where
+ * empty).  Outputs must not overlap the inputs or each other.  The context keeps an 8-byte-per-
+ * destination-pixel z-buffer, grown (after a device synchronisation) when a larger image comes;
+ * warps in flight on different streams of one context race on it.  Sizes 1..16384 per side.
+ * Async on `stream`.  Errors: RAYPC_ERR_INVALID (NULL input or output image, bad camera or size,
+ * overlapping buffers), RAYPC_ERR_NOMEM. */
+int raypc_warp(raypc_ctx *ctx, const raypc_camera *src_cam, int src_width, int src_height, const float *rgba,
+               const float *depth, const raypc_camera *dst_cam, int dst_width, int dst_height, float *rgba_out,
+               float *depth_out, int32_t *source_out, void *stream);
+
 /* ---------------------------------------------------------------- debug exports
  * For parity tests and accounting.  All outputs are device buffers (async). */
 

@@ -371,6 +371,7 @@ void raypc_destroy(raypc_ctx* ctx) {
     (void)hipDeviceSynchronize();
     for (auto& kv : ctx->vols) free_volume(kv.second);
     for (auto& t : ctx->tf) (void)hipFree(t.dev);
+    if (ctx->warp_keys) (void)hipFree(ctx->warp_keys);
     delete ctx;
 }
 
@@ -662,6 +663,99 @@ int raypc_render_jittered(raypc_ctx* ctx, int volume_id, const raypc_camera* cam
     a.mean = reinterpret_cast<float4*>(mean_inout);
     HIP_TRY(launch_render_jittered(a, storage, nominal != nullptr || composited != nullptr, s),
             "jittered ray-march kernel launch");
+    return RAYPC_OK;
+}
+
+int raypc_render_depth(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
+                       float step, float* rgba_out, float* depth_out, void* stream) {
+    if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
+    if (!depth_out) return fail(RAYPC_ERR_INVALID, "depth_out is NULL");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Volume* v = find_volume(ctx, volume_id);
+    if (!v) return fail(RAYPC_ERR_INVALID, "unknown volume id %d", volume_id);
+    RenderArgs a;
+    int storage = 0, level = 0;
+    int rc = prepare_render(ctx, volume_id, cam, width, height, lod, step, v->active, v->lo, v->hi, v->coord, 0, rgba_out,
+                            true, s, a, storage, level, nullptr);
+    if (rc) return rc;
+    a.depth = depth_out;
+    HIP_TRY(launch_render_depth(a, storage, s), "depth ray-march kernel launch");
+    return RAYPC_OK;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return a && b && x < y + nb && y < x + na;
+}
+
+int raypc_warp(raypc_ctx* ctx, const raypc_camera* src_cam, int src_width, int src_height, const float* rgba,
+               const float* depth, const raypc_camera* dst_cam, int dst_width, int dst_height, float* rgba_out,
+               float* depth_out, int32_t* source_out, void* stream) {
+    if (!ctx || !rgba || !depth || !rgba_out) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    if (src_width < 1 || src_width > 16384 || src_height < 1 || src_height > 16384 || dst_width < 1 ||
+        dst_width > 16384 || dst_height < 1 || dst_height > 16384)
+        return fail(RAYPC_ERR_INVALID, "image sizes %dx%d -> %dx%d outside [1, 16384]", src_width, src_height,
+                    dst_width, dst_height);
+    const size_t ns = static_cast<size_t>(src_width) * src_height, nd = static_cast<size_t>(dst_width) * dst_height;
+    const void* inputs[2] = {rgba, depth};
+    const size_t in_bytes[2] = {ns * 16, ns * 4};
+    const void* outputs[3] = {rgba_out, depth_out, source_out};
+    const size_t out_bytes[3] = {nd * 16, nd * 4, nd * 4};
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 2; ++j)
+            if (overlaps(outputs[i], out_bytes[i], inputs[j], in_bytes[j]))
+                return fail(RAYPC_ERR_INVALID, "an output buffer overlaps an input (the warp is not in place)");
+        for (int j = i + 1; j < 3; ++j)
+            if (overlaps(outputs[i], out_bytes[i], outputs[j], out_bytes[j]))
+                return fail(RAYPC_ERR_INVALID, "output buffers overlap");
+    }
+    RenderArgs cs, cd;
+    std::memset(&cs, 0, sizeof(cs));
+    std::memset(&cd, 0, sizeof(cd));
+    int rc = camera_setup(src_cam, src_width, src_height, cs);
+    if (rc) return rc;
+    rc = camera_setup(dst_cam, dst_width, dst_height, cd);
+    if (rc) return rc;
+    WarpArgs w;
+    std::memset(&w, 0, sizeof(w));
+    auto frame = [](const RenderArgs& r, WarpCamera& c) {
+        for (int k = 0; k < 3; ++k) {
+            c.eye[k] = r.eye[k];
+            c.fwd[k] = r.fwd[k];
+            c.right[k] = r.right[k];
+            c.up[k] = r.upv[k];
+        }
+        c.sx_scale = r.sx_scale;
+        c.sy_scale = r.sy_scale;
+        c.inv_w2 = r.inv_w2;
+        c.inv_h2 = r.inv_h2;
+        c.width = r.width;
+        c.height = r.height;
+    };
+    frame(cs, w.src);
+    frame(cd, w.dst);
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (nd > ctx->warp_keys_n) {
+        // a warp still in flight may use the old buffer
+        HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize before growing the warp buffer");
+        if (ctx->warp_keys) (void)hipFree(ctx->warp_keys);
+        ctx->warp_keys = nullptr;
+        ctx->warp_keys_n = 0;
+        if (hipMalloc(reinterpret_cast<void**>(&ctx->warp_keys), nd * sizeof(unsigned long long)) != hipSuccess)
+            return fail(RAYPC_ERR_NOMEM, "warp z-buffer of %zu pixels", nd);
+        ctx->warp_keys_n = nd;
+    }
+    w.rgba = reinterpret_cast<const float4*>(rgba);
+    w.depth = depth;
+    w.n_src = static_cast<uint32_t>(ns);
+    w.keys = ctx->warp_keys;
+    w.out = reinterpret_cast<float4*>(rgba_out);
+    w.out_depth = depth_out;
+    w.out_src = source_out;
+    HIP_TRY(launch_warp(w, static_cast<hipStream_t>(stream)), "warp kernel launches");
     return RAYPC_OK;
 }
 

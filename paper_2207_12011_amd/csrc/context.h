@@ -71,6 +71,8 @@ struct raypc_ctx {
     bool has_bg = false;
     std::mutex mu;  // guards state shared with the serving thread
     raypc::Server* server = nullptr;
+    unsigned long long* warp_keys = nullptr;  // image-warp z-buffer, grown on demand
+    size_t warp_keys_n = 0;
 };
 
 

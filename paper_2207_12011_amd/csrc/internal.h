@@ -180,9 +180,30 @@ struct RenderArgs {
     uint32_t pass, n_passes;
     float inv_pass1;
     float4* mean;
+    float* depth;                 // depth kernels only: H x W opacity-weighted depth (+inf: nothing composited)
 };
 hipError_t launch_render(const RenderArgs& a, int kind, bool counts, hipStream_t s);
 hipError_t launch_render_jittered(const RenderArgs& a, int kind, bool counts, hipStream_t s);
+hipError_t launch_render_depth(const RenderArgs& a, int kind, hipStream_t s);
+
+// Image warping: a camera's frame in float32 (the render's frame), and one warp's buffers.
+struct WarpCamera {
+    float eye[3], fwd[3], right[3], up[3];
+    float sx_scale, sy_scale;     // tan(fov/2) * aspect, tan(fov/2)
+    float inv_w2, inv_h2;         // 2 / W, 2 / H
+    int width, height;
+};
+struct WarpArgs {
+    WarpCamera src, dst;
+    const float4* rgba;           // src H x W
+    const float* depth;           // src H x W
+    uint32_t n_src;               // src H * W
+    unsigned long long* keys;     // dst H x W z-buffer (scratch)
+    float4* out;                  // dst H x W
+    float* out_depth;             // may be null
+    int32_t* out_src;             // may be null
+};
+hipError_t launch_warp(const WarpArgs& a, hipStream_t s);
 // Work of one batched launch, passed by value in the kernel arguments: range r covers items
 // [end[r-1], end[r]) (end[-1] = 0), which march tiles first[r], first[r] + 1, ... of the request whose
 // arguments are descs[slot[r]].  Every descriptor's volume uses the launch's kernel kind.

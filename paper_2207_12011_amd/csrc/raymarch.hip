@@ -280,8 +280,10 @@ __device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) 
 // One 8 x 8 pixel tile (index blk in row-major tile order) of the image described by A, marched by
 // the calling 256-thread block.  NB is the number of brushed fields, or kRuntimeNB to read it from A.
 // JIT: a jittered progressive pass (the sample grid of every segment starts s ds before it, so the
-// first and last samples of a segment are partial).
-template <int K, int NB, bool COUNTS, bool JIT = false>
+// first and last samples of a segment are partial).  DEPTH: also write the opacity-weighted depth, the
+// mean distance of the composited samples, each weighted by its share w of the pixel's opacity (the
+// depth that image warping reprojects with; +inf where nothing was composited).
+template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false>
 __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, const float4* s_tf) {
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
@@ -344,6 +346,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     const float r_full = ds * A.inv_ref;
 
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    float D = 0.0f;  // DEPTH: sum of w tm over the composited samples
     uint32_t cnt_nom = 0, cnt_comp = 0;
     uint32_t last_brick = 0xFFFFFFFFu;
     int seg = 0, j0 = 0;  // j0: first sample of the quad's current group of four
@@ -545,6 +548,14 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                 C1 = fmaf(w3, g3, C1);
                 C2 = fmaf(w3, b3, C2);
             }
+            if constexpr (DEPTH) {
+                // samples that were not composited have w = 0 and a finite tm: no change
+                D = fmaf(w0, quad_bcast<0>(tm), D);
+                const float m1 = quad_bcast<1>(tm), m2 = quad_bcast<2>(tm), m3 = quad_bcast<3>(tm);
+                if (first_stop >= 1) D = fmaf(w1, m1, D);
+                if (first_stop >= 2) D = fmaf(w2, m2, D);
+                if (first_stop >= 3) D = fmaf(w3, m3, D);
+            }
         }
         if constexpr (COUNTS) {
             const unsigned long long comp_mask = __ballot(contributes);
@@ -577,7 +588,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     }
 
     if (!inside || sub != 0) return;
-    float4 res = make_float4(C0, C1, C2, 1.0f - T);
+    const float acc = 1.0f - T;
+    float4 res = make_float4(C0, C1, C2, acc);
     if (A.has_bg) {
         res.x = fmaf(T, A.bg[0], res.x);
         res.y = fmaf(T, A.bg[1], res.y);
@@ -606,9 +618,13 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
         if (A.nominal) A.nominal[pix] = cnt_nom;
         if (A.composited) A.composited[pix] = cnt_comp;
     }
+    if constexpr (DEPTH) {
+        // the weights sum to the opacity 1 - T (before the background, which has no depth)
+        A.depth[pix] = acc > 0.0f ? D / acc : INFINITY;
+    }
 }
 
-template <int K, int NB, bool COUNTS, bool JIT = false>
+template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false>
 __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     int bx, by;
     interleaved_tile(blockIdx.x, A.blocks_x, bx, by);
@@ -619,7 +635,7 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
         s_tf[threadIdx.x] = make_float4(e.x, e.y, e.z, e.w);
     }
     __syncthreads();
-    march_tile<K, NB, COUNTS, JIT>(A, bx, by, s_tf);
+    march_tile<K, NB, COUNTS, JIT, DEPTH>(A, bx, by, s_tf);
 }
 
 // Batched launch: item j marches one tile of one request, as the ranges in the kernel arguments
@@ -719,6 +735,26 @@ hipError_t launch_jit_kind(const RenderArgs& a, int kind, hipStream_t s) {
 
 hipError_t launch_render_jittered(const RenderArgs& a, int kind, bool counts, hipStream_t s) {
     return counts ? launch_jit_kind<true>(a, kind, s) : launch_jit_kind<false>(a, kind, s);
+}
+
+namespace {
+template <int K>
+hipError_t launch_depth(const RenderArgs& a, hipStream_t s) {
+    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x)), block(256);
+    hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, false, false, true>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_render_depth(const RenderArgs& a, int kind, hipStream_t s) {
+    switch (kind) {
+        case kKindF32: return launch_depth<kKindF32>(a, s);
+        case kKindF16: return launch_depth<kKindF16>(a, s);
+        case kKindU8: return launch_depth<kKindU8>(a, s);
+        case kKindF32Rec: return launch_depth<kKindF32Rec>(a, s);
+        case kKindF16Rec: return launch_depth<kKindF16Rec>(a, s);
+        default: return launch_depth<kKindU8Rec>(a, s);
+    }
 }
 
 hipError_t launch_render(const RenderArgs& a, int kind, bool counts, hipStream_t s) {

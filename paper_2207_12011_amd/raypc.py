@@ -89,6 +89,9 @@ _export_subskip = _sig("raypc_export_subskip", _I, _P, _I, _I, _I, _P, _P)
 _export_mask = _sig("raypc_export_voxel_mask", _I, _P, _I, _I, _P, _P)
 _render_debug = _sig("raypc_render_debug", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _P, _I,
                      _P)
+_render_depth = _sig("raypc_render_depth", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P)
+_warp = _sig("raypc_warp", _I, _P, ctypes.POINTER(Camera), _I, _I, _P, _P, ctypes.POINTER(Camera), _I, _I, _P, _P, _P,
+             _P)
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", _I), ("tiles_per_step", _I),
@@ -127,7 +130,7 @@ EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_po
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
             "raypc_export_level", "raypc_export_minmax", "raypc_export_minmax_sub", "raypc_export_skiplist",
             "raypc_export_subskip", "raypc_export_voxel_mask", "raypc_render_debug", "raypc_pc_lines",
-            "raypc_render_jittered", "raypc_set_coordinate_brush"]
+            "raypc_render_jittered", "raypc_set_coordinate_brush", "raypc_render_depth", "raypc_warp"]
 
 
 class RaypcError(RuntimeError):
@@ -314,6 +317,40 @@ def render_jittered(ctx, volume_id: int, camera, width: int, height: int, lod: i
                             out.data_ptr(), mptr, None if nom is None else nom.data_ptr(),
                             None if comp is None else comp.data_ptr(), _stream(stream)))
     return out, nom, comp
+
+
+def render_depth(ctx, volume_id: int, camera, width: int, height: int, lod: int = -1, step: float = 0.5,
+                 out: Optional[torch.Tensor] = None, depth: Optional[torch.Tensor] = None, stream=None):
+    """Async render plus opacity-weighted depth: (rgba [H,W,4] f32, depth [H,W] f32) CUDA tensors."""
+    out = _image(out, width, height, "cuda")
+    if depth is None:
+        depth = torch.empty((height, width), dtype=torch.float32, device="cuda")
+    _dptr(depth, torch.float32, width * height, "depth")
+    _check(_render_depth(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height), int(lod),
+                         float(step), out.data_ptr(), depth.data_ptr(), _stream(stream)))
+    return out, depth
+
+
+def warp(ctx, rgba: torch.Tensor, depth: torch.Tensor, src_camera, dst_camera, dst_width: Optional[int] = None,
+         dst_height: Optional[int] = None, out: Optional[torch.Tensor] = None, out_depth: Optional[torch.Tensor] = None,
+         out_source: Optional[torch.Tensor] = None, want_depth: bool = True, want_source: bool = True, stream=None):
+    """Warp a frame (rgba [H,W,4] f32, depth [H,W] f32 CUDA tensors rendered with src_camera) to
+    dst_camera: (rgba [H',W',4] f32, depth [H',W'] f32 or None, source [H',W'] int32 or None), async."""
+    sh, sw = int(rgba.shape[0]), int(rgba.shape[1])
+    dw = sw if dst_width is None else int(dst_width)
+    dh = sh if dst_height is None else int(dst_height)
+    _dptr(rgba, torch.float32, sw * sh * 4, "rgba")
+    _dptr(depth, torch.float32, sw * sh, "depth")
+    out = _image(out, dw, dh, "cuda")
+    if want_depth and out_depth is None:
+        out_depth = torch.empty((dh, dw), dtype=torch.float32, device="cuda")
+    if want_source and out_source is None:
+        out_source = torch.empty((dh, dw), dtype=torch.int32, device="cuda")
+    dptr = None if out_depth is None else _dptr(out_depth, torch.float32, dw * dh, "out_depth")
+    sptr = None if out_source is None else _dptr(out_source, torch.int32, dw * dh, "out_source")
+    _check(_warp(ctx, ctypes.byref(Camera.make(src_camera)), sw, sh, rgba.data_ptr(), depth.data_ptr(),
+                 ctypes.byref(Camera.make(dst_camera)), dw, dh, out.data_ptr(), dptr, sptr, _stream(stream)))
+    return out, out_depth, out_source
 
 
 # ----------------------------------------------------------------------------- exports
