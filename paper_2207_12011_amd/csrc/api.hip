@@ -241,6 +241,54 @@ uint32_t coord_kernel_form(const CoordBrush& c, float clo[4], float chi[4]) {
     return mask;
 }
 
+// Greedy test order: after the fields chosen so far, the field that the fewest sampled cells still
+// passing them pass, ties to the lower field index.  Only cells whose sub-brick the skip rule keeps
+// count (the renderer evaluates no other sample).  A sample that fails a brush test fetches no
+// further field, so this keeps the expected number of fields fetched per sample low when fields are
+// correlated (a field that mostly rejects the same samples as one already tested saves little).
+void brush_order(const Volume* v, const uint8_t* active, const float* lo, const float* hi, int* order,
+                 int& n_brushed) {
+    int fields[kMaxFields], m = 0;
+    for (int f = 0; f < v->nf; ++f)
+        if (active[f]) fields[m++] = f;
+    n_brushed = m;
+    const int k = v->order_k, words = (k + 63) / 64;
+    if (m <= 1 || k == 0) {
+        for (int i = 0; i < m; ++i) order[i] = fields[i];
+        return;
+    }
+    constexpr int kWords = (kOrderSample + 63) / 64;
+    uint64_t pass[kMaxFields][kWords] = {}, alive[kWords];
+    uint64_t kept[kWords];
+    for (int w = 0; w < words; ++w) kept[w] = ~0ull;
+    for (int i = 0; i < m; ++i) {
+        const float* x = &v->order_sample[static_cast<size_t>(fields[i]) * k];
+        const float2* mm = &v->order_sub[static_cast<size_t>(fields[i]) * k];
+        const float l = lo[fields[i]], h = hi[fields[i]];
+        for (int c = 0; c < k; ++c) {
+            if (x[c] >= l && x[c] <= h) pass[i][c >> 6] |= 1ull << (c & 63);
+            if (!(mm[c].x <= h && mm[c].y >= l && l <= h)) kept[c >> 6] &= ~(1ull << (c & 63));
+        }
+    }
+    for (int w = 0; w < words; ++w) alive[w] = kept[w];
+    bool used[kMaxFields] = {};
+    for (int pos = 0; pos < m; ++pos) {
+        int best = -1, best_count = 0;
+        for (int i = 0; i < m; ++i) {
+            if (used[i]) continue;
+            int cnt = 0;
+            for (int w = 0; w < words; ++w) cnt += __builtin_popcountll(alive[w] & pass[i][w]);
+            if (best < 0 || cnt < best_count) {
+                best = i;
+                best_count = cnt;
+            }
+        }
+        used[best] = true;
+        order[pos] = fields[best];
+        for (int w = 0; w < words; ++w) alive[w] &= pass[best][w];
+    }
+}
+
 int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
                    float step, const uint8_t* brush_active, const float* brush_lo, const float* brush_hi,
                    const CoordBrush& coord, int tf_slot, float* rgba_out, bool use_volume_state, hipStream_t s,
@@ -272,10 +320,12 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
     if (rc) return rc;
     const Level& L = v->lv[lod];
 
+    int order[kMaxFields], n_brushed = 0;
+    brush_order(v, brush_active, brush_lo, brush_hi, order, n_brushed);
     int k = 0;
     bool tf_brushed = false;
-    for (int f = 0; f < v->nf; ++f) {
-        if (!brush_active[f]) continue;
+    for (int i = 0; i < n_brushed; ++i) {
+        const int f = order[i];
         a.field[k] = L.data[f];
         a.u8par[k] = L.par[f];
         a.rec[k] = L.rec[f];
@@ -421,6 +471,37 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
     float* stage = nullptr;
     float* lvbuf[2] = {nullptr, nullptr};
     unsigned int* flag = nullptr;
+    // shell cells whose values estimate each brush's field selectivities: uniform over the cells whose
+    // centre lies in the shell, drawn with a SplitMix64 stream (Steele, Lea and Flood, OOPSLA 2014)
+    std::vector<uint32_t> cells;
+    {
+        uint64_t z = 0x2207120110ull;
+        const double h = 2.0 / n;
+        for (int tries = 0; static_cast<int>(cells.size()) < kOrderSample && tries < 64 * kOrderSample; ++tries) {
+            z += 0x9E3779B97F4A7C15ull;
+            uint64_t r = z;
+            r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
+            r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
+            r ^= r >> 31;
+            const uint32_t i = static_cast<uint32_t>(r % nvox);
+            const double x = (i % n + 0.5) * h - 1.0, y = ((i / n) % n + 0.5) * h - 1.0;
+            const double zc = (i / (static_cast<size_t>(n) * n) + 0.5) * h - 1.0;
+            const double rad = std::sqrt(x * x + y * y + zc * zc);
+            if (rad >= r_inner && rad <= r_outer) cells.push_back(i);
+        }
+    }
+    const int n_cells = static_cast<int>(cells.size());
+    std::vector<uint32_t> cell_sub(cells.size());  // index of each cell's sub-brick in the level-0 tables
+    for (int c = 0; c < n_cells; ++c) {
+        const uint32_t i = cells[c], x = i % n, y = (i / n) % n, zc = i / (static_cast<uint32_t>(n) * n);
+        const uint32_t nbk = static_cast<uint32_t>(n / kBrick);
+        const uint32_t brick = ((zc >> 3) * nbk + (y >> 3)) * nbk + (x >> 3);
+        cell_sub[c] = brick * 8 + (((x >> 2) & 1) | (((y >> 2) & 1) << 1) | (((zc >> 2) & 1) << 2));
+    }
+    uint32_t* d_cells = nullptr;
+    uint32_t* d_cell_sub = nullptr;
+    float* d_sample = nullptr;
+    float2* d_sub = nullptr;
     do {
         for (int l = 0; l < n_lods && !rc; ++l) {
             Level& L = v->lv[l];
@@ -442,6 +523,18 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
         if (n_lods > 1 && (rc = tmp_alloc(reinterpret_cast<void**>(&lvbuf[0]), nvox / 8 * sizeof(float)))) break;
         if (n_lods > 2 && (rc = tmp_alloc(reinterpret_cast<void**>(&lvbuf[1]), nvox / 64 * sizeof(float)))) break;
         if ((rc = tmp_alloc(reinterpret_cast<void**>(&flag), sizeof(unsigned int)))) break;
+        if (n_cells > 0) {
+            if ((rc = tmp_alloc(reinterpret_cast<void**>(&d_cells), n_cells * sizeof(uint32_t)))) break;
+            if ((rc = tmp_alloc(reinterpret_cast<void**>(&d_sample), static_cast<size_t>(n_fields) * n_cells * sizeof(float))))
+                break;
+            if ((rc = tmp_alloc(reinterpret_cast<void**>(&d_cell_sub), n_cells * sizeof(uint32_t)))) break;
+            if ((rc = tmp_alloc(reinterpret_cast<void**>(&d_sub), static_cast<size_t>(n_fields) * n_cells * sizeof(float2))))
+                break;
+            hipError_t ce = hipMemcpyAsync(d_cells, cells.data(), n_cells * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+            if (ce == hipSuccess)
+                ce = hipMemcpyAsync(d_cell_sub, cell_sub.data(), n_cells * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+            if (ce != hipSuccess) { rc = hip_fail(ce, "hipMemcpyAsync(cells)"); break; }
+        }
         hipError_t e = hipMemsetAsync(flag, 0, sizeof(unsigned int), s);
         if (e != hipSuccess) { rc = hip_fail(e, "hipMemsetAsync"); break; }
         for (int f = 0; f < n_fields && !rc; ++f) {
@@ -452,6 +545,10 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 src = stage;
             }
             if ((e = launch_count_nonfinite(src, nvox, flag, s)) != hipSuccess) { rc = hip_fail(e, "finite check"); break; }
+            if ((e = launch_gather_cells(src, d_cells, n_cells, d_sample + static_cast<size_t>(f) * n_cells, s)) != hipSuccess) {
+                rc = hip_fail(e, "cell sample");
+                break;
+            }
             const float* cur = src;
             for (int l = 0; l < n_lods; ++l) {
                 Level& L = v->lv[l];
@@ -462,12 +559,25 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 }
                 if ((e = launch_encode(cur, L.n, storage, L.data[f], L.par[f], s)) != hipSuccess) { rc = hip_fail(e, "encode"); break; }
                 if ((e = launch_minmax(L.data[f], L.par[f], L.n, storage, L.mm[f], L.mm_sub[f], s)) != hipSuccess) { rc = hip_fail(e, "min/max"); break; }
+                if (l == 0 && (e = launch_gather_pairs(L.mm_sub[f], d_cell_sub, n_cells, d_sub + static_cast<size_t>(f) * n_cells,
+                                                       s)) != hipSuccess) {
+                    rc = hip_fail(e, "sub-brick sample");
+                    break;
+                }
                 if (v->records && (e = launch_records(L.data[f], L.par[f], L.n, storage, L.rec[f], s)) != hipSuccess) { rc = hip_fail(e, "neighbourhood records"); break; }
             }
         }
         if (rc) break;
         unsigned int h_flag = 0;
+        v->order_sample.resize(static_cast<size_t>(n_fields) * n_cells);
+        v->order_sub.resize(static_cast<size_t>(n_fields) * n_cells);
+        v->order_k = n_cells;
         e = hipMemcpyAsync(&h_flag, flag, sizeof(h_flag), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && n_cells > 0)
+            e = hipMemcpyAsync(v->order_sample.data(), d_sample, v->order_sample.size() * sizeof(float),
+                               hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && n_cells > 0)
+            e = hipMemcpyAsync(v->order_sub.data(), d_sub, v->order_sub.size() * sizeof(float2), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { rc = hip_fail(e, "load synchronisation"); break; }
         if (h_flag) rc = fail(RAYPC_ERR_INVALID, "input contains a non-finite value");

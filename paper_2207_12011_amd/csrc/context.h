@@ -47,7 +47,20 @@ struct Volume {
     uint64_t bytes = 0;
     std::vector<void*> allocs;
     int refs = 0;  // serving requests queued or running on this volume
+    // a fixed random sample of shell cells, from which each brush's field test order is chosen: their
+    // values and the (min, max) of their 4^3 sub-bricks at level 0, field after field (order_k per field)
+    int order_k = 0;
+    std::vector<float> order_sample;
+    std::vector<float2> order_sub;
 };
+
+constexpr int kOrderSample = 2048;  // sampled shell cells per volume
+
+// The order in which a render tests the brushed fields (brush_active / lo / hi per field of v): order[0 ..
+// n_brushed) lists the active fields.  Every order gives the same image; the chosen one fetches fewer
+// fields per sample on average.
+void brush_order(const Volume* v, const uint8_t* active, const float* lo, const float* hi, int* order,
+                 int& n_brushed);
 
 struct TFSlot {
     bool defined = false;

@@ -70,6 +70,8 @@ __device__ __forceinline__ float cell_coord(int i, int n) {
 
 // ------------------------------------------------------------------ preprocessing launchers
 hipError_t launch_count_nonfinite(const float* x, size_t count, unsigned int* flag, hipStream_t s);
+hipError_t launch_gather_cells(const float* x, const uint32_t* cells, int k, float* out, hipStream_t s);
+hipError_t launch_gather_pairs(const float2* x, const uint32_t* idx, int k, float2* out, hipStream_t s);
 // out[N/2]^3 = 2x2x2 mean of in[N]^3 (both linear [z][y][x] float32).
 hipError_t launch_lod_build(const float* in, int n, float* out, hipStream_t s);
 // Encode a linear float32 level into brick-ordered storage (u8 also writes per-brick (scale, offset)).

@@ -50,6 +50,20 @@ __global__ void count_nonfinite_kernel(const float* __restrict__ x, size_t count
     if (__any(bad) && bad) atomicOr(flag, 1u);
 }
 
+// Values of one float32 field at k linear voxel indices (the cells that estimate brush selectivity).
+__global__ void gather_cells_kernel(const float* __restrict__ x, const uint32_t* __restrict__ cells, int k,
+                                    float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) out[i] = x[cells[i]];
+}
+
+// (min, max) pairs of one field's sub-brick table at k indices.
+__global__ void gather_pairs_kernel(const float2* __restrict__ x, const uint32_t* __restrict__ idx, int k,
+                                    float2* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) out[i] = x[idx[i]];
+}
+
 __global__ void lod_build_kernel(const float* __restrict__ in, int n, float* __restrict__ out) {
     const int m = n >> 1;
     const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
@@ -383,6 +397,20 @@ inline unsigned blocks_for(size_t count, unsigned threads) {
 hipError_t launch_count_nonfinite(const float* x, size_t count, unsigned int* flag, hipStream_t s) {
     const unsigned blocks = static_cast<unsigned>(std::min<size_t>(blocks_for(count, 256), 8192));
     hipLaunchKernelGGL(count_nonfinite_kernel, dim3(std::max(blocks, 1u)), dim3(256), 0, s, x, count, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_cells(const float* x, const uint32_t* cells, int k, float* out, hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_cells_kernel, dim3(blocks_for(static_cast<size_t>(k), 256)), dim3(256), 0, s, x, cells,
+                       k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_pairs(const float2* x, const uint32_t* idx, int k, float2* out, hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_pairs_kernel, dim3(blocks_for(static_cast<size_t>(k), 256)), dim3(256), 0, s, x, idx,
+                       k, out);
     return hipGetLastError();
 }
 

@@ -43,3 +43,29 @@ def sample_pixels(width: int, height: int, k: int, seed: int = 0) -> np.ndarray:
     pix = rng.choice(width * height, size=min(k, width * height), replace=False)
     corners = np.array([0, width - 1, (height - 1) * width, height * width - 1])
     return np.unique(np.concatenate([pix, corners]))
+
+
+def depth_tolerance(alpha, r_outer=1.0):
+    """|depth error| bound on a non-fragile pixel.  Writing the depth as t0 + sum w (t - t0) / A with
+    t - t0 in [0, 2 r_outer], the numerator is a colour channel scaled by 2 r_outer, so it carries
+    at most RGBA_TOL * 2 r_outer of error; the opacity A carries at most RGBA_TOL; together
+    |delta depth| <= 2 RGBA_TOL (2 r_outer) / A."""
+    return 2 * RGBA_TOL * 2 * r_outer / np.maximum(alpha, 1e-30)
+
+
+def check_depth(gpu_depth, ref: oracle.OracleImage, label: str = "", min_frac: float = 0.05) -> None:
+    """GPU opacity-weighted depth against the oracle's: defined (finite) on the same non-fragile
+    pixels, and within depth_tolerance of the oracle's opacity there."""
+    g = np.asarray(gpu_depth, np.float64).reshape(ref.depth.shape)
+    frag = ref.fragile.reshape(ref.depth.shape)
+    ok = (frag & oracle.FRAGILE_RGBA) == 0
+    inf_ref = np.isinf(ref.depth)
+    assert np.array_equal(np.isinf(g)[ok], inf_ref[ok]), f"{label}: depth defined on different pixels"
+    fin = ok & ~inf_ref
+    alpha = ref.rgba.reshape(*ref.depth.shape, 4)[..., 3]
+    err = np.abs(g[fin] - ref.depth[fin])
+    tol = depth_tolerance(alpha[fin])
+    print(f"[depth] {label}: {int(fin.sum())} px with depth, max err {err.max() if err.size else 0:.3e}, "
+          f"max err / bound {np.max(err / tol) if err.size else 0:.3e}", flush=True)
+    assert np.all(err <= tol), f"{label}: depth error above the bound"
+    assert fin.sum() > min_frac * fin.size

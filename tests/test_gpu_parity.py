@@ -16,7 +16,7 @@ import oracle
 from oracle import preprocess as pp
 from paper_2207_12011_amd import workloads as W
 
-from .parity import compare, sample_pixels
+from .parity import check_depth, compare, sample_pixels
 
 pytestmark = pytest.mark.gpu
 
@@ -393,6 +393,10 @@ def test_precision_512_full_size_sampled(rp, ctx, c2):
         assert np.array_equal(level.view(np.uint32), want_level.view(np.uint32))
         ref = oracle.render_workload(wl, want_level, pixels=pix)
         compare(rgba.reshape(-1, 4)[pix], ref, nom.reshape(-1)[pix], comp.reshape(-1)[pix], label=f"c2 {storage}")
+        # the depth that image warping reprojects with, from the same frame
+        rgba_d, dep = rp.render_depth(ctx, vid, wl.camera.as_array(), wl.width, wl.height, 0, wl.step)
+        assert np.array_equal(cpu(rgba_d), rgba)
+        check_depth(cpu(dep).reshape(-1)[pix], ref, label=f"c2 {storage} depth", min_frac=0.02)
         rp.unload(ctx, vid)
 
 

@@ -17,7 +17,7 @@ from oracle import preprocess as pp
 from oracle import warp as WP
 from paper_2207_12011_amd import workloads as W
 
-from .parity import RGBA_TOL, compare
+from .parity import check_depth, compare
 
 pytestmark = pytest.mark.gpu
 
@@ -44,30 +44,6 @@ def cpu(t):
 
 def cam(eye, target=(0, 0, 0), up=(0, 1, 0), fov=60.0):
     return np.array([*eye, *target, *up, fov], np.float32)
-
-
-def depth_tolerance(alpha, r_outer=1.0):
-    """|depth error| bound on a non-fragile pixel.  Writing the depth as t0 + sum w (t - t0) / A with
-    t - t0 in [0, 2 r_outer], the numerator is a colour channel scaled by 2 r_outer, so it carries
-    at most RGBA_TOL * 2 r_outer of error; the opacity A carries at most RGBA_TOL; together
-    |delta depth| <= 2 RGBA_TOL (2 r_outer) / A."""
-    return 2 * RGBA_TOL * 2 * r_outer / np.maximum(alpha, 1e-30)
-
-
-def check_depth(gpu_depth, ref, label):
-    g = np.asarray(gpu_depth, np.float64).reshape(ref.depth.shape)
-    frag = ref.fragile.reshape(ref.depth.shape)
-    ok = (frag & oracle.FRAGILE_RGBA) == 0
-    inf_ref = np.isinf(ref.depth)
-    assert np.array_equal(np.isinf(g)[ok], inf_ref[ok]), f"{label}: depth defined on different pixels"
-    fin = ok & ~inf_ref
-    alpha = ref.rgba.reshape(*ref.depth.shape, 4)[..., 3]
-    err = np.abs(g[fin] - ref.depth[fin])
-    tol = depth_tolerance(alpha[fin])
-    print(f"[depth] {label}: {int(fin.sum())} px with depth, max err {err.max() if err.size else 0:.3e}, "
-          f"max err / bound {np.max(err / tol) if err.size else 0:.3e}", flush=True)
-    assert np.all(err <= tol), f"{label}: depth error above the bound"
-    assert fin.sum() > 0.05 * fin.size
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "u8"])
