@@ -390,7 +390,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storages", default="f16,f32,u8,u8c",
                     help="first one is the headline value; a trailing c keeps only the compact layout")
-    ap.add_argument("--cpu-stride", type=int, default=2, help="oracle sample: every k-th row and column")
+    ap.add_argument("--cpu-stride", type=int, default=1, help="oracle sample: every k-th row and column")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--width", type=int, default=1920)
@@ -567,8 +567,9 @@ def main():
         dt = time.perf_counter() - t0
         ns = int(ref.nominal.astype(np.int64).sum())
         cpu_baseline = {"value": ns / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
-                        "sample": f"every {ordinal(args.cpu_stride)} row and column of the {W_}x{H_} frame "
-                                  f"({pix.size} px, {ns} nominal samples, {dt:.1f} s), brush 0, "
+                        "sample": (f"the whole {W_}x{H_} frame" if args.cpu_stride == 1 else
+                                   f"every {ordinal(args.cpu_stride)} row and column of the {W_}x{H_} frame") +
+                                  f" ({pix.size} px, {ns} nominal samples, {dt:.1f} s on {threads} threads), brush 0, "
                                   f"{head}-stored {wl.n}^3 x {wl.n_fields} level 0, FP64"}
 
     line = {

@@ -371,6 +371,38 @@ def test_single_request_256_full_size_sampled(rp, ctx, storage):
     rp.unload(ctx, vid)
 
 
+@pytest.mark.parametrize("storage", STORAGES)
+def test_field_order_does_not_change_the_image(rp, ctx, small5, storage):
+    """The renderer tests brushed fields in an order it picks per brush (to fetch fewer fields per
+    sample).  Loading the same fields in other orders (brush and transfer function permuted with
+    them) changes that order but never the image or the counts, which match the oracle."""
+    wl = small5
+    cam = wl.camera.as_array()
+    first = None
+    for perm in ([0, 1, 2, 3, 4], [4, 3, 2, 1, 0], [2, 0, 4, 1, 3]):
+        print(f"[case] field order {perm} {storage}", flush=True)
+        vid = rp.load_fields(ctx, torch.from_numpy(np.ascontiguousarray(wl.fields[perm])).cuda(), storage, 1,
+                             wl.r_inner, wl.r_outer)
+        rp.set_brush(ctx, vid, wl.brush.active[perm], wl.brush.lo[perm], wl.brush.hi[perm])
+        rp.set_transfer_function(ctx, 0, perm.index(wl.tf.field), wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
+        rp.set_options(ctx, wl.ert)
+        for act in (wl.brush.active[perm], np.array([1, 0, 1, 0, 1], np.uint8)[perm]):
+            rp.set_brush(ctx, vid, act, wl.brush.lo[perm], wl.brush.hi[perm])
+            got = gpu_render(rp, ctx, vid, wl, 0)
+            if first is None:
+                first = {}
+            key = tuple(act[np.argsort(perm)].tolist())
+            if key in first:
+                assert all(np.array_equal(a, b) for a, b in zip(got, first[key])), (perm, key)
+            else:
+                first[key] = got
+                level = pp.stored_levels(wl.fields[perm], 1, storage)[0]
+                ref = oracle.render_workload(wl, level, active=act, lo=wl.brush.lo[perm], hi=wl.brush.hi[perm],
+                                             tf_field=perm.index(wl.tf.field))
+                compare(got[0], ref, got[1], got[2], label=f"field order {perm} {storage}")
+        rp.unload(ctx, vid)
+
+
 @pytest.fixture(scope="module")
 def c2():
     return W.make_workload(2)
