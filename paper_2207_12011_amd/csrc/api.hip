@@ -242,12 +242,19 @@ uint32_t coord_kernel_form(const CoordBrush& c, float clo[4], float chi[4]) {
 }
 
 // Greedy test order: after the fields chosen so far, the field that the fewest sampled cells still
-// passing them pass, ties to the lower field index.  Only cells whose sub-brick the skip rule keeps
-// count (the renderer evaluates no other sample).  A sample that fails a brush test fetches no
+// passing them pass, ties to the lower field index.  Only cells whose sub-brick's value range meets
+// every brushed interval count (the skip rule drops the samples of the other sub-bricks before any
+// fetch).  A sample that fails a brush test fetches no
 // further field, so this keeps the expected number of fields fetched per sample low when fields are
 // correlated (a field that mostly rejects the same samples as one already tested saves little).
-void brush_order(const Volume* v, const uint8_t* active, const float* lo, const float* hi, int* order,
-                 int& n_brushed) {
+// 8 bytes holding 0 or 1 -> 8 bits (byte j -> bit j).
+static inline uint64_t pack8(const uint8_t* b) {
+    uint64_t x;
+    std::memcpy(&x, b, 8);
+    return (x * 0x0102040810204080ull) >> 56;
+}
+
+void brush_order(Volume* v, const uint8_t* active, const float* lo, const float* hi, int* order, int& n_brushed) {
     int fields[kMaxFields], m = 0;
     for (int f = 0; f < v->nf; ++f)
         if (active[f]) fields[m++] = f;
@@ -257,17 +264,36 @@ void brush_order(const Volume* v, const uint8_t* active, const float* lo, const 
         for (int i = 0; i < m; ++i) order[i] = fields[i];
         return;
     }
+    if (v->order_cached) {
+        bool same = true;
+        for (int f = 0; f < v->nf && same; ++f)
+            same = v->order_active[f] == (active[f] ? 1 : 0) &&
+                   (!active[f] || (v->order_lo[f] == lo[f] && v->order_hi[f] == hi[f]));
+        if (same) {
+            for (int i = 0; i < m; ++i) order[i] = v->order_fields[i];
+            return;
+        }
+    }
     constexpr int kWords = (kOrderSample + 63) / 64;
-    uint64_t pass[kMaxFields][kWords] = {}, alive[kWords];
-    uint64_t kept[kWords];
+    uint64_t pass[kMaxFields][kWords] = {}, alive[kWords], kept[kWords];
+    alignas(64) uint8_t pb[kWords * 64] = {}, kb[kWords * 64] = {};
     for (int w = 0; w < words; ++w) kept[w] = ~0ull;
     for (int i = 0; i < m; ++i) {
-        const float* x = &v->order_sample[static_cast<size_t>(fields[i]) * k];
-        const float2* mm = &v->order_sub[static_cast<size_t>(fields[i]) * k];
+        const size_t o = static_cast<size_t>(fields[i]) * k;
+        const float* x = &v->order_sample[o];
+        const float* slo = &v->order_sub_lo[o];
+        const float* shi = &v->order_sub_hi[o];
         const float l = lo[fields[i]], h = hi[fields[i]];
-        for (int c = 0; c < k; ++c) {
-            if (x[c] >= l && x[c] <= h) pass[i][c >> 6] |= 1ull << (c & 63);
-            if (!(mm[c].x <= h && mm[c].y >= l && l <= h)) kept[c >> 6] &= ~(1ull << (c & 63));
+        for (int c = 0; c < k; ++c) pb[c] = (x[c] >= l) & (x[c] <= h);
+        for (int c = 0; c < k; ++c) kb[c] = (slo[c] <= h) & (shi[c] >= l);
+        for (int w = 0; w < words; ++w) {
+            uint64_t p = 0, q = 0;
+            for (int j = 0; j < 8; ++j) {
+                p |= pack8(pb + w * 64 + 8 * j) << (8 * j);
+                q |= pack8(kb + w * 64 + 8 * j) << (8 * j);
+            }
+            pass[i][w] = p;
+            kept[w] &= l <= h ? q : 0;  // an empty interval keeps nothing
         }
     }
     for (int w = 0; w < words; ++w) alive[w] = kept[w];
@@ -287,6 +313,14 @@ void brush_order(const Volume* v, const uint8_t* active, const float* lo, const 
         order[pos] = fields[best];
         for (int w = 0; w < words; ++w) alive[w] &= pass[best][w];
     }
+    v->order_cached = true;
+    for (int f = 0; f < v->nf; ++f) {
+        v->order_active[f] = active[f] ? 1 : 0;
+        v->order_lo[f] = lo[f];
+        v->order_hi[f] = hi[f];
+    }
+    for (int i = 0; i < m; ++i) v->order_fields[i] = order[i];
+    v->order_n = m;
 }
 
 int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
@@ -570,15 +604,21 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
         if (rc) break;
         unsigned int h_flag = 0;
         v->order_sample.resize(static_cast<size_t>(n_fields) * n_cells);
-        v->order_sub.resize(static_cast<size_t>(n_fields) * n_cells);
+        std::vector<float2> sub_pairs(static_cast<size_t>(n_fields) * n_cells);
         v->order_k = n_cells;
         e = hipMemcpyAsync(&h_flag, flag, sizeof(h_flag), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess && n_cells > 0)
             e = hipMemcpyAsync(v->order_sample.data(), d_sample, v->order_sample.size() * sizeof(float),
                                hipMemcpyDeviceToHost, s);
         if (e == hipSuccess && n_cells > 0)
-            e = hipMemcpyAsync(v->order_sub.data(), d_sub, v->order_sub.size() * sizeof(float2), hipMemcpyDeviceToHost, s);
+            e = hipMemcpyAsync(sub_pairs.data(), d_sub, sub_pairs.size() * sizeof(float2), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
+        v->order_sub_lo.resize(sub_pairs.size());
+        v->order_sub_hi.resize(sub_pairs.size());
+        for (size_t i = 0; i < sub_pairs.size(); ++i) {
+            v->order_sub_lo[i] = sub_pairs[i].x;
+            v->order_sub_hi[i] = sub_pairs[i].y;
+        }
         if (e != hipSuccess) { rc = hip_fail(e, "load synchronisation"); break; }
         if (h_flag) rc = fail(RAYPC_ERR_INVALID, "input contains a non-finite value");
     } while (0);

@@ -50,8 +50,12 @@ struct Volume {
     // a fixed random sample of shell cells, from which each brush's field test order is chosen: their
     // values and the (min, max) of their 4^3 sub-bricks at level 0, field after field (order_k per field)
     int order_k = 0;
-    std::vector<float> order_sample;
-    std::vector<float2> order_sub;
+    std::vector<float> order_sample, order_sub_lo, order_sub_hi;
+    // the last brush ordered and its order (callers hold the context mutex)
+    bool order_cached = false;
+    uint8_t order_active[kMaxFields] = {};
+    float order_lo[kMaxFields] = {}, order_hi[kMaxFields] = {};
+    int order_fields[kMaxFields] = {}, order_n = 0;
 };
 
 constexpr int kOrderSample = 2048;  // sampled shell cells per volume
@@ -59,8 +63,7 @@ constexpr int kOrderSample = 2048;  // sampled shell cells per volume
 // The order in which a render tests the brushed fields (brush_active / lo / hi per field of v): order[0 ..
 // n_brushed) lists the active fields.  Every order gives the same image; the chosen one fetches fewer
 // fields per sample on average.
-void brush_order(const Volume* v, const uint8_t* active, const float* lo, const float* hi, int* order,
-                 int& n_brushed);
+void brush_order(Volume* v, const uint8_t* active, const float* lo, const float* hi, int* order, int& n_brushed);
 
 struct TFSlot {
     bool defined = false;
