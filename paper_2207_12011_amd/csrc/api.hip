@@ -404,6 +404,7 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
     a.out = reinterpret_cast<float4*>(rgba_out);
     a.blocks_x = (width + kBlockPix - 1) / kBlockPix;
     a.n_blocks = a.blocks_x * ((height + kBlockPix - 1) / kBlockPix);
+    a.super_log2 = ctx->super_log2;
     a.skip = nullptr;
     if (use_volume_state) {
         rc = ensure_skip(ctx, v, lod, tf_slot, s);
@@ -907,6 +908,86 @@ int raypc_warp(raypc_ctx* ctx, const raypc_camera* src_cam, int src_width, int s
     w.out_src = source_out;
     HIP_TRY(launch_warp(w, static_cast<hipStream_t>(stream)), "warp kernel launches");
     return RAYPC_OK;
+}
+
+int raypc_set_launch_shape(raypc_ctx* ctx, int super_log2) {
+    if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
+    if (super_log2 < 0 || super_log2 > kMaxSuperLog2)
+        return fail(RAYPC_ERR_INVALID, "super_log2 %d outside [0, %d]", super_log2, kMaxSuperLog2);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->super_log2 = super_log2;
+    return RAYPC_OK;
+}
+
+int raypc_get_launch_shape(raypc_ctx* ctx, int* super_log2) {
+    if (!ctx || !super_log2) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *super_log2 = ctx->super_log2;
+    return RAYPC_OK;
+}
+
+int raypc_autotune_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
+                          float step, int repeats, float* times_ms, int* best) {
+    if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
+    if (repeats < 1 || repeats > 1000) return fail(RAYPC_ERR_INVALID, "repeats %d outside [1, 1000]", repeats);
+    DeviceGuard g(ctx->device);
+    const size_t bytes = static_cast<size_t>(std::max(width, 1)) * std::max(height, 1) * sizeof(float4);
+    if (width < 1 || width > 16384 || height < 1 || height > 16384)
+        return fail(RAYPC_ERR_INVALID, "image size %dx%d outside [1, 16384]", width, height);
+    float* out = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&out), bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RAYPC_ERR_NOMEM, "autotune image of %zu bytes", bytes);
+    }
+    int rc = RAYPC_OK;
+    float t[kMaxSuperLog2 + 1];
+    int saved = 2;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        saved = ctx->super_log2;
+    }
+    do {
+        hipError_t e = hipStreamCreate(&s);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e != hipSuccess) { rc = hip_fail(e, "autotune stream / events"); break; }
+        for (int c = 0; c <= kMaxSuperLog2 && !rc; ++c) {
+            {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                ctx->super_log2 = c;
+            }
+            // one untimed render (skip state, caches), then `repeats` timed back to back
+            rc = raypc_render(ctx, volume_id, cam, width, height, lod, step, out, s);
+            if (!rc && (e = hipEventRecord(e0, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+            for (int r = 0; r < repeats && !rc; ++r) rc = raypc_render(ctx, volume_id, cam, width, height, lod, step, out, s);
+            if (!rc && (e = hipEventRecord(e1, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+            if (!rc && (e = hipEventSynchronize(e1)) != hipSuccess) rc = hip_fail(e, "hipEventSynchronize");
+            float ms = 0.0f;
+            if (!rc && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) rc = hip_fail(e, "hipEventElapsedTime");
+            t[c] = ms / repeats;
+        }
+    } while (0);
+    if (s) (void)hipStreamSynchronize(s);
+    int b = saved;
+    if (!rc) {
+        b = 0;
+        for (int c = 1; c <= kMaxSuperLog2; ++c)
+            if (t[c] < t[b]) b = c;
+        if (times_ms)
+            for (int c = 0; c <= kMaxSuperLog2; ++c) times_ms[c] = t[c];
+        if (best) *best = b;
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->super_log2 = b;  // the winner, or the previous shape when tuning failed
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(out);
+    return rc;
 }
 
 int raypc_render_progressive(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,

@@ -89,6 +89,7 @@ struct raypc_ctx {
     raypc::Server* server = nullptr;
     unsigned long long* warp_keys = nullptr;  // image-warp z-buffer, grown on demand
     size_t warp_keys_n = 0;
+    int super_log2 = 2;  // launch shape of single-image renders (raypc_set_launch_shape)
 };
 
 

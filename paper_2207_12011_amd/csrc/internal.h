@@ -175,6 +175,7 @@ struct RenderArgs {
     uint32_t* composited;
     uint32_t* touched;            // debug: bit per brick read by an evaluated sample (may be null)
     int blocks_x, n_blocks;       // 8 x 8 pixel blocks per row, total
+    int super_log2;               // single-image launches: super-tiles of 2^s x 2^s blocks dealt over the XCDs
     // jittered progressive passes (jittered kernels only): pass `pass` of `n_passes` shifts each
     // pixel's sample grid by s ds, s from a SplitMix64 stream at `seed`; `mean` (may be null)
     // holds the running mean of the passes, updated with weight inv_pass1 = 1 / (pass + 1)
@@ -187,6 +188,7 @@ struct RenderArgs {
 hipError_t launch_render(const RenderArgs& a, int kind, bool counts, hipStream_t s);
 hipError_t launch_render_jittered(const RenderArgs& a, int kind, bool counts, hipStream_t s);
 hipError_t launch_render_depth(const RenderArgs& a, int kind, hipStream_t s);
+constexpr int kMaxSuperLog2 = 3;  // super-tiles of up to 8 x 8 blocks (64 x 64 pixels)
 
 // Image warping: a camera's frame in float32 (the render's frame), and one warp's buffers.
 struct WarpCamera {

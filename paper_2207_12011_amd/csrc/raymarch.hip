@@ -242,21 +242,22 @@ __device__ __forceinline__ void tile_coords(int i, int bx_count, int by_count, i
     }
 }
 
-// Single-image launches: the j-th block an XCD receives is tile j % 16 of super-tile (j / 16) * 8 + xcd
-// (super-tiles row-major over the image).  The grid is padded to whole rounds of 8 super-tiles;
-// blocks outside the image return at once.
-__host__ __device__ inline int super_cols(int blocks_x) { return (blocks_x + kSuper - 1) / kSuper; }
-__host__ __device__ inline int padded_blocks(int blocks_x, int blocks_y) {
-    const int supers = super_cols(blocks_x) * ((blocks_y + kSuper - 1) / kSuper);
-    return (supers + 7) / 8 * 8 * kSuperTiles;
+// Single-image launches deal super-tiles of 2^s x 2^s tiles (s = A.super_log2, a launch-shape
+// parameter: 8 << s pixels square; the serving path keeps s = 2): the j-th block an XCD receives is
+// tile j % 4^s of super-tile (j / 4^s) * 8 + xcd (super-tiles row-major over the image).  The grid
+// is padded to whole rounds of 8 super-tiles; blocks outside the image return at once.
+__host__ __device__ inline int super_cols(int blocks_x, int s) { return (blocks_x + (1 << s) - 1) >> s; }
+__host__ __device__ inline int padded_blocks(int blocks_x, int blocks_y, int s) {
+    const int supers = super_cols(blocks_x, s) * ((blocks_y + (1 << s) - 1) >> s);
+    return (supers + 7) / 8 * 8 << (2 * s);
 }
-__device__ __forceinline__ void interleaved_tile(int bid, int blocks_x, int& bx, int& by) {
+__device__ __forceinline__ void interleaved_tile(int bid, int blocks_x, int s, int& bx, int& by) {
     const int xcd = bid & 7, p = bid >> 3;
-    const int st = (p / kSuperTiles) * 8 + xcd;
-    const int w = p % kSuperTiles;
-    const int sc = super_cols(blocks_x);
-    bx = (st % sc) * kSuper + (w % kSuper);
-    by = (st / sc) * kSuper + (w / kSuper);
+    const int st = (p >> (2 * s)) * 8 + xcd;
+    const int w = p & ((1 << (2 * s)) - 1);
+    const int sc = super_cols(blocks_x, s);
+    bx = ((st % sc) << s) + (w & ((1 << s) - 1));
+    by = ((st / sc) << s) + (w >> s);
 }
 
 // Number of brushed fields known only at run time (batched launches mix requests).
@@ -627,7 +628,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
 template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false>
 __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     int bx, by;
-    interleaved_tile(blockIdx.x, A.blocks_x, bx, by);
+    interleaved_tile(blockIdx.x, A.blocks_x, A.super_log2, bx, by);
     if (by * kBlockTile >= A.height || bx * kBlockTile >= A.width) return;  // padding block
     __shared__ float4 s_tf[256];
     {
@@ -665,7 +666,7 @@ __global__ __launch_bounds__(256) void raymarch_batch_kernel(const RenderArgs* _
 
 template <int K, bool COUNTS>
 hipError_t launch_nb(const RenderArgs& a, hipStream_t s) {
-    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x)), block(256);
+    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x, a.super_log2)), block(256);
     if (a.coord_mask) {
         hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, COUNTS>), grid, block, 0, s, a);
         return hipGetLastError();
@@ -716,7 +717,7 @@ hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& R, in
 namespace {
 template <int K, bool COUNTS>
 hipError_t launch_jit(const RenderArgs& a, hipStream_t s) {
-    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x)), block(256);
+    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x, a.super_log2)), block(256);
     hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, COUNTS, true>), grid, block, 0, s, a);
     return hipGetLastError();
 }
@@ -740,7 +741,7 @@ hipError_t launch_render_jittered(const RenderArgs& a, int kind, bool counts, hi
 namespace {
 template <int K>
 hipError_t launch_depth(const RenderArgs& a, hipStream_t s) {
-    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x)), block(256);
+    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x, a.super_log2)), block(256);
     hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, false, false, true>), grid, block, 0, s, a);
     return hipGetLastError();
 }

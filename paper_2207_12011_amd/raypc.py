@@ -90,6 +90,10 @@ _export_mask = _sig("raypc_export_voxel_mask", _I, _P, _I, _I, _P, _P)
 _render_debug = _sig("raypc_render_debug", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _P, _I,
                      _P)
 _render_depth = _sig("raypc_render_depth", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P)
+_set_launch_shape = _sig("raypc_set_launch_shape", _I, _P, _I)
+_get_launch_shape = _sig("raypc_get_launch_shape", _I, _P, ctypes.POINTER(_I))
+_autotune_render = _sig("raypc_autotune_render", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _I, _P,
+                        ctypes.POINTER(_I))
 _warp = _sig("raypc_warp", _I, _P, ctypes.POINTER(Camera), _I, _I, _P, _P, ctypes.POINTER(Camera), _I, _I, _P, _P, _P,
              _P)
 
@@ -130,7 +134,8 @@ EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_po
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
             "raypc_export_level", "raypc_export_minmax", "raypc_export_minmax_sub", "raypc_export_skiplist",
             "raypc_export_subskip", "raypc_export_voxel_mask", "raypc_render_debug", "raypc_pc_lines",
-            "raypc_render_jittered", "raypc_set_coordinate_brush", "raypc_render_depth", "raypc_warp"]
+            "raypc_render_jittered", "raypc_set_coordinate_brush", "raypc_render_depth", "raypc_warp",
+            "raypc_set_launch_shape", "raypc_get_launch_shape", "raypc_autotune_render"]
 
 
 class RaypcError(RuntimeError):
@@ -317,6 +322,27 @@ def render_jittered(ctx, volume_id: int, camera, width: int, height: int, lod: i
                             out.data_ptr(), mptr, None if nom is None else nom.data_ptr(),
                             None if comp is None else comp.data_ptr(), _stream(stream)))
     return out, nom, comp
+
+
+def set_launch_shape(ctx, super_log2: int) -> None:
+    _check(_set_launch_shape(ctx, int(super_log2)))
+
+
+def get_launch_shape(ctx) -> int:
+    s = _I()
+    _check(_get_launch_shape(ctx, ctypes.byref(s)))
+    return s.value
+
+
+def autotune_render(ctx, volume_id: int, camera, width: int, height: int, lod: int = -1, step: float = 0.5,
+                    repeats: int = 10):
+    """Time the launch shapes on this view and keep the fastest: (best super_log2, [ms per render for
+    super_log2 = 0..3])."""
+    times = (_F * 4)()
+    best = _I()
+    _check(_autotune_render(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height), int(lod),
+                            float(step), int(repeats), ctypes.cast(times, _P), ctypes.byref(best)))
+    return best.value, [float(t) for t in times]
 
 
 def render_depth(ctx, volume_id: int, camera, width: int, height: int, lod: int = -1, step: float = 0.5,

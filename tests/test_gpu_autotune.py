@@ -1,0 +1,107 @@
+"""GPU tests of the launch-shape autotuner: every super-tile size gives the image of the default
+shape bit for bit (with its counts), the tuner times all shapes and keeps the fastest, the server
+sweep picks one of its candidates, and invalid arguments are rejected."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2207_12011_amd import autotune as AT
+from paper_2207_12011_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rp():
+    from paper_2207_12011_amd import raypc
+    return raypc
+
+
+@pytest.fixture(scope="module")
+def ctx(rp):
+    c = rp.create(0)
+    yield c
+    rp.destroy(c)
+
+
+def cpu(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def load(rp, ctx, wl, storage="f16"):
+    vid = rp.load_fields(ctx, torch.from_numpy(wl.fields).cuda(), storage, 3, wl.r_inner, wl.r_outer)
+    rp.set_brush(ctx, vid, wl.brush.active, wl.brush.lo, wl.brush.hi)
+    rp.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
+    rp.set_options(ctx, wl.ert)
+    return vid
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "u8"])
+def test_every_launch_shape_gives_the_same_image(rp, ctx, storage):
+    wl = W.make_workload(1, n=64, width=200, height=136)
+    vid = load(rp, ctx, wl, storage)
+    cam = wl.camera.as_array()
+    try:
+        for w, h, lod in ((200, 136, 0), (1, 1, 0), (517, 3, 1), (64, 300, 2), (1920, 1080, 0)):
+            rp.set_launch_shape(ctx, 2)
+            want = [cpu(x) for x in rp.render_debug(ctx, vid, cam, w, h, lod, 0.5)]
+            for s in (0, 1, 3):
+                print(f"[case] launch shape {s} {storage} {w}x{h} lod {lod}", flush=True)
+                rp.set_launch_shape(ctx, s)
+                assert rp.get_launch_shape(ctx) == s
+                got = [cpu(x) for x in rp.render_debug(ctx, vid, cam, w, h, lod, 0.5)]
+                assert all(np.array_equal(a, b) for a, b in zip(got, want)), (s, w, h)
+                jit = cpu(rp.render_jittered(ctx, vid, cam, w, h, lod, 0.5, 1, 4, 7)[0])
+                rp.set_launch_shape(ctx, 2)
+                assert np.array_equal(jit, cpu(rp.render_jittered(ctx, vid, cam, w, h, lod, 0.5, 1, 4, 7)[0]))
+    finally:
+        rp.set_launch_shape(ctx, 2)
+        rp.unload(ctx, vid)
+
+
+def test_autotune_render_keeps_the_fastest(rp, ctx):
+    wl = W.make_workload(1, n=64, width=640, height=360)
+    vid = load(rp, ctx, wl)
+    cam = wl.camera.as_array()
+    try:
+        best, times = rp.autotune_render(ctx, vid, cam, wl.width, wl.height, 0, 0.5, repeats=5)
+        print(f"[autotune] ms per render for super-tiles of 8/16/32/64 px: {times}, best {best}", flush=True)
+        assert 0 <= best <= 3 and all(t > 0 for t in times) and times[best] == min(times)
+        assert rp.get_launch_shape(ctx) == best
+        cache = {}
+        key = AT.render_key(AT.device_name(), 64, "f16", wl.width, wl.height, 0, 0.5)
+        r = AT.tune_render(rp, ctx, vid, cam, wl.width, wl.height, 0, 0.5, repeats=3, cache=cache, key=key)
+        assert not r["cached"] and key in cache
+        rp.set_launch_shape(ctx, 0)
+        r = AT.tune_render(rp, ctx, vid, cam, wl.width, wl.height, 0, 0.5, cache=cache, key=key)
+        assert r["cached"] and rp.get_launch_shape(ctx) == cache[key]["super_log2"]
+        for bad in (0, 1001):
+            with pytest.raises(rp.RaypcError):
+                rp.autotune_render(ctx, vid, cam, wl.width, wl.height, 0, 0.5, repeats=bad)
+        with pytest.raises(rp.RaypcError):
+            rp.autotune_render(ctx, vid, cam, 0, wl.height, 0, 0.5)
+        for bad in (-1, 4):
+            with pytest.raises(rp.RaypcError):
+                rp.set_launch_shape(ctx, bad)
+    finally:
+        rp.set_launch_shape(ctx, 2)
+        rp.unload(ctx, vid)
+
+
+def test_tune_server_picks_a_candidate(rp, ctx):
+    wl = W.make_workload(1, n=64, width=200, height=136)
+    vid = load(rp, ctx, wl)
+    cam = wl.camera.as_array()
+    outs = [torch.empty((h, w, 4), dtype=torch.float32, device="cuda") for w, h in ((200, 136), (64, 64), (333, 97))
+            for _ in range(4)]
+    reqs = [rp.make_request(vid, cam, o.shape[1], o.shape[0], o, 0, 0.5, wl.brush.active, wl.brush.lo, wl.brush.hi)
+            for o in outs]
+    try:
+        r = AT.tune_server(rp, ctx, reqs, candidates=((2048, 1), (8192, 2)), rounds=1)
+        print(f"[autotune] server: {r}", flush=True)
+        assert (r["tiles_per_step"], r["steps_in_flight"]) in ((2048, 1), (8192, 2))
+        single = cpu(rp.render(ctx, vid, cam, 333, 97, 0, 0.5))
+        assert np.array_equal(cpu(outs[-1]), single)
+    finally:
+        rp.unload(ctx, vid)
