@@ -218,6 +218,10 @@ struct BatchRanges {
     int first[kMaxRanges];
     int slot[kMaxRanges];
 };
-hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& ranges, int kind, hipStream_t s);
+// Requests of one batched launch share the kernel kind and the field-count class: the number of
+// brushed fields, or -1 (the run-time count variant) when coordinate axes are enabled.
+int batch_nb_class(const RenderArgs& a);
+hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& ranges, int kind, int nb_class,
+                               hipStream_t s);
 
 }  // namespace raypc

@@ -38,728 +38,16 @@
 // 8^3 brick when all eight of its sub-bricks are flagged): every sample whose
 // base corner lies in such a box would be discarded or fully transparent, so
 // skipping changes no value.  Blocks of 4 waves (8 x 8 pixels) are dealt to the
-// XCDs by 32 x 32-pixel super-tiles; the transfer function sits in LDS.
-#include <hip/hip_fp16.h>
-
-#include "internal.h"
+// XCDs by super-tiles (32 x 32 pixels unless the launch shape says otherwise); the transfer function
+// sits in LDS.  This file holds the single-image launches, whose field count is a template argument;
+// raymarch_batch.hip holds those that read it at run time.
+#include "raymarch_impl.h"
 
 namespace raypc {
-namespace {
-
-constexpr float kSkipShrink = 2e-3f;  // voxels: shrink of a skipped box before computing its exit
-constexpr float kSkipMargin = 0.01f;  // samples: margin on the first sample after a skipped box
-constexpr int kQuad = 4;              // lanes (consecutive samples) per ray
-constexpr int kWaveTile = 4;          // a wave covers kWaveTile x kWaveTile pixels
-constexpr int kBlockTile = 8;         // a 256-thread block covers 8 x 8 pixels
-
-// Global-memory view of a pointer.  Pointers read from memory (the batched launch takes its
-// arguments from a device array) would otherwise be accessed with generic flat loads.
-template <typename T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const void* p) {
-    return reinterpret_cast<const __attribute__((address_space(1))) T*>(reinterpret_cast<uintptr_t>(p));
-}
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// log2 of the bytes per stored value.
-template <int S>
-constexpr int kLogBytes = S == kF32 ? 2 : (S == kF16 ? 1 : 0);
-
-// Where one field's stored values come from.  binary16 and 8-bit fields are read with buffer loads
-// (a uniform 128-bit resource plus a 32-bit per-lane byte offset, range-checked by the hardware
-// against the field size); float32 fields (up to 4 GiB per field) with global loads.
-template <int S>
-struct Source;
-template <>
-struct Source<kF32> {
-    const float* base;
-};
-template <>
-struct Source<kF16> {
-    __amdgpu_buffer_rsrc_t rsrc;
-};
-template <>
-struct Source<kU8> {
-    __amdgpu_buffer_rsrc_t rsrc, par;
-};
-
-constexpr int kRawBufferFlags = 0x00020000;  // raw (untyped) buffer, 32-bit data format
-
-template <int S>
-__device__ __forceinline__ Source<S> source(const RenderArgs& A, int k) {
-    Source<S> src;
-    if constexpr (S == kF32) {
-        src.base = static_cast<const float*>(A.field[k]);
-    } else {
-        src.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(A.field[k]), 0, static_cast<int>(A.field_bytes),
-                                                     kRawBufferFlags);
-        if constexpr (S == kU8)
-            src.par = __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(A.u8par[k]), 0,
-                                                        static_cast<int>(A.par_bytes), kRawBufferFlags);
-    }
-    return src;
-}
-
-// Stored value at byte offset `ob`.
-template <int S>
-__device__ __forceinline__ float corner(const Source<S>& src, uint32_t ob) {
-    if constexpr (S == kF32) {
-        return global_ptr<float>(reinterpret_cast<const char*>(src.base) + ob)[0];
-    } else if constexpr (S == kF16) {
-        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(src.rsrc, static_cast<int>(ob), 0, 0);
-        return __half2float(__ushort_as_half(h));
-    } else {
-        const float q = static_cast<float>(__builtin_amdgcn_raw_buffer_load_b8(src.rsrc, static_cast<int>(ob), 0, 0));
-        const uint32_t pb = (ob >> 9) * 8u;
-        const auto so = __builtin_amdgcn_raw_buffer_load_b64(src.par, static_cast<int>(pb), 0, 0);  // (scale, offset)
-        return __fadd_rn(__fmul_rn(__uint_as_float(so[0]), q), __uint_as_float(so[1]));
-    }
-}
-
-// Trilinear interpolation written as a weighted sum of the eight corners (index bit 0 = x, bit 1 = y,
-// bit 2 = z).  The weights depend only on the sample position, so one sample computes them once for
-// all its fields; each field then costs eight multiply-adds, which take binary16 corners as operands
-// directly (mixed-precision FMA) instead of converting them first.
-struct Tri {
-    float w[8];
-};
-__device__ __forceinline__ Tri tri_weights(float wx, float wy, float wz) {
-    const float ax = 1.0f - wx, ay = 1.0f - wy, az = 1.0f - wz;
-    const float q0 = ay * az, q1 = wy * az, q2 = ay * wz, q3 = wy * wz;  // (y, z) = (0,0) (1,0) (0,1) (1,1)
-    Tri t;
-    t.w[0] = ax * q0, t.w[1] = wx * q0, t.w[2] = ax * q1, t.w[3] = wx * q1;
-    t.w[4] = ax * q2, t.w[5] = wx * q2, t.w[6] = ax * q3, t.w[7] = wx * q3;
-    return t;
-}
-__device__ __forceinline__ float blend(const Tri& t, float c0, float c1, float c2, float c3, float c4, float c5,
-                                       float c6, float c7) {
-    float v = fmaf(t.w[0], c0, 0.0f);
-    v = fmaf(t.w[1], c1, v);
-    v = fmaf(t.w[2], c2, v);
-    v = fmaf(t.w[3], c3, v);
-    v = fmaf(t.w[4], c4, v);
-    v = fmaf(t.w[5], c5, v);
-    v = fmaf(t.w[6], c6, v);
-    return fmaf(t.w[7], c7, v);
-}
-
-// Trilinear value from the 8 stored corners at byte offsets o[].
-template <int S>
-__device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)[8], const Tri& t) {
-    return blend(t, corner<S>(src, o[0]), corner<S>(src, o[1]), corner<S>(src, o[2]), corner<S>(src, o[3]),
-                 corner<S>(src, o[4]), corner<S>(src, o[5]), corner<S>(src, o[6]), corner<S>(src, o[7]));
-}
-
-// Trilinear value from neighbourhood records (8 bytes per voxel): binary16 reads the 2x2 (x, y) records
-// of the base voxel's row at z0 and z1, float32 the x pairs at (y0, z0), (y1, z0), (y0, z1), (y1, z1).
-// ax is the x part of the base voxel's address, ay0 / ay1 / az0 / az1 the y and z parts (see axis_x/y/z).
-// The arithmetic is that of fetch(), so both layouts give identical values.
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-template <int S>
-__device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32_t ax, uint32_t ay0, uint32_t ay1,
-                                           uint32_t az0, uint32_t az1, const Tri& t) {
-    const char* b = static_cast<const char*>(base);
-    if constexpr (S == kF16) {
-        const u32x2 p = global_ptr<u32x2>(b + static_cast<size_t>(ax + ay0 + az0) * 8u)[0];
-        const u32x2 q = global_ptr<u32x2>(b + static_cast<size_t>(ax + ay0 + az1) * 8u)[0];
-        auto lo = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u & 0xFFFFu))); };
-        auto hi = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u >> 16))); };
-        return blend(t, lo(p.x), hi(p.x), lo(p.y), hi(p.y), lo(q.x), hi(q.x), lo(q.y), hi(q.y));
-    } else {
-        const f32x2 p0 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay0 + az0) * 8u)[0];
-        const f32x2 p1 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay1 + az0) * 8u)[0];
-        const f32x2 p2 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay0 + az1) * 8u)[0];
-        const f32x2 p3 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay1 + az1) * 8u)[0];
-        return blend(t, p0.x, p0.y, p1.x, p1.y, p2.x, p2.y, p3.x, p3.y);
-    }
-}
-
-// Kernel kinds: storage type and layout.
-constexpr int storage_of(int K) {
-    return K == kKindF32Rec ? kF32 : (K == kKindF16Rec ? kF16 : (K == kKindU8Rec ? kU8 : K));
-}
-constexpr bool records_of(int K) { return K >= kKindF32Rec; }
-// Value type held by a kind's records: binary16 quads, or float32 pairs (also for decoded 8-bit codes).
-constexpr int record_type_of(int K) { return K == kKindF16Rec ? kF16 : kF32; }
-
-// Ray parameter where u(t) = uo + du t leaves [lo, hi] along one axis (forward only); inv_du = 1/du.
-// Rounding of the reciprocal is covered by the shrink margin of skipped bricks.
-__device__ __forceinline__ float axis_exit(float uo, float du, float inv_du, float lo, float hi) {
-    const float t = ((du > 0.0f ? hi : lo) - uo) * inv_du;
-    return du != 0.0f ? t : INFINITY;
-}
-
-// Stable ray/sphere hit for |d| = 1.  Returns false when the ray misses or touches.
-__device__ __forceinline__ bool sphere_hit(float b, float px, float py, float pz, float r2, float c, float& t0,
-                                           float& t1) {
-    const float disc = r2 - (px * px + py * py + pz * pz);
-    if (!(disc > 0.0f)) return false;
-    const float q = -b - copysignf(sqrtf(disc), b);
-    const float ta = c / q, tb = q;
-    t0 = fminf(ta, tb);
-    t1 = fmaxf(ta, tb);
-    return true;
-}
-
-// Value of `v` held by lane SRC (0..3) of the calling lane's quad (one DPP quad_perm move).
-template <int SRC>
-__device__ __forceinline__ float quad_bcast(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), SRC * 0x55, 0xF, 0xF, true));
-}
-template <int SRC>
-__device__ __forceinline__ int quad_bcast(int v) {
-    return __builtin_amdgcn_mov_dpp(v, SRC * 0x55, 0xF, 0xF, true);
-}
-
-// Tiles are grouped in super-tiles of kSuper x kSuper tiles (32 x 32 pixels) and super-tiles are dealt
-// round-robin over the 8 XCDs (block i runs on XCD i % 8).  The tiles of a super-tile run together
-// on one XCD (their rays share voxels in its L2), and every XCD gets super-tiles from all over the
-// image, so the work of the shell's disc is spread evenly; 32 x 32 pixels balances the two (larger
-// super-tiles leave some XCDs with more of the disc's costly centre, smaller ones share less).
-constexpr int kSuper = 4;
-constexpr int kSuperTiles = kSuper * kSuper;
-
-// Batched launches number a request's tiles super-tile by super-tile in row-major order, tiles
-// row-major inside each (narrower at the right and bottom edges), so consecutive tile indices
-// cover a compact patch of the image.  A bijection of [0, bx_count * by_count).
-__device__ __forceinline__ void tile_coords(int i, int bx_count, int by_count, int& bx, int& by) {
-    const int sr = i / (bx_count * kSuper);
-    const int rem = i - sr * bx_count * kSuper;
-    const int rows = min(kSuper, by_count - sr * kSuper);
-    const int full_cols = bx_count / kSuper;
-    const int sc = rem / (kSuper * rows);
-    if (sc < full_cols) {
-        const int r2 = rem - sc * kSuper * rows;
-        bx = sc * kSuper + r2 % kSuper;
-        by = sr * kSuper + r2 / kSuper;
-    } else {
-        const int wl = bx_count - full_cols * kSuper;
-        const int r3 = rem - full_cols * kSuper * rows;
-        bx = full_cols * kSuper + r3 % wl;
-        by = sr * kSuper + r3 / wl;
-    }
-}
-
-// Single-image launches deal super-tiles of 2^s x 2^s tiles (s = A.super_log2, a launch-shape
-// parameter: 8 << s pixels square; the serving path keeps s = 2): the j-th block an XCD receives is
-// tile j % 4^s of super-tile (j / 4^s) * 8 + xcd (super-tiles row-major over the image).  The grid
-// is padded to whole rounds of 8 super-tiles; blocks outside the image return at once.
-__host__ __device__ inline int super_cols(int blocks_x, int s) { return (blocks_x + (1 << s) - 1) >> s; }
-__host__ __device__ inline int padded_blocks(int blocks_x, int blocks_y, int s) {
-    const int supers = super_cols(blocks_x, s) * ((blocks_y + (1 << s) - 1) >> s);
-    return (supers + 7) / 8 * 8 << (2 * s);
-}
-__device__ __forceinline__ void interleaved_tile(int bid, int blocks_x, int s, int& bx, int& by) {
-    const int xcd = bid & 7, p = bid >> 3;
-    const int st = (p >> (2 * s)) * 8 + xcd;
-    const int w = p & ((1 << (2 * s)) - 1);
-    const int sc = super_cols(blocks_x, s);
-    bx = ((st % sc) << s) + (w & ((1 << s) - 1));
-    by = ((st / sc) << s) + (w >> s);
-}
-
-// Number of brushed fields known only at run time (batched launches mix requests).
-constexpr int kRuntimeNB = -1;
-
-// Sample-grid offset s in [0, 1) of pixel p in a jittered pass: output number c + 1 of a SplitMix64
-// stream started at the seed (Steele, Lea and Flood, OOPSLA 2014: gamma 0x9E3779B97F4A7C15 and the
-// 30 / 27 / 31 xor-shift, multiply mix), for the counter c = pass 2^32 + p; its top 16 bits give
-// xi, and s = min(fl32(fl32(pass + xi) / n_passes), 1 - 2^-24) (stratified per pass).
-__device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) {
-    const uint64_t c = (static_cast<uint64_t>(A.pass) << 32) | p;
-    uint64_t z = A.seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    const float xi = static_cast<float>(static_cast<uint32_t>(z >> 48)) * 0x1p-16f;
-    const float s = __fdiv_rn(__fadd_rn(static_cast<float>(A.pass), xi), static_cast<float>(A.n_passes));
-    return fminf(s, 0x1.fffffep-1f);
-}
-
-// One 8 x 8 pixel tile (index blk in row-major tile order) of the image described by A, marched by
-// the calling 256-thread block.  NB is the number of brushed fields, or kRuntimeNB to read it from A.
-// JIT: a jittered progressive pass (the sample grid of every segment starts s ds before it, so the
-// first and last samples of a segment are partial).  DEPTH: also write the opacity-weighted depth, the
-// mean distance of the composited samples, each weighted by its share w of the pixel's opacity (the
-// depth that image warping reprojects with; +inf where nothing was composited).
-template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false>
-__device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, const float4* s_tf) {
-    constexpr int S = storage_of(K);
-    constexpr bool R = records_of(K);
-    constexpr int RT = record_type_of(K);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ray = lane >> 2, sub = lane & 3, quad_base = lane & ~3;
-    const int px = bx * kBlockTile + (wave & 1) * kWaveTile + (ray & 3);
-    const int py = by * kBlockTile + (wave >> 1) * kWaveTile + (ray >> 2);
-    const bool inside = px < A.width && py < A.height;
-
-    // ---- ray through the pixel centre (identical in the four lanes of the quad)
-    const float sx = fmaf(static_cast<float>(px) + 0.5f, A.inv_w2, -1.0f) * A.sx_scale;
-    const float sy = fmaf(-(static_cast<float>(py) + 0.5f), A.inv_h2, 1.0f) * A.sy_scale;
-    float dx = fmaf(sy, A.upv[0], fmaf(sx, A.right[0], A.fwd[0]));
-    float dy = fmaf(sy, A.upv[1], fmaf(sx, A.right[1], A.fwd[1]));
-    float dz = fmaf(sy, A.upv[2], fmaf(sx, A.right[2], A.fwd[2]));
-    const float inv_len = 1.0f / sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-    dx *= inv_len;
-    dy *= inv_len;
-    dz *= inv_len;
-    const float ox = A.eye[0], oy = A.eye[1], oz = A.eye[2];
-
-    // ---- shell segments
-    const float b = fmaf(ox, dx, fmaf(oy, dy, oz * dz));
-    const float fx = fmaf(-b, dx, ox), fy = fmaf(-b, dy, oy), fz = fmaf(-b, dz, oz);
-    float seg_a[2] = {0.0f, 0.0f}, seg_b[2] = {0.0f, 0.0f};
-    int nseg = 0;
-    float t0, t1;
-    if (inside && sphere_hit(b, fx, fy, fz, A.r_out2, A.c_out, t0, t1)) {
-        float s0, s1;
-        const bool inner = A.has_inner && sphere_hit(b, fx, fy, fz, A.r_in2, A.c_in, s0, s1);
-        float ca0 = t0, cb0 = t1, ca1 = 0.0f, cb1 = 0.0f;
-        if (inner) {
-            cb0 = fminf(t1, s0);
-            ca1 = fmaxf(t0, s1);
-            cb1 = t1;
-        }
-        ca0 = fmaxf(ca0, 0.0f);
-        if (cb0 > ca0) {
-            seg_a[nseg] = ca0;
-            seg_b[nseg] = cb0;
-            ++nseg;
-        }
-        if (inner) {
-            ca1 = fmaxf(ca1, 0.0f);
-            if (cb1 > ca1) {
-                seg_a[nseg] = ca1;
-                seg_b[nseg] = cb1;
-                ++nseg;
-            }
-        }
-    }
-
-    const int n = A.n, nb = A.nb;
-    const float hn = A.half_n;
-    const float uox = fmaf(ox, hn, hn - 0.5f), uoy = fmaf(oy, hn, hn - 0.5f), uoz = fmaf(oz, hn, hn - 0.5f);
-    const float dux = dx * hn, duy = dy * hn, duz = dz * hn;
-    const float inv_dux = 1.0f / dux, inv_duy = 1.0f / duy, inv_duz = 1.0f / duz;
-    const float ds = A.ds, inv_ds = A.inv_ds;
-    const float r_full = ds * A.inv_ref;
-
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    float D = 0.0f;  // DEPTH: sum of w tm over the composited samples
-    uint32_t cnt_nom = 0, cnt_comp = 0;
-    uint32_t last_brick = 0xFFFFFFFFu;
-    int seg = 0, j0 = 0;  // j0: first sample of the quad's current group of four
-    float sa = seg_a[0], sb = seg_b[0];
-    // grid origin of the current segment: sample j covers [max(sa, g + j ds), min(g + (j+1) ds, sb)]
-    float s_jit = 0.0f;
-    if constexpr (JIT) s_jit = jitter_offset(A, static_cast<uint32_t>(py) * A.width + px);
-    float g = JIT ? fmaf(-s_jit, ds, sa) : sa;
-    int ns = nseg > 0 ? max(static_cast<int>(ceilf((sb - g) / ds)), 1) : 0;
-    bool alive = nseg > 0;
-
-    while (alive) {
-        const int j = j0 + sub;
-        const bool valid = j < ns;
-        bool skipped = false, pass = false;
-        float tv = 0.0f;
-        int jn = j + 1;
-        const bool last = j == ns - 1;
-        float tlo = 0.0f, tm = 0.0f, len_partial = 0.0f;
-        bool partial = last;
-
-        if (valid) {
-            if constexpr (JIT) {
-                const bool first = j == 0;
-                partial = first || last;
-                tlo = first ? sa : fmaf(static_cast<float>(j), ds, g);
-                const float thi = last ? sb : fmaf(static_cast<float>(j) + 1.0f, ds, g);
-                tm = partial ? 0.5f * (tlo + thi) : fmaf(static_cast<float>(j) + 0.5f, ds, g);
-                len_partial = fmaxf(thi - tlo, 0.0f);
-            } else {
-                tlo = fmaf(static_cast<float>(j), ds, sa);
-                tm = last ? 0.5f * (tlo + sb) : fmaf(static_cast<float>(j) + 0.5f, ds, sa);
-                len_partial = fmaxf(sb - tlo, 0.0f);
-            }
-            const float ux = fmaf(dux, tm, uox), uy = fmaf(duy, tm, uoy), uz = fmaf(duz, tm, uoz);
-            const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
-            const int ix = static_cast<int>(flx), iy = static_cast<int>(fly), iz = static_cast<int>(flz);
-            const int x0 = min(max(ix, 0), n - 1), x1 = min(max(ix + 1, 0), n - 1);
-            const int y0 = min(max(iy, 0), n - 1), y1 = min(max(iy + 1, 0), n - 1);
-            const int z0 = min(max(iz, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
-            const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
-            const uint32_t brick = (static_cast<uint32_t>(bzi) * nb + byi) * nb + bxi;
-            const uint32_t flags = A.skip != nullptr ? global_ptr<uint8_t>(A.skip)[brick] : 0u;
-            const uint32_t sub = ((x0 >> 2) & 1) | (((y0 >> 2) & 1) << 1) | (((z0 >> 2) & 1) << 2);
-            if ((flags >> sub) & 1u) {
-                // every sample whose base corner lies in this sub-brick (in this brick, when all
-                // eight are flagged) is discarded or transparent: find the first sample that may lie
-                // beyond the box (shrunk by a margin against rounding; open at the grid's faces,
-                // where clamping maps every outside position to the boundary box)
-                skipped = true;
-                const bool whole = flags == 0xFFu;
-                const int e = whole ? 8 : 4;
-                const int cx = whole ? bxi * 8 : x0 & ~3, cy = whole ? byi * 8 : y0 & ~3;
-                const int cz = whole ? bzi * 8 : z0 & ~3;
-                const float lx = cx == 0 ? -INFINITY : static_cast<float>(cx) + kSkipShrink;
-                const float hx = cx + e >= n ? INFINITY : static_cast<float>(cx + e) - kSkipShrink;
-                const float ly = cy == 0 ? -INFINITY : static_cast<float>(cy) + kSkipShrink;
-                const float hy = cy + e >= n ? INFINITY : static_cast<float>(cy + e) - kSkipShrink;
-                const float lz = cz == 0 ? -INFINITY : static_cast<float>(cz) + kSkipShrink;
-                const float hz = cz + e >= n ? INFINITY : static_cast<float>(cz + e) - kSkipShrink;
-                const float t_exit = fminf(axis_exit(uox, dux, inv_dux, lx, hx),
-                                           fminf(axis_exit(uoy, duy, inv_duy, ly, hy),
-                                                 axis_exit(uoz, duz, inv_duz, lz, hz)));
-                float jc = (t_exit - g) * inv_ds - 0.5f - kSkipMargin;
-                jc = fminf(fmaxf(jc, 0.0f), static_cast<float>(ns));
-                jn = max(j + 1, static_cast<int>(ceilf(jc)));
-            } else {
-                if constexpr (COUNTS) {
-                    if (A.touched != nullptr && brick != last_brick) {
-                        atomicOr(&A.touched[brick >> 5], 1u << (brick & 31));
-                        last_brick = brick;
-                    }
-                }
-                // below the grid both corners of an axis clamp to index 0: a zero weight on the upper
-                // corner gives that value exactly, and lets a record of the clamped base voxel serve
-                const float wx = ix < 0 ? 0.0f : ux - flx, wy = iy < 0 ? 0.0f : uy - fly;
-                const float wz = iz < 0 ? 0.0f : uz - flz;
-                const Tri tw = tri_weights(wx, wy, wz);
-                uint32_t o[8];
-                uint32_t ax = 0, ay0 = 0, ay1 = 0, az0 = 0, az1 = 0;
-                if constexpr (R) {
-                    ax = axis_x(x0);
-                    ay0 = axis_y(y0, nb), ay1 = axis_y(y1, nb);
-                    az0 = axis_z(z0, nb), az1 = axis_z(z1, nb);
-                } else {
-                    constexpr int L = kLogBytes<S>;
-                    const uint32_t X0 = axis_x(x0) << L, X1 = axis_x(x1) << L;
-                    const uint32_t Y0 = axis_y(y0, nb) << L, Y1 = axis_y(y1, nb) << L;
-                    const uint32_t Z0 = axis_z(z0, nb) << L, Z1 = axis_z(z1, nb) << L;
-                    const uint32_t zy00 = Z0 + Y0, zy01 = Z0 + Y1, zy10 = Z1 + Y0, zy11 = Z1 + Y1;
-                    o[0] = zy00 + X0, o[1] = zy00 + X1, o[2] = zy01 + X0, o[3] = zy01 + X1;
-                    o[4] = zy10 + X0, o[5] = zy10 + X1, o[6] = zy11 + X0, o[7] = zy11 + X1;
-                }
-                auto field_value = [&](int k) -> float {
-                    if constexpr (R) return fetch_rec<RT>(A.rec[k], ax, ay0, ay1, az0, az1, tw);
-                    else return fetch<S>(source<S>(A, k), o, tw);
-                };
-                // coordinate axes first: a sample outside them fetches no field (the kernels with a
-                // fixed field count carry no coordinate axes; renders that use them take the
-                // run-time variant)
-                pass = true;
-                if constexpr (NB < 0) {
-                    if (A.coord_mask)
-                        pass = coord_ok(A.coord_mask, A.clo, A.chi, fmaf(dx, tm, ox), fmaf(dy, tm, oy), fmaf(dz, tm, oz));
-                }
-                constexpr int kUnroll = NB >= 0 ? NB : kMaxFields;
-                const int nbr = NB >= 0 ? NB : A.n_brushed;
-#pragma unroll
-                for (int k = 0; k < kUnroll; ++k) {
-                    if (pass && (NB >= 0 || k < nbr)) {
-                        const float v = field_value(k);
-                        pass = (v >= A.lo[k]) && (v <= A.hi[k]);
-                        if (k == A.tf_slot) tv = v;
-                    }
-                }
-                if (pass) {
-                    if constexpr (NB >= 0 && NB < kMaxFields) {
-                        if (A.tf_slot == NB) tv = field_value(NB);
-                    } else if constexpr (NB < 0) {
-                        if (A.tf_slot == nbr && nbr < kMaxFields)
-                            tv = field_value(nbr);
-                    }
-                }
-            }
-        }
-        // ---- classification: every lane evaluates it, and a lane whose sample was not fetched or
-        // failed the brush contributes nothing (k = 1, w = 0), so the values merged below are those
-        // of the sequential definition
-        const float xt = fminf(fmaxf((tv - A.vmin) * A.inv_range, 0.0f), 1.0f) * 255.0f;
-        const int it = min(static_cast<int>(xt), 254);
-        const float wt = xt - static_cast<float>(it);
-        const float4 e0 = s_tf[it], e1 = s_tf[it + 1];
-        const float al = fmaf(wt, e1.w - e0.w, e0.w);
-        const bool contributes = pass && al > 0.0f;
-        const float r = partial ? len_partial * A.inv_ref : r_full;
-        const float kc = al >= 1.0f ? 0.0f : __builtin_amdgcn_exp2f(r * __log2f(1.0f - al));
-        const float keep = contributes ? kc : 1.0f;
-        const float cr = contributes ? fmaf(wt, e1.x - e0.x, e0.x) : 0.0f;
-        const float cg = contributes ? fmaf(wt, e1.y - e0.y, e0.y) : 0.0f;
-        const float cb = contributes ? fmaf(wt, e1.z - e0.z, e0.z) : 0.0f;
-
-        // ---- advance past a skipped brick of the quad's fourth sample
-        const int last_skipped = quad_bcast<3>(static_cast<int>(skipped && valid));
-        const int jn3 = quad_bcast<3>(jn);
-        if (__ballot(contributes) == 0ull) {
-            // nothing to composite anywhere in the wave: T and C are unchanged
-            const int next = last_skipped ? max(j0 + kQuad, jn3) : j0 + kQuad;
-            cnt_nom += static_cast<uint32_t>(min(next, ns) - j0);
-            j0 = next;
-            if (j0 >= ns) {
-                if (seg == 0 && nseg == 2) {
-                    seg = 1;
-                    sa = seg_a[1];
-                    sb = seg_b[1];
-                    g = JIT ? fmaf(-s_jit, ds, sa) : sa;
-                    ns = max(static_cast<int>(ceilf((sb - g) / ds)), 1);
-                    j0 = 0;
-                } else {
-                    alive = false;
-                }
-            }
-            continue;
-        }
-
-        // ---- merge the quad's four samples in sample order.  Every lane replays the same
-        // sequential updates (T <- T k, C <- fma(w, rgb, C)) on broadcast values, so the ray
-        // state is identical in the four lanes and independent of how samples were grouped
-        // (a skipped or discarded sample has k = 1 and w = 0, both exact).
-        const float k0 = quad_bcast<0>(keep), k1 = quad_bcast<1>(keep);
-        const float k2 = quad_bcast<2>(keep), k3 = quad_bcast<3>(keep);
-        const float t1 = T * k0, t2 = t1 * k1, t3 = t2 * k2, t4 = t3 * k3;  // T after each sample
-        const float t_before = sub == 0 ? T : (sub == 1 ? t1 : (sub == 2 ? t2 : t3));
-        const float t_after = sub == 0 ? t1 : (sub == 1 ? t2 : (sub == 2 ? t3 : t4));
-        const float w = t_before * (1.0f - keep);
-        const bool stop_here = contributes && A.ert_on && (1.0f - t_after >= A.ert);
-        const unsigned long long stop_mask = __ballot(stop_here);
-        const int stop_bits = static_cast<int>((stop_mask >> quad_base) & 0xFull);
-        const int first_stop = stop_bits ? __ffs(stop_bits) - 1 : kQuad - 1;  // last sample that counts
-        {
-            const float w0 = quad_bcast<0>(w), w1 = quad_bcast<1>(w), w2 = quad_bcast<2>(w), w3 = quad_bcast<3>(w);
-            const float r0 = quad_bcast<0>(cr), r1 = quad_bcast<1>(cr), r2 = quad_bcast<2>(cr), r3 = quad_bcast<3>(cr);
-            const float g0 = quad_bcast<0>(cg), g1 = quad_bcast<1>(cg), g2 = quad_bcast<2>(cg), g3 = quad_bcast<3>(cg);
-            const float b0 = quad_bcast<0>(cb), b1 = quad_bcast<1>(cb), b2 = quad_bcast<2>(cb), b3 = quad_bcast<3>(cb);
-            C0 = fmaf(w0, r0, C0);
-            C1 = fmaf(w0, g0, C1);
-            C2 = fmaf(w0, b0, C2);
-            if (first_stop >= 1) {
-                C0 = fmaf(w1, r1, C0);
-                C1 = fmaf(w1, g1, C1);
-                C2 = fmaf(w1, b1, C2);
-            }
-            if (first_stop >= 2) {
-                C0 = fmaf(w2, r2, C0);
-                C1 = fmaf(w2, g2, C1);
-                C2 = fmaf(w2, b2, C2);
-            }
-            if (first_stop >= 3) {
-                C0 = fmaf(w3, r3, C0);
-                C1 = fmaf(w3, g3, C1);
-                C2 = fmaf(w3, b3, C2);
-            }
-            if constexpr (DEPTH) {
-                // samples that were not composited have w = 0 and a finite tm: no change
-                D = fmaf(w0, quad_bcast<0>(tm), D);
-                const float m1 = quad_bcast<1>(tm), m2 = quad_bcast<2>(tm), m3 = quad_bcast<3>(tm);
-                if (first_stop >= 1) D = fmaf(w1, m1, D);
-                if (first_stop >= 2) D = fmaf(w2, m2, D);
-                if (first_stop >= 3) D = fmaf(w3, m3, D);
-            }
-        }
-        if constexpr (COUNTS) {
-            const unsigned long long comp_mask = __ballot(contributes);
-            const int comp_bits = static_cast<int>((comp_mask >> quad_base) & 0xFull);
-            cnt_comp += __popc(comp_bits & ((2 << first_stop) - 1));
-        }
-        if (stop_bits) {
-            T = first_stop == 0 ? t1 : (first_stop == 1 ? t2 : (first_stop == 2 ? t3 : t4));
-            cnt_nom += static_cast<uint32_t>(first_stop + 1);
-            alive = false;
-        } else {
-            T = t4;
-            // next group: after the four samples, or past the brick of the fourth if it was skipped
-            const int next = last_skipped ? max(j0 + kQuad, jn3) : j0 + kQuad;
-            cnt_nom += static_cast<uint32_t>(min(next, ns) - j0);
-            j0 = next;
-            if (j0 >= ns) {
-                if (seg == 0 && nseg == 2) {
-                    seg = 1;
-                    sa = seg_a[1];
-                    sb = seg_b[1];
-                    g = JIT ? fmaf(-s_jit, ds, sa) : sa;
-                    ns = max(static_cast<int>(ceilf((sb - g) / ds)), 1);
-                    j0 = 0;
-                } else {
-                    alive = false;
-                }
-            }
-        }
-    }
-
-    if (!inside || sub != 0) return;
-    const float acc = 1.0f - T;
-    float4 res = make_float4(C0, C1, C2, acc);
-    if (A.has_bg) {
-        res.x = fmaf(T, A.bg[0], res.x);
-        res.y = fmaf(T, A.bg[1], res.y);
-        res.z = fmaf(T, A.bg[2], res.z);
-        res.w = fmaf(T, A.bg[3], res.w);
-    }
-    const size_t pix = static_cast<size_t>(py) * A.width + px;
-    f32x4 o4;
-    o4.x = res.x, o4.y = res.y, o4.z = res.z, o4.w = res.w;
-    if (!JIT || A.out != nullptr)
-        reinterpret_cast<__attribute__((address_space(1))) f32x4*>(reinterpret_cast<uintptr_t>(A.out))[pix] = o4;
-    if constexpr (JIT) {
-        if (A.mean != nullptr) {
-            // running mean over the passes: m <- m + (c - m) / (pass + 1), exactly c on pass 0
-            auto* m = reinterpret_cast<__attribute__((address_space(1))) f32x4*>(reinterpret_cast<uintptr_t>(A.mean));
-            f32x4 prev = A.pass == 0 ? o4 : m[pix];
-            f32x4 nm;
-            nm.x = fmaf(o4.x - prev.x, A.inv_pass1, prev.x);
-            nm.y = fmaf(o4.y - prev.y, A.inv_pass1, prev.y);
-            nm.z = fmaf(o4.z - prev.z, A.inv_pass1, prev.z);
-            nm.w = fmaf(o4.w - prev.w, A.inv_pass1, prev.w);
-            m[pix] = nm;
-        }
-    }
-    if constexpr (COUNTS) {
-        if (A.nominal) A.nominal[pix] = cnt_nom;
-        if (A.composited) A.composited[pix] = cnt_comp;
-    }
-    if constexpr (DEPTH) {
-        // the weights sum to the opacity 1 - T (before the background, which has no depth)
-        A.depth[pix] = acc > 0.0f ? D / acc : INFINITY;
-    }
-}
-
-template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false>
-__global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
-    int bx, by;
-    interleaved_tile(blockIdx.x, A.blocks_x, A.super_log2, bx, by);
-    if (by * kBlockTile >= A.height || bx * kBlockTile >= A.width) return;  // padding block
-    __shared__ float4 s_tf[256];
-    {
-        const f32x4 e = global_ptr<f32x4>(A.tf)[threadIdx.x];
-        s_tf[threadIdx.x] = make_float4(e.x, e.y, e.z, e.w);
-    }
-    __syncthreads();
-    march_tile<K, NB, COUNTS, JIT, DEPTH>(A, bx, by, s_tf);
-}
-
-// Batched launch: item j marches one tile of one request, as the ranges in the kernel arguments
-// say.  Tiles of many requests (different images, brushes, levels and transfer functions, one
-// kernel kind) share a launch; each tile runs exactly the code path of a single-request render.
-// Chunks of 16 consecutive items (one super-tile of a request, as the scheduler lists them) are
-// dealt round-robin over the 8 XCDs; the grid is padded to whole rounds of 8 chunks.
-template <int K>
-__global__ __launch_bounds__(256) void raymarch_batch_kernel(const RenderArgs* __restrict__ descs, BatchRanges R) {
-    __shared__ float4 s_tf[256];
-    const int xcd = blockIdx.x & 7, p = blockIdx.x >> 3;
-    const int j = ((p / kSuperTiles) * 8 + xcd) * kSuperTiles + p % kSuperTiles;
-    if (j >= R.end[R.n - 1]) return;  // padding block
-    int r = 0;
-    while (j >= R.end[r]) ++r;
-    const int tile = R.first[r] + j - (r ? R.end[r - 1] : 0);
-    const RenderArgs& A = descs[R.slot[r]];
-    {
-        const f32x4 e = global_ptr<f32x4>(A.tf)[threadIdx.x];
-        s_tf[threadIdx.x] = make_float4(e.x, e.y, e.z, e.w);
-    }
-    __syncthreads();
-    int bx, by;
-    tile_coords(tile, A.blocks_x, A.n_blocks / A.blocks_x, bx, by);
-    march_tile<K, kRuntimeNB, false>(A, bx, by, s_tf);
-}
-
-template <int K, bool COUNTS>
-hipError_t launch_nb(const RenderArgs& a, hipStream_t s) {
-    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x, a.super_log2)), block(256);
-    if (a.coord_mask) {
-        hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, COUNTS>), grid, block, 0, s, a);
-        return hipGetLastError();
-    }
-    switch (a.n_brushed) {
-        case 0: hipLaunchKernelGGL((raymarch_kernel<K, 0, COUNTS>), grid, block, 0, s, a); break;
-        case 1: hipLaunchKernelGGL((raymarch_kernel<K, 1, COUNTS>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((raymarch_kernel<K, 2, COUNTS>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((raymarch_kernel<K, 3, COUNTS>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((raymarch_kernel<K, 4, COUNTS>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((raymarch_kernel<K, 5, COUNTS>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((raymarch_kernel<K, 6, COUNTS>), grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((raymarch_kernel<K, 7, COUNTS>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((raymarch_kernel<K, 8, COUNTS>), grid, block, 0, s, a); break;
-    }
-    return hipGetLastError();
-}
-
-template <bool COUNTS>
-hipError_t launch_kind(const RenderArgs& a, int kind, hipStream_t s) {
-    switch (kind) {
-        case kKindF32: return launch_nb<kKindF32, COUNTS>(a, s);
-        case kKindF16: return launch_nb<kKindF16, COUNTS>(a, s);
-        case kKindU8: return launch_nb<kKindU8, COUNTS>(a, s);
-        case kKindF32Rec: return launch_nb<kKindF32Rec, COUNTS>(a, s);
-        case kKindF16Rec: return launch_nb<kKindF16Rec, COUNTS>(a, s);
-        default: return launch_nb<kKindU8Rec, COUNTS>(a, s);
-    }
-}
-
-}  // namespace
-
-hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& R, int kind, hipStream_t s) {
-    if (R.n <= 0 || R.n > kMaxRanges || R.end[R.n - 1] <= 0) return hipSuccess;
-    constexpr int kRound = 8 * kSuperTiles;
-    const dim3 grid((R.end[R.n - 1] + kRound - 1) / kRound * kRound), block(256);
-    switch (kind) {
-        case kKindF32: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF32>, grid, block, 0, s, descs, R); break;
-        case kKindF16: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16>, grid, block, 0, s, descs, R); break;
-        case kKindU8: hipLaunchKernelGGL(raymarch_batch_kernel<kKindU8>, grid, block, 0, s, descs, R); break;
-        case kKindF32Rec: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF32Rec>, grid, block, 0, s, descs, R); break;
-        case kKindF16Rec: hipLaunchKernelGGL(raymarch_batch_kernel<kKindF16Rec>, grid, block, 0, s, descs, R); break;
-        default: hipLaunchKernelGGL(raymarch_batch_kernel<kKindU8Rec>, grid, block, 0, s, descs, R); break;
-    }
-    return hipGetLastError();
-}
-
-namespace {
-template <int K, bool COUNTS>
-hipError_t launch_jit(const RenderArgs& a, hipStream_t s) {
-    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x, a.super_log2)), block(256);
-    hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, COUNTS, true>), grid, block, 0, s, a);
-    return hipGetLastError();
-}
-template <bool COUNTS>
-hipError_t launch_jit_kind(const RenderArgs& a, int kind, hipStream_t s) {
-    switch (kind) {
-        case kKindF32: return launch_jit<kKindF32, COUNTS>(a, s);
-        case kKindF16: return launch_jit<kKindF16, COUNTS>(a, s);
-        case kKindU8: return launch_jit<kKindU8, COUNTS>(a, s);
-        case kKindF32Rec: return launch_jit<kKindF32Rec, COUNTS>(a, s);
-        case kKindF16Rec: return launch_jit<kKindF16Rec, COUNTS>(a, s);
-        default: return launch_jit<kKindU8Rec, COUNTS>(a, s);
-    }
-}
-}  // namespace
-
-hipError_t launch_render_jittered(const RenderArgs& a, int kind, bool counts, hipStream_t s) {
-    return counts ? launch_jit_kind<true>(a, kind, s) : launch_jit_kind<false>(a, kind, s);
-}
-
-namespace {
-template <int K>
-hipError_t launch_depth(const RenderArgs& a, hipStream_t s) {
-    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x, a.super_log2)), block(256);
-    hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, false, false, true>), grid, block, 0, s, a);
-    return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_render_depth(const RenderArgs& a, int kind, hipStream_t s) {
-    switch (kind) {
-        case kKindF32: return launch_depth<kKindF32>(a, s);
-        case kKindF16: return launch_depth<kKindF16>(a, s);
-        case kKindU8: return launch_depth<kKindU8>(a, s);
-        case kKindF32Rec: return launch_depth<kKindF32Rec>(a, s);
-        case kKindF16Rec: return launch_depth<kKindF16Rec>(a, s);
-        default: return launch_depth<kKindU8Rec>(a, s);
-    }
-}
 
 hipError_t launch_render(const RenderArgs& a, int kind, bool counts, hipStream_t s) {
-    return counts ? launch_kind<true>(a, kind, s) : launch_kind<false>(a, kind, s);
+    return counts ? launch_fixed_kind<true, false, false>(a, kind, s) : launch_fixed_kind<false, false, false>(a, kind, s);
 }
 
 }  // namespace raypc
+

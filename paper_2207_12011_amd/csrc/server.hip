@@ -61,6 +61,7 @@ struct Request {
     SkipArgs skip_args{};          // complete except the output pointers
     float tf_rgba[RAYPC_TF_ENTRIES * 4];
     int storage = 0;  // kernel kind
+    int nb_class = 0;  // field-count class of its launches (batch_nb_class)
     int n_tiles = 0, next_tile = 0;
     uint64_t bytes = 0;
     int slot = -1;
@@ -228,8 +229,8 @@ bool has_pending_tiles(const Server* S) {
     return false;
 }
 
-// One batched step: tile ranges of the admitted requests, oldest first, one launch per kernel kind
-// (more if a kind has more ranges than one launch carries).
+// One batched step: tile ranges of the admitted requests, oldest first, one launch per kernel kind and
+// field-count class present (more if one has more ranges than a launch carries).
 void launch_step(Server* S) {
     struct Take {
         Request* r;
@@ -254,25 +255,27 @@ void launch_step(Server* S) {
     }
     int k = 0;
     for (int kind = 0; kind < kKinds && e == hipSuccess; ++kind) {
-        BatchRanges R;
-        R.n = 0;
-        int items = 0;
-        for (const Take& t : takes) {
-            if (t.r->storage != kind) continue;
-            if (R.n == kMaxRanges) {
-                e = launch_render_batch(S->d_args, R, kind, s);
-                if (e != hipSuccess) break;
-                R.n = 0;
-                items = 0;
+        for (int nb = -1; nb <= kMaxFields && e == hipSuccess; ++nb) {
+            BatchRanges R;
+            R.n = 0;
+            int items = 0;
+            for (const Take& t : takes) {
+                if (t.r->storage != kind || t.r->nb_class != nb) continue;
+                if (R.n == kMaxRanges) {
+                    e = launch_render_batch(S->d_args, R, kind, nb, s);
+                    if (e != hipSuccess) break;
+                    R.n = 0;
+                    items = 0;
+                }
+                items += t.count;
+                R.end[R.n] = items;
+                R.first[R.n] = t.start;
+                R.slot[R.n] = t.r->slot;
+                R.n++;
+                k += t.count;
             }
-            items += t.count;
-            R.end[R.n] = items;
-            R.first[R.n] = t.start;
-            R.slot[R.n] = t.r->slot;
-            R.n++;
-            k += t.count;
+            if (e == hipSuccess && R.n) e = launch_render_batch(S->d_args, R, kind, nb, s);
         }
-        if (e == hipSuccess && R.n) e = launch_render_batch(S->d_args, R, kind, s);
     }
     Step step;
     if (S->events.empty()) {
@@ -442,6 +445,7 @@ int raypc_submit(raypc_ctx* ctx, const raypc_request* req, uint64_t* ticket) {
             delete r;
             return rc;
         }
+        r->nb_class = batch_nb_class(r->args);
         build_skip_args(ctx, v, level, req->active, req->lo, req->hi, coord, req->tf_slot, r->skip_args);
         std::memcpy(r->tf_rgba, ctx->tf[req->tf_slot].rgba, sizeof(r->tf_rgba));
         r->n_tiles = r->args.n_blocks;
