@@ -245,7 +245,8 @@ int raypc_get_launch_shape(raypc_ctx *ctx, int *super_log2);
 /* Autotuner of the launch shape: renders the given view (as raypc_render, with the volume's brush
  * and transfer slot 0) once untimed and then `repeats` (1..1000) times back to back for each
  * super-tile size s = 0..3, timing each run with HIP events on a stream of its own, and makes the
- * fastest the context's launch shape.  times_ms (4 floats, may be NULL) receives the mean time of
+ * fastest the context's launch shape (the default s = 2 stays unless another shape is more than
+ * 1 % faster, so that runs on one device agree).  times_ms (4 floats, may be NULL) receives the mean time of
  * one render per s; best (may be NULL) the chosen s.  Synchronous; allocates one image for the
  * duration of the call.  On error the previous launch shape stays.  Errors: as raypc_render, plus
  * RAYPC_ERR_INVALID for repeats out of range and RAYPC_ERR_NOMEM. */

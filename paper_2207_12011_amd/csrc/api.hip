@@ -972,9 +972,11 @@ int raypc_autotune_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam
     if (s) (void)hipStreamSynchronize(s);
     int b = saved;
     if (!rc) {
-        b = 0;
-        for (int c = 1; c <= kMaxSuperLog2; ++c)
-            if (t[c] < t[b]) b = c;
+        // the default shape stays unless another is faster by more than the timing noise (1 %), so
+        // that runs on one device agree on the shape
+        b = kDefaultSuperLog2;
+        for (int c = 0; c <= kMaxSuperLog2; ++c)
+            if (t[c] < t[b] && t[c] < 0.99f * t[kDefaultSuperLog2]) b = c;
         if (times_ms)
             for (int c = 0; c <= kMaxSuperLog2; ++c) times_ms[c] = t[c];
         if (best) *best = b;

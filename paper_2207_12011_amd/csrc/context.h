@@ -13,6 +13,8 @@ namespace raypc {
 
 struct Server;
 
+constexpr int kDefaultSuperLog2 = 2;  // default launch shape: super-tiles of 4 x 4 blocks (32 x 32 pixels)
+
 struct Level {
     int n = 0, nb = 0;
     void* data[kMaxFields] = {};
@@ -89,7 +91,7 @@ struct raypc_ctx {
     raypc::Server* server = nullptr;
     unsigned long long* warp_keys = nullptr;  // image-warp z-buffer, grown on demand
     size_t warp_keys_n = 0;
-    int super_log2 = 2;  // launch shape of single-image renders (raypc_set_launch_shape)
+    int super_log2 = raypc::kDefaultSuperLog2;  // launch shape of single-image renders (raypc_set_launch_shape)
 };
 
 

@@ -67,7 +67,8 @@ def test_autotune_render_keeps_the_fastest(rp, ctx):
     try:
         best, times = rp.autotune_render(ctx, vid, cam, wl.width, wl.height, 0, 0.5, repeats=5)
         print(f"[autotune] ms per render for super-tiles of 8/16/32/64 px: {times}, best {best}", flush=True)
-        assert 0 <= best <= 3 and all(t > 0 for t in times) and times[best] == min(times)
+        assert 0 <= best <= 3 and all(t > 0 for t in times)
+        assert times[best] == min(times) and times[best] < 0.99 * times[2] if best != 2 else min(times) >= 0.99 * times[2]
         assert rp.get_launch_shape(ctx) == best
         cache = {}
         key = AT.render_key(AT.device_name(), 64, "f16", wl.width, wl.height, 0, 0.5)
