@@ -403,6 +403,43 @@ def test_field_order_does_not_change_the_image(rp, ctx, small5, storage):
         rp.unload(ctx, vid)
 
 
+def test_narrow_storage_equals_float32_on_representable_data(rp, ctx, small5):
+    """Fields of integers in [0, 255] with a 0 and a 255 in every 8^3 brick: binary16 holds them
+    exactly and the 8-bit scale of every brick is exactly 1, so all storages and layouts store the
+    same values and must render the same image and counts, bit for bit (level 0)."""
+    wl = small5
+    f = wl.fields
+    lo_f, hi_f = f.reshape(5, -1).min(axis=1), f.reshape(5, -1).max(axis=1)
+    q = np.rint((f - lo_f[:, None, None, None]) / (hi_f - lo_f)[:, None, None, None] * 255).astype(np.float32)
+    q[:, ::8, ::8, ::8] = 0.0
+    q[:, ::8, ::8, 1::8] = 255.0
+    fields = np.ascontiguousarray(q)
+    m = W.shell_mask(W.radius(64))
+    # bounds half-way between integers, so that few samples sit on a bound
+    brush_lo = np.array([np.quantile(fields[k][m], 0.3) + 0.5 for k in range(5)], np.float32)
+    brush_hi = np.array([np.quantile(fields[k][m], 0.95) - 0.5 for k in range(5)], np.float32)
+    act = np.array([1, 1, 0, 1, 1], np.uint8)
+    cam = wl.camera.as_array()
+    want = None
+    for storage in ("f32", "f16", "u8", "f32c", "f16c", "u8c"):
+        print(f"[case] representable data, {storage}", flush=True)
+        vid = rp.load_fields(ctx, torch.from_numpy(fields).cuda(), storage, 1, wl.r_inner, wl.r_outer)
+        rp.set_brush(ctx, vid, act, brush_lo, brush_hi)
+        rp.set_transfer_function(ctx, 0, 1, 0.0, 255.0, wl.tf.rgba, wl.tf.ref_step)
+        rp.set_options(ctx, wl.ert)
+        level = cpu(rp.export_level(ctx, vid, 0, 2))
+        assert np.array_equal(level, fields[2]), storage
+        got = gpu_render(rp, ctx, vid, wl, 0)
+        rp.unload(ctx, vid)
+        if want is None:
+            want = got
+            ref = oracle.render_workload(wl, fields, active=act, lo=brush_lo, hi=brush_hi, tf_field=1, vmin=0.0,
+                                         vmax=255.0)
+            compare(got[0], ref, got[1], got[2], label="representable data f32")
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(got, want)), storage
+
+
 @pytest.fixture(scope="module")
 def c2():
     return W.make_workload(2)
