@@ -303,6 +303,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     }
 
     const int n = A.n, nb = A.nb;
+    const uint32_t nbu = static_cast<uint32_t>(nb);
     const float hn = A.half_n;
     const float uox = fmaf(ox, hn, hn - 0.5f), uoy = fmaf(oy, hn, hn - 0.5f), uoz = fmaf(oz, hn, hn - 0.5f);
     const float dux = dx * hn, duy = dy * hn, duz = dz * hn;
@@ -353,7 +354,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
             const int y0 = min(max(iy, 0), n - 1), y1 = min(max(iy + 1, 0), n - 1);
             const int z0 = min(max(iz, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
             const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
-            const uint32_t brick = (static_cast<uint32_t>(bzi) * nb + byi) * nb + bxi;
+            // brick rows and slabs below 2^7, bricks per row below 2^8: 24-bit products are exact
+            const uint32_t brick = __umul24(__umul24(static_cast<uint32_t>(bzi), nbu) + byi, nbu) + bxi;
             const uint32_t flags = A.skip != nullptr ? global_ptr<uint8_t>(A.skip)[brick] : 0u;
             const uint32_t sub = ((x0 >> 2) & 1) | (((y0 >> 2) & 1) << 1) | (((z0 >> 2) & 1) << 2);
             if ((flags >> sub) & 1u) {
@@ -456,83 +458,70 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
         // ---- advance past a skipped brick of the quad's fourth sample
         const int last_skipped = quad_bcast<3>(static_cast<int>(skipped && valid));
         const int jn3 = quad_bcast<3>(jn);
-        if (__ballot(contributes) == 0ull) {
-            // nothing to composite anywhere in the wave: T and C are unchanged
-            const int next = last_skipped ? max(j0 + kQuad, jn3) : j0 + kQuad;
-            cnt_nom += static_cast<uint32_t>(min(next, ns) - j0);
-            j0 = next;
-            if (j0 >= ns) {
-                if (seg == 0 && nseg == 2) {
-                    seg = 1;
-                    sa = seg_a[1];
-                    sb = seg_b[1];
-                    g = JIT ? fmaf(-s_jit, ds, sa) : sa;
-                    ns = max(static_cast<int>(ceilf((sb - g) / ds)), 1);
-                    j0 = 0;
-                } else {
-                    alive = false;
+        bool stopped = false;
+        if (__ballot(contributes) != 0ull) {  // else nothing to composite anywhere in the wave
+            // ---- merge the quad's four samples in sample order.  Every lane replays the same
+            // sequential updates (T <- T k, C <- fma(w, rgb, C)) on broadcast values, so the ray
+            // state is identical in the four lanes and independent of how samples were grouped
+            // (a skipped or discarded sample has k = 1 and w = 0, both exact).
+            const float k0 = quad_bcast<0>(keep), k1 = quad_bcast<1>(keep);
+            const float k2 = quad_bcast<2>(keep), k3 = quad_bcast<3>(keep);
+            const float t1 = T * k0, t2 = t1 * k1, t3 = t2 * k2, t4 = t3 * k3;  // T after each sample
+            const float t_before = sub == 0 ? T : (sub == 1 ? t1 : (sub == 2 ? t2 : t3));
+            const float t_after = sub == 0 ? t1 : (sub == 1 ? t2 : (sub == 2 ? t3 : t4));
+            const float w = t_before * (1.0f - keep);
+            const bool stop_here = contributes && A.ert_on && (1.0f - t_after >= A.ert);
+            const unsigned long long stop_mask = __ballot(stop_here);
+            const int stop_bits = static_cast<int>((stop_mask >> quad_base) & 0xFull);
+            const int first_stop = stop_bits ? __ffs(stop_bits) - 1 : kQuad - 1;  // last sample that counts
+            {
+                const float w0 = quad_bcast<0>(w), w1 = quad_bcast<1>(w), w2 = quad_bcast<2>(w), w3 = quad_bcast<3>(w);
+                const float r0 = quad_bcast<0>(cr), r1 = quad_bcast<1>(cr), r2 = quad_bcast<2>(cr), r3 = quad_bcast<3>(cr);
+                const float g0 = quad_bcast<0>(cg), g1 = quad_bcast<1>(cg), g2 = quad_bcast<2>(cg), g3 = quad_bcast<3>(cg);
+                const float b0 = quad_bcast<0>(cb), b1 = quad_bcast<1>(cb), b2 = quad_bcast<2>(cb), b3 = quad_bcast<3>(cb);
+                C0 = fmaf(w0, r0, C0);
+                C1 = fmaf(w0, g0, C1);
+                C2 = fmaf(w0, b0, C2);
+                if (first_stop >= 1) {
+                    C0 = fmaf(w1, r1, C0);
+                    C1 = fmaf(w1, g1, C1);
+                    C2 = fmaf(w1, b1, C2);
+                }
+                if (first_stop >= 2) {
+                    C0 = fmaf(w2, r2, C0);
+                    C1 = fmaf(w2, g2, C1);
+                    C2 = fmaf(w2, b2, C2);
+                }
+                if (first_stop >= 3) {
+                    C0 = fmaf(w3, r3, C0);
+                    C1 = fmaf(w3, g3, C1);
+                    C2 = fmaf(w3, b3, C2);
+                }
+                if constexpr (DEPTH) {
+                    // samples that were not composited have w = 0 and a finite tm: no change
+                    D = fmaf(w0, quad_bcast<0>(tm), D);
+                    const float m1 = quad_bcast<1>(tm), m2 = quad_bcast<2>(tm), m3 = quad_bcast<3>(tm);
+                    if (first_stop >= 1) D = fmaf(w1, m1, D);
+                    if (first_stop >= 2) D = fmaf(w2, m2, D);
+                    if (first_stop >= 3) D = fmaf(w3, m3, D);
                 }
             }
-            continue;
-        }
-
-        // ---- merge the quad's four samples in sample order.  Every lane replays the same
-        // sequential updates (T <- T k, C <- fma(w, rgb, C)) on broadcast values, so the ray
-        // state is identical in the four lanes and independent of how samples were grouped
-        // (a skipped or discarded sample has k = 1 and w = 0, both exact).
-        const float k0 = quad_bcast<0>(keep), k1 = quad_bcast<1>(keep);
-        const float k2 = quad_bcast<2>(keep), k3 = quad_bcast<3>(keep);
-        const float t1 = T * k0, t2 = t1 * k1, t3 = t2 * k2, t4 = t3 * k3;  // T after each sample
-        const float t_before = sub == 0 ? T : (sub == 1 ? t1 : (sub == 2 ? t2 : t3));
-        const float t_after = sub == 0 ? t1 : (sub == 1 ? t2 : (sub == 2 ? t3 : t4));
-        const float w = t_before * (1.0f - keep);
-        const bool stop_here = contributes && A.ert_on && (1.0f - t_after >= A.ert);
-        const unsigned long long stop_mask = __ballot(stop_here);
-        const int stop_bits = static_cast<int>((stop_mask >> quad_base) & 0xFull);
-        const int first_stop = stop_bits ? __ffs(stop_bits) - 1 : kQuad - 1;  // last sample that counts
-        {
-            const float w0 = quad_bcast<0>(w), w1 = quad_bcast<1>(w), w2 = quad_bcast<2>(w), w3 = quad_bcast<3>(w);
-            const float r0 = quad_bcast<0>(cr), r1 = quad_bcast<1>(cr), r2 = quad_bcast<2>(cr), r3 = quad_bcast<3>(cr);
-            const float g0 = quad_bcast<0>(cg), g1 = quad_bcast<1>(cg), g2 = quad_bcast<2>(cg), g3 = quad_bcast<3>(cg);
-            const float b0 = quad_bcast<0>(cb), b1 = quad_bcast<1>(cb), b2 = quad_bcast<2>(cb), b3 = quad_bcast<3>(cb);
-            C0 = fmaf(w0, r0, C0);
-            C1 = fmaf(w0, g0, C1);
-            C2 = fmaf(w0, b0, C2);
-            if (first_stop >= 1) {
-                C0 = fmaf(w1, r1, C0);
-                C1 = fmaf(w1, g1, C1);
-                C2 = fmaf(w1, b1, C2);
+            if constexpr (COUNTS) {
+                const unsigned long long comp_mask = __ballot(contributes);
+                const int comp_bits = static_cast<int>((comp_mask >> quad_base) & 0xFull);
+                cnt_comp += __popc(comp_bits & ((2 << first_stop) - 1));
             }
-            if (first_stop >= 2) {
-                C0 = fmaf(w2, r2, C0);
-                C1 = fmaf(w2, g2, C1);
-                C2 = fmaf(w2, b2, C2);
-            }
-            if (first_stop >= 3) {
-                C0 = fmaf(w3, r3, C0);
-                C1 = fmaf(w3, g3, C1);
-                C2 = fmaf(w3, b3, C2);
-            }
-            if constexpr (DEPTH) {
-                // samples that were not composited have w = 0 and a finite tm: no change
-                D = fmaf(w0, quad_bcast<0>(tm), D);
-                const float m1 = quad_bcast<1>(tm), m2 = quad_bcast<2>(tm), m3 = quad_bcast<3>(tm);
-                if (first_stop >= 1) D = fmaf(w1, m1, D);
-                if (first_stop >= 2) D = fmaf(w2, m2, D);
-                if (first_stop >= 3) D = fmaf(w3, m3, D);
+            if (stop_bits) {
+                T = first_stop == 0 ? t1 : (first_stop == 1 ? t2 : (first_stop == 2 ? t3 : t4));
+                cnt_nom += static_cast<uint32_t>(first_stop + 1);
+                stopped = true;
+            } else {
+                T = t4;
             }
         }
-        if constexpr (COUNTS) {
-            const unsigned long long comp_mask = __ballot(contributes);
-            const int comp_bits = static_cast<int>((comp_mask >> quad_base) & 0xFull);
-            cnt_comp += __popc(comp_bits & ((2 << first_stop) - 1));
-        }
-        if (stop_bits) {
-            T = first_stop == 0 ? t1 : (first_stop == 1 ? t2 : (first_stop == 2 ? t3 : t4));
-            cnt_nom += static_cast<uint32_t>(first_stop + 1);
+        if (stopped) {
             alive = false;
         } else {
-            T = t4;
             // next group: after the four samples, or past the brick of the fourth if it was skipped
             const int next = last_skipped ? max(j0 + kQuad, jn3) : j0 + kQuad;
             cnt_nom += static_cast<uint32_t>(min(next, ns) - j0);
