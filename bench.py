@@ -396,6 +396,7 @@ def main():
     ap.add_argument("--storages", default="f16,f32,u8,u8c",
                     help="first one is the headline value; a trailing c keeps only the compact layout")
     ap.add_argument("--cpu-stride", type=int, default=1, help="oracle sample: every k-th row and column")
+    ap.add_argument("--orbit-frames", type=int, default=200, help="single-request latency frames (seeded orbit cameras)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--width", type=int, default=1920)
@@ -512,6 +513,21 @@ def main():
         torch.cuda.synchronize()
         kms = float(np.mean([a.elapsed_time(e) for a, e in kev]))
 
+        # single-request latency over seeded orbit cameras (headline brush, LOD by the rule, HIP events)
+        orng = np.random.default_rng(220712011 + 7)
+        ocams = [W.orbit_camera(orng.uniform(0.0, 2 * math.pi), math.radians(orng.uniform(-60.0, 60.0))).as_array()
+                 for _ in range(args.orbit_frames)]
+        raypc.set_brush(ctx, vid, b.active, b.lo, b.hi)
+        for c in ocams[:5]:
+            raypc.render(ctx, vid, c, W_, H_, -1, wl.step, out=out, stream=stream)
+        oev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in ocams]
+        for c, (a_, e_) in zip(ocams, oev):
+            a_.record(stream)
+            raypc.render(ctx, vid, c, W_, H_, -1, wl.step, out=out, stream=stream)
+            e_.record(stream)
+        torch.cuda.synchronize()
+        olat = [a_.elapsed_time(e_) for a_, e_ in oev]
+
         alg_bytes = touched_bricks[0] * 512 * n_needed * bpv[storage] + W_ * H_ * IMAGE_BYTES_PER_PIXEL
         if storage.startswith("u8"):
             alg_bytes += touched_bricks[0] * 8 * n_needed
@@ -529,6 +545,9 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
             "alg_ops_per_launch": alg_ops,
             "volume_bytes": raypc.volume_info(ctx, vid)["bytes"],
+            "orbit_latency_ms": {"frames": len(olat), "p50": percentile(olat, 50), "p99": percentile(olat, 99),
+                                 "max": max(olat), "cameras": "seeded orbit: azimuth U[0, 360), elevation U[-60, 60] deg, "
+                                                              "distance 3, up +z, 60 deg"},
             "launch_shape": {"super_tile_px": shape["tile_px"], "ms_by_super_tile_px":
                              {str(8 << k): t for k, t in enumerate(shape["ms"])}},
         }
