@@ -469,6 +469,35 @@ def test_precision_512_full_size_sampled(rp, ctx, c2):
         rp.unload(ctx, vid)
 
 
+def test_jitter_and_coordinates_512_full_size_sampled(rp, ctx, c2):
+    """The widened rows at the full 512^3 x 5 / 1920x1080 size (f16, sampled pixels): one jittered
+    pass against the oracle given the same per-pixel offsets, and a coordinate cut (an x slab with a
+    radius floor) against the oracle, with exact counts on non-fragile pixels."""
+    from oracle import jitter as J
+    wl = c2
+    print("[case] 512^3 x 5, 1920x1080, jittered pass and coordinate cut (f16)", flush=True)
+    vid = rp.load_fields(ctx, torch.from_numpy(wl.fields).cuda(), "f16", 1, wl.r_inner, wl.r_outer)
+    rp.set_brush(ctx, vid, wl.brush.active, wl.brush.lo, wl.brush.hi)
+    rp.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
+    rp.set_options(ctx, wl.ert)
+    level = np.stack([pp.stored_values(wl.fields[f], "f16") for f in range(wl.n_fields)])
+    pix = sample_pixels(wl.width, wl.height, 2000, seed=5)
+    cam = wl.camera.as_array()
+    try:
+        rgba, nom, comp = rp.render_jittered(ctx, vid, cam, wl.width, wl.height, 0, wl.step, 3, 8, 0x2207, counts=True)
+        s = J.offsets(wl.width, pix, 3, 8, 0x2207)
+        ref = oracle.render_workload(wl, level, pixels=pix, jitter=s)
+        compare(cpu(rgba).reshape(-1, 4)[pix], ref, cpu(nom).reshape(-1)[pix], cpu(comp).reshape(-1)[pix],
+                label="c2 f16 jittered pass 3 of 8")
+        coord = ([1, 0, 0, 1], [-0.3, 0, 0, 0.7], [0.4, 0, 0, 2.0])
+        rp.set_coordinate_brush(ctx, vid, *coord)
+        rgba, nom, comp = gpu_render(rp, ctx, vid, wl, 0)
+        ref = oracle.render_workload(wl, level, pixels=pix, coord=coord)
+        compare(rgba.reshape(-1, 4)[pix], ref, nom.reshape(-1)[pix], comp.reshape(-1)[pix], label="c2 f16 coordinate cut")
+    finally:
+        rp.unload(ctx, vid)
+
+
 # Bounds on the storage-precision error of whole images (every pixel, fragile ones included) against
 # the FP64 oracle on the original float32 fields.  float32 storage differs from the reference only by
 # FP32 arithmetic and the threshold decisions it flips; binary16 and 8-bit codes move sample values by
