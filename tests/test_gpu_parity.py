@@ -510,7 +510,7 @@ PRECISION_BOUNDS = {"f32": (0.05, 1e-5, 2e-4), "f16": (0.15, 3e-4, 0.01), "u8": 
 
 
 def test_storage_precision_report(rp, ctx, c2):
-    """SURVEY c2 precision study: per storage, max-abs / mean-abs RGBA error and the fraction of pixels
+    """Precision study (512^3 x 5 fields, 1920x1080): per storage, max-abs / mean-abs RGBA error and the fraction of pixels
     with error > 1e-2 against the FP64 oracle on the ORIGINAL float32 fields (every 4th row and
     column of the 1920x1080 frame)."""
     wl = c2
