@@ -282,9 +282,10 @@ int raypc_render_depth(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, i
  * Outputs (device, dst_height x dst_width): rgba_out = the winner's RGBA unchanged (0 where empty);
  * depth_out (may be NULL) = the winner's distance from dst_cam's eye (+inf where empty);
  * source_out (may be NULL) = the winner's linear source index py * src_width + px (-1 where
- * empty).  Outputs must not overlap the inputs or each other.  The context keeps an 8-byte-per-
- * destination-pixel z-buffer, grown (after a device synchronisation) when a larger image comes;
- * warps in flight on different streams of one context race on it.  Sizes 1..16384 per side.
+ * empty).  Outputs must not overlap the inputs or each other.  The context keeps two 8-byte-per-
+ * destination-pixel z-buffers, used in turn (each warp empties the other one's pixels for the next
+ * warp) and grown (after a device synchronisation) when a larger image comes; warps in flight on
+ * different streams of one context race on them.  Sizes 1..16384 per side.
  * Async on `stream`.  Errors: RAYPC_ERR_INVALID (NULL input or output image, bad camera or size,
  * overlapping buffers), RAYPC_ERR_NOMEM. */
 int raypc_warp(raypc_ctx *ctx, const raypc_camera *src_cam, int src_width, int src_height, const float *rgba,

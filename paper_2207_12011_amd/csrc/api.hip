@@ -456,7 +456,8 @@ void raypc_destroy(raypc_ctx* ctx) {
     (void)hipDeviceSynchronize();
     for (auto& kv : ctx->vols) free_volume(kv.second);
     for (auto& t : ctx->tf) (void)hipFree(t.dev);
-    if (ctx->warp_keys) (void)hipFree(ctx->warp_keys);
+    for (auto* k : ctx->warp_keys)
+        if (k) (void)hipFree(k);
     delete ctx;
 }
 
@@ -890,23 +891,41 @@ int raypc_warp(raypc_ctx* ctx, const raypc_camera* src_cam, int src_width, int s
     DeviceGuard g(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (nd > ctx->warp_keys_n) {
-        // a warp still in flight may use the old buffer
-        HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize before growing the warp buffer");
-        if (ctx->warp_keys) (void)hipFree(ctx->warp_keys);
-        ctx->warp_keys = nullptr;
+        // a warp still in flight may use the old buffers
+        HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize before growing the warp buffers");
+        for (int i = 0; i < 2; ++i) {
+            if (ctx->warp_keys[i]) (void)hipFree(ctx->warp_keys[i]);
+            ctx->warp_keys[i] = nullptr;
+            ctx->warp_clean_n[i] = 0;
+        }
         ctx->warp_keys_n = 0;
-        if (hipMalloc(reinterpret_cast<void**>(&ctx->warp_keys), nd * sizeof(unsigned long long)) != hipSuccess)
-            return fail(RAYPC_ERR_NOMEM, "warp z-buffer of %zu pixels", nd);
+        for (int i = 0; i < 2; ++i) {
+            if (hipMalloc(reinterpret_cast<void**>(&ctx->warp_keys[i]), nd * sizeof(unsigned long long)) != hipSuccess) {
+                (void)hipGetLastError();
+                for (int j = 0; j < i; ++j) {
+                    (void)hipFree(ctx->warp_keys[j]);
+                    ctx->warp_keys[j] = nullptr;
+                }
+                return fail(RAYPC_ERR_NOMEM, "warp z-buffers of %zu pixels", nd);
+            }
+        }
         ctx->warp_keys_n = nd;
     }
+    const int cur = ctx->warp_cur, other = 1 - cur;
     w.rgba = reinterpret_cast<const float4*>(rgba);
     w.depth = depth;
     w.n_src = static_cast<uint32_t>(ns);
-    w.keys = ctx->warp_keys;
+    w.keys = ctx->warp_keys[cur];
+    w.clear_keys = ctx->warp_clean_n[cur] < nd;
+    w.next_keys = ctx->warp_keys[other];
     w.out = reinterpret_cast<float4*>(rgba_out);
     w.out_depth = depth_out;
     w.out_src = source_out;
+    ctx->warp_clean_n[cur] = 0;  // holds this warp's keys from now on
+    ctx->warp_clean_n[other] = 0;
     HIP_TRY(launch_warp(w, static_cast<hipStream_t>(stream)), "warp kernel launches");
+    ctx->warp_clean_n[other] = nd;  // emptied by this warp's resolve
+    ctx->warp_cur = other;
     return RAYPC_OK;
 }
 

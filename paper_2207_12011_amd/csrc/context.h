@@ -89,8 +89,10 @@ struct raypc_ctx {
     bool has_bg = false;
     std::mutex mu;  // guards state shared with the serving thread
     raypc::Server* server = nullptr;
-    unsigned long long* warp_keys = nullptr;  // image-warp z-buffer, grown on demand
-    size_t warp_keys_n = 0;
+    unsigned long long* warp_keys[2] = {nullptr, nullptr};  // image-warp z-buffers, used in turn, grown on demand
+    size_t warp_keys_n = 0;        // capacity of each, pixels
+    size_t warp_clean_n[2] = {0, 0};  // leading pixels of each known to hold the empty key
+    int warp_cur = 0;              // the buffer the next warp splats into
     int super_log2 = raypc::kDefaultSuperLog2;  // launch shape of single-image renders (raypc_set_launch_shape)
 };
 

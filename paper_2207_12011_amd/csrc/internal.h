@@ -203,6 +203,8 @@ struct WarpArgs {
     const float* depth;           // src H x W
     uint32_t n_src;               // src H * W
     unsigned long long* keys;     // dst H x W z-buffer (scratch)
+    int clear_keys;               // keys not known to be empty: fill them first
+    unsigned long long* next_keys;  // the other z-buffer: the resolve empties its dst H x W pixels (may be null)
     float4* out;                  // dst H x W
     float* out_depth;             // may be null
     int32_t* out_src;             // may be null

@@ -19,10 +19,12 @@
 // in float32 one correctly rounded operation at a time (the library is compiled without contraction;
 // float32 division and square root compile to correctly rounded sequences), in a fixed order.
 //
-// Mapping to CDNA4.  Three passes over the destination and source images, all bound by memory:
-// a fill of the 64-bit keys, a splat (one lane per source pixel: 20 bytes in, one 64-bit atomic
-// minimum on the key of its landing pixel), and a resolve (one lane per destination pixel: its key,
-// for empty pixels the eight neighbour keys, a 16-byte gather of the winner's RGBA and the outputs).
+// Mapping to CDNA4.  Two passes over the source and destination images, both bound by memory: a
+// splat (one lane per source pixel: 20 bytes in, one 64-bit atomic minimum on the key of its landing
+// pixel) and a resolve (one lane per destination pixel: its key, for empty pixels the eight neighbour
+// keys, a 16-byte gather of the winner's RGBA and the outputs).  Two z-buffers are used in turn: the
+// resolve empties its pixels in the other one, so the next warp of no larger size needs no fill pass
+// (a fill kernel runs only when a buffer is not known to be empty).
 // Blocks cover 16 x 16 pixel tiles so that a block's atomics and neighbour reads stay within a few
 // cache lines of keys.
 #include <algorithm>
@@ -122,14 +124,17 @@ __global__ __launch_bounds__(256) void warp_resolve_kernel(WarpArgs A) {
     reinterpret_cast<f32x4*>(A.out)[t] = c;
     if (A.out_depth) A.out_depth[t] = dep;
     if (A.out_src) A.out_src[t] = src;
+    if (A.next_keys) A.next_keys[t] = kEmpty;  // ready for the next warp, which uses the other buffer
 }
 
 }  // namespace
 
 hipError_t launch_warp(const WarpArgs& a, hipStream_t s) {
     const size_t n_dst = static_cast<size_t>(a.dst.width) * a.dst.height;
-    const unsigned clear_blocks = static_cast<unsigned>(std::min<size_t>((n_dst + 255) / 256, 8192));
-    hipLaunchKernelGGL(warp_clear_kernel, dim3(clear_blocks), dim3(256), 0, s, a.keys, n_dst);
+    if (a.clear_keys) {
+        const unsigned clear_blocks = static_cast<unsigned>(std::min<size_t>((n_dst + 255) / 256, 8192));
+        hipLaunchKernelGGL(warp_clear_kernel, dim3(clear_blocks), dim3(256), 0, s, a.keys, n_dst);
+    }
     const dim3 src_grid((a.src.width + kTile - 1) / kTile, (a.src.height + kTile - 1) / kTile);
     hipLaunchKernelGGL(warp_splat_kernel, src_grid, dim3(256), 0, s, a);
     const dim3 dst_grid((a.dst.width + kTile - 1) / kTile, (a.dst.height + kTile - 1) / kTile);

@@ -152,6 +152,20 @@ def test_warp_bitexact(rp, ctx, move, sizes):
         assert np.all(src == -1)
 
 
+def test_warps_in_a_row_of_changing_sizes(rp, ctx):
+    """Warps use two z-buffers in turn, each emptied by the previous warp's resolve up to that warp's
+    size: a sequence that grows, shrinks and grows again (fill passes needed and not needed) must
+    give the oracle's result every time."""
+    rng = np.random.default_rng(11)
+    sizes = [((64, 48), (64, 48)), ((64, 48), (64, 48)), ((90, 40), (100, 30)), ((20, 20), (20, 20)),
+             ((64, 48), (100, 30)), ((40, 40), (64, 48)), ((64, 48), (64, 48)), ((300, 200), (320, 240)),
+             ((64, 48), (64, 48))]
+    for (sw, sh), (dw, dh) in sizes:
+        depth = smooth_depth(rng, sw, sh)
+        rgba = rng.random((sh, sw, 4)).astype(F32)
+        run_warp(rp, ctx, rgba, depth, cam((0.2, 0.1, 3.0)), MOVES["translate"](), dw, dh, f"sequence {sw}x{sh}->{dw}x{dh}")
+
+
 def test_warp_degenerate_shapes(rp, ctx):
     rng = np.random.default_rng(7)
     for (sw, sh), (dw, dh) in (((1, 1), (1, 1)), ((1, 1), (5, 3)), ((4096, 1), (1, 4096)), ((1, 777), (300, 2)),
