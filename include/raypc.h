@@ -113,9 +113,13 @@ int raypc_version(void);
  *   stream     work is enqueued here; the call synchronises it before
  *              returning, so inputs may be freed or reused afterwards.
  *   volume_id  receives a handle (> 0).
- * Builds, per level: the encoded brick-ordered field data and the per-brick
- * (min, max) tables of the stored values over each brick's 9^3 window.  The
- * brush starts with no variable restricted.
+ * Builds, per level: the encoded brick-ordered field data, the per-brick
+ * (min, max) tables of the stored values over each brick's 9^3 window and
+ * its eight 4^3 sub-bricks' tables, and (unless compact) the neighbourhood
+ * records.  It also keeps, on the host, the values and level-0 sub-brick
+ * (min, max) of 2 048 random shell cells (a fixed SplitMix64 stream), from
+ * which each brush's field test order is chosen.  The brush starts with no
+ * variable restricted.
  * Errors: RAYPC_ERR_INVALID (argument out of range, NULL pointer, or a
  * non-finite input value), RAYPC_ERR_NOMEM, RAYPC_ERR_DEVICE.
  */
@@ -138,7 +142,12 @@ int raypc_volume_info(const raypc_ctx *ctx, int volume_id, int *n_fields, int *n
  *   [lo[f], hi[f]]; inactive variables are not tested.  lo > hi selects
  *   nothing; +-INFINITY bounds are allowed; NaN bounds are rejected.
  * Copies the arrays; touches no device memory (the affected skip lists are
- * recomputed by the next render).  Errors: RAYPC_ERR_INVALID.
+ * recomputed by the next render).  Renders test the restricted variables in
+ * an order chosen per brush: greedily, the variable that the fewest sampled
+ * shell cells still passing the earlier tests pass (cells in sub-bricks the
+ * skip rule drops do not count); a sample that fails one test fetches no
+ * further variable, and any order gives the same image.
+ * Errors: RAYPC_ERR_INVALID.
  */
 int raypc_set_brush(raypc_ctx *ctx, int volume_id, int n_fields, const uint8_t *active, const float *lo,
                     const float *hi);
