@@ -418,9 +418,8 @@ def main():
                          "prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the renderer shards by "
-              "request across GPUs with no communication, so per-GPU numbers are the 1-GPU numbers.",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the renderer shards by request across "
+              "GPUs with no communication, so per-GPU numbers are the 1-GPU numbers.", file=sys.stderr)
         sys.exit(2)
 
     import torch
