@@ -148,10 +148,12 @@ constexpr bool records_of(int K) { return K >= kKindF32Rec; }
 constexpr int record_type_of(int K) { return K == kKindF16Rec ? kF16 : kF32; }
 
 // Ray parameter where u(t) = uo + du t leaves [lo, hi] along one axis (forward only); inv_du = 1/du.
-// Rounding of the reciprocal is covered by the shrink margin of skipped bricks.
-__device__ __forceinline__ float axis_exit(float uo, float du, float inv_du, float lo, float hi) {
-    const float t = ((du > 0.0f ? hi : lo) - uo) * inv_du;
-    return du != 0.0f ? t : INFINITY;
+// The later of the two face crossings: that of hi for du > 0, that of lo for du < 0 (the same rounded
+// value as taking that face alone); for du = 0 (inv_du infinite) +inf when lo < uo < hi, else an earlier
+// and therefore conservative exit.  Written without a per-ray select, so no per-lane condition stays
+// live across the march.  Rounding of the reciprocal is covered by the shrink margin of skipped bricks.
+__device__ __forceinline__ float axis_exit(float uo, float inv_du, float lo, float hi) {
+    return fmaxf((lo - uo) * inv_du, (hi - uo) * inv_du);
 }
 
 // Stable ray/sphere hit for |d| = 1.  Returns false when the ray misses or touches.
@@ -374,9 +376,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                 const float hy = cy + e >= n ? INFINITY : static_cast<float>(cy + e) - kSkipShrink;
                 const float lz = cz == 0 ? -INFINITY : static_cast<float>(cz) + kSkipShrink;
                 const float hz = cz + e >= n ? INFINITY : static_cast<float>(cz + e) - kSkipShrink;
-                const float t_exit = fminf(axis_exit(uox, dux, inv_dux, lx, hx),
-                                           fminf(axis_exit(uoy, duy, inv_duy, ly, hy),
-                                                 axis_exit(uoz, duz, inv_duz, lz, hz)));
+                const float t_exit = fminf(axis_exit(uox, inv_dux, lx, hx),
+                                           fminf(axis_exit(uoy, inv_duy, ly, hy), axis_exit(uoz, inv_duz, lz, hz)));
                 float jc = (t_exit - g) * inv_ds - 0.5f - kSkipMargin;
                 jc = fminf(fmaxf(jc, 0.0f), static_cast<float>(ns));
                 jn = max(j + 1, static_cast<int>(ceilf(jc)));
@@ -421,19 +422,23 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                 }
                 constexpr int kUnroll = NB >= 0 ? NB : kMaxFields;
                 const int nbr = NB >= 0 ? NB : A.n_brushed;
+                // The slot comparisons below are made afresh in every step: hoisted out of the loop,
+                // each would hold a 64-bit lane mask for the whole march.
+                int tfs = A.tf_slot;
+                asm volatile("" : "+s"(tfs));
 #pragma unroll
                 for (int k = 0; k < kUnroll; ++k) {
                     if (pass && (NB >= 0 || k < nbr)) {
                         const float v = field_value(k);
                         pass = (v >= A.lo[k]) && (v <= A.hi[k]);
-                        if (k == A.tf_slot) tv = v;
+                        if (k == tfs) tv = v;
                     }
                 }
                 if (pass) {
                     if constexpr (NB >= 0 && NB < kMaxFields) {
-                        if (A.tf_slot == NB) tv = field_value(NB);
+                        if (tfs == NB) tv = field_value(NB);
                     } else if constexpr (NB < 0) {
-                        if (A.tf_slot == nbr && nbr < kMaxFields)
+                        if (tfs == nbr && nbr < kMaxFields)
                             tv = field_value(nbr);
                     }
                 }
@@ -527,7 +532,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
             cnt_nom += static_cast<uint32_t>(min(next, ns) - j0);
             j0 = next;
             if (j0 >= ns) {
-                if (seg == 0 && nseg == 2) {
+                if (seg + 1 < nseg) {
                     seg = 1;
                     sa = seg_a[1];
                     sb = seg_b[1];
