@@ -466,7 +466,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
         bool stopped = false;
         if (__ballot(contributes) != 0ull) {  // else nothing to composite anywhere in the wave
             // ---- merge the quad's four samples in sample order.  Every lane replays the same
-            // sequential updates (T <- T k, C <- fma(w, rgb, C)) on broadcast values, so the ray
+            // sequential updates (T <- T k, then C <- C + w rgb) on broadcast values, so the ray
             // state is identical in the four lanes and independent of how samples were grouped
             // (a skipped or discarded sample has k = 1 and w = 0, both exact).
             const float k0 = quad_bcast<0>(keep), k1 = quad_bcast<1>(keep);
@@ -480,35 +480,30 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
             const int stop_bits = static_cast<int>((stop_mask >> quad_base) & 0xFull);
             const int first_stop = stop_bits ? __ffs(stop_bits) - 1 : kQuad - 1;  // last sample that counts
             {
-                const float w0 = quad_bcast<0>(w), w1 = quad_bcast<1>(w), w2 = quad_bcast<2>(w), w3 = quad_bcast<3>(w);
-                const float r0 = quad_bcast<0>(cr), r1 = quad_bcast<1>(cr), r2 = quad_bcast<2>(cr), r3 = quad_bcast<3>(cr);
-                const float g0 = quad_bcast<0>(cg), g1 = quad_bcast<1>(cg), g2 = quad_bcast<2>(cg), g3 = quad_bcast<3>(cg);
-                const float b0 = quad_bcast<0>(cb), b1 = quad_bcast<1>(cb), b2 = quad_bcast<2>(cb), b3 = quad_bcast<3>(cb);
-                C0 = fmaf(w0, r0, C0);
-                C1 = fmaf(w0, g0, C1);
-                C2 = fmaf(w0, b0, C2);
-                if (first_stop >= 1) {
-                    C0 = fmaf(w1, r1, C0);
-                    C1 = fmaf(w1, g1, C1);
-                    C2 = fmaf(w1, b1, C2);
-                }
-                if (first_stop >= 2) {
-                    C0 = fmaf(w2, r2, C0);
-                    C1 = fmaf(w2, g2, C1);
-                    C2 = fmaf(w2, b2, C2);
-                }
-                if (first_stop >= 3) {
-                    C0 = fmaf(w3, r3, C0);
-                    C1 = fmaf(w3, g3, C1);
-                    C2 = fmaf(w3, b3, C2);
-                }
+                // each lane forms its own sample's contribution w rgb (zero past the first stop:
+                // those samples are not composited), and the four are added to the ray's sums in
+                // sample order, each addition taking its operand from the lane that holds it
+                const float wq = sub <= first_stop ? w : 0.0f;
+                const float pr = wq * cr, pg = wq * cg, pb = wq * cb;
+                C0 = C0 + quad_bcast<0>(pr);
+                C1 = C1 + quad_bcast<0>(pg);
+                C2 = C2 + quad_bcast<0>(pb);
+                C0 = C0 + quad_bcast<1>(pr);
+                C1 = C1 + quad_bcast<1>(pg);
+                C2 = C2 + quad_bcast<1>(pb);
+                C0 = C0 + quad_bcast<2>(pr);
+                C1 = C1 + quad_bcast<2>(pg);
+                C2 = C2 + quad_bcast<2>(pb);
+                C0 = C0 + quad_bcast<3>(pr);
+                C1 = C1 + quad_bcast<3>(pg);
+                C2 = C2 + quad_bcast<3>(pb);
                 if constexpr (DEPTH) {
-                    // samples that were not composited have w = 0 and a finite tm: no change
-                    D = fmaf(w0, quad_bcast<0>(tm), D);
-                    const float m1 = quad_bcast<1>(tm), m2 = quad_bcast<2>(tm), m3 = quad_bcast<3>(tm);
-                    if (first_stop >= 1) D = fmaf(w1, m1, D);
-                    if (first_stop >= 2) D = fmaf(w2, m2, D);
-                    if (first_stop >= 3) D = fmaf(w3, m3, D);
+                    // samples that were not composited add w tm = 0
+                    const float pd = wq * tm;
+                    D = D + quad_bcast<0>(pd);
+                    D = D + quad_bcast<1>(pd);
+                    D = D + quad_bcast<2>(pd);
+                    D = D + quad_bcast<3>(pd);
                 }
             }
             if constexpr (COUNTS) {
@@ -516,13 +511,12 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                 const int comp_bits = static_cast<int>((comp_mask >> quad_base) & 0xFull);
                 cnt_comp += __popc(comp_bits & ((2 << first_stop) - 1));
             }
-            if (stop_bits) {
-                T = first_stop == 0 ? t1 : (first_stop == 1 ? t2 : (first_stop == 2 ? t3 : t4));
-                cnt_nom += static_cast<uint32_t>(first_stop + 1);
-                stopped = true;
-            } else {
-                T = t4;
-            }
+            // T after the last sample that counts: t4 without a stop (selected on the stop bits, not
+            // on first_stop, which would become a branch and part the additions above from their
+            // lane moves)
+            T = (stop_bits & 1) ? t1 : ((stop_bits & 2) ? t2 : ((stop_bits & 4) ? t3 : t4));
+            stopped = stop_bits != 0;
+            cnt_nom += stopped ? static_cast<uint32_t>(first_stop + 1) : 0u;
         }
         if (stopped) {
             alive = false;
