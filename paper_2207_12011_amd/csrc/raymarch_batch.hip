@@ -15,7 +15,7 @@ namespace {
 // scheduler lists them) are dealt round-robin over the 8 XCDs; the grid is padded to whole rounds of
 // 8 chunks.
 template <int K, int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves(K), 8))) void raymarch_batch_kernel(
+__global__ __launch_bounds__(256) void raymarch_batch_kernel(
     const RenderArgs* __restrict__ descs, BatchRanges R) {
     __shared__ float4 s_tf[256];
     const int xcd = blockIdx.x & 7, p = blockIdx.x >> 3;

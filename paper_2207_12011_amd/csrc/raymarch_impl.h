@@ -577,13 +577,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     }
 }
 
-// Waves per SIMD the kernel is compiled for: binary16 records run best at 8 (more waves in flight
-// hide the dependent loads), the other kinds at the compiler's own choice (8 forced costs them
-// more in cache thrash than it gains).
-constexpr int min_waves(int K) { return K == kKindF16Rec ? 8 : 1; }
-
 template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves(K), 8))) void raymarch_kernel(RenderArgs A) {
+__global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     int bx, by;
     interleaved_tile(blockIdx.x, A.blocks_x, A.super_log2, bx, by);
     if (by * kBlockTile >= A.height || bx * kBlockTile >= A.width) return;  // padding block
