@@ -147,13 +147,17 @@ constexpr bool records_of(int K) { return K >= kKindF32Rec; }
 // Value type held by a kind's records: binary16 quads, or float32 pairs (also for decoded 8-bit codes).
 constexpr int record_type_of(int K) { return K == kKindF16Rec ? kF16 : kF32; }
 
-// Ray parameter where u(t) = uo + du t leaves [lo, hi] along one axis (forward only); inv_du = 1/du.
-// The later of the two face crossings: that of hi for du > 0, that of lo for du < 0 (the same rounded
-// value as taking that face alone); for du = 0 (inv_du infinite) +inf when lo < uo < hi, else an earlier
-// and therefore conservative exit.  Written without a per-ray select, so no per-lane condition stays
-// live across the march.  Rounding of the reciprocal is covered by the shrink margin of skipped bricks.
-__device__ __forceinline__ float axis_exit(float uo, float inv_du, float lo, float hi) {
-    return fmaxf((lo - uo) * inv_du, (hi - uo) * inv_du);
+// Ray parameter where u(t) = uo + du t leaves the box [c, c + e) along one axis (voxel units, forward
+// only): the crossing of the face the ray moves towards, moved kSkipShrink into the box against
+// rounding, or +inf when that face is a face of the grid (clamping maps every position beyond it into
+// the boundary box).  Per ray: up = -1 when the component's sign bit is clear (moving up; +0 too), else
+// 0; uos = uo + kSkipShrink when moving up, uo - kSkipShrink when moving down; inv_du = 1 / du.  For
+// du = 0 the result is +inf or a conservative (earlier) exit.  Written without a per-ray select, so
+// no per-lane condition stays live across the march.
+__device__ __forceinline__ float box_exit(int c, int e, int up, float uos, float inv_du, int n) {
+    const int face = c + (e & up);
+    const float t = (static_cast<float>(face) - uos) * inv_du;
+    return static_cast<uint32_t>(face - 1) >= static_cast<uint32_t>(n - 1) ? INFINITY : t;
 }
 
 // Stable ray/sphere hit for |d| = 1.  Returns false when the ray misses or touches.
@@ -310,6 +314,12 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     const float uox = fmaf(ox, hn, hn - 0.5f), uoy = fmaf(oy, hn, hn - 0.5f), uoz = fmaf(oz, hn, hn - 0.5f);
     const float dux = dx * hn, duy = dy * hn, duz = dz * hn;
     const float inv_dux = 1.0f / dux, inv_duy = 1.0f / duy, inv_duz = 1.0f / duz;
+    // skipped-box exits (box_exit): direction of each axis as a bit mask, origin moved by the shrink
+    const int upx = static_cast<int>(__float_as_uint(dux) >> 31) - 1;
+    const int upy = static_cast<int>(__float_as_uint(duy) >> 31) - 1;
+    const int upz = static_cast<int>(__float_as_uint(duz) >> 31) - 1;
+    const float uosx = uox - copysignf(kSkipShrink, -dux), uosy = uoy - copysignf(kSkipShrink, -duy);
+    const float uosz = uoz - copysignf(kSkipShrink, -duz);
     const float ds = A.ds, inv_ds = A.inv_ds;
     const float r_full = ds * A.inv_ref;
 
@@ -366,18 +376,10 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                 // beyond the box (shrunk by a margin against rounding; open at the grid's faces,
                 // where clamping maps every outside position to the boundary box)
                 skipped = true;
-                const bool whole = flags == 0xFFu;
-                const int e = whole ? 8 : 4;
-                const int cx = whole ? bxi * 8 : x0 & ~3, cy = whole ? byi * 8 : y0 & ~3;
-                const int cz = whole ? bzi * 8 : z0 & ~3;
-                const float lx = cx == 0 ? -INFINITY : static_cast<float>(cx) + kSkipShrink;
-                const float hx = cx + e >= n ? INFINITY : static_cast<float>(cx + e) - kSkipShrink;
-                const float ly = cy == 0 ? -INFINITY : static_cast<float>(cy) + kSkipShrink;
-                const float hy = cy + e >= n ? INFINITY : static_cast<float>(cy + e) - kSkipShrink;
-                const float lz = cz == 0 ? -INFINITY : static_cast<float>(cz) + kSkipShrink;
-                const float hz = cz + e >= n ? INFINITY : static_cast<float>(cz + e) - kSkipShrink;
-                const float t_exit = fminf(axis_exit(uox, inv_dux, lx, hx),
-                                           fminf(axis_exit(uoy, inv_duy, ly, hy), axis_exit(uoz, inv_duz, lz, hz)));
+                const int m = flags == 0xFFu ? -8 : -4;  // box of 8^3 or 4^3 voxels: corner x0 & m, edge -m
+                const float t_exit = fminf(box_exit(x0 & m, -m, upx, uosx, inv_dux, n),
+                                           fminf(box_exit(y0 & m, -m, upy, uosy, inv_duy, n),
+                                                 box_exit(z0 & m, -m, upz, uosz, inv_duz, n)));
                 float jc = (t_exit - g) * inv_ds - 0.5f - kSkipMargin;
                 jc = fminf(fmaxf(jc, 0.0f), static_cast<float>(ns));
                 jn = max(j + 1, static_cast<int>(ceilf(jc)));
