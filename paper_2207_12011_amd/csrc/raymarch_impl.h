@@ -6,6 +6,10 @@
 
 #include "internal.h"
 
+// 24-bit unsigned multiply (the LLVM intrinsic, full rate; HIP's __umul24 may be selected as a
+// quarter-rate 64-bit multiply-add).
+__device__ uint32_t raypc_mul_u24(uint32_t a, uint32_t b) __asm("llvm.amdgcn.mul.u24.i32");
+
 namespace raypc {
 namespace {
 
@@ -116,25 +120,26 @@ __device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)
 
 // Trilinear value from neighbourhood records (8 bytes per voxel): binary16 reads the 2x2 (x, y) records
 // of the base voxel's row at z0 and z1, float32 the x pairs at (y0, z0), (y1, z0), (y0, z1), (y1, z1).
-// ax is the x part of the base voxel's address, ay0 / ay1 / az0 / az1 the y and z parts (see axis_x/y/z).
-// The arithmetic is that of fetch(), so both layouts give identical values.
+// r00 / r10 / r01 / r11 are the record numbers of the base voxel's row at (y0, z0), (y1, z0), (y0, z1),
+// (y1, z1) (the layout of axis_x/y/z).  The arithmetic is that of fetch(), so both layouts give
+// identical values.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <int S>
-__device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32_t ax, uint32_t ay0, uint32_t ay1,
-                                           uint32_t az0, uint32_t az1, const Tri& t) {
+__device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32_t r00, uint32_t r10, uint32_t r01,
+                                           uint32_t r11, const Tri& t) {
     const char* b = static_cast<const char*>(base);
     if constexpr (S == kF16) {
-        const u32x2 p = global_ptr<u32x2>(b + static_cast<size_t>(ax + ay0 + az0) * 8u)[0];
-        const u32x2 q = global_ptr<u32x2>(b + static_cast<size_t>(ax + ay0 + az1) * 8u)[0];
+        const u32x2 p = global_ptr<u32x2>(b + static_cast<size_t>(r00) * 8u)[0];
+        const u32x2 q = global_ptr<u32x2>(b + static_cast<size_t>(r01) * 8u)[0];
         auto lo = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u & 0xFFFFu))); };
         auto hi = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u >> 16))); };
         return blend(t, lo(p.x), hi(p.x), lo(p.y), hi(p.y), lo(q.x), hi(q.x), lo(q.y), hi(q.y));
     } else {
-        const f32x2 p0 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay0 + az0) * 8u)[0];
-        const f32x2 p1 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay1 + az0) * 8u)[0];
-        const f32x2 p2 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay0 + az1) * 8u)[0];
-        const f32x2 p3 = global_ptr<f32x2>(b + static_cast<size_t>(ax + ay1 + az1) * 8u)[0];
+        const f32x2 p0 = global_ptr<f32x2>(b + static_cast<size_t>(r00) * 8u)[0];
+        const f32x2 p1 = global_ptr<f32x2>(b + static_cast<size_t>(r10) * 8u)[0];
+        const f32x2 p2 = global_ptr<f32x2>(b + static_cast<size_t>(r01) * 8u)[0];
+        const f32x2 p3 = global_ptr<f32x2>(b + static_cast<size_t>(r11) * 8u)[0];
         return blend(t, p0.x, p0.y, p1.x, p1.y, p2.x, p2.y, p3.x, p3.y);
     }
 }
@@ -310,6 +315,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
 
     const int n = A.n, nb = A.nb;
     const uint32_t nbu = static_cast<uint32_t>(nb);
+    // record-number steps to the next voxel in y and z from the last voxel of a brick (see below)
+    const uint32_t y_brick_step = nbu * 512u - 140u, z_brick_step = nbu * nbu * 512u - 304u;
     const float hn = A.half_n;
     const float uox = fmaf(ox, hn, hn - 0.5f), uoy = fmaf(oy, hn, hn - 0.5f), uoz = fmaf(oz, hn, hn - 0.5f);
     const float dux = dx * hn, duy = dy * hn, duz = dz * hn;
@@ -367,10 +374,10 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
             const int z0 = min(max(iz, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
             const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
             // brick rows and slabs below 2^7, bricks per row below 2^8: 24-bit products are exact
-            const uint32_t brick = __umul24(__umul24(static_cast<uint32_t>(bzi), nbu) + byi, nbu) + bxi;
+            const uint32_t brick = raypc_mul_u24(raypc_mul_u24(static_cast<uint32_t>(bzi), nbu) + byi, nbu) + bxi;
             const uint32_t flags = A.skip != nullptr ? global_ptr<uint8_t>(A.skip)[brick] : 0u;
-            const uint32_t sub = ((x0 >> 2) & 1) | (((y0 >> 2) & 1) << 1) | (((z0 >> 2) & 1) << 2);
-            if ((flags >> sub) & 1u) {
+            const uint32_t sbi = ((x0 >> 2) & 1) | (((y0 >> 2) & 1) << 1) | (((z0 >> 2) & 1) << 2);  // sub-brick
+            if ((flags >> sbi) & 1u) {
                 // every sample whose base corner lies in this sub-brick (in this brick, when all
                 // eight are flagged) is discarded or transparent: find the first sample that may lie
                 // beyond the box (shrunk by a margin against rounding; open at the grid's faces,
@@ -396,11 +403,22 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                 const float wz = iz < 0 ? 0.0f : uz - flz;
                 const Tri tw = tri_weights(wx, wy, wz);
                 uint32_t o[8];
-                uint32_t ax = 0, ay0 = 0, ay1 = 0, az0 = 0, az1 = 0;
+                uint32_t r00 = 0, r10 = 0, r01 = 0, r11 = 0;
                 if constexpr (R) {
-                    ax = axis_x(x0);
-                    ay0 = axis_y(y0, nb), ay1 = axis_y(y1, nb);
-                    az0 = axis_z(z0, nb), az1 = axis_z(z1, nb);
+                    // record number of the base voxel (the layout of axis_x/y/z): its brick, the 4^3
+                    // sub-brick in bits 6-8 and its place in that in bits 0-5.  The voxel one up in
+                    // z (y) follows by a step that depends on where the base voxel lies in its
+                    // sub-brick and brick: +16 (+4) inside a sub-brick, to the next sub-brick, or to
+                    // the next brick; none where the upper corner clamps onto the base voxel.
+                    r00 = (brick << 9) | (sbi << 6) | static_cast<uint32_t>((x0 & 3) | ((y0 & 3) << 2) | ((z0 & 3) << 4));
+                    const uint32_t dz = (z0 & 3) != 3 ? 16u : ((z0 & 4) == 0 ? 208u : z_brick_step);
+                    r01 = r00 + (static_cast<uint32_t>(iz) < static_cast<uint32_t>(n - 1) ? dz : 0u);
+                    if constexpr (RT == kF32) {
+                        const uint32_t dy = (y0 & 3) != 3 ? 4u : ((y0 & 4) == 0 ? 116u : y_brick_step);
+                        const uint32_t dyv = static_cast<uint32_t>(iy) < static_cast<uint32_t>(n - 1) ? dy : 0u;
+                        r10 = r00 + dyv;
+                        r11 = r01 + dyv;
+                    }
                 } else {
                     constexpr int L = kLogBytes<S>;
                     const uint32_t X0 = axis_x(x0) << L, X1 = axis_x(x1) << L;
@@ -411,7 +429,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                     o[4] = zy10 + X0, o[5] = zy10 + X1, o[6] = zy11 + X0, o[7] = zy11 + X1;
                 }
                 auto field_value = [&](int k) -> float {
-                    if constexpr (R) return fetch_rec<RT>(A.rec[k], ax, ay0, ay1, az0, az1, tw);
+                    if constexpr (R) return fetch_rec<RT>(A.rec[k], r00, r10, r01, r11, tw);
                     else return fetch<S>(source<S>(A, k), o, tw);
                 };
                 // coordinate axes first: a sample outside them fetches no field (the kernels with a
