@@ -384,6 +384,8 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
         const uint64_t fb = static_cast<uint64_t>(L.n) * L.n * L.n * storage_bytes(v->storage);
         a.field_bytes = fb > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(fb);
         a.par_bytes = static_cast<uint32_t>(L.n_bricks() * sizeof(float2));
+        const uint64_t rb = static_cast<uint64_t>(L.n) * L.n * L.n * 8u;
+        a.rec_bytes = rb > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(rb);
     }
     a.half_n = 0.5f * static_cast<float>(L.n);
     a.tf = tf.dev;

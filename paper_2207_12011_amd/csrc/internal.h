@@ -152,6 +152,7 @@ struct RenderArgs {
     int n, nb;
     uint32_t field_bytes;         // bytes of one field of this level (buffer range; f16 and u8 only)
     uint32_t par_bytes;           // bytes of one field's per-brick (scale, offset) table (u8)
+    uint32_t rec_bytes;           // bytes of one field's records (buffer range; fields below 4 GiB only)
     float half_n;                 // N / 2: u = (p + 1) N/2 - 1/2
     const uint8_t* skip;          // per brick, bit sx + 2 sy + 4 sz: 4^3 sub-brick skipped (nullptr: no skipping)
     const float4* tf;             // 256 straight-RGBA entries

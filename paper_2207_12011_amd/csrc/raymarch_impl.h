@@ -122,25 +122,36 @@ __device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)
 // of the base voxel's row at z0 and z1, float32 the x pairs at (y0, z0), (y1, z0), (y0, z1), (y1, z1).
 // r00 / r10 / r01 / r11 are the record numbers of the base voxel's row at (y0, z0), (y1, z0), (y0, z1),
 // (y1, z1) (the layout of axis_x/y/z).  The arithmetic is that of fetch(), so both layouts give
-// identical values.
+// identical values.  WIDE: global loads at 64-bit byte offsets (fields of 4 GiB and more); else buffer
+// loads at 32-bit byte offsets, whose base the load adds itself (`bytes`: the field's size).
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-template <int S>
-__device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32_t r00, uint32_t r10, uint32_t r01,
-                                           uint32_t r11, const Tri& t) {
-    const char* b = static_cast<const char*>(base);
+template <bool WIDE>
+__device__ __forceinline__ u32x2 load_record(const void* base, uint32_t bytes, uint32_t r) {
+    if constexpr (WIDE) {
+        return global_ptr<u32x2>(static_cast<const char*>(base) + static_cast<size_t>(r) * 8u)[0];
+    } else {
+        const __amdgpu_buffer_rsrc_t rsrc =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes), kRawBufferFlags);
+        return __builtin_amdgcn_raw_buffer_load_b64(rsrc, static_cast<int>(r << 3), 0, 0);
+    }
+}
+template <int S, bool WIDE>
+__device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32_t bytes, uint32_t r00, uint32_t r10,
+                                           uint32_t r01, uint32_t r11, const Tri& t) {
     if constexpr (S == kF16) {
-        const u32x2 p = global_ptr<u32x2>(b + static_cast<size_t>(r00) * 8u)[0];
-        const u32x2 q = global_ptr<u32x2>(b + static_cast<size_t>(r01) * 8u)[0];
+        const u32x2 p = load_record<WIDE>(base, bytes, r00);
+        const u32x2 q = load_record<WIDE>(base, bytes, r01);
         auto lo = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u & 0xFFFFu))); };
         auto hi = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u >> 16))); };
         return blend(t, lo(p.x), hi(p.x), lo(p.y), hi(p.y), lo(q.x), hi(q.x), lo(q.y), hi(q.y));
     } else {
-        const f32x2 p0 = global_ptr<f32x2>(b + static_cast<size_t>(r00) * 8u)[0];
-        const f32x2 p1 = global_ptr<f32x2>(b + static_cast<size_t>(r10) * 8u)[0];
-        const f32x2 p2 = global_ptr<f32x2>(b + static_cast<size_t>(r01) * 8u)[0];
-        const f32x2 p3 = global_ptr<f32x2>(b + static_cast<size_t>(r11) * 8u)[0];
-        return blend(t, p0.x, p0.y, p1.x, p1.y, p2.x, p2.y, p3.x, p3.y);
+        const u32x2 p0 = load_record<WIDE>(base, bytes, r00);
+        const u32x2 p1 = load_record<WIDE>(base, bytes, r10);
+        const u32x2 p2 = load_record<WIDE>(base, bytes, r01);
+        const u32x2 p3 = load_record<WIDE>(base, bytes, r11);
+        return blend(t, __uint_as_float(p0.x), __uint_as_float(p0.y), __uint_as_float(p1.x), __uint_as_float(p1.y),
+                     __uint_as_float(p2.x), __uint_as_float(p2.y), __uint_as_float(p3.x), __uint_as_float(p3.y));
     }
 }
 
@@ -258,8 +269,9 @@ __device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) 
 // JIT: a jittered progressive pass (the sample grid of every segment starts s ds before it, so the
 // first and last samples of a segment are partial).  DEPTH: also write the opacity-weighted depth, the
 // mean distance of the composited samples, each weighted by its share w of the pixel's opacity (the
-// depth that image warping reprojects with; +inf where nothing was composited).
-template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false>
+// depth that image warping reprojects with; +inf where nothing was composited).  WIDE: 64-bit record
+// offsets (needed for record fields of 4 GiB and more).
+template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true>
 __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, const float4* s_tf) {
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
@@ -317,6 +329,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     const uint32_t nbu = static_cast<uint32_t>(nb);
     // record-number steps to the next voxel in y and z from the last voxel of a brick (see below)
     const uint32_t y_brick_step = nbu * 512u - 140u, z_brick_step = nbu * nbu * 512u - 304u;
+    const float top = static_cast<float>(n - 1);  // largest voxel index
     const float hn = A.half_n;
     const float uox = fmaf(ox, hn, hn - 0.5f), uoy = fmaf(oy, hn, hn - 0.5f), uoz = fmaf(oz, hn, hn - 0.5f);
     const float dux = dx * hn, duy = dy * hn, duz = dz * hn;
@@ -369,9 +382,11 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
             const float ux = fmaf(dux, tm, uox), uy = fmaf(duy, tm, uoy), uz = fmaf(duz, tm, uoz);
             const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
             const int ix = static_cast<int>(flx), iy = static_cast<int>(fly), iz = static_cast<int>(flz);
-            const int x0 = min(max(ix, 0), n - 1), x1 = min(max(ix + 1, 0), n - 1);
-            const int y0 = min(max(iy, 0), n - 1), y1 = min(max(iy + 1, 0), n - 1);
-            const int z0 = min(max(iz, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
+            // corner indices clamped onto the grid (the clamp taken on the integer-valued floors)
+            const int x0 = static_cast<int>(__builtin_amdgcn_fmed3f(flx, 0.0f, top));
+            const int y0 = static_cast<int>(__builtin_amdgcn_fmed3f(fly, 0.0f, top));
+            const int z0 = static_cast<int>(__builtin_amdgcn_fmed3f(flz, 0.0f, top));
+            const int x1 = min(max(ix + 1, 0), n - 1), y1 = min(max(iy + 1, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
             const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
             // brick rows and slabs below 2^7, bricks per row below 2^8: 24-bit products are exact
             const uint32_t brick = raypc_mul_u24(raypc_mul_u24(static_cast<uint32_t>(bzi), nbu) + byi, nbu) + bxi;
@@ -399,8 +414,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                 }
                 // below the grid both corners of an axis clamp to index 0: a zero weight on the upper
                 // corner gives that value exactly, and lets a record of the clamped base voxel serve
-                const float wx = ix < 0 ? 0.0f : ux - flx, wy = iy < 0 ? 0.0f : uy - fly;
-                const float wz = iz < 0 ? 0.0f : uz - flz;
+                const float wx = flx < 0.0f ? 0.0f : ux - flx, wy = fly < 0.0f ? 0.0f : uy - fly;
+                const float wz = flz < 0.0f ? 0.0f : uz - flz;
                 const Tri tw = tri_weights(wx, wy, wz);
                 uint32_t o[8];
                 uint32_t r00 = 0, r10 = 0, r01 = 0, r11 = 0;
@@ -412,10 +427,10 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                     // the next brick; none where the upper corner clamps onto the base voxel.
                     r00 = (brick << 9) | (sbi << 6) | static_cast<uint32_t>((x0 & 3) | ((y0 & 3) << 2) | ((z0 & 3) << 4));
                     const uint32_t dz = (z0 & 3) != 3 ? 16u : ((z0 & 4) == 0 ? 208u : z_brick_step);
-                    r01 = r00 + (static_cast<uint32_t>(iz) < static_cast<uint32_t>(n - 1) ? dz : 0u);
+                    r01 = r00 + (flz >= 0.0f && flz < top ? dz : 0u);
                     if constexpr (RT == kF32) {
                         const uint32_t dy = (y0 & 3) != 3 ? 4u : ((y0 & 4) == 0 ? 116u : y_brick_step);
-                        const uint32_t dyv = static_cast<uint32_t>(iy) < static_cast<uint32_t>(n - 1) ? dy : 0u;
+                        const uint32_t dyv = fly >= 0.0f && fly < top ? dy : 0u;
                         r10 = r00 + dyv;
                         r11 = r01 + dyv;
                     }
@@ -429,7 +444,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
                     o[4] = zy10 + X0, o[5] = zy10 + X1, o[6] = zy11 + X0, o[7] = zy11 + X1;
                 }
                 auto field_value = [&](int k) -> float {
-                    if constexpr (R) return fetch_rec<RT>(A.rec[k], r00, r10, r01, r11, tw);
+                    if constexpr (R) return fetch_rec<RT, WIDE>(A.rec[k], A.rec_bytes, r00, r10, r01, r11, tw);
                     else return fetch<S>(source<S>(A, k), o, tw);
                 };
                 // coordinate axes first: a sample outside them fetches no field (the kernels with a
@@ -597,7 +612,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     }
 }
 
-template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false>
+template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true>
 __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
     int bx, by;
     interleaved_tile(blockIdx.x, A.blocks_x, A.super_log2, bx, by);
@@ -608,36 +623,52 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
         s_tf[threadIdx.x] = make_float4(e.x, e.y, e.z, e.w);
     }
     __syncthreads();
-    march_tile<K, NB, COUNTS, JIT, DEPTH>(A, bx, by, s_tf);
+    march_tile<K, NB, COUNTS, JIT, DEPTH, WIDE>(A, bx, by, s_tf);
 }
 
 // Single-image launch of the kernel with the request's field count as a template argument (the field
 // loop unrolled, no per-field guard); coordinate axes take the run-time count variant, which carries
 // their test.
-template <int K, bool COUNTS, bool JIT, bool DEPTH>
+template <int K, bool COUNTS, bool JIT, bool DEPTH, bool WIDE = true>
 hipError_t launch_fixed(const RenderArgs& a, hipStream_t s) {
     const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x, a.super_log2)), block(256);
     if (a.coord_mask) {
-        hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, COUNTS, JIT, DEPTH>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a);
         return hipGetLastError();
     }
     switch (a.n_brushed) {
-        case 0: hipLaunchKernelGGL((raymarch_kernel<K, 0, COUNTS, JIT, DEPTH>), grid, block, 0, s, a); break;
-        case 1: hipLaunchKernelGGL((raymarch_kernel<K, 1, COUNTS, JIT, DEPTH>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((raymarch_kernel<K, 2, COUNTS, JIT, DEPTH>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((raymarch_kernel<K, 3, COUNTS, JIT, DEPTH>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((raymarch_kernel<K, 4, COUNTS, JIT, DEPTH>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((raymarch_kernel<K, 5, COUNTS, JIT, DEPTH>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((raymarch_kernel<K, 6, COUNTS, JIT, DEPTH>), grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((raymarch_kernel<K, 7, COUNTS, JIT, DEPTH>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((raymarch_kernel<K, 8, COUNTS, JIT, DEPTH>), grid, block, 0, s, a); break;
+        case 0: hipLaunchKernelGGL((raymarch_kernel<K, 0, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((raymarch_kernel<K, 1, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((raymarch_kernel<K, 2, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((raymarch_kernel<K, 3, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((raymarch_kernel<K, 4, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((raymarch_kernel<K, 5, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((raymarch_kernel<K, 6, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((raymarch_kernel<K, 7, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((raymarch_kernel<K, 8, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a); break;
     }
     return hipGetLastError();
 }
 
-// The same for every kernel kind.
+// Record fields below 4 GiB (every level of grids up to 812^3) take 32-bit record offsets.
+inline bool narrow_records(const RenderArgs& a) {
+    return static_cast<uint64_t>(a.n) * a.n * a.n * 8u < 0x100000000ull;
+}
+
+// The same for every kernel kind; plain renders of record kinds with narrow records take the 32-bit
+// offset variant.
 template <bool COUNTS, bool JIT, bool DEPTH>
 hipError_t launch_fixed_kind(const RenderArgs& a, int kind, hipStream_t s) {
+    if constexpr (!COUNTS && !JIT && !DEPTH) {
+        if (narrow_records(a)) {
+            switch (kind) {
+                case kKindF32Rec: return launch_fixed<kKindF32Rec, false, false, false, false>(a, s);
+                case kKindF16Rec: return launch_fixed<kKindF16Rec, false, false, false, false>(a, s);
+                case kKindU8Rec: return launch_fixed<kKindU8Rec, false, false, false, false>(a, s);
+                default: break;
+            }
+        }
+    }
     switch (kind) {
         case kKindF32: return launch_fixed<kKindF32, COUNTS, JIT, DEPTH>(a, s);
         case kKindF16: return launch_fixed<kKindF16, COUNTS, JIT, DEPTH>(a, s);
