@@ -221,10 +221,17 @@ struct BatchRanges {
     int first[kMaxRanges];
     int slot[kMaxRanges];
 };
-// Requests of one batched launch share the kernel kind and the field-count class: the number of
-// brushed fields, or -1 (the run-time count variant) when coordinate axes are enabled.
+// Requests of one batched launch share the kernel kind, the field-count class (the number of brushed
+// fields, or -1, the run-time count variant, when coordinate axes are enabled) and the record offset
+// width (batch_wide: record kinds whose record fields reach 4 GiB take 64-bit offsets).
 int batch_nb_class(const RenderArgs& a);
-hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& ranges, int kind, int nb_class,
+bool batch_wide(const RenderArgs& a, int kind);
+hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& ranges, int kind, int nb_class, bool wide,
                                hipStream_t s);
+
+// Record fields below 4 GiB (every level of grids up to 812^3) can be read at 32-bit byte offsets.
+inline bool narrow_records(const RenderArgs& a) {
+    return static_cast<uint64_t>(a.n) * a.n * a.n * 8u < 0x100000000ull;
+}
 
 }  // namespace raypc

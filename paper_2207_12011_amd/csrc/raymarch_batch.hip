@@ -13,8 +13,8 @@ namespace {
 // kernel kind and field count) share a launch; each tile runs exactly the code path of a
 // single-request render.  Chunks of 16 consecutive items (one super-tile of a request, as the
 // scheduler lists them) are dealt round-robin over the 8 XCDs; the grid is padded to whole rounds of
-// 8 chunks.
-template <int K, int NB>
+// 8 chunks.  WIDE: 64-bit record offsets (record fields of 4 GiB and more).
+template <int K, int NB, bool WIDE>
 __global__ __launch_bounds__(256) void raymarch_batch_kernel(
     const RenderArgs* __restrict__ descs, BatchRanges R) {
     __shared__ float4 s_tf[256];
@@ -32,23 +32,23 @@ __global__ __launch_bounds__(256) void raymarch_batch_kernel(
     __syncthreads();
     int bx, by;
     tile_coords(tile, A.blocks_x, A.n_blocks / A.blocks_x, bx, by);
-    march_tile<K, NB, false>(A, bx, by, s_tf);
+    march_tile<K, NB, false, false, false, WIDE>(A, bx, by, s_tf);
 }
 
-template <int K>
+template <int K, bool WIDE>
 hipError_t launch_batch_nb(const RenderArgs* descs, const BatchRanges& R, int nb_class, dim3 grid, hipStream_t s) {
     const dim3 block(256);
     switch (nb_class) {
-        case kRuntimeNB: hipLaunchKernelGGL((raymarch_batch_kernel<K, kRuntimeNB>), grid, block, 0, s, descs, R); break;
-        case 0: hipLaunchKernelGGL((raymarch_batch_kernel<K, 0>), grid, block, 0, s, descs, R); break;
-        case 1: hipLaunchKernelGGL((raymarch_batch_kernel<K, 1>), grid, block, 0, s, descs, R); break;
-        case 2: hipLaunchKernelGGL((raymarch_batch_kernel<K, 2>), grid, block, 0, s, descs, R); break;
-        case 3: hipLaunchKernelGGL((raymarch_batch_kernel<K, 3>), grid, block, 0, s, descs, R); break;
-        case 4: hipLaunchKernelGGL((raymarch_batch_kernel<K, 4>), grid, block, 0, s, descs, R); break;
-        case 5: hipLaunchKernelGGL((raymarch_batch_kernel<K, 5>), grid, block, 0, s, descs, R); break;
-        case 6: hipLaunchKernelGGL((raymarch_batch_kernel<K, 6>), grid, block, 0, s, descs, R); break;
-        case 7: hipLaunchKernelGGL((raymarch_batch_kernel<K, 7>), grid, block, 0, s, descs, R); break;
-        default: hipLaunchKernelGGL((raymarch_batch_kernel<K, 8>), grid, block, 0, s, descs, R); break;
+        case kRuntimeNB: hipLaunchKernelGGL((raymarch_batch_kernel<K, kRuntimeNB, WIDE>), grid, block, 0, s, descs, R); break;
+        case 0: hipLaunchKernelGGL((raymarch_batch_kernel<K, 0, WIDE>), grid, block, 0, s, descs, R); break;
+        case 1: hipLaunchKernelGGL((raymarch_batch_kernel<K, 1, WIDE>), grid, block, 0, s, descs, R); break;
+        case 2: hipLaunchKernelGGL((raymarch_batch_kernel<K, 2, WIDE>), grid, block, 0, s, descs, R); break;
+        case 3: hipLaunchKernelGGL((raymarch_batch_kernel<K, 3, WIDE>), grid, block, 0, s, descs, R); break;
+        case 4: hipLaunchKernelGGL((raymarch_batch_kernel<K, 4, WIDE>), grid, block, 0, s, descs, R); break;
+        case 5: hipLaunchKernelGGL((raymarch_batch_kernel<K, 5, WIDE>), grid, block, 0, s, descs, R); break;
+        case 6: hipLaunchKernelGGL((raymarch_batch_kernel<K, 6, WIDE>), grid, block, 0, s, descs, R); break;
+        case 7: hipLaunchKernelGGL((raymarch_batch_kernel<K, 7, WIDE>), grid, block, 0, s, descs, R); break;
+        default: hipLaunchKernelGGL((raymarch_batch_kernel<K, 8, WIDE>), grid, block, 0, s, descs, R); break;
     }
     return hipGetLastError();
 }
@@ -57,17 +57,26 @@ hipError_t launch_batch_nb(const RenderArgs* descs, const BatchRanges& R, int nb
 
 int batch_nb_class(const RenderArgs& a) { return a.coord_mask ? kRuntimeNB : a.n_brushed; }
 
-hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& R, int kind, int nb_class, hipStream_t s) {
+bool batch_wide(const RenderArgs& a, int kind) { return records_of(kind) && !narrow_records(a); }
+
+hipError_t launch_render_batch(const RenderArgs* descs, const BatchRanges& R, int kind, int nb_class, bool wide,
+                               hipStream_t s) {
     if (R.n <= 0 || R.n > kMaxRanges || R.end[R.n - 1] <= 0) return hipSuccess;
     constexpr int kRound = 8 * kSuperTiles;
     const dim3 grid((R.end[R.n - 1] + kRound - 1) / kRound * kRound);
     switch (kind) {
-        case kKindF32: return launch_batch_nb<kKindF32>(descs, R, nb_class, grid, s);
-        case kKindF16: return launch_batch_nb<kKindF16>(descs, R, nb_class, grid, s);
-        case kKindU8: return launch_batch_nb<kKindU8>(descs, R, nb_class, grid, s);
-        case kKindF32Rec: return launch_batch_nb<kKindF32Rec>(descs, R, nb_class, grid, s);
-        case kKindF16Rec: return launch_batch_nb<kKindF16Rec>(descs, R, nb_class, grid, s);
-        default: return launch_batch_nb<kKindU8Rec>(descs, R, nb_class, grid, s);
+        case kKindF32: return launch_batch_nb<kKindF32, true>(descs, R, nb_class, grid, s);
+        case kKindF16: return launch_batch_nb<kKindF16, true>(descs, R, nb_class, grid, s);
+        case kKindU8: return launch_batch_nb<kKindU8, true>(descs, R, nb_class, grid, s);
+        case kKindF32Rec:
+            return wide ? launch_batch_nb<kKindF32Rec, true>(descs, R, nb_class, grid, s)
+                        : launch_batch_nb<kKindF32Rec, false>(descs, R, nb_class, grid, s);
+        case kKindF16Rec:
+            return wide ? launch_batch_nb<kKindF16Rec, true>(descs, R, nb_class, grid, s)
+                        : launch_batch_nb<kKindF16Rec, false>(descs, R, nb_class, grid, s);
+        default:
+            return wide ? launch_batch_nb<kKindU8Rec, true>(descs, R, nb_class, grid, s)
+                        : launch_batch_nb<kKindU8Rec, false>(descs, R, nb_class, grid, s);
     }
 }
 

@@ -650,21 +650,16 @@ hipError_t launch_fixed(const RenderArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Record fields below 4 GiB (every level of grids up to 812^3) take 32-bit record offsets.
-inline bool narrow_records(const RenderArgs& a) {
-    return static_cast<uint64_t>(a.n) * a.n * a.n * 8u < 0x100000000ull;
-}
-
-// The same for every kernel kind; plain renders of record kinds with narrow records take the 32-bit
-// offset variant.
+// The same for every kernel kind; record kinds with record fields below 4 GiB take the 32-bit offset
+// variant (except the counting variant, a debugging aid).
 template <bool COUNTS, bool JIT, bool DEPTH>
 hipError_t launch_fixed_kind(const RenderArgs& a, int kind, hipStream_t s) {
-    if constexpr (!COUNTS && !JIT && !DEPTH) {
+    if constexpr (!COUNTS) {
         if (narrow_records(a)) {
             switch (kind) {
-                case kKindF32Rec: return launch_fixed<kKindF32Rec, false, false, false, false>(a, s);
-                case kKindF16Rec: return launch_fixed<kKindF16Rec, false, false, false, false>(a, s);
-                case kKindU8Rec: return launch_fixed<kKindU8Rec, false, false, false, false>(a, s);
+                case kKindF32Rec: return launch_fixed<kKindF32Rec, false, JIT, DEPTH, false>(a, s);
+                case kKindF16Rec: return launch_fixed<kKindF16Rec, false, JIT, DEPTH, false>(a, s);
+                case kKindU8Rec: return launch_fixed<kKindU8Rec, false, JIT, DEPTH, false>(a, s);
                 default: break;
             }
         }

@@ -62,6 +62,7 @@ struct Request {
     float tf_rgba[RAYPC_TF_ENTRIES * 4];
     int storage = 0;  // kernel kind
     int nb_class = 0;  // field-count class of its launches (batch_nb_class)
+    bool wide = false;  // 64-bit record offsets (batch_wide)
     int n_tiles = 0, next_tile = 0;
     uint64_t bytes = 0;
     int slot = -1;
@@ -229,8 +230,9 @@ bool has_pending_tiles(const Server* S) {
     return false;
 }
 
-// One batched step: tile ranges of the admitted requests, oldest first, one launch per kernel kind and
-// field-count class present (more if one has more ranges than a launch carries).
+// One batched step: tile ranges of the admitted requests, oldest first, one launch per kernel kind,
+// field-count class and record offset width present (more if one has more ranges than a launch
+// carries).
 void launch_step(Server* S) {
     struct Take {
         Request* r;
@@ -255,14 +257,16 @@ void launch_step(Server* S) {
     }
     int k = 0;
     for (int kind = 0; kind < kKinds && e == hipSuccess; ++kind) {
-        for (int nb = -1; nb <= kMaxFields && e == hipSuccess; ++nb) {
+        for (int cls = 0; cls < 2 * (kMaxFields + 2) && e == hipSuccess; ++cls) {
+            const int nb = cls % (kMaxFields + 2) - 1;
+            const bool wide = cls >= kMaxFields + 2;
             BatchRanges R;
             R.n = 0;
             int items = 0;
             for (const Take& t : takes) {
-                if (t.r->storage != kind || t.r->nb_class != nb) continue;
+                if (t.r->storage != kind || t.r->nb_class != nb || t.r->wide != wide) continue;
                 if (R.n == kMaxRanges) {
-                    e = launch_render_batch(S->d_args, R, kind, nb, s);
+                    e = launch_render_batch(S->d_args, R, kind, nb, wide, s);
                     if (e != hipSuccess) break;
                     R.n = 0;
                     items = 0;
@@ -274,7 +278,7 @@ void launch_step(Server* S) {
                 R.n++;
                 k += t.count;
             }
-            if (e == hipSuccess && R.n) e = launch_render_batch(S->d_args, R, kind, nb, s);
+            if (e == hipSuccess && R.n) e = launch_render_batch(S->d_args, R, kind, nb, wide, s);
         }
     }
     Step step;
@@ -446,6 +450,7 @@ int raypc_submit(raypc_ctx* ctx, const raypc_request* req, uint64_t* ticket) {
             return rc;
         }
         r->nb_class = batch_nb_class(r->args);
+        r->wide = batch_wide(r->args, r->storage);
         build_skip_args(ctx, v, level, req->active, req->lo, req->hi, coord, req->tf_slot, r->skip_args);
         std::memcpy(r->tf_rgba, ctx->tf[req->tf_slot].rgba, sizeof(r->tf_rgba));
         r->n_tiles = r->args.n_blocks;
