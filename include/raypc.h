@@ -327,6 +327,16 @@ int raypc_export_skiplist(raypc_ctx *ctx, int volume_id, int lod, int slot, uint
  * A skipped brick has all eight bits set.  The renderer skips by these. */
 int raypc_export_subskip(raypc_ctx *ctx, int volume_id, int lod, int slot, uint8_t *out, void *stream);
 
+/* The renderer's per-brick flag words for the same brush and slot: nb^3
+ * uint16, word k = brick k; bits 0-7 are raypc_export_subskip's byte, bit 8 is
+ * set when every brick of brick k's aligned 2x2x2-brick group has all eight
+ * sub-bricks skipped, bit 9 the same for its aligned 4x4x4-brick group (a
+ * group cut by the grid's upper faces counts the bricks inside the grid).  A
+ * sample in such a group is stepped past the whole group.  `out` is device
+ * memory of nb^3 * 2 bytes, written asynchronously on `stream`; errors as for
+ * raypc_export_subskip. */
+int raypc_export_skip_words(raypc_ctx *ctx, int volume_id, int lod, int slot, uint16_t *out, void *stream);
+
 /* Voxel brush mask of one level: N_l^3 bytes, 1 where every active variable
  * lies in its [lo, hi]. */
 int raypc_export_voxel_mask(raypc_ctx *ctx, int volume_id, int lod, uint8_t *out, void *stream);

@@ -241,6 +241,25 @@ def sub_skip(fields_level, active, lo, hi, tf_field: int, vmin: float, vmax: flo
     return sub_skip_bytes(skip_bits(mins, maxs, active, lo, hi, tf_field, vmin, vmax, tf_rgba, coord, n, SUB))
 
 
+def skip_words(sub_bytes: np.ndarray, nb: int) -> np.ndarray:
+    """Per-brick flag words of the renderer (an empty-space structure of this implementation; the
+    paper has only bricks): uint16 [nb^3], bits 0-7 the sub-brick skip byte, bit 8 set when every
+    brick of the brick's aligned 2x2x2-brick group has all eight sub-bricks skipped, bit 9 the same
+    for its aligned 4x4x4-brick group.  A group cut by the grid's upper faces counts only the bricks
+    inside the grid."""
+    sub = np.asarray(sub_bytes, np.uint8).reshape(nb, nb, nb)
+    full = sub == 0xFF
+    words = sub.astype(np.uint16)
+    for g, bit in ((2, 0x100), (4, 0x200)):
+        ng = -(-nb // g)
+        padded = np.ones((ng * g,) * 3, bool)
+        padded[:nb, :nb, :nb] = full
+        empty = padded.reshape(ng, g, ng, g, ng, g).all(axis=(1, 3, 5))
+        spread = np.repeat(np.repeat(np.repeat(empty, g, 0), g, 1), g, 2)[:nb, :nb, :nb]
+        words |= np.where(spread, bit, 0).astype(np.uint16)
+    return words.reshape(-1)
+
+
 def pack_bits(flags: np.ndarray) -> np.ndarray:
     """bool array (linear brick order) -> uint32 words, brick k in word k//32 bit k%32."""
     flat = np.asarray(flags, bool).ravel()

@@ -554,7 +554,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 if (!rc && v->records) rc = dev_alloc(v, &L.rec[f], lvox * 8);
             }
             if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip), L.n_words() * sizeof(uint32_t));
-            if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip_sub), L.n_bricks());
+            if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip_sub), L.n_bricks() * sizeof(uint16_t));
         }
         if (rc) break;
         if (!on_device && (rc = tmp_alloc(reinterpret_cast<void**>(&stage), nvox * sizeof(float)))) break;
@@ -1080,7 +1080,8 @@ int raypc_export_minmax_sub(raypc_ctx* ctx, int volume_id, int lod, int field, f
     return RAYPC_OK;
 }
 
-static int export_skip(raypc_ctx* ctx, int volume_id, int lod, int slot, void* out, bool sub, void* stream) {
+// what: 0 the skip bits, 1 the sub-brick flags (low bytes of the flag words), 2 the flag words.
+static int export_skip(raypc_ctx* ctx, int volume_id, int lod, int slot, void* out, int what, void* stream) {
     if (!ctx || !out) return fail(RAYPC_ERR_INVALID, "NULL argument");
     DeviceGuard g(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1095,8 +1096,12 @@ static int export_skip(raypc_ctx* ctx, int volume_id, int lod, int slot, void* o
     rc = ensure_skip(ctx, v, lod, slot, s);
     if (rc) return rc;
     const Level& L = v->lv[lod];
-    if (sub)
-        HIP_TRY(hipMemcpyAsync(out, L.skip_sub, L.n_bricks(), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(sub-brick flags)");
+    if (what == 1)  // the low bytes of the flag words
+        HIP_TRY(hipMemcpy2DAsync(out, 1, L.skip_sub, sizeof(uint16_t), 1, L.n_bricks(), hipMemcpyDeviceToDevice, s),
+                "hipMemcpy2DAsync(sub-brick flags)");
+    else if (what == 2)
+        HIP_TRY(hipMemcpyAsync(out, L.skip_sub, L.n_bricks() * sizeof(uint16_t), hipMemcpyDeviceToDevice, s),
+                "hipMemcpyAsync(skip flag words)");
     else
         HIP_TRY(hipMemcpyAsync(out, L.skip, L.n_words() * sizeof(uint32_t), hipMemcpyDeviceToDevice, s),
                 "hipMemcpyAsync(skip list)");
@@ -1104,11 +1109,15 @@ static int export_skip(raypc_ctx* ctx, int volume_id, int lod, int slot, void* o
 }
 
 int raypc_export_skiplist(raypc_ctx* ctx, int volume_id, int lod, int slot, uint32_t* out, void* stream) {
-    return export_skip(ctx, volume_id, lod, slot, out, false, stream);
+    return export_skip(ctx, volume_id, lod, slot, out, 0, stream);
 }
 
 int raypc_export_subskip(raypc_ctx* ctx, int volume_id, int lod, int slot, uint8_t* out, void* stream) {
-    return export_skip(ctx, volume_id, lod, slot, out, true, stream);
+    return export_skip(ctx, volume_id, lod, slot, out, 1, stream);
+}
+
+int raypc_export_skip_words(raypc_ctx* ctx, int volume_id, int lod, int slot, uint16_t* out, void* stream) {
+    return export_skip(ctx, volume_id, lod, slot, out, 2, stream);
 }
 
 int raypc_pc_lines(raypc_ctx* ctx, int volume_id, int lod, int n_lines, const uint32_t* cells, const float* axis_lo,

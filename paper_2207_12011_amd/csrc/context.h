@@ -23,7 +23,7 @@ struct Level {
     float2* mm_sub[kMaxFields] = {};  // per brick, its eight 4^3 sub-bricks' (min, max)
     void* rec[kMaxFields] = {};  // neighbourhood records (null when the volume keeps only the compact layout)
     uint32_t* skip = nullptr;    // brick skip bits
-    uint8_t* skip_sub = nullptr; // sub-brick skip flags, one byte per brick
+    uint16_t* skip_sub = nullptr; // per brick: sub-brick skip flags (bits 0-7) and empty-group bits (8, 9)
     bool skip_valid = false;
     uint64_t skip_brush_gen = 0, skip_tf_gen = 0;
     int skip_slot = -1;

@@ -134,8 +134,13 @@ struct SkipArgs {
     float h;                               // fl32(2 / n)
     uint32_t n_bricks;
     uint32_t* out;                         // brick skip bits, ceil(n_bricks / 32) words (may be null)
-    uint8_t* out_sub;                      // sub-brick skip flags, one byte per brick (may be null)
+    uint16_t* out_sub;                     // per-brick flag words (may be null), see below
 };
+// Per-brick flag words: bits 0-7 the sub-brick skip flags (bit sx + 2 sy + 4 sz: that 4^3 sub-brick is
+// skipped), bit 8 set when every brick of the brick's aligned 2^3-brick group (16^3 voxels) has all
+// eight sub-bricks skipped, bit 9 the same for its aligned 4^3-brick group (32^3 voxels); groups cut by
+// the grid's upper faces count only the bricks inside it.  launch_skip writes them (when out_sub is
+// set) together with the skip bits.
 hipError_t launch_skip(const SkipArgs& a, hipStream_t s);
 
 // ------------------------------------------------------------------ ray marcher
@@ -154,7 +159,7 @@ struct RenderArgs {
     uint32_t par_bytes;           // bytes of one field's per-brick (scale, offset) table (u8)
     uint32_t rec_bytes;           // bytes of one field's records (buffer range; fields below 4 GiB only)
     float half_n;                 // N / 2: u = (p + 1) N/2 - 1/2
-    const uint8_t* skip;          // per brick, bit sx + 2 sy + 4 sz: 4^3 sub-brick skipped (nullptr: no skipping)
+    const uint16_t* skip;         // per-brick flag words of launch_skip (nullptr: no skipping)
     const float4* tf;             // 256 straight-RGBA entries
     float vmin, inv_range;
     float inv_ref;                // 1 / ref_step

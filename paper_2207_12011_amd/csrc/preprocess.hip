@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void skip_kernel(SkipArgs a) {
                         if (coord_box_miss(a, bx * 8 + (i & 1) * 4, by * 8 + ((i >> 1) & 1) * 4, bz * 8 + (i >> 2) * 4, 4))
                             sub |= 1u << i;
             }
-            a.out_sub[b] = static_cast<uint8_t>(sub);
+            a.out_sub[b] = static_cast<uint16_t>(sub);
         }
     }
     if (a.out == nullptr) return;
@@ -386,6 +386,26 @@ __global__ __launch_bounds__(256) void skip_kernel(SkipArgs a) {
     const uint32_t n_words = (a.n_bricks + 31) >> 5;
     if (lane == 0 && word < n_words) a.out[word] = static_cast<uint32_t>(m);
     if (lane == 32 && word + 1 < n_words) a.out[word + 1] = static_cast<uint32_t>(m >> 32);
+}
+
+// Empty-group bits of the flag words: one wave per aligned 4^3-brick group, lane t on the brick at
+// offset (x, y, z) with t = x0 + 2 y0 + 4 z0 + 8 (x1 + 2 y1 + 4 z1) (bit 0 and bit 1 of each offset), so
+// that each 2^3-brick subgroup is one run of 8 lanes.  Bricks outside the grid count as empty.
+__global__ __launch_bounds__(64) void skip_groups_kernel(uint16_t* __restrict__ flags, int nb) {
+    const int gpa = (nb + 3) / 4;  // groups per axis
+    const int g = blockIdx.x;
+    const int gx = g % gpa, gy = (g / gpa) % gpa, gz = g / (gpa * gpa);
+    const int t = threadIdx.x;
+    const int x = gx * 4 + ((t & 1) | ((t >> 2) & 2));
+    const int y = gy * 4 + (((t >> 1) & 1) | ((t >> 3) & 2));
+    const int z = gz * 4 + (((t >> 2) & 1) | ((t >> 4) & 2));
+    const bool inside = x < nb && y < nb && z < nb;
+    const size_t b = (static_cast<size_t>(z) * nb + y) * nb + x;
+    const uint32_t w = inside ? flags[b] : 0xFFu;
+    const unsigned long long full = __ballot((w & 0xFFu) == 0xFFu);
+    const bool group16 = ((full >> (t & ~7)) & 0xFFull) == 0xFFull;
+    const bool group32 = full == ~0ull;
+    if (inside) flags[b] = static_cast<uint16_t>((w & 0xFFu) | (group16 ? 0x100u : 0u) | (group32 ? 0x200u : 0u));
 }
 
 inline unsigned blocks_for(size_t count, unsigned threads) {
@@ -502,6 +522,10 @@ hipError_t launch_skip(const SkipArgs& a, hipStream_t s) {
     // whole waves only, so that every ballot covers 64 consecutive bricks
     const unsigned blocks = blocks_for(a.n_bricks, 256);
     hipLaunchKernelGGL(skip_kernel, dim3(std::max(blocks, 1u)), dim3(256), 0, s, a);
+    if (a.out_sub != nullptr) {
+        const unsigned gpa = static_cast<unsigned>((a.nb + 3) / 4);
+        hipLaunchKernelGGL(skip_groups_kernel, dim3(gpa * gpa * gpa), dim3(64), 0, s, a.out_sub, a.nb);
+    }
     return hipGetLastError();
 }
 

@@ -390,15 +390,17 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
             const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
             // brick rows and slabs below 2^7, bricks per row below 2^8: 24-bit products are exact
             const uint32_t brick = raypc_mul_u24(raypc_mul_u24(static_cast<uint32_t>(bzi), nbu) + byi, nbu) + bxi;
-            const uint32_t flags = A.skip != nullptr ? global_ptr<uint8_t>(A.skip)[brick] : 0u;
+            const uint32_t flags = A.skip != nullptr ? global_ptr<uint16_t>(A.skip)[brick] : 0u;
             const uint32_t sbi = ((x0 >> 2) & 1) | (((y0 >> 2) & 1) << 1) | (((z0 >> 2) & 1) << 2);  // sub-brick
             if ((flags >> sbi) & 1u) {
-                // every sample whose base corner lies in this sub-brick (in this brick, when all
-                // eight are flagged) is discarded or transparent: find the first sample that may lie
-                // beyond the box (shrunk by a margin against rounding; open at the grid's faces,
-                // where clamping maps every outside position to the boundary box)
+                // every sample whose base corner lies in this sub-brick (in this brick, or its
+                // empty brick group, when flagged so) is discarded or transparent: find the first
+                // sample that may lie beyond the box (shrunk by a margin against rounding; open at the
+                // grid's faces, where clamping maps every outside position to the boundary box)
                 skipped = true;
-                const int m = flags == 0xFFu ? -8 : -4;  // box of 8^3 or 4^3 voxels: corner x0 & m, edge -m
+                // the largest empty box holding the sample's base corner: its aligned 4^3- or 2^3-brick
+                // group, the brick, or the sub-brick (corner x0 & m, edge -m voxels)
+                const int m = (flags & 0x200u) ? -32 : ((flags & 0x100u) ? -16 : ((flags & 0xFFu) == 0xFFu ? -8 : -4));
                 const float t_exit = fminf(box_exit(x0 & m, -m, upx, uosx, inv_dux, n),
                                            fminf(box_exit(y0 & m, -m, upy, uosy, inv_duy, n),
                                                  box_exit(z0 & m, -m, upz, uosz, inv_duz, n)));

@@ -49,7 +49,7 @@ double now_ms() {
 }
 
 constexpr int kMaxSlots = 256;
-constexpr size_t kMaxSkipBytes = 128u * 128u * 128u;  // sub-brick flags of a level with 128^3 bricks
+constexpr size_t kMaxSkipWords = 128u * 128u * 128u;  // flag words of a level with 128^3 bricks
 constexpr int kDefaultTilesPerStep = 32768;
 
 struct Request {
@@ -101,7 +101,7 @@ struct Server {
     RenderArgs* h_args = nullptr;
     float4* d_tf = nullptr;
     float4* h_tf = nullptr;
-    uint8_t* d_skip = nullptr;
+    uint16_t* d_skip = nullptr;
     int fatal = 0;  // set when a device call failed: every later request fails with it
 };
 
@@ -188,13 +188,13 @@ void admit(Server* S) {
         const int slot = S->free_slots.back();
         S->free_slots.pop_back();
         RenderArgs a = r->args;
-        a.skip = S->d_skip + static_cast<size_t>(slot) * kMaxSkipBytes;
+        a.skip = S->d_skip + static_cast<size_t>(slot) * kMaxSkipWords;
         a.tf = S->d_tf + static_cast<size_t>(slot) * RAYPC_TF_ENTRIES;
         S->h_args[slot] = a;
         std::memcpy(S->h_tf + static_cast<size_t>(slot) * RAYPC_TF_ENTRIES, r->tf_rgba, sizeof(r->tf_rgba));
         SkipArgs sk = r->skip_args;
         sk.out = nullptr;  // the renderer reads only the sub-brick flags
-        sk.out_sub = const_cast<uint8_t*>(a.skip);
+        sk.out_sub = const_cast<uint16_t*>(a.skip);
         hipError_t e = hipMemcpyAsync(S->d_args + slot, S->h_args + slot, sizeof(RenderArgs), hipMemcpyHostToDevice,
                                       S->upload);
         if (e == hipSuccess)
@@ -403,7 +403,7 @@ int raypc_server_start(raypc_ctx* ctx, const raypc_server_cfg* cfg) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->uploaded, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_args), slots * sizeof(RenderArgs));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_tf), slots * RAYPC_TF_ENTRIES * sizeof(float4));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_skip), slots * kMaxSkipBytes);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_skip), slots * kMaxSkipWords * sizeof(uint16_t));
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&S->h_args), slots * sizeof(RenderArgs), 0);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&S->h_tf), slots * RAYPC_TF_ENTRIES * sizeof(float4), 0);
     if (e != hipSuccess) {

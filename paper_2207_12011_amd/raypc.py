@@ -86,6 +86,7 @@ _render_jittered = _sig("raypc_render_jittered", _I, _P, _I, _P, _I, _I, _I, cty
                         ctypes.c_uint64, _P, _P, _P, _P, _P)
 _export_skip = _sig("raypc_export_skiplist", _I, _P, _I, _I, _I, _P, _P)
 _export_subskip = _sig("raypc_export_subskip", _I, _P, _I, _I, _I, _P, _P)
+_export_skip_words = _sig("raypc_export_skip_words", _I, _P, _I, _I, _I, _P, _P)
 _export_mask = _sig("raypc_export_voxel_mask", _I, _P, _I, _I, _P, _P)
 _render_debug = _sig("raypc_render_debug", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _P, _I,
                      _P)
@@ -133,7 +134,7 @@ EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_po
             "raypc_unload", "raypc_volume_info", "raypc_set_brush", "raypc_set_transfer_function",
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
             "raypc_export_level", "raypc_export_minmax", "raypc_export_minmax_sub", "raypc_export_skiplist",
-            "raypc_export_subskip", "raypc_export_voxel_mask", "raypc_render_debug", "raypc_pc_lines",
+            "raypc_export_subskip", "raypc_export_skip_words", "raypc_export_voxel_mask", "raypc_render_debug", "raypc_pc_lines",
             "raypc_render_jittered", "raypc_set_coordinate_brush", "raypc_render_depth", "raypc_warp",
             "raypc_set_launch_shape", "raypc_get_launch_shape", "raypc_autotune_render"]
 
@@ -407,6 +408,13 @@ def export_subskip(ctx, volume_id: int, lod: int, slot: int = 0, stream=None) ->
     nb = (volume_info(ctx, volume_id)["n"] >> lod) // 8
     out = torch.empty((nb ** 3,), dtype=torch.uint8, device="cuda")
     _check(_export_subskip(ctx, int(volume_id), int(lod), int(slot), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def export_skip_words(ctx, volume_id: int, lod: int, slot: int = 0, stream=None) -> torch.Tensor:
+    nb = (volume_info(ctx, volume_id)["n"] >> lod) // 8
+    out = torch.empty((nb ** 3,), dtype=torch.int16, device="cuda")
+    _check(_export_skip_words(ctx, int(volume_id), int(lod), int(slot), out.data_ptr(), _stream(stream)))
     return out
 
 

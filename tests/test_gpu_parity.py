@@ -116,6 +116,9 @@ def test_skiplist_and_mask_bitexact(rp, ctx, small5, storage):
                 want_sub = pp.sub_skip(levels[lod], act, lo, hi, wl.tf.field, wl.tf.vmin, wl.tf.vmax, t)
                 got_sub = cpu(rp.export_subskip(ctx, vid, lod, slot))
                 assert np.array_equal(got_sub, want_sub), (bi, lod, slot)
+                nb = (wl.n >> lod) // 8
+                got_words = cpu(rp.export_skip_words(ctx, vid, lod, slot)).view(np.uint16)
+                assert np.array_equal(got_words, pp.skip_words(want_sub, nb)), (bi, lod, slot)
             m = cpu(rp.export_voxel_mask(ctx, vid, lod))
             assert np.array_equal(m, pp.voxel_mask(levels[lod], act, lo, hi)), (bi, lod)
     rp.unload(ctx, vid)

@@ -5,6 +5,8 @@ storage types; admission is FIFO under a memory budget; oversized requests,
 deadlines, cancellation and busy volumes are reported as documented."""
 import math
 
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -163,6 +165,11 @@ def test_deadline_cancel_and_busy_volume(rp, setup):
     try:
         big = torch.empty((512, 512, 4), device="cuda")
         t_big = rp.submit(ctx, rp.make_request(vid, cam, 512, 512, big, active=[0] * 5, lo=[0] * 5, hi=[0] * 5))
+        # the scheduler thread admits it asynchronously: wait until it holds the slot
+        t0 = time.monotonic()
+        while rp.poll(ctx, t_big) == rp.REQ_QUEUED and time.monotonic() - t0 < 10.0:
+            time.sleep(0.0005)
+        assert rp.poll(ctx, t_big) == rp.REQ_RUNNING
         small = [torch.empty((16, 16, 4), device="cuda") for _ in range(3)]
         t_dead = rp.submit(ctx, rp.make_request(vid, cam, 16, 16, small[0], deadline_ms=0.01))
         t_cancel = rp.submit(ctx, rp.make_request(vid, cam, 16, 16, small[1]))

@@ -532,6 +532,32 @@ def test_sub_skip_layout():
     assert list(np.flatnonzero(~coarse)) == [1]
 
 
+@pytest.mark.parametrize("nb", [2, 4, 6, 8])
+def test_skip_words_groups_bruteforce(nb):
+    """Group bits of the flag words against a per-brick enumeration of each brick's aligned group
+    (clipped to the grid), on seeded random sub-brick bytes, mostly all-skipped so that empty groups
+    occur; the low byte is the sub-brick byte itself."""
+    rng = np.random.default_rng(nb)
+    sub = np.where(rng.random(nb ** 3) < 0.9, 0xFF, rng.integers(0, 255, nb ** 3)).astype(np.uint8)
+    cube = sub.reshape(nb, nb, nb)
+    cube[:4, :4, :4] = 0xFF  # an empty 4^3 group (clipped for nb = 2)
+    if nb >= 8:
+        cube[4:, 4:, 4:] = 0xFF
+        cube[7, 7, 7] = 0x7F  # a 4^3 group with empty 2^3 subgroups but one hole
+    words = pp.skip_words(sub, nb)
+    full = (sub == 0xFF).reshape(nb, nb, nb)
+    for k in range(nb ** 3):
+        z, y, x = k // (nb * nb), (k // nb) % nb, k % nb
+        want = int(sub[k])
+        for g, bit in ((2, 0x100), (4, 0x200)):
+            zs, ys, xs = (z // g) * g, (y // g) * g, (x // g) * g
+            if full[zs:zs + g, ys:ys + g, xs:xs + g].all():
+                want |= bit
+        assert int(words[k]) == want, (nb, k)
+    if nb == 8:  # both kinds of group occur in this seeded case
+        assert np.any(words & 0x200) and np.any((words & 0x300) == 0x100)
+
+
 def test_sub_skip_refines_brick_skip():
     """A skipped brick has all eight sub-bricks skipped (its window contains theirs), and the
     sub-brick rule skips strictly more on the tiny workload."""
