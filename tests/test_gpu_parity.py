@@ -562,4 +562,23 @@ def test_max_size_1024_sampled(rp, ctx):
         compare(rgba.reshape(-1, 4)[pix], ref, nom.reshape(-1)[pix], comp.reshape(-1)[pix], label=f"1024 {storage}")
         lod2 = gpu_render(rp, ctx, vid, wl, 2, width=480, height=270)[0]
         assert np.isfinite(lod2).all() and lod2[..., 3].max() > 0
+        if storage in ("f16", "u8"):
+            # served requests at this size: level 0's record fields reach 4 GiB, so the batched kernel
+            # reads them at 64-bit offsets (level 1 at 32-bit ones); either way the image is the
+            # single render's bit for bit
+            print(f"[case] 1024^3 {storage} served", flush=True)
+            cam = wl.camera.as_array()
+            rp.server_start(ctx, 0, 4, 0, 0)
+            try:
+                for lod, (w, h) in ((0, (320, 180)), (1, (256, 144))):
+                    single = cpu(rp.render(ctx, vid, cam, w, h, lod, wl.step))
+                    out = torch.empty((h, w, 4), dtype=torch.float32, device="cuda")
+                    t = rp.submit(ctx, rp.make_request(vid, cam, w, h, out, lod, wl.step, wl.brush.active,
+                                                       wl.brush.lo, wl.brush.hi))
+                    rp.wait(ctx, t, 60000)
+                    assert np.array_equal(cpu(out), single), (storage, lod)
+                    assert single[..., 3].max() > 0
+                    rp.release(ctx, t)
+            finally:
+                rp.server_stop(ctx)
         rp.unload(ctx, vid)
