@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void raymarch_batch_kernel(
     __syncthreads();
     int bx, by;
     tile_coords(tile, A.blocks_x, A.n_blocks / A.blocks_x, bx, by);
-    march_tile<K, NB, false, false, false, WIDE>(A, bx, by, s_tf);
+    march_tile<K, NB, false, false, false, WIDE>(A, &A, bx, by, s_tf);
 }
 
 template <int K, bool WIDE>

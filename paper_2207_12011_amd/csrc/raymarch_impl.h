@@ -270,9 +270,10 @@ __device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) 
 // first and last samples of a segment are partial).  DEPTH: also write the opacity-weighted depth, the
 // mean distance of the composited samples, each weighted by its share w of the pixel's opacity (the
 // depth that image warping reprojects with; +inf where nothing was composited).  WIDE: 64-bit record
-// offsets (needed for record fields of 4 GiB and more).
-template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true>
-__device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, const float4* s_tf) {
+// offsets (needed for record fields of 4 GiB and more).  L points to the same arguments as A; the
+// pixel's outputs are written through it (see late_args).
+template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true, typename LP>
+__device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, int by, const float4* s_tf) {
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
     constexpr int RT = record_type_of(K);
@@ -580,38 +581,48 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, int bx, int by, 
     if (!inside || sub != 0) return;
     const float acc = 1.0f - T;
     float4 res = make_float4(C0, C1, C2, acc);
-    if (A.has_bg) {
-        res.x = fmaf(T, A.bg[0], res.x);
-        res.y = fmaf(T, A.bg[1], res.y);
-        res.z = fmaf(T, A.bg[2], res.z);
-        res.w = fmaf(T, A.bg[3], res.w);
+    if (L->has_bg) {
+        res.x = fmaf(T, L->bg[0], res.x);
+        res.y = fmaf(T, L->bg[1], res.y);
+        res.z = fmaf(T, L->bg[2], res.z);
+        res.w = fmaf(T, L->bg[3], res.w);
     }
-    const size_t pix = static_cast<size_t>(py) * A.width + px;
+    const size_t pix = static_cast<size_t>(py) * L->width + px;
     f32x4 o4;
     o4.x = res.x, o4.y = res.y, o4.z = res.z, o4.w = res.w;
-    if (!JIT || A.out != nullptr)
-        reinterpret_cast<__attribute__((address_space(1))) f32x4*>(reinterpret_cast<uintptr_t>(A.out))[pix] = o4;
+    if (!JIT || L->out != nullptr)
+        reinterpret_cast<__attribute__((address_space(1))) f32x4*>(reinterpret_cast<uintptr_t>(L->out))[pix] = o4;
     if constexpr (JIT) {
-        if (A.mean != nullptr) {
+        if (L->mean != nullptr) {
             // running mean over the passes: m <- m + (c - m) / (pass + 1), exactly c on pass 0
-            auto* m = reinterpret_cast<__attribute__((address_space(1))) f32x4*>(reinterpret_cast<uintptr_t>(A.mean));
-            f32x4 prev = A.pass == 0 ? o4 : m[pix];
+            auto* m = reinterpret_cast<__attribute__((address_space(1))) f32x4*>(reinterpret_cast<uintptr_t>(L->mean));
+            f32x4 prev = L->pass == 0 ? o4 : m[pix];
             f32x4 nm;
-            nm.x = fmaf(o4.x - prev.x, A.inv_pass1, prev.x);
-            nm.y = fmaf(o4.y - prev.y, A.inv_pass1, prev.y);
-            nm.z = fmaf(o4.z - prev.z, A.inv_pass1, prev.z);
-            nm.w = fmaf(o4.w - prev.w, A.inv_pass1, prev.w);
+            nm.x = fmaf(o4.x - prev.x, L->inv_pass1, prev.x);
+            nm.y = fmaf(o4.y - prev.y, L->inv_pass1, prev.y);
+            nm.z = fmaf(o4.z - prev.z, L->inv_pass1, prev.z);
+            nm.w = fmaf(o4.w - prev.w, L->inv_pass1, prev.w);
             m[pix] = nm;
         }
     }
     if constexpr (COUNTS) {
-        if (A.nominal) A.nominal[pix] = cnt_nom;
-        if (A.composited) A.composited[pix] = cnt_comp;
+        if (L->nominal) L->nominal[pix] = cnt_nom;
+        if (L->composited) L->composited[pix] = cnt_comp;
     }
     if constexpr (DEPTH) {
         // the weights sum to the opacity 1 - T (before the background, which has no depth)
-        A.depth[pix] = acc > 0.0f ? D / acc : INFINITY;
+        L->depth[pix] = acc > 0.0f ? D / acc : INFINITY;
     }
+}
+
+// The kernel's arguments read through a pointer to the argument segment that the compiler cannot see
+// through: the loads of the arguments used only after the march (outputs, background, running mean)
+// then stay there instead of holding scalar registers throughout it.
+typedef const __attribute__((address_space(4))) RenderArgs* KernelArgsPtr;
+__device__ __forceinline__ KernelArgsPtr late_args() {
+    KernelArgsPtr p = (KernelArgsPtr)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return p;
 }
 
 template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true>
@@ -625,7 +636,7 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
         s_tf[threadIdx.x] = make_float4(e.x, e.y, e.z, e.w);
     }
     __syncthreads();
-    march_tile<K, NB, COUNTS, JIT, DEPTH, WIDE>(A, bx, by, s_tf);
+    march_tile<K, NB, COUNTS, JIT, DEPTH, WIDE>(A, late_args(), bx, by, s_tf);
 }
 
 // Single-image launch of the kernel with the request's field count as a template argument (the field
