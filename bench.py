@@ -594,11 +594,26 @@ def main():
                             ert=wl.ert, r_inner=wl.r_inner, r_outer=wl.r_outer, pixels=pix, threads=threads)
         dt = time.perf_counter() - t0
         ns = int(ref.nominal.astype(np.int64).sum())
+        # one thread on every 8th row and column (a 1/64 subset of the frame)
+        ys1, xs1 = np.meshgrid(np.arange(0, H_, 8), np.arange(0, W_, 8), indexing="ij")
+        pix1 = (ys1 * W_ + xs1).ravel()
+        t1 = time.perf_counter()
+        ref1 = oracle.render(level, cam, W_, H_, wl.step, active=b.active, lo=b.lo, hi=b.hi, tf_field=wl.tf.field,
+                             vmin=wl.tf.vmin, vmax=wl.tf.vmax, tf_rgba=wl.tf.rgba, ref_step=wl.tf.ref_step,
+                             ert=wl.ert, r_inner=wl.r_inner, r_outer=wl.r_outer, pixels=pix1, threads=1)
+        dt1 = time.perf_counter() - t1
+        ns1 = int(ref1.nominal.astype(np.int64).sum())
+        # nominal samples of the whole frame (brush 0): the oracle's own count when it rendered all of it
+        frame_samples = ns if args.cpu_stride == 1 else results[head]["nominal_samples_per_frame"][0]
         cpu_baseline = {"value": ns / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+                        "frames_per_s": ns / dt / frame_samples,
                         "sample": (f"the whole {W_}x{H_} frame" if args.cpu_stride == 1 else
                                    f"every {ordinal(args.cpu_stride)} row and column of the {W_}x{H_} frame") +
                                   f" ({pix.size} px, {ns} nominal samples, {dt:.1f} s on {threads} threads), brush 0, "
-                                  f"{head}-stored {wl.n}^3 x {wl.n_fields} level 0, FP64"}
+                                  f"{head}-stored {wl.n}^3 x {wl.n_fields} level 0, FP64",
+                        "single_thread": {"value": ns1 / dt1, "unit": "samples/s", "frames_per_s": ns1 / dt1 / frame_samples,
+                                          "sample": f"every 8th row and column ({pix1.size} px, {ns1} nominal samples, "
+                                                    f"{dt1:.1f} s on 1 thread)"}}
 
     line = {
         "metric": "brushed ray-march samples/s (FP16 fields; frames/s, p50/p99 latency and FP32/u8 alongside)",
