@@ -244,10 +244,10 @@ int raypc_render_jittered(raypc_ctx *ctx, int volume_id, const raypc_camera *cam
                           uint32_t *nominal, uint32_t *composited, void *stream);
 
 /* Launch shape of single-image renders (raypc_render, _debug, _progressive, _jittered, _depth): the
- * 8x8-pixel tiles are dealt to the 8 XCDs in super-tiles of 2^s x 2^s tiles (8 << s pixels square,
- * s = super_log2 in 0..3; default 2, 32x32 pixels), round-robin, so that a super-tile's rays share
+ * 4x4-pixel tiles (one wave each) are dealt to the 8 XCDs in super-tiles of 8 << s pixels square
+ * (s = super_log2 in 0..3; default 2, 32x32 pixels), round-robin, so that a super-tile's rays share
  * one XCD's L2 while every XCD gets tiles from all over the image.  The shape changes timing only,
- * never an image.  Serving launches keep s = 2.  Errors: RAYPC_ERR_INVALID. */
+ * never an image.  Serving launches keep 32x32-pixel super-tiles.  Errors: RAYPC_ERR_INVALID. */
 int raypc_set_launch_shape(raypc_ctx *ctx, int super_log2);
 int raypc_get_launch_shape(raypc_ctx *ctx, int *super_log2);
 
@@ -380,7 +380,7 @@ int raypc_render_debug(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, i
  * (Section 2.2: rendering is decoupled from the application's frame rate):
  * a scheduler thread owned by the context admits requests in submission order
  * while a request slot is free and the memory budget allows, and every
- * launch ("step") marches 8x8-pixel tiles of all admitted requests together,
+ * launch ("step") marches 4x4-pixel tiles of all admitted requests together,
  * oldest request first; requests that arrive while others run join the next
  * step.  Each request carries its own brush and names a transfer-function slot;
  * the brush, the table and the options (termination threshold, background)
@@ -393,10 +393,10 @@ int raypc_render_debug(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, i
 
 typedef struct {
     uint64_t mem_budget_bytes; /* device memory in-flight requests may hold: each counts its image
-                                  (width*height*16 bytes, caller-owned) plus its sub-brick skip flags (one byte per brick);
+                                  (width*height*16 bytes, caller-owned) plus its skip flag words (two bytes per brick);
                                   0 = unlimited */
     int max_inflight;          /* request slots, 1..256 */
-    int tiles_per_step;        /* 8x8-pixel tiles per step, 0 = 32768 (about one 1920x1080 image) */
+    int tiles_per_step;        /* work per step in units of 8x8 pixels, 0 = 32768 (about one 1920x1080 image) */
     int steps_in_flight;       /* steps queued ahead on the device, 1..4 (0 = 2) */
 } raypc_server_cfg;
 

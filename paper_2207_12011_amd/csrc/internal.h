@@ -12,7 +12,7 @@ namespace raypc {
 constexpr int kMaxFields = 8;
 constexpr int kBrick = 8;           // brick edge in voxels
 constexpr int kBrickVoxels = 512;   // 8^3
-constexpr int kBlockPix = 8;        // a 256-thread ray-march block covers 8 x 8 pixels
+constexpr int kBlockPix = 4;        // a ray-march block is one wave and covers 4 x 4 pixels
 
 enum Storage : int { kF32 = 0, kF16 = 1, kU8 = 2 };
 // Kernel variants: a storage type, read from the compact layout or from neighbourhood records.
@@ -180,8 +180,8 @@ struct RenderArgs {
     uint32_t* nominal;            // debug counts (only in the counting variant)
     uint32_t* composited;
     uint32_t* touched;            // debug: bit per brick read by an evaluated sample (may be null)
-    int blocks_x, n_blocks;       // 8 x 8 pixel blocks per row, total
-    int super_log2;               // single-image launches: super-tiles of 2^s x 2^s blocks dealt over the XCDs
+    int blocks_x, n_blocks;       // 4 x 4 pixel blocks (tiles) per row, total
+    int super_log2;               // single-image launches: super-tiles of 8 << s pixels dealt over the XCDs
     // jittered progressive passes (jittered kernels only): pass `pass` of `n_passes` shifts each
     // pixel's sample grid by s ds, s from a SplitMix64 stream at `seed`; `mean` (may be null)
     // holds the running mean of the passes, updated with weight inv_pass1 = 1 / (pass + 1)

@@ -37,7 +37,7 @@
 // 4^3 sub-bricks flagged as skipped are stepped over without fetching (the whole
 // 8^3 brick when all eight of its sub-bricks are flagged): every sample whose
 // base corner lies in such a box would be discarded or fully transparent, so
-// skipping changes no value.  Blocks of 4 waves (8 x 8 pixels) are dealt to the
+// skipping changes no value.  Blocks of one wave (4 x 4 pixels) are dealt to the
 // XCDs by super-tiles (32 x 32 pixels unless the launch shape says otherwise); the transfer function
 // sits in LDS.  This file holds the single-image launches, whose field count is a template argument;
 // raymarch_batch.hip holds those that read it at run time.

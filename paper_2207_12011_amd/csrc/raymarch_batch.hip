@@ -11,11 +11,11 @@ namespace {
 // Batched launch: item j marches one tile of one request, as the ranges in the kernel arguments
 // say.  Tiles of many requests (different images, brushes, levels and transfer functions, one
 // kernel kind and field count) share a launch; each tile runs exactly the code path of a
-// single-request render.  Chunks of 16 consecutive items (one super-tile of a request, as the
+// single-request render.  Chunks of 64 consecutive items (one super-tile of a request, as the
 // scheduler lists them) are dealt round-robin over the 8 XCDs; the grid is padded to whole rounds of
-// 8 chunks.  WIDE: 64-bit record offsets (record fields of 4 GiB and more).
+// 8 chunks.  Blocks are single waves (4 x 4 pixels).  WIDE: 64-bit record offsets (record fields of 4 GiB and more).
 template <int K, int NB, bool WIDE>
-__global__ __launch_bounds__(256) void raymarch_batch_kernel(
+__global__ __launch_bounds__(64) void raymarch_batch_kernel(
     const RenderArgs* __restrict__ descs, BatchRanges R) {
     __shared__ float4 s_tf[256];
     const int xcd = blockIdx.x & 7, p = blockIdx.x >> 3;
@@ -25,11 +25,7 @@ __global__ __launch_bounds__(256) void raymarch_batch_kernel(
     while (j >= R.end[r]) ++r;
     const int tile = R.first[r] + j - (r ? R.end[r - 1] : 0);
     const RenderArgs& A = descs[R.slot[r]];
-    {
-        const f32x4 e = global_ptr<f32x4>(A.tf)[threadIdx.x];
-        s_tf[threadIdx.x] = make_float4(e.x, e.y, e.z, e.w);
-    }
-    __syncthreads();
+    load_tf(A.tf, s_tf);
     int bx, by;
     tile_coords(tile, A.blocks_x, A.n_blocks / A.blocks_x, bx, by);
     march_tile<K, NB, false, false, false, WIDE>(A, &A, bx, by, s_tf);
@@ -37,7 +33,7 @@ __global__ __launch_bounds__(256) void raymarch_batch_kernel(
 
 template <int K, bool WIDE>
 hipError_t launch_batch_nb(const RenderArgs* descs, const BatchRanges& R, int nb_class, dim3 grid, hipStream_t s) {
-    const dim3 block(256);
+    const dim3 block(64);
     switch (nb_class) {
         case kRuntimeNB: hipLaunchKernelGGL((raymarch_batch_kernel<K, kRuntimeNB, WIDE>), grid, block, 0, s, descs, R); break;
         case 0: hipLaunchKernelGGL((raymarch_batch_kernel<K, 0, WIDE>), grid, block, 0, s, descs, R); break;

@@ -16,8 +16,7 @@ namespace {
 constexpr float kSkipShrink = 2e-3f;  // voxels: shrink of a skipped box before computing its exit
 constexpr float kSkipMargin = 0.01f;  // samples: margin on the first sample after a skipped box
 constexpr int kQuad = 4;              // lanes (consecutive samples) per ray
-constexpr int kWaveTile = 4;          // a wave covers kWaveTile x kWaveTile pixels
-constexpr int kBlockTile = 8;         // a 256-thread block covers 8 x 8 pixels
+constexpr int kBlockTile = 4;         // a block is one wave and covers 4 x 4 pixels (16 rays)
 
 // Global-memory view of a pointer.  Pointers read from memory (the batched launch takes its
 // arguments from a device array) would otherwise be accessed with generic flat loads.
@@ -199,11 +198,13 @@ __device__ __forceinline__ int quad_bcast(int v) {
 }
 
 // Tiles are grouped in super-tiles of kSuper x kSuper tiles (32 x 32 pixels) and super-tiles are dealt
-// round-robin over the 8 XCDs (block i runs on XCD i % 8).  The tiles of a super-tile run together
+// round-robin over the 8 XCDs (block i runs on XCD i % 8).  A block is a single wave, so its slot on
+// the CU frees as soon as its 16 rays are done (a block of several waves holds its slot until the
+// slowest of them ends).  The tiles of a super-tile run together
 // on one XCD (their rays share voxels in its L2), and every XCD gets super-tiles from all over the
 // image, so the work of the shell's disc is spread evenly; 32 x 32 pixels balances the two (larger
 // super-tiles leave some XCDs with more of the disc's costly centre, smaller ones share less).
-constexpr int kSuper = 4;
+constexpr int kSuper = 8;
 constexpr int kSuperTiles = kSuper * kSuper;
 
 // Batched launches number a request's tiles super-tile by super-tile in row-major order, tiles
@@ -227,10 +228,11 @@ __device__ __forceinline__ void tile_coords(int i, int bx_count, int by_count, i
     }
 }
 
-// Single-image launches deal super-tiles of 2^s x 2^s tiles (s = A.super_log2, a launch-shape
-// parameter: 8 << s pixels square; the serving path keeps s = 2): the j-th block an XCD receives is
-// tile j % 4^s of super-tile (j / 4^s) * 8 + xcd (super-tiles row-major over the image).  The grid
-// is padded to whole rounds of 8 super-tiles; blocks outside the image return at once.
+// Single-image launches deal super-tiles of 2^s x 2^s tiles (s = A.super_log2 + 1 for the launch-shape
+// parameter A.super_log2: 8 << A.super_log2 pixels square; the serving path keeps 32 pixels): the j-th
+// block an XCD receives is tile j % 4^s of super-tile (j / 4^s) * 8 + xcd (super-tiles row-major over
+// the image).  The grid is padded to whole rounds of 8 super-tiles; blocks outside the image return
+// at once.
 __host__ __device__ inline int super_cols(int blocks_x, int s) { return (blocks_x + (1 << s) - 1) >> s; }
 __host__ __device__ inline int padded_blocks(int blocks_x, int blocks_y, int s) {
     const int supers = super_cols(blocks_x, s) * ((blocks_y + (1 << s) - 1) >> s);
@@ -243,6 +245,16 @@ __device__ __forceinline__ void interleaved_tile(int bid, int blocks_x, int s, i
     const int sc = super_cols(blocks_x, s);
     bx = ((st % sc) << s) + (w & ((1 << s) - 1));
     by = ((st / sc) << s) + (w >> s);
+}
+
+// The 256-entry transfer-function table into LDS by a one-wave block (four entries per lane).
+__device__ __forceinline__ void load_tf(const float4* tf, float4* s_tf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const f32x4 e = global_ptr<f32x4>(tf)[threadIdx.x + 64 * i];
+        s_tf[threadIdx.x + 64 * i] = make_float4(e.x, e.y, e.z, e.w);
+    }
+    __syncthreads();
 }
 
 // Number of brushed fields known only at run time, tested per field in the loop (coordinate axes take
@@ -264,8 +276,7 @@ __device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) 
     return fminf(s, 0x1.fffffep-1f);
 }
 
-// One 8 x 8 pixel tile (index blk in row-major tile order) of the image described by A, marched by
-// the calling 256-thread block.  NB is the number of brushed fields, or kRuntimeNB to read it from A.
+// One 4 x 4 pixel tile (bx, by) of the image described by A, marched by the calling one-wave block.  NB is the number of brushed fields, or kRuntimeNB to read it from A.
 // JIT: a jittered progressive pass (the sample grid of every segment starts s ds before it, so the
 // first and last samples of a segment are partial).  DEPTH: also write the opacity-weighted depth, the
 // mean distance of the composited samples, each weighted by its share w of the pixel's opacity (the
@@ -277,10 +288,10 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
     constexpr int RT = record_type_of(K);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lane = threadIdx.x;
     const int ray = lane >> 2, sub = lane & 3, quad_base = lane & ~3;
-    const int px = bx * kBlockTile + (wave & 1) * kWaveTile + (ray & 3);
-    const int py = by * kBlockTile + (wave >> 1) * kWaveTile + (ray >> 2);
+    const int px = bx * kBlockTile + (ray & 3);
+    const int py = by * kBlockTile + (ray >> 2);
     const bool inside = px < A.width && py < A.height;
 
     // ---- ray through the pixel centre (identical in the four lanes of the quad)
@@ -626,16 +637,12 @@ __device__ __forceinline__ KernelArgsPtr late_args() {
 }
 
 template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true>
-__global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
+__global__ __launch_bounds__(64) void raymarch_kernel(RenderArgs A) {
     int bx, by;
-    interleaved_tile(blockIdx.x, A.blocks_x, A.super_log2, bx, by);
+    interleaved_tile(blockIdx.x, A.blocks_x, A.super_log2 + 1, bx, by);
     if (by * kBlockTile >= A.height || bx * kBlockTile >= A.width) return;  // padding block
     __shared__ float4 s_tf[256];
-    {
-        const f32x4 e = global_ptr<f32x4>(A.tf)[threadIdx.x];
-        s_tf[threadIdx.x] = make_float4(e.x, e.y, e.z, e.w);
-    }
-    __syncthreads();
+    load_tf(A.tf, s_tf);
     march_tile<K, NB, COUNTS, JIT, DEPTH, WIDE>(A, late_args(), bx, by, s_tf);
 }
 
@@ -644,7 +651,7 @@ __global__ __launch_bounds__(256) void raymarch_kernel(RenderArgs A) {
 // their test.
 template <int K, bool COUNTS, bool JIT, bool DEPTH, bool WIDE = true>
 hipError_t launch_fixed(const RenderArgs& a, hipStream_t s) {
-    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x, a.super_log2)), block(256);
+    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x, a.super_log2 + 1)), block(64);
     if (a.coord_mask) {
         hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a);
         return hipGetLastError();

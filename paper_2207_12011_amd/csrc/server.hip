@@ -239,7 +239,8 @@ void launch_step(Server* S) {
         int start, count;
     };
     std::vector<Take> takes;
-    int budget = S->cfg.tiles_per_step;
+    // the budget counts 8x8-pixel units; the renderer's tiles are 4x4 pixels
+    int budget = S->cfg.tiles_per_step * (8 / kBlockPix) * (8 / kBlockPix);
     for (Request* r : S->active) {
         if (budget == 0) break;
         const int left = r->n_tiles - r->next_tile;
@@ -455,7 +456,7 @@ int raypc_submit(raypc_ctx* ctx, const raypc_request* req, uint64_t* ticket) {
         std::memcpy(r->tf_rgba, ctx->tf[req->tf_slot].rgba, sizeof(r->tf_rgba));
         r->n_tiles = r->args.n_blocks;
         r->bytes = static_cast<uint64_t>(req->width) * req->height * 16u +
-                   static_cast<uint64_t>(r->skip_args.n_bricks);
+                   static_cast<uint64_t>(r->skip_args.n_bricks) * sizeof(uint16_t);
         if (S->cfg.mem_budget_bytes && r->bytes > S->cfg.mem_budget_bytes) {
             delete r;
             return set_error(RAYPC_ERR_NOMEM, "request needs %llu bytes, the server budget is %llu",

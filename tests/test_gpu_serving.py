@@ -122,7 +122,7 @@ def test_budget_queues_requests_fifo(rp, setup):
     reqs = random_requests(rng, vols, 8)
     for q in reqs:
         q["w"], q["h"] = 96, 96
-    per_req = 96 * 96 * 16 + 8 * 8 * 8    # image + one byte of sub-brick skip flags per brick
+    per_req = 96 * 96 * 16 + 8 * 8 * 8 * 2    # image + the two-byte skip flag word per brick
     rp.server_start(ctx, per_req + 100, 8, 16, 2)       # room for exactly one request at a time
     try:
         tickets, outs = submit_all(rp, ctx, reqs)
