@@ -25,7 +25,6 @@ __global__ __launch_bounds__(64) void raymarch_batch_kernel(
     while (j >= R.end[r]) ++r;
     const int tile = R.first[r] + j - (r ? R.end[r - 1] : 0);
     const RenderArgs& A = descs[R.slot[r]];
-    load_tf(A.tf, s_tf);
     int bx, by;
     tile_coords(tile, A.blocks_x, A.n_blocks / A.blocks_x, bx, by);
     march_tile<K, NB, false, false, false, WIDE>(A, &A, bx, by, s_tf);

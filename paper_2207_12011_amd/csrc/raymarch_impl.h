@@ -284,7 +284,7 @@ __device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) 
 // offsets (needed for record fields of 4 GiB and more).  L points to the same arguments as A; the
 // pixel's outputs are written through it (see late_args).
 template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true, typename LP>
-__device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, int by, const float4* s_tf) {
+__device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, int by, float4* s_tf) {
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
     constexpr int RT = record_type_of(K);
@@ -336,6 +336,10 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
             }
         }
     }
+
+    // the transfer-function table into LDS, by waves with a ray through the shell only (most waves of
+    // a frame see background alone)
+    if (__ballot(nseg > 0) != 0ull) load_tf(A.tf, s_tf);
 
     const int n = A.n, nb = A.nb;
     const uint32_t nbu = static_cast<uint32_t>(nb);
@@ -642,7 +646,6 @@ __global__ __launch_bounds__(64) void raymarch_kernel(RenderArgs A) {
     interleaved_tile(blockIdx.x, A.blocks_x, A.super_log2 + 1, bx, by);
     if (by * kBlockTile >= A.height || bx * kBlockTile >= A.width) return;  // padding block
     __shared__ float4 s_tf[256];
-    load_tf(A.tf, s_tf);
     march_tile<K, NB, COUNTS, JIT, DEPTH, WIDE>(A, late_args(), bx, by, s_tf);
 }
 
