@@ -27,7 +27,7 @@ __global__ __launch_bounds__(64) void raymarch_batch_kernel(
     const RenderArgs& A = descs[R.slot[r]];
     int bx, by;
     tile_coords(tile, A.blocks_x, A.n_blocks / A.blocks_x, bx, by);
-    march_tile<K, NB, false, false, false, WIDE>(A, &A, bx, by, s_tf);
+    march_tile<K, NB, false, false, false, WIDE, 1>(A, &A, bx, by, s_tf);
 }
 
 template <int K, bool WIDE>

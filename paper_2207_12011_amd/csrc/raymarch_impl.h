@@ -16,7 +16,7 @@ namespace {
 constexpr float kSkipShrink = 2e-3f;  // voxels: shrink of a skipped box before computing its exit
 constexpr float kSkipMargin = 0.01f;  // samples: margin on the first sample after a skipped box
 constexpr int kQuad = 4;              // lanes (consecutive samples) per ray
-constexpr int kBlockTile = 4;         // a block is one wave and covers 4 x 4 pixels (16 rays)
+constexpr int kWaveTile = 4;          // a wave covers 4 x 4 pixels (16 rays)
 
 // Global-memory view of a pointer.  Pointers read from memory (the batched launch takes its
 // arguments from a device array) would otherwise be accessed with generic flat loads.
@@ -228,8 +228,8 @@ __device__ __forceinline__ void tile_coords(int i, int bx_count, int by_count, i
     }
 }
 
-// Single-image launches deal super-tiles of 2^s x 2^s tiles (s = A.super_log2 + 1 for the launch-shape
-// parameter A.super_log2: 8 << A.super_log2 pixels square; the serving path keeps 32 pixels): the j-th
+// Single-image launches deal super-tiles of 2^s x 2^s tiles (8 << A.super_log2 pixels square for the
+// launch-shape parameter A.super_log2, see launch_tiles; the serving path keeps 32 pixels): the j-th
 // block an XCD receives is tile j % 4^s of super-tile (j / 4^s) * 8 + xcd (super-tiles row-major over
 // the image).  The grid is padded to whole rounds of 8 super-tiles; blocks outside the image return
 // at once.
@@ -247,12 +247,19 @@ __device__ __forceinline__ void interleaved_tile(int bid, int blocks_x, int s, i
     by = ((st / sc) << s) + (w >> s);
 }
 
-// The 256-entry transfer-function table into LDS by a one-wave block (four entries per lane).
+// Waves per block of the single-image kernels: record fields of 4 GiB and more (the WIDE record kinds,
+// level 0 of a 1024^3 grid) keep four waves on 8 x 8 pixels, whose rays share a CU's L1 (faster on such
+// volumes); every other kernel runs one wave on 4 x 4 pixels, whose CU slot frees as soon as its 16
+// rays end (a block of several waves holds its slot until the slowest of them ends).
+constexpr int block_waves(int K, bool WIDE) { return records_of(K) && WIDE ? 4 : 1; }
+
+// The 256-entry transfer-function table into LDS by a block of BW waves.
+template <int BW>
 __device__ __forceinline__ void load_tf(const float4* tf, float4* s_tf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const f32x4 e = global_ptr<f32x4>(tf)[threadIdx.x + 64 * i];
-        s_tf[threadIdx.x + 64 * i] = make_float4(e.x, e.y, e.z, e.w);
+    for (int i = 0; i < 4 / BW; ++i) {
+        const f32x4 e = global_ptr<f32x4>(tf)[threadIdx.x + 64 * BW * i];
+        s_tf[threadIdx.x + 64 * BW * i] = make_float4(e.x, e.y, e.z, e.w);
     }
     __syncthreads();
 }
@@ -283,15 +290,17 @@ __device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) 
 // depth that image warping reprojects with; +inf where nothing was composited).  WIDE: 64-bit record
 // offsets (needed for record fields of 4 GiB and more).  L points to the same arguments as A; the
 // pixel's outputs are written through it (see late_args).
-template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true, typename LP>
+template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true, int BW = 1,
+          typename LP>
 __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, int by, float4* s_tf) {
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
     constexpr int RT = record_type_of(K);
-    const int lane = threadIdx.x;
+    constexpr int BT = BW == 4 ? 2 * kWaveTile : kWaveTile;  // block tile: 2 x 2 waves or one
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ray = lane >> 2, sub = lane & 3, quad_base = lane & ~3;
-    const int px = bx * kBlockTile + (ray & 3);
-    const int py = by * kBlockTile + (ray >> 2);
+    const int px = bx * BT + (wave & 1) * kWaveTile + (ray & 3);
+    const int py = by * BT + (wave >> 1) * kWaveTile + (ray >> 2);
     const bool inside = px < A.width && py < A.height;
 
     // ---- ray through the pixel centre (identical in the four lanes of the quad)
@@ -337,9 +346,9 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
         }
     }
 
-    // the transfer-function table into LDS, by waves with a ray through the shell only (most waves of
-    // a frame see background alone)
-    if (__ballot(nseg > 0) != 0ull) load_tf(A.tf, s_tf);
+    // the transfer-function table into LDS; a one-wave block loads it only if one of its rays passes
+    // through the shell (most waves of a frame see background alone)
+    if (BW > 1 || __ballot(nseg > 0) != 0ull) load_tf<BW>(A.tf, s_tf);
 
     const int n = A.n, nb = A.nb;
     const uint32_t nbu = static_cast<uint32_t>(nb);
@@ -640,13 +649,27 @@ __device__ __forceinline__ KernelArgsPtr late_args() {
     return p;
 }
 
+// Tiles of a single-image launch: the host counts 4 x 4 pixel tiles (blocks_x per row); blocks of four
+// waves take 8 x 8 pixels, and super-tiles of 2^s x 2^s such tiles keep 8 << super_log2 pixels.
+struct LaunchTiles {
+    int cols, rows, s;
+};
+template <int BW>
+__host__ __device__ inline LaunchTiles launch_tiles(int blocks_x, int n_blocks, int super_log2) {
+    const int rows4 = n_blocks / blocks_x;
+    if (BW == 4) return {(blocks_x + 1) / 2, (rows4 + 1) / 2, super_log2};
+    return {blocks_x, rows4, super_log2 + 1};
+}
+
 template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true>
-__global__ __launch_bounds__(64) void raymarch_kernel(RenderArgs A) {
+__global__ __launch_bounds__(64 * block_waves(K, WIDE)) void raymarch_kernel(RenderArgs A) {
+    constexpr int BW = block_waves(K, WIDE), BT = BW == 4 ? 2 * kWaveTile : kWaveTile;
+    const LaunchTiles lt = launch_tiles<BW>(A.blocks_x, A.n_blocks, A.super_log2);
     int bx, by;
-    interleaved_tile(blockIdx.x, A.blocks_x, A.super_log2 + 1, bx, by);
-    if (by * kBlockTile >= A.height || bx * kBlockTile >= A.width) return;  // padding block
+    interleaved_tile(blockIdx.x, lt.cols, lt.s, bx, by);
+    if (by * BT >= A.height || bx * BT >= A.width) return;  // padding block
     __shared__ float4 s_tf[256];
-    march_tile<K, NB, COUNTS, JIT, DEPTH, WIDE>(A, late_args(), bx, by, s_tf);
+    march_tile<K, NB, COUNTS, JIT, DEPTH, WIDE, BW>(A, late_args(), bx, by, s_tf);
 }
 
 // Single-image launch of the kernel with the request's field count as a template argument (the field
@@ -654,7 +677,9 @@ __global__ __launch_bounds__(64) void raymarch_kernel(RenderArgs A) {
 // their test.
 template <int K, bool COUNTS, bool JIT, bool DEPTH, bool WIDE = true>
 hipError_t launch_fixed(const RenderArgs& a, hipStream_t s) {
-    const dim3 grid(padded_blocks(a.blocks_x, a.n_blocks / a.blocks_x, a.super_log2 + 1)), block(64);
+    constexpr int BW = block_waves(K, WIDE);
+    const LaunchTiles lt = launch_tiles<BW>(a.blocks_x, a.n_blocks, a.super_log2);
+    const dim3 grid(padded_blocks(lt.cols, lt.rows, lt.s)), block(64 * BW);
     if (a.coord_mask) {
         hipLaunchKernelGGL((raymarch_kernel<K, kRuntimeNB, COUNTS, JIT, DEPTH, WIDE>), grid, block, 0, s, a);
         return hipGetLastError();
