@@ -52,6 +52,9 @@ def test_every_launch_shape_gives_the_same_image(rp, ctx, storage):
                 assert rp.get_launch_shape(ctx) == s
                 got = [cpu(x) for x in rp.render_debug(ctx, vid, cam, w, h, lod, 0.5)]
                 assert all(np.array_equal(a, b) for a, b in zip(got, want)), (s, w, h)
+                # the plain render (one-wave blocks, 32-bit record offsets) and the counting variant
+                # (four-wave blocks, 64-bit offsets for the record kinds) march the same samples
+                assert np.array_equal(cpu(rp.render(ctx, vid, cam, w, h, lod, 0.5)), want[0]), (s, w, h)
                 jit = cpu(rp.render_jittered(ctx, vid, cam, w, h, lod, 0.5, 1, 4, 7)[0])
                 rp.set_launch_shape(ctx, 2)
                 assert np.array_equal(jit, cpu(rp.render_jittered(ctx, vid, cam, w, h, lod, 0.5, 1, 4, 7)[0]))
