@@ -331,8 +331,9 @@ int raypc_export_subskip(raypc_ctx *ctx, int volume_id, int lod, int slot, uint8
  * uint16, word k = brick k; bits 0-7 are raypc_export_subskip's byte, bit 8 is
  * set when every brick of brick k's aligned 2x2x2-brick group has all eight
  * sub-bricks skipped, bit 9 the same for its aligned 4x4x4-brick group (a
- * group cut by the grid's upper faces counts the bricks inside the grid).  A
- * sample in such a group is stepped past the whole group.  `out` is device
+ * group cut by the grid's upper faces counts the bricks inside the grid), and
+ * bit 10 is brick k's bit of raypc_export_skiplist.  A sample in an empty
+ * group is stepped past the whole group.  `out` is device
  * memory of nb^3 * 2 bytes, written asynchronously on `stream`; errors as for
  * raypc_export_subskip. */
 int raypc_export_skip_words(raypc_ctx *ctx, int volume_id, int lod, int slot, uint16_t *out, void *stream);

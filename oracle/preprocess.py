@@ -241,12 +241,13 @@ def sub_skip(fields_level, active, lo, hi, tf_field: int, vmin: float, vmax: flo
     return sub_skip_bytes(skip_bits(mins, maxs, active, lo, hi, tf_field, vmin, vmax, tf_rgba, coord, n, SUB))
 
 
-def skip_words(sub_bytes: np.ndarray, nb: int) -> np.ndarray:
+def skip_words(sub_bytes: np.ndarray, nb: int, brick_skip=None) -> np.ndarray:
     """Per-brick flag words of the renderer (an empty-space structure of this implementation; the
     paper has only bricks): uint16 [nb^3], bits 0-7 the sub-brick skip byte, bit 8 set when every
     brick of the brick's aligned 2x2x2-brick group has all eight sub-bricks skipped, bit 9 the same
-    for its aligned 4x4x4-brick group.  A group cut by the grid's upper faces counts only the bricks
-    inside the grid."""
+    for its aligned 4x4x4-brick group (a group cut by the grid's upper faces counts only the bricks
+    inside the grid), bit 10 the brick's own skip bit (`brick_skip`, bool per brick in linear
+    order; bit 10 clear when it is None)."""
     sub = np.asarray(sub_bytes, np.uint8).reshape(nb, nb, nb)
     full = sub == 0xFF
     words = sub.astype(np.uint16)
@@ -257,7 +258,10 @@ def skip_words(sub_bytes: np.ndarray, nb: int) -> np.ndarray:
         empty = padded.reshape(ng, g, ng, g, ng, g).all(axis=(1, 3, 5))
         spread = np.repeat(np.repeat(np.repeat(empty, g, 0), g, 1), g, 2)[:nb, :nb, :nb]
         words |= np.where(spread, bit, 0).astype(np.uint16)
-    return words.reshape(-1)
+    words = words.reshape(-1)
+    if brick_skip is not None:
+        words |= np.where(np.asarray(brick_skip, bool).reshape(-1), 0x400, 0).astype(np.uint16)
+    return words
 
 
 def pack_bits(flags: np.ndarray) -> np.ndarray:

@@ -205,7 +205,6 @@ void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t
     a.nb = L.nb;
     a.h = 2.0f / static_cast<float>(L.n);
     a.n_bricks = L.n_bricks();
-    a.out = nullptr;
     a.out_sub = nullptr;
 }
 
@@ -218,7 +217,6 @@ static int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s
         return RAYPC_OK;
     SkipArgs a;
     build_skip_args(ctx, v, l, v->active, v->lo, v->hi, v->coord, slot, a);
-    a.out = L.skip;
     a.out_sub = L.skip_sub;
     HIP_TRY(launch_skip(a, s), "skip-list kernel launch");
     L.skip_valid = true;
@@ -553,7 +551,6 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm_sub[f]), L.n_bricks() * 8 * sizeof(float2));
                 if (!rc && v->records) rc = dev_alloc(v, &L.rec[f], lvox * 8);
             }
-            if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip), L.n_words() * sizeof(uint32_t));
             if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip_sub), L.n_bricks() * sizeof(uint16_t));
         }
         if (rc) break;
@@ -1080,7 +1077,8 @@ int raypc_export_minmax_sub(raypc_ctx* ctx, int volume_id, int lod, int field, f
     return RAYPC_OK;
 }
 
-// what: 0 the skip bits, 1 the sub-brick flags (low bytes of the flag words), 2 the flag words.
+// what: 0 the skip bits (bit 10 of the flag words, packed), 1 the sub-brick flags (low bytes of the flag
+// words), 2 the flag words.
 static int export_skip(raypc_ctx* ctx, int volume_id, int lod, int slot, void* out, int what, void* stream) {
     if (!ctx || !out) return fail(RAYPC_ERR_INVALID, "NULL argument");
     DeviceGuard g(ctx->device);
@@ -1103,8 +1101,7 @@ static int export_skip(raypc_ctx* ctx, int volume_id, int lod, int slot, void* o
         HIP_TRY(hipMemcpyAsync(out, L.skip_sub, L.n_bricks() * sizeof(uint16_t), hipMemcpyDeviceToDevice, s),
                 "hipMemcpyAsync(skip flag words)");
     else
-        HIP_TRY(hipMemcpyAsync(out, L.skip, L.n_words() * sizeof(uint32_t), hipMemcpyDeviceToDevice, s),
-                "hipMemcpyAsync(skip list)");
+        HIP_TRY(launch_pack_skip_bits(L.skip_sub, L.n_bricks(), static_cast<uint32_t*>(out), s), "skip-bit packing");
     return RAYPC_OK;
 }
 

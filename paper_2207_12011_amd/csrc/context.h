@@ -22,7 +22,6 @@ struct Level {
     float2* mm[kMaxFields] = {};
     float2* mm_sub[kMaxFields] = {};  // per brick, its eight 4^3 sub-bricks' (min, max)
     void* rec[kMaxFields] = {};  // neighbourhood records (null when the volume keeps only the compact layout)
-    uint32_t* skip = nullptr;    // brick skip bits
     uint16_t* skip_sub = nullptr; // per brick: sub-brick skip flags (bits 0-7) and empty-group bits (8, 9)
     bool skip_valid = false;
     uint64_t skip_brush_gen = 0, skip_tf_gen = 0;

@@ -133,15 +133,17 @@ struct SkipArgs {
     int n, nb;                             // level size in voxels and bricks per axis
     float h;                               // fl32(2 / n)
     uint32_t n_bricks;
-    uint32_t* out;                         // brick skip bits, ceil(n_bricks / 32) words (may be null)
-    uint16_t* out_sub;                     // per-brick flag words (may be null), see below
+    uint16_t* out_sub;                     // per-brick flag words, see below
 };
 // Per-brick flag words: bits 0-7 the sub-brick skip flags (bit sx + 2 sy + 4 sz: that 4^3 sub-brick is
 // skipped), bit 8 set when every brick of the brick's aligned 2^3-brick group (16^3 voxels) has all
-// eight sub-bricks skipped, bit 9 the same for its aligned 4^3-brick group (32^3 voxels); groups cut by
-// the grid's upper faces count only the bricks inside it.  launch_skip writes them (when out_sub is
-// set) together with the skip bits.
+// eight sub-bricks skipped, bit 9 the same for its aligned 4^3-brick group (32^3 voxels; groups cut by
+// the grid's upper faces count only the bricks inside it), bit 10 the brick's own skip bit (the skip
+// rule on the brick's window).  launch_skip writes them; launch_pack_skip_bits packs the bit-10 skip
+// bits 32 to a word (brick k: bit k % 32 of word k / 32).
+constexpr uint32_t kBrickSkipBit = 0x400u;
 hipError_t launch_skip(const SkipArgs& a, hipStream_t s);
+hipError_t launch_pack_skip_bits(const uint16_t* words, uint32_t n_bricks, uint32_t* out, hipStream_t s);
 
 // ------------------------------------------------------------------ ray marcher
 struct RenderArgs {

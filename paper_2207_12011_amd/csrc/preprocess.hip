@@ -343,69 +343,67 @@ __device__ bool coord_box_miss(const SkipArgs& a, int x0, int y0, int z0, int bo
     return miss;
 }
 
-// One thread per brick: the brick's skip bit (a wave ballot packs 64 into two words) and its byte
-// of sub-brick flags.  A skipped brick's sub-bricks are all skipped (their windows lie inside its
-// window and the table index map is monotone), so only the other bricks read sub-brick tables.
-__global__ __launch_bounds__(256) void skip_kernel(SkipArgs a) {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+// One brick's flag word without the group bits: the brick rule's skip bit (kBrickSkipBit) and the
+// sub-brick flags (bits 0-7).  A skipped brick's sub-bricks are all skipped (their windows lie inside
+// its window and the table index map is monotone), so only the other bricks read sub-brick tables.
+__device__ uint32_t brick_word(const SkipArgs& a, uint32_t b, int bx, int by, int bz) {
     bool skip = false;
-    if (b < a.n_bricks) {
-        for (int f = 0; f < a.n_active; ++f) {
-            const float2 mm = a.minmax[f][b];
-            skip |= (mm.y < a.lo[f]) | (mm.x > a.hi[f]) | (a.lo[f] > a.hi[f]);
-        }
-        skip |= tf_range_empty(a, a.tf_minmax[b]);
-        const int bx = static_cast<int>(b % a.nb), by = static_cast<int>((b / a.nb) % a.nb);
-        const int bz = static_cast<int>(b / (static_cast<uint32_t>(a.nb) * a.nb));
-        if (a.coord_mask) skip = skip || coord_box_miss(a, bx * 8, by * 8, bz * 8, 8);
-        if (a.out_sub != nullptr) {
-            uint32_t sub = 0xFFu;
-            if (!skip) {
-                sub = 0;
-                for (int f = 0; f < a.n_active; ++f)
-                    sub |= sub_range_misses(a.minmax_sub[f] + static_cast<size_t>(b) * 8, a.lo[f], a.hi[f]);
-                const float4* q = reinterpret_cast<const float4*>(a.tf_minmax_sub + static_cast<size_t>(b) * 8);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float4 v = q[k];
-                    sub |= static_cast<uint32_t>(tf_range_empty(a, make_float2(v.x, v.y))) << (2 * k);
-                    sub |= static_cast<uint32_t>(tf_range_empty(a, make_float2(v.z, v.w))) << (2 * k + 1);
-                }
-                if (a.coord_mask)
-                    for (int i = 0; i < 8; ++i)
-                        if (coord_box_miss(a, bx * 8 + (i & 1) * 4, by * 8 + ((i >> 1) & 1) * 4, bz * 8 + (i >> 2) * 4, 4))
-                            sub |= 1u << i;
-            }
-            a.out_sub[b] = static_cast<uint16_t>(sub);
-        }
+    for (int f = 0; f < a.n_active; ++f) {
+        const float2 mm = a.minmax[f][b];
+        skip |= (mm.y < a.lo[f]) | (mm.x > a.hi[f]) | (a.lo[f] > a.hi[f]);
     }
-    if (a.out == nullptr) return;
-    const unsigned long long m = __ballot(skip);
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t word = (b - lane) >> 5;  // first of the wave's two words
-    const uint32_t n_words = (a.n_bricks + 31) >> 5;
-    if (lane == 0 && word < n_words) a.out[word] = static_cast<uint32_t>(m);
-    if (lane == 32 && word + 1 < n_words) a.out[word + 1] = static_cast<uint32_t>(m >> 32);
+    skip |= tf_range_empty(a, a.tf_minmax[b]);
+    if (a.coord_mask) skip = skip || coord_box_miss(a, bx * 8, by * 8, bz * 8, 8);
+    if (skip) return 0xFFu | kBrickSkipBit;
+    uint32_t sub = 0;
+    for (int f = 0; f < a.n_active; ++f) sub |= sub_range_misses(a.minmax_sub[f] + static_cast<size_t>(b) * 8, a.lo[f], a.hi[f]);
+    const float4* q = reinterpret_cast<const float4*>(a.tf_minmax_sub + static_cast<size_t>(b) * 8);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float4 v = q[k];
+        sub |= static_cast<uint32_t>(tf_range_empty(a, make_float2(v.x, v.y))) << (2 * k);
+        sub |= static_cast<uint32_t>(tf_range_empty(a, make_float2(v.z, v.w))) << (2 * k + 1);
+    }
+    if (a.coord_mask)
+        for (int i = 0; i < 8; ++i)
+            if (coord_box_miss(a, bx * 8 + (i & 1) * 4, by * 8 + ((i >> 1) & 1) * 4, bz * 8 + (i >> 2) * 4, 4))
+                sub |= 1u << i;
+    return sub;
 }
 
-// Empty-group bits of the flag words: one wave per aligned 4^3-brick group, lane t on the brick at
+// The skip pass: one wave per aligned 4^3-brick group (four groups per block), lane t on the brick at
 // offset (x, y, z) with t = x0 + 2 y0 + 4 z0 + 8 (x1 + 2 y1 + 4 z1) (bit 0 and bit 1 of each offset), so
-// that each 2^3-brick subgroup is one run of 8 lanes.  Bricks outside the grid count as empty.
-__global__ __launch_bounds__(64) void skip_groups_kernel(uint16_t* __restrict__ flags, int nb) {
-    const int gpa = (nb + 3) / 4;  // groups per axis
-    const int g = blockIdx.x;
+// that each 2^3-brick subgroup is one run of 8 lanes; a wave ballot gives the empty-group bits.
+// Bricks outside the grid count as empty.
+__global__ __launch_bounds__(256) void skip_kernel(SkipArgs a) {
+    const int gpa = (a.nb + 3) / 4;  // groups per axis
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= gpa * gpa * gpa) return;  // the whole wave
     const int gx = g % gpa, gy = (g / gpa) % gpa, gz = g / (gpa * gpa);
-    const int t = threadIdx.x;
+    const int t = threadIdx.x & 63;
     const int x = gx * 4 + ((t & 1) | ((t >> 2) & 2));
     const int y = gy * 4 + (((t >> 1) & 1) | ((t >> 3) & 2));
     const int z = gz * 4 + (((t >> 2) & 1) | ((t >> 4) & 2));
-    const bool inside = x < nb && y < nb && z < nb;
-    const size_t b = (static_cast<size_t>(z) * nb + y) * nb + x;
-    const uint32_t w = inside ? flags[b] : 0xFFu;
+    const bool inside = x < a.nb && y < a.nb && z < a.nb;
+    const uint32_t b = (static_cast<uint32_t>(z) * a.nb + y) * a.nb + x;
+    const uint32_t w = inside ? brick_word(a, b, x, y, z) : 0xFFu;
     const unsigned long long full = __ballot((w & 0xFFu) == 0xFFu);
     const bool group16 = ((full >> (t & ~7)) & 0xFFull) == 0xFFull;
     const bool group32 = full == ~0ull;
-    if (inside) flags[b] = static_cast<uint16_t>((w & 0xFFu) | (group16 ? 0x100u : 0u) | (group32 ? 0x200u : 0u));
+    if (inside) a.out_sub[b] = static_cast<uint16_t>(w | (group16 ? 0x100u : 0u) | (group32 ? 0x200u : 0u));
+}
+
+// Brick skip bits of the flag words packed 32 to a word (brick k: bit k % 32 of word k / 32).
+__global__ __launch_bounds__(256) void pack_skip_bits_kernel(const uint16_t* __restrict__ words, uint32_t n_bricks,
+                                                             uint32_t* __restrict__ out) {
+    const uint32_t wd = blockIdx.x * blockDim.x + threadIdx.x;
+    if (wd >= (n_bricks + 31) / 32) return;
+    uint32_t m = 0;
+    for (uint32_t i = 0; i < 32; ++i) {
+        const uint32_t b = wd * 32 + i;
+        if (b < n_bricks && (words[b] & kBrickSkipBit)) m |= 1u << i;
+    }
+    out[wd] = m;
 }
 
 inline unsigned blocks_for(size_t count, unsigned threads) {
@@ -519,13 +517,15 @@ hipError_t launch_pc_lines(const PcArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_skip(const SkipArgs& a, hipStream_t s) {
-    // whole waves only, so that every ballot covers 64 consecutive bricks
-    const unsigned blocks = blocks_for(a.n_bricks, 256);
-    hipLaunchKernelGGL(skip_kernel, dim3(std::max(blocks, 1u)), dim3(256), 0, s, a);
-    if (a.out_sub != nullptr) {
-        const unsigned gpa = static_cast<unsigned>((a.nb + 3) / 4);
-        hipLaunchKernelGGL(skip_groups_kernel, dim3(gpa * gpa * gpa), dim3(64), 0, s, a.out_sub, a.nb);
-    }
+    const unsigned gpa = static_cast<unsigned>((a.nb + 3) / 4);
+    const unsigned groups = gpa * gpa * gpa;
+    hipLaunchKernelGGL(skip_kernel, dim3(std::max((groups + 3) / 4, 1u)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_skip_bits(const uint16_t* words, uint32_t n_bricks, uint32_t* out, hipStream_t s) {
+    const unsigned blocks = blocks_for((n_bricks + 31) / 32, 256);
+    hipLaunchKernelGGL(pack_skip_bits_kernel, dim3(std::max(blocks, 1u)), dim3(256), 0, s, words, n_bricks, out);
     return hipGetLastError();
 }
 

@@ -193,7 +193,6 @@ void admit(Server* S) {
         S->h_args[slot] = a;
         std::memcpy(S->h_tf + static_cast<size_t>(slot) * RAYPC_TF_ENTRIES, r->tf_rgba, sizeof(r->tf_rgba));
         SkipArgs sk = r->skip_args;
-        sk.out = nullptr;  // the renderer reads only the sub-brick flags
         sk.out_sub = const_cast<uint16_t*>(a.skip);
         hipError_t e = hipMemcpyAsync(S->d_args + slot, S->h_args + slot, sizeof(RenderArgs), hipMemcpyHostToDevice,
                                       S->upload);

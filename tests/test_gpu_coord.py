@@ -87,13 +87,15 @@ def test_coordinate_cuts_on_cells_bitexact(rp, ctx, small5, storage):
             want = pp.voxel_mask(levels[lod], wl.brush.active, wl.brush.lo, wl.brush.hi, coord=coord)
             assert np.array_equal(cpu(rp.export_voxel_mask(ctx, vid, lod)), want), (coord, lod)
             mins, maxs = zip(*[pp.brick_minmax(levels[lod][f]) for f in range(nf)])
-            bits = pp.pack_bits(pp.skip_bits(mins, maxs, wl.brush.active, wl.brush.lo, wl.brush.hi, wl.tf.field,
-                                             wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, coord, n))
+            brick_skip = pp.skip_bits(mins, maxs, wl.brush.active, wl.brush.lo, wl.brush.hi, wl.tf.field,
+                                      wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, coord, n)
+            bits = pp.pack_bits(brick_skip)
             assert np.array_equal(cpu(rp.export_skiplist(ctx, vid, lod, 0)).view(np.uint32), bits), (coord, lod)
             sub = pp.sub_skip(levels[lod], wl.brush.active, wl.brush.lo, wl.brush.hi, wl.tf.field, wl.tf.vmin,
                               wl.tf.vmax, wl.tf.rgba, coord=coord)
             assert np.array_equal(cpu(rp.export_subskip(ctx, vid, lod, 0)), sub), (coord, lod)
-            assert np.array_equal(cpu(rp.export_skip_words(ctx, vid, lod, 0)).view(np.uint16), pp.skip_words(sub, n // 8)), (coord, lod)
+            assert np.array_equal(cpu(rp.export_skip_words(ctx, vid, lod, 0)).view(np.uint16),
+                                  pp.skip_words(sub, n // 8, brick_skip)), (coord, lod)
             cells = W.pc_line_cells(n, 2000 >> lod, seed=lod)
             _, passes, hist = rp.pc_lines(ctx, vid, lod, torch.from_numpy(cells.astype(np.int32)).cuda(),
                                           axis_lo, axis_hi, 32)

@@ -110,7 +110,8 @@ def test_skiplist_and_mask_bitexact(rp, ctx, small5, storage):
         for lod in range(3):
             mins, maxs = zip(*[pp.brick_minmax(levels[lod][f]) for f in range(nf)])
             for slot, t in ((0, wl.tf.rgba), (1, tab)):
-                want = pp.pack_bits(pp.skip_bits(mins, maxs, act, lo, hi, wl.tf.field, wl.tf.vmin, wl.tf.vmax, t))
+                brick_skip = pp.skip_bits(mins, maxs, act, lo, hi, wl.tf.field, wl.tf.vmin, wl.tf.vmax, t)
+                want = pp.pack_bits(brick_skip)
                 got = cpu(rp.export_skiplist(ctx, vid, lod, slot)).view(np.uint32)
                 assert np.array_equal(got, want), (bi, lod, slot)
                 want_sub = pp.sub_skip(levels[lod], act, lo, hi, wl.tf.field, wl.tf.vmin, wl.tf.vmax, t)
@@ -118,7 +119,7 @@ def test_skiplist_and_mask_bitexact(rp, ctx, small5, storage):
                 assert np.array_equal(got_sub, want_sub), (bi, lod, slot)
                 nb = (wl.n >> lod) // 8
                 got_words = cpu(rp.export_skip_words(ctx, vid, lod, slot)).view(np.uint16)
-                assert np.array_equal(got_words, pp.skip_words(want_sub, nb)), (bi, lod, slot)
+                assert np.array_equal(got_words, pp.skip_words(want_sub, nb, brick_skip)), (bi, lod, slot)
             m = cpu(rp.export_voxel_mask(ctx, vid, lod))
             assert np.array_equal(m, pp.voxel_mask(levels[lod], act, lo, hi)), (bi, lod)
     rp.unload(ctx, vid)

@@ -544,11 +544,13 @@ def test_skip_words_groups_bruteforce(nb):
     if nb >= 8:
         cube[4:, 4:, 4:] = 0xFF
         cube[7, 7, 7] = 0x7F  # a 4^3 group with empty 2^3 subgroups but one hole
-    words = pp.skip_words(sub, nb)
+    brick_skip = (sub == 0xFF) & (rng.random(nb ** 3) < 0.5)  # a skipped brick has all sub-bricks skipped
+    words = pp.skip_words(sub, nb, brick_skip)
+    assert np.array_equal(pp.skip_words(sub, nb) | np.where(brick_skip, 0x400, 0), words)
     full = (sub == 0xFF).reshape(nb, nb, nb)
     for k in range(nb ** 3):
         z, y, x = k // (nb * nb), (k // nb) % nb, k % nb
-        want = int(sub[k])
+        want = int(sub[k]) | (0x400 if brick_skip[k] else 0)
         for g, bit in ((2, 0x100), (4, 0x200)):
             zs, ys, xs = (z // g) * g, (y // g) * g, (x // g) * g
             if full[zs:zs + g, ys:ys + g, xs:xs + g].all():
