@@ -110,11 +110,32 @@ __device__ __forceinline__ float blend(const Tri& t, float c0, float c1, float c
     return fmaf(t.w[7], c7, v);
 }
 
-// Trilinear value from the 8 stored corners at byte offsets o[].
+// Trilinear value from the 8 stored corners at byte offsets o[].  8-bit codes: the base corner's
+// brick (scale, offset) pair serves every corner in the same brick; a corner in another brick (the
+// sample's cell straddles a brick face) loads its own pair, in a branch, so that a wave in which no
+// cell straddles a face issues one pair load per field instead of eight.
 template <int S>
 __device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)[8], const Tri& t) {
-    return blend(t, corner<S>(src, o[0]), corner<S>(src, o[1]), corner<S>(src, o[2]), corner<S>(src, o[3]),
-                 corner<S>(src, o[4]), corner<S>(src, o[5]), corner<S>(src, o[6]), corner<S>(src, o[7]));
+    if constexpr (S == kU8) {
+        const uint32_t b0 = o[0] >> 9;
+        const auto so0 = __builtin_amdgcn_raw_buffer_load_b64(src.par, static_cast<int>(b0 * 8u), 0, 0);
+        float c[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float q = static_cast<float>(__builtin_amdgcn_raw_buffer_load_b8(src.rsrc, static_cast<int>(o[i]), 0, 0));
+            uint32_t sc = so0[0], of = so0[1];
+            if (i != 0 && (o[i] >> 9) != b0) {
+                const auto so = __builtin_amdgcn_raw_buffer_load_b64(src.par, static_cast<int>((o[i] >> 9) * 8u), 0, 0);
+                sc = so[0];
+                of = so[1];
+            }
+            c[i] = __fadd_rn(__fmul_rn(__uint_as_float(sc), q), __uint_as_float(of));
+        }
+        return blend(t, c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7]);
+    } else {
+        return blend(t, corner<S>(src, o[0]), corner<S>(src, o[1]), corner<S>(src, o[2]), corner<S>(src, o[3]),
+                     corner<S>(src, o[4]), corner<S>(src, o[5]), corner<S>(src, o[6]), corner<S>(src, o[7]));
+    }
 }
 
 // Trilinear value from neighbourhood records (8 bytes per voxel): binary16 reads the 2x2 (x, y) records
