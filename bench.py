@@ -78,13 +78,21 @@ def profile(args, wl, raypc, torch):
     torch.cuda.synchronize()
     for _ in range(args.profile_frames):
         raypc.render(ctx, vid, cam, wl.width, wl.height, -1, wl.step, out=out)
+    if args.profile_warps > 0:
+        # the image warp of the bench: the depth render, then warps to the pose moved sideways by 0.1
+        rgba, depth = raypc.render_depth(ctx, vid, cam, wl.width, wl.height, -1, wl.step)
+        c1 = cam.copy()
+        c1[0] += np.float32(0.1)
+        for _ in range(args.profile_warps):
+            raypc.warp(ctx, rgba, depth, cam, c1)
     torch.cuda.synchronize()
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     raypc.destroy(ctx)
-    print(f"[bench] profile mode: {args.profile_frames} frames ({storage}) + 1 GiB copy", file=sys.stderr)
+    print(f"[bench] profile mode: {args.profile_frames} frames ({storage}), {args.profile_warps} warps + 1 GiB copy",
+          file=sys.stderr)
 
 
 def brush_axis_sweep(raypc, torch, ctx, vid, wl, lod, stream, frames=30):
@@ -416,6 +424,9 @@ def main():
                     help="profiling mode: load the headline storage, render this many frames with the first "
                          "brush, then copy 1 GiB device-to-device (a known-size kernel for counter scaling); "
                          "prints no JSON")
+    ap.add_argument("--profile-warps", type=int, default=0,
+                    help="profiling mode: also render the frame with depth and warp it this many times to the "
+                         "pose moved sideways by 0.1")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}): the renderer shards by request across "
