@@ -25,8 +25,12 @@
 // keys, a 16-byte gather of the winner's RGBA and the outputs).  Two z-buffers are used in turn: the
 // resolve empties its pixels in the other one, so the next warp of no larger size needs no fill pass
 // (a fill kernel runs only when a buffer is not known to be empty).
-// Blocks cover 16 x 16 pixel tiles so that a block's atomics and neighbour reads stay within a few
-// cache lines of keys.
+// The splat's waves each cover 64 pixels of one row: points of neighbouring pixels land on neighbouring
+// keys, and the atomics of a wave are sent as one request per 64-byte segment of keys they touch (a
+// device-scope atomic is performed beyond the XCDs' L2 caches, so the request count sets the splat's
+// time); a 64 x 1 wave touches about 9 segments after a small move where a 16 x 4 wave touched 12.
+// The resolve's blocks cover 16 x 16 pixel tiles so that its neighbour reads stay within a few cache
+// lines of keys.
 #include <algorithm>
 
 #include "internal.h"
@@ -36,6 +40,7 @@ namespace {
 
 constexpr unsigned long long kEmpty = ~0ull;
 constexpr int kTile = 16;
+constexpr int kSplatRow = 64, kSplatRows = 4;  // splat blocks: 64 x 4 pixels, one row per wave
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -50,8 +55,8 @@ __global__ __launch_bounds__(256) void warp_clear_kernel(unsigned long long* __r
 }
 
 __global__ __launch_bounds__(256) void warp_splat_kernel(WarpArgs A) {
-    const int px = blockIdx.x * kTile + (threadIdx.x & (kTile - 1));
-    const int py = blockIdx.y * kTile + (threadIdx.x >> 4);
+    const int px = blockIdx.x * kSplatRow + (threadIdx.x & (kSplatRow - 1));
+    const int py = blockIdx.y * kSplatRows + (threadIdx.x / kSplatRow);
     const WarpCamera& S = A.src;
     const WarpCamera& Dc = A.dst;
     if (px >= S.width || py >= S.height) return;
@@ -135,7 +140,7 @@ hipError_t launch_warp(const WarpArgs& a, hipStream_t s) {
         const unsigned clear_blocks = static_cast<unsigned>(std::min<size_t>((n_dst + 255) / 256, 8192));
         hipLaunchKernelGGL(warp_clear_kernel, dim3(clear_blocks), dim3(256), 0, s, a.keys, n_dst);
     }
-    const dim3 src_grid((a.src.width + kTile - 1) / kTile, (a.src.height + kTile - 1) / kTile);
+    const dim3 src_grid((a.src.width + kSplatRow - 1) / kSplatRow, (a.src.height + kSplatRows - 1) / kSplatRows);
     hipLaunchKernelGGL(warp_splat_kernel, src_grid, dim3(256), 0, s, a);
     const dim3 dst_grid((a.dst.width + kTile - 1) / kTile, (a.dst.height + kTile - 1) / kTile);
     hipLaunchKernelGGL(warp_resolve_kernel, dst_grid, dim3(256), 0, s, a);
