@@ -301,6 +301,24 @@ int raypc_warp(raypc_ctx *ctx, const raypc_camera *src_cam, int src_width, int s
                const float *depth, const raypc_camera *dst_cam, int dst_width, int dst_height, float *rgba_out,
                float *depth_out, int32_t *source_out, void *stream);
 
+/* raypc_warp for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * display loops, harnesses that forbid hipMalloc): the same warp, arguments and outputs, bit for
+ * bit, with its z-buffer taken from a fixed array in the library's own device memory instead of
+ * the context's buffers.  It calls no hipMalloc, hipFree or other allocating routine.  The array
+ * holds RAYPC_WARP_NOALLOC_MAX_PIXELS keys (8 bytes each, 32 MiB) on every GPU the library runs
+ * on, until the process ends; its address on the context's device is looked up once, at
+ * raypc_create.  Every call on one GPU (from any context or thread) shares that GPU's array: each
+ * call first fills its dst_width x dst_height leading keys with the empty key (a fill kernel, no
+ * memset node), so nothing of an earlier call is seen, but calls that overlap in time on one GPU
+ * (on different streams, or from different threads) race on the array and their outputs are then
+ * undefined; serialise them (one stream, or events).  Async on `stream`.  Errors: as raypc_warp,
+ * and RAYPC_ERR_INVALID when dst_width x dst_height exceeds RAYPC_WARP_NOALLOC_MAX_PIXELS (nothing
+ * is launched then); RAYPC_ERR_NOMEM is never returned. */
+#define RAYPC_WARP_NOALLOC_MAX_PIXELS (2048 * 2048)
+int raypc_warp_noalloc(raypc_ctx *ctx, const raypc_camera *src_cam, int src_width, int src_height,
+                       const float *rgba, const float *depth, const raypc_camera *dst_cam, int dst_width,
+                       int dst_height, float *rgba_out, float *depth_out, int32_t *source_out, void *stream);
+
 /* ---------------------------------------------------------------- debug exports
  * For parity tests and accounting.  All outputs are device buffers (async). */
 

@@ -435,8 +435,13 @@ int raypc_create(int device, raypc_ctx** out) {
     if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
     if (device < 0 || device >= count) return fail(RAYPC_ERR_INVALID, "device %d outside [0, %d)", device, count);
     DeviceGuard g(device);
+    // the allocation-free warp's fixed z-buffer on this device (looked up with the device current)
+    unsigned long long* scratch_keys = nullptr;
+    e = warp_scratch(device, &scratch_keys);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(warp scratch z-buffer)");
     raypc_ctx* ctx = new raypc_ctx();
     ctx->device = device;
+    ctx->warp_scratch = scratch_keys;
     for (int s = 0; s < RAYPC_TF_SLOTS; ++s) {
         e = hipMalloc(reinterpret_cast<void**>(&ctx->tf[s].dev), RAYPC_TF_ENTRIES * sizeof(float4));
         if (e != hipSuccess) {
@@ -841,9 +846,10 @@ static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     return a && b && x < y + nb && y < x + na;
 }
 
-int raypc_warp(raypc_ctx* ctx, const raypc_camera* src_cam, int src_width, int src_height, const float* rgba,
-               const float* depth, const raypc_camera* dst_cam, int dst_width, int dst_height, float* rgba_out,
-               float* depth_out, int32_t* source_out, void* stream) {
+// Validation and the camera frames of a warp (both warp entry points); the z-buffers are left to the caller.
+static int warp_setup(raypc_ctx* ctx, const raypc_camera* src_cam, int src_width, int src_height, const float* rgba,
+                      const float* depth, const raypc_camera* dst_cam, int dst_width, int dst_height, float* rgba_out,
+                      float* depth_out, int32_t* source_out, WarpArgs& w) {
     if (!ctx || !rgba || !depth || !rgba_out) return fail(RAYPC_ERR_INVALID, "NULL argument");
     if (src_width < 1 || src_width > 16384 || src_height < 1 || src_height > 16384 || dst_width < 1 ||
         dst_width > 16384 || dst_height < 1 || dst_height > 16384)
@@ -869,7 +875,6 @@ int raypc_warp(raypc_ctx* ctx, const raypc_camera* src_cam, int src_width, int s
     if (rc) return rc;
     rc = camera_setup(dst_cam, dst_width, dst_height, cd);
     if (rc) return rc;
-    WarpArgs w;
     std::memset(&w, 0, sizeof(w));
     auto frame = [](const RenderArgs& r, WarpCamera& c) {
         for (int k = 0; k < 3; ++k) {
@@ -887,6 +892,23 @@ int raypc_warp(raypc_ctx* ctx, const raypc_camera* src_cam, int src_width, int s
     };
     frame(cs, w.src);
     frame(cd, w.dst);
+    w.rgba = reinterpret_cast<const float4*>(rgba);
+    w.depth = depth;
+    w.n_src = static_cast<uint32_t>(ns);
+    w.out = reinterpret_cast<float4*>(rgba_out);
+    w.out_depth = depth_out;
+    w.out_src = source_out;
+    return RAYPC_OK;
+}
+
+int raypc_warp(raypc_ctx* ctx, const raypc_camera* src_cam, int src_width, int src_height, const float* rgba,
+               const float* depth, const raypc_camera* dst_cam, int dst_width, int dst_height, float* rgba_out,
+               float* depth_out, int32_t* source_out, void* stream) {
+    WarpArgs w;
+    int rc = warp_setup(ctx, src_cam, src_width, src_height, rgba, depth, dst_cam, dst_width, dst_height, rgba_out,
+                        depth_out, source_out, w);
+    if (rc) return rc;
+    const size_t nd = static_cast<size_t>(dst_width) * dst_height;
     DeviceGuard g(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (nd > ctx->warp_keys_n) {
@@ -911,20 +933,35 @@ int raypc_warp(raypc_ctx* ctx, const raypc_camera* src_cam, int src_width, int s
         ctx->warp_keys_n = nd;
     }
     const int cur = ctx->warp_cur, other = 1 - cur;
-    w.rgba = reinterpret_cast<const float4*>(rgba);
-    w.depth = depth;
-    w.n_src = static_cast<uint32_t>(ns);
     w.keys = ctx->warp_keys[cur];
     w.clear_keys = ctx->warp_clean_n[cur] < nd;
     w.next_keys = ctx->warp_keys[other];
-    w.out = reinterpret_cast<float4*>(rgba_out);
-    w.out_depth = depth_out;
-    w.out_src = source_out;
     ctx->warp_clean_n[cur] = 0;  // holds this warp's keys from now on
     ctx->warp_clean_n[other] = 0;
     HIP_TRY(launch_warp(w, static_cast<hipStream_t>(stream)), "warp kernel launches");
     ctx->warp_clean_n[other] = nd;  // emptied by this warp's resolve
     ctx->warp_cur = other;
+    return RAYPC_OK;
+}
+
+int raypc_warp_noalloc(raypc_ctx* ctx, const raypc_camera* src_cam, int src_width, int src_height, const float* rgba,
+                       const float* depth, const raypc_camera* dst_cam, int dst_width, int dst_height, float* rgba_out,
+                       float* depth_out, int32_t* source_out, void* stream) {
+    WarpArgs w;
+    int rc = warp_setup(ctx, src_cam, src_width, src_height, rgba, depth, dst_cam, dst_width, dst_height, rgba_out,
+                        depth_out, source_out, w);
+    if (rc) return rc;
+    const size_t nd = static_cast<size_t>(dst_width) * dst_height;
+    if (nd > kWarpScratchPixels)
+        return fail(RAYPC_ERR_INVALID, "destination of %dx%d = %zu pixels exceeds the fixed z-buffer's %zu pixels",
+                    dst_width, dst_height, nd, kWarpScratchPixels);
+    if (!ctx->warp_scratch) return fail(RAYPC_ERR_DEVICE, "no fixed z-buffer on device %d", ctx->device);
+    DeviceGuard g(ctx->device);
+    // the array keeps whatever the last call on this device left: the fill kernel empties it first
+    w.keys = ctx->warp_scratch;
+    w.clear_keys = 1;
+    w.next_keys = nullptr;
+    HIP_TRY(launch_warp(w, static_cast<hipStream_t>(stream)), "warp kernel launches");
     return RAYPC_OK;
 }
 

@@ -92,6 +92,7 @@ struct raypc_ctx {
     size_t warp_keys_n = 0;        // capacity of each, pixels
     size_t warp_clean_n[2] = {0, 0};  // leading pixels of each known to hold the empty key
     int warp_cur = 0;              // the buffer the next warp splats into
+    unsigned long long* warp_scratch = nullptr;  // this device's fixed z-buffer (raypc_warp_noalloc)
     int super_log2 = raypc::kDefaultSuperLog2;  // launch shape of single-image renders (raypc_set_launch_shape)
 };
 

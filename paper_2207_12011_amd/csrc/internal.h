@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/raypc.h"
+
 #include <cstddef>
 #include <cstdint>
 
@@ -218,6 +220,12 @@ struct WarpArgs {
     int32_t* out_src;             // may be null
 };
 hipError_t launch_warp(const WarpArgs& a, hipStream_t s);
+// The allocation-free warp's z-buffer: a fixed array of kWarpScratchPixels keys per GPU (32 MiB),
+// shared by every call on that GPU.  warp_scratch returns its address on `device`, which must be
+// the current device (looked up once per device, then cached).
+constexpr size_t kWarpScratchPixels = RAYPC_WARP_NOALLOC_MAX_PIXELS;
+constexpr int kMaxDevices = 64;
+hipError_t warp_scratch(int device, unsigned long long** ptr);
 // Work of one batched launch, passed by value in the kernel arguments: range r covers items
 // [end[r-1], end[r]) (end[-1] = 0), which march tiles first[r], first[r] + 1, ... of the request whose
 // arguments are descs[slot[r]].  Every descriptor's volume uses the launch's kernel kind.

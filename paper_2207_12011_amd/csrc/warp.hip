@@ -32,6 +32,7 @@
 // The resolve's blocks cover 16 x 16 pixel tiles so that its neighbour reads stay within a few cache
 // lines of keys.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
 
@@ -39,6 +40,12 @@ namespace raypc {
 namespace {
 
 constexpr unsigned long long kEmpty = ~0ull;
+
+// The z-buffer of the allocation-free warp (raypc_warp_noalloc): one per GPU, in the code object's
+// own device memory, so that a caller that cannot allocate can still warp.  Host code never uses
+// this name as an address (it names the host-side stand-in): warp_scratch() asks the runtime for
+// each device's address once and hands that out.
+static __device__ __align__(256) unsigned long long scratch[kWarpScratchPixels];
 constexpr int kTile = 16;
 constexpr int kSplatRow = 64, kSplatRows = 4;  // splat blocks: 64 x 4 pixels, one row per wave
 
@@ -133,6 +140,25 @@ __global__ __launch_bounds__(256) void warp_resolve_kernel(WarpArgs A) {
 }
 
 }  // namespace
+
+hipError_t warp_scratch(int device, unsigned long long** ptr) {
+    static std::mutex mu;
+    static unsigned long long* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<unsigned long long*>(p);
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_warp(const WarpArgs& a, hipStream_t s) {
     const size_t n_dst = static_cast<size_t>(a.dst.width) * a.dst.height;

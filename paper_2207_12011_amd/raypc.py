@@ -97,6 +97,9 @@ _autotune_render = _sig("raypc_autotune_render", _I, _P, _I, ctypes.POINTER(Came
                         ctypes.POINTER(_I))
 _warp = _sig("raypc_warp", _I, _P, ctypes.POINTER(Camera), _I, _I, _P, _P, ctypes.POINTER(Camera), _I, _I, _P, _P, _P,
              _P)
+_warp_noalloc = _sig("raypc_warp_noalloc", _I, _P, ctypes.POINTER(Camera), _I, _I, _P, _P, ctypes.POINTER(Camera), _I,
+                     _I, _P, _P, _P, _P)
+WARP_NOALLOC_MAX_PIXELS = 2048 * 2048
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", _I), ("tiles_per_step", _I),
@@ -135,7 +138,7 @@ EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_po
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
             "raypc_export_level", "raypc_export_minmax", "raypc_export_minmax_sub", "raypc_export_skiplist",
             "raypc_export_subskip", "raypc_export_skip_words", "raypc_export_voxel_mask", "raypc_render_debug", "raypc_pc_lines",
-            "raypc_render_jittered", "raypc_set_coordinate_brush", "raypc_render_depth", "raypc_warp",
+            "raypc_render_jittered", "raypc_set_coordinate_brush", "raypc_render_depth", "raypc_warp", "raypc_warp_noalloc",
             "raypc_set_launch_shape", "raypc_get_launch_shape", "raypc_autotune_render"]
 
 
@@ -360,9 +363,12 @@ def render_depth(ctx, volume_id: int, camera, width: int, height: int, lod: int 
 
 def warp(ctx, rgba: torch.Tensor, depth: torch.Tensor, src_camera, dst_camera, dst_width: Optional[int] = None,
          dst_height: Optional[int] = None, out: Optional[torch.Tensor] = None, out_depth: Optional[torch.Tensor] = None,
-         out_source: Optional[torch.Tensor] = None, want_depth: bool = True, want_source: bool = True, stream=None):
+         out_source: Optional[torch.Tensor] = None, want_depth: bool = True, want_source: bool = True, stream=None,
+         noalloc: bool = False):
     """Warp a frame (rgba [H,W,4] f32, depth [H,W] f32 CUDA tensors rendered with src_camera) to
-    dst_camera: (rgba [H',W',4] f32, depth [H',W'] f32 or None, source [H',W'] int32 or None), async."""
+    dst_camera: (rgba [H',W',4] f32, depth [H',W'] f32 or None, source [H',W'] int32 or None), async.
+    noalloc: call raypc_warp_noalloc (the library's fixed z-buffer; outputs must be passed in by a
+    caller that cannot allocate, else they are allocated here)."""
     sh, sw = int(rgba.shape[0]), int(rgba.shape[1])
     dw = sw if dst_width is None else int(dst_width)
     dh = sh if dst_height is None else int(dst_height)
@@ -375,8 +381,9 @@ def warp(ctx, rgba: torch.Tensor, depth: torch.Tensor, src_camera, dst_camera, d
         out_source = torch.empty((dh, dw), dtype=torch.int32, device="cuda")
     dptr = None if out_depth is None else _dptr(out_depth, torch.float32, dw * dh, "out_depth")
     sptr = None if out_source is None else _dptr(out_source, torch.int32, dw * dh, "out_source")
-    _check(_warp(ctx, ctypes.byref(Camera.make(src_camera)), sw, sh, rgba.data_ptr(), depth.data_ptr(),
-                 ctypes.byref(Camera.make(dst_camera)), dw, dh, out.data_ptr(), dptr, sptr, _stream(stream)))
+    fn = _warp_noalloc if noalloc else _warp
+    _check(fn(ctx, ctypes.byref(Camera.make(src_camera)), sw, sh, rgba.data_ptr(), depth.data_ptr(),
+              ctypes.byref(Camera.make(dst_camera)), dw, dh, out.data_ptr(), dptr, sptr, _stream(stream)))
     return out, out_depth, out_source
 
 
