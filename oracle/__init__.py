@@ -28,6 +28,8 @@ FRAGILE_COUNT = 8
 FRAGILE_TFZERO = 16
 # bits whose decision can move RGBA by more than rounding; bit 3 only moves counts
 FRAGILE_RGBA = FRAGILE_BRUSH | FRAGILE_ERT | FRAGILE_GRAZE | FRAGILE_TFZERO
+# decisions whose two outcomes OracleImage.outcomes enumerates
+FRAGILE_FLIPPABLE = FRAGILE_BRUSH | FRAGILE_ERT
 
 
 def lib():
@@ -45,6 +47,12 @@ def lib():
             P, P, P, P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, ctypes.c_double,
             ctypes.c_double, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_long,
             P, P, P, P, P, P, P, P, ctypes.c_int]
+        L.oracle_outcomes.restype = ctypes.c_int
+        L.oracle_outcomes.argtypes = [
+            ctypes.c_int, ctypes.c_int, P, ctypes.c_double, ctypes.c_double,
+            P, P, P, P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, ctypes.c_double,
+            ctypes.c_double, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_long,
+            P, P, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int]
         L.oracle_trilinear.restype = None
         L.oracle_trilinear.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P]
         _lib = L
@@ -56,6 +64,19 @@ def _ptr(a: Optional[np.ndarray]):
 
 
 @dataclass
+class Outcomes:
+    """Legitimate results of some pixels whose flippable decisions (fragile bits 0 and 1) may go
+    either way: for pixel k, count[k] outcomes (-1: more than the limit), outcome 0 being the
+    double-precision result; rgba [k, o, 4], nominal / composited / depth / flips [k, o]."""
+    count: np.ndarray
+    rgba: np.ndarray
+    nominal: np.ndarray
+    composited: np.ndarray
+    depth: np.ndarray
+    flips: np.ndarray
+
+
+@dataclass
 class OracleImage:
     rgba: np.ndarray        # float64 [npix, 4] (or [H, W, 4] for full frames)
     nominal: np.ndarray     # uint32
@@ -63,6 +84,30 @@ class OracleImage:
     fragile: np.ndarray     # uint8 bit mask
     pathlen: np.ndarray     # float64
     depth: np.ndarray       # float64 opacity-weighted mean sample distance (+inf: nothing composited)
+    _call: Optional[tuple] = None  # the render's prepared arguments (for outcomes)
+
+    def outcomes(self, index: np.ndarray, max_flips: int = 8, max_out: int = 256,
+                 threads: Optional[int] = None) -> Outcomes:
+        """Every outcome of the pixels at positions `index` of this image's (flattened) pixel list
+        with at most `max_flips` flippable decisions taken the other way."""
+        args, pix, jit, width = self._call
+        index = np.asarray(index, np.int64).reshape(-1)
+        lin = np.ascontiguousarray(index if pix is None else pix[index])
+        j = None if jit is None else np.ascontiguousarray(jit[index])
+        k = lin.size
+        count = np.zeros(k, np.int32)
+        rgba = np.zeros((k, max_out, 4))
+        nom = np.zeros((k, max_out), np.uint32)
+        comp = np.zeros((k, max_out), np.uint32)
+        dep = np.zeros((k, max_out))
+        fl = np.zeros((k, max_out), np.uint8)
+        if k:
+            rc = lib().oracle_outcomes(*args, int(k), _ptr(lin), _ptr(j), int(max_flips), int(max_out), _ptr(count),
+                                       _ptr(rgba), _ptr(nom), _ptr(comp), _ptr(dep), _ptr(fl),
+                                       int(threads or os.cpu_count() or 1))
+            if rc != 0:
+                raise ValueError("oracle_outcomes: invalid arguments")
+        return Outcomes(count, rgba, nom, comp, dep, fl)
 
 
 def render(level_fields: np.ndarray, camera, width: int, height: int, step: float, *,
@@ -104,19 +149,25 @@ def render(level_fields: np.ndarray, camera, width: int, height: int, step: floa
     plen = np.zeros(npix)
     dep = np.zeros(npix)
     threads = threads or os.cpu_count() or 1
-    rc = lib().oracle_render(
-        nf, n, ctypes.cast(ptrs, ctypes.c_void_p), float(np.float32(r_inner)), float(np.float32(r_outer)),
-        _ptr(act), _ptr(lo64), _ptr(hi64), _ptr(cact), _ptr(clo), _ptr(chi), int(tf_field), float(np.float32(vmin)), float(np.float32(vmax)),
-        _ptr(tf64), float(np.float32(ref_step)), float(np.float32(ert)), _ptr(bg64), _ptr(cam),
-        int(width), int(height), float(np.float32(step)), int(npix), _ptr(pix), _ptr(jit),
-        _ptr(rgba), _ptr(nom), _ptr(comp), _ptr(frag), _ptr(plen), _ptr(dep), int(threads))
+    args = (nf, n, ctypes.cast(ptrs, ctypes.c_void_p), float(np.float32(r_inner)), float(np.float32(r_outer)),
+            _ptr(act), _ptr(lo64), _ptr(hi64), _ptr(cact), _ptr(clo), _ptr(chi), int(tf_field),
+            float(np.float32(vmin)), float(np.float32(vmax)), _ptr(tf64), float(np.float32(ref_step)),
+            float(np.float32(ert)), _ptr(bg64), _ptr(cam), int(width), int(height), float(np.float32(step)))
+    rc = lib().oracle_render(*args, int(npix), _ptr(pix), _ptr(jit),
+                             _ptr(rgba), _ptr(nom), _ptr(comp), _ptr(frag), _ptr(plen), _ptr(dep), int(threads))
     if rc != 0:
         raise ValueError("oracle_render: invalid arguments")
+    # keep the arrays the pointers in `args` refer to alive with the image
+    call = (args, pix, jit, width)
+    call_refs = (lf, ptrs, act, lo64, hi64, tf64, cam, bg64, cact, clo, chi)
     if full:
-        return OracleImage(rgba.reshape(height, width, 4), nom.reshape(height, width),
-                           comp.reshape(height, width), frag.reshape(height, width),
-                           plen.reshape(height, width), dep.reshape(height, width))
-    return OracleImage(rgba, nom, comp, frag, plen, dep)
+        img = OracleImage(rgba.reshape(height, width, 4), nom.reshape(height, width),
+                          comp.reshape(height, width), frag.reshape(height, width),
+                          plen.reshape(height, width), dep.reshape(height, width), call)
+    else:
+        img = OracleImage(rgba, nom, comp, frag, plen, dep, call)
+    img._refs = call_refs
+    return img
 
 
 def trilinear(field: np.ndarray, u_xyz: np.ndarray) -> np.ndarray:

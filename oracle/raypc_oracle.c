@@ -43,6 +43,12 @@
  *          only),
  *   bit 4  a table lookup within 0.05 entries of a zero / non-zero opacity
  *          boundary.
+ * Bits 0 and 1 are decisions with two legitimate outcomes each: oracle_outcomes
+ * renders a pixel again with any of them (up to a limit) taken the other way, so
+ * that a renderer's result on such a pixel can be checked against the set of
+ * results the definition admits there (reading of the paper's Section 2.2: a
+ * sample either passes the brush and is composited or is discarded; a float32
+ * renderer may decide a sample within floating-point reach of a bound either way).
  * Grazing reach: a renderer working in float32 (unit roundoff u = 2^-24) finds
  * a sphere hit from the closest-approach discriminant r^2 - |p|^2, p = o - (o.d) d,
  * which cancels for rays that nearly graze the sphere: a few ulps of error in p
@@ -162,6 +168,22 @@ typedef struct {
     double depth; /* opacity-weighted mean distance of the composited samples; +inf if none */
 } pixel_result;
 
+/* Flippable decisions (fragile bits 0 and 1) met while rendering a pixel, in the order met:
+ * decision i is taken the other way when i < n_forced and forced[i] is set.  NULL: every
+ * decision as the double-precision arithmetic takes it. */
+typedef struct {
+    const uint8_t *forced;
+    int n_forced;
+    int seen; /* decisions met so far */
+} decisions;
+
+static int decide(decisions *dc, int outcome)
+{
+    if (!dc) return outcome;
+    int i = dc->seen++;
+    return (i < dc->n_forced && dc->forced[i]) ? !outcome : outcome;
+}
+
 /* Float32 reach of a root of the sphere of radius rho with discriminant disc (see the header). */
 static double graze_reach(double o_norm, double rho, double disc)
 {
@@ -171,7 +193,7 @@ static double graze_reach(double o_norm, double rho, double disc)
 /* `jit` is the pixel's sample-grid offset s in [0, 1) (in steps): samples of a segment [a, b] are
  * the pieces of [a, b] cut at g + j ds (g = a - s ds), each evaluated at its midpoint; s = 0 gives
  * the regular partition. */
-static void render_pixel(const oracle_params *P, int px, int py, double jit, pixel_result *res)
+static void render_pixel(const oracle_params *P, int px, int py, double jit, pixel_result *res, decisions *dc)
 {
     memset(res, 0, sizeof(*res));
     /* ray through the pixel centre; row 0 is the top row */
@@ -293,7 +315,10 @@ static void render_pixel(const oracle_params *P, int px, int py, double jit, pix
                         robust_fail = 1;
                 }
             }
-            if (near && !robust_fail) res->fragile |= 1;
+            if (near && !robust_fail) {
+                res->fragile |= 1;
+                pass = decide(dc, pass);
+            }
             if (!pass) continue; /* discarded: counted, not composited */
 
             if (!have_tf) tf_value = trilinear(P->fields[P->tf_field], n, u[0], u[1], u[2], NULL);
@@ -325,8 +350,12 @@ static void render_pixel(const oracle_params *P, int px, int py, double jit, pix
             D += (1.0 - A) * alpha * tm;
             A += (1.0 - A) * alpha;
             if (P->ert < 1.0) {
-                if (fabs(A - P->ert) <= 1e-4) res->fragile |= 2;
-                if (A >= P->ert) done = 1;
+                int stop = A >= P->ert;
+                if (fabs(A - P->ert) <= 1e-4) {
+                    res->fragile |= 2;
+                    stop = decide(dc, stop);
+                }
+                if (stop) done = 1;
             }
         }
     }
@@ -341,6 +370,61 @@ static void render_pixel(const oracle_params *P, int px, int py, double jit, pix
     res->rgba[1] = C[1];
     res->rgba[2] = C[2];
     res->rgba[3] = A;
+}
+
+/* Fill the parameters of a render; -1 on invalid arguments. */
+static int setup(oracle_params *P, int n_fields, int n, const float *const *fields, double r_inner, double r_outer,
+                 const uint8_t *active, const double *lo, const double *hi, const uint8_t *coord_active,
+                 const double *coord_lo, const double *coord_hi, int tf_field, double vmin, double vmax,
+                 const double *tf_rgba, double ref_step, double ert, const double *bg, const double *camera,
+                 int width, int height, double step_vox)
+{
+    if (n_fields < 1 || n_fields > ORACLE_MAX_FIELDS || n < 2 || width < 1 || height < 1 ||
+        tf_field < 0 || tf_field >= n_fields || !(vmax > vmin) || !(step_vox > 0) || !(ref_step > 0))
+        return -1;
+    memset(P, 0, sizeof(*P));
+    P->n_fields = n_fields;
+    P->n = n;
+    P->fields = fields;
+    for (int f = 0; f < n_fields; ++f) {
+        double m = 0.0;
+        size_t cnt = (size_t)n * n * n;
+        for (size_t i = 0; i < cnt; ++i)
+            if (fabs((double)fields[f][i]) > m) m = fabs((double)fields[f][i]);
+        P->maxabs[f] = m;
+    }
+    P->r_inner = r_inner;
+    P->r_outer = r_outer;
+    P->active = active;
+    P->lo = lo;
+    P->hi = hi;
+    P->coord_active = coord_active;
+    P->coord_lo = coord_lo;
+    P->coord_hi = coord_hi;
+    P->tf_field = tf_field;
+    P->vmin = vmin;
+    P->vmax = vmax;
+    P->tf = tf_rgba;
+    P->ref_step = ref_step;
+    P->ert = ert;
+    P->bg = bg;
+    P->width = width;
+    P->height = height;
+    P->step_vox = step_vox;
+    double up[3];
+    for (int k = 0; k < 3; ++k) {
+        P->eye[k] = camera[k];
+        P->fwd[k] = camera[3 + k] - camera[k];
+        up[k] = camera[6 + k];
+    }
+    normalize3(P->fwd);
+    cross3(P->fwd, up, P->right);
+    normalize3(P->right);
+    cross3(P->right, P->fwd, P->upv);
+    P->tan_half = tan(0.5 * camera[9] * M_PI / 180.0);
+    P->aspect = (double)width / (double)height;
+
+    return 0;
 }
 
 /*
@@ -363,58 +447,17 @@ int oracle_render(int n_fields, int n, const float *const *fields, double r_inne
                   const int64_t *pix, const double *jitter, double *rgba, uint32_t *nominal,
                   uint32_t *composited, uint8_t *fragile, double *pathlen, double *depth, int n_threads)
 {
-    if (n_fields < 1 || n_fields > ORACLE_MAX_FIELDS || n < 2 || width < 1 || height < 1 ||
-        tf_field < 0 || tf_field >= n_fields || !(vmax > vmin) || !(step_vox > 0) || !(ref_step > 0))
-        return -1;
     oracle_params P;
-    memset(&P, 0, sizeof(P));
-    P.n_fields = n_fields;
-    P.n = n;
-    P.fields = fields;
-    for (int f = 0; f < n_fields; ++f) {
-        double m = 0.0;
-        size_t cnt = (size_t)n * n * n;
-        for (size_t i = 0; i < cnt; ++i)
-            if (fabs((double)fields[f][i]) > m) m = fabs((double)fields[f][i]);
-        P.maxabs[f] = m;
-    }
-    P.r_inner = r_inner;
-    P.r_outer = r_outer;
-    P.active = active;
-    P.lo = lo;
-    P.hi = hi;
-    P.coord_active = coord_active;
-    P.coord_lo = coord_lo;
-    P.coord_hi = coord_hi;
-    P.tf_field = tf_field;
-    P.vmin = vmin;
-    P.vmax = vmax;
-    P.tf = tf_rgba;
-    P.ref_step = ref_step;
-    P.ert = ert;
-    P.bg = bg;
-    P.width = width;
-    P.height = height;
-    P.step_vox = step_vox;
-    double up[3];
-    for (int k = 0; k < 3; ++k) {
-        P.eye[k] = camera[k];
-        P.fwd[k] = camera[3 + k] - camera[k];
-        up[k] = camera[6 + k];
-    }
-    normalize3(P.fwd);
-    cross3(P.fwd, up, P.right);
-    normalize3(P.right);
-    cross3(P.right, P.fwd, P.upv);
-    P.tan_half = tan(0.5 * camera[9] * M_PI / 180.0);
-    P.aspect = (double)width / (double)height;
+    if (setup(&P, n_fields, n, fields, r_inner, r_outer, active, lo, hi, coord_active, coord_lo, coord_hi, tf_field,
+              vmin, vmax, tf_rgba, ref_step, ert, bg, camera, width, height, step_vox) != 0)
+        return -1;
 
     long total = pix ? n_pix : (long)width * height;
 #pragma omp parallel for schedule(dynamic, 64) num_threads(n_threads > 0 ? n_threads : 1)
     for (long k = 0; k < total; ++k) {
         long lin = pix ? (long)pix[k] : k;
         pixel_result r;
-        render_pixel(&P, (int)(lin % width), (int)(lin / width), jitter ? jitter[k] : 0.0, &r);
+        render_pixel(&P, (int)(lin % width), (int)(lin / width), jitter ? jitter[k] : 0.0, &r, NULL);
         if (rgba)
             for (int c = 0; c < 4; ++c) rgba[4 * k + c] = r.rgba[c];
         if (nominal) nominal[k] = r.nominal;
@@ -422,6 +465,98 @@ int oracle_render(int n_fields, int n, const float *const *fields, double r_inne
         if (fragile) fragile[k] = r.fragile;
         if (pathlen) pathlen[k] = r.pathlen;
         if (depth) depth[k] = r.depth;
+    }
+    return 0;
+}
+
+/*
+ * Outcomes of near-threshold decisions.  A pixel's flippable decisions (fragile
+ * bits 0 and 1) each admit two results; the pixel's legitimate results are the
+ * renders with any set of them taken the other way.  They are enumerated depth
+ * first: a render that follows `choice` for its first `len` decisions (the rest
+ * as double precision takes them) is one outcome, and its children take one more
+ * decision i >= len the other way, the decisions between len and i as double
+ * precision takes them; every set of flipped decisions is met exactly once.  At
+ * most `max_flips` decisions are flipped on one path, and at most `max_out`
+ * outcomes are kept.
+ */
+#define ORACLE_MAX_DECISIONS 8192
+
+typedef struct {
+    const oracle_params *P;
+    int px, py;
+    double jit;
+    int max_flips, max_out;
+    uint8_t *choice;
+    pixel_result *outs;
+    uint8_t *flips;
+    int n_out;
+} explore_state;
+
+static int explore(explore_state *E, int len, int flips)
+{
+    if (E->n_out >= E->max_out) return -1;
+    decisions dc = {E->choice, len, 0};
+    render_pixel(E->P, E->px, E->py, E->jit, &E->outs[E->n_out], &dc);
+    E->flips[E->n_out] = (uint8_t)flips;
+    E->n_out++;
+    if (flips >= E->max_flips) return 0;
+    for (int i = len; i < dc.seen; ++i) {
+        if (i >= ORACLE_MAX_DECISIONS) return -1;
+        memset(E->choice + len, 0, (size_t)(i - len));
+        E->choice[i] = 1;
+        if (explore(E, i + 1, flips + 1) != 0) return -1;
+    }
+    return 0;
+}
+
+/*
+ * oracle_outcomes: for each listed pixel (linear index py*width + px, with its
+ * jitter offset or NULL), every outcome with at most `max_flips` of its
+ * flippable decisions taken the other way: n_outcomes[k] outcomes (the first is
+ * the double-precision result itself), or -1 when there are more than `max_out`
+ * or a path meets more than 8192 decisions.  Outcome o of pixel k is at
+ * rgba[(k max_out + o) 4 ...], nominal / composited / depth / flips[k max_out + o]
+ * (flips: how many decisions that outcome takes the other way).  Other
+ * arguments as oracle_render.  Returns 0, or -1 on invalid arguments.
+ */
+int oracle_outcomes(int n_fields, int n, const float *const *fields, double r_inner, double r_outer,
+                    const uint8_t *active, const double *lo, const double *hi, const uint8_t *coord_active,
+                    const double *coord_lo, const double *coord_hi, int tf_field, double vmin, double vmax,
+                    const double *tf_rgba, double ref_step, double ert, const double *bg, const double *camera,
+                    int width, int height, double step_vox, long n_pix, const int64_t *pix, const double *jitter,
+                    int max_flips, int max_out, int32_t *n_outcomes, double *rgba, uint32_t *nominal,
+                    uint32_t *composited, double *depth, uint8_t *flips, int n_threads)
+{
+    oracle_params P;
+    if (!pix || max_out < 1 || max_flips < 0 ||
+        setup(&P, n_fields, n, fields, r_inner, r_outer, active, lo, hi, coord_active, coord_lo, coord_hi, tf_field,
+              vmin, vmax, tf_rgba, ref_step, ert, bg, camera, width, height, step_vox) != 0)
+        return -1;
+#pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
+    {
+        uint8_t *choice = (uint8_t *)calloc(ORACLE_MAX_DECISIONS, 1);
+        pixel_result *outs = (pixel_result *)malloc(sizeof(pixel_result) * (size_t)max_out);
+        uint8_t *fl = (uint8_t *)malloc((size_t)max_out);
+#pragma omp for schedule(dynamic, 1)
+        for (long k = 0; k < n_pix; ++k) {
+            long lin = (long)pix[k];
+            explore_state E = {&P, (int)(lin % width), (int)(lin / width), jitter ? jitter[k] : 0.0,
+                               max_flips, max_out, choice, outs, fl, 0};
+            int ok = choice && outs && fl && explore(&E, 0, 0) == 0;
+            n_outcomes[k] = ok ? E.n_out : -1;
+            for (int o = 0; ok && o < E.n_out; ++o) {
+                size_t at = (size_t)k * max_out + o;
+                for (int c = 0; c < 4; ++c) rgba[4 * at + c] = outs[o].rgba[c];
+                nominal[at] = outs[o].nominal;
+                composited[at] = outs[o].composited;
+                depth[at] = outs[o].depth;
+                flips[at] = fl[o];
+            }
+        }
+        free(choice);
+        free(outs);
+        free(fl);
     }
     return 0;
 }

@@ -460,6 +460,11 @@ def test_precision_512_full_size_sampled(rp, ctx, c2):
         rp.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
         rp.set_options(ctx, wl.ert)
         rgba, nom, comp = gpu_render(rp, ctx, vid, wl, 0)
+        # the kernel that is timed and served (one-wave blocks, 32-bit record offsets, no counts) gives
+        # the counting variant's image bit for bit, at the level the selection rule picks too
+        for lod in (0, -1):
+            plain = cpu(rp.render(ctx, vid, wl.camera.as_array(), wl.width, wl.height, lod, wl.step))
+            assert np.array_equal(plain.view(np.uint32), rgba.view(np.uint32)), (storage, lod)
         level = np.stack([rp_level for rp_level in
                           (cpu(rp.export_level(ctx, vid, 0, f)) for f in range(wl.n_fields))])
         want_level = np.stack([pp.stored_values(wl.fields[f], storage) for f in range(wl.n_fields)])
@@ -469,8 +474,118 @@ def test_precision_512_full_size_sampled(rp, ctx, c2):
         # the depth that image warping reprojects with, from the same frame
         rgba_d, dep = rp.render_depth(ctx, vid, wl.camera.as_array(), wl.width, wl.height, 0, wl.step)
         assert np.array_equal(cpu(rgba_d), rgba)
-        check_depth(cpu(dep).reshape(-1)[pix], ref, label=f"c2 {storage} depth", min_frac=0.02)
+        check_depth(cpu(dep).reshape(-1)[pix], ref, label=f"c2 {storage} depth", min_frac=0.02,
+                    gpu_rgba=rgba.reshape(-1, 4)[pix])
         rp.unload(ctx, vid)
+
+
+def test_served_requests_match_oracle(rp, ctx, c2):
+    """Serving at full size: requests of the serving trace (the 256^3 and 512^3 x 5 binary16 volumes
+    resident, images up to 2048^2, orbit cameras, 1-5-axis quantile brushes, level by the selection
+    rule) submitted together, so that they share batched launches, each checked against the oracle
+    on sampled pixels of the level the rule picks, and equal to its single render bit for bit."""
+    wl512 = c2
+    wl256 = W.make_workload(1)
+    rng = np.random.default_rng(3)
+    tables = [W.quantile_table(wl256.fields, W.shell_mask(W.radius(256)), rng),
+              W.quantile_table(wl512.fields, W.shell_mask(W.radius(512)), rng)]
+    trace = W.serving_trace(tables, n=40)
+    # twelve requests covering both volumes and every image size
+    chosen, seen = [], set()
+    for i, q in enumerate(trace):
+        key = (q.volume, (q.width, q.height))
+        if key not in seen or len(chosen) < 6:
+            seen.add(key)
+            chosen.append(i)
+        if len(chosen) == 12:
+            break
+    wls = [wl256, wl512]
+    tf = wl512.tf
+    rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, tf.rgba, tf.ref_step)
+    rp.set_options(ctx, wl512.ert)
+    vols = [rp.load_fields(ctx, torch.from_numpy(w.fields).cuda(), "f16", 3) for w in wls]
+    levels = [pp.stored_levels(w.fields, 3, "f16") for w in wls]
+    outs = [torch.full((trace[i].height, trace[i].width, 4), -1.0, dtype=torch.float32, device="cuda") for i in chosen]
+    rp.server_start(ctx, 8 << 30, 64, 32768, 2)
+    try:
+        tickets = [rp.submit(ctx, rp.make_request(vols[trace[i].volume], trace[i].camera, trace[i].width,
+                                                  trace[i].height, o, -1, 0.5, trace[i].active, trace[i].lo,
+                                                  trace[i].hi, 0))
+                   for i, o in zip(chosen, outs)]
+        for t in tickets:
+            rp.wait(ctx, t, 120000)
+            rp.release(ctx, t)
+    finally:
+        rp.server_stop(ctx)
+    try:
+        for i, o in zip(chosen, outs):
+            q = trace[i]
+            w = wls[q.volume]
+            cam = q.camera.as_array()
+            lod = pp.select_lod(w.n, 3, cam[:3], float(cam[9]), q.height)
+            assert rp.select_lod(ctx, vols[q.volume], cam, q.width, q.height) == lod
+            label = f"served #{i} {w.n}^3 {q.width}x{q.height} lod {lod} k={int(q.active.sum())}"
+            print(f"[case] {label}", flush=True)
+            served = cpu(o)
+            rp.set_brush(ctx, vols[q.volume], q.active, q.lo, q.hi)
+            single = cpu(rp.render(ctx, vols[q.volume], cam, q.width, q.height, -1, 0.5))
+            assert np.array_equal(served.view(np.uint32), single.view(np.uint32)), label
+            pix = sample_pixels(q.width, q.height, 400, seed=i)
+            ref = oracle.render(levels[q.volume][lod], cam, q.width, q.height, 0.5, active=q.active, lo=q.lo,
+                                hi=q.hi, tf_field=tf.field, vmin=tf.vmin, vmax=tf.vmax, tf_rgba=tf.rgba,
+                                ref_step=tf.ref_step, ert=wl512.ert, pixels=pix)
+            compare(served.reshape(-1, 4)[pix], ref, label=label)
+    finally:
+        for v in vols:
+            rp.unload(ctx, v)
+
+
+@pytest.mark.timeout(1200)
+def test_large_progressive_1024_4k_sampled(rp, ctx, capsys):
+    """The large progressive configuration at its size: 1024^3 x 5 fields stored binary16 (level 0's
+    record fields above 4 GiB, read at 64-bit offsets), a 3840x2160 view, progressive passes at step
+    1.0 / 0.5 / 0.25 voxel for the final (~10 %) brush and for a brush half-way along the narrowing
+    sequence; the first and final passes checked against the oracle on 1 000 sampled pixels, with
+    exact counts where the counting variant is asked."""
+    import time
+    t0 = time.perf_counter()
+
+    def say(msg):
+        with capsys.disabled():
+            print(f"[c4] {msg} ({time.perf_counter() - t0:.0f}s)", flush=True)
+
+    wl = W.make_workload(4, progress=lambda m: say(f"generated {m}"))
+    mask = W.shell_mask(W.radius(wl.n))
+    brushes = W.narrowing_brushes(wl.fields, mask, np.random.default_rng(W.SEED_BASE + 4), wl.brush)
+    del mask
+    rp.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
+    rp.set_options(ctx, wl.ert)
+    vid = rp.load_fields(ctx, torch.from_numpy(wl.fields).cuda(), "f16", 3, wl.r_inner, wl.r_outer)
+    torch.cuda.synchronize()
+    say("loaded f16 with records")
+    level = np.stack([pp.stored_values(wl.fields[f], "f16") for f in range(wl.n_fields)])
+    say("oracle level 0 stored values")
+    cam = wl.camera.as_array()
+    assert rp.select_lod(ctx, vid, cam, wl.width, wl.height) == 0
+    pix = sample_pixels(wl.width, wl.height, 1000, seed=44)
+    try:
+        for b in (brushes[5], brushes[-1]):
+            rp.set_brush(ctx, vid, b.active, b.lo, b.hi)
+            passes = rp.render_progressive(ctx, vid, cam, wl.width, wl.height, -1, wl.step, 3)
+            passes = [cpu(p) for p in passes]
+            for k, st in ((0, wl.step * 4), (2, wl.step)):
+                label = f"c4 f16 pass {k} step {st} brush lo {b.lo[0]:.3g}"
+                ref = oracle.render_workload(wl, level, pixels=pix, step=st, active=b.active, lo=b.lo, hi=b.hi)
+                say(f"oracle {label}")
+                if k == 2 and b is brushes[-1]:
+                    rgba, nom, comp = gpu_render(rp, ctx, vid, wl, 0, step=st)
+                    assert np.array_equal(rgba.view(np.uint32), passes[k].view(np.uint32)), label
+                    compare(rgba.reshape(-1, 4)[pix], ref, nom.reshape(-1)[pix], comp.reshape(-1)[pix], label=label)
+                else:
+                    compare(passes[k].reshape(-1, 4)[pix], ref, label=label)
+    finally:
+        rp.unload(ctx, vid)
+
 
 
 def test_jitter_and_coordinates_512_full_size_sampled(rp, ctx, c2):

@@ -65,7 +65,7 @@ def test_render_depth_matches_oracle(rp, ctx, storage):
         assert np.array_equal(cpu(rgba), cpu(plain)), label
         ref = oracle.render_workload(wl, levels[lod], active=act, step=step)
         compare(cpu(rgba), ref, label=label)
-        check_depth(cpu(dep), ref, label)
+        check_depth(cpu(dep), ref, label, gpu_rgba=cpu(rgba))
     with pytest.raises(rp.RaypcError):
         rp._check(rp._render_depth(ctx, vid, rp.ctypes.byref(rp.Camera.make(c)), 8, 8, 0, 0.5,
                                    rgba.data_ptr(), None, None))
