@@ -1,12 +1,13 @@
 """Shared helpers for the GPU parity tests (HIP path vs FP64 oracle).
 
 Every pixel is checked.  A pixel whose decisions all lie beyond floating-point reach of their
-thresholds has one legitimate result, the oracle's.  A pixel with brush or termination decisions
-within that reach (fragile bits 0 and 1) has several: the oracle enumerates them (every set of
-those decisions taken the other way, OracleImage.outcomes) and the GPU's result must equal one of
-them.  Only pixels with a ray grazing a sphere or a table lookup at a zero / non-zero opacity
-boundary (bits 2 and 4), or with too many flippable decisions to enumerate, stay unchecked, and
-their share is bounded by FRAGILE_MAX.
+thresholds has one legitimate result, the oracle's.  A pixel with decisions within that reach has
+several, the oracle's among them: the GPU's result either equals the oracle's, or, for brush and
+termination decisions (fragile bits 0 and 1), one of the others, which the oracle enumerates
+(every set of those decisions taken the other way, OracleImage.outcomes).  Only a pixel that
+differs from the oracle's result and whose other results cannot be enumerated (a ray grazing a
+sphere or a table lookup at a zero / non-zero opacity boundary, bits 2 and 4, or too many
+decisions) stays unchecked, and their share is bounded by FRAGILE_MAX.
 """
 from __future__ import annotations
 
@@ -35,47 +36,52 @@ def compare(gpu_rgba: np.ndarray, ref: oracle.OracleImage, gpu_nominal=None, gpu
     gc = None if gpu_composited is None else np.asarray(gpu_composited).reshape(-1).astype(np.int64)
 
     single = (ff & oracle.FRAGILE_RGBA) == 0            # one legitimate result
-    multi = ((ff & oracle.FRAGILE_FLIPPABLE) != 0) & ((ff & UNCHECKED) == 0)
-    unchecked = (ff & UNCHECKED) != 0
     err = np.abs(gf - rf).max(axis=-1)
     worst = float(err[single].max()) if single.any() else 0.0
-    stats = {"label": label, "pixels": int(npix), "multi_outcome": float(multi.mean()),
+    stats = {"label": label, "pixels": int(npix), "multi_outcome": float((~single).mean()),
              "max_abs_err": worst, "max_abs_err_all": float(err.max()),
              "mean_abs_err": float(err[single].mean()) if single.any() else 0.0}
     assert worst <= tol, f"{label}: max abs RGBA error {worst:.3e} > {tol:.1e} on single-outcome pixels"
-    cnt_ok = ff == 0                                      # counts are defined up to bit 3 as well
+    # the oracle's own (double-precision) result, counts included where they are defined (bit 3
+    # clear) and given
+    same = err <= tol
+    cnt_defined = (ff & oracle.FRAGILE_COUNT) == 0
     if gn is not None:
-        bad = (gn != ref.nominal.reshape(-1).astype(np.int64)) & single & cnt_ok
-        stats["nominal_mismatch"] = int(bad.sum())
-        assert not bad.any(), f"{label}: nominal counts differ on {int(bad.sum())} single-outcome pixels"
+        same &= (gn == ref.nominal.reshape(-1).astype(np.int64)) | ~cnt_defined
     if gc is not None:
-        bad = (gc != ref.composited.reshape(-1).astype(np.int64)) & single & cnt_ok
-        assert not bad.any(), f"{label}: composited counts differ on {int(bad.sum())} single-outcome pixels"
+        same &= (gc == ref.composited.reshape(-1).astype(np.int64)) | ~cnt_defined
+    bad = single & ~same
+    stats["count_mismatch"] = int(bad.sum())
+    assert not bad.any(), f"{label}: counts differ on {int(bad.sum())} single-outcome pixels"
 
-    # pixels with several legitimate results: the GPU's must be one of them
+    # pixels with several legitimate results whose GPU result is not the oracle's own: it must be
+    # one of the others (enumerated where the decisions are brush or termination tests)
     matched = rf.copy()               # the legitimate result each pixel's GPU result matched
-    matched[unchecked] = np.nan
-    idx = np.nonzero(multi)[0]
+    others = ~single & ~same
+    flippable = others & ((ff & oracle.FRAGILE_FLIPPABLE) != 0) & ((ff & UNCHECKED) == 0)
+    unchecked = others & ~flippable
+    idx = np.nonzero(flippable)[0]
     alt_taken = 0
     if idx.size:
         out = ref.outcomes(idx)
-        unresolved = out.count < 0
-        unchecked[idx[unresolved]] = True
-        matched[idx[unresolved]] = np.nan
-        for k in np.nonzero(~unresolved)[0]:
+        for k in range(idx.size):
             p = idx[k]
             m = int(out.count[k])
+            if m < 0:
+                unchecked[p] = True
+                continue
             e = np.abs(out.rgba[k, :m] - gf[p]).max(axis=-1)
             ok = e <= tol
-            if ff[p] & oracle.FRAGILE_COUNT == 0:
+            if cnt_defined[p]:
                 if gn is not None:
                     ok &= out.nominal[k, :m].astype(np.int64) == gn[p]
                 if gc is not None:
                     ok &= out.composited[k, :m].astype(np.int64) == gc[p]
             assert ok.any(), (f"{label}: pixel {p} matches none of its {m} legitimate outcomes "
                               f"(least RGBA error {e.min():.3e})")
-            alt_taken += int(not ok[0])
+            alt_taken += 1
             matched[p] = out.rgba[k, int(np.argmax(ok))]
+    matched[unchecked] = np.nan
     stats["alternative_taken"] = alt_taken / npix
     stats["unchecked"] = float(unchecked.mean())
     print(f"[parity] {stats}", flush=True)
@@ -104,8 +110,8 @@ def check_depth(gpu_depth, ref: oracle.OracleImage, label: str = "", min_frac: f
                 gpu_rgba=None) -> None:
     """GPU opacity-weighted depth against the oracle's: defined (finite) on the same pixels, and
     within depth_tolerance of the oracle's opacity there.  Single-outcome pixels use the oracle's
-    result; with `gpu_rgba`, pixels with several legitimate results use the outcome whose RGBA the
-    GPU's matches."""
+    result; with `gpu_rgba`, pixels with several legitimate results use the one whose RGBA the GPU's
+    matches (the oracle's own, else an enumerated outcome)."""
     g = np.asarray(gpu_depth, np.float64).reshape(-1)
     frag = ref.fragile.reshape(-1)
     ok = (frag & oracle.FRAGILE_RGBA) == 0
@@ -113,7 +119,9 @@ def check_depth(gpu_depth, ref: oracle.OracleImage, label: str = "", min_frac: f
     ref_alpha = ref.rgba.reshape(-1, 4)[:, 3].copy()
     if gpu_rgba is not None:
         gr = np.asarray(gpu_rgba, np.float64).reshape(-1, 4)
-        idx = np.nonzero(((frag & oracle.FRAGILE_FLIPPABLE) != 0) & ((frag & UNCHECKED) == 0))[0]
+        same = np.abs(gr - ref.rgba.reshape(-1, 4)).max(axis=-1) <= RGBA_TOL
+        ok |= same
+        idx = np.nonzero(~ok & ((frag & oracle.FRAGILE_FLIPPABLE) != 0) & ((frag & UNCHECKED) == 0))[0]
         if idx.size:
             out = ref.outcomes(idx)
             for k in np.nonzero(out.count > 0)[0]:
