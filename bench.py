@@ -35,23 +35,35 @@ IMAGE_BYTES_PER_PIXEL = 16
 
 
 N_NEEDED_DEFAULT = 5  # fields read per sample in the headline workload (5 brushed, TF field among them)
-TRAFFIC_RECORD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                              "raymarch_f16_512x5_1080p_traffic.json")
+# FP32 lane operations of the method's own work: per evaluated (not skipped) sample ~15 for its position
+# and voxel index, per interpolated field value ~22 (weights, eight corners, brush test), per sample that
+# passes the brush ~35 (table lookup, opacity correction with log2 / exp2, front-to-back update)
+OPS_PER_EVALUATED, OPS_PER_FETCH, OPS_PER_PASSED = 15, 22, 35
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+TRAFFIC_RECORD = os.path.join(PROFILES, "raymarch_f16_512x5_1080p_traffic.json")
+SERVING_TRAFFIC_RECORD = os.path.join(PROFILES, "serving_f16_saturated_traffic.json")
 
 
-def measured_traffic():
-    """HBM bytes per ray-march launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE record,
-    or None when the kernel sources changed since the counters were taken."""
+def traffic_record(path):
+    """A committed rocprofv3 counter record (HBM traffic, VALU figures), or None when the kernel
+    sources changed since the counters were taken."""
     import hashlib
     try:
-        rec = json.load(open(TRAFFIC_RECORD))
+        rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
     for f in rec["source_files"]:
         h.update(open(os.path.join(root, f), "rb").read())
-    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+    return rec if h.hexdigest() == rec["source_sha256"] else None
+
+
+def measured_traffic(path=TRAFFIC_RECORD):
+    """HBM bytes per launch (per replay for the serving record) from the committed FETCH_SIZE /
+    WRITE_SIZE record, or None when the kernel sources changed since the counters were taken."""
+    rec = traffic_record(path)
+    return None if rec is None else rec["traffic_bytes_per_launch"]
 
 
 def ordinal(k: int) -> str:
@@ -248,7 +260,7 @@ def pc_lines_timing(raypc, torch, W, ctx, vid, wl, stream, n_lines=100_000, n_bi
     return res
 
 
-def serving(args, raypc, torch, W, wl512, fields512_dev):
+def serving(args, raypc, torch, W, wl512, fields512_dev, profile_only=False):
     """Serving configuration: 256^3 and 512^3 x 5 FP16 volumes resident; a seeded trace of
     requests (sizes 256^2 .. 2048^2, orbit cameras, 1-5-axis quantile brushes, level by the
     selection rule, step 0.5) replayed with Poisson arrivals at several rates through the
@@ -269,7 +281,27 @@ def serving(args, raypc, torch, W, wl512, fields512_dev):
     reqs = [raypc.make_request(vols16[q.volume], q.camera, q.width, q.height, o, -1, 0.5, q.active, q.lo, q.hi, 0)
             for q, o in zip(trace, outs)]
     pixels = sum(q.width * q.height for q in trace)
+    # the method's own work and algorithmic bytes of every request (outside the timed region): touched
+    # bricks x fields read x 2 bytes + the image; evaluated samples, field fetches, passing samples
+    alg_bytes, alg_ops, nominal = 0, 0, 0
+    for q, o in zip(trace, [] if profile_only else outs):
+        vid = vols16[q.volume]
+        raypc.set_brush(ctx, vid, q.active, q.lo, q.hi)
+        lv = raypc.select_lod(ctx, vid, q.camera, q.width, q.height)
+        nb = (raypc.volume_info(ctx, vid)["n"] >> lv) // 8
+        touched = torch.zeros(((nb ** 3 + 31) // 32,), dtype=torch.int32, device="cuda")
+        _, nom, comp = raypc.render_debug(ctx, vid, q.camera, q.width, q.height, -1, 0.5, touched=touched)
+        _, ev_, fe_ = raypc.render_work(ctx, vid, q.camera, q.width, q.height, -1, 0.5)
+        torch.cuda.synchronize()
+        n_needed = len(set(np.flatnonzero(q.active).tolist()) | {tf.field})
+        tb = int(np.unpackbits(touched.cpu().numpy().view(np.uint8)).sum())
+        alg_bytes += tb * 512 * n_needed * 2 + q.width * q.height * IMAGE_BYTES_PER_PIXEL
+        alg_ops += (OPS_PER_EVALUATED * int(ev_.to(torch.int64).sum().item()) +
+                    OPS_PER_FETCH * int(fe_.to(torch.int64).sum().item()) +
+                    OPS_PER_PASSED * int(comp.to(torch.int64).sum().item()))
+        nominal += int(nom.to(torch.int64).sum().item())
     result = {"requests": len(trace), "pixels": pixels, "volumes": ["256^3 x 5 f16", "512^3 x 5 f16"],
+              "alg_bytes": alg_bytes, "alg_ops": alg_ops, "nominal_samples": nominal,
               "sizes": [list(s) for s in W.SERVING_SIZES], "server": {"max_inflight": 64, "tiles_per_step": 32768,
                                                                      "steps_in_flight": 2, "mem_budget_bytes": 8 << 30},
               "by_qps": {}}
@@ -278,7 +310,7 @@ def serving(args, raypc, torch, W, wl512, fields512_dev):
     for r in reqs[:8]:
         raypc.wait(ctx, raypc.submit(ctx, r), 120000)
     raypc.server_stop(ctx)
-    for qps_s in args.serving_qps.split(","):
+    for qps_s in ("inf",) if profile_only else args.serving_qps.split(","):
         qps = float(qps_s)
         raypc.server_start(ctx, 8 << 30, 64, 32768, 2)
         tickets = []
@@ -299,11 +331,26 @@ def serving(args, raypc, torch, W, wl512, fields512_dev):
         span = (times[:, 3].max() - times[:, 0].min()) / 1e3
         result["by_qps"][qps_s] = {"p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
                                    "max_ms": float(lat.max()), "requests_per_s": len(trace) / span,
-                                   "pixels_per_s": pixels / span, "steps": stats["steps"],
-                                   "peak_bytes_in_use": stats["peak_bytes_in_use"]}
+                                   "pixels_per_s": pixels / span, "samples_per_s": nominal / span,
+                                   "steps": stats["steps"], "peak_bytes_in_use": stats["peak_bytes_in_use"]}
+        if not math.isfinite(qps):
+            # the saturated replay: the serving path's own roofline (wall time of the whole replay)
+            traffic = measured_traffic(SERVING_TRAFFIC_RECORD)
+            result["roofline"] = {
+                "span_s": span,
+                "alu": {"bound": "alu", "achieved": alg_ops / span / 1e12, "peak": ALU_PEAK / 1e12,
+                        "unit": "Tlane-op/s", "frac": alg_ops / span / ALU_PEAK},
+                "hbm_algorithmic": {"achieved": alg_bytes / span / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                    "frac": alg_bytes / span / HBM_PEAK},
+                "hbm_measured": None if traffic is None else
+                {"achieved": traffic / span / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                 "frac": traffic / span / HBM_PEAK, "traffic_bytes": traffic}}
         print(f"[bench] serving qps={qps_s}: {result['by_qps'][qps_s]}", file=sys.stderr, flush=True)
     for v in vols16:
         raypc.unload(ctx, v)
+    if profile_only:
+        raypc.destroy(ctx)
+        return result
     # plain FP32 single-request path on the same GPU
     vols32 = [raypc.load_fields(ctx, f256, "f32", 3), raypc.load_fields(ctx, fields512_dev, "f32", 3)]
     lat32 = []
@@ -396,6 +443,61 @@ def progressive(args, raypc, torch, W):
     print(json.dumps(line), flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_run(args, wl, head, cam, b, frame_samples_gpu):
+    """The FP64 oracle as it stands, timed on the host: the render call only, median of 3 runs after
+    one warm-up, with the threads this process may use (OMP_NUM_THREADS, else the CPU affinity),
+    plus a one-thread figure on every 8th row and column."""
+    import oracle
+    from oracle import preprocess as pp
+    W_, H_ = wl.width, wl.height
+    level = np.stack([pp.stored_values(wl.fields[f], head) for f in range(wl.n_fields)])
+    ys, xs = np.meshgrid(np.arange(0, H_, args.cpu_stride), np.arange(0, W_, args.cpu_stride), indexing="ij")
+    pix = (ys * W_ + xs).ravel()
+    affinity = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS") or affinity)
+    kw = dict(active=b.active, lo=b.lo, hi=b.hi, tf_field=wl.tf.field, vmin=wl.tf.vmin, vmax=wl.tf.vmax,
+              tf_rgba=wl.tf.rgba, ref_step=wl.tf.ref_step, ert=wl.ert, r_inner=wl.r_inner, r_outer=wl.r_outer)
+
+    def timed(p, th, runs):
+        ts, ref = [], None
+        for k in range(runs + 1):
+            t0 = time.perf_counter()
+            ref = oracle.render(level, cam, W_, H_, wl.step, pixels=p, threads=th, **kw)
+            if k > 0:
+                ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), ts, int(ref.nominal.astype(np.int64).sum())
+
+    dt, ts, ns = timed(pix, threads, 3)
+    ys1, xs1 = np.meshgrid(np.arange(0, H_, 8), np.arange(0, W_, 8), indexing="ij")
+    pix1 = (ys1 * W_ + xs1).ravel()
+    dt1, ts1, ns1 = timed(pix1, 1, 1)
+    frame_samples = ns if args.cpu_stride == 1 else frame_samples_gpu
+    res = {"value": ns / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+           "frames_per_s": ns / dt / frame_samples,
+           "sample": (f"the whole {W_}x{H_} frame" if args.cpu_stride == 1 else
+                      f"every {ordinal(args.cpu_stride)} row and column of the {W_}x{H_} frame") +
+                     f" ({pix.size} px, {ns} nominal samples, median of 3 runs after a warm-up: "
+                     f"{', '.join(f'{t:.2f}' for t in ts)} s on {threads} threads), brush 0, "
+                     f"{head}-stored {wl.n}^3 x {wl.n_fields} level 0, FP64",
+           "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": affinity,
+                    "omp_num_threads": os.environ.get("OMP_NUM_THREADS")},
+           "single_thread": {"value": ns1 / dt1, "unit": "samples/s", "frames_per_s": ns1 / dt1 / frame_samples,
+                             "sample": f"every 8th row and column ({pix1.size} px, {ns1} nominal samples, "
+                                       f"{dt1:.1f} s on 1 thread after a warm-up)"}}
+    print(f"[bench] cpu baseline: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,6 +529,9 @@ def main():
     ap.add_argument("--profile-warps", type=int, default=0,
                     help="profiling mode: also render the frame with depth and warp it this many times to the "
                          "pose moved sideways by 0.1")
+    ap.add_argument("--profile-serving", action="store_true",
+                    help="profiling mode: replay the serving trace once, all requests at once, then copy 1 GiB "
+                         "device-to-device; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}): the renderer shards by request across "
@@ -445,6 +550,15 @@ def main():
     if args.profile_frames > 0:
         profile(args, wl, raypc, torch)
         return
+    if args.profile_serving:
+        # the saturated serving replay alone, then a known-size copy for counter scaling
+        serving(args, raypc, torch, W, wl, torch.from_numpy(wl.fields).cuda(), profile_only=True)
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] profile mode: saturated serving replay + 1 GiB copy", file=sys.stderr)
+        return
     mask = W.shell_mask(W.radius(wl.n))
     rng = np.random.default_rng(7)
     brushes = [wl.brush] + [W.upper_tail_brush(wl.fields, mask, rng, target=t) for t in (0.08, 0.12, 0.09)]
@@ -454,6 +568,12 @@ def main():
     cam = wl.camera.as_array()
     W_, H_ = wl.width, wl.height
     ctx = raypc.create(0)
+    # the device's measured ceilings (a 1 GiB copy, an FMA loop) beside the vendor's figures
+    peaks = raypc.measure_peaks(ctx)
+    peaks.update({"copy_frac_of_hbm_peak": peaks["copy_bytes_per_s"] / HBM_PEAK,
+                  "fma_frac_of_vendor_rate": peaks["fma_lane_ops_per_s"] / ALU_PEAK,
+                  "vendor": {"hbm_bytes_per_s": HBM_PEAK, "fp32_lane_ops_per_s": ALU_PEAK}})
+    print(f"[bench] measured peaks: {peaks}", file=sys.stderr, flush=True)
     fields_dev = torch.from_numpy(wl.fields).cuda()
     raypc.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
     raypc.set_options(ctx, wl.ert)
@@ -479,11 +599,19 @@ def main():
         for b in brushes:
             raypc.set_brush(ctx, vid, b.active, b.lo, b.hi)
             touched = torch.zeros(((nb ** 3 + 31) // 32,), dtype=torch.int32, device="cuda")
-            _, nom, _ = raypc.render_debug(ctx, vid, cam, W_, H_, lod, wl.step, touched=touched)
+            _, nom, comp = raypc.render_debug(ctx, vid, cam, W_, H_, lod, wl.step, touched=touched)
             torch.cuda.synchronize()
             samples.append(int(nom.to(torch.int64).sum().item()))
             tb = touched.cpu().numpy().view(np.uint32)
             touched_bricks.append(int(np.unpackbits(tb.view(np.uint8)).sum()))
+            if b is brushes[0]:
+                # the method's own work on the headline brush: samples not skipped, field values
+                # interpolated for them, samples that passed the brush
+                _, ev_, fe_ = raypc.render_work(ctx, vid, cam, W_, H_, lod, wl.step)
+                torch.cuda.synchronize()
+                work = {"evaluated_samples": int(ev_.to(torch.int64).sum().item()),
+                        "field_fetches": int(fe_.to(torch.int64).sum().item()),
+                        "passed_samples": int(comp.to(torch.int64).sum().item())}
         n_needed = len(set(np.flatnonzero(brushes[0].active).tolist()) | {wl.tf.field})
 
         # warmup
@@ -541,7 +669,11 @@ def main():
         alg_bytes = touched_bricks[0] * 512 * n_needed * bpv[storage] + W_ * H_ * IMAGE_BYTES_PER_PIXEL
         if storage.startswith("u8"):
             alg_bytes += touched_bricks[0] * 8 * n_needed
-        alg_ops = samples[0] * (50 + 22 * n_needed)
+        alg_ops = (OPS_PER_EVALUATED * work["evaluated_samples"] + OPS_PER_FETCH * work["field_fetches"] +
+                   OPS_PER_PASSED * work["passed_samples"])
+        work["ops_model"] = (f"{OPS_PER_EVALUATED} per evaluated sample + {OPS_PER_FETCH} per field fetch + "
+                             f"{OPS_PER_PASSED} per passing sample")
+        work["dense_equivalent_ops"] = samples[0] * (50 + 22 * n_needed)
         results[storage] = {
             "samples_per_s": total_samples / wall,
             "frames_per_s": args.steps / wall,
@@ -554,6 +686,7 @@ def main():
             "kernel_ms": kms,
             "alg_bytes_per_launch": alg_bytes,
             "alg_ops_per_launch": alg_ops,
+            "work": work,
             "volume_bytes": raypc.volume_info(ctx, vid)["bytes"],
             "orbit_latency_ms": {"frames": len(olat), "p50": percentile(olat, 50), "p99": percentile(olat, 99),
                                  "max": max(olat), "cameras": "seeded orbit: azimuth U[0, 360), elevation U[-60, 60] deg, "
@@ -575,13 +708,21 @@ def main():
     ksec = r["kernel_ms"] * 1e-3
     achieved_bw = r["alg_bytes_per_launch"] / ksec
     achieved_ops = r["alg_ops_per_launch"] / ksec
-    traffic = measured_traffic() if head == "f16" and (wl.n, W_, H_) == (512, 1920, 1080) else None
+    rec = traffic_record(TRAFFIC_RECORD) if head == "f16" and (wl.n, W_, H_) == (512, 1920, 1080) else None
+    traffic = None if rec is None else rec["traffic_bytes_per_launch"]
+    dense = r["work"]["dense_equivalent_ops"] / ksec
     roofline = {"bound": "alu", "kernel": f"raymarch_kernel ({head})", "achieved": achieved_ops / 1e12,
                 "peak": ALU_PEAK / 1e12, "unit": "Tlane-op/s", "frac": achieved_ops / ALU_PEAK,
                 "traffic": traffic, "kernel_ms": r["kernel_ms"],
-                "ops_per_sample": 50 + 22 * N_NEEDED_DEFAULT,
+                "work": r["work"],
+                "frac_of_measured_fma_rate": achieved_ops / peaks["fma_lane_ops_per_s"],
+                "dense_equivalent": {"achieved": dense / 1e12, "frac": dense / ALU_PEAK,
+                                     "note": "every nominal sample charged 50 + 22 x 5 lane-ops, skipped ones "
+                                             "included: not the work done"},
+                "valu_counters": None if rec is None else rec.get("valu"),
                 "hbm_algorithmic": {"achieved": achieved_bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                                    "frac": achieved_bw / HBM_PEAK},
+                                    "frac": achieved_bw / HBM_PEAK,
+                                    "frac_of_measured_copy": achieved_bw / peaks["copy_bytes_per_s"]},
                 "hbm_measured": None if traffic is None else
                 {"achieved": traffic / ksec / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                  "frac": traffic / ksec / HBM_PEAK}}
@@ -592,39 +733,7 @@ def main():
 
     cpu_baseline = None
     if not args.no_cpu_baseline:
-        import oracle
-        from oracle import preprocess as pp
-        level = np.stack([pp.stored_values(wl.fields[f], head) for f in range(wl.n_fields)])
-        ys, xs = np.meshgrid(np.arange(0, H_, args.cpu_stride), np.arange(0, W_, args.cpu_stride), indexing="ij")
-        pix = (ys * W_ + xs).ravel()
-        threads = min(len(os.sched_getaffinity(0)), 16)
-        b = brushes[0]
-        t0 = time.perf_counter()
-        ref = oracle.render(level, cam, W_, H_, wl.step, active=b.active, lo=b.lo, hi=b.hi, tf_field=wl.tf.field,
-                            vmin=wl.tf.vmin, vmax=wl.tf.vmax, tf_rgba=wl.tf.rgba, ref_step=wl.tf.ref_step,
-                            ert=wl.ert, r_inner=wl.r_inner, r_outer=wl.r_outer, pixels=pix, threads=threads)
-        dt = time.perf_counter() - t0
-        ns = int(ref.nominal.astype(np.int64).sum())
-        # one thread on every 8th row and column (a 1/64 subset of the frame)
-        ys1, xs1 = np.meshgrid(np.arange(0, H_, 8), np.arange(0, W_, 8), indexing="ij")
-        pix1 = (ys1 * W_ + xs1).ravel()
-        t1 = time.perf_counter()
-        ref1 = oracle.render(level, cam, W_, H_, wl.step, active=b.active, lo=b.lo, hi=b.hi, tf_field=wl.tf.field,
-                             vmin=wl.tf.vmin, vmax=wl.tf.vmax, tf_rgba=wl.tf.rgba, ref_step=wl.tf.ref_step,
-                             ert=wl.ert, r_inner=wl.r_inner, r_outer=wl.r_outer, pixels=pix1, threads=1)
-        dt1 = time.perf_counter() - t1
-        ns1 = int(ref1.nominal.astype(np.int64).sum())
-        # nominal samples of the whole frame (brush 0): the oracle's own count when it rendered all of it
-        frame_samples = ns if args.cpu_stride == 1 else results[head]["nominal_samples_per_frame"][0]
-        cpu_baseline = {"value": ns / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
-                        "frames_per_s": ns / dt / frame_samples,
-                        "sample": (f"the whole {W_}x{H_} frame" if args.cpu_stride == 1 else
-                                   f"every {ordinal(args.cpu_stride)} row and column of the {W_}x{H_} frame") +
-                                  f" ({pix.size} px, {ns} nominal samples, {dt:.1f} s on {threads} threads), brush 0, "
-                                  f"{head}-stored {wl.n}^3 x {wl.n_fields} level 0, FP64",
-                        "single_thread": {"value": ns1 / dt1, "unit": "samples/s", "frames_per_s": ns1 / dt1 / frame_samples,
-                                          "sample": f"every 8th row and column ({pix1.size} px, {ns1} nominal samples, "
-                                                    f"{dt1:.1f} s on 1 thread)"}}
+        cpu_baseline = cpu_baseline_run(args, wl, head, cam, brushes[0], results[head]["nominal_samples_per_frame"][0])
 
     line = {
         "metric": "brushed ray-march samples/s (FP16 fields; frames/s, p50/p99 latency and FP32/u8 alongside)",
@@ -653,6 +762,7 @@ def main():
         "jittered_passes": jit_result,
         "image_warp": warp_result,
         "cpu_baseline": cpu_baseline,
+        "peaks": peaks,
     }
     raypc.destroy(ctx)
     print(json.dumps(line), flush=True)

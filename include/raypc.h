@@ -319,6 +319,15 @@ int raypc_warp_noalloc(raypc_ctx *ctx, const raypc_camera *src_cam, int src_widt
                        const float *rgba, const float *depth, const raypc_camera *dst_cam, int dst_width,
                        int dst_height, float *rgba_out, float *depth_out, int32_t *source_out, void *stream);
 
+/* The device's measured ceilings, against which the renderer's rates are quoted (the vendor's peak
+ * figures are theoretical): *copy_bytes_per_s = bytes moved per second (reads plus writes) by a
+ * STREAM-like copy of a 1 GiB float32 array, *fma_lane_ops_per_s = FP32 fused multiply-adds per
+ * second of a loop of independent FMA chains in every lane of enough waves to fill every SIMD (one
+ * FMA counted as one lane operation; the library is built without packed FP32); each the best of
+ * five timed passes after a warm-up.  Allocates and frees 2 GiB of scratch memory; synchronises
+ * `stream`.  Errors: RAYPC_ERR_INVALID (NULL argument), RAYPC_ERR_DEVICE. */
+int raypc_measure_peaks(raypc_ctx *ctx, double *copy_bytes_per_s, double *fma_lane_ops_per_s, void *stream);
+
 /* ---------------------------------------------------------------- debug exports
  * For parity tests and accounting.  All outputs are device buffers (async). */
 
@@ -392,6 +401,17 @@ int raypc_pc_lines(raypc_ctx *ctx, int volume_id, int lod, int n_lines, const ui
 int raypc_render_debug(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height, int lod,
                        float step, float *rgba_out, uint32_t *nominal, uint32_t *composited,
                        uint32_t *touched_bricks, int flags, void *stream);
+
+/* raypc_render plus the renderer's own work per pixel, for the roofline accounting (Section 2.2:
+ * a brush change rebuilds nothing, so the skipped share of the samples is decided per frame):
+ * evaluated = samples not skipped (the empty-space skip jumps over the others), fetched = field
+ * values interpolated for them (a sample fetches no field after its first failed brush test, and
+ * the transfer-function field last); both count up to and including an early-termination stop,
+ * like raypc_render_debug's nominal count.  evaluated / fetched: device H x W uint32, either may
+ * be NULL.  The image is raypc_render's.  Uses the volume's brush and transfer slot 0; async on
+ * `stream`.  Errors: as raypc_render. */
+int raypc_render_work(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height, int lod,
+                      float step, float *rgba_out, uint32_t *evaluated, uint32_t *fetched, void *stream);
 
 /* ---------------------------------------------------------------- serving
  * A request loop that keeps volumes resident and renders many requests at once

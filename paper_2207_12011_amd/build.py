@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libraypc.so")
-SOURCES = ["api.hip", "preprocess.hip", "raymarch.hip", "raymarch_batch.hip", "server.hip", "warp.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "raymarch.hip", "raymarch_batch.hip", "server.hip", "warp.hip", "peaks.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

@@ -756,7 +756,8 @@ int raypc_select_lod(const raypc_ctx* ctx, int volume_id, const raypc_camera* ca
 
 static int render_common(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
                          float step, float* rgba_out, uint32_t* nominal, uint32_t* composited, uint32_t* touched,
-                         bool counts, bool use_skip, void* stream) {
+                         bool counts, bool use_skip, void* stream, uint32_t* evaluated = nullptr,
+                         uint32_t* fetched = nullptr) {
     if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
     DeviceGuard g(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -772,6 +773,8 @@ static int render_common(raypc_ctx* ctx, int volume_id, const raypc_camera* cam,
     a.nominal = nominal;
     a.composited = composited;
     a.touched = touched;
+    a.evaluated = evaluated;
+    a.fetched = fetched;
     HIP_TRY(launch_render(a, storage, counts, s), "ray-march kernel launch");
     return RAYPC_OK;
 }
@@ -787,6 +790,12 @@ int raypc_render_debug(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, i
                        int flags, void* stream) {
     return render_common(ctx, volume_id, cam, width, height, lod, step, rgba_out, nominal, composited, touched_bricks,
                          true, (flags & 1) == 0, stream);
+}
+
+int raypc_render_work(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
+                      float step, float* rgba_out, uint32_t* evaluated, uint32_t* fetched, void* stream) {
+    return render_common(ctx, volume_id, cam, width, height, lod, step, rgba_out, nullptr, nullptr, nullptr, true,
+                         true, stream, evaluated, fetched);
 }
 
 int raypc_render_jittered(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
@@ -962,6 +971,14 @@ int raypc_warp_noalloc(raypc_ctx* ctx, const raypc_camera* src_cam, int src_widt
     w.clear_keys = 1;
     w.next_keys = nullptr;
     HIP_TRY(launch_warp(w, static_cast<hipStream_t>(stream)), "warp kernel launches");
+    return RAYPC_OK;
+}
+
+int raypc_measure_peaks(raypc_ctx* ctx, double* copy_bytes_per_s, double* fma_lane_ops_per_s, void* stream) {
+    if (!ctx || !copy_bytes_per_s || !fma_lane_ops_per_s) return fail(RAYPC_ERR_INVALID, "NULL argument");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(measure_peaks(copy_bytes_per_s, fma_lane_ops_per_s, static_cast<hipStream_t>(stream)),
+            "peak-rate kernels");
     return RAYPC_OK;
 }
 

@@ -184,6 +184,8 @@ struct RenderArgs {
     uint32_t* nominal;            // debug counts (only in the counting variant)
     uint32_t* composited;
     uint32_t* touched;            // debug: bit per brick read by an evaluated sample (may be null)
+    uint32_t* evaluated;          // debug: per pixel, samples not skipped, up to the termination stop (may be null)
+    uint32_t* fetched;            // debug: per pixel, field values interpolated for those samples (may be null)
     int blocks_x, n_blocks;       // 4 x 4 pixel blocks (tiles) per row, total
     int super_log2;               // single-image launches: super-tiles of 8 << s pixels dealt over the XCDs
     // jittered progressive passes (jittered kernels only): pass `pass` of `n_passes` shifts each
@@ -226,6 +228,9 @@ hipError_t launch_warp(const WarpArgs& a, hipStream_t s);
 constexpr size_t kWarpScratchPixels = RAYPC_WARP_NOALLOC_MAX_PIXELS;
 constexpr int kMaxDevices = 64;
 hipError_t warp_scratch(int device, unsigned long long** ptr);
+// Measured device ceilings (peaks.hip): best of several passes of a 1 GiB device copy (bytes moved
+// per second, reads plus writes) and of an FMA loop filling every SIMD (FP32 lane operations per second).
+hipError_t measure_peaks(double* copy_bytes_per_s, double* fma_ops_per_s, hipStream_t s);
 // Work of one batched launch, passed by value in the kernel arguments: range r covers items
 // [end[r-1], end[r]) (end[-1] = 0), which march tiles first[r], first[r] + 1, ... of the request whose
 // arguments are descs[slot[r]].  Every descriptor's volume uses the launch's kernel kind.

@@ -392,6 +392,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     float D = 0.0f;  // DEPTH: sum of w tm over the composited samples
     uint32_t cnt_nom = 0, cnt_comp = 0;
+    uint32_t cnt_eval = 0, cnt_fetch = 0;  // COUNTS: this lane's evaluated samples and field fetches
     uint32_t last_brick = 0xFFFFFFFFu;
     int seg = 0, j0 = 0;  // j0: first sample of the quad's current group of four
     float sa = seg_a[0], sb = seg_b[0];
@@ -411,6 +412,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
         const bool last = j == ns - 1;
         float tlo = 0.0f, tm = 0.0f, len_partial = 0.0f;
         bool partial = last;
+        uint32_t it_eval = 0, it_fetch = 0;  // COUNTS: this step's sample evaluated, fields fetched
 
         if (valid) {
             if constexpr (JIT) {
@@ -499,6 +501,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                 // fixed field count carry no coordinate axes; renders that use them take the
                 // run-time variant)
                 pass = true;
+                if constexpr (COUNTS) it_eval = 1;
                 if constexpr (NB < 0) {
                     if (A.coord_mask)
                         pass = coord_ok(A.coord_mask, A.clo, A.chi, fmaf(dx, tm, ox), fmaf(dy, tm, oy), fmaf(dz, tm, oz));
@@ -513,16 +516,22 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                 for (int k = 0; k < kUnroll; ++k) {
                     if (pass && (NB >= 0 || k < nbr)) {
                         const float v = field_value(k);
+                        if constexpr (COUNTS) ++it_fetch;
                         pass = (v >= A.lo[k]) && (v <= A.hi[k]);
                         if (k == tfs) tv = v;
                     }
                 }
                 if (pass) {
                     if constexpr (NB >= 0 && NB < kMaxFields) {
-                        if (tfs == NB) tv = field_value(NB);
+                        if (tfs == NB) {
+                            tv = field_value(NB);
+                            if constexpr (COUNTS) ++it_fetch;
+                        }
                     } else if constexpr (NB < 0) {
-                        if (tfs == nbr && nbr < kMaxFields)
+                        if (tfs == nbr && nbr < kMaxFields) {
                             tv = field_value(nbr);
+                            if constexpr (COUNTS) ++it_fetch;
+                        }
                     }
                 }
             }
@@ -547,6 +556,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
         const int last_skipped = quad_bcast<3>(static_cast<int>(skipped && valid));
         const int jn3 = quad_bcast<3>(jn);
         bool stopped = false;
+        int stop_at = kQuad - 1;  // COUNTS: the quad's last sample that counts
         if (__ballot(contributes) != 0ull) {  // else nothing to composite anywhere in the wave
             // ---- merge the quad's four samples in sample order.  Every lane replays the same
             // sequential updates (T <- T k, then C <- C + w rgb) on broadcast values, so the ray
@@ -600,6 +610,13 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
             T = (stop_bits & 1) ? t1 : ((stop_bits & 2) ? t2 : ((stop_bits & 4) ? t3 : t4));
             stopped = stop_bits != 0;
             cnt_nom += stopped ? static_cast<uint32_t>(first_stop + 1) : 0u;
+            if constexpr (COUNTS) stop_at = first_stop;
+        }
+        if constexpr (COUNTS) {
+            // samples after the termination stop were evaluated by their lanes but are not the method's
+            const bool counted = !stopped || sub <= stop_at;
+            cnt_eval += counted ? it_eval : 0u;
+            cnt_fetch += counted ? it_fetch : 0u;
         }
         if (stopped) {
             alive = false;
@@ -623,6 +640,12 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
         }
     }
 
+    if constexpr (COUNTS) {
+        // the pixel's totals over its quad (every lane takes part in the moves)
+        const int e = static_cast<int>(cnt_eval), f = static_cast<int>(cnt_fetch);
+        cnt_eval = static_cast<uint32_t>(quad_bcast<0>(e) + quad_bcast<1>(e) + quad_bcast<2>(e) + quad_bcast<3>(e));
+        cnt_fetch = static_cast<uint32_t>(quad_bcast<0>(f) + quad_bcast<1>(f) + quad_bcast<2>(f) + quad_bcast<3>(f));
+    }
     if (!inside || sub != 0) return;
     const float acc = 1.0f - T;
     float4 res = make_float4(C0, C1, C2, acc);
@@ -653,6 +676,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     if constexpr (COUNTS) {
         if (L->nominal) L->nominal[pix] = cnt_nom;
         if (L->composited) L->composited[pix] = cnt_comp;
+        if (L->evaluated) L->evaluated[pix] = cnt_eval;
+        if (L->fetched) L->fetched[pix] = cnt_fetch;
     }
     if constexpr (DEPTH) {
         // the weights sum to the opacity 1 - T (before the background, which has no depth)

@@ -90,6 +90,9 @@ _export_skip_words = _sig("raypc_export_skip_words", _I, _P, _I, _I, _I, _P, _P)
 _export_mask = _sig("raypc_export_voxel_mask", _I, _P, _I, _I, _P, _P)
 _render_debug = _sig("raypc_render_debug", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _P, _I,
                      _P)
+_measure_peaks = _sig("raypc_measure_peaks", _I, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                      _P)
+_render_work = _sig("raypc_render_work", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _P)
 _render_depth = _sig("raypc_render_depth", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P)
 _set_launch_shape = _sig("raypc_set_launch_shape", _I, _P, _I)
 _get_launch_shape = _sig("raypc_get_launch_shape", _I, _P, ctypes.POINTER(_I))
@@ -137,7 +140,8 @@ EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_po
             "raypc_unload", "raypc_volume_info", "raypc_set_brush", "raypc_set_transfer_function",
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
             "raypc_export_level", "raypc_export_minmax", "raypc_export_minmax_sub", "raypc_export_skiplist",
-            "raypc_export_subskip", "raypc_export_skip_words", "raypc_export_voxel_mask", "raypc_render_debug", "raypc_pc_lines",
+            "raypc_export_subskip", "raypc_export_skip_words", "raypc_export_voxel_mask", "raypc_render_debug",
+            "raypc_render_work", "raypc_measure_peaks", "raypc_pc_lines",
             "raypc_render_jittered", "raypc_set_coordinate_brush", "raypc_render_depth", "raypc_warp", "raypc_warp_noalloc",
             "raypc_set_launch_shape", "raypc_get_launch_shape", "raypc_autotune_render"]
 
@@ -307,6 +311,24 @@ def render_debug(ctx, volume_id: int, camera, width: int, height: int, lod: int 
                          float(step), out.data_ptr(), nom.data_ptr(), comp.data_ptr(), tptr, 0 if skip else 1,
                          _stream(stream)))
     return out, nom, comp
+
+
+def render_work(ctx, volume_id: int, camera, width: int, height: int, lod: int = -1, step: float = 0.5, stream=None):
+    """(rgba [H,W,4] f32, evaluated [H,W] i32, fetched [H,W] i32) as CUDA tensors (async): the samples the
+    renderer did not skip and the field values it interpolated for them, per pixel."""
+    out = torch.empty((height, width, 4), dtype=torch.float32, device="cuda")
+    ev = torch.empty((height, width), dtype=torch.int32, device="cuda")
+    fe = torch.empty((height, width), dtype=torch.int32, device="cuda")
+    _check(_render_work(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height), int(lod),
+                        float(step), out.data_ptr(), ev.data_ptr(), fe.data_ptr(), _stream(stream)))
+    return out, ev, fe
+
+
+def measure_peaks(ctx, stream=None) -> dict:
+    """Measured device ceilings: {"copy_bytes_per_s", "fma_lane_ops_per_s"} (raypc_measure_peaks)."""
+    c, f = ctypes.c_double(), ctypes.c_double()
+    _check(_measure_peaks(ctx, ctypes.byref(c), ctypes.byref(f), _stream(stream)))
+    return {"copy_bytes_per_s": c.value, "fma_lane_ops_per_s": f.value}
 
 
 def render_jittered(ctx, volume_id: int, camera, width: int, height: int, lod: int, step: float, pass_index: int,

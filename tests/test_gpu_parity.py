@@ -407,6 +407,40 @@ def test_field_order_does_not_change_the_image(rp, ctx, small5, storage):
         rp.unload(ctx, vid)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "u8c"])
+def test_work_counts(rp, ctx, small5, storage):
+    """The renderer's work counts (the roofline's numerator): with an all-inclusive brush and a table
+    positive everywhere nothing is skipped, every sample is evaluated and fetches each needed field
+    once (5 with every field brushed, 1 with none); with the real brush, evaluated samples lie
+    between the passing and the nominal ones and fetch between 1 and 5 fields each.  The image is
+    raypc_render's."""
+    wl = small5
+    vid = load(rp, ctx, wl, storage, 1)
+    cam = wl.camera.as_array()
+    nf = wl.n_fields
+    try:
+        for act, lo, hi, per in ((np.ones(nf, np.uint8), np.full(nf, -np.inf, np.float32), np.full(nf, np.inf, np.float32), 5),
+                                 (np.zeros(nf, np.uint8), wl.brush.lo, wl.brush.hi, 1),
+                                 (wl.brush.active, wl.brush.lo, wl.brush.hi, None)):
+            rp.set_brush(ctx, vid, act, lo, hi)
+            rgba, ev, fe = (cpu(t).astype(np.int64) if i else cpu(t) for i, t in
+                            enumerate(rp.render_work(ctx, vid, cam, wl.width, wl.height, 0, wl.step)))
+            plain = cpu(rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step))
+            assert np.array_equal(rgba.view(np.uint32), plain.view(np.uint32))
+            _, nom, comp = (cpu(t).astype(np.int64) for t in rp.render_debug(ctx, vid, cam, wl.width, wl.height, 0,
+                                                                              wl.step))
+            print(f"[work] {storage} per-sample fields {per}: nominal {nom.sum()}, evaluated {ev.sum()}, "
+                  f"fetched {fe.sum()}, passed {comp.sum()}", flush=True)
+            if per is not None:
+                assert np.array_equal(ev, nom)
+                assert np.array_equal(fe, per * nom)
+            else:
+                assert np.all(comp <= ev) and np.all(ev <= nom) and np.all(ev <= fe) and np.all(fe <= 5 * ev)
+                assert ev.sum() < nom.sum() and fe.sum() < 5 * ev.sum() and comp.sum() > 0
+    finally:
+        rp.unload(ctx, vid)
+
+
 def test_narrow_storage_equals_float32_on_representable_data(rp, ctx, small5):
     """Fields of integers in [0, 255] with a 0 and a 255 in every 8^3 brick: binary16 holds them
     exactly and the 8-bit scale of every brick is exactly 1, so all storages and layouts store the
