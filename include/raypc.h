@@ -164,9 +164,16 @@ int raypc_set_brush(raypc_ctx *ctx, int volume_id, int n_fields, const uint8_t *
  *   n_entries   must be 256.
  *   ref_step    world-space length the table's opacity refers to (> 0);
  *               a sample of length l gets alpha = 1 - (1 - A)^(l / ref_step).
- * Waits for the device before replacing a table that kernels may read.
- * Errors: RAYPC_ERR_INVALID.
+ * Stream-ordered: the table is uploaded into a new version of the slot (on the
+ * context's own stream, waiting for that copy only), so renders already enqueued
+ * on any stream keep the table they were given and renders enqueued after the
+ * call returns use the new one; only every 256th definition of a slot (when its
+ * versions wrap) waits for the device.  Serving requests copy the table at
+ * submission.  Errors: RAYPC_ERR_INVALID, RAYPC_ERR_DEVICE.
  */
+int raypc_set_transfer_function(raypc_ctx *ctx, int slot, int field, float vmin, float vmax, const float *rgba,
+                                int n_entries, float ref_step);
+
 /* Coordinate axes of the brush (Section 2.1 derives the altitude from the position; the paper's
  * appendix cuts the volume by Cartesian coordinates on the same plot).  Axes 0, 1, 2 are the world
  * x, y, z of a sample's position (the volume spans [-1, 1]^3), axis 3 is its radius |p|.
@@ -179,9 +186,6 @@ int raypc_set_brush(raypc_ctx *ctx, int volume_id, int n_fields, const uint8_t *
  * enabled. */
 int raypc_set_coordinate_brush(raypc_ctx *ctx, int volume_id, const uint8_t *active, const float *lo,
                                const float *hi);
-
-int raypc_set_transfer_function(raypc_ctx *ctx, int slot, int field, float vmin, float vmax, const float *rgba,
-                                int n_entries, float ref_step);
 
 /*
  * Early ray termination threshold (default 0.99; >= 1 disables) and the

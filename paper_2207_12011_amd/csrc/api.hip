@@ -443,12 +443,18 @@ int raypc_create(int device, raypc_ctx** out) {
     ctx->device = device;
     ctx->warp_scratch = scratch_keys;
     for (int s = 0; s < RAYPC_TF_SLOTS; ++s) {
-        e = hipMalloc(reinterpret_cast<void**>(&ctx->tf[s].dev), RAYPC_TF_ENTRIES * sizeof(float4));
+        e = hipMalloc(reinterpret_cast<void**>(&ctx->tf[s].pool), size_t(kTFVersions) * RAYPC_TF_ENTRIES * sizeof(float4));
         if (e != hipSuccess) {
-            for (int t = 0; t < s; ++t) (void)hipFree(ctx->tf[t].dev);
+            for (int t = 0; t < s; ++t) (void)hipFree(ctx->tf[t].pool);
             delete ctx;
             return hip_fail(e, "hipMalloc(transfer-function tables)");
         }
+    }
+    e = hipStreamCreateWithFlags(&ctx->upload, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        for (auto& t : ctx->tf) (void)hipFree(t.pool);
+        delete ctx;
+        return hip_fail(e, "hipStreamCreateWithFlags(upload stream)");
     }
     *out = ctx;
     return RAYPC_OK;
@@ -460,7 +466,8 @@ void raypc_destroy(raypc_ctx* ctx) {
     server_shutdown(ctx);
     (void)hipDeviceSynchronize();
     for (auto& kv : ctx->vols) free_volume(kv.second);
-    for (auto& t : ctx->tf) (void)hipFree(t.dev);
+    for (auto& t : ctx->tf) (void)hipFree(t.pool);
+    if (ctx->upload) (void)hipStreamDestroy(ctx->upload);
     for (auto* k : ctx->warp_keys)
         if (k) (void)hipFree(k);
     delete ctx;
@@ -716,10 +723,21 @@ int raypc_set_transfer_function(raypc_ctx* ctx, int slot, int field, float vmin,
     DeviceGuard g(ctx->device);
     std::lock_guard<std::mutex> lk(ctx->mu);
     TFSlot& t = ctx->tf[slot];
-    hipError_t e = hipDeviceSynchronize();  // kernels in flight may read the old table
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    e = hipMemcpy(t.dev, rgba, RAYPC_TF_ENTRIES * sizeof(float4), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(transfer function)");
+    // the new table goes to the slot's next version: renders already enqueued (on any stream) keep
+    // reading the version they were given; renders enqueued after this call read the new one
+    const int next = (t.version + 1) % kTFVersions;
+    if (next == 0 && t.version >= 0) {
+        // the ring wraps (once every kTFVersions definitions of the slot): version 0 may still be read
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    }
+    float4* dst = t.pool + size_t(next) * RAYPC_TF_ENTRIES;
+    // on the context's own non-blocking stream: waits for this copy only, not for other streams
+    hipError_t e = hipMemcpyAsync(dst, rgba, RAYPC_TF_ENTRIES * sizeof(float4), hipMemcpyHostToDevice, ctx->upload);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->upload);
+    if (e != hipSuccess) return hip_fail(e, "transfer-function upload");
+    t.version = next;
+    t.dev = dst;
     t.defined = true;
     t.field = field;
     t.vmin = vmin;

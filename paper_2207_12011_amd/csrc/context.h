@@ -66,13 +66,20 @@ constexpr int kOrderSample = 2048;  // sampled shell cells per volume
 // fields per sample on average.
 void brush_order(Volume* v, const uint8_t* active, const float* lo, const float* hi, int* order, int& n_brushed);
 
+// Versions of a slot's device table kept before one is overwritten: a new table goes to the next
+// version, so renders already enqueued keep reading theirs; only when the ring wraps does the next
+// definition wait for the device.
+constexpr int kTFVersions = 256;
+
 struct TFSlot {
     bool defined = false;
     int field = 0;
     float vmin = 0, vmax = 1, ref_step = 2.0f / 256;
     float rgba[RAYPC_TF_ENTRIES * 4] = {};
     uint64_t gen = 0;
-    float4* dev = nullptr;
+    float4* pool = nullptr;  // kTFVersions tables of RAYPC_TF_ENTRIES entries
+    int version = -1;        // the current one
+    float4* dev = nullptr;   // = pool + version * RAYPC_TF_ENTRIES
 };
 
 }  // namespace raypc
@@ -87,6 +94,7 @@ struct raypc_ctx {
     float bg[4] = {0, 0, 0, 0};
     bool has_bg = false;
     std::mutex mu;  // guards state shared with the serving thread
+    hipStream_t upload = nullptr;  // non-blocking stream of the transfer-function uploads
     raypc::Server* server = nullptr;
     unsigned long long* warp_keys[2] = {nullptr, nullptr};  // image-warp z-buffers, used in turn, grown on demand
     size_t warp_keys_n = 0;        // capacity of each, pixels

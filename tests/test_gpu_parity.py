@@ -687,6 +687,19 @@ def test_storage_precision_report(rp, ctx, c2):
         assert np.isfinite(rgba).all()
         mx, mean, frac = PRECISION_BOUNDS[storage]
         assert stats["max_abs"] <= mx and stats["mean_abs"] <= mean and stats["frac_gt_1e-2"] <= frac, stats
+        if storage == "f32":
+            continue
+        # attribution (oracle only): the error of the image whose fields are the original float32 ones
+        # except field f, stored as `storage`
+        per_field = {}
+        for f in range(wl.n_fields):
+            lv = wl.fields.copy()
+            lv[f] = pp.stored_values(wl.fields[f], storage)
+            e_f = np.abs(oracle.render_workload(wl, lv, pixels=pix).rgba - ref.rgba).max(axis=-1)
+            per_field[wl.field_names[f]] = {"max_abs": float(e_f.max()), "mean_abs": float(e_f.mean()),
+                                            "frac_gt_1e-2": float((e_f > 1e-2).mean())}
+        print(f"[precision] {storage} per field: {per_field}", flush=True)
+        assert sum(v["mean_abs"] for v in per_field.values()) <= 2 * stats["mean_abs"] + 1e-6
 
 
 @pytest.mark.timeout(600)

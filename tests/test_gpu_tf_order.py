@@ -1,0 +1,89 @@
+"""GPU tests of transfer-function changes: they are stream-ordered (a render already enqueued keeps
+its table, a render enqueued after the change uses the new one) and do not wait for the device."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2207_12011_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rp():
+    from paper_2207_12011_amd import raypc
+    return raypc
+
+
+def setup(rp, ctx, wl):
+    vid = rp.load_fields(ctx, torch.from_numpy(wl.fields).cuda(), "f16", 1, wl.r_inner, wl.r_outer)
+    rp.set_brush(ctx, vid, wl.brush.active, wl.brush.lo, wl.brush.hi)
+    rp.set_options(ctx, wl.ert)
+    return vid
+
+
+def coloured(tab, v):
+    t = tab.copy()
+    t[:, :3] = v
+    return t
+
+
+def test_change_does_not_wait_and_is_ordered(rp):
+    ctx = rp.create(0)
+    try:
+        wl = W.make_workload(1, n=64, width=96, height=64)
+        tf = wl.tf
+        vid = setup(rp, ctx, wl)
+        cam = wl.camera.as_array()
+        tab_a, tab_b = coloured(tf.rgba, 0.25), coloured(tf.rgba, 0.75)
+        rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, tab_a, tf.ref_step)
+        want_a = rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step)
+        rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, tab_b, tf.ref_step)
+        want_b = rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step)
+        torch.cuda.synchronize()
+        rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, tab_a, tf.ref_step)
+        s = torch.cuda.Stream()
+        x = torch.randn(4096, 4096, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            for _ in range(40):          # about 5 TFLOP queued ahead of the renders
+                torch.mm(x, x, out=y)
+            got_a = rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step, stream=s)
+            rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, tab_b, tf.ref_step)
+            busy = not s.query()         # the queued work has not finished: nothing waited for it
+            got_b = rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step, stream=s)
+        s.synchronize()
+        assert busy, "set_transfer_function waited for the stream"
+        assert torch.equal(got_a, want_a) and torch.equal(got_b, want_b)
+        assert not torch.equal(want_a, want_b)
+        rp.unload(ctx, vid)
+    finally:
+        rp.destroy(ctx)
+
+
+def test_many_changes_wrap_the_versions(rp):
+    """More definitions of a slot than it keeps versions (256): every render, enqueued between two
+    definitions without waiting, used the table defined just before it."""
+    ctx = rp.create(0)
+    try:
+        wl = W.make_workload(1, n=64, width=32, height=32)
+        tf = wl.tf
+        vid = setup(rp, ctx, wl)
+        cam = wl.camera.as_array()
+        outs = []
+        n = 300
+        for i in range(n):
+            rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, coloured(tf.rgba, (i + 1) / (n + 1)),
+                                     tf.ref_step)
+            outs.append(rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step))
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            a = o.cpu().numpy()
+            m = a[..., 3] > 0.05
+            assert m.sum() > 20
+            ratio = a[..., 0][m] / a[..., 3][m]   # a constant colour c gives premultiplied c * opacity
+            assert np.abs(ratio - (i + 1) / (n + 1)).max() < 1e-5, i
+        rp.unload(ctx, vid)
+    finally:
+        rp.destroy(ctx)
