@@ -16,7 +16,11 @@ library must reproduce these arrays bit for bit:
 
 * level build: parent = fl32(fl32(fl32((a+b)+(c+d)) + fl32((e+f)+(g+h))) * 0.125)
   with the eight children in (z, y, x) lexicographic order;
-* FP16 storage: round to nearest even, subnormals kept;
+* FP16 storage: the field times a power of two 2^k, rounded to nearest even
+  binary16 (subnormals kept), then times 2^-k; k = max(0, 14 - e) for the
+  field's largest |value| f 2^e at level 0 (f in [0.5, 1)), the same k for
+  every level, so a field of small values keeps binary16's normal-range
+  precision (both scalings are exact in float32);
 * 8-bit storage: per 8^3 brick of its own 512 voxels, offset = min,
   scale = fl32((max - min)/255), q = clamp(rint(fl32(fl32(v - offset)/scale)), 0, 255)
   (scale 0 and q 0 for a constant brick); value = fl32(fl32(scale*q) + offset);
@@ -113,12 +117,24 @@ def decode_u8(q: np.ndarray, scale: np.ndarray, offset: np.ndarray) -> np.ndarra
     return _unbricks(val, n)
 
 
-def stored_values(v: np.ndarray, storage: str) -> np.ndarray:
-    """What a renderer reads after storing float32 level data as `storage`."""
+def f16_exponent(v: np.ndarray) -> int:
+    """k of binary16 storage: max(0, 14 - e) with the largest |value| m = f 2^e, f in [0.5, 1)
+    (0 for an all-zero field), so that m 2^k < 2^14."""
+    m = float(np.max(np.abs(np.asarray(v, F32)))) if np.size(v) else 0.0
+    if m == 0.0:
+        return 0
+    return max(0, 14 - math.frexp(m)[1])
+
+
+def stored_values(v: np.ndarray, storage: str, f16_exp: int = None) -> np.ndarray:
+    """What a renderer reads after storing float32 level data as `storage`.  binary16 uses the
+    exponent `f16_exp` (default: the one of `v` itself, right for level 0)."""
     if storage == "f32":
         return np.asarray(v, F32)
     if storage == "f16":
-        return decode_f16(encode_f16(v))
+        k = f16_exponent(v) if f16_exp is None else f16_exp
+        up, down = F32(2.0 ** k), F32(2.0 ** -k)
+        return (decode_f16(encode_f16((np.asarray(v, F32) * up).astype(F32))) * down).astype(F32)
     if storage == "u8":
         return decode_u8(*encode_u8(v))
     raise ValueError(storage)
@@ -127,7 +143,8 @@ def stored_values(v: np.ndarray, storage: str) -> np.ndarray:
 def stored_levels(fields: np.ndarray, n_lods: int, storage: str):
     """levels[l] = float32 [F, N_l, N_l, N_l] stored (dequantised) values of level l."""
     per_field = [build_levels(fields[f], n_lods) for f in range(fields.shape[0])]
-    return [np.stack([stored_values(per_field[f][l], storage) for f in range(fields.shape[0])])
+    exps = [f16_exponent(fields[f]) for f in range(fields.shape[0])]
+    return [np.stack([stored_values(per_field[f][l], storage, exps[f]) for f in range(fields.shape[0])])
             for l in range(n_lods)]
 
 

@@ -361,8 +361,10 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
         a.field[k] = L.data[f];
         a.u8par[k] = L.par[f];
         a.rec[k] = L.rec[f];
-        a.lo[k] = brush_lo[f];
-        a.hi[k] = brush_hi[f];
+        // binary16 codes hold the field times 2^k: the march compares them with the bounds times 2^k,
+        // which decides exactly as the values against the bounds (powers of two scale exactly)
+        a.lo[k] = brush_lo[f] * stored_scale(v, f);
+        a.hi[k] = brush_hi[f] * stored_scale(v, f);
         if (f == tf.field) {
             a.tf_slot = k;
             tf_brushed = true;
@@ -387,8 +389,9 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
     }
     a.half_n = 0.5f * static_cast<float>(L.n);
     a.tf = tf.dev;
-    a.vmin = tf.vmin;
-    a.inv_range = 1.0f / (tf.vmax - tf.vmin);
+    // the table's index map of the scaled values: (s v - s vmin) (inv / s) = (v - vmin) inv exactly
+    a.vmin = tf.vmin * stored_scale(v, tf.field);
+    a.inv_range = (1.0f / (tf.vmax - tf.vmin)) / stored_scale(v, tf.field);
     a.inv_ref = 1.0f / tf.ref_step;
     a.ert = ctx->ert;
     a.ert_on = ctx->ert < 1.0f;
@@ -519,6 +522,9 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
     float* stage = nullptr;
     float* lvbuf[2] = {nullptr, nullptr};
     unsigned int* flag = nullptr;
+    unsigned int* maxbits = nullptr;
+    float* f16_scales = nullptr;
+    int* f16_exps = nullptr;
     // shell cells whose values estimate each brush's field selectivities: uniform over the cells whose
     // centre lies in the shell, drawn with a SplitMix64 stream (Steele, Lea and Flood, OOPSLA 2014)
     std::vector<uint32_t> cells;
@@ -570,6 +576,10 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
         if (n_lods > 1 && (rc = tmp_alloc(reinterpret_cast<void**>(&lvbuf[0]), nvox / 8 * sizeof(float)))) break;
         if (n_lods > 2 && (rc = tmp_alloc(reinterpret_cast<void**>(&lvbuf[1]), nvox / 64 * sizeof(float)))) break;
         if ((rc = tmp_alloc(reinterpret_cast<void**>(&flag), sizeof(unsigned int)))) break;
+        // per field: the largest |value| (bits), binary16's scale pair and exponent
+        if ((rc = tmp_alloc(reinterpret_cast<void**>(&maxbits), kMaxFields * sizeof(unsigned int)))) break;
+        if ((rc = tmp_alloc(reinterpret_cast<void**>(&f16_scales), 2 * kMaxFields * sizeof(float)))) break;
+        if ((rc = tmp_alloc(reinterpret_cast<void**>(&f16_exps), kMaxFields * sizeof(int)))) break;
         if (n_cells > 0) {
             if ((rc = tmp_alloc(reinterpret_cast<void**>(&d_cells), n_cells * sizeof(uint32_t)))) break;
             if ((rc = tmp_alloc(reinterpret_cast<void**>(&d_sample), static_cast<size_t>(n_fields) * n_cells * sizeof(float))))
@@ -583,6 +593,8 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
             if (ce != hipSuccess) { rc = hip_fail(ce, "hipMemcpyAsync(cells)"); break; }
         }
         hipError_t e = hipMemsetAsync(flag, 0, sizeof(unsigned int), s);
+        if (e == hipSuccess) e = hipMemsetAsync(maxbits, 0, kMaxFields * sizeof(unsigned int), s);
+        if (e == hipSuccess) e = hipMemsetAsync(f16_exps, 0, kMaxFields * sizeof(int), s);
         if (e != hipSuccess) { rc = hip_fail(e, "hipMemsetAsync"); break; }
         for (int f = 0; f < n_fields && !rc; ++f) {
             const float* src = fields[f];
@@ -591,7 +603,12 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 if (e != hipSuccess) { rc = hip_fail(e, "hipMemcpyAsync(field)"); break; }
                 src = stage;
             }
-            if ((e = launch_count_nonfinite(src, nvox, flag, s)) != hipSuccess) { rc = hip_fail(e, "finite check"); break; }
+            if ((e = launch_count_nonfinite(src, nvox, flag, maxbits + f, s)) != hipSuccess) { rc = hip_fail(e, "finite check"); break; }
+            const float* f16_scale = storage == kF16 ? f16_scales + 2 * f : nullptr;
+            if (f16_scale && (e = launch_f16_scale(maxbits + f, f16_scales + 2 * f, f16_exps + f, s)) != hipSuccess) {
+                rc = hip_fail(e, "binary16 scale");
+                break;
+            }
             if ((e = launch_gather_cells(src, d_cells, n_cells, d_sample + static_cast<size_t>(f) * n_cells, s)) != hipSuccess) {
                 rc = hip_fail(e, "cell sample");
                 break;
@@ -604,8 +621,8 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                     if ((e = launch_lod_build(cur, v->lv[l - 1].n, nxt, s)) != hipSuccess) { rc = hip_fail(e, "level build"); break; }
                     cur = nxt;
                 }
-                if ((e = launch_encode(cur, L.n, storage, L.data[f], L.par[f], s)) != hipSuccess) { rc = hip_fail(e, "encode"); break; }
-                if ((e = launch_minmax(L.data[f], L.par[f], L.n, storage, L.mm[f], L.mm_sub[f], s)) != hipSuccess) { rc = hip_fail(e, "min/max"); break; }
+                if ((e = launch_encode(cur, L.n, storage, L.data[f], L.par[f], f16_scale, s)) != hipSuccess) { rc = hip_fail(e, "encode"); break; }
+                if ((e = launch_minmax(L.data[f], L.par[f], L.n, storage, L.mm[f], L.mm_sub[f], f16_scale, s)) != hipSuccess) { rc = hip_fail(e, "min/max"); break; }
                 if (l == 0 && (e = launch_gather_pairs(L.mm_sub[f], d_cell_sub, n_cells, d_sub + static_cast<size_t>(f) * n_cells,
                                                        s)) != hipSuccess) {
                     rc = hip_fail(e, "sub-brick sample");
@@ -620,6 +637,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
         std::vector<float2> sub_pairs(static_cast<size_t>(n_fields) * n_cells);
         v->order_k = n_cells;
         e = hipMemcpyAsync(&h_flag, flag, sizeof(h_flag), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(v->f16_exp, f16_exps, kMaxFields * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess && n_cells > 0)
             e = hipMemcpyAsync(v->order_sample.data(), d_sample, v->order_sample.size() * sizeof(float),
                                hipMemcpyDeviceToHost, s);
@@ -1114,7 +1132,8 @@ int raypc_export_level(raypc_ctx* ctx, int volume_id, int lod, int field, float*
     if (rc) return rc;
     if (field < 0 || field >= v->nf) return fail(RAYPC_ERR_INVALID, "field %d outside [0, %d)", field, v->nf);
     const Level& L = v->lv[lod];
-    HIP_TRY(launch_decode(L.data[field], L.par[field], L.n, v->storage, out, static_cast<hipStream_t>(stream)),
+    HIP_TRY(launch_decode(L.data[field], L.par[field], L.n, v->storage, out, 1.0f / stored_scale(v, field),
+                          static_cast<hipStream_t>(stream)),
             "decode kernel launch");
     return RAYPC_OK;
 }
@@ -1222,6 +1241,7 @@ int raypc_pc_lines(raypc_ctx* ctx, int volume_id, int lod, int n_lines, const ui
         a.active[f] = v->active[f];
         a.lo[f] = v->lo[f];
         a.hi[f] = v->hi[f];
+        a.descale[f] = 1.0f / stored_scale(v, f);
     }
     a.n_fields = v->nf;
     a.storage = v->storage;
@@ -1255,6 +1275,7 @@ int raypc_export_voxel_mask(raypc_ctx* ctx, int volume_id, int lod, uint8_t* out
         a.u8par[k] = L.par[f];
         a.lo[k] = v->lo[f];
         a.hi[k] = v->hi[f];
+        a.descale[k] = 1.0f / stored_scale(v, f);
         ++k;
     }
     a.n_active = k;

@@ -1,6 +1,7 @@
 // context.h -- host-side state of a raypc context (internal, shared by api.hip and server.hip).
 #pragma once
 
+#include <cmath>
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -40,6 +41,7 @@ struct Volume {
     int id = 0, n = 0, nf = 0, n_lods = 0, storage = 0;
     bool records = false;  // neighbourhood records kept (binary16 / float32 without RAYPC_STORAGE_COMPACT)
     float r_in = 0.55f, r_out = 1.0f;
+    int f16_exp[kMaxFields] = {};  // binary16 storage: field f is stored times 2^f16_exp[f] (0 otherwise)
     Level lv[RAYPC_MAX_LODS];
     uint8_t active[kMaxFields] = {};
     float lo[kMaxFields] = {}, hi[kMaxFields] = {};
@@ -70,6 +72,9 @@ void brush_order(Volume* v, const uint8_t* active, const float* lo, const float*
 // version, so renders already enqueued keep reading theirs; only when the ring wraps does the next
 // definition wait for the device.
 constexpr int kTFVersions = 256;
+
+// Factor by which the ray march sees field f of v: binary16 codes hold the values times 2^k.
+inline float stored_scale(const Volume* v, int f) { return v->storage == kF16 ? std::ldexp(1.0f, v->f16_exp[f]) : 1.0f; }
 
 struct TFSlot {
     bool defined = false;

@@ -71,29 +71,40 @@ __device__ __forceinline__ float cell_coord(int i, int n) {
 }
 
 // ------------------------------------------------------------------ preprocessing launchers
-hipError_t launch_count_nonfinite(const float* x, size_t count, unsigned int* flag, hipStream_t s);
+// Sets *flag on a non-finite value; raises *maxbits to the bits of the largest finite |value|.
+hipError_t launch_count_nonfinite(const float* x, size_t count, unsigned int* flag, unsigned int* maxbits,
+                                  hipStream_t s);
+// binary16 storage scales a field by 2^k, k = max(0, 14 - e) for its largest |value| f 2^e
+// (f in [0.5, 1)): scale[0] = 2^k, scale[1] = 2^-k, *exponent = k, from *maxbits on the device.
+hipError_t launch_f16_scale(const unsigned int* maxbits, float* scale, int* exponent, hipStream_t s);
 hipError_t launch_gather_cells(const float* x, const uint32_t* cells, int k, float* out, hipStream_t s);
 hipError_t launch_gather_pairs(const float2* x, const uint32_t* idx, int k, float2* out, hipStream_t s);
 // out[N/2]^3 = 2x2x2 mean of in[N]^3 (both linear [z][y][x] float32).
 hipError_t launch_lod_build(const float* in, int n, float* out, hipStream_t s);
-// Encode a linear float32 level into brick-ordered storage (u8 also writes per-brick (scale, offset)).
-hipError_t launch_encode(const float* in, int n, int storage, void* out, float2* u8par, hipStream_t s);
+// Encode a linear float32 level into brick-ordered storage (u8 also writes per-brick (scale, offset);
+// binary16 stores the values times f16_scale[0], a power of two, or times 1 when it is null).
+hipError_t launch_encode(const float* in, int n, int storage, void* out, float2* u8par, const float* f16_scale,
+                         hipStream_t s);
 // Per-brick (min, max) of stored values over the 9^3 apron window, and per 4^3 sub-brick over its 5^3
 // apron window: out_sub[8 brick + sx + 2 sy + 4 sz].
+// (Binary16 codes are taken times f16_scale[1] when it is not null: the tables hold field values.)
 hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, float2* out_sub,
-                         hipStream_t s);
+                         const float* f16_scale, hipStream_t s);
 // Neighbourhood records, 8 bytes per voxel (x, y, z) at brick_addr(x, y, z) x 8 bytes, coordinates
 // clamped to N-1: binary16 keeps the 2x2 values at (x+dx, y+dy, z) in the order dx + 2 dy; float32
 // keeps the pair at (x+dx, y, z), and 8-bit storage the pair of its decoded float32 values.  A
 // trilinear fetch reads 2 (binary16) or 4 (float32, 8-bit) records.
 hipError_t launch_records(const void* data, const float2* u8par, int n, int storage, void* out, hipStream_t s);
 // Decode stored values back to linear [z][y][x] float32.
-hipError_t launch_decode(const void* data, const float2* u8par, int n, int storage, float* out, hipStream_t s);
+// (binary16 codes times f16_descale)
+hipError_t launch_decode(const void* data, const float2* u8par, int n, int storage, float* out, float f16_descale,
+                         hipStream_t s);
 
 struct MaskArgs {
     const void* field[kMaxFields];
     const float2* u8par[kMaxFields];
     float lo[kMaxFields], hi[kMaxFields];
+    float descale[kMaxFields];  // binary16: 2^-k of the field's scale (1 otherwise)
     int n_active;  // fields [0, n_active) of the arrays above are the active ones
     uint32_t coord_mask;  // coordinate axes at the cell centre (as RenderArgs)
     float clo[4], chi[4];
@@ -111,6 +122,7 @@ struct PcArgs {
     uint8_t active[kMaxFields];
     float lo[kMaxFields], hi[kMaxFields];       // the volume's brush
     float axis_lo[kMaxFields], inv[kMaxFields]; // inv = fl32(1 / fl32(axis_hi - axis_lo))
+    float descale[kMaxFields];                  // binary16: 2^-k of the field's scale (1 otherwise)
     uint32_t coord_mask;                        // coordinate axes at the cell centre (as RenderArgs)
     float clo[4], chi[4];
     int n_fields, storage, n, nb, n_bins, n_lines;

@@ -29,12 +29,14 @@
 namespace raypc {
 namespace {
 
+// Stored value at brick-ordered index a: binary16 codes are held scaled by the field's power of two
+// 2^k (see f16_scale_kernel) and `descale` = 2^-k gives the value back exactly.
 template <int S>
-__device__ __forceinline__ float stored(const void* base, const float2* par, uint32_t a) {
+__device__ __forceinline__ float stored(const void* base, const float2* par, uint32_t a, float descale = 1.0f) {
     if constexpr (S == kF32) {
         return static_cast<const float*>(base)[a];
     } else if constexpr (S == kF16) {
-        return __half2float(static_cast<const __half*>(base)[a]);
+        return __half2float(static_cast<const __half*>(base)[a]) * descale;
     } else {
         const float q = static_cast<float>(static_cast<const uint8_t*>(base)[a]);
         const float2 p = par[a >> 9];
@@ -42,12 +44,42 @@ __device__ __forceinline__ float stored(const void* base, const float2* par, uin
     }
 }
 
-__global__ void count_nonfinite_kernel(const float* __restrict__ x, size_t count, unsigned int* flag) {
+__device__ __forceinline__ float wave_max(float v);
+
+// Sets *flag when the field holds a non-finite value; raises *maxbits to the bit pattern of the
+// largest finite |value| (non-negative floats order as their bit patterns).
+__global__ void count_nonfinite_kernel(const float* __restrict__ x, size_t count, unsigned int* flag,
+                                       unsigned int* maxbits) {
     size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     bool bad = false;
-    for (; i < count; i += stride) bad |= !isfinite(x[i]);
+    float m = 0.0f;
+    for (; i < count; i += stride) {
+        const float v = x[i];
+        const bool fin = isfinite(v);
+        bad |= !fin;
+        m = fin ? fmaxf(m, fabsf(v)) : m;
+    }
     if (__any(bad) && bad) atomicOr(flag, 1u);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) atomicMax(maxbits, __float_as_uint(m));
+}
+
+// The power of two that binary16 storage scales a field by: with the field's largest |value| m =
+// f 2^e (f in [0.5, 1)), k = max(0, 14 - e), so the scaled values stay below 2^14 and a field of
+// small values (one that would otherwise fall in binary16's subnormal range) keeps binary16's
+// normal-range precision; k = 0 for an all-zero field.  scale[0] = 2^k, scale[1] = 2^-k.
+__global__ void f16_scale_kernel(const unsigned int* maxbits, float* scale, int* exponent) {
+    const float m = __uint_as_float(*maxbits);
+    int k = 0;
+    if (m > 0.0f) {
+        int e = 0;
+        (void)frexpf(m, &e);
+        k = max(0, 14 - e);
+    }
+    scale[0] = ldexpf(1.0f, k);
+    scale[1] = ldexpf(1.0f, -k);
+    *exponent = k;
 }
 
 // Values of one float32 field at k linear voxel indices (the cells that estimate brush selectivity).
@@ -94,7 +126,7 @@ __device__ __forceinline__ float wave_max(float v) {
 // One 512-thread block per brick; thread t is the brick-local voxel t.
 template <int S>
 __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ in, int n, void* __restrict__ out,
-                                                     float2* __restrict__ u8par) {
+                                                     float2* __restrict__ u8par, const float* __restrict__ f16_scale) {
     const int nb = n >> 3;
     const uint32_t brick = blockIdx.x;
     const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
@@ -106,7 +138,8 @@ __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ i
     if constexpr (S == kF32) {
         static_cast<float*>(out)[a] = v;
     } else if constexpr (S == kF16) {
-        static_cast<__half*>(out)[a] = __float2half_rn(v);
+        // scaling by a power of two is exact: only the binary16 rounding remains
+        static_cast<__half*>(out)[a] = __float2half_rn(v * (f16_scale ? f16_scale[0] : 1.0f));
     } else {
         __shared__ float smin[8], smax[8];
         float mn = wave_min(v), mx = wave_max(v);
@@ -135,7 +168,9 @@ __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ i
 // to both halves).  The brick window is the union of the sub-brick windows.
 template <int S>
 __global__ __launch_bounds__(64) void minmax_kernel(const void* __restrict__ data, const float2* __restrict__ par,
-                                                    int n, float2* __restrict__ out, float2* __restrict__ out_sub) {
+                                                    int n, float2* __restrict__ out, float2* __restrict__ out_sub,
+                                                    const float* __restrict__ f16_scale) {
+    const float descale = f16_scale ? f16_scale[1] : 1.0f;
     const int nb = n >> 3;
     const uint32_t brick = blockIdx.x;
     const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
@@ -150,7 +185,7 @@ __global__ __launch_bounds__(64) void minmax_kernel(const void* __restrict__ dat
         const int x = min(bx * 8 + lx, n - 1);
         const int y = min(by * 8 + ly, n - 1);
         const int z = min(bz * 8 + lz, n - 1);
-        const float v = stored<S>(data, par, brick_addr(x, y, z, nb));
+        const float v = stored<S>(data, par, brick_addr(x, y, z, nb), descale);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const bool in = ((i & 1) ? lx >= 4 : lx <= 4) && ((i & 2) ? ly >= 4 : ly <= 4) &&
@@ -181,12 +216,12 @@ __global__ __launch_bounds__(64) void minmax_kernel(const void* __restrict__ dat
 
 template <int S>
 __global__ void decode_kernel(const void* __restrict__ data, const float2* __restrict__ par, int n,
-                              float* __restrict__ out) {
+                              float* __restrict__ out, float descale) {
     const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t total = static_cast<uint32_t>(n) * n * n;
     if (o >= total) return;
     const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
-    out[o] = stored<S>(data, par, brick_addr(x, y, z, n >> 3));
+    out[o] = stored<S>(data, par, brick_addr(x, y, z, n >> 3), descale);
 }
 
 // One thread per voxel: gather its 8-byte neighbourhood record (bit patterns copied): binary16 the
@@ -233,7 +268,7 @@ __global__ void voxel_mask_kernel(MaskArgs a) {
     const uint32_t addr = brick_addr(x, y, z, a.nb);
     bool keep = true;
     for (int f = 0; f < a.n_active; ++f) {
-        const float v = stored<S>(a.field[f], a.u8par[f], addr);
+        const float v = stored<S>(a.field[f], a.u8par[f], addr, a.descale[f]);
         keep = keep && (v >= a.lo[f]) && (v <= a.hi[f]);
     }
     if (a.coord_mask)
@@ -262,14 +297,14 @@ __global__ __launch_bounds__(256) void pc_lines_kernel(PcArgs a) {
         if (valid && a.coord_mask)
             pass = coord_ok(a.coord_mask, a.clo, a.chi, cell_coord(x, a.n), cell_coord(y, a.n), cell_coord(z, a.n));
         for (int f = 0; f < a.n_fields; ++f) {
-            const float v = valid ? stored<S>(a.field[f], a.u8par[f], addr) : NAN;
+            const float v = valid ? stored<S>(a.field[f], a.u8par[f], addr, a.descale[f]) : NAN;
             if (a.values != nullptr) a.values[static_cast<size_t>(line) * a.n_fields + f] = v;
             if (a.active[f]) pass = pass && (v >= a.lo[f]) && (v <= a.hi[f]);
         }
         if (a.passes != nullptr) a.passes[line] = pass ? 1 : 0;
         if (a.hist != nullptr && valid) {
             for (int f = 0; f < a.n_fields; ++f) {
-                const float v = stored<S>(a.field[f], a.u8par[f], addr);
+                const float v = stored<S>(a.field[f], a.u8par[f], addr, a.descale[f]);
                 const float t = __fmul_rn(__fsub_rn(v, a.axis_lo[f]), a.inv[f]);
                 const float xb = fminf(fmaxf(__fmul_rn(t, static_cast<float>(a.n_bins)), 0.0f),
                                        static_cast<float>(a.n_bins - 1));
@@ -412,9 +447,15 @@ inline unsigned blocks_for(size_t count, unsigned threads) {
 
 }  // namespace
 
-hipError_t launch_count_nonfinite(const float* x, size_t count, unsigned int* flag, hipStream_t s) {
+hipError_t launch_count_nonfinite(const float* x, size_t count, unsigned int* flag, unsigned int* maxbits,
+                                  hipStream_t s) {
     const unsigned blocks = static_cast<unsigned>(std::min<size_t>(blocks_for(count, 256), 8192));
-    hipLaunchKernelGGL(count_nonfinite_kernel, dim3(std::max(blocks, 1u)), dim3(256), 0, s, x, count, flag);
+    hipLaunchKernelGGL(count_nonfinite_kernel, dim3(std::max(blocks, 1u)), dim3(256), 0, s, x, count, flag, maxbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_f16_scale(const unsigned int* maxbits, float* scale, int* exponent, hipStream_t s) {
+    hipLaunchKernelGGL(f16_scale_kernel, dim3(1), dim3(1), 0, s, maxbits, scale, exponent);
     return hipGetLastError();
 }
 
@@ -438,40 +479,42 @@ hipError_t launch_lod_build(const float* in, int n, float* out, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_encode(const float* in, int n, int storage, void* out, float2* u8par, hipStream_t s) {
+hipError_t launch_encode(const float* in, int n, int storage, void* out, float2* u8par, const float* f16_scale,
+                         hipStream_t s) {
     const unsigned nbr = static_cast<unsigned>((n / 8) * (n / 8) * (n / 8));
     switch (storage) {
-        case kF32: hipLaunchKernelGGL(encode_kernel<kF32>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par); break;
-        case kF16: hipLaunchKernelGGL(encode_kernel<kF16>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par); break;
-        default: hipLaunchKernelGGL(encode_kernel<kU8>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par); break;
+        case kF32: hipLaunchKernelGGL(encode_kernel<kF32>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, nullptr); break;
+        case kF16: hipLaunchKernelGGL(encode_kernel<kF16>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, f16_scale); break;
+        default: hipLaunchKernelGGL(encode_kernel<kU8>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, nullptr); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, float2* out_sub,
-                         hipStream_t s) {
+                         const float* f16_scale, hipStream_t s) {
     const unsigned nbr = static_cast<unsigned>((n / 8) * (n / 8) * (n / 8));
     switch (storage) {
         case kF32:
-            hipLaunchKernelGGL(minmax_kernel<kF32>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out, out_sub);
+            hipLaunchKernelGGL(minmax_kernel<kF32>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out, out_sub, nullptr);
             break;
         case kF16:
-            hipLaunchKernelGGL(minmax_kernel<kF16>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out, out_sub);
+            hipLaunchKernelGGL(minmax_kernel<kF16>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out, out_sub, f16_scale);
             break;
         default:
-            hipLaunchKernelGGL(minmax_kernel<kU8>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out, out_sub);
+            hipLaunchKernelGGL(minmax_kernel<kU8>, dim3(nbr), dim3(64), 0, s, data, u8par, n, out, out_sub, nullptr);
             break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_decode(const void* data, const float2* u8par, int n, int storage, float* out, hipStream_t s) {
+hipError_t launch_decode(const void* data, const float2* u8par, int n, int storage, float* out, float f16_descale,
+                         hipStream_t s) {
     const size_t total = static_cast<size_t>(n) * n * n;
     const dim3 g(blocks_for(total, 256));
     switch (storage) {
-        case kF32: hipLaunchKernelGGL(decode_kernel<kF32>, g, dim3(256), 0, s, data, u8par, n, out); break;
-        case kF16: hipLaunchKernelGGL(decode_kernel<kF16>, g, dim3(256), 0, s, data, u8par, n, out); break;
-        default: hipLaunchKernelGGL(decode_kernel<kU8>, g, dim3(256), 0, s, data, u8par, n, out); break;
+        case kF32: hipLaunchKernelGGL(decode_kernel<kF32>, g, dim3(256), 0, s, data, u8par, n, out, 1.0f); break;
+        case kF16: hipLaunchKernelGGL(decode_kernel<kF16>, g, dim3(256), 0, s, data, u8par, n, out, f16_descale); break;
+        default: hipLaunchKernelGGL(decode_kernel<kU8>, g, dim3(256), 0, s, data, u8par, n, out, 1.0f); break;
     }
     return hipGetLastError();
 }

@@ -471,6 +471,41 @@ def test_f16_bit_patterns():
     assert pp.decode_f16(np.array([0x0001], np.uint16))[0] == np.float32(2.0 ** -24)
 
 
+@pytest.mark.parametrize("scale", [1.0, 3e-5, 2.0 ** -20, 700.0, 9000.0])
+def test_f16_storage_power_of_two_scale(scale):
+    """binary16 storage with the field's power of two: equal to rounding v 2^k to binary16 in
+    float64 arithmetic (numpy's own conversion) and dividing by 2^k; k = max(0, 14 - e) for the
+    field's largest |value| f 2^e; error within half a binary16 ulp of the scaled maximum, i.e.
+    relative to the field's range, however small its values (no subnormal codes)."""
+    rng = np.random.default_rng(41)
+    v = (rng.uniform(-1.0, 1.0, (8, 8, 8)) * scale).astype(np.float32)
+    m = float(np.abs(v).max())
+    k = pp.f16_exponent(v)
+    assert k == max(0, 14 - math.frexp(m)[1])
+    assert m * 2.0 ** k < 2.0 ** 14 and (k == 0 or m * 2.0 ** k >= 2.0 ** 13)
+    want = (v.astype(np.float64) * 2.0 ** k).astype(np.float16).astype(np.float64) / 2.0 ** k
+    got = pp.stored_values(v, "f16")
+    assert np.array_equal(got.astype(np.float64), want)
+    assert np.abs(got.astype(np.float64) - v).max() <= 2.0 ** -11 * m
+    # scaling the field by a power of two scales what is stored by the same power, exactly
+    assert np.array_equal(pp.stored_values((v * np.float32(2.0 ** -7)).astype(np.float32), "f16"),
+                          (got * np.float32(2.0 ** -7)).astype(np.float32))
+    if k == 0:
+        assert np.array_equal(got, pp.decode_f16(pp.encode_f16(v)))
+
+
+def test_f16_storage_levels_share_the_exponent():
+    rng = np.random.default_rng(42)
+    v = (rng.uniform(0.0, 1.0, (1, 16, 16, 16)) * 3e-5).astype(np.float32)
+    lv = pp.stored_levels(v, 2, "f16")
+    k = pp.f16_exponent(v[0])
+    assert k == 29
+    assert np.array_equal(lv[1][0], pp.stored_values(pp.build_level(v[0]), "f16", k))
+    # multiples of 2^-8 in [0, 4] are stored exactly
+    e = (rng.integers(0, 1025, (16, 16, 16)) / 256.0).astype(np.float32)
+    assert np.array_equal(pp.stored_values(e, "f16"), e)
+
+
 def test_u8_roundtrip_and_bound():
     rng = np.random.default_rng(5)
     n = 16
