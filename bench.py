@@ -504,6 +504,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--in-flight", type=int, default=2,
+                    help="frames in flight in the timed loop (streams used in turn); 1 = serial")
     ap.add_argument("--storages", default="f16,f32,u8,u8c",
                     help="first one is the headline value; a trailing c keeps only the compact layout")
     ap.add_argument("--cpu-stride", type=int, default=1, help="oracle sample: every k-th row and column")
@@ -615,29 +617,35 @@ def main():
                         "passed_samples": int(comp.to(torch.int64).sum().item())}
         n_needed = len(set(np.flatnonzero(brushes[0].active).tolist()) | {wl.tf.field})
 
-        # warmup
-        for s in range(args.warmup):
-            b = brushes[s % len(brushes)]
-            raypc.set_brush(ctx, vid, b.active, b.lo, b.hi)
-            raypc.render(ctx, vid, cam, W_, H_, -1, wl.step, out=out, stream=stream)
-        torch.cuda.synchronize()
+        # timed: K steps (brush change + frame).  Frames go to `args.in_flight` streams in turn (each
+        # with its own output image), so a frame's first blocks start while the previous frame's last
+        # blocks drain; the skip flags of each brush are a new version, so frames in flight never share
+        # them.  in_flight 1 is the serial loop.
+        def timed_loop(n_flight, steps, warm):
+            sts = [stream] + [torch.cuda.Stream() for _ in range(n_flight - 1)]
+            images = [out] + [torch.empty_like(out) for _ in range(n_flight - 1)]
+            for s_ in range(warm):
+                b_ = brushes[s_ % len(brushes)]
+                raypc.set_brush(ctx, vid, b_.active, b_.lo, b_.hi)
+                raypc.render(ctx, vid, cam, W_, H_, -1, wl.step, out=images[s_ % n_flight], stream=sts[s_ % n_flight])
+            torch.cuda.synchronize()
+            ev_ = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+            tot = 0
+            t0_ = time.perf_counter()
+            for s_ in range(steps):
+                k_ = s_ % len(brushes)
+                b_ = brushes[k_]
+                st_ = sts[s_ % n_flight]
+                raypc.set_brush(ctx, vid, b_.active, b_.lo, b_.hi)
+                ev_[s_][0].record(st_)
+                raypc.render(ctx, vid, cam, W_, H_, -1, wl.step, out=images[s_ % n_flight], stream=st_)
+                ev_[s_][1].record(st_)
+                tot += samples[k_]
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0_, tot, [a_.elapsed_time(e_) for a_, e_ in ev_]
 
-        # timed: K steps (brush change + frame)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-        total_samples = 0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s in range(args.steps):
-            k = s % len(brushes)
-            b = brushes[k]
-            raypc.set_brush(ctx, vid, b.active, b.lo, b.hi)
-            ev[s][0].record(stream)
-            raypc.render(ctx, vid, cam, W_, H_, -1, wl.step, out=out, stream=stream)
-            ev[s][1].record(stream)
-            total_samples += samples[k]
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        lat = [a.elapsed_time(b) for a, b in ev]
+        serial_wall, serial_samples, serial_lat = timed_loop(1, args.steps, args.warmup)
+        wall, total_samples, lat = timed_loop(args.in_flight, args.steps, args.warmup)
 
         # kernel-only: fixed brush (skip bits cached), back-to-back launches on the same stream
         b = brushes[0]
@@ -679,7 +687,12 @@ def main():
             "samples_per_s": total_samples / wall,
             "frames_per_s": args.steps / wall,
             "ms_per_step": 1e3 * wall / args.steps,
+            "frames_in_flight": args.in_flight,
             "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat)},
+            "serial": {"frames_in_flight": 1, "samples_per_s": serial_samples / serial_wall,
+                       "frames_per_s": args.steps / serial_wall, "ms_per_step": 1e3 * serial_wall / args.steps,
+                       "latency_ms": {"p50": percentile(serial_lat, 50), "p99": percentile(serial_lat, 99),
+                                      "max": max(serial_lat)}},
             "nominal_samples_per_frame": samples,
             "touched_bricks": touched_bricks[0],
             "bricks_per_level": nb ** 3,
@@ -712,11 +725,16 @@ def main():
     rec = traffic_record(TRAFFIC_RECORD) if head == "f16" and (wl.n, W_, H_) == (512, 1920, 1080) else None
     traffic = None if rec is None else rec["traffic_bytes_per_launch"]
     dense = r["work"]["dense_equivalent_ops"] / ksec
+    piped = r["alg_ops_per_launch"] / (r["ms_per_step"] * 1e-3)
     roofline = {"bound": "alu", "kernel": f"raymarch_kernel ({head})", "achieved": achieved_ops / 1e12,
                 "peak": ALU_PEAK / 1e12, "unit": "Tlane-op/s", "frac": achieved_ops / ALU_PEAK,
                 "traffic": traffic, "kernel_ms": r["kernel_ms"],
                 "work": r["work"],
                 "frac_of_measured_fma_rate": achieved_ops / peaks["fma_lane_ops_per_s"],
+                "pipelined": {"achieved": piped / 1e12, "frac": piped / ALU_PEAK,
+                              "frames_in_flight": r["frames_in_flight"],
+                              "note": "the method's work per step over the timed loop's time per step (frames "
+                                      "overlapping on streams used in turn); 'achieved' above is one launch alone"},
                 "dense_equivalent": {"achieved": dense / 1e12, "frac": dense / ALU_PEAK,
                                      "note": "every nominal sample charged 50 + 22 x 5 lane-ops, skipped ones "
                                              "included: not the work done"},
@@ -752,7 +770,7 @@ def main():
         "config": {"workload": f"precision study: {wl.n}^3 x {wl.n_fields} fields stored {head}, LOD 3 levels, "
                                f"{W_}x{H_}, step {wl.step} voxel, 5-axis ~10% brush changed every step, ERT 0.99",
                    "volume": wl.n, "fields": wl.n_fields, "width": W_, "height": H_, "step": wl.step,
-                   "storage": head, "lod": r["lod"]},
+                   "storage": head, "lod": r["lod"], "frames_in_flight": args.in_flight},
         "frames_per_s": r["frames_per_s"],
         "latency_ms": r["latency_ms"],
         "per_storage": results,

@@ -67,6 +67,9 @@ namespace {
 size_t storage_bytes(int storage) { return storage == kF32 ? 4 : (storage == kF16 ? 2 : 1); }
 
 void free_volume(Volume* v) {
+    for (auto& L : v->lv)
+        for (auto& users : L.skip_users)
+            for (auto& u : users) (void)hipEventDestroy(u.done);
     for (void* p : v->allocs) (void)hipFree(p);
     delete v;
 }
@@ -210,15 +213,40 @@ void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t
 
 // Recompute the skip bits and sub-brick flags of level l for the volume's own brush and a transfer
 // slot if stale.
+// Record that a launch on `s` read the current skip-flag version of level l (call after the launch).
+static int note_skip_use(Level& L, hipStream_t s) {
+    if (L.skip_cur < 0) return RAYPC_OK;
+    auto& users = L.skip_users[L.skip_cur];
+    SkipUser* u = nullptr;
+    for (auto& x : users)
+        if (x.stream == s) u = &x;  // later work on a stream completes after its earlier work
+    if (!u) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
+        users.push_back({s, e});
+        u = &users.back();
+    }
+    HIP_TRY(hipEventRecord(u->done, s), "hipEventRecord(skip flags in use)");
+    return RAYPC_OK;
+}
+
 static int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s) {
     Level& L = v->lv[l];
     const TFSlot& tf = ctx->tf[slot];
     if (L.skip_valid && L.skip_brush_gen == v->brush_gen && L.skip_slot == slot && L.skip_tf_gen == tf.gen)
         return RAYPC_OK;
+    // the next version: wait (on the host) only for the launches that read it when it was current,
+    // long ago in the usual case; a render on another stream may still read the current version
+    const int next = (L.skip_cur + 1) % kSkipVersions;
+    for (auto& u : L.skip_users[next]) HIP_TRY(hipEventSynchronize(u.done), "hipEventSynchronize(skip flags)");
+    for (auto& u : L.skip_users[next]) (void)hipEventDestroy(u.done);
+    L.skip_users[next].clear();
     SkipArgs a;
     build_skip_args(ctx, v, l, v->active, v->lo, v->hi, v->coord, slot, a);
-    a.out_sub = L.skip_sub;
+    a.out_sub = L.skip_ver[next];
     HIP_TRY(launch_skip(a, s), "skip-list kernel launch");
+    L.skip_cur = next;
+    L.skip_sub = L.skip_ver[next];
     L.skip_valid = true;
     L.skip_brush_gen = v->brush_gen;
     L.skip_slot = slot;
@@ -569,7 +597,8 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm_sub[f]), L.n_bricks() * 8 * sizeof(float2));
                 if (!rc && v->records) rc = dev_alloc(v, &L.rec[f], lvox * 8);
             }
-            if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip_sub), L.n_bricks() * sizeof(uint16_t));
+            for (int k = 0; k < kSkipVersions && !rc; ++k)
+                rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip_ver[k]), L.n_bricks() * sizeof(uint16_t));
         }
         if (rc) break;
         if (!on_device && (rc = tmp_alloc(reinterpret_cast<void**>(&stage), nvox * sizeof(float)))) break;
@@ -812,7 +841,7 @@ static int render_common(raypc_ctx* ctx, int volume_id, const raypc_camera* cam,
     a.evaluated = evaluated;
     a.fetched = fetched;
     HIP_TRY(launch_render(a, storage, counts, s), "ray-march kernel launch");
-    return RAYPC_OK;
+    return a.skip ? note_skip_use(v->lv[level], s) : RAYPC_OK;
 }
 
 int raypc_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod, float step,
@@ -864,7 +893,7 @@ int raypc_render_jittered(raypc_ctx* ctx, int volume_id, const raypc_camera* cam
     a.mean = reinterpret_cast<float4*>(mean_inout);
     HIP_TRY(launch_render_jittered(a, storage, nominal != nullptr || composited != nullptr, s),
             "jittered ray-march kernel launch");
-    return RAYPC_OK;
+    return note_skip_use(v->lv[level], s);
 }
 
 int raypc_render_depth(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
@@ -883,7 +912,7 @@ int raypc_render_depth(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, i
     if (rc) return rc;
     a.depth = depth_out;
     HIP_TRY(launch_render_depth(a, storage, s), "depth ray-march kernel launch");
-    return RAYPC_OK;
+    return note_skip_use(v->lv[level], s);
 }
 
 static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -1184,7 +1213,7 @@ static int export_skip(raypc_ctx* ctx, int volume_id, int lod, int slot, void* o
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = ensure_skip(ctx, v, lod, slot, s);
     if (rc) return rc;
-    const Level& L = v->lv[lod];
+    Level& L = v->lv[lod];
     if (what == 1)  // the low bytes of the flag words
         HIP_TRY(hipMemcpy2DAsync(out, 1, L.skip_sub, sizeof(uint16_t), 1, L.n_bricks(), hipMemcpyDeviceToDevice, s),
                 "hipMemcpy2DAsync(sub-brick flags)");
@@ -1193,7 +1222,7 @@ static int export_skip(raypc_ctx* ctx, int volume_id, int lod, int slot, void* o
                 "hipMemcpyAsync(skip flag words)");
     else
         HIP_TRY(launch_pack_skip_bits(L.skip_sub, L.n_bricks(), static_cast<uint32_t*>(out), s), "skip-bit packing");
-    return RAYPC_OK;
+    return note_skip_use(L, s);
 }
 
 int raypc_export_skiplist(raypc_ctx* ctx, int volume_id, int lod, int slot, uint32_t* out, void* stream) {

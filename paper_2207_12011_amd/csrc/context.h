@@ -16,6 +16,16 @@ struct Server;
 
 constexpr int kDefaultSuperLog2 = 2;  // default launch shape: super-tiles of 4 x 4 blocks (32 x 32 pixels)
 
+// Versions of a level's skip-flag words: a brush or table change computes the flags into the next
+// version, so a render still reading the previous one (on another stream) is not disturbed; a version
+// is overwritten only after the renders that read it have finished (their events).
+constexpr int kSkipVersions = 4;
+
+struct SkipUser {
+    hipStream_t stream;
+    hipEvent_t done;  // recorded on `stream` after its last launch that read the version
+};
+
 struct Level {
     int n = 0, nb = 0;
     void* data[kMaxFields] = {};
@@ -24,6 +34,10 @@ struct Level {
     float2* mm_sub[kMaxFields] = {};  // per brick, its eight 4^3 sub-bricks' (min, max)
     void* rec[kMaxFields] = {};  // neighbourhood records (null when the volume keeps only the compact layout)
     uint16_t* skip_sub = nullptr; // per brick: sub-brick skip flags (bits 0-7) and empty-group bits (8, 9)
+                                  // of the current version (= skip_ver[skip_cur])
+    uint16_t* skip_ver[kSkipVersions] = {};
+    std::vector<SkipUser> skip_users[kSkipVersions];  // launches that read each version
+    int skip_cur = -1;
     bool skip_valid = false;
     uint64_t skip_brush_gen = 0, skip_tf_gen = 0;
     int skip_slot = -1;
