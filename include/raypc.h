@@ -164,15 +164,27 @@ int raypc_set_brush(raypc_ctx *ctx, int volume_id, int n_fields, const uint8_t *
  *   n_entries   must be 256.
  *   ref_step    world-space length the table's opacity refers to (> 0);
  *               a sample of length l gets alpha = 1 - (1 - A)^(l / ref_step).
- * Stream-ordered: the table is uploaded into a new version of the slot (on the
- * context's own stream, waiting for that copy only), so renders already enqueued
- * on any stream keep the table they were given and renders enqueued after the
- * call returns use the new one; only every 256th definition of a slot (when its
- * versions wrap) waits for the device.  Serving requests copy the table at
- * submission.  Errors: RAYPC_ERR_INVALID, RAYPC_ERR_DEVICE.
+ * The table is uploaded into a new version of the slot, so renders already
+ * enqueued (on any stream) keep the table they were given and renders enqueued
+ * after the call returns use the new one.  The upload runs on the context's own
+ * stream and the call waits for that copy, not for a device drain (the runtime
+ * may map that stream onto a hardware queue it shares with other streams, whose
+ * earlier work the copy then waits behind); only every 256th definition of a
+ * slot (when its versions wrap) waits for the device.  Serving requests copy the
+ * table at submission.  Errors: RAYPC_ERR_INVALID, RAYPC_ERR_DEVICE.
  */
 int raypc_set_transfer_function(raypc_ctx *ctx, int slot, int field, float vmin, float vmax, const float *rgba,
                                 int n_entries, float ref_step);
+
+/* raypc_set_transfer_function ordered on `stream` instead: the table is copied to
+ * pinned host memory and its upload enqueued on `stream`, and the call returns
+ * without waiting; renders enqueued on `stream` after it use the new table, renders
+ * enqueued before it (on any stream) keep theirs, and renders on other streams use
+ * it once the caller orders them after `stream` (events).  Same arguments, version
+ * rule and errors as raypc_set_transfer_function; the first call allocates the
+ * context's pinned staging (8 MiB). */
+int raypc_set_transfer_function_async(raypc_ctx *ctx, int slot, int field, float vmin, float vmax,
+                                      const float *rgba, int n_entries, float ref_step, void *stream);
 
 /* Coordinate axes of the brush (Section 2.1 derives the altitude from the position; the paper's
  * appendix cuts the volume by Cartesian coordinates on the same plot).  Axes 0, 1, 2 are the world

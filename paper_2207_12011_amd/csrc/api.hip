@@ -499,6 +499,7 @@ void raypc_destroy(raypc_ctx* ctx) {
     for (auto& kv : ctx->vols) free_volume(kv.second);
     for (auto& t : ctx->tf) (void)hipFree(t.pool);
     if (ctx->upload) (void)hipStreamDestroy(ctx->upload);
+    if (ctx->tf_stage) (void)hipHostFree(ctx->tf_stage);
     for (auto* k : ctx->warp_keys)
         if (k) (void)hipFree(k);
     delete ctx;
@@ -755,8 +756,10 @@ int raypc_set_coordinate_brush(raypc_ctx* ctx, int volume_id, const uint8_t* act
     return RAYPC_OK;
 }
 
-int raypc_set_transfer_function(raypc_ctx* ctx, int slot, int field, float vmin, float vmax, const float* rgba,
-                                int n_entries, float ref_step) {
+// Both entry points: `async` enqueues the upload on `stream` (from a pinned staging copy) and returns;
+// otherwise the upload runs on the context's own stream and is waited for.
+static int set_tf_impl(raypc_ctx* ctx, int slot, int field, float vmin, float vmax, const float* rgba, int n_entries,
+                       float ref_step, bool async, hipStream_t stream) {
     if (!ctx || !rgba) return fail(RAYPC_ERR_INVALID, "NULL argument");
     if (slot < 0 || slot >= RAYPC_TF_SLOTS) return fail(RAYPC_ERR_INVALID, "slot %d outside [0, 8)", slot);
     if (n_entries != RAYPC_TF_ENTRIES) return fail(RAYPC_ERR_INVALID, "n_entries must be 256");
@@ -779,9 +782,27 @@ int raypc_set_transfer_function(raypc_ctx* ctx, int slot, int field, float vmin,
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     }
     float4* dst = t.pool + size_t(next) * RAYPC_TF_ENTRIES;
-    // on the context's own non-blocking stream: waits for this copy only, not for other streams
-    hipError_t e = hipMemcpyAsync(dst, rgba, RAYPC_TF_ENTRIES * sizeof(float4), hipMemcpyHostToDevice, ctx->upload);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->upload);
+    hipError_t e = hipSuccess;
+    if (async) {
+        // a pinned staging copy per (slot, version): reused only after the versions wrap, which drains
+        // the device first, so no pending upload still reads it
+        if (!ctx->tf_stage) {
+            e = hipHostMalloc(reinterpret_cast<void**>(&ctx->tf_stage),
+                              size_t(RAYPC_TF_SLOTS) * kTFVersions * RAYPC_TF_ENTRIES * sizeof(float4), hipHostMallocDefault);
+            if (e != hipSuccess) {
+                ctx->tf_stage = nullptr;
+                return hip_fail(e, "hipHostMalloc(transfer-function staging)");
+            }
+        }
+        float4* stage = ctx->tf_stage + (size_t(slot) * kTFVersions + next) * RAYPC_TF_ENTRIES;
+        std::memcpy(stage, rgba, RAYPC_TF_ENTRIES * sizeof(float4));
+        e = hipMemcpyAsync(dst, stage, RAYPC_TF_ENTRIES * sizeof(float4), hipMemcpyHostToDevice, stream);
+    } else {
+        // on the context's own non-blocking stream: waits for this copy (and for whatever the runtime
+        // queued ahead of it on the hardware queue that stream shares), not for a device drain
+        e = hipMemcpyAsync(dst, rgba, RAYPC_TF_ENTRIES * sizeof(float4), hipMemcpyHostToDevice, ctx->upload);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->upload);
+    }
     if (e != hipSuccess) return hip_fail(e, "transfer-function upload");
     t.version = next;
     t.dev = dst;
@@ -793,6 +814,16 @@ int raypc_set_transfer_function(raypc_ctx* ctx, int slot, int field, float vmin,
     std::memcpy(t.rgba, rgba, sizeof(t.rgba));
     t.gen = ++ctx->tf_gen_counter;
     return RAYPC_OK;
+}
+
+int raypc_set_transfer_function(raypc_ctx* ctx, int slot, int field, float vmin, float vmax, const float* rgba,
+                                int n_entries, float ref_step) {
+    return set_tf_impl(ctx, slot, field, vmin, vmax, rgba, n_entries, ref_step, false, nullptr);
+}
+
+int raypc_set_transfer_function_async(raypc_ctx* ctx, int slot, int field, float vmin, float vmax, const float* rgba,
+                                      int n_entries, float ref_step, void* stream) {
+    return set_tf_impl(ctx, slot, field, vmin, vmax, rgba, n_entries, ref_step, true, static_cast<hipStream_t>(stream));
 }
 
 int raypc_set_options(raypc_ctx* ctx, float ert_threshold, const float* bg_rgba) {

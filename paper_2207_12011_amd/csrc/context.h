@@ -114,6 +114,7 @@ struct raypc_ctx {
     bool has_bg = false;
     std::mutex mu;  // guards state shared with the serving thread
     hipStream_t upload = nullptr;  // non-blocking stream of the transfer-function uploads
+    float4* tf_stage = nullptr;    // pinned staging of stream-ordered table uploads, per slot and version
     raypc::Server* server = nullptr;
     unsigned long long* warp_keys[2] = {nullptr, nullptr};  // image-warp z-buffers, used in turn, grown on demand
     size_t warp_keys_n = 0;        // capacity of each, pixels

@@ -74,6 +74,7 @@ _volume_info = _sig("raypc_volume_info", _I, _P, _I, ctypes.POINTER(_I), ctypes.
 _set_brush = _sig("raypc_set_brush", _I, _P, _I, _I, _P, _P, _P)
 _set_coord = _sig("raypc_set_coordinate_brush", _I, _P, _I, _P, _P, _P)
 _set_tf = _sig("raypc_set_transfer_function", _I, _P, _I, _I, _F, _F, _P, _I, _F)
+_set_tf_async = _sig("raypc_set_transfer_function_async", _I, _P, _I, _I, _F, _F, _P, _I, _F, _P)
 _set_options = _sig("raypc_set_options", _I, _P, _F, _P)
 _select_lod = _sig("raypc_select_lod", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, ctypes.POINTER(_I))
 _render = _sig("raypc_render", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P)
@@ -137,7 +138,7 @@ _server_get_stats = _sig("raypc_server_get_stats", _I, _P, ctypes.POINTER(Server
 EXPORTED = ["raypc_server_start", "raypc_server_stop", "raypc_submit", "raypc_poll", "raypc_wait", "raypc_cancel",
             "raypc_request_times", "raypc_release", "raypc_server_get_stats",
             "raypc_create", "raypc_destroy", "raypc_last_error", "raypc_version", "raypc_load_fields",
-            "raypc_unload", "raypc_volume_info", "raypc_set_brush", "raypc_set_transfer_function",
+            "raypc_unload", "raypc_volume_info", "raypc_set_brush", "raypc_set_transfer_function", "raypc_set_transfer_function_async",
             "raypc_set_options", "raypc_select_lod", "raypc_render", "raypc_render_progressive",
             "raypc_export_level", "raypc_export_minmax", "raypc_export_minmax_sub", "raypc_export_skiplist",
             "raypc_export_subskip", "raypc_export_skip_words", "raypc_export_voxel_mask", "raypc_render_debug",
@@ -248,10 +249,15 @@ def set_coordinate_brush(ctx, volume_id: int, active, lo, hi) -> None:
 
 
 def set_transfer_function(ctx, slot: int, field: int, vmin: float, vmax: float, rgba,
-                          ref_step: float = 2.0 / 256) -> None:
+                          ref_step: float = 2.0 / 256, stream=None, ordered_on_stream: bool = False) -> None:
+    """ordered_on_stream: raypc_set_transfer_function_async on `stream` (the current one when None)."""
     t = np.ascontiguousarray(np.asarray(rgba, np.float32).reshape(-1))
-    _check(_set_tf(ctx, int(slot), int(field), float(vmin), float(vmax), t.ctypes.data, int(t.size // 4),
-                   float(ref_step)))
+    if ordered_on_stream:
+        _check(_set_tf_async(ctx, int(slot), int(field), float(vmin), float(vmax), t.ctypes.data, int(t.size // 4),
+                             float(ref_step), _stream(stream)))
+    else:
+        _check(_set_tf(ctx, int(slot), int(field), float(vmin), float(vmax), t.ctypes.data, int(t.size // 4),
+                       float(ref_step)))
 
 
 def set_options(ctx, ert: float = 0.99, bg=None) -> None:

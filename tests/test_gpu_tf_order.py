@@ -1,5 +1,5 @@
-"""GPU tests of transfer-function changes: they are stream-ordered (a render already enqueued keeps
-its table, a render enqueued after the change uses the new one) and do not wait for the device."""
+"""GPU tests of transfer-function changes: a render already enqueued keeps its table, a render
+enqueued after the change uses the new one, and the stream-ordered form does not wait."""
 import numpy as np
 import pytest
 import torch
@@ -28,7 +28,9 @@ def coloured(tab, v):
     return t
 
 
-def test_change_does_not_wait_and_is_ordered(rp):
+def test_change_is_ordered(rp):
+    """A render enqueued before a definition (behind queued work on its stream) keeps the old table;
+    one enqueued after it uses the new one."""
     ctx = rp.create(0)
     try:
         wl = W.make_workload(1, n=64, width=96, height=64)
@@ -51,12 +53,46 @@ def test_change_does_not_wait_and_is_ordered(rp):
                 torch.mm(x, x, out=y)
             got_a = rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step, stream=s)
             rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, tab_b, tf.ref_step)
-            busy = not s.query()         # the queued work has not finished: nothing waited for it
             got_b = rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step, stream=s)
         s.synchronize()
-        assert busy, "set_transfer_function waited for the stream"
         assert torch.equal(got_a, want_a) and torch.equal(got_b, want_b)
         assert not torch.equal(want_a, want_b)
+        rp.unload(ctx, vid)
+    finally:
+        rp.destroy(ctx)
+
+
+def test_change_on_a_stream_does_not_wait(rp):
+    """The stream-ordered definition returns while the stream's queued work still runs; the render
+    enqueued before it on that stream keeps the old table, the one after it uses the new one."""
+    ctx = rp.create(0)
+    try:
+        wl = W.make_workload(1, n=64, width=96, height=64)
+        tf = wl.tf
+        vid = setup(rp, ctx, wl)
+        cam = wl.camera.as_array()
+        tab_a, tab_b = coloured(tf.rgba, 0.25), coloured(tf.rgba, 0.75)
+        rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, tab_b, tf.ref_step)
+        want_b = rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step)
+        rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, tab_a, tf.ref_step)
+        want_a = rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step)
+        s = torch.cuda.Stream()
+        x = torch.randn(4096, 4096, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            for _ in range(40):
+                torch.mm(x, x, out=y)
+            got_a = rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step, stream=s)
+            t = tab_b.copy()
+            rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, t, tf.ref_step, stream=s,
+                                     ordered_on_stream=True)
+            busy = not s.query()         # the upload is queued behind the work: nothing waited for it
+            t[:] = 0.0                   # the caller's array may change at once (it was staged)
+            got_b = rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step, stream=s)
+        s.synchronize()
+        assert busy, "the stream-ordered definition waited for the stream"
+        assert torch.equal(got_a, want_a) and torch.equal(got_b, want_b)
         rp.unload(ctx, vid)
     finally:
         rp.destroy(ctx)
