@@ -506,6 +506,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--in-flight", type=int, default=2,
                     help="frames in flight in the timed loop (streams used in turn); 1 = serial")
+    ap.add_argument("--in-flight-sweep", default="",
+                    help="also time the headline storage's loop with each of these frames-in-flight counts")
     ap.add_argument("--storages", default="f16,f32,u8,u8c",
                     help="first one is the headline value; a trailing c keeps only the compact layout")
     ap.add_argument("--cpu-stride", type=int, default=1, help="oracle sample: every k-th row and column")
@@ -581,6 +583,10 @@ def main():
     raypc.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
     raypc.set_options(ctx, wl.ert)
     stream = torch.cuda.current_stream()
+    # the streams frames in flight use in turn, created once and one after the other (the runtime maps
+    # streams onto a few hardware queues in turn, so these land on different queues and can overlap)
+    n_streams = max([args.in_flight] + [int(x) for x in args.in_flight_sweep.split(",") if x])
+    flight_streams = [torch.cuda.Stream() for _ in range(n_streams)]
     out = torch.empty((H_, W_, 4), dtype=torch.float32, device="cuda")
     results = {}
     sweep_result = None
@@ -622,7 +628,7 @@ def main():
         # blocks drain; the skip flags of each brush are a new version, so frames in flight never share
         # them.  in_flight 1 is the serial loop.
         def timed_loop(n_flight, steps, warm):
-            sts = [stream] + [torch.cuda.Stream() for _ in range(n_flight - 1)]
+            sts = flight_streams[:n_flight]
             images = [out] + [torch.empty_like(out) for _ in range(n_flight - 1)]
             for s_ in range(warm):
                 b_ = brushes[s_ % len(brushes)]
@@ -646,6 +652,14 @@ def main():
 
         serial_wall, serial_samples, serial_lat = timed_loop(1, args.steps, args.warmup)
         wall, total_samples, lat = timed_loop(args.in_flight, args.steps, args.warmup)
+        in_flight_sweep = None
+        if si == 0 and args.in_flight_sweep:
+            in_flight_sweep = {}
+            for nf_ in (int(x) for x in args.in_flight_sweep.split(",")):
+                w_, t_, l_ = timed_loop(nf_, args.steps, args.warmup)
+                in_flight_sweep[str(nf_)] = {"ms_per_step": 1e3 * w_ / args.steps, "samples_per_s": t_ / w_,
+                                             "latency_p50_ms": percentile(l_, 50), "latency_p99_ms": percentile(l_, 99)}
+            print(f"[bench] frames in flight: {in_flight_sweep}", file=sys.stderr, flush=True)
 
         # kernel-only: fixed brush (skip bits cached), back-to-back launches on the same stream
         b = brushes[0]
@@ -688,6 +702,7 @@ def main():
             "frames_per_s": args.steps / wall,
             "ms_per_step": 1e3 * wall / args.steps,
             "frames_in_flight": args.in_flight,
+            "frames_in_flight_sweep": in_flight_sweep,
             "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat)},
             "serial": {"frames_in_flight": 1, "samples_per_s": serial_samples / serial_wall,
                        "frames_per_s": args.steps / serial_wall, "ms_per_step": 1e3 * serial_wall / args.steps,
