@@ -169,9 +169,12 @@ int raypc_set_brush(raypc_ctx *ctx, int volume_id, int n_fields, const uint8_t *
  * after the call returns use the new one.  The upload runs on the context's own
  * stream and the call waits for that copy, not for a device drain (the runtime
  * may map that stream onto a hardware queue it shares with other streams, whose
- * earlier work the copy then waits behind); only every 256th definition of a
- * slot (when its versions wrap) waits for the device.  Serving requests copy the
- * table at submission.  Errors: RAYPC_ERR_INVALID, RAYPC_ERR_DEVICE.
+ * earlier work the copy then waits behind).  A slot keeps 256 versions; a
+ * version is rewritten only after the launches that read it have finished (an
+ * event per version and stream, recorded by every render), so a definition
+ * waits only if renders enqueued 256 definitions earlier are still running.
+ * Serving requests copy the table at submission.  Errors: RAYPC_ERR_INVALID,
+ * RAYPC_ERR_DEVICE.
  */
 int raypc_set_transfer_function(raypc_ctx *ctx, int slot, int field, float vmin, float vmax, const float *rgba,
                                 int n_entries, float ref_step);

@@ -214,10 +214,8 @@ void build_skip_args(const raypc_ctx* ctx, const Volume* v, int l, const uint8_t
 // Recompute the skip bits and sub-brick flags of level l for the volume's own brush and a transfer
 // slot if stale.
 // Record that a launch on `s` read the current skip-flag version of level l (call after the launch).
-static int note_skip_use(Level& L, hipStream_t s) {
-    if (L.skip_cur < 0) return RAYPC_OK;
-    auto& users = L.skip_users[L.skip_cur];
-    SkipUser* u = nullptr;
+static int note_use(std::vector<StreamUse>& users, hipStream_t s) {
+    StreamUse* u = nullptr;
     for (auto& x : users)
         if (x.stream == s) u = &x;  // later work on a stream completes after its earlier work
     if (!u) {
@@ -226,8 +224,30 @@ static int note_skip_use(Level& L, hipStream_t s) {
         users.push_back({s, e});
         u = &users.back();
     }
-    HIP_TRY(hipEventRecord(u->done, s), "hipEventRecord(skip flags in use)");
+    HIP_TRY(hipEventRecord(u->done, s), "hipEventRecord(version in use)");
     return RAYPC_OK;
+}
+
+// Wait (on the host) until every recorded use of a version has finished, then forget them.
+static int wait_uses(std::vector<StreamUse>& users) {
+    int rc = RAYPC_OK;
+    for (auto& u : users) {
+        const hipError_t e = hipEventSynchronize(u.done);
+        if (e != hipSuccess && !rc) rc = hip_fail(e, "hipEventSynchronize(version in use)");
+    }
+    for (auto& u : users) (void)hipEventDestroy(u.done);
+    users.clear();
+    return rc;
+}
+
+static int note_skip_use(Level& L, hipStream_t s) {
+    return L.skip_cur < 0 ? RAYPC_OK : note_use(L.skip_users[L.skip_cur], s);
+}
+
+// Record that a launch on `s` read the current table version of a transfer-function slot.
+static int note_tf_use(raypc_ctx* ctx, int slot, hipStream_t s) {
+    TFSlot& t = ctx->tf[slot];
+    return t.version < 0 ? RAYPC_OK : note_use(t.users[t.version], s);
 }
 
 static int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s) {
@@ -238,9 +258,10 @@ static int ensure_skip(raypc_ctx* ctx, Volume* v, int l, int slot, hipStream_t s
     // the next version: wait (on the host) only for the launches that read it when it was current,
     // long ago in the usual case; a render on another stream may still read the current version
     const int next = (L.skip_cur + 1) % kSkipVersions;
-    for (auto& u : L.skip_users[next]) HIP_TRY(hipEventSynchronize(u.done), "hipEventSynchronize(skip flags)");
-    for (auto& u : L.skip_users[next]) (void)hipEventDestroy(u.done);
-    L.skip_users[next].clear();
+    {
+        const int rc = wait_uses(L.skip_users[next]);
+        if (rc) return rc;
+    }
     SkipArgs a;
     build_skip_args(ctx, v, l, v->active, v->lo, v->hi, v->coord, slot, a);
     a.out_sub = L.skip_ver[next];
@@ -483,7 +504,11 @@ int raypc_create(int device, raypc_ctx** out) {
     }
     e = hipStreamCreateWithFlags(&ctx->upload, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        for (auto& t : ctx->tf) (void)hipFree(t.pool);
+        for (auto& t : ctx->tf) {
+        for (auto& users : t.users)
+            for (auto& u : users) (void)hipEventDestroy(u.done);
+        (void)hipFree(t.pool);
+    }
         delete ctx;
         return hip_fail(e, "hipStreamCreateWithFlags(upload stream)");
     }
@@ -497,7 +522,11 @@ void raypc_destroy(raypc_ctx* ctx) {
     server_shutdown(ctx);
     (void)hipDeviceSynchronize();
     for (auto& kv : ctx->vols) free_volume(kv.second);
-    for (auto& t : ctx->tf) (void)hipFree(t.pool);
+    for (auto& t : ctx->tf) {
+        for (auto& users : t.users)
+            for (auto& u : users) (void)hipEventDestroy(u.done);
+        (void)hipFree(t.pool);
+    }
     if (ctx->upload) (void)hipStreamDestroy(ctx->upload);
     if (ctx->tf_stage) (void)hipHostFree(ctx->tf_stage);
     for (auto* k : ctx->warp_keys)
@@ -776,16 +805,17 @@ static int set_tf_impl(raypc_ctx* ctx, int slot, int field, float vmin, float vm
     // the new table goes to the slot's next version: renders already enqueued (on any stream) keep
     // reading the version they were given; renders enqueued after this call read the new one
     const int next = (t.version + 1) % kTFVersions;
-    if (next == 0 && t.version >= 0) {
-        // the ring wraps (once every kTFVersions definitions of the slot): version 0 may still be read
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    // the launches that read this version, kTFVersions definitions ago, and its upload have finished
+    // long since in the usual case; wait for them otherwise
+    {
+        const int rc = wait_uses(t.users[next]);
+        if (rc) return rc;
     }
     float4* dst = t.pool + size_t(next) * RAYPC_TF_ENTRIES;
     hipError_t e = hipSuccess;
     if (async) {
-        // a pinned staging copy per (slot, version): reused only after the versions wrap, which drains
-        // the device first, so no pending upload still reads it
+        // a pinned staging copy per (slot, version), reused only after this version's upload (a
+        // recorded use) has finished
         if (!ctx->tf_stage) {
             e = hipHostMalloc(reinterpret_cast<void**>(&ctx->tf_stage),
                               size_t(RAYPC_TF_SLOTS) * kTFVersions * RAYPC_TF_ENTRIES * sizeof(float4), hipHostMallocDefault);
@@ -797,6 +827,10 @@ static int set_tf_impl(raypc_ctx* ctx, int slot, int field, float vmin, float vm
         float4* stage = ctx->tf_stage + (size_t(slot) * kTFVersions + next) * RAYPC_TF_ENTRIES;
         std::memcpy(stage, rgba, RAYPC_TF_ENTRIES * sizeof(float4));
         e = hipMemcpyAsync(dst, stage, RAYPC_TF_ENTRIES * sizeof(float4), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) {
+            const int rc = note_use(t.users[next], stream);
+            if (rc) return rc;
+        }
     } else {
         // on the context's own non-blocking stream: waits for this copy (and for whatever the runtime
         // queued ahead of it on the hardware queue that stream shares), not for a device drain
@@ -872,6 +906,8 @@ static int render_common(raypc_ctx* ctx, int volume_id, const raypc_camera* cam,
     a.evaluated = evaluated;
     a.fetched = fetched;
     HIP_TRY(launch_render(a, storage, counts, s), "ray-march kernel launch");
+    rc = note_tf_use(ctx, 0, s);
+    if (rc) return rc;
     return a.skip ? note_skip_use(v->lv[level], s) : RAYPC_OK;
 }
 
@@ -924,6 +960,8 @@ int raypc_render_jittered(raypc_ctx* ctx, int volume_id, const raypc_camera* cam
     a.mean = reinterpret_cast<float4*>(mean_inout);
     HIP_TRY(launch_render_jittered(a, storage, nominal != nullptr || composited != nullptr, s),
             "jittered ray-march kernel launch");
+    rc = note_tf_use(ctx, 0, s);
+    if (rc) return rc;
     return note_skip_use(v->lv[level], s);
 }
 
@@ -943,6 +981,8 @@ int raypc_render_depth(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, i
     if (rc) return rc;
     a.depth = depth_out;
     HIP_TRY(launch_render_depth(a, storage, s), "depth ray-march kernel launch");
+    rc = note_tf_use(ctx, 0, s);
+    if (rc) return rc;
     return note_skip_use(v->lv[level], s);
 }
 

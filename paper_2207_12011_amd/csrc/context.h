@@ -21,9 +21,11 @@ constexpr int kDefaultSuperLog2 = 2;  // default launch shape: super-tiles of 4 
 // is overwritten only after the renders that read it have finished (their events).
 constexpr int kSkipVersions = 4;
 
-struct SkipUser {
+// A stream's last use of one version of a buffer that several versions take turns in (skip flags,
+// transfer-function tables): the version is overwritten only after every such event has completed.
+struct StreamUse {
     hipStream_t stream;
-    hipEvent_t done;  // recorded on `stream` after its last launch that read the version
+    hipEvent_t done;  // recorded on `stream` after its last launch (or copy) that read the version
 };
 
 struct Level {
@@ -36,7 +38,7 @@ struct Level {
     uint16_t* skip_sub = nullptr; // per brick: sub-brick skip flags (bits 0-7) and empty-group bits (8, 9)
                                   // of the current version (= skip_ver[skip_cur])
     uint16_t* skip_ver[kSkipVersions] = {};
-    std::vector<SkipUser> skip_users[kSkipVersions];  // launches that read each version
+    std::vector<StreamUse> skip_users[kSkipVersions];  // launches that read each version
     int skip_cur = -1;
     bool skip_valid = false;
     uint64_t skip_brush_gen = 0, skip_tf_gen = 0;
@@ -83,8 +85,8 @@ constexpr int kOrderSample = 2048;  // sampled shell cells per volume
 void brush_order(Volume* v, const uint8_t* active, const float* lo, const float* hi, int* order, int& n_brushed);
 
 // Versions of a slot's device table kept before one is overwritten: a new table goes to the next
-// version, so renders already enqueued keep reading theirs; only when the ring wraps does the next
-// definition wait for the device.
+// version, so renders already enqueued keep reading theirs; a version is rewritten only after the
+// launches that read it (and the upload that wrote it) have finished, 256 definitions later.
 constexpr int kTFVersions = 256;
 
 // Factor by which the ray march sees field f of v: binary16 codes hold the values times 2^k.
@@ -99,6 +101,7 @@ struct TFSlot {
     float4* pool = nullptr;  // kTFVersions tables of RAYPC_TF_ENTRIES entries
     int version = -1;        // the current one
     float4* dev = nullptr;   // = pool + version * RAYPC_TF_ENTRIES
+    std::vector<StreamUse> users[kTFVersions];  // launches and uploads that read each version
 };
 
 }  // namespace raypc

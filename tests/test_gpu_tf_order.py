@@ -98,9 +98,11 @@ def test_change_on_a_stream_does_not_wait(rp):
         rp.destroy(ctx)
 
 
-def test_many_changes_wrap_the_versions(rp):
+@pytest.mark.parametrize("ordered_on_stream", [False, True])
+def test_many_changes_wrap_the_versions(rp, ordered_on_stream):
     """More definitions of a slot than it keeps versions (256): every render, enqueued between two
-    definitions without waiting, used the table defined just before it."""
+    definitions without waiting, used the table defined just before it (with the stream-ordered
+    form, the staging copies are reused too)."""
     ctx = rp.create(0)
     try:
         wl = W.make_workload(1, n=64, width=32, height=32)
@@ -108,11 +110,12 @@ def test_many_changes_wrap_the_versions(rp):
         vid = setup(rp, ctx, wl)
         cam = wl.camera.as_array()
         outs = []
-        n = 300
+        n = 600
+        s = torch.cuda.current_stream()
         for i in range(n):
             rp.set_transfer_function(ctx, 0, tf.field, tf.vmin, tf.vmax, coloured(tf.rgba, (i + 1) / (n + 1)),
-                                     tf.ref_step)
-            outs.append(rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step))
+                                     tf.ref_step, stream=s, ordered_on_stream=ordered_on_stream)
+            outs.append(rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step, stream=s))
         torch.cuda.synchronize()
         for i, o in enumerate(outs):
             a = o.cpu().numpy()
