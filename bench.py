@@ -85,8 +85,9 @@ def profile(args, wl, raypc, torch):
     out = torch.empty((wl.height, wl.width, 4), dtype=torch.float32, device="cuda")
     cam = wl.camera.as_array()
     # the launch shape the benchmark would pick; the profiled frames are the last launches
-    best, times = raypc.autotune_render(ctx, vid, cam, wl.width, wl.height, -1, wl.step, 5)
-    print(f"[bench] profile mode: launch shape {8 << best} px super-tiles (ms by shape: {times})", file=sys.stderr)
+    (bs, bt), times = raypc.autotune_render(ctx, vid, cam, wl.width, wl.height, -1, wl.step, 5)
+    print(f"[bench] profile mode: launch shape: {1 << bt}x{16 >> bt} px wave tiles, super_log2 {bs} "
+          f"(ms by [tile][super]: {times})", file=sys.stderr)
     torch.cuda.synchronize()
     for _ in range(args.profile_frames):
         raypc.render(ctx, vid, cam, wl.width, wl.height, -1, wl.step, out=out)
@@ -720,8 +721,10 @@ def main():
             "orbit_latency_ms": {"frames": len(olat), "p50": percentile(olat, 50), "p99": percentile(olat, 99),
                                  "max": max(olat), "cameras": "seeded orbit: azimuth U[0, 360), elevation U[-60, 60] deg, "
                                                               "distance 3, up +z, 60 deg"},
-            "launch_shape": {"super_tile_px": shape["tile_px"], "ms_by_super_tile_px":
-                             {str(8 << k): t for k, t in enumerate(shape["ms"])}},
+            "launch_shape": {"wave_tile_px": shape["wave_tile_px"], "super_tile_px": shape["super_tile_px"],
+                             "ms_by_wave_tile_and_super_log2":
+                             {f"{1 << t}x{16 >> t}": {str(k): ms for k, ms in enumerate(row)}
+                              for t, row in enumerate(shape["ms"])}},
         }
         print(f"[bench] {storage}: {results[storage]}", file=sys.stderr, flush=True)
         if si == 0 and not args.no_sweep:

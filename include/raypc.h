@@ -262,24 +262,29 @@ int raypc_render_jittered(raypc_ctx *ctx, int volume_id, const raypc_camera *cam
                           float step, int pass, int n_passes, uint64_t seed, float *rgba_out, float *mean_inout,
                           uint32_t *nominal, uint32_t *composited, void *stream);
 
-/* Launch shape of single-image renders (raypc_render, _debug, _progressive, _jittered, _depth): the
- * 4x4-pixel tiles (one wave each) are dealt to the 8 XCDs in super-tiles of 8 << s pixels square
- * (s = super_log2 in 0..3; default 2, 32x32 pixels), round-robin, so that a super-tile's rays share
- * one XCD's L2 while every XCD gets tiles from all over the image.  The shape changes timing only,
- * never an image.  Serving launches keep 32x32-pixel super-tiles.  Errors: RAYPC_ERR_INVALID. */
-int raypc_set_launch_shape(raypc_ctx *ctx, int super_log2);
-int raypc_get_launch_shape(raypc_ctx *ctx, int *super_log2);
+/* Launch shape of single-image renders (raypc_render, _debug, _progressive, _jittered, _depth, _work):
+ *   tile_log2w  t in 0..4: each wave marches the 16 rays of a (1 << t) x (16 >> t) pixel tile
+ *               (1x16, 2x8, 4x4, 8x2 or 16x1; default 2, 4x4), four lanes per ray;
+ *   super_log2  s in 0..3: the tiles are dealt to the 8 XCDs in super-tiles of 2^(s+1) x 2^(s+1)
+ *               tiles (default 2: 32x32 pixels with 4x4 tiles), round-robin, so that a super-tile's
+ *               rays share one XCD's L2 while every XCD gets tiles from all over the image.
+ * The shape changes timing only, never an image (every ray is marched by its own four lanes, the
+ * same way whatever tile it is in).  Serving launches keep 4x4 tiles and 32x32-pixel super-tiles.
+ * Errors: RAYPC_ERR_INVALID. */
+int raypc_set_launch_shape(raypc_ctx *ctx, int super_log2, int tile_log2w);
+int raypc_get_launch_shape(raypc_ctx *ctx, int *super_log2, int *tile_log2w);
 
 /* Autotuner of the launch shape: renders the given view (as raypc_render, with the volume's brush
- * and transfer slot 0) once untimed and then `repeats` (1..1000) times back to back for each
- * super-tile size s = 0..3, timing each run with HIP events on a stream of its own, and makes the
- * fastest the context's launch shape (the default s = 2 stays unless another shape is more than
- * 1 % faster, so that runs on one device agree).  times_ms (4 floats, may be NULL) receives the mean time of
- * one render per s; best (may be NULL) the chosen s.  Synchronous; allocates one image for the
- * duration of the call.  On error the previous launch shape stays.  Errors: as raypc_render, plus
+ * and transfer slot 0) once untimed and then `repeats` (1..1000) times back to back for each of the
+ * 20 shapes (tile_log2w t = 0..4, super_log2 s = 0..3), timing each run with HIP events on a stream
+ * of its own, and makes the fastest the context's launch shape (the default t = 2, s = 2 stays
+ * unless another shape is more than 1 % faster, so that runs on one device agree).  times_ms (20
+ * floats, index 4 t + s; may be NULL) receives the mean time of one render per shape; best_super and
+ * best_tile (may be NULL) the chosen shape.  Synchronous; allocates one image for the duration of
+ * the call.  On error the previous launch shape stays.  Errors: as raypc_render, plus
  * RAYPC_ERR_INVALID for repeats out of range and RAYPC_ERR_NOMEM. */
 int raypc_autotune_render(raypc_ctx *ctx, int volume_id, const raypc_camera *cam, int width, int height, int lod,
-                          float step, int repeats, float *times_ms, int *best);
+                          float step, int repeats, float *times_ms, int *best_super, int *best_tile);
 
 /* raypc_render plus the depth that image warping reprojects with (Sections 2 and 2.2 warp the last
  * delivered image to fill the frames the renderer has not produced yet; the paper names no depth,

@@ -2,9 +2,10 @@
 
 Two knobs change how fast the renderer runs without changing any image:
 
-* the launch shape of single-image renders: the size of the super-tiles (2^s x 2^s tiles of 8x8
-  pixels) dealt round-robin over the XCDs.  ``raypc_autotune_render`` times every s on a view on
-  the device and keeps the fastest; here its result is cached per device and workload class;
+* the launch shape of single-image renders: the shape of the pixel tile one wave marches (1x16 to
+  16x1 pixels, 2^t wide) and the size of the super-tiles of such tiles dealt round-robin over the
+  XCDs (2^(s+1) tiles on a side).  ``raypc_autotune_render`` times all 20 shapes on a view on the
+  device and keeps the fastest; here its result is cached per device and workload class;
 * the serving step: how many tiles one batched launch marches (``tiles_per_step``) and how many
   steps may be in flight at once (``steps_in_flight``).  ``tune_server`` replays a burst of
   requests through the public serving calls for each candidate and keeps the one that finishes
@@ -68,10 +69,12 @@ def tune_render(rp, ctx, volume_id: int, camera, width: int, height: int, lod: i
     (the caller saves it)."""
     if cache is not None and key is not None and key in cache and not retune:
         entry = cache[key]
-        rp.set_launch_shape(ctx, int(entry["super_log2"]))
+        rp.set_launch_shape(ctx, int(entry["super_log2"]), int(entry["tile_log2w"]))
         return dict(entry, cached=True)
-    best, times = rp.autotune_render(ctx, volume_id, camera, width, height, lod, step, repeats)
-    entry = {"super_log2": best, "tile_px": 8 << best, "ms": times, "repeats": repeats}
+    (s, t), times = rp.autotune_render(ctx, volume_id, camera, width, height, lod, step, repeats)
+    entry = {"super_log2": s, "tile_log2w": t, "wave_tile_px": [1 << t, 16 >> t],
+             "super_tile_px": [(1 << t) << (s + 1), (16 >> t) << (s + 1)],
+             "ms": times, "repeats": repeats}
     if cache is not None and key is not None:
         cache[key] = entry
     return dict(entry, cached=False)

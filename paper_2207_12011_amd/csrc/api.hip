@@ -454,8 +454,13 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
     a.ds = step * (2.0f / static_cast<float>(L.n));
     a.inv_ds = 1.0f / a.ds;
     a.out = reinterpret_cast<float4*>(rgba_out);
-    a.blocks_x = (width + kBlockPix - 1) / kBlockPix;
-    a.n_blocks = a.blocks_x * ((height + kBlockPix - 1) / kBlockPix);
+    // single-image launches take the context's wave tile shape; serving steps keep 4 x 4 tiles
+    a.tile_log2w = use_volume_state ? ctx->tile_log2w : kDefaultTileLog2W;
+    {
+        const int tw = 1 << a.tile_log2w, th = 16 >> a.tile_log2w;
+        a.blocks_x = (width + tw - 1) / tw;
+        a.n_blocks = a.blocks_x * ((height + th - 1) / th);
+    }
     a.super_log2 = ctx->super_log2;
     a.skip = nullptr;
     if (use_volume_state) {
@@ -1118,24 +1123,28 @@ int raypc_measure_peaks(raypc_ctx* ctx, double* copy_bytes_per_s, double* fma_la
     return RAYPC_OK;
 }
 
-int raypc_set_launch_shape(raypc_ctx* ctx, int super_log2) {
+int raypc_set_launch_shape(raypc_ctx* ctx, int super_log2, int tile_log2w) {
     if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
     if (super_log2 < 0 || super_log2 > kMaxSuperLog2)
         return fail(RAYPC_ERR_INVALID, "super_log2 %d outside [0, %d]", super_log2, kMaxSuperLog2);
+    if (tile_log2w < 0 || tile_log2w > kMaxTileLog2W)
+        return fail(RAYPC_ERR_INVALID, "tile_log2w %d outside [0, %d]", tile_log2w, kMaxTileLog2W);
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->super_log2 = super_log2;
+    ctx->tile_log2w = tile_log2w;
     return RAYPC_OK;
 }
 
-int raypc_get_launch_shape(raypc_ctx* ctx, int* super_log2) {
-    if (!ctx || !super_log2) return fail(RAYPC_ERR_INVALID, "NULL argument");
+int raypc_get_launch_shape(raypc_ctx* ctx, int* super_log2, int* tile_log2w) {
+    if (!ctx || !super_log2 || !tile_log2w) return fail(RAYPC_ERR_INVALID, "NULL argument");
     std::lock_guard<std::mutex> lk(ctx->mu);
     *super_log2 = ctx->super_log2;
+    *tile_log2w = ctx->tile_log2w;
     return RAYPC_OK;
 }
 
 int raypc_autotune_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int width, int height, int lod,
-                          float step, int repeats, float* times_ms, int* best) {
+                          float step, int repeats, float* times_ms, int* best_super, int* best_tile) {
     if (!ctx) return fail(RAYPC_ERR_INVALID, "ctx is NULL");
     if (repeats < 1 || repeats > 1000) return fail(RAYPC_ERR_INVALID, "repeats %d outside [1, 1000]", repeats);
     DeviceGuard g(ctx->device);
@@ -1149,22 +1158,25 @@ int raypc_autotune_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam
         (void)hipGetLastError();
         return fail(RAYPC_ERR_NOMEM, "autotune image of %zu bytes", bytes);
     }
+    constexpr int kSupers = kMaxSuperLog2 + 1, kShapes = (kMaxTileLog2W + 1) * kSupers;
     int rc = RAYPC_OK;
-    float t[kMaxSuperLog2 + 1];
-    int saved = 2;
+    float t[kShapes];
+    int saved_super = kDefaultSuperLog2, saved_tile = kDefaultTileLog2W;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        saved = ctx->super_log2;
+        saved_super = ctx->super_log2;
+        saved_tile = ctx->tile_log2w;
     }
     do {
         hipError_t e = hipStreamCreate(&s);
         if (e == hipSuccess) e = hipEventCreate(&e0);
         if (e == hipSuccess) e = hipEventCreate(&e1);
         if (e != hipSuccess) { rc = hip_fail(e, "autotune stream / events"); break; }
-        for (int c = 0; c <= kMaxSuperLog2 && !rc; ++c) {
+        for (int c = 0; c < kShapes && !rc; ++c) {
             {
                 std::lock_guard<std::mutex> lk(ctx->mu);
-                ctx->super_log2 = c;
+                ctx->tile_log2w = c / kSupers;
+                ctx->super_log2 = c % kSupers;
             }
             // one untimed render (skip state, caches), then `repeats` timed back to back
             rc = raypc_render(ctx, volume_id, cam, width, height, lod, step, out, s);
@@ -1178,20 +1190,25 @@ int raypc_autotune_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam
         }
     } while (0);
     if (s) (void)hipStreamSynchronize(s);
-    int b = saved;
+    int bs = saved_super, bt = saved_tile;
     if (!rc) {
         // the default shape stays unless another is faster by more than the timing noise (1 %), so
         // that runs on one device agree on the shape
-        b = kDefaultSuperLog2;
-        for (int c = 0; c <= kMaxSuperLog2; ++c)
-            if (t[c] < t[b] && t[c] < 0.99f * t[kDefaultSuperLog2]) b = c;
+        const int def = kDefaultTileLog2W * kSupers + kDefaultSuperLog2;
+        int b = def;
+        for (int c = 0; c < kShapes; ++c)
+            if (t[c] < t[b] && t[c] < 0.99f * t[def]) b = c;
+        bt = b / kSupers;
+        bs = b % kSupers;
         if (times_ms)
-            for (int c = 0; c <= kMaxSuperLog2; ++c) times_ms[c] = t[c];
-        if (best) *best = b;
+            for (int c = 0; c < kShapes; ++c) times_ms[c] = t[c];
+        if (best_super) *best_super = bs;
+        if (best_tile) *best_tile = bt;
     }
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->super_log2 = b;  // the winner, or the previous shape when tuning failed
+        ctx->super_log2 = bs;  // the winner, or the previous shape when tuning failed
+        ctx->tile_log2w = bt;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

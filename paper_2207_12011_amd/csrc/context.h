@@ -124,7 +124,8 @@ struct raypc_ctx {
     size_t warp_clean_n[2] = {0, 0};  // leading pixels of each known to hold the empty key
     int warp_cur = 0;              // the buffer the next warp splats into
     unsigned long long* warp_scratch = nullptr;  // this device's fixed z-buffer (raypc_warp_noalloc)
-    int super_log2 = raypc::kDefaultSuperLog2;  // launch shape of single-image renders (raypc_set_launch_shape)
+    int super_log2 = raypc::kDefaultSuperLog2;  // launch shape of single-image renders (raypc_set_launch_shape):
+    int tile_log2w = raypc::kDefaultTileLog2W;  // super-tile size and wave tile shape
 };
 
 

@@ -14,7 +14,7 @@ namespace raypc {
 constexpr int kMaxFields = 8;
 constexpr int kBrick = 8;           // brick edge in voxels
 constexpr int kBrickVoxels = 512;   // 8^3
-constexpr int kBlockPix = 4;        // a ray-march block is one wave and covers 4 x 4 pixels
+constexpr int kBlockPix = 4;        // a serving step's wave tiles are 4 x 4 pixels
 
 enum Storage : int { kF32 = 0, kF16 = 1, kU8 = 2 };
 // Kernel variants: a storage type, read from the compact layout or from neighbourhood records.
@@ -198,8 +198,9 @@ struct RenderArgs {
     uint32_t* touched;            // debug: bit per brick read by an evaluated sample (may be null)
     uint32_t* evaluated;          // debug: per pixel, samples not skipped, up to the termination stop (may be null)
     uint32_t* fetched;            // debug: per pixel, field values interpolated for those samples (may be null)
-    int blocks_x, n_blocks;       // 4 x 4 pixel blocks (tiles) per row, total
-    int super_log2;               // single-image launches: super-tiles of 8 << s pixels dealt over the XCDs
+    int blocks_x, n_blocks;       // wave tiles per row, total
+    int tile_log2w;               // a wave tile is (1 << t) x (16 >> t) pixels (serving: t = 2, 4 x 4)
+    int super_log2;               // single-image launches: super-tiles of 2^(s+1) x 2^(s+1) wave tiles dealt over the XCDs
     // jittered progressive passes (jittered kernels only): pass `pass` of `n_passes` shifts each
     // pixel's sample grid by s ds, s from a SplitMix64 stream at `seed`; `mean` (may be null)
     // holds the running mean of the passes, updated with weight inv_pass1 = 1 / (pass + 1)
@@ -212,7 +213,9 @@ struct RenderArgs {
 hipError_t launch_render(const RenderArgs& a, int kind, bool counts, hipStream_t s);
 hipError_t launch_render_jittered(const RenderArgs& a, int kind, bool counts, hipStream_t s);
 hipError_t launch_render_depth(const RenderArgs& a, int kind, hipStream_t s);
-constexpr int kMaxSuperLog2 = 3;  // super-tiles of up to 8 x 8 blocks (64 x 64 pixels)
+constexpr int kMaxSuperLog2 = 3;  // super-tiles of up to 16 x 16 wave tiles (64 x 64 pixels for 4 x 4 tiles)
+constexpr int kMaxTileLog2W = 4;  // wave tiles from 1 x 16 (t = 0) to 16 x 1 (t = 4) pixels
+constexpr int kDefaultTileLog2W = 2;  // 4 x 4 pixels
 
 // Image warping: a camera's frame in float32 (the render's frame), and one warp's buffers.
 struct WarpCamera {

@@ -16,7 +16,7 @@ namespace {
 constexpr float kSkipShrink = 2e-3f;  // voxels: shrink of a skipped box before computing its exit
 constexpr float kSkipMargin = 0.01f;  // samples: margin on the first sample after a skipped box
 constexpr int kQuad = 4;              // lanes (consecutive samples) per ray
-constexpr int kWaveTile = 4;          // a wave covers 4 x 4 pixels (16 rays)
+constexpr int kWaveRays = 16;         // a wave marches 16 rays, on a tile of (1 << t) x (16 >> t) pixels
 
 // Global-memory view of a pointer.  Pointers read from memory (the batched launch takes its
 // arguments from a device array) would otherwise be accessed with generic flat loads.
@@ -249,8 +249,9 @@ __device__ __forceinline__ void tile_coords(int i, int bx_count, int by_count, i
     }
 }
 
-// Single-image launches deal super-tiles of 2^s x 2^s tiles (8 << A.super_log2 pixels square for the
-// launch-shape parameter A.super_log2, see launch_tiles; the serving path keeps 32 pixels): the j-th
+// Single-image launches deal super-tiles of 2^s x 2^s blocks (2^(A.super_log2 + 1) wave tiles on a
+// side for the launch-shape parameter A.super_log2, see launch_tiles: 8 << A.super_log2 pixels square
+// with 4 x 4 tiles; the serving path keeps 32 pixels): the j-th
 // block an XCD receives is tile j % 4^s of super-tile (j / 4^s) * 8 + xcd (super-tiles row-major over
 // the image).  The grid is padded to whole rounds of 8 super-tiles; blocks outside the image return
 // at once.
@@ -317,11 +318,13 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
     constexpr int RT = record_type_of(K);
-    constexpr int BT = BW == 4 ? 2 * kWaveTile : kWaveTile;  // block tile: 2 x 2 waves or one
+    // the wave tile: tw x th pixels, tw = 2^t (A.tile_log2w), th = 16 / tw; a block of four waves
+    // takes 2 x 2 wave tiles
+    const int tl = A.tile_log2w, tw = 1 << tl, th = kWaveRays >> tl;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ray = lane >> 2, sub = lane & 3, quad_base = lane & ~3;
-    const int px = bx * BT + (wave & 1) * kWaveTile + (ray & 3);
-    const int py = by * BT + (wave >> 1) * kWaveTile + (ray >> 2);
+    const int px = (BW == 4 ? 2 * bx + (wave & 1) : bx) * tw + (ray & (tw - 1));
+    const int py = (BW == 4 ? 2 * by + (wave >> 1) : by) * th + (ray >> tl);
     const bool inside = px < A.width && py < A.height;
 
     // ---- ray through the pixel centre (identical in the four lanes of the quad)
@@ -695,8 +698,8 @@ __device__ __forceinline__ KernelArgsPtr late_args() {
     return p;
 }
 
-// Tiles of a single-image launch: the host counts 4 x 4 pixel tiles (blocks_x per row); blocks of four
-// waves take 8 x 8 pixels, and super-tiles of 2^s x 2^s such tiles keep 8 << super_log2 pixels.
+// Tiles of a single-image launch: the host counts wave tiles (blocks_x per row); blocks of four waves
+// take 2 x 2 of them, and super-tiles hold 2^(s+1) x 2^(s+1) wave tiles (s = super_log2) either way.
 struct LaunchTiles {
     int cols, rows, s;
 };
@@ -709,11 +712,12 @@ __host__ __device__ inline LaunchTiles launch_tiles(int blocks_x, int n_blocks, 
 
 template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true>
 __global__ __launch_bounds__(64 * block_waves(K, WIDE)) void raymarch_kernel(RenderArgs A) {
-    constexpr int BW = block_waves(K, WIDE), BT = BW == 4 ? 2 * kWaveTile : kWaveTile;
+    constexpr int BW = block_waves(K, WIDE), BS = BW == 4 ? 2 : 1;  // wave tiles per block side
     const LaunchTiles lt = launch_tiles<BW>(A.blocks_x, A.n_blocks, A.super_log2);
     int bx, by;
     interleaved_tile(blockIdx.x, lt.cols, lt.s, bx, by);
-    if (by * BT >= A.height || bx * BT >= A.width) return;  // padding block
+    if (by * BS * (kWaveRays >> A.tile_log2w) >= A.height || bx * BS * (1 << A.tile_log2w) >= A.width)
+        return;  // padding block
     __shared__ float4 s_tf[256];
     march_tile<K, NB, COUNTS, JIT, DEPTH, WIDE, BW>(A, late_args(), bx, by, s_tf);
 }

@@ -95,10 +95,10 @@ _measure_peaks = _sig("raypc_measure_peaks", _I, _P, ctypes.POINTER(ctypes.c_dou
                       _P)
 _render_work = _sig("raypc_render_work", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P, _P)
 _render_depth = _sig("raypc_render_depth", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _P, _P, _P)
-_set_launch_shape = _sig("raypc_set_launch_shape", _I, _P, _I)
-_get_launch_shape = _sig("raypc_get_launch_shape", _I, _P, ctypes.POINTER(_I))
+_set_launch_shape = _sig("raypc_set_launch_shape", _I, _P, _I, _I)
+_get_launch_shape = _sig("raypc_get_launch_shape", _I, _P, ctypes.POINTER(_I), ctypes.POINTER(_I))
 _autotune_render = _sig("raypc_autotune_render", _I, _P, _I, ctypes.POINTER(Camera), _I, _I, _I, _F, _I, _P,
-                        ctypes.POINTER(_I))
+                        ctypes.POINTER(_I), ctypes.POINTER(_I))
 _warp = _sig("raypc_warp", _I, _P, ctypes.POINTER(Camera), _I, _I, _P, _P, ctypes.POINTER(Camera), _I, _I, _P, _P, _P,
              _P)
 _warp_noalloc = _sig("raypc_warp_noalloc", _I, _P, ctypes.POINTER(Camera), _I, _I, _P, _P, ctypes.POINTER(Camera), _I,
@@ -356,25 +356,31 @@ def render_jittered(ctx, volume_id: int, camera, width: int, height: int, lod: i
     return out, nom, comp
 
 
-def set_launch_shape(ctx, super_log2: int) -> None:
-    _check(_set_launch_shape(ctx, int(super_log2)))
+TILE_SHAPES = tuple((1 << t, 16 >> t) for t in range(5))   # wave tile (width, height) per tile_log2w
+SUPER_LOG2S = (0, 1, 2, 3)
 
 
-def get_launch_shape(ctx) -> int:
-    s = _I()
-    _check(_get_launch_shape(ctx, ctypes.byref(s)))
-    return s.value
+def set_launch_shape(ctx, super_log2: int, tile_log2w: int = 2) -> None:
+    _check(_set_launch_shape(ctx, int(super_log2), int(tile_log2w)))
+
+
+def get_launch_shape(ctx):
+    """(super_log2, tile_log2w) of the context's single-image launches."""
+    s, t = _I(), _I()
+    _check(_get_launch_shape(ctx, ctypes.byref(s), ctypes.byref(t)))
+    return s.value, t.value
 
 
 def autotune_render(ctx, volume_id: int, camera, width: int, height: int, lod: int = -1, step: float = 0.5,
                     repeats: int = 10):
-    """Time the launch shapes on this view and keep the fastest: (best super_log2, [ms per render for
-    super_log2 = 0..3])."""
-    times = (_F * 4)()
-    best = _I()
+    """Time the launch shapes on this view and keep the fastest: ((best super_log2, best tile_log2w),
+    ms per render [tile_log2w][super_log2])."""
+    times = (_F * 20)()
+    best_s, best_t = _I(), _I()
     _check(_autotune_render(ctx, int(volume_id), ctypes.byref(Camera.make(camera)), int(width), int(height), int(lod),
-                            float(step), int(repeats), ctypes.cast(times, _P), ctypes.byref(best)))
-    return best.value, [float(t) for t in times]
+                            float(step), int(repeats), ctypes.cast(times, _P), ctypes.byref(best_s),
+                            ctypes.byref(best_t)))
+    return (best_s.value, best_t.value), [[float(times[4 * t + k]) for k in range(4)] for t in range(5)]
 
 
 def render_depth(ctx, volume_id: int, camera, width: int, height: int, lod: int = -1, step: float = 0.5,

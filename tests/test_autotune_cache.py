@@ -11,18 +11,18 @@ class FakeRp:
     def __init__(self):
         self.calls = []
 
-    def set_launch_shape(self, ctx, s):
-        self.calls.append(("set", s))
+    def set_launch_shape(self, ctx, s, t):
+        self.calls.append(("set", s, t))
 
     def autotune_render(self, ctx, vid, cam, w, h, lod, step, repeats):
         self.calls.append(("tune", w, h))
-        return 1, [1.2, 1.0, 1.1, 1.3]
+        return (1, 3), [[1.2 + t, 1.0 + t, 1.1 + t, 1.3 + t] for t in (0.5, 0.4, 0.3, -0.1, 0.2)]
 
 
 def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "sub" / "autotune.json")
     assert AT.load_cache(path) == {}
-    cache = {"render|gpu|n512|f16|1920x1080|lod0|step0.5": {"super_log2": 2, "tile_px": 32, "ms": [1, 2, 3, 4]}}
+    cache = {"render|gpu|n512|f16|1920x1080|lod0|step0.5": {"super_log2": 2, "tile_log2w": 2, "ms": [[1, 2, 3, 4]]}}
     AT.save_cache(cache, path)
     assert AT.load_cache(path) == cache
     with open(path) as f:
@@ -47,11 +47,12 @@ def test_tune_render_uses_and_fills_the_cache():
     cache = {}
     key = AT.render_key("dev", 64, "f16", 200, 136, 0, 0.5)
     r = AT.tune_render(rp, None, 1, None, 200, 136, cache=cache, key=key)
-    assert not r["cached"] and r["super_log2"] == 1 and r["tile_px"] == 16 and rp.calls == [("tune", 200, 136)]
-    assert cache[key]["super_log2"] == 1
+    assert not r["cached"] and (r["super_log2"], r["tile_log2w"]) == (1, 3)
+    assert r["wave_tile_px"] == [8, 2] and r["super_tile_px"] == [32, 8] and rp.calls == [("tune", 200, 136)]
+    assert (cache[key]["super_log2"], cache[key]["tile_log2w"]) == (1, 3)
     rp.calls.clear()
     r = AT.tune_render(rp, None, 1, None, 200, 136, cache=cache, key=key)
-    assert r["cached"] and rp.calls == [("set", 1)]
+    assert r["cached"] and rp.calls == [("set", 1, 3)]
     rp.calls.clear()
     AT.tune_render(rp, None, 1, None, 200, 136, cache=cache, key=key, retune=True)
     assert rp.calls == [("tune", 200, 136)]

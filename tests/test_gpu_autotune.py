@@ -1,6 +1,6 @@
-"""GPU tests of the launch-shape autotuner: every super-tile size gives the image of the default
-shape bit for bit (with its counts), the tuner times all shapes and keeps the fastest, the server
-sweep picks one of its candidates, and invalid arguments are rejected."""
+"""GPU tests of the launch-shape autotuner: every wave tile shape and super-tile size gives the image
+of the default shape bit for bit (with its counts), the tuner times all shapes and keeps the
+fastest, the server sweep picks one of its candidates, and invalid arguments are rejected."""
 import numpy as np
 import pytest
 import torch
@@ -37,6 +37,9 @@ def load(rp, ctx, wl, storage="f16"):
     return vid
 
 
+SHAPES = [(0, 2), (1, 2), (3, 2), (2, 0), (2, 1), (2, 3), (2, 4), (0, 4), (3, 0), (1, 3)]
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16", "u8"])
 def test_every_launch_shape_gives_the_same_image(rp, ctx, storage):
     wl = W.make_workload(1, n=64, width=200, height=136)
@@ -44,22 +47,25 @@ def test_every_launch_shape_gives_the_same_image(rp, ctx, storage):
     cam = wl.camera.as_array()
     try:
         for w, h, lod in ((200, 136, 0), (1, 1, 0), (517, 3, 1), (64, 300, 2), (1920, 1080, 0)):
-            rp.set_launch_shape(ctx, 2)
+            rp.set_launch_shape(ctx, 2, 2)
             want = [cpu(x) for x in rp.render_debug(ctx, vid, cam, w, h, lod, 0.5)]
-            for s in (0, 1, 3):
-                print(f"[case] launch shape {s} {storage} {w}x{h} lod {lod}", flush=True)
-                rp.set_launch_shape(ctx, s)
-                assert rp.get_launch_shape(ctx) == s
+            want_jit = cpu(rp.render_jittered(ctx, vid, cam, w, h, lod, 0.5, 1, 4, 7)[0])
+            want_depth = cpu(rp.render_depth(ctx, vid, cam, w, h, lod, 0.5)[1])
+            for s, t in SHAPES:
+                print(f"[case] launch shape s={s} t={t} {storage} {w}x{h} lod {lod}", flush=True)
+                rp.set_launch_shape(ctx, s, t)
+                assert rp.get_launch_shape(ctx) == (s, t)
                 got = [cpu(x) for x in rp.render_debug(ctx, vid, cam, w, h, lod, 0.5)]
-                assert all(np.array_equal(a, b) for a, b in zip(got, want)), (s, w, h)
+                assert all(np.array_equal(a, b) for a, b in zip(got, want)), (s, t, w, h)
                 # the plain render (one-wave blocks, 32-bit record offsets) and the counting variant
                 # (four-wave blocks, 64-bit offsets for the record kinds) march the same samples
-                assert np.array_equal(cpu(rp.render(ctx, vid, cam, w, h, lod, 0.5)), want[0]), (s, w, h)
+                assert np.array_equal(cpu(rp.render(ctx, vid, cam, w, h, lod, 0.5)), want[0]), (s, t, w, h)
                 jit = cpu(rp.render_jittered(ctx, vid, cam, w, h, lod, 0.5, 1, 4, 7)[0])
-                rp.set_launch_shape(ctx, 2)
-                assert np.array_equal(jit, cpu(rp.render_jittered(ctx, vid, cam, w, h, lod, 0.5, 1, 4, 7)[0]))
+                assert np.array_equal(jit, want_jit), (s, t, w, h)
+                rgba_d, dep = rp.render_depth(ctx, vid, cam, w, h, lod, 0.5)
+                assert np.array_equal(cpu(rgba_d), want[0]) and np.array_equal(cpu(dep), want_depth), (s, t, w, h)
     finally:
-        rp.set_launch_shape(ctx, 2)
+        rp.set_launch_shape(ctx, 2, 2)
         rp.unload(ctx, vid)
 
 
@@ -68,28 +74,33 @@ def test_autotune_render_keeps_the_fastest(rp, ctx):
     vid = load(rp, ctx, wl)
     cam = wl.camera.as_array()
     try:
-        best, times = rp.autotune_render(ctx, vid, cam, wl.width, wl.height, 0, 0.5, repeats=5)
-        print(f"[autotune] ms per render for super-tiles of 8/16/32/64 px: {times}, best {best}", flush=True)
-        assert 0 <= best <= 3 and all(t > 0 for t in times)
-        assert times[best] == min(times) and times[best] < 0.99 * times[2] if best != 2 else min(times) >= 0.99 * times[2]
-        assert rp.get_launch_shape(ctx) == best
+        (bs, bt), times = rp.autotune_render(ctx, vid, cam, wl.width, wl.height, 0, 0.5, repeats=5)
+        print(f"[autotune] ms per render [tile_log2w][super_log2]: {times}, best s={bs} t={bt}", flush=True)
+        flat = [ms for row in times for ms in row]
+        assert 0 <= bs <= 3 and 0 <= bt <= 4 and len(flat) == 20 and all(x > 0 for x in flat)
+        if (bs, bt) != (2, 2):
+            assert times[bt][bs] == min(flat) and times[bt][bs] < 0.99 * times[2][2]
+        else:
+            assert min(flat) >= 0.99 * times[2][2]
+        assert rp.get_launch_shape(ctx) == (bs, bt)
         cache = {}
         key = AT.render_key(AT.device_name(), 64, "f16", wl.width, wl.height, 0, 0.5)
         r = AT.tune_render(rp, ctx, vid, cam, wl.width, wl.height, 0, 0.5, repeats=3, cache=cache, key=key)
         assert not r["cached"] and key in cache
-        rp.set_launch_shape(ctx, 0)
+        rp.set_launch_shape(ctx, 0, 0)
         r = AT.tune_render(rp, ctx, vid, cam, wl.width, wl.height, 0, 0.5, cache=cache, key=key)
-        assert r["cached"] and rp.get_launch_shape(ctx) == cache[key]["super_log2"]
+        assert r["cached"] and rp.get_launch_shape(ctx) == (cache[key]["super_log2"], cache[key]["tile_log2w"])
         for bad in (0, 1001):
             with pytest.raises(rp.RaypcError):
                 rp.autotune_render(ctx, vid, cam, wl.width, wl.height, 0, 0.5, repeats=bad)
         with pytest.raises(rp.RaypcError):
             rp.autotune_render(ctx, vid, cam, 0, wl.height, 0, 0.5)
-        for bad in (-1, 4):
+        for bad in ((-1, 2), (4, 2), (2, -1), (2, 5)):
             with pytest.raises(rp.RaypcError):
-                rp.set_launch_shape(ctx, bad)
+                rp.set_launch_shape(ctx, *bad)
+        assert rp.get_launch_shape(ctx) == (cache[key]["super_log2"], cache[key]["tile_log2w"])
     finally:
-        rp.set_launch_shape(ctx, 2)
+        rp.set_launch_shape(ctx, 2, 2)
         rp.unload(ctx, vid)
 
 
