@@ -509,7 +509,7 @@ def main():
                     help="frames in flight in the timed loop (streams used in turn); 1 = serial")
     ap.add_argument("--in-flight-sweep", default="",
                     help="also time the headline storage's loop with each of these frames-in-flight counts")
-    ap.add_argument("--storages", default="f16,f32,u8,u8c",
+    ap.add_argument("--storages", default="f16,f32,u8,f16c,u8c",
                     help="first one is the headline value; a trailing c keeps only the compact layout")
     ap.add_argument("--cpu-stride", type=int, default=1, help="oracle sample: every k-th row and column")
     ap.add_argument("--orbit-frames", type=int, default=200, help="single-request latency frames (seeded orbit cameras)")
@@ -524,9 +524,9 @@ def main():
     ap.add_argument("--prog-n", type=int, default=1024)
     ap.add_argument("--prog-width", type=int, default=3840)
     ap.add_argument("--prog-height", type=int, default=2160)
-    ap.add_argument("--prog-storages", default="f16,u8,u8c")
+    ap.add_argument("--prog-storages", default="f16,f16c,u8,u8c")
     ap.add_argument("--serving-requests", type=int, default=512)
-    ap.add_argument("--serving-qps", default="50,100,200,400,inf",
+    ap.add_argument("--serving-qps", default="25,50,100,200,400,inf",
                     help="Poisson arrival rates (requests/s); inf submits the whole trace at once")
     ap.add_argument("--profile-frames", type=int, default=0,
                     help="profiling mode: load the headline storage, render this many frames with the first "
