@@ -569,17 +569,11 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
             const float k2 = quad_bcast<2>(keep), k3 = quad_bcast<3>(keep);
             const float t1 = T * k0, t2 = t1 * k1, t3 = t2 * k2, t4 = t3 * k3;  // T after each sample
             const float t_before = sub == 0 ? T : (sub == 1 ? t1 : (sub == 2 ? t2 : t3));
-            const float t_after = sub == 0 ? t1 : (sub == 1 ? t2 : (sub == 2 ? t3 : t4));
             const float w = t_before * (1.0f - keep);
-            const bool stop_here = contributes && A.ert_on && (1.0f - t_after >= A.ert);
-            const unsigned long long stop_mask = __ballot(stop_here);
-            const int stop_bits = static_cast<int>((stop_mask >> quad_base) & 0xFull);
-            const int first_stop = stop_bits ? __ffs(stop_bits) - 1 : kQuad - 1;  // last sample that counts
-            {
-                // each lane forms its own sample's contribution w rgb (zero past the first stop:
-                // those samples are not composited), and the four are added to the ray's sums in
-                // sample order, each addition taking its operand from the lane that holds it
-                const float wq = sub <= first_stop ? w : 0.0f;
+            // each lane forms its own sample's contribution w rgb (zero past the first stop: those
+            // samples are not composited), and the four are added to the ray's sums in sample order,
+            // each addition taking its operand from the lane that holds it
+            auto merge = [&](float wq) {
                 const float pr = wq * cr, pg = wq * cg, pb = wq * cb;
                 C0 = C0 + quad_bcast<0>(pr);
                 C1 = C1 + quad_bcast<0>(pg);
@@ -601,18 +595,35 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                     D = D + quad_bcast<2>(pd);
                     D = D + quad_bcast<3>(pd);
                 }
+            };
+            int first_stop = kQuad - 1;  // last sample that counts
+            // A sample can end its ray only if it contributes and its quad's transmittance after all
+            // four samples, t4 (<= the transmittance after any of them: every factor is at most 1),
+            // is at or past the threshold.  When no lane of the wave has such a sample (the usual
+            // case) every sample counts and T becomes t4: the stop search below would find nothing
+            // and give the same values.
+            if (__ballot(contributes && A.ert_on && (1.0f - t4 >= A.ert)) == 0ull) {
+                merge(w);
+                T = t4;
+            } else {
+                const float t_after = sub == 0 ? t1 : (sub == 1 ? t2 : (sub == 2 ? t3 : t4));
+                const bool stop_here = contributes && (1.0f - t_after >= A.ert);
+                const unsigned long long stop_mask = __ballot(stop_here);
+                const int stop_bits = static_cast<int>((stop_mask >> quad_base) & 0xFull);
+                if (stop_bits) first_stop = __ffs(stop_bits) - 1;
+                merge(sub <= first_stop ? w : 0.0f);
+                // T after the last sample that counts: t4 without a stop (selected on the stop bits,
+                // not on first_stop, which would become a branch and part the additions above from
+                // their lane moves)
+                T = (stop_bits & 1) ? t1 : ((stop_bits & 2) ? t2 : ((stop_bits & 4) ? t3 : t4));
+                stopped = stop_bits != 0;
+                cnt_nom += stopped ? static_cast<uint32_t>(first_stop + 1) : 0u;
             }
             if constexpr (COUNTS) {
                 const unsigned long long comp_mask = __ballot(contributes);
                 const int comp_bits = static_cast<int>((comp_mask >> quad_base) & 0xFull);
                 cnt_comp += __popc(comp_bits & ((2 << first_stop) - 1));
             }
-            // T after the last sample that counts: t4 without a stop (selected on the stop bits, not
-            // on first_stop, which would become a branch and part the additions above from their
-            // lane moves)
-            T = (stop_bits & 1) ? t1 : ((stop_bits & 2) ? t2 : ((stop_bits & 4) ? t3 : t4));
-            stopped = stop_bits != 0;
-            cnt_nom += stopped ? static_cast<uint32_t>(first_stop + 1) : 0u;
             if constexpr (COUNTS) stop_at = first_stop;
         }
         if constexpr (COUNTS) {
