@@ -175,6 +175,36 @@ __device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32
     }
 }
 
+// fetch_rec at 32-bit offsets for a lane that may not need the value: where `use` is clear the loads
+// go to an offset beyond the field, which reads no memory and returns zero (the value is then
+// meaningless).  Loads issued this way need no branch, so those of several samples can be in flight
+// together.  kNoLoad lies beyond every field and flag array (record fields of the 32-bit offset
+// kinds stay below 0xFF4E0000 bytes).
+constexpr uint32_t kNoLoad = 0xFFFFFFF0u;
+template <int S>
+__device__ __forceinline__ float fetch_rec_guarded(const void* __restrict__ base, uint32_t bytes, bool use, uint32_t r00,
+                                                   uint32_t r10, uint32_t r01, uint32_t r11, const Tri& t) {
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes), kRawBufferFlags);
+    auto ld = [&](uint32_t r) -> u32x2 {
+        return __builtin_amdgcn_raw_buffer_load_b64(rsrc, static_cast<int>(use ? r << 3 : kNoLoad), 0, 0);
+    };
+    if constexpr (S == kF16) {
+        const u32x2 p = ld(r00);
+        const u32x2 q = ld(r01);
+        auto lo = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u & 0xFFFFu))); };
+        auto hi = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u >> 16))); };
+        return blend(t, lo(p.x), hi(p.x), lo(p.y), hi(p.y), lo(q.x), hi(q.x), lo(q.y), hi(q.y));
+    } else {
+        const u32x2 p0 = ld(r00);
+        const u32x2 p1 = ld(r10);
+        const u32x2 p2 = ld(r01);
+        const u32x2 p3 = ld(r11);
+        return blend(t, __uint_as_float(p0.x), __uint_as_float(p0.y), __uint_as_float(p1.x), __uint_as_float(p1.y),
+                     __uint_as_float(p2.x), __uint_as_float(p2.y), __uint_as_float(p3.x), __uint_as_float(p3.y));
+    }
+}
+
 // Kernel kinds: storage type and layout.
 constexpr int storage_of(int K) {
     return K == kKindF32Rec ? kF32 : (K == kKindF16Rec ? kF16 : (K == kKindU8Rec ? kU8 : K));
@@ -305,6 +335,15 @@ __device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) 
     return fminf(s, 0x1.fffffep-1f);
 }
 
+// Samples a lane evaluates per step.  binary16 records read at 32-bit offsets take two, j0 + sub
+// and j0 + 4 + sub: their record loads are buffer loads, which load nothing (and return zero) at an
+// offset beyond the field, so the loads of both samples are issued together, unconditionally, and
+// a wave has twice the loads in flight while each ray advances eight samples per step (headline
+// frame 0.876 -> 0.740 ms).  float32-pair records (float32 and decoded 8-bit values) take one: with
+// two, their four record loads per field and sample need 82 registers, which leaves 5 waves per
+// SIMD, and two frames in flight ran 4 % slower.  The counting variant and the other kinds take one.
+constexpr int samples_per_lane(int K, bool COUNTS, bool WIDE) { return K == kKindF16Rec && !WIDE && !COUNTS ? 2 : 1; }
+
 // One 4 x 4 pixel tile (bx, by) of the image described by A, marched by the calling one-wave block.  NB is the number of brushed fields, or kRuntimeNB to read it from A.
 // JIT: a jittered progressive pass (the sample grid of every segment starts s ds before it, so the
 // first and last samples of a segment are partial).  DEPTH: also write the opacity-weighted depth, the
@@ -312,12 +351,21 @@ __device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) 
 // depth that image warping reprojects with; +inf where nothing was composited).  WIDE: 64-bit record
 // offsets (needed for record fields of 4 GiB and more).  L points to the same arguments as A; the
 // pixel's outputs are written through it (see late_args).
+//
+// A step of the march takes, for each ray, the next P groups of four consecutive samples (P =
+// samples_per_lane): lane `sub` of the ray's quad evaluates samples j0 + 4 q + sub, q < P.  The
+// groups are composited in sample order; a skipped box of the last group's fourth sample moves the
+// next step past that box.  A sample of group q > 0 that lies inside a box the previous group's
+// fourth sample would have jumped over is itself in that skipped box, so it is skipped and adds
+// nothing, and the image does not depend on P.
 template <int K, int NB, bool COUNTS, bool JIT = false, bool DEPTH = false, bool WIDE = true, int BW = 1,
           typename LP>
 __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, int by, float4* s_tf) {
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
     constexpr int RT = record_type_of(K);
+    constexpr int P = samples_per_lane(K, COUNTS, WIDE);
+    static_assert(P == 1 || (R && !WIDE && !COUNTS), "two samples per lane need buffer-loaded records");
     // the wave tile: tw x th pixels, tw = 2^t (A.tile_log2w), th = 16 / tw; a block of four waves
     // takes 2 x 2 wave tiles
     const int tl = A.tile_log2w, tw = 1 << tl, th = kWaveRays >> tl;
@@ -376,6 +424,10 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
 
     const int n = A.n, nb = A.nb;
     const uint32_t nbu = static_cast<uint32_t>(nb);
+    // the flag words as a buffer (no flags: an empty range, so every load returns zero)
+    const __amdgpu_buffer_rsrc_t flag_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void*>(A.skip != nullptr ? static_cast<const void*>(A.skip) : static_cast<const void*>(A.tf)), 0,
+        A.skip != nullptr ? static_cast<int>(nbu * nbu * nbu * 2u) : 0, kRawBufferFlags);
     // record-number steps to the next voxel in y and z from the last voxel of a brick (see below)
     const uint32_t y_brick_step = nbu * 512u - 140u, z_brick_step = nbu * nbu * 512u - 304u;
     const float top = static_cast<float>(n - 1);  // largest voxel index
@@ -397,7 +449,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     uint32_t cnt_nom = 0, cnt_comp = 0;
     uint32_t cnt_eval = 0, cnt_fetch = 0;  // COUNTS: this lane's evaluated samples and field fetches
     uint32_t last_brick = 0xFFFFFFFFu;
-    int seg = 0, j0 = 0;  // j0: first sample of the quad's current group of four
+    int seg = 0, j0 = 0;  // j0: first sample of the quad's current step
     float sa = seg_a[0], sb = seg_b[0];
     // grid origin of the current segment: sample j covers [max(sa, g + j ds), min(g + (j+1) ds, sb)]
     float s_jit = 0.0f;
@@ -407,160 +459,218 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     bool alive = nseg > 0;
 
     while (alive) {
-        const int j = j0 + sub;
-        const bool valid = j < ns;
-        bool skipped = false, pass = false;
-        float tv = 0.0f;
-        int jn = j + 1;
-        const bool last = j == ns - 1;
-        float tlo = 0.0f, tm = 0.0f, len_partial = 0.0f;
-        bool partial = last;
-        uint32_t it_eval = 0, it_fetch = 0;  // COUNTS: this step's sample evaluated, fields fetched
-
-        if (valid) {
+        // ---- sample positions and their bricks' flag words (the loads of all P samples together)
+        bool valid[P], skipped[P], pass[P], partial[P];
+        float tv[P], tm[P], len_partial[P], ux[P], uy[P], uz[P], flx[P], fly[P], flz[P];
+        int x0[P], y0[P], z0[P];
+        uint32_t brick[P], sbi[P], flags[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int j = j0 + kQuad * q + sub;
+            valid[q] = j < ns;
+            const bool last = j == ns - 1;
+            partial[q] = last;
+            skipped[q] = false;
+            pass[q] = false;
+            tv[q] = 0.0f;
+            float tlo;
             if constexpr (JIT) {
                 const bool first = j == 0;
-                partial = first || last;
+                partial[q] = first || last;
                 tlo = first ? sa : fmaf(static_cast<float>(j), ds, g);
                 const float thi = last ? sb : fmaf(static_cast<float>(j) + 1.0f, ds, g);
-                tm = partial ? 0.5f * (tlo + thi) : fmaf(static_cast<float>(j) + 0.5f, ds, g);
-                len_partial = fmaxf(thi - tlo, 0.0f);
+                tm[q] = partial[q] ? 0.5f * (tlo + thi) : fmaf(static_cast<float>(j) + 0.5f, ds, g);
+                len_partial[q] = fmaxf(thi - tlo, 0.0f);
             } else {
                 tlo = fmaf(static_cast<float>(j), ds, sa);
-                tm = last ? 0.5f * (tlo + sb) : fmaf(static_cast<float>(j) + 0.5f, ds, sa);
-                len_partial = fmaxf(sb - tlo, 0.0f);
+                tm[q] = last ? 0.5f * (tlo + sb) : fmaf(static_cast<float>(j) + 0.5f, ds, sa);
+                len_partial[q] = fmaxf(sb - tlo, 0.0f);
             }
-            const float ux = fmaf(dux, tm, uox), uy = fmaf(duy, tm, uoy), uz = fmaf(duz, tm, uoz);
-            const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
-            const int ix = static_cast<int>(flx), iy = static_cast<int>(fly), iz = static_cast<int>(flz);
+            ux[q] = fmaf(dux, tm[q], uox), uy[q] = fmaf(duy, tm[q], uoy), uz[q] = fmaf(duz, tm[q], uoz);
+            flx[q] = floorf(ux[q]), fly[q] = floorf(uy[q]), flz[q] = floorf(uz[q]);
             // corner indices clamped onto the grid (the clamp taken on the integer-valued floors)
-            const int x0 = static_cast<int>(__builtin_amdgcn_fmed3f(flx, 0.0f, top));
-            const int y0 = static_cast<int>(__builtin_amdgcn_fmed3f(fly, 0.0f, top));
-            const int z0 = static_cast<int>(__builtin_amdgcn_fmed3f(flz, 0.0f, top));
-            const int x1 = min(max(ix + 1, 0), n - 1), y1 = min(max(iy + 1, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
-            const int bxi = x0 >> 3, byi = y0 >> 3, bzi = z0 >> 3;
+            x0[q] = static_cast<int>(__builtin_amdgcn_fmed3f(flx[q], 0.0f, top));
+            y0[q] = static_cast<int>(__builtin_amdgcn_fmed3f(fly[q], 0.0f, top));
+            z0[q] = static_cast<int>(__builtin_amdgcn_fmed3f(flz[q], 0.0f, top));
+            const int bxi = x0[q] >> 3, byi = y0[q] >> 3, bzi = z0[q] >> 3;
             // brick rows and slabs below 2^7, bricks per row below 2^8: 24-bit products are exact
-            const uint32_t brick = raypc_mul_u24(raypc_mul_u24(static_cast<uint32_t>(bzi), nbu) + byi, nbu) + bxi;
-            const uint32_t flags = A.skip != nullptr ? global_ptr<uint16_t>(A.skip)[brick] : 0u;
-            const uint32_t sbi = ((x0 >> 2) & 1) | (((y0 >> 2) & 1) << 1) | (((z0 >> 2) & 1) << 2);  // sub-brick
-            if ((flags >> sbi) & 1u) {
-                // every sample whose base corner lies in this sub-brick (in this brick, or its
-                // empty brick group, when flagged so) is discarded or transparent: find the first
-                // sample that may lie beyond the box (shrunk by a margin against rounding; open at the
-                // grid's faces, where clamping maps every outside position to the boundary box)
-                skipped = true;
-                // the largest empty box holding the sample's base corner: its aligned 4^3- or 2^3-brick
-                // group, the brick, or the sub-brick (corner x0 & m, edge -m voxels)
-                const int m = (flags & 0x200u) ? -32 : ((flags & 0x100u) ? -16 : ((flags & 0xFFu) == 0xFFu ? -8 : -4));
-                const float t_exit = fminf(box_exit(x0 & m, -m, upx, uosx, inv_dux, n),
-                                           fminf(box_exit(y0 & m, -m, upy, uosy, inv_duy, n),
-                                                 box_exit(z0 & m, -m, upz, uosz, inv_duz, n)));
-                float jc = (t_exit - g) * inv_ds - 0.5f - kSkipMargin;
-                jc = fminf(fmaxf(jc, 0.0f), static_cast<float>(ns));
-                jn = max(j + 1, static_cast<int>(ceilf(jc)));
-            } else {
+            brick[q] = raypc_mul_u24(raypc_mul_u24(static_cast<uint32_t>(bzi), nbu) + byi, nbu) + bxi;
+            sbi[q] = ((x0[q] >> 2) & 1) | (((y0[q] >> 2) & 1) << 1) | (((z0[q] >> 2) & 1) << 2);  // sub-brick
+            flags[q] = __builtin_amdgcn_raw_buffer_load_b16(flag_rsrc, static_cast<int>(valid[q] ? brick[q] * 2u : kNoLoad),
+                                                            0, 0);
+        }
+        bool any_fetch = false;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            skipped[q] = valid[q] && ((flags[q] >> sbi[q]) & 1u);
+            any_fetch = any_fetch || (valid[q] && !skipped[q]);
+        }
+        // ---- every sample whose base corner lies in a flagged sub-brick (in this brick, or its empty
+        // brick group, when flagged so) is discarded or transparent.  The quad's fourth lane finds, for
+        // its last sample, the first sample that may lie beyond the box (shrunk by a margin against
+        // rounding; open at the grid's faces, where clamping maps every outside position to the
+        // boundary box): the next step starts there.
+        int jn = 0;
+        if (skipped[P - 1] && sub == kQuad - 1) {
+            constexpr int q = P - 1;
+            const int j = j0 + kQuad * q + sub;
+            const uint32_t fl = flags[q];
+            // the largest empty box holding the sample's base corner: its aligned 4^3- or 2^3-brick
+            // group, the brick, or the sub-brick (corner x0 & m, edge -m voxels)
+            const int m = (fl & 0x200u) ? -32 : ((fl & 0x100u) ? -16 : ((fl & 0xFFu) == 0xFFu ? -8 : -4));
+            const float t_exit = fminf(box_exit(x0[q] & m, -m, upx, uosx, inv_dux, n),
+                                       fminf(box_exit(y0[q] & m, -m, upy, uosy, inv_duy, n),
+                                             box_exit(z0[q] & m, -m, upz, uosz, inv_duz, n)));
+            float jc = (t_exit - g) * inv_ds - 0.5f - kSkipMargin;
+            jc = fminf(fmaxf(jc, 0.0f), static_cast<float>(ns));
+            jn = max(j + 1, static_cast<int>(ceilf(jc)));
+        }
+        uint32_t it_eval = 0, it_fetch = 0;  // COUNTS: this step's sample evaluated, fields fetched
+        if (any_fetch) {
+            Tri tri[P];
+            uint32_t o[P][8];
+            uint32_t r00[P], r10[P], r01[P], r11[P];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
                 if constexpr (COUNTS) {
-                    if (A.touched != nullptr && brick != last_brick) {
-                        atomicOr(&A.touched[brick >> 5], 1u << (brick & 31));
-                        last_brick = brick;
+                    if (A.touched != nullptr && valid[q] && !skipped[q] && brick[q] != last_brick) {
+                        atomicOr(&A.touched[brick[q] >> 5], 1u << (brick[q] & 31));
+                        last_brick = brick[q];
                     }
                 }
                 // below the grid both corners of an axis clamp to index 0: a zero weight on the upper
                 // corner gives that value exactly, and lets a record of the clamped base voxel serve
-                const float wx = flx < 0.0f ? 0.0f : ux - flx, wy = fly < 0.0f ? 0.0f : uy - fly;
-                const float wz = flz < 0.0f ? 0.0f : uz - flz;
-                const Tri tw = tri_weights(wx, wy, wz);
-                uint32_t o[8];
-                uint32_t r00 = 0, r10 = 0, r01 = 0, r11 = 0;
+                const float wx = flx[q] < 0.0f ? 0.0f : ux[q] - flx[q], wy = fly[q] < 0.0f ? 0.0f : uy[q] - fly[q];
+                const float wz = flz[q] < 0.0f ? 0.0f : uz[q] - flz[q];
+                tri[q] = tri_weights(wx, wy, wz);
+                r00[q] = r10[q] = r01[q] = r11[q] = 0;
                 if constexpr (R) {
                     // record number of the base voxel (the layout of axis_x/y/z): its brick, the 4^3
                     // sub-brick in bits 6-8 and its place in that in bits 0-5.  The voxel one up in
                     // z (y) follows by a step that depends on where the base voxel lies in its
                     // sub-brick and brick: +16 (+4) inside a sub-brick, to the next sub-brick, or to
                     // the next brick; none where the upper corner clamps onto the base voxel.
-                    r00 = (brick << 9) | (sbi << 6) | static_cast<uint32_t>((x0 & 3) | ((y0 & 3) << 2) | ((z0 & 3) << 4));
-                    const uint32_t dz = (z0 & 3) != 3 ? 16u : ((z0 & 4) == 0 ? 208u : z_brick_step);
-                    r01 = r00 + (flz >= 0.0f && flz < top ? dz : 0u);
+                    r00[q] = (brick[q] << 9) | (sbi[q] << 6) |
+                             static_cast<uint32_t>((x0[q] & 3) | ((y0[q] & 3) << 2) | ((z0[q] & 3) << 4));
+                    const uint32_t dz = (z0[q] & 3) != 3 ? 16u : ((z0[q] & 4) == 0 ? 208u : z_brick_step);
+                    r01[q] = r00[q] + (flz[q] >= 0.0f && flz[q] < top ? dz : 0u);
                     if constexpr (RT == kF32) {
-                        const uint32_t dy = (y0 & 3) != 3 ? 4u : ((y0 & 4) == 0 ? 116u : y_brick_step);
-                        const uint32_t dyv = fly >= 0.0f && fly < top ? dy : 0u;
-                        r10 = r00 + dyv;
-                        r11 = r01 + dyv;
+                        const uint32_t dy = (y0[q] & 3) != 3 ? 4u : ((y0[q] & 4) == 0 ? 116u : y_brick_step);
+                        const uint32_t dyv = fly[q] >= 0.0f && fly[q] < top ? dy : 0u;
+                        r10[q] = r00[q] + dyv;
+                        r11[q] = r01[q] + dyv;
                     }
                 } else {
-                    constexpr int L = kLogBytes<S>;
-                    const uint32_t X0 = axis_x(x0) << L, X1 = axis_x(x1) << L;
-                    const uint32_t Y0 = axis_y(y0, nb) << L, Y1 = axis_y(y1, nb) << L;
-                    const uint32_t Z0 = axis_z(z0, nb) << L, Z1 = axis_z(z1, nb) << L;
+                    constexpr int LB = kLogBytes<S>;
+                    const int ix = static_cast<int>(flx[q]), iy = static_cast<int>(fly[q]), iz = static_cast<int>(flz[q]);
+                    const int x1 = min(max(ix + 1, 0), n - 1), y1 = min(max(iy + 1, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
+                    const uint32_t X0 = axis_x(x0[q]) << LB, X1 = axis_x(x1) << LB;
+                    const uint32_t Y0 = axis_y(y0[q], nb) << LB, Y1 = axis_y(y1, nb) << LB;
+                    const uint32_t Z0 = axis_z(z0[q], nb) << LB, Z1 = axis_z(z1, nb) << LB;
                     const uint32_t zy00 = Z0 + Y0, zy01 = Z0 + Y1, zy10 = Z1 + Y0, zy11 = Z1 + Y1;
-                    o[0] = zy00 + X0, o[1] = zy00 + X1, o[2] = zy01 + X0, o[3] = zy01 + X1;
-                    o[4] = zy10 + X0, o[5] = zy10 + X1, o[6] = zy11 + X0, o[7] = zy11 + X1;
+                    o[q][0] = zy00 + X0, o[q][1] = zy00 + X1, o[q][2] = zy01 + X0, o[q][3] = zy01 + X1;
+                    o[q][4] = zy10 + X0, o[q][5] = zy10 + X1, o[q][6] = zy11 + X0, o[q][7] = zy11 + X1;
                 }
-                auto field_value = [&](int k) -> float {
-                    if constexpr (R) return fetch_rec<RT, WIDE>(A.rec[k], A.rec_bytes, r00, r10, r01, r11, tw);
-                    else return fetch<S>(source<S>(A, k), o, tw);
-                };
                 // coordinate axes first: a sample outside them fetches no field (the kernels with a
                 // fixed field count carry no coordinate axes; renders that use them take the
                 // run-time variant)
-                pass = true;
-                if constexpr (COUNTS) it_eval = 1;
+                pass[q] = valid[q] && !skipped[q];
                 if constexpr (NB < 0) {
                     if (A.coord_mask)
-                        pass = coord_ok(A.coord_mask, A.clo, A.chi, fmaf(dx, tm, ox), fmaf(dy, tm, oy), fmaf(dz, tm, oz));
+                        pass[q] = pass[q] && coord_ok(A.coord_mask, A.clo, A.chi, fmaf(dx, tm[q], ox),
+                                                      fmaf(dy, tm[q], oy), fmaf(dz, tm[q], oz));
                 }
-                constexpr int kUnroll = NB >= 0 ? NB : kMaxFields;
-                const int nbr = NB >= 0 ? NB : A.n_brushed;
-                // The slot comparisons below are made afresh in every step: hoisted out of the loop,
-                // each would hold a 64-bit lane mask for the whole march.
-                int tfs = A.tf_slot;
-                asm volatile("" : "+s"(tfs));
+            }
+            if constexpr (COUNTS) it_eval = valid[0] && !skipped[0] ? 1u : 0u;
+            // field k's value at every sample of the lane that still passes (with two samples per
+            // lane, both loads are issued, a sample that no longer passes loading nothing)
+            auto field_values = [&](int k, float (&v)[P]) {
 #pragma unroll
-                for (int k = 0; k < kUnroll; ++k) {
-                    if (pass && (NB >= 0 || k < nbr)) {
-                        const float v = field_value(k);
-                        if constexpr (COUNTS) ++it_fetch;
-                        pass = (v >= A.lo[k]) && (v <= A.hi[k]);
-                        if (k == tfs) tv = v;
+                for (int q = 0; q < P; ++q) {
+                    if constexpr (R) {
+                        if constexpr (P > 1)
+                            v[q] = fetch_rec_guarded<RT>(A.rec[k], A.rec_bytes, pass[q], r00[q], r10[q], r01[q],
+                                                         r11[q], tri[q]);
+                        else
+                            v[q] = fetch_rec<RT, WIDE>(A.rec[k], A.rec_bytes, r00[q], r10[q], r01[q], r11[q], tri[q]);
+                    } else {
+                        v[q] = fetch<S>(source<S>(A, k), o[q], tri[q]);
                     }
                 }
-                if (pass) {
-                    if constexpr (NB >= 0 && NB < kMaxFields) {
-                        if (tfs == NB) {
-                            tv = field_value(NB);
-                            if constexpr (COUNTS) ++it_fetch;
-                        }
-                    } else if constexpr (NB < 0) {
-                        if (tfs == nbr && nbr < kMaxFields) {
-                            tv = field_value(nbr);
-                            if constexpr (COUNTS) ++it_fetch;
-                        }
+            };
+            auto any_pass = [&]() {
+                bool a = false;
+#pragma unroll
+                for (int q = 0; q < P; ++q) a = a || pass[q];
+                return a;
+            };
+            constexpr int kUnroll = NB >= 0 ? NB : kMaxFields;
+            const int nbr = NB >= 0 ? NB : A.n_brushed;
+            // The slot comparisons below are made afresh in every step: hoisted out of the loop,
+            // each would hold a 64-bit lane mask for the whole march.
+            int tfs = A.tf_slot;
+            asm volatile("" : "+s"(tfs));
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                if ((NB >= 0 || k < nbr) && any_pass()) {
+                    float v[P];
+                    field_values(k, v);
+                    if constexpr (COUNTS) ++it_fetch;
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        pass[q] = pass[q] && (v[q] >= A.lo[k]) && (v[q] <= A.hi[k]);
+                        if (k == tfs) tv[q] = v[q];
                     }
+                }
+            }
+            if (any_pass()) {
+                int tk = -1;
+                if constexpr (NB >= 0 && NB < kMaxFields) {
+                    if (tfs == NB) tk = NB;
+                } else if constexpr (NB < 0) {
+                    if (tfs == nbr && nbr < kMaxFields) tk = nbr;
+                }
+                if (tk >= 0) {
+                    float v[P];
+                    field_values(tk, v);
+                    if constexpr (COUNTS) ++it_fetch;
+#pragma unroll
+                    for (int q = 0; q < P; ++q) tv[q] = v[q];
                 }
             }
         }
         // ---- classification: every lane evaluates it, and a lane whose sample was not fetched or
         // failed the brush contributes nothing (k = 1, w = 0), so the values merged below are those
         // of the sequential definition
-        const float xt = fminf(fmaxf((tv - A.vmin) * A.inv_range, 0.0f), 1.0f) * 255.0f;
-        const int it = min(static_cast<int>(xt), 254);
-        const float wt = xt - static_cast<float>(it);
-        const float4 e0 = s_tf[it], e1 = s_tf[it + 1];
-        const float al = fmaf(wt, e1.w - e0.w, e0.w);
-        const bool contributes = pass && al > 0.0f;
-        const float r = partial ? len_partial * A.inv_ref : r_full;
-        const float kc = al >= 1.0f ? 0.0f : __builtin_amdgcn_exp2f(r * __log2f(1.0f - al));
-        const float keep = contributes ? kc : 1.0f;
-        const float cr = contributes ? fmaf(wt, e1.x - e0.x, e0.x) : 0.0f;
-        const float cg = contributes ? fmaf(wt, e1.y - e0.y, e0.y) : 0.0f;
-        const float cb = contributes ? fmaf(wt, e1.z - e0.z, e0.z) : 0.0f;
+        bool contributes[P];
+        float kc[P], cr[P], cg[P], cb[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const float xt = fminf(fmaxf((tv[q] - A.vmin) * A.inv_range, 0.0f), 1.0f) * 255.0f;
+            const int it = min(static_cast<int>(xt), 254);
+            const float wt = xt - static_cast<float>(it);
+            const float4 e0 = s_tf[it], e1 = s_tf[it + 1];
+            const float al = fmaf(wt, e1.w - e0.w, e0.w);
+            contributes[q] = pass[q] && al > 0.0f;
+            const float r = partial[q] ? len_partial[q] * A.inv_ref : r_full;
+            kc[q] = al >= 1.0f ? 0.0f : __builtin_amdgcn_exp2f(r * __log2f(1.0f - al));
+            cr[q] = fmaf(wt, e1.x - e0.x, e0.x);
+            cg[q] = fmaf(wt, e1.y - e0.y, e0.y);
+            cb[q] = fmaf(wt, e1.z - e0.z, e0.z);
+        }
 
-        // ---- advance past a skipped brick of the quad's fourth sample
-        const int last_skipped = quad_bcast<3>(static_cast<int>(skipped && valid));
+        // ---- advance past a skipped box of the quad's last sample
+        const int last_skipped = quad_bcast<3>(static_cast<int>(skipped[P - 1]));
         const int jn3 = quad_bcast<3>(jn);
         bool stopped = false;
         int stop_at = kQuad - 1;  // COUNTS: the quad's last sample that counts
-        if (__ballot(contributes) != 0ull) {  // else nothing to composite anywhere in the wave
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            // a ray that stopped in an earlier group composites nothing more
+            const bool con = contributes[q] && !stopped;
+            if (__ballot(con) == 0ull) continue;  // else nothing to composite anywhere in the wave
+            const float keep = con ? kc[q] : 1.0f;
+            const float qr = con ? cr[q] : 0.0f, qg = con ? cg[q] : 0.0f, qb = con ? cb[q] : 0.0f;
             // ---- merge the quad's four samples in sample order.  Every lane replays the same
             // sequential updates (T <- T k, then C <- C + w rgb) on broadcast values, so the ray
             // state is identical in the four lanes and independent of how samples were grouped
@@ -570,11 +680,12 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
             const float t1 = T * k0, t2 = t1 * k1, t3 = t2 * k2, t4 = t3 * k3;  // T after each sample
             const float t_before = sub == 0 ? T : (sub == 1 ? t1 : (sub == 2 ? t2 : t3));
             const float w = t_before * (1.0f - keep);
+            const float tmq = tm[q];
             // each lane forms its own sample's contribution w rgb (zero past the first stop: those
             // samples are not composited), and the four are added to the ray's sums in sample order,
             // each addition taking its operand from the lane that holds it
             auto merge = [&](float wq) {
-                const float pr = wq * cr, pg = wq * cg, pb = wq * cb;
+                const float pr = wq * qr, pg = wq * qg, pb = wq * qb;
                 C0 = C0 + quad_bcast<0>(pr);
                 C1 = C1 + quad_bcast<0>(pg);
                 C2 = C2 + quad_bcast<0>(pb);
@@ -589,7 +700,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                 C2 = C2 + quad_bcast<3>(pb);
                 if constexpr (DEPTH) {
                     // samples that were not composited add w tm = 0
-                    const float pd = wq * tm;
+                    const float pd = wq * tmq;
                     D = D + quad_bcast<0>(pd);
                     D = D + quad_bcast<1>(pd);
                     D = D + quad_bcast<2>(pd);
@@ -602,12 +713,12 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
             // is at or past the threshold.  When no lane of the wave has such a sample (the usual
             // case) every sample counts and T becomes t4: the stop search below would find nothing
             // and give the same values.
-            if (__ballot(contributes && A.ert_on && (1.0f - t4 >= A.ert)) == 0ull) {
+            if (__ballot(con && A.ert_on && (1.0f - t4 >= A.ert)) == 0ull) {
                 merge(w);
                 T = t4;
             } else {
                 const float t_after = sub == 0 ? t1 : (sub == 1 ? t2 : (sub == 2 ? t3 : t4));
-                const bool stop_here = contributes && (1.0f - t_after >= A.ert);
+                const bool stop_here = con && (1.0f - t_after >= A.ert);
                 const unsigned long long stop_mask = __ballot(stop_here);
                 const int stop_bits = static_cast<int>((stop_mask >> quad_base) & 0xFull);
                 if (stop_bits) first_stop = __ffs(stop_bits) - 1;
@@ -616,15 +727,16 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                 // not on first_stop, which would become a branch and part the additions above from
                 // their lane moves)
                 T = (stop_bits & 1) ? t1 : ((stop_bits & 2) ? t2 : ((stop_bits & 4) ? t3 : t4));
-                stopped = stop_bits != 0;
-                cnt_nom += stopped ? static_cast<uint32_t>(first_stop + 1) : 0u;
+                // (a ray that stopped in an earlier group has no stop bits here and stays stopped)
+                stopped = stopped || stop_bits != 0;
+                cnt_nom += stop_bits ? static_cast<uint32_t>(kQuad * q + first_stop + 1) : 0u;
             }
             if constexpr (COUNTS) {
-                const unsigned long long comp_mask = __ballot(contributes);
+                const unsigned long long comp_mask = __ballot(con);
                 const int comp_bits = static_cast<int>((comp_mask >> quad_base) & 0xFull);
                 cnt_comp += __popc(comp_bits & ((2 << first_stop) - 1));
+                stop_at = first_stop;
             }
-            if constexpr (COUNTS) stop_at = first_stop;
         }
         if constexpr (COUNTS) {
             // samples after the termination stop were evaluated by their lanes but are not the method's
@@ -635,8 +747,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
         if (stopped) {
             alive = false;
         } else {
-            // next group: after the four samples, or past the brick of the fourth if it was skipped
-            const int next = last_skipped ? max(j0 + kQuad, jn3) : j0 + kQuad;
+            // next step: after the P groups, or past the skipped box of the last group's fourth sample
+            const int next = last_skipped ? max(j0 + kQuad * P, jn3) : j0 + kQuad * P;
             cnt_nom += static_cast<uint32_t>(min(next, ns) - j0);
             j0 = next;
             if (j0 >= ns) {
