@@ -66,6 +66,114 @@ def measured_traffic(path=TRAFFIC_RECORD):
     return None if rec is None else rec["traffic_bytes_per_launch"]
 
 
+HEADLINE_SOURCES = ["paper_2207_12011_amd/csrc/raymarch.hip", "paper_2207_12011_amd/csrc/raymarch_impl.h",
+                    "paper_2207_12011_amd/csrc/internal.h", "paper_2207_12011_amd/csrc/preprocess.hip"]
+SERVING_SOURCES = ["paper_2207_12011_amd/csrc/raymarch_impl.h", "paper_2207_12011_amd/csrc/raymarch_batch.hip",
+                   "paper_2207_12011_amd/csrc/server.hip", "paper_2207_12011_amd/csrc/internal.h",
+                   "paper_2207_12011_amd/csrc/preprocess.hip"]
+
+
+def counter_record(kind, root, frames, out_path, trace_frames=50):
+    """Summarise rocprofv3 output under `root` (every *_counter_collection.csv of the --pmc passes,
+    and a *_kernel_trace.csv if present) into the counter record read by the roofline.
+
+    kind "headline": the last `frames` launches of the headline ray march (bench.py
+    --profile-frames runs), averaged per launch; kind "serving": every batched ray-march and skip
+    launch of a bench.py --profile-serving run, summed.  FETCH_SIZE and WRITE_SIZE are scaled by
+    what they read for the 1 GiB device copy at the end of the same run."""
+    import csv
+    import glob
+    import hashlib
+    root_dir = os.path.dirname(os.path.abspath(__file__))
+    rows = []
+    for f in sorted(glob.glob(os.path.join(root, "**", "*_counter_collection.csv"), recursive=True)):
+        rows += [(f, r) for r in csv.DictReader(open(f))]
+    if not rows:
+        raise SystemExit(f"no *_counter_collection.csv under {root}")
+
+    def is_kernel(name):
+        if kind == "headline":
+            return "raymarch_kernel" in name
+        return "raymarch_batch_kernel" in name or "skip_kernel" in name
+
+    counters = {}   # counter -> per-launch values (headline: the last `frames` launches of its run)
+    copy = {}
+    by_file = {}
+    for f, r in rows:
+        by_file.setdefault(f, []).append(r)
+    for f, rs in by_file.items():
+        launches = {}
+        for r in rs:
+            launches.setdefault(int(r["Dispatch_Id"]), []).append(r)
+        order = sorted(launches)
+        picked = [d for d in order if is_kernel(launches[d][0]["Kernel_Name"])]
+        if kind == "headline":
+            picked = picked[-frames:]
+        copies = [d for d in order if "copyBuffer" in launches[d][0]["Kernel_Name"]]
+        for d in picked:
+            per = {}
+            for r in launches[d]:
+                per[r["Counter_Name"]] = per.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            for c, v in per.items():
+                counters.setdefault(c, {}).setdefault(d, 0.0)
+                counters[c][d] += v
+        if copies:
+            for r in launches[copies[-1]]:
+                copy[r["Counter_Name"]] = copy.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    agg = {c: (sum(v.values()) / len(v) if kind == "headline" else sum(v.values())) for c, v in counters.items()}
+    gib_kib = float(1 << 20)
+    fetch_scale = gib_kib / copy["FETCH_SIZE"]
+    write_scale = gib_kib / copy["WRITE_SIZE"]
+    traffic = (agg["FETCH_SIZE"] * fetch_scale + agg["WRITE_SIZE"] * write_scale) * 1024.0
+    files = HEADLINE_SOURCES if kind == "headline" else SERVING_SOURCES
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(root_dir, f), "rb").read())
+    rec = {"kernel": ("raymarch_kernel<f16 neighbourhood records, 5 brushed fields, no counts, 32-bit record offsets>"
+                      if kind == "headline" else
+                      "raymarch_batch_kernel (every field count) and skip_kernel of the saturated serving replay"),
+           "workload": ("512^3 x 5 fields f16, 1920x1080, step 0.5, ~10% 5-axis brush (the benchmark's headline frame)"
+                        if kind == "headline" else
+                        "serving trace: 256^3 and 512^3 x 5 f16 volumes, 512 requests 256^2..2048^2, all submitted "
+                        "at once"),
+           "source_sha256": h.hexdigest(), "source_files": files,
+           "copy_1gib_fetch_size_kib": copy["FETCH_SIZE"], "copy_1gib_write_size_kib": copy["WRITE_SIZE"],
+           "fetch_scale": fetch_scale, "write_scale": write_scale, "traffic_bytes_per_launch": traffic}
+    if kind == "headline":
+        rec["fetch_size_kib_per_dispatch"] = agg["FETCH_SIZE"]
+        rec["write_size_kib_per_dispatch"] = agg["WRITE_SIZE"]
+    else:
+        rec["fetch_size_kib_total"] = agg["FETCH_SIZE"]
+        rec["write_size_kib_total"] = agg["WRITE_SIZE"]
+        rec["note"] = ("traffic_bytes_per_launch is the whole replay (every batched and skip launch of it); "
+                       "FETCH_SIZE and WRITE_SIZE from separate rocprofv3 --pmc runs of bench.py --profile-serving, "
+                       "scaled by what they read for the 1 GiB copy at the end of the same runs")
+    traces = sorted(glob.glob(os.path.join(root, "**", "*_kernel_trace.csv"), recursive=True))
+    if kind == "headline" and traces:
+        ts = [r for r in csv.DictReader(open(traces[-1])) if is_kernel(r["Kernel_Name"])]
+        ts = sorted(ts, key=lambda r: int(r["Start_Timestamp"]))[-trace_frames:]
+        rec["trace_avg_ms"] = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in ts) / len(ts) / 1e6
+        rec["trace_note"] = f"mean of the last {len(ts)} launches of the kernel trace run (one stream)"
+    if kind == "headline" and "SQ_INSTS_VALU" in agg and "GRBM_GUI_ACTIVE" in agg:
+        simds, xcds = 1024, 8
+        cycles = agg["GRBM_GUI_ACTIVE"] / xcds
+        valu = {"busy_frac": agg["SQ_INSTS_VALU"] * 4 / (simds * cycles)}
+        if "SQ_THREAD_CYCLES_VALU" in agg and "SQ_ACTIVE_INST_VALU" in agg:
+            valu["lane_active_frac"] = agg["SQ_THREAD_CYCLES_VALU"] / (64 * agg["SQ_ACTIVE_INST_VALU"])
+            valu["executed_lane_ops"] = agg["SQ_THREAD_CYCLES_VALU"]
+            valu["lane_op_frac"] = valu["busy_frac"] * valu["lane_active_frac"]
+        if "SQ_WAVE_CYCLES" in agg:
+            valu["waves_per_simd"] = agg["SQ_WAVE_CYCLES"] * 4 / (simds * cycles)
+        rec["valu"] = valu
+        rec["counters_per_launch"] = agg
+        if "TCC_HIT_sum" in agg:
+            rec["l2_hit_frac"] = agg["TCC_HIT_sum"] / (agg["TCC_HIT_sum"] + agg["TCC_MISS_sum"])
+        if "TCP_TCC_READ_REQ_sum" in agg:
+            rec["l1_hit_frac"] = 1 - agg["TCP_TCC_READ_REQ_sum"] / agg["TCP_TOTAL_CACHE_ACCESSES_sum"]
+    json.dump(rec, open(out_path, "w"), indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def ordinal(k: int) -> str:
     return f"{k}{'th' if 10 <= k % 100 <= 20 else {1: 'st', 2: 'nd', 3: 'rd'}.get(k % 10, 'th')}"
 
@@ -538,7 +646,18 @@ def main():
     ap.add_argument("--profile-serving", action="store_true",
                     help="profiling mode: replay the serving trace once, all requests at once, then copy 1 GiB "
                          "device-to-device; prints no JSON")
+    ap.add_argument("--counter-record", choices=["headline", "serving"], default=None,
+                    help="no GPU: summarise the rocprofv3 CSVs under --counter-dir into the counter record "
+                         "--counter-out (the headline's last --counter-frames launches, or the serving replay)")
+    ap.add_argument("--counter-dir", default="")
+    ap.add_argument("--counter-out", default="")
+    ap.add_argument("--counter-frames", type=int, default=2)
+    ap.add_argument("--counter-trace-frames", type=int, default=50)
     args = ap.parse_args()
+    if args.counter_record:
+        counter_record(args.counter_record, args.counter_dir, args.counter_frames, args.counter_out,
+                       args.counter_trace_frames)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}): the renderer shards by request across "
               "GPUs with no communication, so per-GPU numbers are the 1-GPU numbers.", file=sys.stderr)

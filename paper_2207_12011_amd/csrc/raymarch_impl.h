@@ -390,7 +390,9 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     // ---- shell segments
     const float b = fmaf(ox, dx, fmaf(oy, dy, oz * dz));
     const float fx = fmaf(-b, dx, ox), fy = fmaf(-b, dy, oy), fz = fmaf(-b, dz, oz);
-    float seg_a[2] = {0.0f, 0.0f}, seg_b[2] = {0.0f, 0.0f};
+    // the non-empty segments in ray order, (sa0, sb0) then (sa1, sb1) (scalars: an array indexed by
+    // the segment count would live in scratch memory)
+    float sa0 = 0.0f, sb0 = 0.0f, sa1 = 0.0f, sb1 = 0.0f;
     int nseg = 0;
     float t0, t1;
     if (inside && sphere_hit(b, fx, fy, fz, A.r_out2, A.c_out, t0, t1)) {
@@ -403,19 +405,13 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
             cb1 = t1;
         }
         ca0 = fmaxf(ca0, 0.0f);
-        if (cb0 > ca0) {
-            seg_a[nseg] = ca0;
-            seg_b[nseg] = cb0;
-            ++nseg;
-        }
-        if (inner) {
-            ca1 = fmaxf(ca1, 0.0f);
-            if (cb1 > ca1) {
-                seg_a[nseg] = ca1;
-                seg_b[nseg] = cb1;
-                ++nseg;
-            }
-        }
+        ca1 = fmaxf(ca1, 0.0f);
+        const bool near = cb0 > ca0, far = inner && cb1 > ca1;
+        nseg = static_cast<int>(near) + static_cast<int>(far);
+        sa0 = near ? ca0 : ca1;
+        sb0 = near ? cb0 : cb1;
+        sa1 = ca1;
+        sb1 = cb1;
     }
 
     // the transfer-function table into LDS; a one-wave block loads it only if one of its rays passes
@@ -450,7 +446,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     uint32_t cnt_eval = 0, cnt_fetch = 0;  // COUNTS: this lane's evaluated samples and field fetches
     uint32_t last_brick = 0xFFFFFFFFu;
     int seg = 0, j0 = 0;  // j0: first sample of the quad's current step
-    float sa = seg_a[0], sb = seg_b[0];
+    float sa = sa0, sb = sb0;
     // grid origin of the current segment: sample j covers [max(sa, g + j ds), min(g + (j+1) ds, sb)]
     float s_jit = 0.0f;
     if constexpr (JIT) s_jit = jitter_offset(A, static_cast<uint32_t>(py) * A.width + px);
@@ -754,8 +750,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
             if (j0 >= ns) {
                 if (seg + 1 < nseg) {
                     seg = 1;
-                    sa = seg_a[1];
-                    sb = seg_b[1];
+                    sa = sa1;
+                    sb = sb1;
                     g = JIT ? fmaf(-s_jit, ds, sa) : sa;
                     ns = max(static_cast<int>(ceilf((sb - g) / ds)), 1);
                     j0 = 0;
