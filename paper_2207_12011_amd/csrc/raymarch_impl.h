@@ -453,11 +453,27 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     float g = JIT ? fmaf(-s_jit, ds, sa) : sa;
     int ns = nseg > 0 ? max(static_cast<int>(ceilf((sb - g) / ds)), 1) : 0;
     bool alive = nseg > 0;
+    // The segment's partial samples, computed once per segment: the last (and, in a jittered pass, the
+    // first) sample covers only part of its step; it is taken at the midpoint of what it covers and its
+    // opacity corrected to that length (r = length / ref_step).  Every other sample j sits at
+    // g + (j + 1/2) ds with r = ds / ref_step.
+    float tm_first = 0.0f, r_first = 0.0f, tm_last = 0.0f, r_last = 0.0f;
+    auto partial_samples = [&]() {
+        if constexpr (JIT) {
+            const float thi0 = ns == 1 ? sb : fmaf(1.0f, ds, g);
+            tm_first = 0.5f * (sa + thi0);
+            r_first = fmaxf(thi0 - sa, 0.0f) * A.inv_ref;
+        }
+        const float tlo = fmaf(static_cast<float>(ns - 1), ds, g);
+        tm_last = 0.5f * (tlo + sb);
+        r_last = fmaxf(sb - tlo, 0.0f) * A.inv_ref;
+    };
+    partial_samples();
 
     while (alive) {
         // ---- sample positions and their bricks' flag words (the loads of all P samples together)
-        bool valid[P], skipped[P], pass[P], partial[P];
-        float tv[P], tm[P], len_partial[P], ux[P], uy[P], uz[P], flx[P], fly[P], flz[P];
+        bool valid[P], skipped[P], pass[P];
+        float tv[P], tm[P], rs[P], ux[P], uy[P], uz[P], flx[P], fly[P], flz[P];
         int x0[P], y0[P], z0[P];
         uint32_t brick[P], sbi[P], flags[P];
 #pragma unroll
@@ -465,22 +481,16 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
             const int j = j0 + kQuad * q + sub;
             valid[q] = j < ns;
             const bool last = j == ns - 1;
-            partial[q] = last;
             skipped[q] = false;
             pass[q] = false;
             tv[q] = 0.0f;
-            float tlo;
+            tm[q] = last ? tm_last : fmaf(static_cast<float>(j) + 0.5f, ds, g);
+            rs[q] = last ? r_last : r_full;
             if constexpr (JIT) {
-                const bool first = j == 0;
-                partial[q] = first || last;
-                tlo = first ? sa : fmaf(static_cast<float>(j), ds, g);
-                const float thi = last ? sb : fmaf(static_cast<float>(j) + 1.0f, ds, g);
-                tm[q] = partial[q] ? 0.5f * (tlo + thi) : fmaf(static_cast<float>(j) + 0.5f, ds, g);
-                len_partial[q] = fmaxf(thi - tlo, 0.0f);
-            } else {
-                tlo = fmaf(static_cast<float>(j), ds, sa);
-                tm[q] = last ? 0.5f * (tlo + sb) : fmaf(static_cast<float>(j) + 0.5f, ds, sa);
-                len_partial[q] = fmaxf(sb - tlo, 0.0f);
+                if (j == 0) {
+                    tm[q] = tm_first;
+                    rs[q] = r_first;
+                }
             }
             ux[q] = fmaf(dux, tm[q], uox), uy[q] = fmaf(duy, tm[q], uoy), uz[q] = fmaf(duz, tm[q], uoz);
             flx[q] = floorf(ux[q]), fly[q] = floorf(uy[q]), flz[q] = floorf(uz[q]);
@@ -635,26 +645,6 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                 }
             }
         }
-        // ---- classification: every lane evaluates it, and a lane whose sample was not fetched or
-        // failed the brush contributes nothing (k = 1, w = 0), so the values merged below are those
-        // of the sequential definition
-        bool contributes[P];
-        float kc[P], cr[P], cg[P], cb[P];
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            const float xt = fminf(fmaxf((tv[q] - A.vmin) * A.inv_range, 0.0f), 1.0f) * 255.0f;
-            const int it = min(static_cast<int>(xt), 254);
-            const float wt = xt - static_cast<float>(it);
-            const float4 e0 = s_tf[it], e1 = s_tf[it + 1];
-            const float al = fmaf(wt, e1.w - e0.w, e0.w);
-            contributes[q] = pass[q] && al > 0.0f;
-            const float r = partial[q] ? len_partial[q] * A.inv_ref : r_full;
-            kc[q] = al >= 1.0f ? 0.0f : __builtin_amdgcn_exp2f(r * __log2f(1.0f - al));
-            cr[q] = fmaf(wt, e1.x - e0.x, e0.x);
-            cg[q] = fmaf(wt, e1.y - e0.y, e0.y);
-            cb[q] = fmaf(wt, e1.z - e0.z, e0.z);
-        }
-
         // ---- advance past a skipped box of the quad's last sample
         const int last_skipped = quad_bcast<3>(static_cast<int>(skipped[P - 1]));
         const int jn3 = quad_bcast<3>(jn);
@@ -662,11 +652,23 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
         int stop_at = kQuad - 1;  // COUNTS: the quad's last sample that counts
 #pragma unroll
         for (int q = 0; q < P; ++q) {
+            // nothing to classify or composite when no sample of the group passed the brush
+            if (__ballot(pass[q] && !stopped) == 0ull) continue;
+            const float xt = fminf(fmaxf((tv[q] - A.vmin) * A.inv_range, 0.0f), 1.0f) * 255.0f;
+            const int it = min(static_cast<int>(xt), 254);
+            const float wt = xt - static_cast<float>(it);
+            const float4 e0 = s_tf[it], e1 = s_tf[it + 1];
+            const float al = fmaf(wt, e1.w - e0.w, e0.w);
+            const bool contributes = pass[q] && al > 0.0f;
+            const float kcq = al >= 1.0f ? 0.0f : __builtin_amdgcn_exp2f(rs[q] * __log2f(1.0f - al));
             // a ray that stopped in an earlier group composites nothing more
-            const bool con = contributes[q] && !stopped;
+            const bool con = contributes && !stopped;
             if (__ballot(con) == 0ull) continue;  // else nothing to composite anywhere in the wave
-            const float keep = con ? kc[q] : 1.0f;
-            const float qr = con ? cr[q] : 0.0f, qg = con ? cg[q] : 0.0f, qb = con ? cb[q] : 0.0f;
+            const float crq = fmaf(wt, e1.x - e0.x, e0.x);
+            const float cgq = fmaf(wt, e1.y - e0.y, e0.y);
+            const float cbq = fmaf(wt, e1.z - e0.z, e0.z);
+            const float keep = con ? kcq : 1.0f;
+            const float qr = con ? crq : 0.0f, qg = con ? cgq : 0.0f, qb = con ? cbq : 0.0f;
             // ---- merge the quad's four samples in sample order.  Every lane replays the same
             // sequential updates (T <- T k, then C <- C + w rgb) on broadcast values, so the ray
             // state is identical in the four lanes and independent of how samples were grouped
@@ -754,6 +756,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                     sb = sb1;
                     g = JIT ? fmaf(-s_jit, ds, sa) : sa;
                     ns = max(static_cast<int>(ceilf((sb - g) / ds)), 1);
+                    partial_samples();
                     j0 = 0;
                 } else {
                     alive = false;
