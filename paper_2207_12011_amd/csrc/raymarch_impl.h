@@ -175,19 +175,25 @@ __device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32
     }
 }
 
-// fetch_rec at 32-bit offsets for a lane that may not need the value: where `use` is clear the loads
-// go to an offset beyond the field, which reads no memory and returns zero (the value is then
-// meaningless).  Loads issued this way need no branch, so those of several samples can be in flight
-// together.  kNoLoad lies beyond every field and flag array (record fields of the 32-bit offset
-// kinds stay below 0xFF4E0000 bytes).
+// fetch_rec for a lane that may not need the value (the value is then meaningless).  At 32-bit offsets
+// the loads of a lane whose `use` is clear go to an offset beyond the field, which reads no memory and
+// returns zero: issued this way the loads need no branch, so those of several samples are in flight
+// together.  kNoLoad lies beyond every field and flag array (record fields of the 32-bit offset kinds
+// stay below 0xFF4E0000 bytes).  At 64-bit offsets (global loads) the loads are predicated.
 constexpr uint32_t kNoLoad = 0xFFFFFFF0u;
-template <int S>
+template <int S, bool WIDE>
 __device__ __forceinline__ float fetch_rec_guarded(const void* __restrict__ base, uint32_t bytes, bool use, uint32_t r00,
                                                    uint32_t r10, uint32_t r01, uint32_t r11, const Tri& t) {
-    const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes), kRawBufferFlags);
     auto ld = [&](uint32_t r) -> u32x2 {
-        return __builtin_amdgcn_raw_buffer_load_b64(rsrc, static_cast<int>(use ? r << 3 : kNoLoad), 0, 0);
+        if constexpr (WIDE) {
+            u32x2 v = {0u, 0u};
+            if (use) v = global_ptr<u32x2>(static_cast<const char*>(base) + static_cast<size_t>(r) * 8u)[0];
+            return v;
+        } else {
+            const __amdgpu_buffer_rsrc_t rsrc =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes), kRawBufferFlags);
+            return __builtin_amdgcn_raw_buffer_load_b64(rsrc, static_cast<int>(use ? r << 3 : kNoLoad), 0, 0);
+        }
     };
     if constexpr (S == kF16) {
         const u32x2 p = ld(r00);
@@ -335,14 +341,14 @@ __device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) 
     return fminf(s, 0x1.fffffep-1f);
 }
 
-// Samples a lane evaluates per step.  binary16 records read at 32-bit offsets take two, j0 + sub
-// and j0 + 4 + sub: their record loads are buffer loads, which load nothing (and return zero) at an
-// offset beyond the field, so the loads of both samples are issued together, unconditionally, and
-// a wave has twice the loads in flight while each ray advances eight samples per step (headline
-// frame 0.876 -> 0.740 ms).  float32-pair records (float32 and decoded 8-bit values) take one: with
-// two, their four record loads per field and sample need 82 registers, which leaves 5 waves per
-// SIMD, and two frames in flight ran 4 % slower.  The counting variant and the other kinds take one.
-constexpr int samples_per_lane(int K, bool COUNTS, bool WIDE) { return K == kKindF16Rec && !WIDE && !COUNTS ? 2 : 1; }
+// Samples a lane evaluates per step.  binary16 records take two, j0 + sub and j0 + 4 + sub: the
+// loads of both samples are issued together (see fetch_rec_guarded), so a wave has twice the loads
+// in flight while each ray advances eight samples per step (headline frame 0.876 -> 0.740 ms; the
+// 1024^3 4K passes at 64-bit offsets 17-21 % faster).  The other kinds take one: with two, float32-pair
+// records (float32 and decoded 8-bit values) need 82 registers, which leaves 5 waves per SIMD (two
+// frames in flight 4 % slower); the compact binary16 layout 87 (7 % slower) and the compact 8-bit
+// layout 151 (10 % slower).  The counting variant takes one.
+constexpr int samples_per_lane(int K, bool COUNTS) { return !COUNTS && K == kKindF16Rec ? 2 : 1; }
 
 // One 4 x 4 pixel tile (bx, by) of the image described by A, marched by the calling one-wave block.  NB is the number of brushed fields, or kRuntimeNB to read it from A.
 // JIT: a jittered progressive pass (the sample grid of every segment starts s ds before it, so the
@@ -364,8 +370,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     constexpr int S = storage_of(K);
     constexpr bool R = records_of(K);
     constexpr int RT = record_type_of(K);
-    constexpr int P = samples_per_lane(K, COUNTS, WIDE);
-    static_assert(P == 1 || (R && !WIDE && !COUNTS), "two samples per lane need buffer-loaded records");
+    constexpr int P = samples_per_lane(K, COUNTS);
+    static_assert(P == 1 || !COUNTS, "the counting variant takes one sample per lane");
     // the wave tile: tw x th pixels, tw = 2^t (A.tile_log2w), th = 16 / tw; a block of four waves
     // takes 2 x 2 wave tiles
     const int tl = A.tile_log2w, tw = 1 << tl, th = kWaveRays >> tl;
@@ -595,8 +601,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                 for (int q = 0; q < P; ++q) {
                     if constexpr (R) {
                         if constexpr (P > 1)
-                            v[q] = fetch_rec_guarded<RT>(A.rec[k], A.rec_bytes, pass[q], r00[q], r10[q], r01[q],
-                                                         r11[q], tri[q]);
+                            v[q] = fetch_rec_guarded<RT, WIDE>(A.rec[k], A.rec_bytes, pass[q], r00[q], r10[q], r01[q],
+                                                               r11[q], tri[q]);
                         else
                             v[q] = fetch_rec<RT, WIDE>(A.rec[k], A.rec_bytes, r00[q], r10[q], r01[q], r11[q], tri[q]);
                     } else {
