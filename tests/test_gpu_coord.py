@@ -68,6 +68,8 @@ def test_coordinate_cuts_match_oracle(rp, ctx, small5, storage):
             compare(cpu(rgba), ref, cpu(nom), cpu(comp), label=f"{storage} cut {ci} brushed {brushed}")
             a = rp.render_debug(ctx, vid, cam, wl.width, wl.height, 0, wl.step, skip=False)
             assert all(np.array_equal(cpu(x), cpu(y)) for x, y in zip((rgba, nom, comp), a))
+            # the plain render (run-time field count; two samples per lane for binary16 records)
+            assert np.array_equal(cpu(rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step)), cpu(rgba))
     rp.set_coordinate_brush(ctx, vid, [0, 0, 0, 0], [0] * 4, [0] * 4)
     rp.unload(ctx, vid)
 

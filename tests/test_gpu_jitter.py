@@ -66,6 +66,10 @@ def test_jittered_passes_match_oracle(rp, ctx, small5, storage):
         ref = oracle.render_workload(wl, level, pixels=np.arange(npx), jitter=s)
         st = compare(cpu(rgba).reshape(-1, 4), ref, cpu(nom).reshape(-1), cpu(comp).reshape(-1),
                      label=f"{storage} pass {k}")
+        # the plain jittered kernel (two samples per lane for binary16 records) marches the same samples
+        # as the counting one (one per lane)
+        plain = rp.render_jittered(ctx, vid, wl.camera.as_array(), wl.width, wl.height, 0, wl.step, k, K, SEED)[0]
+        assert np.array_equal(cpu(plain), cpu(rgba)), (storage, k)
         gpu_passes.append(cpu(rgba).reshape(-1, 4).astype(np.float64))
         ref_sum += st["matched"]
     m = cpu(mean).reshape(-1, 4).astype(np.float64)

@@ -642,11 +642,15 @@ def test_jitter_and_coordinates_512_full_size_sampled(rp, ctx, c2):
         ref = oracle.render_workload(wl, level, pixels=pix, jitter=s)
         compare(cpu(rgba).reshape(-1, 4)[pix], ref, cpu(nom).reshape(-1)[pix], cpu(comp).reshape(-1)[pix],
                 label="c2 f16 jittered pass 3 of 8")
+        # the plain jittered kernel (two samples per lane) gives the counting kernel's image
+        plain = rp.render_jittered(ctx, vid, cam, wl.width, wl.height, 0, wl.step, 3, 8, 0x2207)[0]
+        assert np.array_equal(cpu(plain), cpu(rgba))
         coord = ([1, 0, 0, 1], [-0.3, 0, 0, 0.7], [0.4, 0, 0, 2.0])
         rp.set_coordinate_brush(ctx, vid, *coord)
         rgba, nom, comp = gpu_render(rp, ctx, vid, wl, 0)
         ref = oracle.render_workload(wl, level, pixels=pix, coord=coord)
         compare(rgba.reshape(-1, 4)[pix], ref, nom.reshape(-1)[pix], comp.reshape(-1)[pix], label="c2 f16 coordinate cut")
+        assert np.array_equal(cpu(rp.render(ctx, vid, cam, wl.width, wl.height, 0, wl.step)), rgba)
     finally:
         rp.unload(ctx, vid)
 
