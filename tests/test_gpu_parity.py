@@ -617,6 +617,18 @@ def test_large_progressive_1024_4k_sampled(rp, ctx, capsys):
                     compare(rgba.reshape(-1, 4)[pix], ref, nom.reshape(-1)[pix], comp.reshape(-1)[pix], label=label)
                 else:
                     compare(passes[k].reshape(-1, 4)[pix], ref, label=label)
+        # the same final pass served (the batched kernel at 64-bit record offsets, two samples per
+        # lane) equals the single render bit for bit
+        b = brushes[-1]
+        out = torch.empty((wl.height, wl.width, 4), dtype=torch.float32, device="cuda")
+        rp.server_start(ctx, 8 << 30, 8, 32768, 2)
+        try:
+            req = rp.make_request(vid, cam, wl.width, wl.height, out, -1, wl.step, b.active, b.lo, b.hi, 0)
+            rp.wait(ctx, rp.submit(ctx, req), 120000)
+        finally:
+            rp.server_stop(ctx)
+        say("served the final pass")
+        assert np.array_equal(cpu(out).view(np.uint32), passes[2].view(np.uint32))
     finally:
         rp.unload(ctx, vid)
 
