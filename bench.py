@@ -96,7 +96,9 @@ def counter_record(kind, root, frames, out_path, trace_frames=50):
             return "raymarch_kernel" in name
         return "raymarch_batch_kernel" in name or "skip_kernel" in name
 
-    counters = {}   # counter -> per-launch values (headline: the last `frames` launches of its run)
+    # counter -> {(pass file, launch): value}; a counter collected in several passes is averaged over
+    # them (headline) rather than added up
+    counters = {}
     copy = {}
     by_file = {}
     for f, r in rows:
@@ -115,12 +117,18 @@ def counter_record(kind, root, frames, out_path, trace_frames=50):
             for r in launches[d]:
                 per[r["Counter_Name"]] = per.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
             for c, v in per.items():
-                counters.setdefault(c, {}).setdefault(d, 0.0)
-                counters[c][d] += v
+                counters.setdefault(c, {})[(f, d)] = v
         if copies:
             for r in launches[copies[-1]]:
                 copy[r["Counter_Name"]] = copy.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
-    agg = {c: (sum(v.values()) / len(v) if kind == "headline" else sum(v.values())) for c, v in counters.items()}
+    def combine(vals):
+        per_file = {}
+        for (f, _), v in vals.items():
+            per_file.setdefault(f, []).append(v)
+        if kind == "headline":   # mean per launch
+            return sum(vals.values()) / len(vals)
+        return sum(sum(v) for v in per_file.values()) / len(per_file)   # whole replay, mean over passes
+    agg = {c: combine(v) for c, v in counters.items()}
     gib_kib = float(1 << 20)
     fetch_scale = gib_kib / copy["FETCH_SIZE"]
     write_scale = gib_kib / copy["WRITE_SIZE"]
