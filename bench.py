@@ -119,8 +119,11 @@ def counter_record(kind, root, frames, out_path, trace_frames=50):
             for c, v in per.items():
                 counters.setdefault(c, {})[(f, d)] = v
         if copies:
+            per = {}
             for r in launches[copies[-1]]:
-                copy[r["Counter_Name"]] = copy.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+                per[r["Counter_Name"]] = per.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            for c, v in per.items():
+                copy.setdefault(c, []).append(v)
     def combine(vals):
         per_file = {}
         for (f, _), v in vals.items():
@@ -129,6 +132,7 @@ def counter_record(kind, root, frames, out_path, trace_frames=50):
             return sum(vals.values()) / len(vals)
         return sum(sum(v) for v in per_file.values()) / len(per_file)   # whole replay, mean over passes
     agg = {c: combine(v) for c, v in counters.items()}
+    copy = {c: sum(v) / len(v) for c, v in copy.items()}
     gib_kib = float(1 << 20)
     fetch_scale = gib_kib / copy["FETCH_SIZE"]
     write_scale = gib_kib / copy["WRITE_SIZE"]
