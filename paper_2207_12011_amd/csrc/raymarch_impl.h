@@ -498,7 +498,11 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                     rs[q] = r_first;
                 }
             }
-            ux[q] = fmaf(dux, tm[q], uox), uy[q] = fmaf(duy, tm[q], uoy), uz[q] = fmaf(duz, tm[q], uoz);
+            // a position below the grid (u < 0 on an axis, where both corners clamp to index 0) is taken
+            // on its lower face, u = 0: the upper corner's weight is then zero, which gives the clamped
+            // value exactly (and lets a record of the base voxel serve)
+            ux[q] = fmaxf(fmaf(dux, tm[q], uox), 0.0f), uy[q] = fmaxf(fmaf(duy, tm[q], uoy), 0.0f);
+            uz[q] = fmaxf(fmaf(duz, tm[q], uoz), 0.0f);
             flx[q] = floorf(ux[q]), fly[q] = floorf(uy[q]), flz[q] = floorf(uz[q]);
             // corner indices clamped onto the grid (the clamp taken on the integer-valued floors)
             x0[q] = static_cast<int>(__builtin_amdgcn_fmed3f(flx[q], 0.0f, top));
@@ -550,10 +554,7 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                         last_brick = brick[q];
                     }
                 }
-                // below the grid both corners of an axis clamp to index 0: a zero weight on the upper
-                // corner gives that value exactly, and lets a record of the clamped base voxel serve
-                const float wx = flx[q] < 0.0f ? 0.0f : ux[q] - flx[q], wy = fly[q] < 0.0f ? 0.0f : uy[q] - fly[q];
-                const float wz = flz[q] < 0.0f ? 0.0f : uz[q] - flz[q];
+                const float wx = ux[q] - flx[q], wy = uy[q] - fly[q], wz = uz[q] - flz[q];
                 tri[q] = tri_weights(wx, wy, wz);
                 r00[q] = r10[q] = r01[q] = r11[q] = 0;
                 if constexpr (R) {
@@ -561,21 +562,22 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                     // sub-brick in bits 6-8 and its place in that in bits 0-5.  The voxel one up in
                     // z (y) follows by a step that depends on where the base voxel lies in its
                     // sub-brick and brick: +16 (+4) inside a sub-brick, to the next sub-brick, or to
-                    // the next brick; none where the upper corner clamps onto the base voxel.
+                    // the next brick; none where the upper corner clamps onto the base voxel (at the
+                    // grid's upper face).
                     r00[q] = (brick[q] << 9) | (sbi[q] << 6) |
                              static_cast<uint32_t>((x0[q] & 3) | ((y0[q] & 3) << 2) | ((z0[q] & 3) << 4));
                     const uint32_t dz = (z0[q] & 3) != 3 ? 16u : ((z0[q] & 4) == 0 ? 208u : z_brick_step);
-                    r01[q] = r00[q] + (flz[q] >= 0.0f && flz[q] < top ? dz : 0u);
+                    r01[q] = r00[q] + (flz[q] < top ? dz : 0u);
                     if constexpr (RT == kF32) {
                         const uint32_t dy = (y0[q] & 3) != 3 ? 4u : ((y0[q] & 4) == 0 ? 116u : y_brick_step);
-                        const uint32_t dyv = fly[q] >= 0.0f && fly[q] < top ? dy : 0u;
+                        const uint32_t dyv = fly[q] < top ? dy : 0u;
                         r10[q] = r00[q] + dyv;
                         r11[q] = r01[q] + dyv;
                     }
                 } else {
                     constexpr int LB = kLogBytes<S>;
                     const int ix = static_cast<int>(flx[q]), iy = static_cast<int>(fly[q]), iz = static_cast<int>(flz[q]);
-                    const int x1 = min(max(ix + 1, 0), n - 1), y1 = min(max(iy + 1, 0), n - 1), z1 = min(max(iz + 1, 0), n - 1);
+                    const int x1 = min(ix + 1, n - 1), y1 = min(iy + 1, n - 1), z1 = min(iz + 1, n - 1);
                     const uint32_t X0 = axis_x(x0[q]) << LB, X1 = axis_x(x1) << LB;
                     const uint32_t Y0 = axis_y(y0[q], nb) << LB, Y1 = axis_y(y1, nb) << LB;
                     const uint32_t Z0 = axis_z(z0[q], nb) << LB, Z1 = axis_z(z1, nb) << LB;
