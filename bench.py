@@ -204,10 +204,14 @@ def profile(args, wl, raypc, torch):
     raypc.set_brush(ctx, vid, wl.brush.active, wl.brush.lo, wl.brush.hi)
     out = torch.empty((wl.height, wl.width, 4), dtype=torch.float32, device="cuda")
     cam = wl.camera.as_array()
-    # the launch shape the benchmark would pick; the profiled frames are the last launches
-    (bs, bt), times = raypc.autotune_render(ctx, vid, cam, wl.width, wl.height, -1, wl.step, 5)
-    print(f"[bench] profile mode: launch shape: {1 << bt}x{16 >> bt} px wave tiles, super_log2 {bs} "
-          f"(ms by [tile][super]: {times})", file=sys.stderr)
+    # the default launch shape (4x4-pixel wave tiles in 32x32-pixel super-tiles, the one the benchmark's
+    # autotuner keeps on this device), fixed so that every counter pass profiles the same launches
+    # (timing a tuner under counter collection would pick among nearly equal shapes by noise); a few
+    # warm-up frames, then the profiled frames are the last launches
+    raypc.set_launch_shape(ctx, 2, 2)
+    for _ in range(5):
+        raypc.render(ctx, vid, cam, wl.width, wl.height, -1, wl.step, out=out)
+    print("[bench] profile mode: launch shape: 4x4 px wave tiles, super_log2 2 (fixed)", file=sys.stderr)
     torch.cuda.synchronize()
     for _ in range(args.profile_frames):
         raypc.render(ctx, vid, cam, wl.width, wl.height, -1, wl.step, out=out)
