@@ -432,7 +432,7 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
     {
         const uint64_t fb = static_cast<uint64_t>(L.n) * L.n * L.n * storage_bytes(v->storage);
         a.field_bytes = fb > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(fb);
-        a.par_bytes = static_cast<uint32_t>(L.n_bricks() * sizeof(float2));
+        a.par_bytes = static_cast<uint32_t>((L.n_bricks() + 1) * sizeof(float2));   // with the zero pair after the last brick
         const uint64_t rb = static_cast<uint64_t>(L.n) * L.n * L.n * 8u;
         a.rec_bytes = rb > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(rb);
     }
@@ -627,7 +627,9 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
             const size_t lvox = static_cast<size_t>(L.n) * L.n * L.n;
             for (int f = 0; f < n_fields && !rc; ++f) {
                 rc = dev_alloc(v, &L.data[f], lvox * storage_bytes(storage));
-                if (!rc && storage == kU8) rc = dev_alloc(v, reinterpret_cast<void**>(&L.par[f]), L.n_bricks() * sizeof(float2));
+                // one pair more than the bricks, left zero: the ray march reads each brick's pair together
+                // with the next one, the last brick's included
+                if (!rc && storage == kU8) rc = dev_alloc(v, reinterpret_cast<void**>(&L.par[f]), (L.n_bricks() + 1) * sizeof(float2));
                 if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm[f]), L.n_bricks() * sizeof(float2));
                 if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm_sub[f]), L.n_bricks() * 8 * sizeof(float2));
                 if (!rc && v->records) rc = dev_alloc(v, &L.rec[f], lvox * 8);
@@ -685,6 +687,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                     if ((e = launch_lod_build(cur, v->lv[l - 1].n, nxt, s)) != hipSuccess) { rc = hip_fail(e, "level build"); break; }
                     cur = nxt;
                 }
+                if (storage == kU8 && (e = hipMemsetAsync(L.par[f] + L.n_bricks(), 0, sizeof(float2), s)) != hipSuccess) { rc = hip_fail(e, "pair padding"); break; }
                 if ((e = launch_encode(cur, L.n, storage, L.data[f], L.par[f], f16_scale, s)) != hipSuccess) { rc = hip_fail(e, "encode"); break; }
                 if ((e = launch_minmax(L.data[f], L.par[f], L.n, storage, L.mm[f], L.mm_sub[f], f16_scale, s)) != hipSuccess) { rc = hip_fail(e, "min/max"); break; }
                 if (l == 0 && (e = launch_gather_pairs(L.mm_sub[f], d_cell_sub, n_cells, d_sub + static_cast<size_t>(f) * n_cells,
