@@ -50,6 +50,28 @@ __host__ __device__ inline uint32_t brick_local(int x, int y, int z) {
            (static_cast<uint32_t>(y & 3) << 2) | static_cast<uint32_t>(x & 3);
 }
 
+// 8-bit codes use a layout of their own: each 8^3 brick is a 9 x 9 x 8 block of bytes, [z][y][x]
+// (648 bytes, bricks in [bz][by][bx] order), holding its 512 codes and, at local x = 8 and y = 8,
+// copies of the codes one voxel beyond its upper x and y faces (the next bricks' first voxels; at the
+// grid's upper faces the last voxel again, where the interpolation clamps).  The four corners of a
+// cell at one z then lie at byte offsets 0, 1, 9 and 10 from its base voxel, within one 12-byte load.
+// A copy keeps the code of the voxel it copies: each corner is still decoded with the (scale, offset)
+// pair of the brick the voxel belongs to.
+constexpr uint32_t kU8BrickBytes = 648;
+__host__ __device__ inline uint32_t brick_index(int x, int y, int z, int nb) {
+    return static_cast<uint32_t>(x >> 3) + static_cast<uint32_t>(nb) * (static_cast<uint32_t>(y >> 3) +
+                                                                        static_cast<uint32_t>(nb) * static_cast<uint32_t>(z >> 3));
+}
+__host__ __device__ inline uint32_t u8_addr(int x, int y, int z, int nb) {
+    return brick_index(x, y, z, nb) * kU8BrickBytes + static_cast<uint32_t>(z & 7) * 81u +
+           static_cast<uint32_t>(y & 7) * 9u + static_cast<uint32_t>(x & 7);
+}
+// Bytes of one field's 8-bit code array on a level with nb bricks per axis: the bricks plus 16 bytes,
+// so that the 12-byte load at the last brick's last voxel stays inside the array.
+__host__ __device__ inline size_t u8_field_bytes(int nb) {
+    return static_cast<size_t>(nb) * nb * nb * kU8BrickBytes + 16;
+}
+
 // Coordinate axes of a brush at a position (x, y, z world units): bit a of mask enables axis a
 // (x, y, z, radius) with inclusive bounds [clo[a], chi[a]]; the radius is tested on float32
 // squares, r^2 = fl32(fl32(fl32(x x) + fl32(y y)) + fl32(z z)) against clo[3] <= r^2 <= chi[3].

@@ -29,17 +29,19 @@
 namespace raypc {
 namespace {
 
-// Stored value at brick-ordered index a: binary16 codes are held scaled by the field's power of two
-// 2^k (see f16_scale_kernel) and `descale` = 2^-k gives the value back exactly.
+// Stored value of voxel (x, y, z) on a level with nb bricks per axis: binary16 codes are held scaled
+// by the field's power of two 2^k (see f16_scale_kernel) and `descale` = 2^-k gives the value back
+// exactly; an 8-bit code is decoded with its brick's (scale, offset) pair.
 template <int S>
-__device__ __forceinline__ float stored(const void* base, const float2* par, uint32_t a, float descale = 1.0f) {
+__device__ __forceinline__ float stored(const void* base, const float2* par, int x, int y, int z, int nb,
+                                        float descale = 1.0f) {
     if constexpr (S == kF32) {
-        return static_cast<const float*>(base)[a];
+        return static_cast<const float*>(base)[brick_addr(x, y, z, nb)];
     } else if constexpr (S == kF16) {
-        return __half2float(static_cast<const __half*>(base)[a]) * descale;
+        return __half2float(static_cast<const __half*>(base)[brick_addr(x, y, z, nb)]) * descale;
     } else {
-        const float q = static_cast<float>(static_cast<const uint8_t*>(base)[a]);
-        const float2 p = par[a >> 9];
+        const float q = static_cast<float>(static_cast<const uint8_t*>(base)[u8_addr(x, y, z, nb)]);
+        const float2 p = par[brick_index(x, y, z, nb)];
         return __fadd_rn(__fmul_rn(p.x, q), p.y);
     }
 }
@@ -134,10 +136,11 @@ __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ i
     const int x = bx * 8 + (t & 7), y = by * 8 + ((t >> 3) & 7), z = bz * 8 + (t >> 6);
     const size_t nn = static_cast<size_t>(n);
     const float v = in[(static_cast<size_t>(z) * nn + y) * nn + x];
-    const uint32_t a = (brick << 9) | brick_local(t & 7, (t >> 3) & 7, t >> 6);
     if constexpr (S == kF32) {
+        const uint32_t a = (brick << 9) | brick_local(t & 7, (t >> 3) & 7, t >> 6);
         static_cast<float*>(out)[a] = v;
     } else if constexpr (S == kF16) {
+        const uint32_t a = (brick << 9) | brick_local(t & 7, (t >> 3) & 7, t >> 6);
         // scaling by a power of two is exact: only the binary16 rounding remains
         static_cast<__half*>(out)[a] = __float2half_rn(v * (f16_scale ? f16_scale[0] : 1.0f));
     } else {
@@ -158,9 +161,24 @@ __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ i
         const float scale = __fdiv_rn(__fsub_rn(mx, mn), 255.0f);
         float q = 0.0f;
         if (scale > 0.0f) q = fminf(fmaxf(rintf(__fdiv_rn(__fsub_rn(v, mn), scale)), 0.0f), 255.0f);
-        static_cast<uint8_t*>(out)[a] = static_cast<uint8_t>(q);
+        static_cast<uint8_t*>(out)[brick * kU8BrickBytes + (t >> 6) * 81u + ((t >> 3) & 7) * 9u + (t & 7)] =
+            static_cast<uint8_t>(q);
         if (t == 0) u8par[brick] = make_float2(scale, mn);
     }
+}
+
+// 8-bit codes: the copies at local x = 8 and y = 8 of every brick (136 per brick: 9 at y = 8 and 8 at
+// x = 8 in each of the 8 z planes), taken from the voxels they copy once every brick is encoded.
+__global__ __launch_bounds__(192) void u8_apron_kernel(uint8_t* __restrict__ codes, int n) {
+    const int nb = n >> 3;
+    const uint32_t brick = blockIdx.x;
+    const int k = threadIdx.x;
+    if (k >= 136) return;
+    const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
+    const int lz = k / 17, r = k % 17;
+    const int lx = r < 9 ? r : 8, ly = r < 9 ? 8 : r - 9;
+    const int x = min(bx * 8 + lx, n - 1), y = min(by * 8 + ly, n - 1), z = bz * 8 + lz;
+    codes[brick * kU8BrickBytes + lz * 81u + ly * 9u + lx] = codes[u8_addr(x, y, z, nb)];
 }
 
 // One wave per brick: min / max over the 9^3 apron window of stored values, and over the 5^3 apron
@@ -185,7 +203,7 @@ __global__ __launch_bounds__(64) void minmax_kernel(const void* __restrict__ dat
         const int x = min(bx * 8 + lx, n - 1);
         const int y = min(by * 8 + ly, n - 1);
         const int z = min(bz * 8 + lz, n - 1);
-        const float v = stored<S>(data, par, brick_addr(x, y, z, nb), descale);
+        const float v = stored<S>(data, par, x, y, z, nb, descale);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const bool in = ((i & 1) ? lx >= 4 : lx <= 4) && ((i & 2) ? ly >= 4 : ly <= 4) &&
@@ -221,7 +239,7 @@ __global__ void decode_kernel(const void* __restrict__ data, const float2* __res
     const uint32_t total = static_cast<uint32_t>(n) * n * n;
     if (o >= total) return;
     const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
-    out[o] = stored<S>(data, par, brick_addr(x, y, z, n >> 3), descale);
+    out[o] = stored<S>(data, par, x, y, z, n >> 3, descale);
 }
 
 // One thread per voxel: gather its 8-byte neighbourhood record (bit patterns copied): binary16 the
@@ -255,8 +273,8 @@ __global__ void records_u8_kernel(const void* __restrict__ data, const float2* _
     const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
     const int x1 = min(x + 1, n - 1);
     float* r = out + static_cast<size_t>(brick_addr(x, y, z, nb)) * 2;
-    r[0] = stored<kU8>(data, par, brick_addr(x, y, z, nb));
-    r[1] = stored<kU8>(data, par, brick_addr(x1, y, z, nb));
+    r[0] = stored<kU8>(data, par, x, y, z, nb);
+    r[1] = stored<kU8>(data, par, x1, y, z, nb);
 }
 
 template <int S>
@@ -265,10 +283,9 @@ __global__ void voxel_mask_kernel(MaskArgs a) {
     const uint32_t total = static_cast<uint32_t>(a.n) * a.n * a.n;
     if (o >= total) return;
     const int x = o % a.n, y = (o / a.n) % a.n, z = o / (static_cast<uint32_t>(a.n) * a.n);
-    const uint32_t addr = brick_addr(x, y, z, a.nb);
     bool keep = true;
     for (int f = 0; f < a.n_active; ++f) {
-        const float v = stored<S>(a.field[f], a.u8par[f], addr, a.descale[f]);
+        const float v = stored<S>(a.field[f], a.u8par[f], x, y, z, a.nb, a.descale[f]);
         keep = keep && (v >= a.lo[f]) && (v <= a.hi[f]);
     }
     if (a.coord_mask)
@@ -292,19 +309,18 @@ __global__ __launch_bounds__(256) void pc_lines_kernel(PcArgs a) {
         const bool valid = c < total;
         const int x = static_cast<int>(c % a.n), y = static_cast<int>((c / a.n) % a.n);
         const int z = static_cast<int>(c / (static_cast<uint32_t>(a.n) * a.n));
-        const uint32_t addr = valid ? brick_addr(x, y, z, a.nb) : 0u;
         bool pass = valid;
         if (valid && a.coord_mask)
             pass = coord_ok(a.coord_mask, a.clo, a.chi, cell_coord(x, a.n), cell_coord(y, a.n), cell_coord(z, a.n));
         for (int f = 0; f < a.n_fields; ++f) {
-            const float v = valid ? stored<S>(a.field[f], a.u8par[f], addr, a.descale[f]) : NAN;
+            const float v = valid ? stored<S>(a.field[f], a.u8par[f], x, y, z, a.nb, a.descale[f]) : NAN;
             if (a.values != nullptr) a.values[static_cast<size_t>(line) * a.n_fields + f] = v;
             if (a.active[f]) pass = pass && (v >= a.lo[f]) && (v <= a.hi[f]);
         }
         if (a.passes != nullptr) a.passes[line] = pass ? 1 : 0;
         if (a.hist != nullptr && valid) {
             for (int f = 0; f < a.n_fields; ++f) {
-                const float v = stored<S>(a.field[f], a.u8par[f], addr, a.descale[f]);
+                const float v = stored<S>(a.field[f], a.u8par[f], x, y, z, a.nb, a.descale[f]);
                 const float t = __fmul_rn(__fsub_rn(v, a.axis_lo[f]), a.inv[f]);
                 const float xb = fminf(fmaxf(__fmul_rn(t, static_cast<float>(a.n_bins)), 0.0f),
                                        static_cast<float>(a.n_bins - 1));
@@ -485,7 +501,10 @@ hipError_t launch_encode(const float* in, int n, int storage, void* out, float2*
     switch (storage) {
         case kF32: hipLaunchKernelGGL(encode_kernel<kF32>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, nullptr); break;
         case kF16: hipLaunchKernelGGL(encode_kernel<kF16>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, f16_scale); break;
-        default: hipLaunchKernelGGL(encode_kernel<kU8>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, nullptr); break;
+        default:
+            hipLaunchKernelGGL(encode_kernel<kU8>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, nullptr);
+            hipLaunchKernelGGL(u8_apron_kernel, dim3(nbr), dim3(192), 0, s, static_cast<uint8_t*>(out), n);
+            break;
     }
     return hipGetLastError();
 }

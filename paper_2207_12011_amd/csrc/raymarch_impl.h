@@ -67,19 +67,15 @@ __device__ __forceinline__ Source<S> source(const RenderArgs& A, int k) {
     return src;
 }
 
-// Stored value at byte offset `ob`.
+// Stored value at byte offset `ob` (float32 and binary16 compact layouts).
 template <int S>
 __device__ __forceinline__ float corner(const Source<S>& src, uint32_t ob) {
+    static_assert(S != kU8, "8-bit codes are read by rows (fetch)");
     if constexpr (S == kF32) {
         return global_ptr<float>(reinterpret_cast<const char*>(src.base) + ob)[0];
-    } else if constexpr (S == kF16) {
+    } else {
         const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(src.rsrc, static_cast<int>(ob), 0, 0);
         return __half2float(__ushort_as_half(h));
-    } else {
-        const float q = static_cast<float>(__builtin_amdgcn_raw_buffer_load_b8(src.rsrc, static_cast<int>(ob), 0, 0));
-        const uint32_t pb = (ob >> 9) * 8u;
-        const auto so = __builtin_amdgcn_raw_buffer_load_b64(src.par, static_cast<int>(pb), 0, 0);  // (scale, offset)
-        return __fadd_rn(__fmul_rn(__uint_as_float(so[0]), q), __uint_as_float(so[1]));
     }
 }
 
@@ -110,28 +106,34 @@ __device__ __forceinline__ float blend(const Tri& t, float c0, float c1, float c
     return fmaf(t.w[7], c7, v);
 }
 
-// Trilinear value from the 8 stored corners at byte offsets o[].  8-bit codes: each corner is decoded
-// with the (scale, offset) pair of its own brick.  The corners of one x row (y, z fixed) lie in the
-// brick of the row's first corner or, when the cell straddles a brick face in x, in the next brick,
-// whose pair is stored right after: one 16-byte load per row brings both pairs, and the second corner
-// takes the second pair only where its brick differs.  Four such loads per field, issued without a
-// branch, cost less than one pair load plus a pair load per straddling corner in a branch each
-// (headline frame 2.16 -> 1.79 ms): a wave nearly always holds some cell on a brick face, so every
-// branch ran, and its loads waited at the branch's end.  The second pair of the last brick lies beyond
-// the pair array; the range check returns zero there, and no corner takes it (the upper corner clamps
-// onto the grid's last voxel).
+// Trilinear value from the 8 stored corners.  float32 and binary16: o[] holds the corners' byte
+// offsets.  8-bit codes (the 9 x 9 x 8 brick blocks of u8_addr): o[0] and o[1] are the byte offsets of
+// the cell's base voxel (x0, y0) in the z0 and z1 planes, each the start of one 12-byte load whose bytes
+// 0, 1, 9 and 10 are the plane's four corners; o[2..5] the bricks of the corners (x0, y, z) of the rows
+// (y, z) = (y0, z0), (y1, z0), (y0, z1), (y1, z1); o[6] is nonzero where x1 lies in the next brick.
+// Each corner is decoded with the (scale, offset) pair of its own brick: one 16-byte load per row
+// brings the pairs of the row's brick and of the next brick in x, stored side by side, and the row's
+// x1 corner takes the second pair where it lies in that brick.  Without a branch, a field costs two
+// code loads and four pair loads (one byte and one pair load per corner, with a pair load per
+// straddling corner in a branch each, took 2.16 ms for the headline frame; rows of pairs with byte
+// loads 1.80 ms).  The second pair of the last brick lies beyond the pair array: a zero pair is
+// stored there, and no corner takes it (the upper corner clamps onto the grid's last voxel).
 template <int S>
 __device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)[8], const Tri& t) {
     if constexpr (S == kU8) {
+        typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+        const u32x3 p0 = __builtin_amdgcn_raw_buffer_load_b96(src.rsrc, static_cast<int>(o[0]), 0, 0);
+        const u32x3 p1 = __builtin_amdgcn_raw_buffer_load_b96(src.rsrc, static_cast<int>(o[1]), 0, 0);
+        // codes of the corners (bit 0 = x, bit 1 = y, bit 2 = z): bytes 0 and 1 of the first word, 1 and
+        // 2 of the third (plane bytes 9 and 10)
+        const uint32_t code[8] = {p0.x, p0.x >> 8, p0.z >> 8, p0.z >> 16, p1.x, p1.x >> 8, p1.z >> 8, p1.z >> 16};
+        const bool next = o[6] != 0;
         float c[8];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const uint32_t br = o[2 * r] >> 9;   // the row's first corner's brick
-            const u32x4 pr = __builtin_amdgcn_raw_buffer_load_b128(src.par, static_cast<int>(br * 8u), 0, 0);
-            const bool next = (o[2 * r + 1] >> 9) != br;
-            const float q0 = static_cast<float>(__builtin_amdgcn_raw_buffer_load_b8(src.rsrc, static_cast<int>(o[2 * r]), 0, 0));
-            const float q1 =
-                static_cast<float>(__builtin_amdgcn_raw_buffer_load_b8(src.rsrc, static_cast<int>(o[2 * r + 1]), 0, 0));
+            const u32x4 pr = __builtin_amdgcn_raw_buffer_load_b128(src.par, static_cast<int>(o[2 + r] * 8u), 0, 0);
+            const float q0 = static_cast<float>(code[2 * r] & 0xFFu);
+            const float q1 = static_cast<float>(code[2 * r + 1] & 0xFFu);
             c[2 * r] = __fadd_rn(__fmul_rn(__uint_as_float(pr.x), q0), __uint_as_float(pr.y));
             c[2 * r + 1] =
                 __fadd_rn(__fmul_rn(__uint_as_float(next ? pr.z : pr.x), q1), __uint_as_float(next ? pr.w : pr.y));
@@ -579,6 +581,21 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                         r10[q] = r00[q] + dyv;
                         r11[q] = r01[q] + dyv;
                     }
+                } else if constexpr (S == kU8) {
+                    // the slots of fetch() for 8-bit codes
+                    const int ix = static_cast<int>(flx[q]), iy = static_cast<int>(fly[q]), iz = static_cast<int>(flz[q]);
+                    const int x1 = min(ix + 1, n - 1), y1 = min(iy + 1, n - 1), z1 = min(iz + 1, n - 1);
+                    const uint32_t dyb = (y1 >> 3) != (y0[q] >> 3) ? nbu : 0u;
+                    const uint32_t dzb = (z1 >> 3) != (z0[q] >> 3) ? nbu * nbu : 0u;
+                    const uint32_t in_xy = static_cast<uint32_t>(y0[q] & 7) * 9u + static_cast<uint32_t>(x0[q] & 7);
+                    o[q][0] = raypc_mul_u24(brick[q], kU8BrickBytes) + static_cast<uint32_t>(z0[q] & 7) * 81u + in_xy;
+                    o[q][1] = raypc_mul_u24(brick[q] + dzb, kU8BrickBytes) + static_cast<uint32_t>(z1 & 7) * 81u + in_xy;
+                    o[q][2] = brick[q];
+                    o[q][3] = brick[q] + dyb;
+                    o[q][4] = brick[q] + dzb;
+                    o[q][5] = brick[q] + dyb + dzb;
+                    o[q][6] = (x1 >> 3) != (x0[q] >> 3) ? 1u : 0u;
+                    o[q][7] = 0;
                 } else {
                     constexpr int LB = kLogBytes<S>;
                     const int ix = static_cast<int>(flx[q]), iy = static_cast<int>(fly[q]), iz = static_cast<int>(flz[q]);
