@@ -231,6 +231,39 @@ def test_records_equal_compact_layout(rp, ctx, small5, c0, base):
         rp.unload(ctx, cmp_)
 
 
+def test_u8_blocks_at_the_grid_faces(rp, ctx, small5):
+    """8-bit code blocks at the grid's faces: with the shell touching the cube (r_outer = 1), samples
+    next to each face centre have base voxels on the last (or first) voxel plane, where the upper
+    corner clamps onto the base voxel and the block reads its copied codes.  The compact layout equals
+    the 8-bit records (decoded pairs gathered from the codes themselves) bit for bit there, on every
+    level, with all five fields fetched (an all-inclusive brush)."""
+    wl = small5
+    nf = wl.n_fields
+    vids = {}
+    for st in ("u8", "u8c"):
+        print(f"[case] u8 blocks at the faces {st}", flush=True)
+        vid = rp.load_fields(ctx, torch.from_numpy(wl.fields).cuda(), st, 3, 0.0, 1.0)
+        rp.set_brush(ctx, vid, np.ones(nf, np.uint8), np.full(nf, -np.inf, np.float32),
+                     np.full(nf, np.inf, np.float32))
+        vids[st] = vid
+    rp.set_transfer_function(ctx, 0, wl.tf.field, wl.tf.vmin, wl.tf.vmax, wl.tf.rgba, wl.tf.ref_step)
+    rp.set_options(ctx, wl.ert)
+    ups = {0: (0, 0, 1), 1: (0, 0, 1), 2: (0, 1, 0)}
+    for axis in range(3):
+        for sign in (1.0, -1.0):
+            eye = [0.0, 0.0, 0.0]
+            eye[axis] = 3.0 * sign
+            cam = np.array(eye + [0, 0, 0] + list(ups[axis]) + [12], np.float32)
+            for lod in range(3):
+                a = gpu_render(rp, ctx, vids["u8"], wl, lod, 0.5, camera=cam, width=48, height=40)
+                b = gpu_render(rp, ctx, vids["u8c"], wl, lod, 0.5, camera=cam, width=48, height=40)
+                assert a[0][..., 3].max() > 0.0, (axis, sign, lod)
+                for x, y in zip(a, b):
+                    assert np.array_equal(x, y), (axis, sign, lod)
+    for vid in vids.values():
+        rp.unload(ctx, vid)
+
+
 def test_inclusive_brush_equals_none_and_empty_is_background(rp, ctx, small5):
     wl = small5
     vid = load(rp, ctx, wl, "f16")
