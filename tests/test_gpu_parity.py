@@ -544,6 +544,13 @@ def test_precision_512_full_size_sampled(rp, ctx, c2):
         check_depth(cpu(dep).reshape(-1)[pix], ref, label=f"c2 {storage} depth", min_frac=0.02,
                     gpu_rgba=rgba.reshape(-1, 4)[pix])
         rp.unload(ctx, vid)
+        # the compact layout's timed kernel (8-bit: the code blocks) gives the records' image bit for bit
+        print(f"[case] 512^3 x 5, 1920x1080, {storage} compact", flush=True)
+        vid = rp.load_fields(ctx, fields_dev, storage + "c", 3, wl.r_inner, wl.r_outer)
+        rp.set_brush(ctx, vid, wl.brush.active, wl.brush.lo, wl.brush.hi)
+        plain = cpu(rp.render(ctx, vid, wl.camera.as_array(), wl.width, wl.height, 0, wl.step))
+        assert np.array_equal(plain.view(np.uint32), rgba.view(np.uint32)), storage + "c"
+        rp.unload(ctx, vid)
 
 
 def test_served_requests_match_oracle(rp, ctx, c2):
