@@ -430,7 +430,9 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
     a.n = L.n;
     a.nb = L.nb;
     {
-        const uint64_t fb = v->storage == kU8 ? u8_field_bytes(L.nb) : static_cast<uint64_t>(L.n) * L.n * L.n * storage_bytes(v->storage);
+        const uint64_t fb = v->storage == kU8    ? u8_field_bytes(L.nb)
+                            : v->storage == kF16 ? f16_field_bytes(L.nb)
+                                                 : static_cast<uint64_t>(L.n) * L.n * L.n * storage_bytes(v->storage);
         a.field_bytes = fb > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(fb);
         a.par_bytes = static_cast<uint32_t>((L.n_bricks() + 1) * sizeof(float2));   // with the zero pair after the last brick
         const uint64_t rb = static_cast<uint64_t>(L.n) * L.n * L.n * 8u;
@@ -626,7 +628,8 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
             L.nb = L.n / kBrick;
             const size_t lvox = static_cast<size_t>(L.n) * L.n * L.n;
             for (int f = 0; f < n_fields && !rc; ++f) {
-                rc = dev_alloc(v, &L.data[f], storage == kU8 ? u8_field_bytes(L.nb) : lvox * storage_bytes(storage));
+                rc = dev_alloc(v, &L.data[f], storage == kU8 ? u8_field_bytes(L.nb)
+                                              : (storage == kF16 ? f16_field_bytes(L.nb) : lvox * storage_bytes(storage)));
                 // one pair more than the bricks, left zero: the ray march reads each brick's pair together
                 // with the next one, the last brick's included
                 if (!rc && storage == kU8) rc = dev_alloc(v, reinterpret_cast<void**>(&L.par[f]), (L.n_bricks() + 1) * sizeof(float2));
@@ -690,6 +693,11 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 if (storage == kU8 && ((e = hipMemsetAsync(L.par[f] + L.n_bricks(), 0, sizeof(float2), s)) != hipSuccess ||
                                        (e = hipMemsetAsync(static_cast<uint8_t*>(L.data[f]) + u8_field_bytes(L.nb) - 16, 0, 16, s)) != hipSuccess)) {
                     rc = hip_fail(e, "8-bit padding");
+                    break;
+                }
+                if (storage == kF16 &&
+                    (e = hipMemsetAsync(static_cast<uint8_t*>(L.data[f]) + f16_field_bytes(L.nb) - 16, 0, 16, s)) != hipSuccess) {
+                    rc = hip_fail(e, "binary16 padding");
                     break;
                 }
                 if ((e = launch_encode(cur, L.n, storage, L.data[f], L.par[f], f16_scale, s)) != hipSuccess) { rc = hip_fail(e, "encode"); break; }

@@ -72,6 +72,21 @@ __host__ __device__ inline size_t u8_field_bytes(int nb) {
     return static_cast<size_t>(nb) * nb * nb * kU8BrickBytes + 16;
 }
 
+// binary16 values use a layout of their own too: each 8^3 brick is a 9 x 8 x 8 block of values,
+// [z][y][x] (576 values, 1152 bytes), holding its 512 values and, at local x = 8, a copy of the value
+// one voxel beyond its upper x face (the next brick's first voxel; at the grid's upper x face the last
+// voxel again).  The two corners of a cell's row (x0 and x0 + 1 at one y and z) are then adjacent,
+// one 4-byte load.
+constexpr uint32_t kF16BrickValues = 576;
+__host__ __device__ inline uint32_t f16_index(int x, int y, int z, int nb) {
+    return brick_index(x, y, z, nb) * kF16BrickValues + static_cast<uint32_t>(z & 7) * 72u +
+           static_cast<uint32_t>(y & 7) * 9u + static_cast<uint32_t>(x & 7);
+}
+// Bytes of one field's binary16 array on a level: the bricks plus 16 bytes of padding.
+__host__ __device__ inline size_t f16_field_bytes(int nb) {
+    return static_cast<size_t>(nb) * nb * nb * kF16BrickValues * 2 + 16;
+}
+
 // Coordinate axes of a brush at a position (x, y, z world units): bit a of mask enables axis a
 // (x, y, z, radius) with inclusive bounds [clo[a], chi[a]]; the radius is tested on float32
 // squares, r^2 = fl32(fl32(fl32(x x) + fl32(y y)) + fl32(z z)) against clo[3] <= r^2 <= chi[3].

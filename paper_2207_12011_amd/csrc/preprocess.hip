@@ -38,7 +38,7 @@ __device__ __forceinline__ float stored(const void* base, const float2* par, int
     if constexpr (S == kF32) {
         return static_cast<const float*>(base)[brick_addr(x, y, z, nb)];
     } else if constexpr (S == kF16) {
-        return __half2float(static_cast<const __half*>(base)[brick_addr(x, y, z, nb)]) * descale;
+        return __half2float(static_cast<const __half*>(base)[f16_index(x, y, z, nb)]) * descale;
     } else {
         const float q = static_cast<float>(static_cast<const uint8_t*>(base)[u8_addr(x, y, z, nb)]);
         const float2 p = par[brick_index(x, y, z, nb)];
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ i
         const uint32_t a = (brick << 9) | brick_local(t & 7, (t >> 3) & 7, t >> 6);
         static_cast<float*>(out)[a] = v;
     } else if constexpr (S == kF16) {
-        const uint32_t a = (brick << 9) | brick_local(t & 7, (t >> 3) & 7, t >> 6);
+        const uint32_t a = brick * kF16BrickValues + (t >> 6) * 72u + ((t >> 3) & 7) * 9u + (t & 7);
         // scaling by a power of two is exact: only the binary16 rounding remains
         static_cast<__half*>(out)[a] = __float2half_rn(v * (f16_scale ? f16_scale[0] : 1.0f));
     } else {
@@ -165,6 +165,18 @@ __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ i
             static_cast<uint8_t>(q);
         if (t == 0) u8par[brick] = make_float2(scale, mn);
     }
+}
+
+// binary16 values: the copies at local x = 8 of every brick (64 per brick), taken from the voxels
+// they copy once every brick is encoded.
+__global__ __launch_bounds__(64) void f16_apron_kernel(uint16_t* __restrict__ values, int n) {
+    const int nb = n >> 3;
+    const uint32_t brick = blockIdx.x;
+    const int k = threadIdx.x;
+    const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
+    const int ly = k & 7, lz = k >> 3;
+    const int x = min(bx * 8 + 8, n - 1), y = by * 8 + ly, z = bz * 8 + lz;
+    values[brick * kF16BrickValues + lz * 72u + ly * 9u + 8u] = values[f16_index(x, y, z, nb)];
 }
 
 // 8-bit codes: the copies at local x = 8 and y = 8 of every brick (136 per brick: 9 at y = 8 and 8 at
@@ -253,12 +265,14 @@ __global__ void records_kernel(const T* __restrict__ data, int n, T* __restrict_
     const int nb = n >> 3;
     const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
     const int x1 = min(x + 1, n - 1), y1 = min(y + 1, n - 1);
+    // the source array: float32 at brick_addr, binary16 in its 9 x 8 x 8 blocks (f16_index)
+    auto at = [&](int xx, int yy) { return kValues == 4 ? f16_index(xx, yy, z, nb) : brick_addr(xx, yy, z, nb); };
     T* r = out + static_cast<size_t>(brick_addr(x, y, z, nb)) * kValues;
-    r[0] = data[brick_addr(x, y, z, nb)];
-    r[1] = data[brick_addr(x1, y, z, nb)];
+    r[0] = data[at(x, y)];
+    r[1] = data[at(x1, y)];
     if constexpr (kValues == 4) {
-        r[2] = data[brick_addr(x, y1, z, nb)];
-        r[3] = data[brick_addr(x1, y1, z, nb)];
+        r[2] = data[at(x, y1)];
+        r[3] = data[at(x1, y1)];
     }
 }
 
@@ -500,7 +514,10 @@ hipError_t launch_encode(const float* in, int n, int storage, void* out, float2*
     const unsigned nbr = static_cast<unsigned>((n / 8) * (n / 8) * (n / 8));
     switch (storage) {
         case kF32: hipLaunchKernelGGL(encode_kernel<kF32>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, nullptr); break;
-        case kF16: hipLaunchKernelGGL(encode_kernel<kF16>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, f16_scale); break;
+        case kF16:
+            hipLaunchKernelGGL(encode_kernel<kF16>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, f16_scale);
+            hipLaunchKernelGGL(f16_apron_kernel, dim3(nbr), dim3(64), 0, s, static_cast<uint16_t*>(out), n);
+            break;
         default:
             hipLaunchKernelGGL(encode_kernel<kU8>, dim3(nbr), dim3(512), 0, s, in, n, out, u8par, nullptr);
             hipLaunchKernelGGL(u8_apron_kernel, dim3(nbr), dim3(192), 0, s, static_cast<uint8_t*>(out), n);

@@ -108,16 +108,11 @@ __device__ __forceinline__ Source<S> source(const RenderArgs& A, int k) {
     return src;
 }
 
-// Stored value at byte offset `ob` (float32 and binary16 compact layouts).
+// Stored float32 value at byte offset `ob` (the other storages are read by rows, see fetch).
 template <int S>
 __device__ __forceinline__ float corner(const Source<S>& src, uint32_t ob) {
-    static_assert(S != kU8, "8-bit codes are read by rows (fetch)");
-    if constexpr (S == kF32) {
-        return global_ptr<float>(reinterpret_cast<const char*>(src.base) + ob)[0];
-    } else {
-        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(src.rsrc, static_cast<int>(ob), 0, 0);
-        return __half2float(__ushort_as_half(h));
-    }
+    static_assert(S == kF32, "binary16 and 8-bit values are read by rows (fetch)");
+    return global_ptr<float>(reinterpret_cast<const char*>(src.base) + ob)[0];
 }
 
 // Trilinear interpolation written as a weighted sum of the eight corners (index bit 0 = x, bit 1 = y,
@@ -147,8 +142,11 @@ __device__ __forceinline__ float blend(const Tri& t, float c0, float c1, float c
     return fmaf(t.w[7], c7, v);
 }
 
-// Trilinear value from the 8 stored corners.  float32 and binary16: o[] holds the corners' byte
-// offsets.  8-bit codes (the 9 x 9 x 8 brick blocks of u8_addr): o[0] and o[1] are the byte offsets of
+// Trilinear value from the 8 stored corners.  float32: o[] holds the corners' byte offsets.
+// binary16 (the 9 x 8 x 8 blocks of f16_index): o[0..3] are the byte offsets of the corners (x0, y, z)
+// of the rows (y, z) = (y0, z0), (y1, z0), (y0, z1), (y1, z1), each the start of one 4-byte load of the
+// row's two values (eight 2-byte loads took 1.24 ms for the headline frame, four row loads 0.85 ms).
+// 8-bit codes (the 9 x 9 x 8 brick blocks of u8_addr): o[0] and o[1] are the byte offsets of
 // the cell's base voxel (x0, y0) in the z0 and z1 planes, each the start of one 12-byte load whose bytes
 // 0, 1, 9 and 10 are the plane's four corners; o[2..5] the bricks of the corners (x0, y, z) of the rows
 // (y, z) = (y0, z0), (y1, z0), (y0, z1), (y1, z1); o[6] is nonzero where x1 lies in the next brick.
@@ -178,6 +176,15 @@ __device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)
             c[2 * r] = __fadd_rn(__fmul_rn(__uint_as_float(pr.x), q0), __uint_as_float(pr.y));
             c[2 * r + 1] =
                 __fadd_rn(__fmul_rn(__uint_as_float(next ? pr.z : pr.x), q1), __uint_as_float(next ? pr.w : pr.y));
+        }
+        return blend(t, c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7]);
+    } else if constexpr (S == kF16) {
+        float c[8];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(src.rsrc, static_cast<int>(o[r]), 0, 0);
+            c[2 * r] = __half2float(__ushort_as_half(static_cast<unsigned short>(w & 0xFFFFu)));
+            c[2 * r + 1] = __half2float(__ushort_as_half(static_cast<unsigned short>(w >> 16)));
         }
         return blend(t, c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7]);
     } else {
@@ -480,6 +487,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
         A.skip != nullptr ? static_cast<int>(nbu * nbu * nbu * 2u) : 0, kRawBufferFlags);
     // record-number steps to the next voxel in y and z from the last voxel of a brick (see below)
     const uint32_t y_brick_step = nbu * 512u - 140u, z_brick_step = nbu * nbu * 512u - 304u;
+    // binary16 blocks: from a row at local y = 7 (z = 7) to the row at local 0 of the next brick
+    const uint32_t f16_y_brick_step = nbu * kF16BrickValues - 63u, f16_z_brick_step = nbu * nbu * kF16BrickValues - 504u;
     const float top = static_cast<float>(n - 1);  // largest voxel index
     const float hn = A.half_n;
     const float uox = fmaf(ox, hn, hn - 0.5f), uoy = fmaf(oy, hn, hn - 0.5f), uoz = fmaf(oz, hn, hn - 0.5f);
@@ -622,6 +631,22 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                         r10[q] = r00[q] + dyv;
                         r11[q] = r01[q] + dyv;
                     }
+                } else if constexpr (S == kF16) {
+                    // the slots of fetch() for binary16 values: byte offsets of the four rows at x0.  The
+                    // row one up in y (z) is 9 (72) values on inside a brick, in the next brick beyond
+                    // its face, and the same row where the upper corner clamps onto the grid's face.
+                    const int iy = static_cast<int>(fly[q]), iz = static_cast<int>(flz[q]);
+                    const int y1 = min(iy + 1, n - 1), z1 = min(iz + 1, n - 1);
+                    const uint32_t dyv = y1 == y0[q] ? 0u : ((y0[q] & 7) != 7 ? 9u : f16_y_brick_step);
+                    const uint32_t dzv = z1 == z0[q] ? 0u : ((z0[q] & 7) != 7 ? 72u : f16_z_brick_step);
+                    const uint32_t base = raypc_mul_u24(brick[q], kF16BrickValues) +
+                                          static_cast<uint32_t>(z0[q] & 7) * 72u +
+                                          static_cast<uint32_t>(y0[q] & 7) * 9u + static_cast<uint32_t>(x0[q] & 7);
+                    o[q][0] = base * 2u;
+                    o[q][1] = (base + dyv) * 2u;
+                    o[q][2] = (base + dzv) * 2u;
+                    o[q][3] = (base + dyv + dzv) * 2u;
+                    o[q][4] = o[q][5] = o[q][6] = o[q][7] = 0;
                 } else if constexpr (S == kU8) {
                     // the slots of fetch() for 8-bit codes
                     const int ix = static_cast<int>(flx[q]), iy = static_cast<int>(fly[q]), iz = static_cast<int>(flz[q]);

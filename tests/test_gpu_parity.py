@@ -231,17 +231,18 @@ def test_records_equal_compact_layout(rp, ctx, small5, c0, base):
         rp.unload(ctx, cmp_)
 
 
-def test_u8_blocks_at_the_grid_faces(rp, ctx, small5):
-    """8-bit code blocks at the grid's faces: with the shell touching the cube (r_outer = 1), samples
-    next to each face centre have base voxels on the last (or first) voxel plane, where the upper
-    corner clamps onto the base voxel and the block reads its copied codes.  The compact layout equals
-    the 8-bit records (decoded pairs gathered from the codes themselves) bit for bit there, on every
-    level, with all five fields fetched (an all-inclusive brush)."""
+@pytest.mark.parametrize("base", ["u8", "f16"])
+def test_blocks_at_the_grid_faces(rp, ctx, small5, base):
+    """The 8-bit and binary16 blocks at the grid's faces: with the shell touching the cube (r_outer =
+    1), samples next to each face centre have base voxels on the last (or first) voxel plane, where
+    the upper corner clamps onto the base voxel and the block reads its copied values.  The compact
+    layout equals the records (gathered from the stored values themselves) bit for bit there, on
+    every level, with all five fields fetched (an all-inclusive brush)."""
     wl = small5
     nf = wl.n_fields
     vids = {}
-    for st in ("u8", "u8c"):
-        print(f"[case] u8 blocks at the faces {st}", flush=True)
+    for st in (base, base + "c"):
+        print(f"[case] blocks at the faces {st}", flush=True)
         vid = rp.load_fields(ctx, torch.from_numpy(wl.fields).cuda(), st, 3, 0.0, 1.0)
         rp.set_brush(ctx, vid, np.ones(nf, np.uint8), np.full(nf, -np.inf, np.float32),
                      np.full(nf, np.inf, np.float32))
@@ -255,8 +256,8 @@ def test_u8_blocks_at_the_grid_faces(rp, ctx, small5):
             eye[axis] = 3.0 * sign
             cam = np.array(eye + [0, 0, 0] + list(ups[axis]) + [12], np.float32)
             for lod in range(3):
-                a = gpu_render(rp, ctx, vids["u8"], wl, lod, 0.5, camera=cam, width=48, height=40)
-                b = gpu_render(rp, ctx, vids["u8c"], wl, lod, 0.5, camera=cam, width=48, height=40)
+                a = gpu_render(rp, ctx, vids[base], wl, lod, 0.5, camera=cam, width=48, height=40)
+                b = gpu_render(rp, ctx, vids[base + "c"], wl, lod, 0.5, camera=cam, width=48, height=40)
                 assert a[0][..., 3].max() > 0.0, (axis, sign, lod)
                 for x, y in zip(a, b):
                     assert np.array_equal(x, y), (axis, sign, lod)
