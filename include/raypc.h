@@ -51,7 +51,9 @@ enum {
 
 enum {
     RAYPC_STORAGE_F32 = 0,      /* 4 bytes per value */
-    RAYPC_STORAGE_F16 = 1,      /* IEEE binary16, round to nearest even, subnormals kept */
+    RAYPC_STORAGE_F16 = 1,      /* IEEE binary16, round to nearest even, subnormals kept; a brick's
+                                 * values are held with copies of the next brick's first x voxels
+                                 * (2.25 bytes per voxel) */
     RAYPC_STORAGE_U8_BRICK = 2, /* 8-bit codes with a (scale, offset) pair per 8^3 brick; the codes
                                  * of a brick are held with copies of the next bricks' first x and
                                  * y voxels (1.27 bytes per voxel) */
@@ -59,7 +61,7 @@ enum {
      * keeps, per voxel, an 8-byte record of neighbouring stored values (binary16: the 2x2 values
      * at (x..x+1, y..y+1, z); float32 and 8-bit: the pair of float32 (decoded) values at
      * (x..x+1, y, z)), so that a sample's trilinear fetch takes 2 (binary16) or 4 loads instead
-     * of 8 (float32, binary16) or 2 code loads and 4 (scale, offset) loads (8-bit).  Records cost
+     * of 8 (float32), 4 (binary16) or 2 code loads and 4 (scale, offset) loads (8-bit).  Records cost
      * 8 bytes per voxel and field besides the compact data; both layouts hold the same values and
      * render identically. */
     RAYPC_STORAGE_COMPACT = 0x100
