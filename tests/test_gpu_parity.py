@@ -621,7 +621,8 @@ def test_large_progressive_1024_4k_sampled(rp, ctx, capsys):
     record fields above 4 GiB, read at 64-bit offsets), a 3840x2160 view, progressive passes at step
     1.0 / 0.5 / 0.25 voxel for the final (~10 %) brush and for a brush half-way along the narrowing
     sequence; the first and final passes checked against the oracle on 1 000 sampled pixels, with
-    exact counts where the counting variant is asked."""
+    exact counts where the counting variant is asked; the final pass served, and rendered from the
+    compact binary16 blocks, equal to it bit for bit."""
     import time
     t0 = time.perf_counter()
 
@@ -670,6 +671,16 @@ def test_large_progressive_1024_4k_sampled(rp, ctx, capsys):
             rp.server_stop(ctx)
         say("served the final pass")
         assert np.array_equal(cpu(out).view(np.uint32), passes[2].view(np.uint32))
+        # the compact binary16 blocks (2.4 GB per field at level 0, byte offsets beyond 2^31) give
+        # the final pass of the records bit for bit
+        cvid = rp.load_fields(ctx, torch.from_numpy(wl.fields).cuda(), "f16c", 3, wl.r_inner, wl.r_outer)
+        try:
+            rp.set_brush(ctx, cvid, b.active, b.lo, b.hi)
+            plain = cpu(rp.render(ctx, cvid, cam, wl.width, wl.height, 0, wl.step))
+            say("compact binary16 final pass")
+            assert np.array_equal(plain.view(np.uint32), passes[2].view(np.uint32))
+        finally:
+            rp.unload(ctx, cvid)
     finally:
         rp.unload(ctx, vid)
 
