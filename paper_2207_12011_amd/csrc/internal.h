@@ -22,12 +22,12 @@ enum Kind : int {
     kKindF32 = 0, kKindF16 = 1, kKindU8 = 2, kKindF32Rec = 3, kKindF16Rec = 4, kKindU8Rec = 5, kKinds = 6
 };
 
-// Brick-ordered address of voxel (x, y, z) on a level with nb bricks per axis:
-// bricks in [bz][by][bx] order, 512 voxels each.  Inside a brick the voxels
-// form eight 4^3 sub-bricks (x, y, z half-index in bits 6, 7, 8), each stored
-// [z][y][x]; with binary16 storage one 128-byte cache line is one 4x4x4 block,
-// so a compact cluster of samples touches few lines whatever the view direction.
-// The address is a sum of independent per-axis parts (see axis_x/y/z).
+// Brick-ordered number of voxel (x, y, z) on a level with nb bricks per axis: bricks in [bz][by][bx]
+// order, 512 voxels each.  Inside a brick the voxels form eight 4^3 sub-bricks (x, y, z half-index in
+// bits 6, 7, 8), each [z][y][x], so a compact cluster of samples touches few cache lines whatever the
+// view direction.  The number is a sum of independent per-axis parts (see axis_x/y/z).  It places the
+// float32 compact values and the neighbourhood records of every storage; binary16 and 8-bit compact
+// values are held in blocks of their own (f16_index, u8_addr).
 __host__ __device__ inline uint32_t axis_x(int x) {
     return (static_cast<uint32_t>(x >> 3) << 9) | (static_cast<uint32_t>((x >> 2) & 1) << 6) |
            static_cast<uint32_t>(x & 3);

@@ -28,8 +28,8 @@
 // samples of it at once (binary16 records: two such groups per step, each lane
 // taking samples j and j + 4, their loads issued together); a wave64 covers a
 // 4 x 4 pixel tile, so the samples it fetches per step form a compact cluster
-// of a few voxels on a side, which the brick layout (4^3 sub-bricks per cache
-// line for binary16) serves from a handful of cache lines.  Each group of four
+// of a few voxels on a side, which the brick-ordered layouts serve from a
+// handful of cache lines.  Each group of four
 // is merged in order with DPP quad broadcasts: every lane replays the four sequential
 // front-to-back updates, stopping at the first sample whose accumulated
 // opacity reaches the threshold, so the result is bit for bit the sequential
