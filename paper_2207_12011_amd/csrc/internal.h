@@ -86,6 +86,10 @@ __host__ __device__ inline uint32_t f16_index(int x, int y, int z, int nb) {
 __host__ __device__ inline size_t f16_field_bytes(int nb) {
     return static_cast<size_t>(nb) * nb * nb * kF16BrickValues * 2 + 16;
 }
+// Bytes of one field's binary16 records (pair blocks: 4 bytes per entry of the same numbering).
+__host__ __device__ inline size_t f16_pair_bytes(int nb) {
+    return static_cast<size_t>(nb) * nb * nb * kF16BrickValues * 4 + 16;
+}
 
 // Coordinate axes of a brush at a position (x, y, z world units): bit a of mask enables axis a
 // (x, y, z, radius) with inclusive bounds [clo[a], chi[a]]; the radius is tested on float32

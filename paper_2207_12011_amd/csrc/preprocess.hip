@@ -254,26 +254,36 @@ __global__ void decode_kernel(const void* __restrict__ data, const float2* __res
     out[o] = stored<S>(data, par, x, y, z, n >> 3, descale);
 }
 
-// One thread per voxel: gather its 8-byte neighbourhood record (bit patterns copied): binary16 the
-// 2x2 values at (x..x+1, y..y+1, z), float32 the pair at (x..x+1, y, z), clamped to N-1.
-template <typename T>
-__global__ void records_kernel(const T* __restrict__ data, int n, T* __restrict__ out) {
-    constexpr int kValues = 8 / sizeof(T);
+// float32 records: one thread per voxel, the pair at (x..x+1, y, z) (x + 1 clamped to N-1, bit
+// patterns copied) at the voxel's brick-ordered number.
+__global__ void records_kernel(const uint32_t* __restrict__ data, int n, uint32_t* __restrict__ out) {
     const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t total = static_cast<uint32_t>(n) * n * n;
     if (o >= total) return;
     const int nb = n >> 3;
     const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
-    const int x1 = min(x + 1, n - 1), y1 = min(y + 1, n - 1);
-    // the source array: float32 at brick_addr, binary16 in its 9 x 8 x 8 blocks (f16_index)
-    auto at = [&](int xx, int yy) { return kValues == 4 ? f16_index(xx, yy, z, nb) : brick_addr(xx, yy, z, nb); };
-    T* r = out + static_cast<size_t>(brick_addr(x, y, z, nb)) * kValues;
-    r[0] = data[at(x, y)];
-    r[1] = data[at(x1, y)];
-    if constexpr (kValues == 4) {
-        r[2] = data[at(x, y1)];
-        r[3] = data[at(x1, y1)];
-    }
+    const int x1 = min(x + 1, n - 1);
+    uint32_t* r = out + static_cast<size_t>(brick_addr(x, y, z, nb)) * 2;
+    r[0] = data[brick_addr(x, y, z, nb)];
+    r[1] = data[brick_addr(x1, y, z, nb)];
+}
+
+// binary16 records: pair blocks, one thread per entry.  Entry (x, y, z) of a brick's 9 x 8 x 8 block
+// (f16_index numbering, x = 8 the next brick's first voxel, clamped to N-1) holds the values at (x, y)
+// and (x, y + 1) (y + 1 clamped to N-1), bit patterns copied from the binary16 blocks.
+__global__ __launch_bounds__(256) void pair_records_kernel(const uint16_t* __restrict__ data, int n,
+                                                           uint32_t* __restrict__ out) {
+    const int nb = n >> 3;
+    const uint32_t total = static_cast<uint32_t>(nb) * nb * nb * kF16BrickValues;
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const uint32_t brick = e / kF16BrickValues, rem = e % kF16BrickValues;
+    const int lz = rem / 72, ly = (rem / 9) % 8, lx = rem % 9;
+    const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
+    const int x = min(bx * 8 + lx, n - 1), y = by * 8 + ly, z = bz * 8 + lz;
+    const int y1 = min(y + 1, n - 1);
+    out[e] = static_cast<uint32_t>(data[f16_index(x, y, z, nb)]) |
+             (static_cast<uint32_t>(data[f16_index(x, y1, z, nb)]) << 16);
 }
 
 // 8-bit storage: the pair of decoded float32 values at (x..x+1, y, z) (exact, as the compact path
@@ -559,11 +569,13 @@ hipError_t launch_records(const void* data, const float2* u8par, int n, int stor
     const size_t total = static_cast<size_t>(n) * n * n;
     const dim3 g(blocks_for(total, 256));
     if (storage == kF32)
-        hipLaunchKernelGGL(records_kernel<uint32_t>, g, dim3(256), 0, s, static_cast<const uint32_t*>(data), n,
+        hipLaunchKernelGGL(records_kernel, g, dim3(256), 0, s, static_cast<const uint32_t*>(data), n,
                            static_cast<uint32_t*>(out));
-    else if (storage == kF16)
-        hipLaunchKernelGGL(records_kernel<uint16_t>, g, dim3(256), 0, s, static_cast<const uint16_t*>(data), n,
-                           static_cast<uint16_t*>(out));
+    else if (storage == kF16) {
+        const size_t entries = static_cast<size_t>(n >> 3) * (n >> 3) * (n >> 3) * kF16BrickValues;
+        hipLaunchKernelGGL(pair_records_kernel, dim3(blocks_for(entries, 256)), dim3(256), 0, s,
+                           static_cast<const uint16_t*>(data), n, static_cast<uint32_t*>(out));
+    }
     else
         hipLaunchKernelGGL(records_u8_kernel, g, dim3(256), 0, s, data, u8par, n, static_cast<float*>(out));
     return hipGetLastError();

@@ -193,38 +193,43 @@ __device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)
     }
 }
 
-// Trilinear value from neighbourhood records (8 bytes per voxel): binary16 reads the 2x2 (x, y) records
-// of the base voxel's row at z0 and z1, float32 the x pairs at (y0, z0), (y1, z0), (y0, z1), (y1, z1).
-// r00 / r10 / r01 / r11 are the record numbers of the base voxel's row at (y0, z0), (y1, z0), (y0, z1),
-// (y1, z1) (the layout of axis_x/y/z).  The arithmetic is that of fetch(), so both layouts give
-// identical values.  WIDE: global loads at 64-bit byte offsets (fields of 4 GiB and more); else buffer
-// loads at 32-bit byte offsets, whose base the load adds itself (`bytes`: the field's size).
+// Trilinear value from neighbourhood records.  binary16: pair blocks (4 bytes per entry, f16_index
+// numbering), entry (x, y, z) holding the values at (x, y) and (x, y + 1), so the 8 bytes at the base
+// voxel's entry are the cell's 2x2 (x, y) corners in the plane; one load for z0 and one for z1.
+// float32 (8 bytes per voxel, the numbering of axis_x/y/z): the x pairs at (y0, z0), (y1, z0), (y0,
+// z1), (y1, z1).  r00 / r10 / r01 / r11 are the entry (record) numbers of the base voxel's row at (y0,
+// z0), (y1, z0), (y0, z1), (y1, z1).  The arithmetic is that of fetch(), so both layouts give identical
+// values.  WIDE: global loads at 64-bit byte offsets (fields of 4 GiB and more); else buffer loads at
+// 32-bit byte offsets, whose base the load adds itself (`bytes`: the field's size).
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-template <bool WIDE>
+template <int S>
+constexpr uint32_t kRecShift = S == kF16 ? 2 : 3;  // log2 of the bytes per entry number
+template <int S, bool WIDE>
 __device__ __forceinline__ u32x2 load_record(const void* base, uint32_t bytes, uint32_t r) {
     if constexpr (WIDE) {
-        return global_ptr<u32x2>(static_cast<const char*>(base) + static_cast<size_t>(r) * 8u)[0];
+        return global_ptr<u32x2>(static_cast<const char*>(base) + (static_cast<size_t>(r) << kRecShift<S>))[0];
     } else {
         const __amdgpu_buffer_rsrc_t rsrc =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes), kRawBufferFlags);
-        return __builtin_amdgcn_raw_buffer_load_b64(rsrc, static_cast<int>(r << 3), 0, 0);
+        return __builtin_amdgcn_raw_buffer_load_b64(rsrc, static_cast<int>(r << kRecShift<S>), 0, 0);
     }
 }
 template <int S, bool WIDE>
 __device__ __forceinline__ float fetch_rec(const void* __restrict__ base, uint32_t bytes, uint32_t r00, uint32_t r10,
                                            uint32_t r01, uint32_t r11, const Tri& t) {
     if constexpr (S == kF16) {
-        const u32x2 p = load_record<WIDE>(base, bytes, r00);
-        const u32x2 q = load_record<WIDE>(base, bytes, r01);
+        // entries (x0, y) and (x1, y): the halves are (x0, y0), (x0, y1), (x1, y0), (x1, y1)
+        const u32x2 p = load_record<S, WIDE>(base, bytes, r00);
+        const u32x2 q = load_record<S, WIDE>(base, bytes, r01);
         auto lo = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u & 0xFFFFu))); };
         auto hi = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u >> 16))); };
-        return blend(t, lo(p.x), hi(p.x), lo(p.y), hi(p.y), lo(q.x), hi(q.x), lo(q.y), hi(q.y));
+        return blend(t, lo(p.x), lo(p.y), hi(p.x), hi(p.y), lo(q.x), lo(q.y), hi(q.x), hi(q.y));
     } else {
-        const u32x2 p0 = load_record<WIDE>(base, bytes, r00);
-        const u32x2 p1 = load_record<WIDE>(base, bytes, r10);
-        const u32x2 p2 = load_record<WIDE>(base, bytes, r01);
-        const u32x2 p3 = load_record<WIDE>(base, bytes, r11);
+        const u32x2 p0 = load_record<S, WIDE>(base, bytes, r00);
+        const u32x2 p1 = load_record<S, WIDE>(base, bytes, r10);
+        const u32x2 p2 = load_record<S, WIDE>(base, bytes, r01);
+        const u32x2 p3 = load_record<S, WIDE>(base, bytes, r11);
         return blend(t, __uint_as_float(p0.x), __uint_as_float(p0.y), __uint_as_float(p1.x), __uint_as_float(p1.y),
                      __uint_as_float(p2.x), __uint_as_float(p2.y), __uint_as_float(p3.x), __uint_as_float(p3.y));
     }
@@ -242,12 +247,12 @@ __device__ __forceinline__ float fetch_rec_guarded(const void* __restrict__ base
     auto ld = [&](uint32_t r) -> u32x2 {
         if constexpr (WIDE) {
             u32x2 v = {0u, 0u};
-            if (use) v = global_ptr<u32x2>(static_cast<const char*>(base) + static_cast<size_t>(r) * 8u)[0];
+            if (use) v = global_ptr<u32x2>(static_cast<const char*>(base) + (static_cast<size_t>(r) << kRecShift<S>))[0];
             return v;
         } else {
             const __amdgpu_buffer_rsrc_t rsrc =
                 __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes), kRawBufferFlags);
-            return __builtin_amdgcn_raw_buffer_load_b64(rsrc, static_cast<int>(use ? r << 3 : kNoLoad), 0, 0);
+            return __builtin_amdgcn_raw_buffer_load_b64(rsrc, static_cast<int>(use ? r << kRecShift<S> : kNoLoad), 0, 0);
         }
     };
     if constexpr (S == kF16) {
@@ -255,7 +260,7 @@ __device__ __forceinline__ float fetch_rec_guarded(const void* __restrict__ base
         const u32x2 q = ld(r01);
         auto lo = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u & 0xFFFFu))); };
         auto hi = [](unsigned int u) { return __half2float(__ushort_as_half(static_cast<unsigned short>(u >> 16))); };
-        return blend(t, lo(p.x), hi(p.x), lo(p.y), hi(p.y), lo(q.x), hi(q.x), lo(q.y), hi(q.y));
+        return blend(t, lo(p.x), lo(p.y), hi(p.x), hi(p.y), lo(q.x), lo(q.y), hi(q.x), hi(q.y));
     } else {
         const u32x2 p0 = ld(r00);
         const u32x2 p1 = ld(r10);
@@ -614,7 +619,16 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                 const float wx = ux[q] - flx[q], wy = uy[q] - fly[q], wz = uz[q] - flz[q];
                 tri[q] = tri_weights(wx, wy, wz);
                 r00[q] = r10[q] = r01[q] = r11[q] = 0;
-                if constexpr (R) {
+                if constexpr (R && RT == kF16) {
+                    // pair number of the base voxel in the binary16 pair blocks (f16_index): its brick's
+                    // block, then z, y, x.  The plane one up in z is 72 pairs on inside a brick, in the
+                    // next brick beyond its face, and the same plane where the upper corner clamps onto
+                    // the base voxel (at the grid's upper face).
+                    r00[q] = raypc_mul_u24(brick[q], kF16BrickValues) + static_cast<uint32_t>(z0[q] & 7) * 72u +
+                             static_cast<uint32_t>(y0[q] & 7) * 9u + static_cast<uint32_t>(x0[q] & 7);
+                    const uint32_t dz = (z0[q] & 7) != 7 ? 72u : f16_z_brick_step;
+                    r01[q] = r00[q] + (flz[q] < top ? dz : 0u);
+                } else if constexpr (R) {
                     // record number of the base voxel (the layout of axis_x/y/z): its brick, the 4^3
                     // sub-brick in bits 6-8 and its place in that in bits 0-5.  The voxel one up in
                     // z (y) follows by a step that depends on where the base voxel lies in its
