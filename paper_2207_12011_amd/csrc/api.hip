@@ -435,7 +435,7 @@ int prepare_render(raypc_ctx* ctx, int volume_id, const raypc_camera* cam, int w
                                                  : static_cast<uint64_t>(L.n) * L.n * L.n * storage_bytes(v->storage);
         a.field_bytes = fb > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(fb);
         a.par_bytes = static_cast<uint32_t>((L.n_bricks() + 1) * sizeof(float2));   // with the zero pair after the last brick
-        const uint64_t rb = v->storage == kF16 ? f16_pair_bytes(L.nb) : static_cast<uint64_t>(L.n) * L.n * L.n * 8u;
+        const uint64_t rb = record_bytes(L.nb);
         a.rec_bytes = rb > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(rb);
     }
     a.half_n = 0.5f * static_cast<float>(L.n);
@@ -635,7 +635,7 @@ int raypc_load_fields(raypc_ctx* ctx, int n_fields, int n, const float* const* f
                 if (!rc && storage == kU8) rc = dev_alloc(v, reinterpret_cast<void**>(&L.par[f]), (L.n_bricks() + 1) * sizeof(float2));
                 if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm[f]), L.n_bricks() * sizeof(float2));
                 if (!rc) rc = dev_alloc(v, reinterpret_cast<void**>(&L.mm_sub[f]), L.n_bricks() * 8 * sizeof(float2));
-                if (!rc && v->records) rc = dev_alloc(v, &L.rec[f], storage == kF16 ? f16_pair_bytes(L.nb) : lvox * 8);
+                if (!rc && v->records) rc = dev_alloc(v, &L.rec[f], record_bytes(L.nb));
             }
             for (int k = 0; k < kSkipVersions && !rc; ++k)
                 rc = dev_alloc(v, reinterpret_cast<void**>(&L.skip_ver[k]), L.n_bricks() * sizeof(uint16_t));

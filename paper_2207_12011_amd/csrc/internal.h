@@ -26,8 +26,8 @@ enum Kind : int {
 // order, 512 voxels each.  Inside a brick the voxels form eight 4^3 sub-bricks (x, y, z half-index in
 // bits 6, 7, 8), each [z][y][x], so a compact cluster of samples touches few cache lines whatever the
 // view direction.  The number is a sum of independent per-axis parts (see axis_x/y/z).  It places the
-// float32 compact values and the neighbourhood records of every storage; binary16 and 8-bit compact
-// values are held in blocks of their own (f16_index, u8_addr).
+// float32 compact values; binary16 and 8-bit compact values and the neighbourhood records of every
+// storage are held in blocks (block_index9, u8_addr).
 __host__ __device__ inline uint32_t axis_x(int x) {
     return (static_cast<uint32_t>(x >> 3) << 9) | (static_cast<uint32_t>((x >> 2) & 1) << 6) |
            static_cast<uint32_t>(x & 3);
@@ -72,23 +72,24 @@ __host__ __device__ inline size_t u8_field_bytes(int nb) {
     return static_cast<size_t>(nb) * nb * nb * kU8BrickBytes + 16;
 }
 
-// binary16 values use a layout of their own too: each 8^3 brick is a 9 x 8 x 8 block of values,
-// [z][y][x] (576 values, 1152 bytes), holding its 512 values and, at local x = 8, a copy of the value
-// one voxel beyond its upper x face (the next brick's first voxel; at the grid's upper x face the last
-// voxel again).  The two corners of a cell's row (x0 and x0 + 1 at one y and z) are then adjacent,
-// one 4-byte load.
-constexpr uint32_t kF16BrickValues = 576;
-__host__ __device__ inline uint32_t f16_index(int x, int y, int z, int nb) {
-    return brick_index(x, y, z, nb) * kF16BrickValues + static_cast<uint32_t>(z & 7) * 72u +
+// Blocks of 9 x 8 x 8 entries per 8^3 brick, [z][y][x] (576 entries, bricks in [bz][by][bx] order):
+// the brick's 512 voxels and, at local x = 8, a copy of the voxel one beyond its upper x face (the
+// next brick's first voxel; at the grid's upper x face the last voxel again, as the interpolation
+// clamps), so the two corners of a cell's row (x0 and x0 + 1 at one y and z) are adjacent entries.
+// binary16 compact values are 2-byte entries (a row is one 4-byte load); the neighbourhood records are
+// 4-byte entries (an x pair, or for binary16 a 2x2 (x, y) quad, is one 8-byte load).
+constexpr uint32_t kBlockValues = 576;
+__host__ __device__ inline uint32_t block_index9(int x, int y, int z, int nb) {
+    return brick_index(x, y, z, nb) * kBlockValues + static_cast<uint32_t>(z & 7) * 72u +
            static_cast<uint32_t>(y & 7) * 9u + static_cast<uint32_t>(x & 7);
 }
 // Bytes of one field's binary16 array on a level: the bricks plus 16 bytes of padding.
 __host__ __device__ inline size_t f16_field_bytes(int nb) {
-    return static_cast<size_t>(nb) * nb * nb * kF16BrickValues * 2 + 16;
+    return static_cast<size_t>(nb) * nb * nb * kBlockValues * 2 + 16;
 }
-// Bytes of one field's binary16 records (pair blocks: 4 bytes per entry of the same numbering).
-__host__ __device__ inline size_t f16_pair_bytes(int nb) {
-    return static_cast<size_t>(nb) * nb * nb * kF16BrickValues * 4 + 16;
+// Bytes of one field's records (4-byte entries of the same numbering).
+__host__ __device__ inline size_t record_bytes(int nb) {
+    return static_cast<size_t>(nb) * nb * nb * kBlockValues * 4 + 16;
 }
 
 // Coordinate axes of a brush at a position (x, y, z world units): bit a of mask enables axis a

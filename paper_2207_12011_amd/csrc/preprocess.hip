@@ -38,7 +38,7 @@ __device__ __forceinline__ float stored(const void* base, const float2* par, int
     if constexpr (S == kF32) {
         return static_cast<const float*>(base)[brick_addr(x, y, z, nb)];
     } else if constexpr (S == kF16) {
-        return __half2float(static_cast<const __half*>(base)[f16_index(x, y, z, nb)]) * descale;
+        return __half2float(static_cast<const __half*>(base)[block_index9(x, y, z, nb)]) * descale;
     } else {
         const float q = static_cast<float>(static_cast<const uint8_t*>(base)[u8_addr(x, y, z, nb)]);
         const float2 p = par[brick_index(x, y, z, nb)];
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ i
         const uint32_t a = (brick << 9) | brick_local(t & 7, (t >> 3) & 7, t >> 6);
         static_cast<float*>(out)[a] = v;
     } else if constexpr (S == kF16) {
-        const uint32_t a = brick * kF16BrickValues + (t >> 6) * 72u + ((t >> 3) & 7) * 9u + (t & 7);
+        const uint32_t a = brick * kBlockValues + (t >> 6) * 72u + ((t >> 3) & 7) * 9u + (t & 7);
         // scaling by a power of two is exact: only the binary16 rounding remains
         static_cast<__half*>(out)[a] = __float2half_rn(v * (f16_scale ? f16_scale[0] : 1.0f));
     } else {
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(64) void f16_apron_kernel(uint16_t* __restrict__ va
     const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
     const int ly = k & 7, lz = k >> 3;
     const int x = min(bx * 8 + 8, n - 1), y = by * 8 + ly, z = bz * 8 + lz;
-    values[brick * kF16BrickValues + lz * 72u + ly * 9u + 8u] = values[f16_index(x, y, z, nb)];
+    values[brick * kBlockValues + lz * 72u + ly * 9u + 8u] = values[block_index9(x, y, z, nb)];
 }
 
 // 8-bit codes: the copies at local x = 8 and y = 8 of every brick (136 per brick: 9 at y = 8 and 8 at
@@ -254,51 +254,31 @@ __global__ void decode_kernel(const void* __restrict__ data, const float2* __res
     out[o] = stored<S>(data, par, x, y, z, n >> 3, descale);
 }
 
-// float32 records: one thread per voxel, the pair at (x..x+1, y, z) (x + 1 clamped to N-1, bit
-// patterns copied) at the voxel's brick-ordered number.
-__global__ void records_kernel(const uint32_t* __restrict__ data, int n, uint32_t* __restrict__ out) {
-    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t total = static_cast<uint32_t>(n) * n * n;
-    if (o >= total) return;
+// Records, one thread per entry of the 9 x 8 x 8 blocks (block_index9 numbering): entry (x, y, z)
+// is the voxel at (min(x, N-1), y, z), x = 8 being the next brick's first voxel.  float32: its value
+// (bit pattern copied from the float32 array); 8-bit: its value decoded exactly as the compact path
+// decodes it; binary16: the pair of values at (x, y) and (x, min(y + 1, N-1)) from the binary16 blocks.
+template <int S>
+__global__ __launch_bounds__(256) void records_kernel(const void* __restrict__ data, const float2* __restrict__ par,
+                                                      int n, uint32_t* __restrict__ out) {
     const int nb = n >> 3;
-    const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
-    const int x1 = min(x + 1, n - 1);
-    uint32_t* r = out + static_cast<size_t>(brick_addr(x, y, z, nb)) * 2;
-    r[0] = data[brick_addr(x, y, z, nb)];
-    r[1] = data[brick_addr(x1, y, z, nb)];
-}
-
-// binary16 records: pair blocks, one thread per entry.  Entry (x, y, z) of a brick's 9 x 8 x 8 block
-// (f16_index numbering, x = 8 the next brick's first voxel, clamped to N-1) holds the values at (x, y)
-// and (x, y + 1) (y + 1 clamped to N-1), bit patterns copied from the binary16 blocks.
-__global__ __launch_bounds__(256) void pair_records_kernel(const uint16_t* __restrict__ data, int n,
-                                                           uint32_t* __restrict__ out) {
-    const int nb = n >> 3;
-    const uint32_t total = static_cast<uint32_t>(nb) * nb * nb * kF16BrickValues;
+    const uint32_t total = static_cast<uint32_t>(nb) * nb * nb * kBlockValues;
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
-    const uint32_t brick = e / kF16BrickValues, rem = e % kF16BrickValues;
+    const uint32_t brick = e / kBlockValues, rem = e % kBlockValues;
     const int lz = rem / 72, ly = (rem / 9) % 8, lx = rem % 9;
     const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
     const int x = min(bx * 8 + lx, n - 1), y = by * 8 + ly, z = bz * 8 + lz;
-    const int y1 = min(y + 1, n - 1);
-    out[e] = static_cast<uint32_t>(data[f16_index(x, y, z, nb)]) |
-             (static_cast<uint32_t>(data[f16_index(x, y1, z, nb)]) << 16);
-}
-
-// 8-bit storage: the pair of decoded float32 values at (x..x+1, y, z) (exact, as the compact path
-// decodes them).
-__global__ void records_u8_kernel(const void* __restrict__ data, const float2* __restrict__ par, int n,
-                                  float* __restrict__ out) {
-    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t total = static_cast<uint32_t>(n) * n * n;
-    if (o >= total) return;
-    const int nb = n >> 3;
-    const int x = o % n, y = (o / n) % n, z = o / (static_cast<uint32_t>(n) * n);
-    const int x1 = min(x + 1, n - 1);
-    float* r = out + static_cast<size_t>(brick_addr(x, y, z, nb)) * 2;
-    r[0] = stored<kU8>(data, par, x, y, z, nb);
-    r[1] = stored<kU8>(data, par, x1, y, z, nb);
+    if constexpr (S == kF32) {
+        out[e] = static_cast<const uint32_t*>(data)[brick_addr(x, y, z, nb)];
+    } else if constexpr (S == kU8) {
+        out[e] = __float_as_uint(stored<kU8>(data, par, x, y, z, nb));
+    } else {
+        const uint16_t* v = static_cast<const uint16_t*>(data);
+        const int y1 = min(y + 1, n - 1);
+        out[e] = static_cast<uint32_t>(v[block_index9(x, y, z, nb)]) |
+                 (static_cast<uint32_t>(v[block_index9(x, y1, z, nb)]) << 16);
+    }
 }
 
 template <int S>
@@ -566,18 +546,14 @@ hipError_t launch_decode(const void* data, const float2* u8par, int n, int stora
 }
 
 hipError_t launch_records(const void* data, const float2* u8par, int n, int storage, void* out, hipStream_t s) {
-    const size_t total = static_cast<size_t>(n) * n * n;
-    const dim3 g(blocks_for(total, 256));
-    if (storage == kF32)
-        hipLaunchKernelGGL(records_kernel, g, dim3(256), 0, s, static_cast<const uint32_t*>(data), n,
-                           static_cast<uint32_t*>(out));
-    else if (storage == kF16) {
-        const size_t entries = static_cast<size_t>(n >> 3) * (n >> 3) * (n >> 3) * kF16BrickValues;
-        hipLaunchKernelGGL(pair_records_kernel, dim3(blocks_for(entries, 256)), dim3(256), 0, s,
-                           static_cast<const uint16_t*>(data), n, static_cast<uint32_t*>(out));
+    const size_t entries = static_cast<size_t>(n >> 3) * (n >> 3) * (n >> 3) * kBlockValues;
+    const dim3 g(blocks_for(entries, 256));
+    uint32_t* o = static_cast<uint32_t*>(out);
+    switch (storage) {
+        case kF32: hipLaunchKernelGGL(records_kernel<kF32>, g, dim3(256), 0, s, data, u8par, n, o); break;
+        case kF16: hipLaunchKernelGGL(records_kernel<kF16>, g, dim3(256), 0, s, data, u8par, n, o); break;
+        default: hipLaunchKernelGGL(records_kernel<kU8>, g, dim3(256), 0, s, data, u8par, n, o); break;
     }
-    else
-        hipLaunchKernelGGL(records_u8_kernel, g, dim3(256), 0, s, data, u8par, n, static_cast<float*>(out));
     return hipGetLastError();
 }
 

@@ -143,7 +143,7 @@ __device__ __forceinline__ float blend(const Tri& t, float c0, float c1, float c
 }
 
 // Trilinear value from the 8 stored corners.  float32: o[] holds the corners' byte offsets.
-// binary16 (the 9 x 8 x 8 blocks of f16_index): o[0..3] are the byte offsets of the corners (x0, y, z)
+// binary16 (the 9 x 8 x 8 blocks of block_index9): o[0..3] are the byte offsets of the corners (x0, y, z)
 // of the rows (y, z) = (y0, z0), (y1, z0), (y0, z1), (y1, z1), each the start of one 4-byte load of the
 // row's two values (eight 2-byte loads took 1.24 ms for the headline frame, four row loads 0.85 ms).
 // 8-bit codes (the 9 x 9 x 8 brick blocks of u8_addr): o[0] and o[1] are the byte offsets of
@@ -193,18 +193,19 @@ __device__ __forceinline__ float fetch(const Source<S>& src, const uint32_t (&o)
     }
 }
 
-// Trilinear value from neighbourhood records.  binary16: pair blocks (4 bytes per entry, f16_index
-// numbering), entry (x, y, z) holding the values at (x, y) and (x, y + 1), so the 8 bytes at the base
-// voxel's entry are the cell's 2x2 (x, y) corners in the plane; one load for z0 and one for z1.
-// float32 (8 bytes per voxel, the numbering of axis_x/y/z): the x pairs at (y0, z0), (y1, z0), (y0,
-// z1), (y1, z1).  r00 / r10 / r01 / r11 are the entry (record) numbers of the base voxel's row at (y0,
-// z0), (y1, z0), (y0, z1), (y1, z1).  The arithmetic is that of fetch(), so both layouts give identical
+// Trilinear value from neighbourhood records: 4-byte entries in 9 x 8 x 8 brick blocks (the block_index9
+// numbering, x = 8 a copy of the next brick's first voxel), so that the 8 bytes at the base voxel's
+// entry are the cell's two x-neighbouring entries.  binary16: entry (x, y, z) holds the values at
+// (x, y) and (x, y + 1), and those 8 bytes are the cell's 2x2 (x, y) corners in the plane: one load for
+// z0 and one for z1.  float32 (and decoded 8-bit values): entry (x, y, z) holds the value at (x, y),
+// and the 8 bytes are an x pair: loads for the rows (y0, z0), (y1, z0), (y0, z1), (y1, z1).  r00 / r10 /
+// r01 / r11 are the entry numbers of the base voxel's row at (y0, z0), (y1, z0), (y0, z1), (y1, z1).  The arithmetic is that of fetch(), so both layouts give identical
 // values.  WIDE: global loads at 64-bit byte offsets (fields of 4 GiB and more); else buffer loads at
 // 32-bit byte offsets, whose base the load adds itself (`bytes`: the field's size).
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <int S>
-constexpr uint32_t kRecShift = S == kF16 ? 2 : 3;  // log2 of the bytes per entry number
+constexpr uint32_t kRecShift = 2;  // log2 of the bytes per entry
 template <int S, bool WIDE>
 __device__ __forceinline__ u32x2 load_record(const void* base, uint32_t bytes, uint32_t r) {
     if constexpr (WIDE) {
@@ -491,9 +492,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
         const_cast<void*>(A.skip != nullptr ? static_cast<const void*>(A.skip) : static_cast<const void*>(A.tf)), 0,
         A.skip != nullptr ? static_cast<int>(nbu * nbu * nbu * 2u) : 0, kRawBufferFlags);
     // record-number steps to the next voxel in y and z from the last voxel of a brick (see below)
-    const uint32_t y_brick_step = nbu * 512u - 140u, z_brick_step = nbu * nbu * 512u - 304u;
     // binary16 blocks: from a row at local y = 7 (z = 7) to the row at local 0 of the next brick
-    const uint32_t f16_y_brick_step = nbu * kF16BrickValues - 63u, f16_z_brick_step = nbu * nbu * kF16BrickValues - 504u;
+    const uint32_t block_y_step = nbu * kBlockValues - 63u, block_z_step = nbu * nbu * kBlockValues - 504u;
     const float top = static_cast<float>(n - 1);  // largest voxel index
     const float hn = A.half_n;
     const float uox = fmaf(ox, hn, hn - 0.5f), uoy = fmaf(oy, hn, hn - 0.5f), uoz = fmaf(oz, hn, hn - 0.5f);
@@ -619,28 +619,18 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                 const float wx = ux[q] - flx[q], wy = uy[q] - fly[q], wz = uz[q] - flz[q];
                 tri[q] = tri_weights(wx, wy, wz);
                 r00[q] = r10[q] = r01[q] = r11[q] = 0;
-                if constexpr (R && RT == kF16) {
-                    // pair number of the base voxel in the binary16 pair blocks (f16_index): its brick's
-                    // block, then z, y, x.  The plane one up in z is 72 pairs on inside a brick, in the
-                    // next brick beyond its face, and the same plane where the upper corner clamps onto
-                    // the base voxel (at the grid's upper face).
-                    r00[q] = raypc_mul_u24(brick[q], kF16BrickValues) + static_cast<uint32_t>(z0[q] & 7) * 72u +
+                if constexpr (R) {
+                    // entry number of the base voxel in the record blocks (the block_index9 numbering): its
+                    // brick's block, then z, y, x.  The row one up in y (z) is 9 (72) entries on inside a
+                    // brick, in the next brick beyond its face, and the same row where the upper corner
+                    // clamps onto the base voxel (at the grid's upper face).  binary16 entries hold y and
+                    // y + 1, so they need no row in y.
+                    r00[q] = raypc_mul_u24(brick[q], kBlockValues) + static_cast<uint32_t>(z0[q] & 7) * 72u +
                              static_cast<uint32_t>(y0[q] & 7) * 9u + static_cast<uint32_t>(x0[q] & 7);
-                    const uint32_t dz = (z0[q] & 7) != 7 ? 72u : f16_z_brick_step;
-                    r01[q] = r00[q] + (flz[q] < top ? dz : 0u);
-                } else if constexpr (R) {
-                    // record number of the base voxel (the layout of axis_x/y/z): its brick, the 4^3
-                    // sub-brick in bits 6-8 and its place in that in bits 0-5.  The voxel one up in
-                    // z (y) follows by a step that depends on where the base voxel lies in its
-                    // sub-brick and brick: +16 (+4) inside a sub-brick, to the next sub-brick, or to
-                    // the next brick; none where the upper corner clamps onto the base voxel (at the
-                    // grid's upper face).
-                    r00[q] = (brick[q] << 9) | (sbi[q] << 6) |
-                             static_cast<uint32_t>((x0[q] & 3) | ((y0[q] & 3) << 2) | ((z0[q] & 3) << 4));
-                    const uint32_t dz = (z0[q] & 3) != 3 ? 16u : ((z0[q] & 4) == 0 ? 208u : z_brick_step);
+                    const uint32_t dz = (z0[q] & 7) != 7 ? 72u : block_z_step;
                     r01[q] = r00[q] + (flz[q] < top ? dz : 0u);
                     if constexpr (RT == kF32) {
-                        const uint32_t dy = (y0[q] & 3) != 3 ? 4u : ((y0[q] & 4) == 0 ? 116u : y_brick_step);
+                        const uint32_t dy = (y0[q] & 7) != 7 ? 9u : block_y_step;
                         const uint32_t dyv = fly[q] < top ? dy : 0u;
                         r10[q] = r00[q] + dyv;
                         r11[q] = r01[q] + dyv;
@@ -651,9 +641,9 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                     // its face, and the same row where the upper corner clamps onto the grid's face.
                     const int iy = static_cast<int>(fly[q]), iz = static_cast<int>(flz[q]);
                     const int y1 = min(iy + 1, n - 1), z1 = min(iz + 1, n - 1);
-                    const uint32_t dyv = y1 == y0[q] ? 0u : ((y0[q] & 7) != 7 ? 9u : f16_y_brick_step);
-                    const uint32_t dzv = z1 == z0[q] ? 0u : ((z0[q] & 7) != 7 ? 72u : f16_z_brick_step);
-                    const uint32_t base = raypc_mul_u24(brick[q], kF16BrickValues) +
+                    const uint32_t dyv = y1 == y0[q] ? 0u : ((y0[q] & 7) != 7 ? 9u : block_y_step);
+                    const uint32_t dzv = z1 == z0[q] ? 0u : ((z0[q] & 7) != 7 ? 72u : block_z_step);
+                    const uint32_t base = raypc_mul_u24(brick[q], kBlockValues) +
                                           static_cast<uint32_t>(z0[q] & 7) * 72u +
                                           static_cast<uint32_t>(y0[q] & 7) * 9u + static_cast<uint32_t>(x0[q] & 7);
                     o[q][0] = base * 2u;
