@@ -406,8 +406,8 @@ __device__ __forceinline__ float jitter_offset(const RenderArgs& A, uint32_t p) 
 // loads of both samples are issued together (see fetch_rec_guarded), so a wave has twice the loads
 // in flight while each ray advances eight samples per step (headline frame 0.876 -> 0.740 ms; the
 // 1024^3 4K passes at 64-bit offsets 17-21 % faster).  The other kinds take one: with two, float32-pair
-// records (float32 and decoded 8-bit values) need 82 registers, which leaves 5 waves per SIMD (two
-// frames in flight 4 % slower); the compact binary16 layout 87 (7 % slower) and the 8-bit code
+// records (float32 and decoded 8-bit values) need 80 registers, which leaves 6 waves per SIMD (two
+// frames in flight 0.840 -> 0.878 ms per step); the compact binary16 layout 87 (7 % slower) and the 8-bit code
 // blocks 116, 4 waves per SIMD (1.55 -> 1.70 ms).  The counting variant takes one.
 constexpr int samples_per_lane(int K, bool COUNTS) { return !COUNTS && K == kKindF16Rec ? 2 : 1; }
 
