@@ -58,12 +58,12 @@ enum {
                                  * of a brick are held with copies of the next bricks' first x and
                                  * y voxels (1.27 bytes per voxel) */
     /* Flag OR-ed into a storage type: keep only the compact layout.  Without it the library also
-     * keeps, per voxel, an 8-byte record of neighbouring stored values (binary16: the 2x2 values
-     * at (x..x+1, y..y+1, z); float32 and 8-bit: the pair of float32 (decoded) values at
-     * (x..x+1, y, z)), so that a sample's trilinear fetch takes 2 (binary16) or 4 loads instead
-     * of 8 (float32), 4 (binary16) or 2 code loads and 4 (scale, offset) loads (8-bit).  Records cost
-     * 8 bytes per voxel and field besides the compact data; both layouts hold the same values and
-     * render identically. */
+     * keeps neighbourhood records: per voxel a 4-byte entry, in brick blocks that also copy the next
+     * brick's first x voxels (binary16: the values at (x, y) and (x, y + 1); float32 and 8-bit: the
+     * float32 (decoded) value), so that a sample's trilinear fetch takes 2 (binary16) or 4 loads
+     * of 8 bytes instead of 8 (float32), 4 (binary16) or 2 code loads and 4 (scale, offset) loads
+     * (8-bit).  Records cost 4.5 bytes per voxel and field besides the compact data; both layouts
+     * hold the same values and render identically. */
     RAYPC_STORAGE_COMPACT = 0x100
 };
 
