@@ -79,9 +79,10 @@ __host__ __device__ inline size_t u8_field_bytes(int nb) {
 // binary16 compact values are 2-byte entries (a row is one 4-byte load); the neighbourhood records are
 // 4-byte entries (an x pair, or for binary16 a 2x2 (x, y) quad, is one 8-byte load).
 constexpr uint32_t kBlockValues = 576;
+constexpr uint32_t kBlockYStride = 9, kBlockZStride = 72;  // entries between neighbours in y and in z
 __host__ __device__ inline uint32_t block_index9(int x, int y, int z, int nb) {
-    return brick_index(x, y, z, nb) * kBlockValues + static_cast<uint32_t>(z & 7) * 72u +
-           static_cast<uint32_t>(y & 7) * 9u + static_cast<uint32_t>(x & 7);
+    return brick_index(x, y, z, nb) * kBlockValues + static_cast<uint32_t>(z & 7) * kBlockZStride +
+           static_cast<uint32_t>(y & 7) * kBlockYStride + static_cast<uint32_t>(x & 7);
 }
 // Bytes of one field's binary16 array on a level: the bricks plus 16 bytes of padding.
 __host__ __device__ inline size_t f16_field_bytes(int nb) {

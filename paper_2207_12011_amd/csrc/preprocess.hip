@@ -140,7 +140,7 @@ __global__ __launch_bounds__(512) void encode_kernel(const float* __restrict__ i
         const uint32_t a = (brick << 9) | brick_local(t & 7, (t >> 3) & 7, t >> 6);
         static_cast<float*>(out)[a] = v;
     } else if constexpr (S == kF16) {
-        const uint32_t a = brick * kBlockValues + (t >> 6) * 72u + ((t >> 3) & 7) * 9u + (t & 7);
+        const uint32_t a = brick * kBlockValues + (t >> 6) * kBlockZStride + ((t >> 3) & 7) * kBlockYStride + (t & 7);
         // scaling by a power of two is exact: only the binary16 rounding remains
         static_cast<__half*>(out)[a] = __float2half_rn(v * (f16_scale ? f16_scale[0] : 1.0f));
     } else {
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(64) void f16_apron_kernel(uint16_t* __restrict__ va
     const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
     const int ly = k & 7, lz = k >> 3;
     const int x = min(bx * 8 + 8, n - 1), y = by * 8 + ly, z = bz * 8 + lz;
-    values[brick * kBlockValues + lz * 72u + ly * 9u + 8u] = values[block_index9(x, y, z, nb)];
+    values[brick * kBlockValues + lz * kBlockZStride + ly * kBlockYStride + 8u] = values[block_index9(x, y, z, nb)];
 }
 
 // 8-bit codes: the copies at local x = 8 and y = 8 of every brick (136 per brick: 9 at y = 8 and 8 at
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void records_kernel(const void* __restrict__ d
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     const uint32_t brick = e / kBlockValues, rem = e % kBlockValues;
-    const int lz = rem / 72, ly = (rem / 9) % 8, lx = rem % 9;
+    const int lz = (rem / kBlockZStride) % 8, ly = (rem / kBlockYStride) % 8, lx = rem % 9;
     const int bx = brick % nb, by = (brick / nb) % nb, bz = brick / (nb * nb);
     const int x = min(bx * 8 + lx, n - 1), y = by * 8 + ly, z = bz * 8 + lz;
     if constexpr (S == kF32) {

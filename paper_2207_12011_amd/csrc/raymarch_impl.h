@@ -493,7 +493,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
         A.skip != nullptr ? static_cast<int>(nbu * nbu * nbu * 2u) : 0, kRawBufferFlags);
     // record-number steps to the next voxel in y and z from the last voxel of a brick (see below)
     // binary16 blocks: from a row at local y = 7 (z = 7) to the row at local 0 of the next brick
-    const uint32_t block_y_step = nbu * kBlockValues - 63u, block_z_step = nbu * nbu * kBlockValues - 504u;
+    const uint32_t block_y_step = nbu * kBlockValues - 7u * kBlockYStride;
+    const uint32_t block_z_step = nbu * nbu * kBlockValues - 7u * kBlockZStride;
     const float top = static_cast<float>(n - 1);  // largest voxel index
     const float hn = A.half_n;
     const float uox = fmaf(ox, hn, hn - 0.5f), uoy = fmaf(oy, hn, hn - 0.5f), uoz = fmaf(oz, hn, hn - 0.5f);
@@ -625,12 +626,12 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                     // brick, in the next brick beyond its face, and the same row where the upper corner
                     // clamps onto the base voxel (at the grid's upper face).  binary16 entries hold y and
                     // y + 1, so they need no row in y.
-                    r00[q] = raypc_mul_u24(brick[q], kBlockValues) + static_cast<uint32_t>(z0[q] & 7) * 72u +
-                             static_cast<uint32_t>(y0[q] & 7) * 9u + static_cast<uint32_t>(x0[q] & 7);
-                    const uint32_t dz = (z0[q] & 7) != 7 ? 72u : block_z_step;
+                    r00[q] = raypc_mul_u24(brick[q], kBlockValues) + static_cast<uint32_t>(z0[q] & 7) * kBlockZStride +
+                             static_cast<uint32_t>(y0[q] & 7) * kBlockYStride + static_cast<uint32_t>(x0[q] & 7);
+                    const uint32_t dz = (z0[q] & 7) != 7 ? kBlockZStride : block_z_step;
                     r01[q] = r00[q] + (flz[q] < top ? dz : 0u);
                     if constexpr (RT == kF32) {
-                        const uint32_t dy = (y0[q] & 7) != 7 ? 9u : block_y_step;
+                        const uint32_t dy = (y0[q] & 7) != 7 ? kBlockYStride : block_y_step;
                         const uint32_t dyv = fly[q] < top ? dy : 0u;
                         r10[q] = r00[q] + dyv;
                         r11[q] = r01[q] + dyv;
@@ -641,11 +642,11 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
                     // its face, and the same row where the upper corner clamps onto the grid's face.
                     const int iy = static_cast<int>(fly[q]), iz = static_cast<int>(flz[q]);
                     const int y1 = min(iy + 1, n - 1), z1 = min(iz + 1, n - 1);
-                    const uint32_t dyv = y1 == y0[q] ? 0u : ((y0[q] & 7) != 7 ? 9u : block_y_step);
-                    const uint32_t dzv = z1 == z0[q] ? 0u : ((z0[q] & 7) != 7 ? 72u : block_z_step);
+                    const uint32_t dyv = y1 == y0[q] ? 0u : ((y0[q] & 7) != 7 ? kBlockYStride : block_y_step);
+                    const uint32_t dzv = z1 == z0[q] ? 0u : ((z0[q] & 7) != 7 ? kBlockZStride : block_z_step);
                     const uint32_t base = raypc_mul_u24(brick[q], kBlockValues) +
-                                          static_cast<uint32_t>(z0[q] & 7) * 72u +
-                                          static_cast<uint32_t>(y0[q] & 7) * 9u + static_cast<uint32_t>(x0[q] & 7);
+                                          static_cast<uint32_t>(z0[q] & 7) * kBlockZStride +
+                                          static_cast<uint32_t>(y0[q] & 7) * kBlockYStride + static_cast<uint32_t>(x0[q] & 7);
                     o[q][0] = base * 2u;
                     o[q][1] = (base + dyv) * 2u;
                     o[q][2] = (base + dzv) * 2u;
