@@ -133,10 +133,11 @@ hipError_t launch_encode(const float* in, int n, int storage, void* out, float2*
 // (Binary16 codes are taken times f16_scale[1] when it is not null: the tables hold field values.)
 hipError_t launch_minmax(const void* data, const float2* u8par, int n, int storage, float2* out, float2* out_sub,
                          const float* f16_scale, hipStream_t s);
-// Neighbourhood records, 8 bytes per voxel (x, y, z) at brick_addr(x, y, z) x 8 bytes, coordinates
-// clamped to N-1: binary16 keeps the 2x2 values at (x+dx, y+dy, z) in the order dx + 2 dy; float32
-// keeps the pair at (x+dx, y, z), and 8-bit storage the pair of its decoded float32 values.  A
-// trilinear fetch reads 2 (binary16) or 4 (float32, 8-bit) records.
+// Neighbourhood records: 4-byte entries in the 9 x 8 x 8 blocks (block_index9; entry x = 8 is the next
+// brick's first voxel, coordinates clamped to N-1): binary16 keeps the values at (x, y) and (x, y + 1)
+// (low and high half), float32 the value, 8-bit storage its decoded float32 value.  A trilinear fetch
+// reads 8 bytes (two entries) twice (binary16: the 2x2 corners of the planes z0 and z1) or four times
+// (float32, 8-bit: the x pairs of the rows (y0 | y1, z0 | z1)).
 hipError_t launch_records(const void* data, const float2* u8par, int n, int storage, void* out, hipStream_t s);
 // Decode stored values back to linear [z][y][x] float32.
 // (binary16 codes times f16_descale)

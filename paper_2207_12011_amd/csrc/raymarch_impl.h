@@ -277,7 +277,7 @@ constexpr int storage_of(int K) {
     return K == kKindF32Rec ? kF32 : (K == kKindF16Rec ? kF16 : (K == kKindU8Rec ? kU8 : K));
 }
 constexpr bool records_of(int K) { return K >= kKindF32Rec; }
-// Value type held by a kind's records: binary16 quads, or float32 pairs (also for decoded 8-bit codes).
+// Value type held by a kind's records: binary16 pairs in y, or float32 values (also for decoded 8-bit codes).
 constexpr int record_type_of(int K) { return K == kKindF16Rec ? kF16 : kF32; }
 
 // Ray parameter where u(t) = uo + du t leaves the box [c, c + e) along one axis (voxel units, forward
@@ -491,8 +491,8 @@ __device__ __forceinline__ void march_tile(const RenderArgs& A, LP L, int bx, in
     const __amdgpu_buffer_rsrc_t flag_rsrc = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<void*>(A.skip != nullptr ? static_cast<const void*>(A.skip) : static_cast<const void*>(A.tf)), 0,
         A.skip != nullptr ? static_cast<int>(nbu * nbu * nbu * 2u) : 0, kRawBufferFlags);
-    // record-number steps to the next voxel in y and z from the last voxel of a brick (see below)
-    // binary16 blocks: from a row at local y = 7 (z = 7) to the row at local 0 of the next brick
+    // block entry steps (records and binary16 values) from a row at local y = 7 (z = 7) to the row at
+    // local 0 of the next brick
     const uint32_t block_y_step = nbu * kBlockValues - 7u * kBlockYStride;
     const uint32_t block_z_step = nbu * nbu * kBlockValues - 7u * kBlockZStride;
     const float top = static_cast<float>(n - 1);  // largest voxel index
